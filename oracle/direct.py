@@ -1,0 +1,67 @@
+"""ctypes front end of the oracle's direct C sums (test infrastructure only).
+
+build() compiles oracle/direct.c with gcc into oracle/_direct.so; the
+sums themselves are documented in direct.c.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from . import fbim as F
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO = os.path.join(HERE, "_direct.so")
+
+
+def build():
+    src = os.path.join(HERE, "direct.c")
+    tmp = SO + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+    os.replace(tmp, SO)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO):
+            build()
+        _lib = ctypes.CDLL(SO)
+        d, i = ctypes.c_double, ctypes.c_int
+        p = ctypes.c_void_p
+        _lib.oracle_e1.restype = d
+        _lib.oracle_e1.argtypes = [d]
+        _lib.oracle_real_space.argtypes = [i, p, p, d, d, d, d, i, p, p]
+        _lib.oracle_wave_space.argtypes = [i, p, p, i, p, p, i, p, p]
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def real_space(X, mu, L, xi, r_c, targets=None, eta=1.0):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    N = len(X)
+    tg = np.arange(N, dtype=np.int32) if targets is None else np.ascontiguousarray(targets, dtype=np.int32)
+    out = np.zeros(2 * len(tg))
+    lib().oracle_real_space(N, _ptr(X), _ptr(mu), L, xi, eta, r_c, len(tg), _ptr(tg), _ptr(out))
+    return out
+
+
+def wave_space(X, mu, L, xi, targets=None, eta=1.0):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    kv, k2 = F.wave_vectors(L, xi)
+    B = np.ascontiguousarray(F.wave_multiplier(kv, k2, xi, L, eta))
+    kv = np.ascontiguousarray(kv)
+    N = len(X)
+    tg = np.arange(N, dtype=np.int32) if targets is None else np.ascontiguousarray(targets, dtype=np.int32)
+    out = np.zeros(2 * len(tg))
+    lib().oracle_wave_space(N, _ptr(X), _ptr(mu), len(kv), _ptr(kv), _ptr(B), len(tg), _ptr(tg), _ptr(out))
+    return out
