@@ -1,0 +1,207 @@
+/* fbim.h -- C ABI of the MI355X (gfx950) fluctuating boundary integral library.
+ *
+ * The library implements the hot path of the fluctuating boundary integral
+ * method (Bao, Rachh, Keaveny, Greengard, Donev, "A fluctuating boundary
+ * integral method for Brownian suspensions", arXiv:1709.01480) for rigid
+ * bodies in a two-dimensional periodic Stokes fluid:
+ *
+ *   - the single-layer matvec M mu = (M^(t) + M^(a) + M^(w)) mu of Section 3.2
+ *     (Ewald split of the periodic Stokeslet, eqs. 3.13-3.20: real-space pair
+ *     sum with cell lists, Alpert self-correction, and the spectral-Ewald
+ *     spread / FFT / multiplier / inverse FFT / interpolate chain);
+ *   - the first-kind mobility solve (saddle point system eq. 3.8) by GMRES
+ *     with the block-diagonal preconditioner of Section 3.4;
+ *   - the Brownian slip M^(1/2) W split as in eq. 3.27: preconditioned
+ *     Lanczos for (M^(r))^(1/2) (eqs. 3.38-3.42) plus the random Fourier
+ *     field (eq. 3.30);
+ *   - the Euler-Maruyama random-finite-difference step (eq. 4.3).
+ *
+ * Conventions (all entry points):
+ *   - Pointers documented as DEVICE point to memory on the GPU of the
+ *     context; HOST pointers to ordinary host memory.  The caller owns every
+ *     array it passes; the library keeps no pointer after a call returns.
+ *   - Node vectors have 2N doubles: for body b = 0..n-1 (in the order given to
+ *     fbim_set_bodies) and node j = 0..N_p-1 of that body, entries
+ *     (x, y) of node j at parameter s_j = 2 pi j / N_p.
+ *   - Body vectors have 3n doubles: (f_x, f_y, tau) or (u_x, u_y, omega) per
+ *     body; omega x r = omega (-r_y, r_x), tau = r_x f_y - r_y f_x.
+ *   - All work is enqueued on the context's stream (fbim_set_stream); calls
+ *     that return solver information synchronise that stream.
+ *   - Every call returns an fbim_status; on error nothing is written to the
+ *     outputs unless stated, and fbim_last_error() describes the failure.
+ *   - A context is not thread safe; distinct contexts are independent.
+ */
+#ifndef FBIM_H
+#define FBIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FBIM_OK = 0,
+  FBIM_EINVAL = 1,     /* invalid argument or parameter combination */
+  FBIM_ENOMEM = 2,     /* device or host allocation failed */
+  FBIM_EOVERLAP = 3,   /* bodies overlap or nodes of distinct bodies are unresolved */
+  FBIM_ENOCONV = 4,    /* Krylov solver hit its iteration limit (outputs still written) */
+  FBIM_EDEVICE = 5,    /* HIP / rocFFT runtime error */
+  FBIM_ENOTSUP = 6,    /* unsupported option */
+  FBIM_WACCURACY = 7   /* warning: r_Alpert / r_c > 0.6 (Section 4.1); context usable */
+} fbim_status;
+
+enum { FBIM_PREC_FP64 = 0, FBIM_PREC_MIXED = 1 };
+
+/* bits of `parts` in fbim_apply_M */
+enum { FBIM_PART_REAL = 1u, FBIM_PART_ALPERT = 2u, FBIM_PART_WAVE = 4u, FBIM_PART_ALL = 7u };
+
+/* Numerical parameters (Section 3.2, eq. 3.26).  Fields set to 0 are derived:
+ *   r_c = L / n_box;  C_r exp(-xi^2 r_c^2) <= tol_ewald  (C_r = 100);
+ *   C_w exp(-k_max^2 / 4 xi^2) <= tol_ewald (C_w = 1, k_max = pi M / L);
+ *   exp(-pi P / 2) <= tol_ewald (P odd); Gaussian shape m = sqrt(pi P),
+ *   eta_s = (P h xi / m)^2 with h = L / M.
+ * When the grid is given but neither n_box nor xi, n_box is the largest box
+ * count whose xi still satisfies the wave-space estimate. */
+typedef struct {
+  double L;              /* periodic box side (> 0) */
+  double eta;            /* viscosity (> 0) */
+  double kT;             /* thermal energy */
+  double tol_ewald;      /* Ewald / NUFFT tolerance epsilon */
+  double tol_gmres;      /* GMRES relative residual ||b - A x|| <= tol ||b|| */
+  double tol_lanczos;    /* Lanczos stop: ||y_k - y_{k-1}|| <= tol ||y_k|| */
+  double xi;             /* Ewald splitting parameter (0: derive) */
+  double tau_spurious;   /* eigenvalues <= tau * lambda_max treated as spurious (default 1e-8) */
+  int32_t alpert_order;  /* 4 or 8 */
+  int32_t n_box;         /* cells per side; r_c = L / n_box (0: derive); must be >= 3 */
+  int32_t grid_M;        /* Fourier grid M (even; 0: derive) */
+  int32_t P;             /* spreading support (odd; 0: derive) */
+  int32_t precision;     /* FBIM_PREC_FP64 or FBIM_PREC_MIXED */
+  int32_t gmres_restart; /* Krylov dimension before restart (0: 100) */
+  int32_t gmres_maxiter; /* total GMRES iteration limit (0: 1000) */
+  int32_t lanczos_maxiter; /* Lanczos iteration limit (0: 200) */
+  int32_t tile;          /* spreading tile edge in grid points (0: choose) */
+  uint32_t flags;        /* reserved, 0 */
+} fbim_params;
+
+/* Derived quantities reported back by fbim_get_derived. */
+typedef struct {
+  double xi, r_c, h, eta_s, r_alpert;
+  int32_t n_box, grid_M, P, tile;
+  int32_t alpert_j, alpert_a;    /* rule size and dropped-point count */
+  int32_t n_bodies, n_nodes;
+} fbim_derived;
+
+/* Per-call solver report. */
+typedef struct {
+  int32_t gmres_iters;        /* total GMRES iterations of the call (all solves) */
+  int32_t gmres_solves;
+  int32_t lanczos_iters;
+  int32_t status;             /* fbim_status of the last solver */
+  double gmres_residual;      /* largest final true relative residual over the solves */
+  double lanczos_change;      /* final relative change of the Lanczos iterate */
+  double ms_total;            /* wall time of the call (host clock, stream synchronised) */
+} fbim_info;
+
+typedef struct fbim_ctx fbim_ctx;
+
+/* Create a context on the current HIP device.  Parameters are validated and
+ * derived (Section 3.2); the Alpert rule of the requested order is derived
+ * from its moment conditions.  Returns FBIM_EINVAL for inconsistent values
+ * (n_box < 3, odd grid, (P-1)/2 larger than a spreading tile, ...). */
+fbim_status fbim_create(const fbim_params *params, fbim_ctx **out);
+void fbim_destroy(fbim_ctx *ctx);
+const char *fbim_last_error(const fbim_ctx *ctx);  /* never NULL */
+const char *fbim_status_string(fbim_status s);
+
+/* Stream for all subsequent work (a hipStream_t passed as void*; NULL = the
+ * null stream). */
+fbim_status fbim_set_stream(fbim_ctx *ctx, void *stream);
+
+/* Add a body shape given by HOST ref_xy[2*n_p]: the node positions of the
+ * reference configuration (theta = 0, tracking point at the origin) at
+ * s_j = 2 pi j / n_p, j = 0..n_p-1 (Section 3.1).  Off-node points needed by
+ * the Alpert rule are obtained by trigonometric interpolation of ref_xy, so
+ * the curve must be resolved by its nodes.  Precomputes, in FP64 on the host,
+ * the symmetrised Alpert block M^(a)_ref (Sections 3.2-3.3), the reference
+ * self block M_ref and its pseudo-inverse for the block-diagonal
+ * preconditioner (eqs. 3.31-3.37), and G_ref = V (Sigma^+)^(1/2) V^T,
+ * G_ref^+ = V Sigma^(1/2) V^T from M^(r)_ref (eqs. 3.40-3.41, symmetric
+ * reading).  n_p must be even, 16 <= n_p <= 512. */
+fbim_status fbim_add_shape(fbim_ctx *ctx, int32_t n_p, const double *ref_xy, int32_t *shape_id);
+
+/* Helper: ref_xy of the starfish r(s) = r_s (1 + b cos(n_arm s)) (Section 4.4.1). */
+void fbim_starfish(double r_s, double b, int32_t n_arm, int32_t n_p, double *ref_xy);
+
+/* Set the bodies (HOST arrays): shape_id[n], q[2n] tracking points, theta[n].
+ * Builds node positions, the cell list (cells of side L/n_box) and the
+ * spreading tile lists on the device.  Returns FBIM_EOVERLAP if two nodes of
+ * distinct bodies are closer than 0.05 of the smaller node spacing. */
+fbim_status fbim_set_bodies(fbim_ctx *ctx, int32_t n, const int32_t *shape_id, const double *q,
+                            const double *theta);
+
+fbim_status fbim_get_derived(const fbim_ctx *ctx, fbim_derived *out);
+
+/* DEVICE out[2N] <- node positions (wrapped into [0, L)^2), node order. */
+fbim_status fbim_get_nodes(fbim_ctx *ctx, double *x);
+
+/* DEVICE out[2N] = M mu (Section 3.2, eq. 3.20) restricted to `parts`
+ * (FBIM_PART_REAL: trapezoid pairs within r_c, FBIM_PART_ALPERT: symmetrised
+ * Alpert correction, FBIM_PART_WAVE: spectral-Ewald M^(w)).  mu, out: DEVICE,
+ * 2N doubles, must not alias.  Precision follows the context. */
+fbim_status fbim_apply_M(fbim_ctx *ctx, const double *mu, double *out, uint32_t parts);
+
+/* DEVICE out[2N] = (M^(w))^(1/2) W^(w) by eq. 3.30 from DEVICE W_grid[2 M M]
+ * standard normals laid out [component][y][x]: W(kappa) = FFT(W_grid)/M,
+ * scaled by V^(-1/2) sqrt(H(k))/k (I - k k^T/k^2), inverse FFT keeping the
+ * real part, Gaussian interpolation.  Excludes the sqrt(2 kT/dt) factor. */
+fbim_status fbim_random_field(fbim_ctx *ctx, const double *W_grid, double *out);
+
+/* DEVICE out[2N] = G^+ (G M^(r) G^T)^(1/2) W_r (eq. 3.38) by Lanczos with
+ * full reorthogonalisation, from DEVICE W_r[2N]. */
+fbim_status fbim_sqrt_Mr(fbim_ctx *ctx, const double *W_r, double *out, fbim_info *info);
+
+/* Mobility solve of eq. 3.8: [M -K; -K^T 0][mu; U] = -[slip; F].
+ * DEVICE F[3n]; DEVICE slip[2N] or NULL (zero slip); DEVICE U[3n];
+ * DEVICE mu_out[2N] or NULL.  FBIM_ENOCONV still writes U and mu. */
+fbim_status fbim_mobility(fbim_ctx *ctx, const double *F, const double *slip, double *U,
+                          double *mu_out, fbim_info *info);
+
+/* U = N F + sqrt(2 kT/dt) N^(1/2) W (eqs. 2.4 and 3.9), with the slip
+ * sqrt(2 kT/dt) (v^(r) + v^(w)) built from DEVICE W_r[2N] and W_grid[2 M M]
+ * standard normals (eq. 3.27). */
+fbim_status fbim_brownian_velocity(fbim_ctx *ctx, double dt, const double *F, const double *W_r,
+                                   const double *W_grid, double *U, fbim_info *info);
+
+/* One Euler-Maruyama step with the centred random finite difference (eq. 4.3):
+ *   dQ = dt U0 + dt kT/delta [N(Q + delta/2 Wt) Wt - N(Q - delta/2 Wt) Wt]
+ * with U0 from fbim_brownian_velocity at Q.  DEVICE F[3n], W_r[2N],
+ * W_grid[2MM], W_tilde[3n]; DEVICE dQ[3n] = (dq_x, dq_y, dtheta) per body.
+ * If apply != 0 the bodies are moved by dQ afterwards; otherwise the
+ * configuration is restored to Q. */
+fbim_status fbim_step_em_rfd(fbim_ctx *ctx, double dt, double delta, const double *F,
+                             const double *W_r, const double *W_grid, const double *W_tilde,
+                             double *dQ, int32_t apply, fbim_info *info);
+
+/* Host utility (no device needed): derive parameters as fbim_create does.
+ * Writes the derived values into *out; returns FBIM_EINVAL on bad input. */
+fbim_status fbim_derive_params(const fbim_params *in, fbim_derived *out);
+
+/* Host utility: the Alpert log-singular end correction of the given order
+ * (4 or 8) derived from its moment conditions (Section 3.1): j nodes chi[j]
+ * and weights w[j] replacing the a - 1 trapezoid points next to the
+ * singularity.  HOST chi, w must hold 8 doubles. */
+fbim_status fbim_alpert_rule(int32_t order, int32_t *j, int32_t *a, double *chi, double *w);
+
+/* Kernel timing (for measurement): when enabled, device events bracket each
+ * launch of the named kernel class; fbim_kernel_time returns the summed
+ * milliseconds and launch count since the last reset.  Classes: "pair",
+ * "alpert", "spread", "interp", "fft", "multiplier", "precond", "blas". */
+fbim_status fbim_set_timing(fbim_ctx *ctx, int32_t enable);
+fbim_status fbim_kernel_time(fbim_ctx *ctx, const char *name, double *ms, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FBIM_H */

@@ -1,0 +1,252 @@
+"""Python binding of the MI355X FBIM library (libfbim.so, C ABI in include/fbim.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Device arrays are torch tensors on the GPU (float64, contiguous); torch is used
+for device memory and the current stream.  If the built library is missing the
+import of this module fails loudly -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["Params", "Derived", "Info", "Context", "lib", "derive_params", "alpert_rule", "starfish",
+           "PART_REAL", "PART_ALPERT", "PART_WAVE", "PART_ALL", "PREC_FP64", "PREC_MIXED", "FbimError",
+           "LIB_PATH"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfbim.so")
+
+PART_REAL, PART_ALPERT, PART_WAVE, PART_ALL = 1, 2, 4, 7
+PREC_FP64, PREC_MIXED = 0, 1
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EOVERLAP", 4: "ENOCONV", 5: "EDEVICE", 6: "ENOTSUP",
+          7: "WACCURACY"}
+
+
+class FbimError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_double), ("eta", ctypes.c_double), ("kT", ctypes.c_double),
+                ("tol_ewald", ctypes.c_double), ("tol_gmres", ctypes.c_double),
+                ("tol_lanczos", ctypes.c_double), ("xi", ctypes.c_double), ("tau_spurious", ctypes.c_double),
+                ("alpert_order", ctypes.c_int32), ("n_box", ctypes.c_int32), ("grid_M", ctypes.c_int32),
+                ("P", ctypes.c_int32), ("precision", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
+                ("gmres_maxiter", ctypes.c_int32), ("lanczos_maxiter", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class Derived(ctypes.Structure):
+    _fields_ = [("xi", ctypes.c_double), ("r_c", ctypes.c_double), ("h", ctypes.c_double),
+                ("eta_s", ctypes.c_double), ("r_alpert", ctypes.c_double), ("n_box", ctypes.c_int32),
+                ("grid_M", ctypes.c_int32), ("P", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("alpert_j", ctypes.c_int32), ("alpert_a", ctypes.c_int32), ("n_bodies", ctypes.c_int32),
+                ("n_nodes", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("gmres_iters", ctypes.c_int32), ("gmres_solves", ctypes.c_int32),
+                ("lanczos_iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("gmres_residual", ctypes.c_double), ("lanczos_change", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libfbim.so is not built; run `python -m paper_1709_01480_amd.build` "
+                          "(no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    p, i32, u32, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "fbim_create": (i32, [P(Params), P(p)]),
+        "fbim_destroy": (None, [p]),
+        "fbim_last_error": (ctypes.c_char_p, [p]),
+        "fbim_status_string": (ctypes.c_char_p, [i32]),
+        "fbim_set_stream": (i32, [p, p]),
+        "fbim_add_shape": (i32, [p, i32, p, P(i32)]),
+        "fbim_starfish": (None, [d, d, i32, i32, p]),
+        "fbim_set_bodies": (i32, [p, i32, p, p, p]),
+        "fbim_get_derived": (i32, [p, P(Derived)]),
+        "fbim_get_nodes": (i32, [p, p]),
+        "fbim_apply_M": (i32, [p, p, p, u32]),
+        "fbim_random_field": (i32, [p, p, p]),
+        "fbim_sqrt_Mr": (i32, [p, p, p, P(Info)]),
+        "fbim_mobility": (i32, [p, p, p, p, p, P(Info)]),
+        "fbim_brownian_velocity": (i32, [p, d, p, p, p, p, P(Info)]),
+        "fbim_step_em_rfd": (i32, [p, d, d, p, p, p, p, p, i32, P(Info)]),
+        "fbim_derive_params": (i32, [P(Params), P(Derived)]),
+        "fbim_alpert_rule": (i32, [i32, P(i32), P(i32), p, p]),
+        "fbim_set_timing": (i32, [p, i32]),
+        "fbim_kernel_time": (i32, [p, ctypes.c_char_p, P(d), P(ctypes.c_int64)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+def make_params(**kw) -> Params:
+    prm = Params()
+    prm.eta = 1.0
+    prm.kT = 1.0
+    prm.tol_gmres = 1e-6
+    prm.tol_lanczos = 1e-6
+    prm.tau_spurious = 1e-8
+    prm.alpert_order = 4
+    for k, v in kw.items():
+        setattr(prm, k, v)
+    return prm
+
+
+def derive_params(**kw) -> dict:
+    out = Derived()
+    st = lib.fbim_derive_params(ctypes.byref(make_params(**kw)), ctypes.byref(out))
+    if st != 0:
+        raise FbimError(st, "parameter derivation failed")
+    return out.as_dict()
+
+
+def alpert_rule(order: int):
+    import numpy as np
+    j, a = ctypes.c_int32(), ctypes.c_int32()
+    chi = (ctypes.c_double * 8)()
+    w = (ctypes.c_double * 8)()
+    st = lib.fbim_alpert_rule(order, ctypes.byref(j), ctypes.byref(a), chi, w)
+    if st != 0:
+        raise FbimError(st, "no Alpert rule")
+    return np.array(chi[:j.value]), np.array(w[:j.value]), a.value
+
+
+def starfish(r_s: float, b: float, n_arm: int, n_p: int):
+    import numpy as np
+    out = np.zeros(2 * n_p)
+    lib.fbim_starfish(r_s, b, n_arm, n_p, out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def _dptr(t, n=None):
+    """Device pointer of a float64 contiguous GPU tensor (checked)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 GPU tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError("expected %d elements, got %d" % (n, t.numel()))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One library context (fbim_ctx) bound to torch's current stream."""
+
+    def __init__(self, **params):
+        import torch
+        self._ctx = ctypes.c_void_p()
+        self.params = make_params(**params)
+        st = lib.fbim_create(ctypes.byref(self.params), ctypes.byref(self._ctx))
+        if st != 0:
+            raise FbimError(st, "fbim_create failed")
+        self._check(lib.fbim_set_stream(self._ctx, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        self.n = 0
+        self.N = 0
+
+    def _check(self, st, allow=()):
+        if st != 0 and st not in allow:
+            raise FbimError(st, lib.fbim_last_error(self._ctx).decode())
+        return st
+
+    def close(self):
+        if self._ctx:
+            lib.fbim_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- setup
+    def add_shape(self, ref_xy):
+        import numpy as np
+        ref = np.ascontiguousarray(ref_xy, dtype=np.float64)
+        sid = ctypes.c_int32()
+        st = lib.fbim_add_shape(self._ctx, len(ref) // 2, ref.ctypes.data_as(ctypes.c_void_p), ctypes.byref(sid))
+        self._check(st, allow=(7,))
+        return sid.value
+
+    def set_bodies(self, shape_id, q, theta):
+        import numpy as np
+        sid = np.ascontiguousarray(shape_id, dtype=np.int32)
+        q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        self._check(lib.fbim_set_bodies(self._ctx, len(th), sid.ctypes.data_as(ctypes.c_void_p),
+                                        q.ctypes.data_as(ctypes.c_void_p), th.ctypes.data_as(ctypes.c_void_p)))
+        d = self.get_derived()
+        self.n, self.N = d["n_bodies"], d["n_nodes"]
+
+    def get_derived(self) -> dict:
+        out = Derived()
+        self._check(lib.fbim_get_derived(self._ctx, ctypes.byref(out)))
+        return out.as_dict()
+
+    # -- hot path
+    def get_nodes(self, x):
+        self._check(lib.fbim_get_nodes(self._ctx, _dptr(x, 2 * self.N)))
+
+    def apply_M(self, mu, out, parts=PART_ALL):
+        self._check(lib.fbim_apply_M(self._ctx, _dptr(mu, 2 * self.N), _dptr(out, 2 * self.N), parts))
+
+    def random_field(self, W_grid, out):
+        M = self.get_derived()["grid_M"]
+        self._check(lib.fbim_random_field(self._ctx, _dptr(W_grid, 2 * M * M), _dptr(out, 2 * self.N)))
+
+    def sqrt_Mr(self, W_r, out):
+        info = Info()
+        self._check(lib.fbim_sqrt_Mr(self._ctx, _dptr(W_r, 2 * self.N), _dptr(out, 2 * self.N),
+                                     ctypes.byref(info)))
+        return info.as_dict()
+
+    def mobility(self, F, U, slip=None, mu_out=None):
+        info = Info()
+        self._check(lib.fbim_mobility(self._ctx, _dptr(F, 3 * self.n),
+                                      None if slip is None else _dptr(slip, 2 * self.N), _dptr(U, 3 * self.n),
+                                      None if mu_out is None else _dptr(mu_out, 2 * self.N),
+                                      ctypes.byref(info)))
+        return info.as_dict()
+
+    def brownian_velocity(self, dt, F, W_r, W_grid, U):
+        M = self.get_derived()["grid_M"]
+        info = Info()
+        self._check(lib.fbim_brownian_velocity(self._ctx, dt, _dptr(F, 3 * self.n), _dptr(W_r, 2 * self.N),
+                                               _dptr(W_grid, 2 * M * M), _dptr(U, 3 * self.n),
+                                               ctypes.byref(info)))
+        return info.as_dict()
+
+    def step_em_rfd(self, dt, delta, F, W_r, W_grid, W_tilde, dQ, apply=False):
+        M = self.get_derived()["grid_M"]
+        info = Info()
+        self._check(lib.fbim_step_em_rfd(self._ctx, dt, delta, _dptr(F, 3 * self.n), _dptr(W_r, 2 * self.N),
+                                         _dptr(W_grid, 2 * M * M), _dptr(W_tilde, 3 * self.n),
+                                         _dptr(dQ, 3 * self.n), 1 if apply else 0, ctypes.byref(info)))
+        return info.as_dict()
+
+    # -- measurement
+    def set_timing(self, enable=True):
+        self._check(lib.fbim_set_timing(self._ctx, 1 if enable else 0))
+
+    def kernel_time(self, name):
+        ms, cnt = ctypes.c_double(), ctypes.c_int64()
+        self._check(lib.fbim_kernel_time(self._ctx, name.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value

@@ -1,0 +1,1134 @@
+// C ABI of the FBIM library: context, geometry, the single-layer matvec
+// pipeline, GMRES (mobility), Lanczos ((M^(r))^(1/2)), Brownian velocity and
+// the EM-RFD step.  Host code driving the gfx950 kernels and rocFFT.
+#include <hip/hip_runtime.h>
+#include <rocfft/rocfft.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/fbim.h"
+#include "host_math.h"
+#include "kernels.h"
+
+using namespace fbim;
+
+namespace {
+
+struct ShapeDev {
+  ShapeHost h;
+  double *ref = nullptr, *band = nullptr, *Mp = nullptr, *Pref = nullptr, *Nt = nullptr, *G = nullptr,
+         *Gp = nullptr;
+};
+
+template <class T>
+hipError_t dalloc(T *&p, size_t n) {
+  if (p) {
+    hipFree(p);
+    p = nullptr;
+  }
+  if (n == 0) return hipSuccess;
+  return hipMalloc((void **)&p, n * sizeof(T));
+}
+
+template <class T>
+void dfree(T *&p) {
+  if (p) hipFree(p);
+  p = nullptr;
+}
+
+struct TimedLaunch {
+  hipEvent_t a, b;
+};
+
+bool g_rocfft_ready = false;
+
+}  // namespace
+
+struct fbim_ctx {
+  fbim_params p{};
+  Derived d{};
+  int order = 4, aj = 0, aa = 0;
+  double chi[8]{}, w[8]{};
+  std::string err;
+  hipStream_t stream = nullptr;
+  bool mixed = false;
+
+  std::vector<ShapeDev> shapes;
+  double **d_ref_arr = nullptr, **d_band_arr = nullptr, **d_Mp_arr = nullptr, **d_Pref_arr = nullptr,
+         **d_Nt_arr = nullptr, **d_G_arr = nullptr, **d_Gp_arr = nullptr;
+  int *d_band = nullptr, *d_np = nullptr;
+  int max_np = 0;
+
+  // geometry
+  int n = 0, N = 0, capN = 0, capn = 0;
+  std::vector<int> h_shape, h_off;
+  std::vector<double> h_q, h_theta;
+  int *d_shape = nullptr, *d_off = nullptr, *d_body = nullptr;
+  double *d_q = nullptr, *d_theta = nullptr, *d_x = nullptr;
+  bool have_bodies = false;
+
+  // cell list
+  int ncell = 0, max_cell = 0, nbatch = 0;
+  int *d_ckey = nullptr, *d_ccount = nullptr, *d_cstart = nullptr, *d_cperm = nullptr, *d_ccursor = nullptr;
+  double *d_xs = nullptr;
+  // tiles
+  int nts = 0, ntile = 0, max_tile = 0;
+  int *d_tkey = nullptr, *d_tcount = nullptr, *d_tstart = nullptr, *d_tperm = nullptr, *d_tcursor = nullptr;
+  double *d_xt = nullptr;
+  int *d_anchor = nullptr;
+  int *d_scal_int = nullptr;  // [0] max count, [1] overlap flag
+
+  // matvec scratch
+  double *d_mus = nullptr, *d_mut = nullptr;
+  float *d_xs32 = nullptr, *d_mus32 = nullptr, *d_xt32 = nullptr, *d_mut32 = nullptr;
+  double *d_grid = nullptr, *d_spec = nullptr;
+  float *d_grid32 = nullptr, *d_spec32 = nullptr;
+  rocfft_plan fwd = nullptr, inv = nullptr, fwd32 = nullptr, inv32 = nullptr;
+  rocfft_execution_info einfo = nullptr;
+  void *fft_work = nullptr;
+  size_t fft_work_bytes = 0;
+  double *d_e1tab = nullptr;
+  float *d_e1tab32 = nullptr;
+
+  // Krylov
+  int restart = 100, gmres_max = 1000, lanczos_max = 200;
+  size_t ntot = 0, capV = 0;
+  int kn = -1;
+  double *d_V = nullptr;      // (restart+1) * ntot  (also Lanczos basis)
+  double *d_w = nullptr, *d_t1 = nullptr, *d_t2 = nullptr, *d_b = nullptr, *d_x2 = nullptr, *d_r = nullptr;
+  double *d_partial = nullptr, *d_h = nullptr, *d_h2 = nullptr, *d_nrm = nullptr, *d_c = nullptr;
+  int nblk = 256;
+  double *d_vec_a = nullptr, *d_vec_b = nullptr, *d_U3 = nullptr, *d_U4 = nullptr, *d_U5 = nullptr;
+
+  // timing
+  bool timing = false;
+  std::map<std::string, std::vector<TimedLaunch>> pending;
+  std::map<std::string, std::pair<double, int64_t>> acc;
+
+  GeomDev geom() const {
+    GeomDev g;
+    g.n = n;
+    g.N = N;
+    g.shape = d_shape;
+    g.off = d_off;
+    g.body = d_body;
+    g.q = d_q;
+    g.theta = d_theta;
+    g.ref = d_ref_arr;
+    g.np = d_np;
+    return g;
+  }
+  BodyMats mats() const {
+    BodyMats m;
+    m.Mp = d_Mp_arr;
+    m.Pref = d_Pref_arr;
+    m.Nt = d_Nt_arr;
+    m.G = d_G_arr;
+    m.Gp = d_Gp_arr;
+    m.max_np = max_np;
+    return m;
+  }
+};
+
+namespace {
+
+fbim_status fail(fbim_ctx *c, fbim_status s, const std::string &msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                        \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess)                                                                        \
+      return fail(ctx, FBIM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+#define FFTCHK(ctx, expr)                                                                        \
+  do {                                                                                           \
+    rocfft_status e_ = (expr);                                                                   \
+    if (e_ != rocfft_status_success)                                                             \
+      return fail(ctx, FBIM_EDEVICE, std::string(#expr) + ": rocfft status " + std::to_string((int)e_)); \
+  } while (0)
+
+#define STCHK(expr)                    \
+  do {                                 \
+    fbim_status s_ = (expr);           \
+    if (s_ != FBIM_OK) return s_;      \
+  } while (0)
+
+// RAII timing bracket of one launch class
+struct Timer {
+  fbim_ctx *c;
+  const char *name;
+  TimedLaunch t{};
+  Timer(fbim_ctx *c_, const char *n_) : c(c_), name(n_) {
+    if (c->timing) {
+      hipEventCreate(&t.a);
+      hipEventCreate(&t.b);
+      hipEventRecord(t.a, c->stream);
+    }
+  }
+  ~Timer() {
+    if (c->timing) {
+      hipEventRecord(t.b, c->stream);
+      c->pending[name].push_back(t);
+    }
+  }
+};
+
+void resolve_timing(fbim_ctx *c) {
+  if (c->pending.empty()) return;
+  hipStreamSynchronize(c->stream);
+  for (auto &kv : c->pending) {
+    auto &a = c->acc[kv.first];
+    for (auto &t : kv.second) {
+      float ms = 0;
+      hipEventElapsedTime(&ms, t.a, t.b);
+      a.first += ms;
+      a.second += 1;
+      hipEventDestroy(t.a);
+      hipEventDestroy(t.b);
+    }
+  }
+  c->pending.clear();
+}
+
+template <class T>
+fbim_status upload(fbim_ctx *c, T *&dst, const std::vector<T> &src) {
+  HIPCHK(c, dalloc(dst, src.size()));
+  if (!src.empty()) HIPCHK(c, hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  return FBIM_OK;
+}
+
+fbim_status rebuild_shape_arrays(fbim_ctx *c) {
+  std::vector<double *> ref, band, Mp, Pref, Nt, G, Gp;
+  std::vector<int> bw, np;
+  for (auto &s : c->shapes) {
+    ref.push_back(s.ref);
+    band.push_back(s.band);
+    Mp.push_back(s.Mp);
+    Pref.push_back(s.Pref);
+    Nt.push_back(s.Nt);
+    G.push_back(s.G);
+    Gp.push_back(s.Gp);
+    bw.push_back(s.h.band);
+    np.push_back(s.h.n_p);
+  }
+  STCHK(upload(c, c->d_ref_arr, ref));
+  STCHK(upload(c, c->d_band_arr, band));
+  STCHK(upload(c, c->d_Mp_arr, Mp));
+  STCHK(upload(c, c->d_Pref_arr, Pref));
+  STCHK(upload(c, c->d_Nt_arr, Nt));
+  STCHK(upload(c, c->d_G_arr, G));
+  STCHK(upload(c, c->d_Gp_arr, Gp));
+  STCHK(upload(c, c->d_band, bw));
+  STCHK(upload(c, c->d_np, np));
+  return FBIM_OK;
+}
+
+fbim_status setup_fft(fbim_ctx *c) {
+  if (!g_rocfft_ready) {
+    FFTCHK(c, rocfft_setup());
+    g_rocfft_ready = true;
+  }
+  const size_t len[2] = {(size_t)c->d.M, (size_t)c->d.M};
+  FFTCHK(c, rocfft_plan_create(&c->fwd, rocfft_placement_notinplace, rocfft_transform_type_real_forward,
+                               rocfft_precision_double, 2, len, 2, nullptr));
+  FFTCHK(c, rocfft_plan_create(&c->inv, rocfft_placement_notinplace, rocfft_transform_type_real_inverse,
+                               rocfft_precision_double, 2, len, 2, nullptr));
+  size_t w1 = 0, w2 = 0, w3 = 0, w4 = 0;
+  FFTCHK(c, rocfft_plan_get_work_buffer_size(c->fwd, &w1));
+  FFTCHK(c, rocfft_plan_get_work_buffer_size(c->inv, &w2));
+  if (c->mixed) {
+    FFTCHK(c, rocfft_plan_create(&c->fwd32, rocfft_placement_notinplace, rocfft_transform_type_real_forward,
+                                 rocfft_precision_single, 2, len, 2, nullptr));
+    FFTCHK(c, rocfft_plan_create(&c->inv32, rocfft_placement_notinplace, rocfft_transform_type_real_inverse,
+                                 rocfft_precision_single, 2, len, 2, nullptr));
+    FFTCHK(c, rocfft_plan_get_work_buffer_size(c->fwd32, &w3));
+    FFTCHK(c, rocfft_plan_get_work_buffer_size(c->inv32, &w4));
+  }
+  c->fft_work_bytes = std::max(std::max(w1, w2), std::max(w3, w4));
+  if (c->fft_work_bytes) HIPCHK(c, hipMalloc(&c->fft_work, c->fft_work_bytes));
+  FFTCHK(c, rocfft_execution_info_create(&c->einfo));
+  if (c->fft_work_bytes) FFTCHK(c, rocfft_execution_info_set_work_buffer(c->einfo, c->fft_work, c->fft_work_bytes));
+  FFTCHK(c, rocfft_execution_info_set_stream(c->einfo, c->stream));
+  const size_t M = c->d.M;
+  HIPCHK(c, dalloc(c->d_grid, 2 * M * M));
+  HIPCHK(c, dalloc(c->d_spec, 2 * 2 * M * (M / 2 + 1)));
+  if (c->mixed) {
+    HIPCHK(c, dalloc(c->d_grid32, 2 * M * M));
+    HIPCHK(c, dalloc(c->d_spec32, 2 * 2 * M * (M / 2 + 1)));
+  }
+  return FBIM_OK;
+}
+
+fbim_status ensure_krylov(fbim_ctx *c) {
+  const size_t ntot = 2 * (size_t)c->N + 3 * (size_t)c->n;
+  const size_t cols = (size_t)std::max(c->restart, c->lanczos_max) + 1;
+  if (ntot == c->ntot && c->capV == cols && c->kn == c->n) return FBIM_OK;
+  c->kn = c->n;
+  c->ntot = ntot;
+  c->capV = cols;
+  HIPCHK(c, dalloc(c->d_V, cols * ntot));
+  HIPCHK(c, dalloc(c->d_w, ntot));
+  HIPCHK(c, dalloc(c->d_t1, ntot));
+  HIPCHK(c, dalloc(c->d_t2, ntot));
+  HIPCHK(c, dalloc(c->d_b, ntot));
+  HIPCHK(c, dalloc(c->d_x2, ntot));
+  HIPCHK(c, dalloc(c->d_r, ntot));
+  HIPCHK(c, dalloc(c->d_partial, (size_t)c->nblk * cols));
+  HIPCHK(c, dalloc(c->d_h, cols));
+  HIPCHK(c, dalloc(c->d_h2, cols));
+  HIPCHK(c, dalloc(c->d_nrm, 4));
+  HIPCHK(c, dalloc(c->d_c, cols));
+  HIPCHK(c, dalloc(c->d_vec_a, 2 * (size_t)c->N));
+  HIPCHK(c, dalloc(c->d_vec_b, 2 * (size_t)c->N));
+  HIPCHK(c, dalloc(c->d_U3, 3 * (size_t)c->n));
+  HIPCHK(c, dalloc(c->d_U4, 3 * (size_t)c->n));
+  HIPCHK(c, dalloc(c->d_U5, 3 * (size_t)c->n));
+  return FBIM_OK;
+}
+
+// ------------------------------------------------------------------ geometry
+fbim_status build_geometry(fbim_ctx *c) {
+  const int N = c->N, n = c->n;
+  hipStream_t s = c->stream;
+  HIPCHK(c, hipMemcpyAsync(c->d_q, c->h_q.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_theta, c->h_theta.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(c, launch_nodes(c->geom(), c->d.L, c->d_x, s));
+  // cell list
+  HIPCHK(c, hipMemsetAsync(c->d_ccount, 0, c->ncell * sizeof(int), s));
+  HIPCHK(c, hipMemsetAsync(c->d_ccursor, 0, c->ncell * sizeof(int), s));
+  HIPCHK(c, launch_cell_keys(N, c->d_x, c->d.L, c->d.n_box, c->d_ckey, c->d_ccount, s));
+  HIPCHK(c, launch_scan(c->ncell, c->d_ccount, c->d_cstart, c->d_scal_int, s));
+  HIPCHK(c, launch_scatter(N, c->d_ckey, c->d_cstart, c->d_ccursor, c->d_cperm, s));
+  HIPCHK(c, launch_sort_bins(c->ncell, c->d_cstart, c->d_cperm, s));
+  HIPCHK(c, launch_gather2(N, c->d_cperm, c->d_x, c->d_xs, s));
+  // tiles
+  HIPCHK(c, hipMemsetAsync(c->d_tcount, 0, c->ntile * sizeof(int), s));
+  HIPCHK(c, hipMemsetAsync(c->d_tcursor, 0, c->ntile * sizeof(int), s));
+  HIPCHK(c, launch_tile_keys(N, c->d_x, c->d.h, c->d.M, c->d.tile, c->d_tkey, c->d_tcount, s));
+  HIPCHK(c, launch_scan(c->ntile, c->d_tcount, c->d_tstart, c->d_scal_int + 2, s));
+  HIPCHK(c, launch_scatter(N, c->d_tkey, c->d_tstart, c->d_tcursor, c->d_tperm, s));
+  HIPCHK(c, launch_sort_bins(c->ntile, c->d_tstart, c->d_tperm, s));
+  HIPCHK(c, launch_gather2(N, c->d_tperm, c->d_x, c->d_xt, s));
+  HIPCHK(c, launch_anchors(N, c->d_tperm, c->d_x, c->d.h, c->d_anchor, s));
+  if (c->mixed) {
+    HIPCHK(c, launch_cast_f32(2 * (size_t)N, c->d_xs, c->d_xs32, s));
+    HIPCHK(c, launch_cast_f32(2 * (size_t)N, c->d_xt, c->d_xt32, s));
+  }
+  // overlap check: nodes of distinct bodies closer than 5% of the smallest node spacing
+  double spacing = 1e300;
+  for (auto &sh : c->shapes) {
+    for (int j = 0; j < sh.h.n_p; ++j) {
+      const int k = (j + 1) % sh.h.n_p;
+      const double dx = sh.h.ref_xy[2 * j] - sh.h.ref_xy[2 * k], dy = sh.h.ref_xy[2 * j + 1] - sh.h.ref_xy[2 * k + 1];
+      spacing = std::min(spacing, std::sqrt(dx * dx + dy * dy));
+    }
+  }
+  HIPCHK(c, hipMemsetAsync(c->d_scal_int + 1, 0, sizeof(int), s));
+  HIPCHK(c, launch_overlap(N, c->d_cstart, c->d_cperm, c->d_xs, c->d_body, c->d.n_box, c->d.L, 0.05 * spacing,
+                           c->d_scal_int + 1, s));
+  int hv[3];
+  HIPCHK(c, hipMemcpyAsync(hv, c->d_scal_int, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  c->max_cell = hv[0];
+  c->nbatch = std::max(1, (hv[0] + 63) / 64);
+  c->max_tile = hv[2];
+  if (hv[1]) return fail(c, FBIM_EOVERLAP, "nodes of distinct bodies closer than 5% of the node spacing");
+  return FBIM_OK;
+}
+
+// ------------------------------------------------------------------ matvec
+fbim_status apply_M(fbim_ctx *c, const double *mu, double *out, unsigned parts) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  if (!c->have_bodies) return fail(c, FBIM_EINVAL, "no bodies set");
+  if (parts & FBIM_PART_REAL) {
+    PairArgs a;
+    a.cell_start = c->d_cstart;
+    a.perm = c->d_cperm;
+    a.nb = c->d.n_box;
+    a.nbatch = c->nbatch;
+    a.L = c->d.L;
+    a.rc2 = c->d.r_c * c->d.r_c;
+    a.xi2 = c->d.xi * c->d.xi;
+    a.cG = 1.0 / (4.0 * kPi * c->p.eta);
+    a.e1tab = c->d_e1tab;
+    a.e1tab32 = c->d_e1tab32;
+    if (c->mixed) {
+      HIPCHK(c, launch_gather2f(N, c->d_cperm, mu, c->d_mus32, s));
+      Timer t(c, "pair");
+      HIPCHK(c, launch_pair_f32(a, c->d_xs32, c->d_mus32, out, s));
+    } else {
+      HIPCHK(c, launch_gather2(N, c->d_cperm, mu, c->d_mus, s));
+      Timer t(c, "pair");
+      HIPCHK(c, launch_pair_f64(a, c->d_xs, c->d_mus, out, s));
+    }
+  } else {
+    HIPCHK(c, launch_fill(2 * (size_t)N, 0.0, out, s));
+  }
+  if (parts & FBIM_PART_ALPERT) {
+    Timer t(c, "alpert");
+    HIPCHK(c, launch_alpert(c->geom(), c->d_band_arr, c->d_band, mu, out, 1, s));
+  }
+  if (parts & FBIM_PART_WAVE) {
+    WaveArgs w;
+    w.M = c->d.M;
+    w.T = c->d.tile;
+    w.P = c->d.P;
+    w.nts = c->nts;
+    w.h = c->d.h;
+    w.L = c->d.L;
+    w.ag = 2.0 * c->d.xi * c->d.xi / c->d.eta_s;
+    w.cg = 2.0 * c->d.xi * c->d.xi / (kPi * c->d.eta_s);
+    w.tile_start = c->d_tstart;
+    w.anchor = c->d_anchor;
+    const double scale = c->d.h * c->d.h / (c->p.eta * c->d.L * c->d.L);
+    if (c->mixed) {
+      HIPCHK(c, launch_gather2f(N, c->d_tperm, mu, c->d_mut32, s));
+      {
+        Timer t(c, "spread");
+        HIPCHK(c, launch_spread_f32(w, c->d_xt32, c->d_mut32, c->d_grid32, s));
+      }
+      {
+        Timer t(c, "fft");
+        void *in[1] = {c->d_grid32}, *o[1] = {c->d_spec32};
+        FFTCHK(c, rocfft_execute(c->fwd32, in, o, c->einfo));
+      }
+      {
+        Timer t(c, "multiplier");
+        HIPCHK(c, launch_multiplier_f32(c->d.M, c->d.L, c->d.xi, c->d.eta_s, scale, 0, c->d_spec32, s));
+      }
+      {
+        Timer t(c, "fft");
+        void *in[1] = {c->d_spec32}, *o[1] = {c->d_grid32};
+        FFTCHK(c, rocfft_execute(c->inv32, in, o, c->einfo));
+      }
+      Timer t(c, "interp");
+      HIPCHK(c, launch_interp_f32(w, c->d_xt32, c->d_tperm, c->d_grid32, out, s));
+    } else {
+      HIPCHK(c, launch_gather2(N, c->d_tperm, mu, c->d_mut, s));
+      {
+        Timer t(c, "spread");
+        HIPCHK(c, launch_spread_f64(w, c->d_xt, c->d_mut, c->d_grid, s));
+      }
+      {
+        Timer t(c, "fft");
+        void *in[1] = {c->d_grid}, *o[1] = {c->d_spec};
+        FFTCHK(c, rocfft_execute(c->fwd, in, o, c->einfo));
+      }
+      {
+        Timer t(c, "multiplier");
+        HIPCHK(c, launch_multiplier_f64(c->d.M, c->d.L, c->d.xi, c->d.eta_s, scale, 0, c->d_spec, s));
+      }
+      {
+        Timer t(c, "fft");
+        void *in[1] = {c->d_spec}, *o[1] = {c->d_grid};
+        FFTCHK(c, rocfft_execute(c->inv, in, o, c->einfo));
+      }
+      Timer t(c, "interp");
+      HIPCHK(c, launch_interp_f64(w, c->d_xt, c->d_tperm, c->d_grid, out, s));
+    }
+  }
+  return FBIM_OK;
+}
+
+fbim_status random_field(fbim_ctx *c, const double *W_grid, double *out) {
+  hipStream_t s = c->stream;
+  const size_t M = c->d.M;
+  WaveArgs w;
+  w.M = c->d.M;
+  w.T = c->d.tile;
+  w.P = c->d.P;
+  w.nts = c->nts;
+  w.h = c->d.h;
+  w.L = c->d.L;
+  w.ag = 2.0 * c->d.xi * c->d.xi / c->d.eta_s;
+  w.cg = 2.0 * c->d.xi * c->d.xi / (kPi * c->d.eta_s);
+  w.tile_start = c->d_tstart;
+  w.anchor = c->d_anchor;
+  const double scale = 1.0 / ((double)M * std::sqrt(c->p.eta * c->d.L * c->d.L));
+  HIPCHK(c, launch_fill(2 * (size_t)c->N, 0.0, out, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_grid, W_grid, 2 * M * M * sizeof(double), hipMemcpyDeviceToDevice, s));
+  {
+    Timer t(c, "fft");
+    void *in[1] = {c->d_grid}, *o[1] = {c->d_spec};
+    FFTCHK(c, rocfft_execute(c->fwd, in, o, c->einfo));
+  }
+  {
+    Timer t(c, "multiplier");
+    HIPCHK(c, launch_multiplier_f64(c->d.M, c->d.L, c->d.xi, c->d.eta_s, scale, 1, c->d_spec, s));
+  }
+  {
+    Timer t(c, "fft");
+    void *in[1] = {c->d_spec}, *o[1] = {c->d_grid};
+    FFTCHK(c, rocfft_execute(c->inv, in, o, c->einfo));
+  }
+  Timer t(c, "interp");
+  HIPCHK(c, launch_interp_f64(w, c->d_xt, c->d_tperm, c->d_grid, out, s));
+  return FBIM_OK;
+}
+
+// saddle operator of eq. 3.8: y = [M mu - K U; -K^T mu]
+fbim_status apply_saddle(fbim_ctx *c, const double *x, double *y) {
+  const size_t twoN = 2 * (size_t)c->N;
+  STCHK(apply_M(c, x, y, FBIM_PART_ALL));
+  HIPCHK(c, launch_sub_KU(c->geom(), x + twoN, y, c->stream));
+  HIPCHK(c, launch_KT(c->geom(), x, -1.0, y + twoN, c->stream));
+  return FBIM_OK;
+}
+
+fbim_status apply_precond(fbim_ctx *c, const double *z, double *y) {
+  Timer t(c, "precond");
+  HIPCHK(c, launch_precond(c->geom(), c->mats(), z, y, c->stream));
+  return FBIM_OK;
+}
+
+// dots h[0..k) = V[:, 0..k)^T w  (device)
+fbim_status dots(fbim_ctx *c, const double *V, int k, const double *w, size_t n, double *h) {
+  Timer t(c, "blas");
+  HIPCHK(c, launch_dots(V, c->ntot, k, w, n, c->d_partial, c->nblk, c->stream));
+  HIPCHK(c, launch_reduce_partials(c->d_partial, c->nblk, k, h, c->stream));
+  return FBIM_OK;
+}
+
+// CGS with one reorthogonalisation: w -= V h, h = h1 + h2; returns ||w||^2 in d_nrm[0]
+fbim_status orthogonalise(fbim_ctx *c, const double *V, int k, double *w, size_t n) {
+  STCHK(dots(c, V, k, w, n, c->d_h));
+  {
+    Timer t(c, "blas");
+    HIPCHK(c, launch_sub_Vh(V, c->ntot, k, c->d_h, w, n, c->stream));
+  }
+  STCHK(dots(c, V, k, w, n, c->d_h2));
+  {
+    Timer t(c, "blas");
+    HIPCHK(c, launch_sub_Vh(V, c->ntot, k, c->d_h2, w, n, c->stream));
+    HIPCHK(c, launch_vec_add(k, c->d_h2, c->d_h, c->stream));
+  }
+  STCHK(dots(c, w, 1, w, n, c->d_nrm));
+  return FBIM_OK;
+}
+
+fbim_status norm2(fbim_ctx *c, const double *x, size_t n, double &out) {
+  STCHK(dots(c, x, 1, x, n, c->d_nrm));
+  double v;
+  HIPCHK(c, hipMemcpyAsync(&v, c->d_nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  out = std::sqrt(std::max(v, 0.0));
+  return FBIM_OK;
+}
+
+// right-preconditioned restarted GMRES for the saddle system; b, x device (ntot)
+fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iters, double &relres) {
+  const size_t nt = c->ntot;
+  hipStream_t s = c->stream;
+  const int m = c->restart;
+  iters = 0;
+  relres = 0;
+  double nb;
+  STCHK(norm2(c, b, nt, nb));
+  HIPCHK(c, launch_fill(nt, 0.0, x, s));
+  if (nb == 0.0) return FBIM_OK;
+  std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), hcol(m + 2), y(m);
+  bool first = true;
+  for (;;) {
+    // r = b - A x
+    if (first) {
+      HIPCHK(c, hipMemcpyAsync(c->d_r, b, nt * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+      STCHK(apply_saddle(c, x, c->d_r));
+      HIPCHK(c, launch_axpby(nt, 1.0, b, -1.0, c->d_r, s));
+    }
+    double beta;
+    STCHK(norm2(c, c->d_r, nt, beta));
+    relres = beta / nb;
+    if (relres <= tol) return FBIM_OK;
+    if (iters >= c->gmres_max) return fail(c, FBIM_ENOCONV, "GMRES iteration limit reached");
+    first = false;
+    {
+      Timer t(c, "blas");
+      HIPCHK(c, launch_axpby(nt, 1.0 / beta, c->d_r, 0.0, c->d_V, s));
+    }
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jend = 0;
+    for (int j = 0; j < m; ++j) {
+      double *vj = c->d_V + (size_t)j * nt;
+      double *w = c->d_V + (size_t)(j + 1) * nt;
+      STCHK(apply_precond(c, vj, c->d_t1));
+      STCHK(apply_saddle(c, c->d_t1, w));
+      STCHK(orthogonalise(c, c->d_V, j + 1, w, nt));
+      HIPCHK(c, hipMemcpyAsync(hcol.data(), c->d_h, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipMemcpyAsync(hcol.data() + j + 1, c->d_nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      const double hn = std::sqrt(std::max(hcol[j + 1], 0.0));
+      hcol[j + 1] = hn;
+      if (hn > 0) {
+        Timer t(c, "blas");
+        HIPCHK(c, launch_scale_copy(nt, w, c->d_nrm, 1, w, s));
+      }
+      for (int i = 0; i < j; ++i) {  // previous rotations
+        const double t1 = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
+        hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];
+        hcol[i] = t1;
+      }
+      const double den = std::hypot(hcol[j], hcol[j + 1]);
+      cs[j] = den > 0 ? hcol[j] / den : 1.0;
+      sn[j] = den > 0 ? hcol[j + 1] / den : 0.0;
+      hcol[j] = den;
+      hcol[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i];
+      ++iters;
+      jend = j + 1;
+      if (std::fabs(g[j + 1]) <= tol * nb || iters >= c->gmres_max || hn == 0.0) break;
+    }
+    // y = H^-1 g, x += P^-1 V y
+    for (int i = jend - 1; i >= 0; --i) {
+      double sacc = g[i];
+      for (int k = i + 1; k < jend; ++k) sacc -= H[(size_t)i * m + k] * y[k];
+      y[i] = sacc / H[(size_t)i * m + i];
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_c, y.data(), jend * sizeof(double), hipMemcpyHostToDevice, s));
+    {
+      Timer t(c, "blas");
+      HIPCHK(c, launch_Vc(c->d_V, nt, jend, c->d_c, c->d_t2, nt, s));
+    }
+    STCHK(apply_precond(c, c->d_t2, c->d_t1));
+    HIPCHK(c, launch_axpby(nt, 1.0, c->d_t1, 1.0, x, s));
+  }
+}
+
+// Lanczos for (G M^(r) G^T)^(1/2) b with full reorthogonalisation; y = ||b|| V f(T) e_1
+fbim_status lanczos_sqrt(fbim_ctx *c, const double *b, double *out, int &iters, double &change) {
+  const size_t n2 = 2 * (size_t)c->N;
+  hipStream_t s = c->stream;
+  iters = 0;
+  change = 0;
+  double beta0;
+  STCHK(norm2(c, b, n2, beta0));
+  if (beta0 == 0.0) {
+    HIPCHK(c, launch_fill(n2, 0.0, out, s));
+    return FBIM_OK;
+  }
+  const int kmax = std::min(c->lanczos_max, (int)c->capV - 1);
+  HIPCHK(c, launch_axpby(n2, 1.0 / beta0, b, 0.0, c->d_V, s));
+  std::vector<double> alpha, beta, cprev, cur, hbuf(kmax + 2);
+  fbim_status st = FBIM_OK;
+  int k = 0;
+  for (;; ++k) {
+    double *vk = c->d_V + (size_t)k * c->ntot;
+    double *w = c->d_V + (size_t)(k + 1) * c->ntot;
+    HIPCHK(c, launch_body_apply(c->geom(), c->mats(), 0, vk, c->d_vec_a, s));
+    STCHK(apply_M(c, c->d_vec_a, c->d_vec_b, FBIM_PART_REAL | FBIM_PART_ALPERT));
+    HIPCHK(c, launch_body_apply(c->geom(), c->mats(), 0, c->d_vec_b, w, s));
+    STCHK(orthogonalise(c, c->d_V, k + 1, w, n2));
+    HIPCHK(c, hipMemcpyAsync(hbuf.data(), c->d_h, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(hbuf.data() + k + 1, c->d_nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    alpha.push_back(hbuf[k]);
+    const double bk = std::sqrt(std::max(hbuf[k + 1], 0.0));
+    // coefficients c = beta0 Q sqrt(max(L, 0)) Q^T e1 of the (k+1) x (k+1) tridiagonal
+    const int m = k + 1;
+    std::vector<double> T((size_t)m * m, 0.0), lam, Q;
+    for (int i = 0; i < m; ++i) {
+      T[(size_t)i * m + i] = alpha[i];
+      if (i + 1 < m) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = beta[i];
+    }
+    jacobi_eigh(m, T, lam, Q);
+    cur.assign(m, 0.0);
+    for (int r = 0; r < m; ++r) {
+      double sacc = 0;
+      for (int q = 0; q < m; ++q) sacc += Q[(size_t)r * m + q] * std::sqrt(std::max(lam[q], 0.0)) * Q[q];
+      cur[r] = beta0 * sacc;
+    }
+    double dn = 0, cn = 0;
+    for (int r = 0; r < m; ++r) {
+      const double pv = r < (int)cprev.size() ? cprev[r] : 0.0;
+      dn += (cur[r] - pv) * (cur[r] - pv);
+      cn += cur[r] * cur[r];
+    }
+    change = std::sqrt(dn / std::max(cn, 1e-300));
+    cprev = cur;
+    iters = m;
+    const bool breakdown = bk <= 1e-14 * std::fabs(alpha[0]);
+    if ((k > 0 && change <= c->p.tol_lanczos) || breakdown) break;
+    if (m >= kmax) {
+      st = FBIM_ENOCONV;
+      c->err = "Lanczos iteration limit reached";
+      break;
+    }
+    beta.push_back(bk);
+    HIPCHK(c, launch_scale_copy(n2, w, c->d_nrm, 1, w, s));
+  }
+  HIPCHK(c, hipMemcpyAsync(c->d_c, cur.data(), cur.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  {
+    Timer t(c, "blas");
+    HIPCHK(c, launch_Vc(c->d_V, c->ntot, (int)cur.size(), c->d_c, c->d_vec_a, n2, s));
+  }
+  HIPCHK(c, launch_body_apply(c->geom(), c->mats(), 1, c->d_vec_a, out, s));
+  return st;
+}
+
+fbim_status mobility(fbim_ctx *c, const double *F, const double *slip, double *U, double *mu_out, int &its,
+                     double &res) {
+  const size_t twoN = 2 * (size_t)c->N, nt = c->ntot;
+  hipStream_t s = c->stream;
+  // b = -[slip; F]
+  if (slip)
+    HIPCHK(c, launch_axpby(twoN, -1.0, slip, 0.0, c->d_b, s));
+  else
+    HIPCHK(c, launch_fill(twoN, 0.0, c->d_b, s));
+  HIPCHK(c, launch_axpby(3 * (size_t)c->n, -1.0, F, 0.0, c->d_b + twoN, s));
+  fbim_status st = gmres(c, c->d_b, c->d_x2, c->p.tol_gmres, its, res);
+  if (st != FBIM_OK && st != FBIM_ENOCONV) return st;
+  HIPCHK(c, hipMemcpyAsync(U, c->d_x2 + twoN, 3 * (size_t)c->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (mu_out) HIPCHK(c, hipMemcpyAsync(mu_out, c->d_x2, twoN * sizeof(double), hipMemcpyDeviceToDevice, s));
+  (void)nt;
+  return st;
+}
+
+fbim_status brownian(fbim_ctx *c, double dt, const double *F, const double *W_r, const double *W_grid, double *U,
+                     fbim_info *info) {
+  hipStream_t s = c->stream;
+  const size_t twoN = 2 * (size_t)c->N;
+  int li = 0, gi = 0;
+  double lc = 0, gr = 0;
+  // v^(r) into d_U? no: use d_r's leading 2N as the slip accumulator
+  double *slip = c->d_r;  // reused; gmres copies b before touching d_r
+  fbim_status st = lanczos_sqrt(c, W_r, slip, li, lc);
+  if (st != FBIM_OK && st != FBIM_ENOCONV) return st;
+  STCHK(random_field(c, W_grid, c->d_vec_b));
+  const double amp = std::sqrt(2.0 * c->p.kT / dt);
+  // slip = amp (v_r + v_w); store in d_w (free outside GMRES) then pass to mobility
+  HIPCHK(c, launch_axpby(twoN, 1.0, c->d_vec_b, 1.0, slip, s));
+  HIPCHK(c, launch_axpby(twoN, amp, slip, 0.0, c->d_w, s));
+  fbim_status st2 = mobility(c, F, c->d_w, U, nullptr, gi, gr);
+  if (info) {
+    info->lanczos_iters += li;
+    info->lanczos_change = lc;
+    info->gmres_iters += gi;
+    info->gmres_solves += 1;
+    info->gmres_residual = std::max(info->gmres_residual, gr);
+  }
+  if (st2 != FBIM_OK) return st2;
+  return st;
+}
+
+void info_reset(fbim_info *info) {
+  if (!info) return;
+  std::memset(info, 0, sizeof(*info));
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char *fbim_status_string(fbim_status s) {
+  switch (s) {
+    case FBIM_OK: return "ok";
+    case FBIM_EINVAL: return "invalid argument";
+    case FBIM_ENOMEM: return "out of memory";
+    case FBIM_EOVERLAP: return "bodies overlap";
+    case FBIM_ENOCONV: return "solver did not converge";
+    case FBIM_EDEVICE: return "device error";
+    case FBIM_ENOTSUP: return "not supported";
+    case FBIM_WACCURACY: return "accuracy warning";
+  }
+  return "unknown status";
+}
+
+const char *fbim_last_error(const fbim_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+fbim_status fbim_derive_params(const fbim_params *in, fbim_derived *out) {
+  if (!in || !out) return FBIM_EINVAL;
+  Derived d;
+  if (!derive(*in, d).empty()) return FBIM_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  out->xi = d.xi;
+  out->r_c = d.r_c;
+  out->h = d.h;
+  out->eta_s = d.eta_s;
+  out->n_box = d.n_box;
+  out->grid_M = d.M;
+  out->P = d.P;
+  out->tile = d.tile;
+  return FBIM_OK;
+}
+
+fbim_status fbim_alpert_rule(int32_t order, int32_t *j, int32_t *a, double *chi, double *w) {
+  if (!j || !a || !chi || !w) return FBIM_EINVAL;
+  int jj, aa;
+  std::string err;
+  if (!fbim::alpert_rule(order, jj, aa, chi, w, err)) return FBIM_EINVAL;
+  *j = jj;
+  *a = aa;
+  return FBIM_OK;
+}
+
+void fbim_starfish(double r_s, double b, int32_t n_arm, int32_t n_p, double *ref_xy) {
+  for (int j = 0; j < n_p; ++j) {
+    const double sj = 2.0 * kPi * j / n_p;
+    const double r = r_s * (1.0 + b * std::cos(n_arm * sj));
+    ref_xy[2 * j] = r * std::cos(sj);
+    ref_xy[2 * j + 1] = r * std::sin(sj);
+  }
+}
+
+fbim_status fbim_create(const fbim_params *params, fbim_ctx **out) {
+  if (!params || !out) return FBIM_EINVAL;
+  *out = nullptr;
+  auto *c = new fbim_ctx();
+  c->p = *params;
+  if (c->p.eta <= 0) c->p.eta = 1.0;
+  if (c->p.tau_spurious <= 0) c->p.tau_spurious = 1e-8;
+  if (c->p.tol_gmres <= 0) c->p.tol_gmres = 1e-6;
+  if (c->p.tol_lanczos <= 0) c->p.tol_lanczos = 1e-6;
+  if (c->p.alpert_order == 0) c->p.alpert_order = 4;
+  c->restart = c->p.gmres_restart > 0 ? c->p.gmres_restart : 100;
+  c->gmres_max = c->p.gmres_maxiter > 0 ? c->p.gmres_maxiter : 1000;
+  c->lanczos_max = c->p.lanczos_maxiter > 0 ? c->p.lanczos_maxiter : 200;
+  c->mixed = c->p.precision == FBIM_PREC_MIXED;
+  if (c->p.precision != FBIM_PREC_FP64 && c->p.precision != FBIM_PREC_MIXED) {
+    fbim_destroy(c);
+    return FBIM_EINVAL;
+  }
+  std::string err = derive(c->p, c->d);
+  if (!err.empty()) {
+    fbim_destroy(c);
+    return FBIM_EINVAL;
+  }
+  if (c->d.P > 15) {
+    fbim_destroy(c);
+    return FBIM_ENOTSUP;
+  }
+  c->order = c->p.alpert_order;
+  if (!fbim::alpert_rule(c->order, c->aj, c->aa, c->chi, c->w, err)) {
+    fbim_destroy(c);
+    return FBIM_EINVAL;
+  }
+  c->ncell = c->d.n_box * c->d.n_box;
+  c->nts = c->d.M / c->d.tile;
+  c->ntile = c->nts * c->nts;
+  fbim_status st = FBIM_OK;
+  auto t64 = e1_table(kE1Deg64);
+  auto t32d = e1_table(kE1Deg32);
+  std::vector<float> t32(t32d.begin(), t32d.end());
+  if ((st = upload(c, c->d_e1tab, t64)) != FBIM_OK || (st = upload(c, c->d_e1tab32, t32)) != FBIM_OK ||
+      hipMalloc((void **)&c->d_scal_int, 4 * sizeof(int)) != hipSuccess ||
+      dalloc(c->d_ccount, c->ncell) != hipSuccess || dalloc(c->d_ccursor, c->ncell) != hipSuccess ||
+      dalloc(c->d_cstart, c->ncell + 1) != hipSuccess || dalloc(c->d_tcount, c->ntile) != hipSuccess ||
+      dalloc(c->d_tcursor, c->ntile) != hipSuccess || dalloc(c->d_tstart, c->ntile + 1) != hipSuccess) {
+    fbim_destroy(c);
+    return FBIM_EDEVICE;
+  }
+  if ((st = setup_fft(c)) != FBIM_OK) {
+    fbim_destroy(c);
+    return st;
+  }
+  *out = c;
+  return FBIM_OK;
+}
+
+void fbim_destroy(fbim_ctx *c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  resolve_timing(c);
+  for (auto &s : c->shapes) {
+    dfree(s.ref);
+    dfree(s.band);
+    dfree(s.Mp);
+    dfree(s.Pref);
+    dfree(s.Nt);
+    dfree(s.G);
+    dfree(s.Gp);
+  }
+  if (c->fwd) rocfft_plan_destroy(c->fwd);
+  if (c->inv) rocfft_plan_destroy(c->inv);
+  if (c->fwd32) rocfft_plan_destroy(c->fwd32);
+  if (c->inv32) rocfft_plan_destroy(c->inv32);
+  if (c->einfo) rocfft_execution_info_destroy(c->einfo);
+  if (c->fft_work) hipFree(c->fft_work);
+  void *ptrs[] = {c->d_ref_arr, c->d_band_arr, c->d_Mp_arr, c->d_Pref_arr, c->d_Nt_arr, c->d_G_arr, c->d_Gp_arr,
+                  c->d_band, c->d_np, c->d_shape, c->d_off, c->d_body, c->d_q, c->d_theta, c->d_x,
+                  c->d_ckey, c->d_ccount, c->d_cstart, c->d_cperm, c->d_ccursor, c->d_xs, c->d_tkey,
+                  c->d_tcount, c->d_tstart, c->d_tperm, c->d_tcursor, c->d_xt, c->d_anchor, c->d_scal_int, c->d_mus,
+                  c->d_mut, c->d_xs32, c->d_mus32, c->d_xt32, c->d_mut32, c->d_grid, c->d_spec, c->d_grid32,
+                  c->d_spec32, c->d_e1tab, c->d_e1tab32, c->d_V, c->d_w, c->d_t1, c->d_t2, c->d_b, c->d_x2,
+                  c->d_r, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
+                  c->d_U4, c->d_U5};
+  for (void *p : ptrs)
+    if (p) hipFree(p);
+  delete c;
+}
+
+fbim_status fbim_set_stream(fbim_ctx *c, void *stream) {
+  if (!c) return FBIM_EINVAL;
+  c->stream = (hipStream_t)stream;
+  if (c->einfo) FFTCHK(c, rocfft_execution_info_set_stream(c->einfo, c->stream));
+  return FBIM_OK;
+}
+
+fbim_status fbim_add_shape(fbim_ctx *c, int32_t n_p, const double *ref_xy, int32_t *shape_id) {
+  if (!c || !ref_xy || !shape_id) return fail(c, FBIM_EINVAL, "null argument");
+  ShapeDev sd;
+  std::string err = build_shape(n_p, ref_xy, c->d, c->p.eta, c->order, c->p.tau_spurious, sd.h);
+  if (!err.empty()) return fail(c, FBIM_EINVAL, err);
+  STCHK(upload(c, sd.ref, sd.h.ref_xy));
+  STCHK(upload(c, sd.band, sd.h.alpert));
+  STCHK(upload(c, sd.Mp, sd.h.Mpinv));
+  STCHK(upload(c, sd.Pref, sd.h.Pref));
+  STCHK(upload(c, sd.Nt, sd.h.Nt));
+  STCHK(upload(c, sd.G, sd.h.Gref));
+  STCHK(upload(c, sd.Gp, sd.h.Gpref));
+  c->shapes.push_back(sd);
+  c->max_np = std::max(c->max_np, n_p);
+  STCHK(rebuild_shape_arrays(c));
+  *shape_id = (int32_t)c->shapes.size() - 1;
+  if (sd.h.r_alpert > 0.6 * c->d.r_c) {
+    c->err = "r_Alpert / r_c exceeds 0.6";
+    return FBIM_WACCURACY;
+  }
+  return FBIM_OK;
+}
+
+fbim_status fbim_set_bodies(fbim_ctx *c, int32_t n, const int32_t *shape_id, const double *q,
+                            const double *theta) {
+  if (!c || n <= 0 || !shape_id || !q || !theta) return fail(c, FBIM_EINVAL, "invalid bodies");
+  std::vector<int> off(n + 1, 0);
+  for (int b = 0; b < n; ++b) {
+    if (shape_id[b] < 0 || shape_id[b] >= (int)c->shapes.size()) return fail(c, FBIM_EINVAL, "bad shape id");
+    if (!std::isfinite(q[2 * b]) || !std::isfinite(q[2 * b + 1]) || !std::isfinite(theta[b]))
+      return fail(c, FBIM_EINVAL, "non-finite body coordinate");
+    off[b + 1] = off[b] + c->shapes[shape_id[b]].h.n_p;
+  }
+  const int N = off[n];
+  if (N >= (1 << 30) / 4) return fail(c, FBIM_EINVAL, "too many nodes");
+  const bool realloc_n = n != c->capn, realloc_N = N != c->capN;
+  c->h_shape.assign(shape_id, shape_id + n);
+  c->h_off = off;
+  c->h_q.assign(q, q + 2 * n);
+  c->h_theta.assign(theta, theta + n);
+  c->n = n;
+  c->N = N;
+  if (realloc_n) {
+    HIPCHK(c, dalloc(c->d_shape, n));
+    HIPCHK(c, dalloc(c->d_off, n + 1));
+    HIPCHK(c, dalloc(c->d_q, 2 * n));
+    HIPCHK(c, dalloc(c->d_theta, n));
+    c->capn = n;
+  }
+  if (realloc_N) {
+    HIPCHK(c, dalloc(c->d_body, N));
+    HIPCHK(c, dalloc(c->d_x, 2 * N));
+    HIPCHK(c, dalloc(c->d_ckey, N));
+    HIPCHK(c, dalloc(c->d_cperm, N));
+    HIPCHK(c, dalloc(c->d_xs, 2 * N));
+    HIPCHK(c, dalloc(c->d_tkey, N));
+    HIPCHK(c, dalloc(c->d_tperm, N));
+    HIPCHK(c, dalloc(c->d_xt, 2 * N));
+    HIPCHK(c, dalloc(c->d_anchor, 2 * N));
+    HIPCHK(c, dalloc(c->d_mus, 2 * N));
+    HIPCHK(c, dalloc(c->d_mut, 2 * N));
+    if (c->mixed) {
+      HIPCHK(c, dalloc(c->d_xs32, 2 * N));
+      HIPCHK(c, dalloc(c->d_mus32, 2 * N));
+      HIPCHK(c, dalloc(c->d_xt32, 2 * N));
+      HIPCHK(c, dalloc(c->d_mut32, 2 * N));
+    }
+    c->capN = N;
+  }
+  std::vector<int> body(N);
+  for (int b = 0; b < n; ++b)
+    for (int i = off[b]; i < off[b + 1]; ++i) body[i] = b;
+  HIPCHK(c, hipMemcpy(c->d_shape, c->h_shape.data(), n * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_off, off.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_body, body.data(), N * sizeof(int), hipMemcpyHostToDevice));
+  c->have_bodies = true;
+  STCHK(ensure_krylov(c));
+  return build_geometry(c);
+}
+
+fbim_status fbim_get_derived(const fbim_ctx *c, fbim_derived *out) {
+  if (!c || !out) return FBIM_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  out->xi = c->d.xi;
+  out->r_c = c->d.r_c;
+  out->h = c->d.h;
+  out->eta_s = c->d.eta_s;
+  out->n_box = c->d.n_box;
+  out->grid_M = c->d.M;
+  out->P = c->d.P;
+  out->tile = c->d.tile;
+  out->alpert_j = c->aj;
+  out->alpert_a = c->aa;
+  out->n_bodies = c->n;
+  out->n_nodes = c->N;
+  double ra = 0;
+  for (auto &s : c->shapes) ra = std::max(ra, s.h.r_alpert);
+  out->r_alpert = ra;
+  return FBIM_OK;
+}
+
+fbim_status fbim_get_nodes(fbim_ctx *c, double *x) {
+  if (!c || !x || !c->have_bodies) return fail(c, FBIM_EINVAL, "no bodies");
+  HIPCHK(c, hipMemcpyAsync(x, c->d_x, 2 * (size_t)c->N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  return FBIM_OK;
+}
+
+fbim_status fbim_apply_M(fbim_ctx *c, const double *mu, double *out, uint32_t parts) {
+  if (!c || !mu || !out || mu == out) return fail(c, FBIM_EINVAL, "invalid pointers");
+  if (parts == 0 || parts > FBIM_PART_ALL) return fail(c, FBIM_EINVAL, "invalid parts");
+  return apply_M(c, mu, out, parts);
+}
+
+fbim_status fbim_random_field(fbim_ctx *c, const double *W_grid, double *out) {
+  if (!c || !W_grid || !out || !c->have_bodies) return fail(c, FBIM_EINVAL, "invalid arguments");
+  return random_field(c, W_grid, out);
+}
+
+fbim_status fbim_sqrt_Mr(fbim_ctx *c, const double *W_r, double *out, fbim_info *info) {
+  if (!c || !W_r || !out || !c->have_bodies) return fail(c, FBIM_EINVAL, "invalid arguments");
+  info_reset(info);
+  const double t0 = now_ms();
+  int it = 0;
+  double ch = 0;
+  fbim_status st = lanczos_sqrt(c, W_r, out, it, ch);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (info) {
+    info->lanczos_iters = it;
+    info->lanczos_change = ch;
+    info->status = st;
+    info->ms_total = now_ms() - t0;
+  }
+  return st;
+}
+
+fbim_status fbim_mobility(fbim_ctx *c, const double *F, const double *slip, double *U, double *mu_out,
+                          fbim_info *info) {
+  if (!c || !F || !U || !c->have_bodies) return fail(c, FBIM_EINVAL, "invalid arguments");
+  info_reset(info);
+  const double t0 = now_ms();
+  int it = 0;
+  double res = 0;
+  fbim_status st = mobility(c, F, slip, U, mu_out, it, res);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (info) {
+    info->gmres_iters = it;
+    info->gmres_solves = 1;
+    info->gmres_residual = res;
+    info->status = st;
+    info->ms_total = now_ms() - t0;
+  }
+  return st;
+}
+
+fbim_status fbim_brownian_velocity(fbim_ctx *c, double dt, const double *F, const double *W_r,
+                                   const double *W_grid, double *U, fbim_info *info) {
+  if (!c || !F || !W_r || !W_grid || !U || !(dt > 0) || !c->have_bodies) return fail(c, FBIM_EINVAL, "invalid arguments");
+  info_reset(info);
+  const double t0 = now_ms();
+  fbim_status st = brownian(c, dt, F, W_r, W_grid, U, info);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (info) {
+    info->status = st;
+    info->ms_total = now_ms() - t0;
+  }
+  return st;
+}
+
+fbim_status fbim_step_em_rfd(fbim_ctx *c, double dt, double delta, const double *F, const double *W_r,
+                             const double *W_grid, const double *W_tilde, double *dQ, int32_t apply,
+                             fbim_info *info) {
+  if (!c || !F || !W_r || !W_grid || !W_tilde || !dQ || !(dt > 0) || !(delta > 0) || !c->have_bodies)
+    return fail(c, FBIM_EINVAL, "invalid arguments");
+  info_reset(info);
+  const double t0 = now_ms();
+  hipStream_t s = c->stream;
+  const int n = c->n;
+  const size_t n3 = 3 * (size_t)n;
+  // U0 = N F + sqrt(2kT/dt) N^(1/2) W at Q
+  fbim_status st = brownian(c, dt, F, W_r, W_grid, c->d_U3, info);
+  if (st != FBIM_OK && st != FBIM_ENOCONV) return st;
+  fbim_status worst = st;
+  std::vector<double> wt(n3), q0 = c->h_q, th0 = c->h_theta, qs(2 * n), ths(n);
+  std::vector<int> sid = c->h_shape;
+  HIPCHK(c, hipMemcpyAsync(wt.data(), W_tilde, n3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  // RFD solves N(Q +- delta/2 Wt) Wt
+  for (int sgn = 1; sgn >= -1; sgn -= 2) {
+    for (int b = 0; b < n; ++b) {
+      qs[2 * b] = q0[2 * b] + sgn * 0.5 * delta * wt[3 * b];
+      qs[2 * b + 1] = q0[2 * b + 1] + sgn * 0.5 * delta * wt[3 * b + 1];
+      ths[b] = th0[b] + sgn * 0.5 * delta * wt[3 * b + 2];
+    }
+    STCHK(fbim_set_bodies(c, n, sid.data(), qs.data(), ths.data()));
+    int it = 0;
+    double res = 0;
+    fbim_status s2 = mobility(c, W_tilde, nullptr, sgn > 0 ? c->d_U4 : c->d_U5, nullptr, it, res);
+    if (s2 != FBIM_OK && s2 != FBIM_ENOCONV) return s2;
+    if (s2 != FBIM_OK) worst = s2;
+    if (info) {
+      info->gmres_iters += it;
+      info->gmres_solves += 1;
+      info->gmres_residual = std::max(info->gmres_residual, res);
+    }
+  }
+  // dQ = dt U0 + dt kT/delta (U+ - U-)
+  HIPCHK(c, launch_axpby(n3, dt, c->d_U3, 0.0, dQ, s));
+  HIPCHK(c, launch_axpby(n3, dt * c->p.kT / delta, c->d_U4, 1.0, dQ, s));
+  HIPCHK(c, launch_axpby(n3, -dt * c->p.kT / delta, c->d_U5, 1.0, dQ, s));
+  if (apply) {
+    std::vector<double> dq(n3);
+    HIPCHK(c, hipMemcpyAsync(dq.data(), dQ, n3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (int b = 0; b < n; ++b) {
+      qs[2 * b] = q0[2 * b] + dq[3 * b];
+      qs[2 * b + 1] = q0[2 * b + 1] + dq[3 * b + 1];
+      ths[b] = th0[b] + dq[3 * b + 2];
+    }
+    STCHK(fbim_set_bodies(c, n, sid.data(), qs.data(), ths.data()));
+  } else {
+    STCHK(fbim_set_bodies(c, n, sid.data(), q0.data(), th0.data()));
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (info) {
+    info->status = worst;
+    info->ms_total = now_ms() - t0;
+  }
+  return worst;
+}
+
+fbim_status fbim_set_timing(fbim_ctx *c, int32_t enable) {
+  if (!c) return FBIM_EINVAL;
+  resolve_timing(c);
+  c->acc.clear();
+  c->timing = enable != 0;
+  return FBIM_OK;
+}
+
+fbim_status fbim_kernel_time(fbim_ctx *c, const char *name, double *ms, int64_t *count) {
+  if (!c || !name || !ms || !count) return FBIM_EINVAL;
+  resolve_timing(c);
+  auto it = c->acc.find(name);
+  *ms = it == c->acc.end() ? 0.0 : it->second.first;
+  *count = it == c->acc.end() ? 0 : it->second.second;
+  return FBIM_OK;
+}
+
+}  // extern "C"

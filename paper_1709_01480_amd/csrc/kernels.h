@@ -1,0 +1,111 @@
+// Launch wrappers of the FBIM device kernels (gfx950).  All pointers are device
+// pointers; every wrapper enqueues on `s` and returns the launch status.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fbim {
+
+struct GeomDev {
+  int n, N;
+  const int *shape;      // [n]
+  const int *off;        // [n+1] first node of each body
+  const int *body;       // [N] body of each node
+  const double *q;       // [2n]
+  const double *theta;   // [n]
+  const double *const *ref;  // per shape: ref_xy [2 n_p]   (device array of device pointers)
+  const int *np;         // per shape: n_p
+};
+
+// nodes (wrapped into [0, L)) -> x[2N]
+hipError_t launch_nodes(const GeomDev &g, double L, double *x, hipStream_t s);
+
+// binning: key per node, counts (atomic), exclusive scan, scatter, in-bin sort
+hipError_t launch_cell_keys(int N, const double *x, double L, int nb, int *key, int *count, hipStream_t s);
+hipError_t launch_tile_keys(int N, const double *x, double h, int M, int T, int *key, int *count, hipStream_t s);
+hipError_t launch_scan(int n, const int *count, int *start, int *maxcount, hipStream_t s);
+hipError_t launch_scatter(int N, const int *key, const int *start, int *cursor, int *perm, hipStream_t s);
+hipError_t launch_sort_bins(int nbins, const int *start, int *perm, hipStream_t s);
+hipError_t launch_gather2(int N, const int *perm, const double *src, double *dst, hipStream_t s);
+hipError_t launch_gather2f(int N, const int *perm, const double *src, float *dst, hipStream_t s);
+// nearest grid indices floor(x / h + 1/2) of the nodes in tile order
+hipError_t launch_anchors(int N, const int *tperm, const double *x, double h, int *anchor, hipStream_t s);
+
+// closest approach of nodes of distinct bodies (cell list); flag set if < thresh
+hipError_t launch_overlap(int N, const int *cell_start, const int *perm, const double *xs, const int *body,
+                          int nb, double L, double thresh, int *flag, hipStream_t s);
+
+// real-space pair sum (eq. 3.15, trapezoid pairs within r_c): out[perm[i]] = sum
+struct PairArgs {
+  const int *cell_start;
+  const int *perm;
+  int nb, nbatch;
+  double L, rc2, xi2, cG;
+  const double *e1tab;  // FP64 table
+  const float *e1tab32; // FP32 table
+};
+hipError_t launch_pair_f64(const PairArgs &a, const double *xs, const double *mus, double *out, hipStream_t s);
+hipError_t launch_pair_f32(const PairArgs &a, const float *xs, const float *mus, double *out, hipStream_t s);
+
+// Alpert band: out[i] += R_b A_ref R_b^T mu (per node); accumulate=1 adds
+hipError_t launch_alpert(const GeomDev &g, const double *const *band_tab, const int *band, const double *mu,
+                         double *out, int accumulate, hipStream_t s);
+
+// spectral Ewald
+struct WaveArgs {
+  int M, T, P, nts;
+  double h, L, ag, cg;  // Gaussian exp(-ag r^2) * cg
+  const int *tile_start;
+  const int *anchor;    // per tile-sorted node: nearest grid indices (ix, iy), unwrapped, from FP64 positions
+};
+hipError_t launch_spread_f64(const WaveArgs &w, const double *xt, const double *mut, double *grid, hipStream_t s);
+hipError_t launch_spread_f32(const WaveArgs &w, const float *xt, const float *mut, float *grid, hipStream_t s);
+hipError_t launch_interp_f64(const WaveArgs &w, const double *xt, const int *tperm, const double *grid,
+                             double *out, hipStream_t s);
+hipError_t launch_interp_f32(const WaveArgs &w, const float *xt, const int *tperm, const float *grid,
+                             double *out, hipStream_t s);
+// multiplier on the half spectrum [2][M][M/2+1]: mode 0 = M^(w) (eq. 3.23-3.25),
+// mode 1 = random field B^(1/2) (eq. 3.28-3.30)
+hipError_t launch_multiplier_f64(int M, double L, double xi, double eta_s, double scale, int mode, double *spec,
+                                 hipStream_t s);
+hipError_t launch_multiplier_f32(int M, double L, double xi, double eta_s, double scale, int mode, float *spec,
+                                 hipStream_t s);
+
+// rigid-body maps (Section 3.1)
+// y_mu[i] = y_mu[i] - (K U)_i ; y_U[b] = sgn * (K^T mu)_b
+hipError_t launch_sub_KU(const GeomDev &g, const double *U, double *y, hipStream_t s);
+hipError_t launch_KT(const GeomDev &g, const double *mu, double sgn, double *out, hipStream_t s);
+
+// per-body dense operators (Sections 3.3-3.4), single shape per launch group
+struct BodyMats {
+  const double *const *Mp;    // per shape (2n_p)^2 column-major
+  const double *const *Pref;  // per shape 2n_p x 3 column-major
+  const double *const *Nt;    // per shape 3x3
+  const double *const *G;     // per shape
+  const double *const *Gp;    // per shape
+  int max_np;
+};
+// block-diagonal saddle preconditioner: z = [a (2N) | b (3n)] -> y = [mu | U]
+hipError_t launch_precond(const GeomDev &g, const BodyMats &m, const double *z, double *y, hipStream_t s);
+// y_b = R_b X_ref R_b^T x_b with X = G (which = 0) or G^+ (which = 1)
+hipError_t launch_body_apply(const GeomDev &g, const BodyMats &m, int which, const double *x, double *y,
+                             hipStream_t s);
+
+// Krylov helpers (FP64)
+// partial[blk][j] = sum over the block's rows of V[j*ld + i] * w[i], j < k
+hipError_t launch_dots(const double *V, size_t ld, int k, const double *w, size_t n, double *partial, int nblk,
+                       hipStream_t s);
+hipError_t launch_reduce_partials(const double *partial, int nblk, int k, double *out, hipStream_t s);
+// w[i] -= sum_j V[j*ld + i] * h[j]   (h on device)
+hipError_t launch_sub_Vh(const double *V, size_t ld, int k, const double *h, double *w, size_t n, hipStream_t s);
+// y[i] = sum_j V[j*ld + i] * c[j]
+hipError_t launch_Vc(const double *V, size_t ld, int k, const double *c, double *y, size_t n, hipStream_t s);
+hipError_t launch_axpby(size_t n, double a, const double *x, double b, double *y, hipStream_t s);  // y = a x + b y
+hipError_t launch_scale_copy(size_t n, const double *x, const double *alpha_dev, int invert, double *y,
+                             hipStream_t s);  // y = x * alpha (or / alpha)
+hipError_t launch_vec_add(int k, const double *a, double *b, hipStream_t s);  // b += a
+hipError_t launch_cast_f32(size_t n, const double *x, float *y, hipStream_t s);
+hipError_t launch_fill(size_t n, double v, double *y, hipStream_t s);
+
+}  // namespace fbim

@@ -1,0 +1,225 @@
+// Geometry kernels: node positions (Section 3.1), cell and tile binning for the
+// real-space cell list (Section 3.2) and the spreading tiles.
+#include "kernels.h"
+
+namespace fbim {
+
+__global__ void k_nodes(int N, const int *__restrict__ body, const int *__restrict__ off,
+                        const int *__restrict__ shape, const double *__restrict__ q,
+                        const double *__restrict__ theta, const double *const *ref, double L,
+                        double *__restrict__ x) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int b = body[i];
+  const int t = i - off[b];
+  const double *r = ref[shape[b]];
+  double sn, cs;
+  sincos(theta[b], &sn, &cs);
+  const double rx = r[2 * t], ry = r[2 * t + 1];
+  double px = q[2 * b] + cs * rx - sn * ry;
+  double py = q[2 * b + 1] + sn * rx + cs * ry;
+  px -= L * floor(px / L);
+  py -= L * floor(py / L);
+  if (px >= L) px -= L;  // guard against rounding up to L
+  if (py >= L) py -= L;
+  x[2 * i] = px;
+  x[2 * i + 1] = py;
+}
+
+hipError_t launch_nodes(const GeomDev &g, double L, double *x, hipStream_t s) {
+  if (g.N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_nodes, dim3((g.N + 255) / 256), dim3(256), 0, s, g.N, g.body, g.off, g.shape, g.q,
+                     g.theta, g.ref, L, x);
+  return hipGetLastError();
+}
+
+__global__ void k_cell_keys(int N, const double *__restrict__ x, double inv_cell, int nb, int *__restrict__ key,
+                            int *__restrict__ count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int cx = (int)floor(x[2 * i] * inv_cell), cy = (int)floor(x[2 * i + 1] * inv_cell);
+  cx = min(max(cx, 0), nb - 1);
+  cy = min(max(cy, 0), nb - 1);
+  const int c = cy * nb + cx;
+  key[i] = c;
+  atomicAdd(&count[c], 1);
+}
+
+hipError_t launch_cell_keys(int N, const double *x, double L, int nb, int *key, int *count, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cell_keys, dim3((N + 255) / 256), dim3(256), 0, s, N, x, nb / L, nb, key, count);
+  return hipGetLastError();
+}
+
+// tile of the grid point nearest to the node (the centre of its spreading stencil)
+__global__ void k_tile_keys(int N, const double *__restrict__ x, double inv_h, int M, int T,
+                            int *__restrict__ key, int *__restrict__ count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int ix = (int)floor(x[2 * i] * inv_h + 0.5), iy = (int)floor(x[2 * i + 1] * inv_h + 0.5);
+  ix = ((ix % M) + M) % M;
+  iy = ((iy % M) + M) % M;
+  const int nts = M / T;
+  const int c = (iy / T) * nts + ix / T;
+  key[i] = c;
+  atomicAdd(&count[c], 1);
+}
+
+hipError_t launch_tile_keys(int N, const double *x, double h, int M, int T, int *key, int *count, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_keys, dim3((N + 255) / 256), dim3(256), 0, s, N, x, 1.0 / h, M, T, key, count);
+  return hipGetLastError();
+}
+
+// single-workgroup exclusive scan (n up to a few 10^5), also the maximum count
+__global__ __launch_bounds__(1024) void k_scan(int n, const int *__restrict__ count, int *__restrict__ start,
+                                               int *__restrict__ maxcount) {
+  __shared__ int buf[1024];
+  __shared__ int carry;
+  __shared__ int mx[1024];
+  const int tid = threadIdx.x;
+  if (tid == 0) carry = 0;
+  int lmax = 0;
+  __syncthreads();
+  for (int base = 0; base < n; base += 1024) {
+    const int i = base + tid;
+    const int v = (i < n) ? count[i] : 0;
+    lmax = max(lmax, v);
+    buf[tid] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {  // inclusive Hillis-Steele
+      int t = (tid >= o) ? buf[tid - o] : 0;
+      __syncthreads();
+      buf[tid] += t;
+      __syncthreads();
+    }
+    if (i < n) start[i] = carry + buf[tid] - v;
+    __syncthreads();
+    if (tid == 1023) carry += buf[1023];
+    __syncthreads();
+  }
+  if (tid == 0) start[n] = carry;
+  mx[tid] = lmax;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (tid < o) mx[tid] = max(mx[tid], mx[tid + o]);
+    __syncthreads();
+  }
+  if (tid == 0) *maxcount = mx[0];
+}
+
+hipError_t launch_scan(int n, const int *count, int *start, int *maxcount, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, n, count, start, maxcount);
+  return hipGetLastError();
+}
+
+__global__ void k_scatter(int N, const int *__restrict__ key, const int *__restrict__ start, int *__restrict__ cursor,
+                          int *__restrict__ perm) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int c = key[i];
+  perm[start[c] + atomicAdd(&cursor[c], 1)] = i;
+}
+
+hipError_t launch_scatter(int N, const int *key, const int *start, int *cursor, int *perm, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter, dim3((N + 255) / 256), dim3(256), 0, s, N, key, start, cursor, perm);
+  return hipGetLastError();
+}
+
+// order nodes inside each bin by node index (makes the permutation deterministic)
+__global__ void k_sort_bins(int nbins, const int *__restrict__ start, int *__restrict__ perm) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nbins) return;
+  const int a = start[c], b = start[c + 1];
+  for (int i = a + 1; i < b; ++i) {
+    const int v = perm[i];
+    int j = i - 1;
+    while (j >= a && perm[j] > v) {
+      perm[j + 1] = perm[j];
+      --j;
+    }
+    perm[j + 1] = v;
+  }
+}
+
+hipError_t launch_sort_bins(int nbins, const int *start, int *perm, hipStream_t s) {
+  hipLaunchKernelGGL(k_sort_bins, dim3((nbins + 255) / 256), dim3(256), 0, s, nbins, start, perm);
+  return hipGetLastError();
+}
+
+__global__ void k_gather2(int N, const int *__restrict__ perm, const double2 *__restrict__ src,
+                          double2 *__restrict__ dst) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) dst[i] = src[perm[i]];
+}
+
+__global__ void k_gather2f(int N, const int *__restrict__ perm, const double2 *__restrict__ src,
+                           float2 *__restrict__ dst) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) {
+    const double2 v = src[perm[i]];
+    dst[i] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
+hipError_t launch_gather2(int N, const int *perm, const double *src, double *dst, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather2, dim3((N + 255) / 256), dim3(256), 0, s, N, perm, (const double2 *)src,
+                     (double2 *)dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather2f(int N, const int *perm, const double *src, float *dst, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather2f, dim3((N + 255) / 256), dim3(256), 0, s, N, perm, (const double2 *)src,
+                     (float2 *)dst);
+  return hipGetLastError();
+}
+
+__global__ void k_anchors(int N, const int *__restrict__ tperm, const double *__restrict__ x, double inv_h,
+                          int2 *__restrict__ anchor) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const int i = tperm[k];
+  anchor[k] = make_int2((int)floor(x[2 * i] * inv_h + 0.5), (int)floor(x[2 * i + 1] * inv_h + 0.5));
+}
+
+hipError_t launch_anchors(int N, const int *tperm, const double *x, double h, int *anchor, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_anchors, dim3((N + 255) / 256), dim3(256), 0, s, N, tperm, x, 1.0 / h, (int2 *)anchor);
+  return hipGetLastError();
+}
+
+// one thread per node: scan the 3x3 neighbouring cells for nodes of other bodies
+__global__ void k_overlap(int N, const int *__restrict__ cell_start, const int *__restrict__ perm,
+                          const double *__restrict__ xs, const int *__restrict__ body, int nb, double L,
+                          double thresh2, int *__restrict__ flag) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const double x = xs[2 * p], y = xs[2 * p + 1];
+  const int bi = body[perm[p]];
+  const double inv = nb / L;
+  const int cx = min(max((int)floor(x * inv), 0), nb - 1), cy = min(max((int)floor(y * inv), 0), nb - 1);
+  for (int dy = -1; dy <= 1; ++dy)
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int c = ((cy + dy + nb) % nb) * nb + (cx + dx + nb) % nb;
+      for (int k = cell_start[c]; k < cell_start[c + 1]; ++k) {
+        if (body[perm[k]] == bi) continue;
+        double ex = x - xs[2 * k], ey = y - xs[2 * k + 1];
+        ex -= L * rint(ex / L);
+        ey -= L * rint(ey / L);
+        if (ex * ex + ey * ey < thresh2) atomicOr(flag, 1);
+      }
+    }
+}
+
+hipError_t launch_overlap(int N, const int *cell_start, const int *perm, const double *xs, const int *body, int nb,
+                          double L, double thresh, int *flag, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_overlap, dim3((N + 255) / 256), dim3(256), 0, s, N, cell_start, perm, xs, body, nb, L,
+                     thresh * thresh, flag);
+  return hipGetLastError();
+}
+
+}  // namespace fbim

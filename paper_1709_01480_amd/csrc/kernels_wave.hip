@@ -1,0 +1,262 @@
+// Wave-space part of the single-layer matvec (Section 3.2, eqs. 3.21-3.25) and
+// the random Fourier field (Section 3.3, eqs. 3.28-3.30):
+//   spread  S : H_c(x_g) = sum_n mu_{n,c} g(x_g - x_n), g = cg exp(-ag r^2), P x P
+//               nearest grid points; each work group owns a T x T grid tile and
+//               accumulates it in LDS (no global atomics);
+//   multiply B: on the half spectrum, with the Gaussian deconvolution folded in;
+//   interp  S*: v_n = h^2 sum_g g(x_n - x_g) U(x_g), grid window staged in LDS.
+// The FFTs in between are rocFFT plans owned by the context.
+#include "kernels.h"
+
+namespace fbim {
+
+namespace {
+
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
+__device__ inline double dev_exp(double x) { return exp(x); }
+__device__ inline float dev_exp(float x) { return __expf(x); }
+
+constexpr int kTmax = 32;
+constexpr int kPmax = 15;
+constexpr int kList = 768;
+
+__device__ inline int wrapi(int i, int M) {
+  i %= M;
+  return i < 0 ? i + M : i;
+}
+
+__device__ inline int xcd_remap(int b, int n) {
+  const int q = n / 8, r = n % 8;
+  const int xcd = b % 8, idx = b / 8;
+  return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_spread(int M, int TT, int P, int nts, T h, T ag, T cg,
+                                                const int *__restrict__ tile_start,
+                                                const typename Vec2<T>::type *__restrict__ xt,
+                                                const int2 *__restrict__ anchor,
+                                                const typename Vec2<T>::type *__restrict__ mut,
+                                                T *__restrict__ grid) {
+  __shared__ T acc[2][kTmax * kTmax];
+  __shared__ int lst[kList];
+  __shared__ int lcount;
+  const int tid = threadIdx.x;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tyi = tile / nts, txi = tile % nts;
+  const int gx0 = txi * TT, gy0 = tyi * TT;
+  const int half = (P - 1) / 2;
+  for (int i = tid; i < TT * TT; i += 256) acc[0][i] = acc[1][i] = T(0);
+  if (tid == 0) lcount = 0;
+  int nstart[9], pre[10];
+  pre[0] = 0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const int dx = k % 3 - 1, dy = k / 3 - 1;
+    const int tt = wrapi(tyi + dy, nts) * nts + wrapi(txi + dx, nts);
+    nstart[k] = tile_start[tt];
+    pre[k + 1] = pre[k] + tile_start[tt + 1] - tile_start[tt];
+  }
+  const int ncand = pre[9];
+  __syncthreads();
+
+  auto process = [&]() {
+    const int cnt = lcount;
+    const int items = cnt * P;
+    for (int it = tid; it < items; it += 256) {
+      const int j = it / P, qrow = it - j * P;
+      const int g = lst[j];
+      const auto p = xt[g];
+      const auto m = mut[g];
+      const int2 an = anchor[g];
+      const int ixn = an.x, iyn = an.y;
+      const int iy = iyn - half + qrow;
+      const int ry = wrapi(iy - gy0, M);
+      if (ry >= TT) continue;
+      const T dy = p.y - iy * h;
+      const T wy = cg * dev_exp(-ag * dy * dy);
+      for (int pc = 0; pc < P; ++pc) {
+        const int ix = ixn - half + pc;
+        const int rx = wrapi(ix - gx0, M);
+        if (rx >= TT) continue;
+        const T dx = p.x - ix * h;
+        const T wgt = wy * dev_exp(-ag * dx * dx);
+        atomicAdd(&acc[0][ry * TT + rx], wgt * m.x);
+        atomicAdd(&acc[1][ry * TT + rx], wgt * m.y);
+      }
+    }
+  };
+
+  for (int v0 = 0; v0 < ncand; v0 += 256) {
+    const int v = v0 + tid;
+    if (v < ncand) {
+      int k = 0;
+      while (k < 8 && v >= pre[k + 1]) ++k;
+      const int g = nstart[k] + (v - pre[k]);
+      const int2 an = anchor[g];
+      const int ixn = an.x, iyn = an.y;
+      const int ux = wrapi(ixn - half - gx0, M), uy = wrapi(iyn - half - gy0, M);
+      const bool hitx = ux < TT || ux + P - 1 >= M;
+      const bool hity = uy < TT || uy + P - 1 >= M;
+      if (hitx && hity) lst[atomicAdd(&lcount, 1)] = g;
+    }
+    __syncthreads();
+    if (lcount > kList - 256 || v0 + 256 >= ncand) {
+      process();
+      __syncthreads();
+      if (tid == 0) lcount = 0;
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < TT * TT; i += 256) {
+    const int ry = i / TT, rx = i - ry * TT;
+    const size_t gidx = (size_t)(gy0 + ry) * M + gx0 + rx;
+    grid[gidx] = acc[0][i];
+    grid[(size_t)M * M + gidx] = acc[1][i];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_interp(int M, int TT, int P, int nts, T h, T ag, T scale,
+                                                const int *__restrict__ tile_start,
+                                                const typename Vec2<T>::type *__restrict__ xt,
+                                                const int2 *__restrict__ anchor,
+                                                const int *__restrict__ tperm, const T *__restrict__ grid,
+                                                double *__restrict__ out) {
+  constexpr int W = kTmax + kPmax - 1;
+  __shared__ T win[2][W * W];
+  const int tid = threadIdx.x;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tyi = tile / nts, txi = tile % nts;
+  const int gx0 = txi * TT, gy0 = tyi * TT;
+  const int half = (P - 1) / 2;
+  const int w = TT + P - 1;
+  for (int i = tid; i < w * w; i += 256) {
+    const int ry = i / w, rx = i - ry * w;
+    const size_t gidx = (size_t)wrapi(gy0 - half + ry, M) * M + wrapi(gx0 - half + rx, M);
+    win[0][i] = grid[gidx];
+    win[1][i] = grid[(size_t)M * M + gidx];
+  }
+  __syncthreads();
+  const int a = tile_start[tile], b = tile_start[tile + 1];
+  for (int k = a + tid; k < b; k += 256) {
+    const auto p = xt[k];
+    const int2 an = anchor[k];
+    const int ixn = an.x, iyn = an.y;
+    const int bx = wrapi(ixn - half - (gx0 - half), M);  // window column of the first stencil point
+    const int by = wrapi(iyn - half - (gy0 - half), M);
+    T wx[kPmax];
+    for (int pc = 0; pc < P; ++pc) {
+      const T dx = p.x - (ixn - half + pc) * h;
+      wx[pc] = dev_exp(-ag * dx * dx);
+    }
+    T sx = 0, sy = 0;
+    for (int qr = 0; qr < P; ++qr) {
+      const T dy = p.y - (iyn - half + qr) * h;
+      const T wy = dev_exp(-ag * dy * dy);
+      const T *r0 = &win[0][(by + qr) * w + bx];
+      const T *r1 = &win[1][(by + qr) * w + bx];
+      T rx0 = 0, rx1 = 0;
+      for (int pc = 0; pc < P; ++pc) {
+        rx0 += wx[pc] * r0[pc];
+        rx1 += wx[pc] * r1[pc];
+      }
+      sx += wy * rx0;
+      sy += wy * rx1;
+    }
+    const int node = tperm[k];
+    out[2 * node] += (double)(scale * sx);
+    out[2 * node + 1] += (double)(scale * sy);
+  }
+}
+
+// mode 0: (1+u) exp(-(1-eta_s) u) / k^2 (I - k k^T/k^2)          (M^(w), eq. 3.23)
+// mode 1: sqrt(1+u) exp(-(1-eta_s) u/2) / k (I - k k^T/k^2)       (B^(1/2), eq. 3.29)
+// with u = k^2 / 4 xi^2, times `scale`; zero at k = 0.  On the Nyquist row and
+// column the off-diagonal term is dropped, which makes the complex-to-real
+// inverse transform equal to the real part of the full inverse transform.
+template <typename T>
+__global__ void k_multiplier(int M, T twopi_L, T inv4xi2, T one_m_eta, T scale, int mode,
+                             typename Vec2<T>::type *__restrict__ spec) {
+  const int nh = M / 2 + 1;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * nh) return;
+  const int row = idx / nh, col = idx - row * nh;
+  const T kx = twopi_L * col;
+  const T ky = twopi_L * (row < M / 2 ? row : row - M);
+  const T k2 = kx * kx + ky * ky;
+  auto &Fx = spec[idx];
+  auto &Fy = spec[(size_t)M * nh + idx];
+  if (k2 == T(0)) {
+    Fx.x = Fx.y = Fy.x = Fy.y = T(0);
+    return;
+  }
+  const T u = k2 * inv4xi2;
+  T s;
+  if (mode == 0)
+    s = (T(1) + u) * exp(-one_m_eta * u) / k2 * scale;
+  else
+    s = sqrt(T(1) + u) * exp(T(-0.5) * one_m_eta * u) / sqrt(k2) * scale;
+  const T pxx = T(1) - kx * kx / k2, pyy = T(1) - ky * ky / k2;
+  const T pxy = (col == M / 2 || row == M / 2) ? T(0) : -kx * ky / k2;
+  const auto fx = Fx, fy = Fy;
+  Fx.x = s * (pxx * fx.x + pxy * fy.x);
+  Fx.y = s * (pxx * fx.y + pxy * fy.y);
+  Fy.x = s * (pxy * fx.x + pyy * fy.x);
+  Fy.y = s * (pxy * fx.y + pyy * fy.y);
+}
+
+}  // namespace
+
+hipError_t launch_spread_f64(const WaveArgs &w, const double *xt, const double *mut, double *grid, hipStream_t s) {
+  const int nt = w.nts * w.nts;
+  hipLaunchKernelGGL(k_spread<double>, dim3(nt), dim3(256), 0, s, w.M, w.T, w.P, w.nts, w.h, w.ag, w.cg,
+                     w.tile_start, (const double2 *)xt, (const int2 *)w.anchor, (const double2 *)mut, grid);
+  return hipGetLastError();
+}
+
+hipError_t launch_spread_f32(const WaveArgs &w, const float *xt, const float *mut, float *grid, hipStream_t s) {
+  const int nt = w.nts * w.nts;
+  hipLaunchKernelGGL(k_spread<float>, dim3(nt), dim3(256), 0, s, w.M, w.T, w.P, w.nts, (float)w.h, (float)w.ag,
+                     (float)w.cg, w.tile_start, (const float2 *)xt, (const int2 *)w.anchor, (const float2 *)mut,
+                     grid);
+  return hipGetLastError();
+}
+
+hipError_t launch_interp_f64(const WaveArgs &w, const double *xt, const int *tperm, const double *grid,
+                             double *out, hipStream_t s) {
+  const int nt = w.nts * w.nts;
+  hipLaunchKernelGGL(k_interp<double>, dim3(nt), dim3(256), 0, s, w.M, w.T, w.P, w.nts, w.h, w.ag,
+                     w.h * w.h * w.cg, w.tile_start, (const double2 *)xt, (const int2 *)w.anchor, tperm, grid, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_interp_f32(const WaveArgs &w, const float *xt, const int *tperm, const float *grid, double *out,
+                             hipStream_t s) {
+  const int nt = w.nts * w.nts;
+  hipLaunchKernelGGL(k_interp<float>, dim3(nt), dim3(256), 0, s, w.M, w.T, w.P, w.nts, (float)w.h, (float)w.ag,
+                     (float)(w.h * w.h * w.cg), w.tile_start, (const float2 *)xt, (const int2 *)w.anchor, tperm,
+                     grid, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_multiplier_f64(int M, double L, double xi, double eta_s, double scale, int mode, double *spec,
+                                 hipStream_t s) {
+  const int n = M * (M / 2 + 1);
+  hipLaunchKernelGGL(k_multiplier<double>, dim3((n + 255) / 256), dim3(256), 0, s, M, 2.0 * M_PI / L,
+                     1.0 / (4.0 * xi * xi), 1.0 - eta_s, scale, mode, (double2 *)spec);
+  return hipGetLastError();
+}
+
+hipError_t launch_multiplier_f32(int M, double L, double xi, double eta_s, double scale, int mode, float *spec,
+                                 hipStream_t s) {
+  const int n = M * (M / 2 + 1);
+  hipLaunchKernelGGL(k_multiplier<float>, dim3((n + 255) / 256), dim3(256), 0, s, M, (float)(2.0 * M_PI / L),
+                     (float)(1.0 / (4.0 * xi * xi)), (float)(1.0 - eta_s), (float)scale, mode, (float2 *)spec);
+  return hipGetLastError();
+}
+
+}  // namespace fbim
