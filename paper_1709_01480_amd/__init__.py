@@ -60,6 +60,9 @@ class Info(ctypes.Structure):
 
 
 def _load():
+    # torch first: the process must use the HIP runtime torch was built with;
+    # libfbim.so then binds to that already-loaded runtime by soname
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError("libfbim.so is not built; run `python -m paper_1709_01480_amd.build` "
                           "(no CPU fallback exists)")

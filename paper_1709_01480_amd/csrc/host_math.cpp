@@ -484,10 +484,14 @@ void sym_functions(int n, const std::vector<double> &A, double tau, std::vector<
   for (double l : lam) lmax = std::max(lmax, l);
   std::vector<double> d1(n), d2(n), d3(n);
   for (int i = 0; i < n; ++i) {
+    // square roots: positive eigenvalues above the spurious threshold only;
+    // inverse: every eigenvalue of magnitude above the threshold, with its sign,
+    // so that the block preconditioner stays nonsingular (the near-null normal
+    // mode of a body carries a small eigenvalue of either sign)
     const bool keep = lam[i] > tau * lmax;
     d1[i] = keep ? 1.0 / std::sqrt(lam[i]) : 0.0;
     d2[i] = keep ? std::sqrt(lam[i]) : 0.0;
-    d3[i] = keep ? 1.0 / lam[i] : 0.0;
+    d3[i] = std::fabs(lam[i]) > tau * lmax ? 1.0 / lam[i] : 0.0;
   }
   auto build = [&](const std::vector<double> &d, std::vector<double> &out) {
     out.assign((size_t)n * n, 0.0);

@@ -133,4 +133,6 @@ def test_random_field_same_algorithm():
     Wg = np.random.default_rng(3).standard_normal(2 * M * M)
     out = zeros(2 * wl.n_nodes)
     ctx.random_field(dev(Wg), out)
-    assert relerr(host(out), OF.random_field(X, Wg, prm)) < 1e-10
+    # the Gaussian deconvolution scales the highest modes (and their FFT round-off)
+    # by up to exp(eta_s u_max / 2) ~ 1e2, hence a looser bound than the matvec
+    assert relerr(host(out), OF.random_field(X, Wg, prm)) < 1e-9
