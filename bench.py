@@ -89,6 +89,10 @@ def main():
     ap.add_argument("--config", default="starfish10k")
     ap.add_argument("--matvecs", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="step", choices=["step", "matvec", "copy"],
+                    help="step: the EM-RFD benchmark; matvec: only single-layer matvecs "
+                         "(short runs for counter collection); copy: a plain 1 GiB device copy "
+                         "used to calibrate the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -102,6 +106,15 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.mode == "copy":
+        n = (1 << 30) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read": 8 * n, "bytes_written": 8 * n, "copies": args.steps}))
+        return
     wl = W.make(args.config)
     prec = fb.PREC_FP64 if args.precision == "fp64" else fb.PREC_MIXED
     log("workload %s: %d bodies x %d nodes" % (args.config, wl.n_bodies, wl.n_p))
@@ -130,6 +143,10 @@ def main():
     torch.cuda.synchronize()
     t_mv = (time.perf_counter() - t0) / args.matvecs
     log("matvec: %.3f ms (%.1f Mnodes/s)" % (1e3 * t_mv, N / t_mv / 1e6))
+    if args.mode == "matvec":
+        print(json.dumps({"mode": "matvec", "nodes": N, "ms": 1e3 * t_mv, "Mnodes/s": N / t_mv / 1e6}))
+        ctx.close()
+        return
 
     # ---- EM-RFD steps
     for i in range(args.warmup):
