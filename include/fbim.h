@@ -54,6 +54,13 @@ typedef enum {
 
 enum { FBIM_PREC_FP64 = 0, FBIM_PREC_MIXED = 1 };
 
+/* bits of fbim_params.flags */
+enum {
+  /* Arnoldi / Lanczos: second Gram-Schmidt pass only when the first cancels more than
+     half of ||w||^2 (default: always two passes) */
+  FBIM_FLAG_SELECTIVE_REORTH = 1u
+};
+
 /* bits of `parts` in fbim_apply_M */
 enum { FBIM_PART_REAL = 1u, FBIM_PART_ALPERT = 2u, FBIM_PART_WAVE = 4u, FBIM_PART_ALL = 7u };
 
@@ -82,7 +89,7 @@ typedef struct {
   int32_t gmres_maxiter; /* total GMRES iteration limit (0: 1000) */
   int32_t lanczos_maxiter; /* Lanczos iteration limit (0: 200) */
   int32_t tile;          /* spreading tile edge in grid points (0: choose) */
-  uint32_t flags;        /* reserved, 0 */
+  uint32_t flags;        /* FBIM_FLAG_* bits */
 } fbim_params;
 
 /* Derived quantities reported back by fbim_get_derived. */

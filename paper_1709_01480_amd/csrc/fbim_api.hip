@@ -59,6 +59,7 @@ struct fbim_ctx {
   std::string err;
   hipStream_t stream = nullptr;
   bool mixed = false;
+  bool cur32 = true;  // in a mixed context: matvecs use the FP32 kernels
 
   std::vector<ShapeDev> shapes;
   double **d_ref_arr = nullptr, **d_band_arr = nullptr, **d_Mp_arr = nullptr, **d_Pref_arr = nullptr,
@@ -84,6 +85,11 @@ struct fbim_ctx {
   double *d_xt = nullptr;
   int *d_anchor = nullptr;
   int *d_scal_int = nullptr;  // [0] max count, [1] overlap flag
+  // neighbour lists of the real-space sum
+  int ngroups = 0;
+  size_t ell_cap = 0;
+  int *d_cnt_near = nullptr, *d_cnt_far = nullptr, *d_gnn = nullptr, *d_gnf = nullptr, *d_goff = nullptr,
+      *d_gsize = nullptr, *d_ell = nullptr;
 
   // matvec scratch
   double *d_mus = nullptr, *d_mut = nullptr;
@@ -103,8 +109,10 @@ struct fbim_ctx {
   int kn = -1;
   double *d_V = nullptr;      // (restart+1) * ntot  (also Lanczos basis)
   double *d_w = nullptr, *d_t1 = nullptr, *d_t2 = nullptr, *d_b = nullptr, *d_x2 = nullptr, *d_r = nullptr;
+  unsigned *d_counter = nullptr;
   double *d_partial = nullptr, *d_h = nullptr, *d_h2 = nullptr, *d_nrm = nullptr, *d_c = nullptr;
-  int nblk = 256;
+  int nblk = 1024;
+  double *d_irx = nullptr, *d_irr = nullptr, *d_ird = nullptr;
   double *d_vec_a = nullptr, *d_vec_b = nullptr, *d_U3 = nullptr, *d_U4 = nullptr, *d_U5 = nullptr;
 
   // timing
@@ -112,6 +120,32 @@ struct fbim_ctx {
   std::map<std::string, std::vector<TimedLaunch>> pending;
   std::map<std::string, std::pair<double, int64_t>> acc;
 
+  PairArgs pair_args() const {
+    PairArgs a;
+    a.cell_start = d_cstart;
+    a.perm = d_cperm;
+    a.nb = d.n_box;
+    a.nbatch = nbatch;
+    a.cell = d.L / d.n_box;
+    a.rc2 = d.r_c * d.r_c;
+    a.xi2 = d.xi * d.xi;
+    a.cG = 1.0 / (4.0 * kPi * p.eta);
+    a.e1tab = d_e1tab;
+    a.e1tab32 = d_e1tab32;
+    return a;
+  }
+  PairLists lists() const {
+    PairLists pl;
+    pl.N = N;
+    pl.ngroups = ngroups;
+    pl.cnt_near = d_cnt_near;
+    pl.cnt_far = d_cnt_far;
+    pl.gnn = d_gnn;
+    pl.gnf = d_gnf;
+    pl.goff = d_goff;
+    pl.ell = d_ell;
+    return pl;
+  }
   GeomDev geom() const {
     GeomDev g;
     g.n = n;
@@ -284,6 +318,11 @@ fbim_status ensure_krylov(fbim_ctx *c) {
   HIPCHK(c, dalloc(c->d_b, ntot));
   HIPCHK(c, dalloc(c->d_x2, ntot));
   HIPCHK(c, dalloc(c->d_r, ntot));
+  if (c->mixed) {
+    HIPCHK(c, dalloc(c->d_irx, ntot));
+    HIPCHK(c, dalloc(c->d_irr, ntot));
+    HIPCHK(c, dalloc(c->d_ird, ntot));
+  }
   HIPCHK(c, dalloc(c->d_partial, (size_t)c->nblk * cols));
   HIPCHK(c, dalloc(c->d_h, cols));
   HIPCHK(c, dalloc(c->d_h2, cols));
@@ -311,7 +350,8 @@ fbim_status build_geometry(fbim_ctx *c) {
   HIPCHK(c, launch_scan(c->ncell, c->d_ccount, c->d_cstart, c->d_scal_int, s));
   HIPCHK(c, launch_scatter(N, c->d_ckey, c->d_cstart, c->d_ccursor, c->d_cperm, s));
   HIPCHK(c, launch_sort_bins(c->ncell, c->d_cstart, c->d_cperm, s));
-  HIPCHK(c, launch_gather2(N, c->d_cperm, c->d_x, c->d_xs, s));
+  HIPCHK(c, launch_cell_local(N, c->d_cperm, c->d_ckey, c->d_x, c->d.n_box, c->d.L / c->d.n_box, c->d_xs,
+                              c->mixed ? c->d_xs32 : nullptr, s));
   // tiles
   HIPCHK(c, hipMemsetAsync(c->d_tcount, 0, c->ntile * sizeof(int), s));
   HIPCHK(c, hipMemsetAsync(c->d_tcursor, 0, c->ntile * sizeof(int), s));
@@ -319,12 +359,7 @@ fbim_status build_geometry(fbim_ctx *c) {
   HIPCHK(c, launch_scan(c->ntile, c->d_tcount, c->d_tstart, c->d_scal_int + 2, s));
   HIPCHK(c, launch_scatter(N, c->d_tkey, c->d_tstart, c->d_tcursor, c->d_tperm, s));
   HIPCHK(c, launch_sort_bins(c->ntile, c->d_tstart, c->d_tperm, s));
-  HIPCHK(c, launch_gather2(N, c->d_tperm, c->d_x, c->d_xt, s));
-  HIPCHK(c, launch_anchors(N, c->d_tperm, c->d_x, c->d.h, c->d_anchor, s));
-  if (c->mixed) {
-    HIPCHK(c, launch_cast_f32(2 * (size_t)N, c->d_xs, c->d_xs32, s));
-    HIPCHK(c, launch_cast_f32(2 * (size_t)N, c->d_xt, c->d_xt32, s));
-  }
+  HIPCHK(c, launch_anchors(N, c->d_tperm, c->d_x, c->d.h, c->d_anchor, c->d_xt, c->mixed ? c->d_xt32 : nullptr, s));
   // overlap check: nodes of distinct bodies closer than 5% of the smallest node spacing
   double spacing = 1e300;
   for (auto &sh : c->shapes) {
@@ -335,7 +370,7 @@ fbim_status build_geometry(fbim_ctx *c) {
     }
   }
   HIPCHK(c, hipMemsetAsync(c->d_scal_int + 1, 0, sizeof(int), s));
-  HIPCHK(c, launch_overlap(N, c->d_cstart, c->d_cperm, c->d_xs, c->d_body, c->d.n_box, c->d.L, 0.05 * spacing,
+  HIPCHK(c, launch_overlap(N, c->d_cstart, c->d_cperm, c->d_x, c->d_body, c->d.n_box, c->d.L, 0.05 * spacing,
                            c->d_scal_int + 1, s));
   int hv[3];
   HIPCHK(c, hipMemcpyAsync(hv, c->d_scal_int, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -344,6 +379,23 @@ fbim_status build_geometry(fbim_ctx *c) {
   c->nbatch = std::max(1, (hv[0] + 63) / 64);
   c->max_tile = hv[2];
   if (hv[1]) return fail(c, FBIM_EOVERLAP, "nodes of distinct bodies closer than 5% of the node spacing");
+  // neighbour lists of the real-space sum: count, group rows, offsets, fill
+  PairArgs pa = c->pair_args();
+  PairLists pl = c->lists();
+  HIPCHK(c, launch_pair_lists(pa, pl, c->d_xs, 0, s));
+  HIPCHK(c, launch_group_rows(pl, c->d_gsize, s));
+  HIPCHK(c, launch_scan(c->ngroups, c->d_gsize, c->d_goff, c->d_scal_int + 3, s));
+  int total = 0;
+  HIPCHK(c, hipMemcpyAsync(&total, c->d_goff + c->ngroups, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if ((size_t)total > c->ell_cap) {
+    const size_t cap = (size_t)total + total / 4 + 64;
+    HIPCHK(c, dalloc(c->d_ell, cap));
+    c->ell_cap = cap;
+    pl.ell = c->d_ell;
+  }
+  HIPCHK(c, launch_fill_int((size_t)total, -1, c->d_ell, s));
+  HIPCHK(c, launch_pair_lists(pa, pl, c->d_xs, 1, s));
   return FBIM_OK;
 }
 
@@ -352,26 +404,18 @@ fbim_status apply_M(fbim_ctx *c, const double *mu, double *out, unsigned parts) 
   hipStream_t s = c->stream;
   const int N = c->N;
   if (!c->have_bodies) return fail(c, FBIM_EINVAL, "no bodies set");
+  const bool f32 = c->mixed && c->cur32;
   if (parts & FBIM_PART_REAL) {
-    PairArgs a;
-    a.cell_start = c->d_cstart;
-    a.perm = c->d_cperm;
-    a.nb = c->d.n_box;
-    a.nbatch = c->nbatch;
-    a.L = c->d.L;
-    a.rc2 = c->d.r_c * c->d.r_c;
-    a.xi2 = c->d.xi * c->d.xi;
-    a.cG = 1.0 / (4.0 * kPi * c->p.eta);
-    a.e1tab = c->d_e1tab;
-    a.e1tab32 = c->d_e1tab32;
-    if (c->mixed) {
+    const PairArgs a = c->pair_args();
+    const PairLists pl = c->lists();
+    if (f32) {
       HIPCHK(c, launch_gather2f(N, c->d_cperm, mu, c->d_mus32, s));
       Timer t(c, "pair");
-      HIPCHK(c, launch_pair_f32(a, c->d_xs32, c->d_mus32, out, s));
+      HIPCHK(c, launch_pair_f32(pl, a, c->d_xs32, c->d_mus32, out, s));
     } else {
       HIPCHK(c, launch_gather2(N, c->d_cperm, mu, c->d_mus, s));
       Timer t(c, "pair");
-      HIPCHK(c, launch_pair_f64(a, c->d_xs, c->d_mus, out, s));
+      HIPCHK(c, launch_pair_f64(pl, a, c->d_xs, c->d_mus, out, s));
     }
   } else {
     HIPCHK(c, launch_fill(2 * (size_t)N, 0.0, out, s));
@@ -393,7 +437,7 @@ fbim_status apply_M(fbim_ctx *c, const double *mu, double *out, unsigned parts) 
     w.tile_start = c->d_tstart;
     w.anchor = c->d_anchor;
     const double scale = c->d.h * c->d.h / (c->p.eta * c->d.L * c->d.L);
-    if (c->mixed) {
+    if (f32) {
       HIPCHK(c, launch_gather2f(N, c->d_tperm, mu, c->d_mut32, s));
       {
         Timer t(c, "spread");
@@ -493,33 +537,55 @@ fbim_status apply_precond(fbim_ctx *c, const double *z, double *y) {
   return FBIM_OK;
 }
 
-// dots h[0..k) = V[:, 0..k)^T w  (device)
-fbim_status dots(fbim_ctx *c, const double *V, int k, const double *w, size_t n, double *h) {
+// dots out[0..k) = V[:, 0..k)^T w (device); out[k] = w^T w if with_norm
+fbim_status dots(fbim_ctx *c, const double *V, int k, const double *w, size_t n, double *out, int with_norm = 0,
+                 const double *cond = nullptr) {
   Timer t(c, "blas");
-  HIPCHK(c, launch_dots(V, c->ntot, k, w, n, c->d_partial, c->nblk, c->stream));
-  HIPCHK(c, launch_reduce_partials(c->d_partial, c->nblk, k, h, c->stream));
+  HIPCHK(c, launch_dots(V, c->ntot, k, w, n, with_norm, cond, c->d_partial, c->nblk, c->d_counter, out, c->stream));
   return FBIM_OK;
 }
 
-// CGS with one reorthogonalisation: w -= V h, h = h1 + h2; returns ||w||^2 in d_nrm[0]
-fbim_status orthogonalise(fbim_ctx *c, const double *V, int k, double *w, size_t n) {
-  STCHK(dots(c, V, k, w, n, c->d_h));
+// Classical Gram-Schmidt of w against the k columns of V with a second pass
+// only when the first one cancels more than half of ||w||^2 (Daniel, Gragg,
+// Kaufman, Stewart criterion).  The decision is taken on the device, so one
+// host synchronisation per call suffices.  On return h[0..k) holds the
+// projection coefficients (host), hn = ||w|| after orthogonalisation, and
+// d_nrm[0] = hn^2.
+fbim_status orthogonalise(fbim_ctx *c, const double *V, int k, double *w, size_t n, double *h, double &hn) {
+  hipStream_t s = c->stream;
+  double *flag = c->d_nrm + 1, *nrm2 = c->d_nrm + 2;
+  STCHK(dots(c, V, k, w, n, c->d_h, 1));
   {
     Timer t(c, "blas");
-    HIPCHK(c, launch_sub_Vh(V, c->ntot, k, c->d_h, w, n, c->stream));
+    HIPCHK(c, launch_sub_Vh(V, c->ntot, k, c->d_h, w, n, nullptr, c->d_partial, c->nblk, c->d_counter, c->d_nrm, s));
+    if (c->p.flags & FBIM_FLAG_SELECTIVE_REORTH)
+      HIPCHK(c, launch_need_second_pass(c->d_nrm, c->d_h + k, flag, s));
+    else
+      HIPCHK(c, launch_fill(1, 1.0, flag, s));
   }
-  STCHK(dots(c, V, k, w, n, c->d_h2));
+  STCHK(dots(c, V, k, w, n, c->d_h2, 0, flag));
   {
     Timer t(c, "blas");
-    HIPCHK(c, launch_sub_Vh(V, c->ntot, k, c->d_h2, w, n, c->stream));
-    HIPCHK(c, launch_vec_add(k, c->d_h2, c->d_h, c->stream));
+    HIPCHK(c, launch_sub_Vh(V, c->ntot, k, c->d_h2, w, n, flag, c->d_partial, c->nblk, c->d_counter, nrm2, s));
   }
-  STCHK(dots(c, w, 1, w, n, c->d_nrm));
+  std::vector<double> h2(k + 3);
+  HIPCHK(c, hipMemcpyAsync(h, c->d_h, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(h2.data(), c->d_h2, k * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(h2.data() + k, c->d_nrm, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  double after = h2[k];
+  if (h2[k + 1] != 0.0) {
+    for (int i = 0; i < k; ++i) h[i] += h2[i];
+    after = h2[k + 2];
+    // keep d_nrm[0] = ||w||^2 for the normalisation kernels
+    HIPCHK(c, hipMemcpyAsync(c->d_nrm, c->d_nrm + 2, sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  hn = std::sqrt(std::max(after, 0.0));
   return FBIM_OK;
 }
 
 fbim_status norm2(fbim_ctx *c, const double *x, size_t n, double &out) {
-  STCHK(dots(c, x, 1, x, n, c->d_nrm));
+  STCHK(dots(c, x, 1, x, n, c->d_nrm, 0));
   double v;
   HIPCHK(c, hipMemcpyAsync(&v, c->d_nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -528,7 +594,7 @@ fbim_status norm2(fbim_ctx *c, const double *x, size_t n, double &out) {
 }
 
 // right-preconditioned restarted GMRES for the saddle system; b, x device (ntot)
-fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iters, double &relres) {
+fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iters, double &relres, int maxit) {
   const size_t nt = c->ntot;
   hipStream_t s = c->stream;
   const int m = c->restart;
@@ -538,7 +604,7 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
   STCHK(norm2(c, b, nt, nb));
   HIPCHK(c, launch_fill(nt, 0.0, x, s));
   if (nb == 0.0) return FBIM_OK;
-  std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), hcol(m + 2), y(m);
+  std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), hcol(m + 3), y(m);
   bool first = true;
   for (;;) {
     // r = b - A x
@@ -552,7 +618,7 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
     STCHK(norm2(c, c->d_r, nt, beta));
     relres = beta / nb;
     if (relres <= tol) return FBIM_OK;
-    if (iters >= c->gmres_max) return fail(c, FBIM_ENOCONV, "GMRES iteration limit reached");
+    if (iters >= maxit) return fail(c, FBIM_ENOCONV, "GMRES iteration limit reached");
     first = false;
     {
       Timer t(c, "blas");
@@ -566,11 +632,8 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
       double *w = c->d_V + (size_t)(j + 1) * nt;
       STCHK(apply_precond(c, vj, c->d_t1));
       STCHK(apply_saddle(c, c->d_t1, w));
-      STCHK(orthogonalise(c, c->d_V, j + 1, w, nt));
-      HIPCHK(c, hipMemcpyAsync(hcol.data(), c->d_h, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(c, hipMemcpyAsync(hcol.data() + j + 1, c->d_nrm, sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(c, hipStreamSynchronize(s));
-      const double hn = std::sqrt(std::max(hcol[j + 1], 0.0));
+      double hn = 0;
+      STCHK(orthogonalise(c, c->d_V, j + 1, w, nt, hcol.data(), hn));
       hcol[j + 1] = hn;
       if (hn > 0) {
         Timer t(c, "blas");
@@ -591,7 +654,7 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i];
       ++iters;
       jend = j + 1;
-      if (std::fabs(g[j + 1]) <= tol * nb || iters >= c->gmres_max || hn == 0.0) break;
+      if (std::fabs(g[j + 1]) <= tol * nb || iters >= maxit || hn == 0.0) break;
     }
     // y = H^-1 g, x += P^-1 V y
     for (int i = jend - 1; i >= 0; --i) {
@@ -609,6 +672,43 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
   }
 }
 
+// Solve the saddle system to tol.  FP64 contexts: GMRES directly.  Mixed
+// contexts: iterative refinement -- the residual b - A x is formed with the
+// FP64 matvec, and each correction solves A d = r with GMRES on the FP32
+// matvec to a relative tolerance of 1e-3.
+fbim_status solve_saddle(fbim_ctx *c, const double *b, double *x, double tol, int &iters, double &relres) {
+  if (!c->mixed) return gmres(c, b, x, tol, iters, relres, c->gmres_max);
+  const size_t nt = c->ntot;
+  hipStream_t s = c->stream;
+  iters = 0;
+  double nb;
+  STCHK(norm2(c, b, nt, nb));
+  HIPCHK(c, launch_fill(nt, 0.0, x, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_irr, b, nt * sizeof(double), hipMemcpyDeviceToDevice, s));
+  relres = nb > 0 ? 1.0 : 0.0;
+  if (nb == 0.0) return FBIM_OK;
+  for (int outer = 0; outer < 20; ++outer) {
+    int it = 0;
+    double rr = 0;
+    c->cur32 = true;
+    fbim_status st = gmres(c, c->d_irr, c->d_ird, 1e-3, it, rr, std::max(1, c->gmres_max - iters));
+    iters += it;
+    if (st != FBIM_OK && st != FBIM_ENOCONV) return st;
+    HIPCHK(c, launch_axpby(nt, 1.0, c->d_ird, 1.0, x, s));
+    c->cur32 = false;  // FP64 residual of the refined solution
+    fbim_status st2 = apply_saddle(c, x, c->d_irr);
+    c->cur32 = true;
+    STCHK(st2);
+    HIPCHK(c, launch_axpby(nt, 1.0, b, -1.0, c->d_irr, s));
+    double nr;
+    STCHK(norm2(c, c->d_irr, nt, nr));
+    relres = nr / nb;
+    if (relres <= tol) return FBIM_OK;
+    if (iters >= c->gmres_max) break;
+  }
+  return fail(c, FBIM_ENOCONV, "GMRES iterative refinement did not reach the tolerance");
+}
+
 // Lanczos for (G M^(r) G^T)^(1/2) b with full reorthogonalisation; y = ||b|| V f(T) e_1
 fbim_status lanczos_sqrt(fbim_ctx *c, const double *b, double *out, int &iters, double &change) {
   const size_t n2 = 2 * (size_t)c->N;
@@ -623,7 +723,7 @@ fbim_status lanczos_sqrt(fbim_ctx *c, const double *b, double *out, int &iters, 
   }
   const int kmax = std::min(c->lanczos_max, (int)c->capV - 1);
   HIPCHK(c, launch_axpby(n2, 1.0 / beta0, b, 0.0, c->d_V, s));
-  std::vector<double> alpha, beta, cprev, cur, hbuf(kmax + 2);
+  std::vector<double> alpha, beta, cprev, cur, hbuf(kmax + 3);
   fbim_status st = FBIM_OK;
   int k = 0;
   for (;; ++k) {
@@ -632,12 +732,9 @@ fbim_status lanczos_sqrt(fbim_ctx *c, const double *b, double *out, int &iters, 
     HIPCHK(c, launch_body_apply(c->geom(), c->mats(), 0, vk, c->d_vec_a, s));
     STCHK(apply_M(c, c->d_vec_a, c->d_vec_b, FBIM_PART_REAL | FBIM_PART_ALPERT));
     HIPCHK(c, launch_body_apply(c->geom(), c->mats(), 0, c->d_vec_b, w, s));
-    STCHK(orthogonalise(c, c->d_V, k + 1, w, n2));
-    HIPCHK(c, hipMemcpyAsync(hbuf.data(), c->d_h, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(hbuf.data() + k + 1, c->d_nrm, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
+    double bk = 0;
+    STCHK(orthogonalise(c, c->d_V, k + 1, w, n2, hbuf.data(), bk));
     alpha.push_back(hbuf[k]);
-    const double bk = std::sqrt(std::max(hbuf[k + 1], 0.0));
     // coefficients c = beta0 Q sqrt(max(L, 0)) Q^T e1 of the (k+1) x (k+1) tridiagonal
     const int m = k + 1;
     std::vector<double> T((size_t)m * m, 0.0), lam, Q;
@@ -690,7 +787,7 @@ fbim_status mobility(fbim_ctx *c, const double *F, const double *slip, double *U
   else
     HIPCHK(c, launch_fill(twoN, 0.0, c->d_b, s));
   HIPCHK(c, launch_axpby(3 * (size_t)c->n, -1.0, F, 0.0, c->d_b + twoN, s));
-  fbim_status st = gmres(c, c->d_b, c->d_x2, c->p.tol_gmres, its, res);
+  fbim_status st = solve_saddle(c, c->d_b, c->d_x2, c->p.tol_gmres, its, res);
   if (st != FBIM_OK && st != FBIM_ENOCONV) return st;
   HIPCHK(c, hipMemcpyAsync(U, c->d_x2 + twoN, 3 * (size_t)c->n * sizeof(double), hipMemcpyDeviceToDevice, s));
   if (mu_out) HIPCHK(c, hipMemcpyAsync(mu_out, c->d_x2, twoN * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -804,6 +901,10 @@ fbim_status fbim_create(const fbim_params *params, fbim_ctx **out) {
   c->gmres_max = c->p.gmres_maxiter > 0 ? c->p.gmres_maxiter : 1000;
   c->lanczos_max = c->p.lanczos_maxiter > 0 ? c->p.lanczos_maxiter : 200;
   c->mixed = c->p.precision == FBIM_PREC_MIXED;
+  if (c->restart > 500 || c->lanczos_max > 500) {
+    fbim_destroy(c);
+    return FBIM_EINVAL;
+  }
   if (c->p.precision != FBIM_PREC_FP64 && c->p.precision != FBIM_PREC_MIXED) {
     fbim_destroy(c);
     return FBIM_EINVAL;
@@ -830,7 +931,9 @@ fbim_status fbim_create(const fbim_params *params, fbim_ctx **out) {
   auto t32d = e1_table(kE1Deg32);
   std::vector<float> t32(t32d.begin(), t32d.end());
   if ((st = upload(c, c->d_e1tab, t64)) != FBIM_OK || (st = upload(c, c->d_e1tab32, t32)) != FBIM_OK ||
-      hipMalloc((void **)&c->d_scal_int, 4 * sizeof(int)) != hipSuccess ||
+      hipMalloc((void **)&c->d_scal_int, 8 * sizeof(int)) != hipSuccess ||
+      hipMalloc((void **)&c->d_counter, sizeof(unsigned)) != hipSuccess ||
+      hipMemset(c->d_counter, 0, sizeof(unsigned)) != hipSuccess ||
       dalloc(c->d_ccount, c->ncell) != hipSuccess || dalloc(c->d_ccursor, c->ncell) != hipSuccess ||
       dalloc(c->d_cstart, c->ncell + 1) != hipSuccess || dalloc(c->d_tcount, c->ntile) != hipSuccess ||
       dalloc(c->d_tcursor, c->ntile) != hipSuccess || dalloc(c->d_tstart, c->ntile + 1) != hipSuccess) {
@@ -870,8 +973,8 @@ void fbim_destroy(fbim_ctx *c) {
                   c->d_tcount, c->d_tstart, c->d_tperm, c->d_tcursor, c->d_xt, c->d_anchor, c->d_scal_int, c->d_mus,
                   c->d_mut, c->d_xs32, c->d_mus32, c->d_xt32, c->d_mut32, c->d_grid, c->d_spec, c->d_grid32,
                   c->d_spec32, c->d_e1tab, c->d_e1tab32, c->d_V, c->d_w, c->d_t1, c->d_t2, c->d_b, c->d_x2,
-                  c->d_r, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
-                  c->d_U4, c->d_U5};
+                  c->d_r, c->d_counter, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
+                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell};
   for (void *p : ptrs)
     if (p) hipFree(p);
   delete c;
@@ -945,6 +1048,13 @@ fbim_status fbim_set_bodies(fbim_ctx *c, int32_t n, const int32_t *shape_id, con
     HIPCHK(c, dalloc(c->d_anchor, 2 * N));
     HIPCHK(c, dalloc(c->d_mus, 2 * N));
     HIPCHK(c, dalloc(c->d_mut, 2 * N));
+    c->ngroups = (N + 63) / 64;
+    HIPCHK(c, dalloc(c->d_cnt_near, N));
+    HIPCHK(c, dalloc(c->d_cnt_far, N));
+    HIPCHK(c, dalloc(c->d_gnn, c->ngroups));
+    HIPCHK(c, dalloc(c->d_gnf, c->ngroups));
+    HIPCHK(c, dalloc(c->d_gsize, c->ngroups));
+    HIPCHK(c, dalloc(c->d_goff, c->ngroups + 1));
     if (c->mixed) {
       HIPCHK(c, dalloc(c->d_xs32, 2 * N));
       HIPCHK(c, dalloc(c->d_mus32, 2 * N));

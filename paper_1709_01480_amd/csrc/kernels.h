@@ -29,24 +29,43 @@ hipError_t launch_scatter(int N, const int *key, const int *start, int *cursor, 
 hipError_t launch_sort_bins(int nbins, const int *start, int *perm, hipStream_t s);
 hipError_t launch_gather2(int N, const int *perm, const double *src, double *dst, hipStream_t s);
 hipError_t launch_gather2f(int N, const int *perm, const double *src, float *dst, hipStream_t s);
-// nearest grid indices floor(x / h + 1/2) of the nodes in tile order
-hipError_t launch_anchors(int N, const int *tperm, const double *x, double h, int *anchor, hipStream_t s);
+// tile order: nearest grid indices a = floor(x / h + 1/2) and offsets x - a h (FP64, and FP32 if off32)
+hipError_t launch_anchors(int N, const int *tperm, const double *x, double h, int *anchor, double *off64,
+                          float *off32, hipStream_t s);
+// cell order: coordinates relative to the node's cell corner (FP64, and FP32 if loc32)
+hipError_t launch_cell_local(int N, const int *cperm, const int *key, const double *x, int nb, double cell,
+                             double *loc64, float *loc32, hipStream_t s);
 
-// closest approach of nodes of distinct bodies (cell list); flag set if < thresh
-hipError_t launch_overlap(int N, const int *cell_start, const int *perm, const double *xs, const int *body,
+// closest approach of nodes of distinct bodies (cell list, absolute positions xa); flag set if < thresh
+hipError_t launch_overlap(int N, const int *cell_start, const int *perm, const double *xa, const int *body,
                           int nb, double L, double thresh, int *flag, hipStream_t s);
 
-// real-space pair sum (eq. 3.15, trapezoid pairs within r_c): out[perm[i]] = sum
+// real-space pair sum (eq. 3.15, trapezoid pairs within r_c): out[perm[i]] = sum;
+// xs are cell-local coordinates (launch_cell_local)
 struct PairArgs {
   const int *cell_start;
   const int *perm;
   int nb, nbatch;
-  double L, rc2, xi2, cG;
+  double cell, rc2, xi2, cG;  // cell side L / n_box
   const double *e1tab;  // FP64 table
   const float *e1tab32; // FP32 table
 };
-hipError_t launch_pair_f64(const PairArgs &a, const double *xs, const double *mus, double *out, hipStream_t s);
-hipError_t launch_pair_f32(const PairArgs &a, const float *xs, const float *mus, double *out, hipStream_t s);
+// Neighbour lists in ELL layout (groups of 64 cell-sorted targets; near rows first)
+struct PairLists {
+  int N, ngroups;
+  int *cnt_near, *cnt_far;  // [N]
+  int *gnn, *gnf, *goff;    // [ngroups], goff [ngroups + 1]
+  int *ell;                 // [goff[ngroups]]
+};
+// mode 0: per-target near / far counts; mode 1: fill pl.ell (pre-set to -1)
+hipError_t launch_pair_lists(const PairArgs &a, PairLists &pl, const double *xs, int mode, hipStream_t s);
+// gnn, gnf and gsize[g] = 64 (gnn + gnf) from the counts
+hipError_t launch_group_rows(PairLists &pl, int *gsize, hipStream_t s);
+hipError_t launch_pair_f64(const PairLists &pl, const PairArgs &a, const double *xs, const double *mus, double *out,
+                           hipStream_t s);
+hipError_t launch_pair_f32(const PairLists &pl, const PairArgs &a, const float *xs, const float *mus, double *out,
+                           hipStream_t s);
+hipError_t launch_fill_int(size_t n, int v, int *y, hipStream_t s);
 
 // Alpert band: out[i] += R_b A_ref R_b^T mu (per node); accumulate=1 adds
 hipError_t launch_alpert(const GeomDev &g, const double *const *band_tab, const int *band, const double *mu,
@@ -59,6 +78,7 @@ struct WaveArgs {
   const int *tile_start;
   const int *anchor;    // per tile-sorted node: nearest grid indices (ix, iy), unwrapped, from FP64 positions
 };
+// xt are the tile-ordered offsets from the nearest grid point (launch_anchors)
 hipError_t launch_spread_f64(const WaveArgs &w, const double *xt, const double *mut, double *grid, hipStream_t s);
 hipError_t launch_spread_f32(const WaveArgs &w, const float *xt, const float *mut, float *grid, hipStream_t s);
 hipError_t launch_interp_f64(const WaveArgs &w, const double *xt, const int *tperm, const double *grid,
@@ -93,12 +113,18 @@ hipError_t launch_body_apply(const GeomDev &g, const BodyMats &m, int which, con
                              hipStream_t s);
 
 // Krylov helpers (FP64)
-// partial[blk][j] = sum over the block's rows of V[j*ld + i] * w[i], j < k
-hipError_t launch_dots(const double *V, size_t ld, int k, const double *w, size_t n, double *partial, int nblk,
-                       hipStream_t s);
-hipError_t launch_reduce_partials(const double *partial, int nblk, int k, double *out, hipStream_t s);
-// w[i] -= sum_j V[j*ld + i] * h[j]   (h on device)
-hipError_t launch_sub_Vh(const double *V, size_t ld, int k, const double *h, double *w, size_t n, hipStream_t s);
+// out[j] = V[:, j]^T w (j < k) and, if with_norm, out[k] = w^T w.  partial holds
+// nblk * (k + 1) doubles; counter is a zero-initialised device word reserved for
+// this stream (the last block to finish reduces and resets it).
+// If cond is given and cond[0] == 0 the kernel does nothing (conditional second pass).
+hipError_t launch_dots(const double *V, size_t ld, int k, const double *w, size_t n, int with_norm,
+                       const double *cond, double *partial, int nblk, unsigned *counter, double *out, hipStream_t s);
+// w[i] -= sum_j V[j*ld + i] * h[j] (h on device, k <= 512); nrm[0] = ||w||^2 afterwards
+hipError_t launch_sub_Vh(const double *V, size_t ld, int k, const double *h, double *w, size_t n,
+                         const double *cond, double *partial, int nblk, unsigned *counter, double *nrm,
+                         hipStream_t s);
+// flag[0] = 1 if nrm[0] < before[0] / 2 (classical Gram-Schmidt lost more than half of ||w||^2)
+hipError_t launch_need_second_pass(const double *nrm, const double *before, double *flag, hipStream_t s);
 // y[i] = sum_j V[j*ld + i] * c[j]
 hipError_t launch_Vc(const double *V, size_t ld, int k, const double *c, double *y, size_t n, hipStream_t s);
 hipError_t launch_axpby(size_t n, double a, const double *x, double b, double *y, hipStream_t s);  // y = a x + b y

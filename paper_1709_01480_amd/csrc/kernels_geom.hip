@@ -127,24 +127,41 @@ hipError_t launch_scatter(int N, const int *key, const int *start, int *cursor, 
   return hipGetLastError();
 }
 
-// order nodes inside each bin by node index (makes the permutation deterministic)
-__global__ void k_sort_bins(int nbins, const int *__restrict__ start, int *__restrict__ perm) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nbins) return;
-  const int a = start[c], b = start[c + 1];
-  for (int i = a + 1; i < b; ++i) {
-    const int v = perm[i];
-    int j = i - 1;
-    while (j >= a && perm[j] > v) {
-      perm[j + 1] = perm[j];
-      --j;
-    }
-    perm[j + 1] = v;
+// Order the nodes inside each bin by node index (makes the permutation
+// deterministic).  One work group per bin: the bin is staged in LDS and every
+// entry is written to the position given by its rank (all entries distinct).
+constexpr int kSortCap = 2048;
+
+__global__ __launch_bounds__(256) void k_sort_bins(const int *__restrict__ start, int *__restrict__ perm) {
+  __shared__ int buf[kSortCap];
+  const int a = start[blockIdx.x], n = start[blockIdx.x + 1] - a;
+  if (n <= 1) return;
+  if (n > kSortCap) {  // rare oversized bin: serial insertion sort
+    if (threadIdx.x == 0)
+      for (int i = a + 1; i < a + n; ++i) {
+        const int v = perm[i];
+        int j = i - 1;
+        while (j >= a && perm[j] > v) {
+          perm[j + 1] = perm[j];
+          --j;
+        }
+        perm[j + 1] = v;
+      }
+    return;
+  }
+  for (int i = threadIdx.x; i < n; i += 256) buf[i] = perm[a + i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const int v = buf[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) rank += buf[j] < v;
+    perm[a + rank] = v;
   }
 }
 
 hipError_t launch_sort_bins(int nbins, const int *start, int *perm, hipStream_t s) {
-  hipLaunchKernelGGL(k_sort_bins, dim3((nbins + 255) / 256), dim3(256), 0, s, nbins, start, perm);
+  if (nbins == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sort_bins, dim3(nbins), dim3(256), 0, s, start, perm);
   return hipGetLastError();
 }
 
@@ -177,27 +194,57 @@ hipError_t launch_gather2f(int N, const int *perm, const double *src, float *dst
   return hipGetLastError();
 }
 
-__global__ void k_anchors(int N, const int *__restrict__ tperm, const double *__restrict__ x, double inv_h,
-                          int2 *__restrict__ anchor) {
+// Tile-ordered stencil data: nearest grid indices a = floor(x/h + 1/2) (unwrapped)
+// and the FP64 offsets x - a h, |offset| <= h/2 (also stored in FP32).
+__global__ void k_anchors(int N, const int *__restrict__ tperm, const double *__restrict__ x, double h,
+                          int2 *__restrict__ anchor, double2 *__restrict__ off64, float2 *__restrict__ off32) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
   const int i = tperm[k];
-  anchor[k] = make_int2((int)floor(x[2 * i] * inv_h + 0.5), (int)floor(x[2 * i + 1] * inv_h + 0.5));
+  const double px = x[2 * i], py = x[2 * i + 1];
+  const int ax = (int)floor(px / h + 0.5), ay = (int)floor(py / h + 0.5);
+  anchor[k] = make_int2(ax, ay);
+  const double ox = px - ax * h, oy = py - ay * h;
+  off64[k] = make_double2(ox, oy);
+  if (off32) off32[k] = make_float2((float)ox, (float)oy);
 }
 
-hipError_t launch_anchors(int N, const int *tperm, const double *x, double h, int *anchor, hipStream_t s) {
+hipError_t launch_anchors(int N, const int *tperm, const double *x, double h, int *anchor, double *off64,
+                          float *off32, hipStream_t s) {
   if (N == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_anchors, dim3((N + 255) / 256), dim3(256), 0, s, N, tperm, x, 1.0 / h, (int2 *)anchor);
+  hipLaunchKernelGGL(k_anchors, dim3((N + 255) / 256), dim3(256), 0, s, N, tperm, x, h, (int2 *)anchor,
+                     (double2 *)off64, (float2 *)off32);
+  return hipGetLastError();
+}
+
+// Cell-ordered coordinates relative to the lower-left corner of the node's cell.
+__global__ void k_cell_local(int N, const int *__restrict__ cperm, const int *__restrict__ key,
+                             const double *__restrict__ x, int nb, double cell, double2 *__restrict__ loc64,
+                             float2 *__restrict__ loc32) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const int i = cperm[k];
+  const int c = key[i];
+  const double lx = x[2 * i] - (c % nb) * cell, ly = x[2 * i + 1] - (c / nb) * cell;
+  loc64[k] = make_double2(lx, ly);
+  if (loc32) loc32[k] = make_float2((float)lx, (float)ly);
+}
+
+hipError_t launch_cell_local(int N, const int *cperm, const int *key, const double *x, int nb, double cell,
+                             double *loc64, float *loc32, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cell_local, dim3((N + 255) / 256), dim3(256), 0, s, N, cperm, key, x, nb, cell,
+                     (double2 *)loc64, (float2 *)loc32);
   return hipGetLastError();
 }
 
 // one thread per node: scan the 3x3 neighbouring cells for nodes of other bodies
 __global__ void k_overlap(int N, const int *__restrict__ cell_start, const int *__restrict__ perm,
-                          const double *__restrict__ xs, const int *__restrict__ body, int nb, double L,
+                          const double *__restrict__ xa, const int *__restrict__ body, int nb, double L,
                           double thresh2, int *__restrict__ flag) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= N) return;
-  const double x = xs[2 * p], y = xs[2 * p + 1];
+  const double x = xa[2 * perm[p]], y = xa[2 * perm[p] + 1];
   const int bi = body[perm[p]];
   const double inv = nb / L;
   const int cx = min(max((int)floor(x * inv), 0), nb - 1), cy = min(max((int)floor(y * inv), 0), nb - 1);
@@ -206,7 +253,7 @@ __global__ void k_overlap(int N, const int *__restrict__ cell_start, const int *
       const int c = ((cy + dy + nb) % nb) * nb + (cx + dx + nb) % nb;
       for (int k = cell_start[c]; k < cell_start[c + 1]; ++k) {
         if (body[perm[k]] == bi) continue;
-        double ex = x - xs[2 * k], ey = y - xs[2 * k + 1];
+        double ex = x - xa[2 * perm[k]], ey = y - xa[2 * perm[k] + 1];
         ex -= L * rint(ex / L);
         ey -= L * rint(ey / L);
         if (ex * ex + ey * ey < thresh2) atomicOr(flag, 1);
@@ -214,10 +261,10 @@ __global__ void k_overlap(int N, const int *__restrict__ cell_start, const int *
     }
 }
 
-hipError_t launch_overlap(int N, const int *cell_start, const int *perm, const double *xs, const int *body, int nb,
+hipError_t launch_overlap(int N, const int *cell_start, const int *perm, const double *xa, const int *body, int nb,
                           double L, double thresh, int *flag, hipStream_t s) {
   if (N == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_overlap, dim3((N + 255) / 256), dim3(256), 0, s, N, cell_start, perm, xs, body, nb, L,
+  hipLaunchKernelGGL(k_overlap, dim3((N + 255) / 256), dim3(256), 0, s, N, cell_start, perm, xa, body, nb, L,
                      thresh * thresh, flag);
   return hipGetLastError();
 }

@@ -214,20 +214,52 @@ hipError_t launch_body_apply(const GeomDev &g, const BodyMats &m, int which, con
 // ------------------------------------------------------------------ Krylov vector kernels
 constexpr int kDotCols = 8;
 
-// partial[blk * k + j] for columns j < k, rows of this block's grid-stride range
+// Column sums of a block-partial array partial[j * nblk + b] by the last block to
+// finish (fixed summation order, so the result is deterministic).
+__device__ void last_block_reduce(double *__restrict__ partial, int nblk, int k, unsigned *__restrict__ counter,
+                                  double *__restrict__ out) {
+  __shared__ bool last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int j = wv; j < k; j += nw) {
+    double s = 0.0;
+    for (int b = lane; b < nblk; b += 64)
+      s += __hip_atomic_load(&partial[(size_t)j * nblk + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o);
+    if (lane == 0) out[j] = s;
+  }
+  if (threadIdx.x == 0) *counter = 0u;  // ready for the next launch on this stream
+}
+
+// out[j] = V[:, j]^T w for j < k, and out[k] = w^T w if with_norm
 __global__ __launch_bounds__(256) void k_dots(const double *__restrict__ V, size_t ld, int k,
-                                              const double *__restrict__ w, size_t n, double *__restrict__ partial) {
+                                              const double *__restrict__ w, size_t n, int with_norm,
+                                              const double *__restrict__ cond, double *__restrict__ partial,
+                                              unsigned *__restrict__ counter, double *__restrict__ out) {
   __shared__ double red[kDotCols][4];
+  if (cond && cond[0] == 0.0) return;  // conditional pass not requested
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int j0 = 0; j0 < k; j0 += kDotCols) {
+  const int kk = k + (with_norm ? 1 : 0);
+  for (int j0 = 0; j0 < kk; j0 += kDotCols) {
     double acc[kDotCols];
 #pragma unroll
     for (int c = 0; c < kDotCols; ++c) acc[c] = 0.0;
     for (size_t i = (size_t)blockIdx.x * 256 + tid; i < n; i += (size_t)gridDim.x * 256) {
       const double wi = w[i];
 #pragma unroll
-      for (int c = 0; c < kDotCols; ++c)
-        if (j0 + c < k) acc[c] += V[(size_t)(j0 + c) * ld + i] * wi;
+      for (int c = 0; c < kDotCols; ++c) {
+        const int j = j0 + c;
+        if (j < k)
+          acc[c] += V[(size_t)j * ld + i] * wi;
+        else if (j == k && with_norm)
+          acc[c] += wi * wi;
+      }
     }
 #pragma unroll
     for (int c = 0; c < kDotCols; ++c) {
@@ -237,43 +269,64 @@ __global__ __launch_bounds__(256) void k_dots(const double *__restrict__ V, size
       if (lane == 0) red[c][wv] = v;
     }
     __syncthreads();
-    if (tid < kDotCols && j0 + tid < k)
-      partial[(size_t)blockIdx.x * k + j0 + tid] = red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
+    if (tid < kDotCols && j0 + tid < kk)
+      partial[(size_t)(j0 + tid) * gridDim.x + blockIdx.x] = red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
     __syncthreads();
   }
+  last_block_reduce(partial, gridDim.x, kk, counter, out);
 }
 
-hipError_t launch_dots(const double *V, size_t ld, int k, const double *w, size_t n, double *partial, int nblk,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_dots, dim3(nblk), dim3(256), 0, s, V, ld, k, w, n, partial);
+hipError_t launch_dots(const double *V, size_t ld, int k, const double *w, size_t n, int with_norm,
+                       const double *cond, double *partial, int nblk, unsigned *counter, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_dots, dim3(nblk), dim3(256), 0, s, V, ld, k, w, n, with_norm, cond, partial, counter, out);
   return hipGetLastError();
 }
 
-__global__ void k_reduce_partials(const double *__restrict__ partial, int nblk, int k, double *__restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= k) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[(size_t)b * k + j];
-  out[j] = s;
-}
-
-hipError_t launch_reduce_partials(const double *partial, int nblk, int k, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_partials, dim3((k + 63) / 64), dim3(64), 0, s, partial, nblk, k, out);
-  return hipGetLastError();
-}
-
-__global__ void k_sub_Vh(const double *__restrict__ V, size_t ld, int k, const double *__restrict__ h,
-                         double *__restrict__ w, size_t n) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+// w[i] -= sum_j V[j*ld + i] h[j]; nrm[0] = ||w||^2 afterwards and, if before is
+// given, nrm[1] = 1 when nrm[0] < before[0] / 2 (a second pass is needed), else 0
+__global__ __launch_bounds__(256) void k_sub_Vh(const double *__restrict__ V, size_t ld, int k,
+                                                const double *__restrict__ h, double *__restrict__ w, size_t n,
+                                                const double *__restrict__ cond, const double *__restrict__ before,
+                                                double *__restrict__ partial, unsigned *__restrict__ counter,
+                                                double *__restrict__ nrm) {
+  __shared__ double red[4];
+  __shared__ double hs[512];
+  const int tid = threadIdx.x;
+  if (cond && cond[0] == 0.0) return;
+  for (int j = tid; j < k && j < 512; j += 256) hs[j] = h[j];
+  __syncthreads();
+  double acc2 = 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + tid; i < n; i += (size_t)gridDim.x * 256) {
     double acc = 0.0;
-    for (int j = 0; j < k; ++j) acc += V[(size_t)j * ld + i] * h[j];
-    w[i] -= acc;
+    for (int j = 0; j < k; ++j) acc += V[(size_t)j * ld + i] * hs[j];
+    const double v = w[i] - acc;
+    w[i] = v;
+    acc2 += v * v;
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc2 += __shfl_down(acc2, o);
+  if ((tid & 63) == 0) red[tid >> 6] = acc2;
+  __syncthreads();
+  if (tid == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  last_block_reduce(partial, gridDim.x, 1, counter, nrm);
 }
 
-hipError_t launch_sub_Vh(const double *V, size_t ld, int k, const double *h, double *w, size_t n, hipStream_t s) {
-  const int nb = (int)std::min<size_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_sub_Vh, dim3(nb), dim3(256), 0, s, V, ld, k, h, w, n);
+// flag[0] = nrm[0] < before[0] / 2 ? 1 : 0
+__global__ void k_need_second_pass(const double *__restrict__ nrm, const double *__restrict__ before,
+                                   double *__restrict__ flag) {
+  flag[0] = nrm[0] < 0.5 * before[0] ? 1.0 : 0.0;
+}
+
+hipError_t launch_sub_Vh(const double *V, size_t ld, int k, const double *h, double *w, size_t n,
+                         const double *cond, double *partial, int nblk, unsigned *counter, double *nrm,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_Vh, dim3(nblk), dim3(256), 0, s, V, ld, k, h, w, n, cond, (const double *)nullptr,
+                     partial, counter, nrm);
+  return hipGetLastError();
+}
+
+hipError_t launch_need_second_pass(const double *nrm, const double *before, double *flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_need_second_pass, dim3(1), dim3(1), 0, s, nrm, before, flag);
   return hipGetLastError();
 }
 
@@ -336,6 +389,17 @@ hipError_t launch_fill(size_t n, double v, double *y, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int nb = (int)std::min<size_t>((n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, s, n, v, y);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_int(size_t n, int v, int *__restrict__ y) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) y[i] = v;
+}
+
+hipError_t launch_fill_int(size_t n, int v, int *y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int nb = (int)std::min<size_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_fill_int, dim3(nb), dim3(256), 0, s, n, v, y);
   return hipGetLastError();
 }
 

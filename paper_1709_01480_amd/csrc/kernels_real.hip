@@ -12,7 +12,7 @@ template <typename T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
 
-constexpr int kPairChunk = 256;   // sources staged in LDS per pass
+constexpr int kPairChunk = 128;   // sources staged in LDS per pass
 constexpr int kE1Int = 9;         // intervals of the E1 table
 
 // blockIdx -> work item such that consecutive items land on the same XCD
@@ -27,16 +27,12 @@ __device__ inline double dev_exp(double x) { return exp(x); }
 __device__ inline float dev_exp(float x) { return __expf(x); }
 __device__ inline double dev_log(double x) { return log(x); }
 __device__ inline float dev_log(float x) { return __logf(x); }
-__device__ inline double dev_rint(double x) { return rint(x); }
-__device__ inline float dev_rint(float x) { return rintf(x); }
 
 // E1(z) from the piecewise Chebyshev table: interval 0 holds E1 + ln z on [0, 2],
 // interval k >= 1 holds e^z E1(z) on [2*1.5^(k-1), 2*1.5^k].
+// Chebyshev series of interval k of the E1 table (Clenshaw).
 template <typename T, int DEG>
-__device__ inline T e1_eval(T z, T lz, T ez, const T *tab) {
-  int k = 0;
-  if (z > T(2)) k = min(kE1Int - 1, 1 + (int)((lz - T(0.69314718055994530942)) * T(2.46630346237643166674)));
-  const T *row = tab + k * (DEG + 3);
+__device__ inline T cheb(const T *row, T z) {
   const T x = (z - row[0]) * row[1];
   T b1 = 0, b2 = 0;
 #pragma unroll
@@ -45,39 +41,42 @@ __device__ inline T e1_eval(T z, T lz, T ez, const T *tab) {
     b2 = b1;
     b1 = b0;
   }
-  const T f = row[2] + x * b1 - b2;
-  return k == 0 ? f - lz : ez * f;
+  return row[2] + x * b1 - b2;
 }
 
-template <typename T, int DEG>
-__global__ __launch_bounds__(64) void k_pair(const int *__restrict__ cell_start, const int *__restrict__ perm,
-                                             int nb, int nbatch, T L, T rc2, T xi2, T cG,
-                                             const T *__restrict__ e1tab,
-                                             const typename Vec2<T>::type *__restrict__ xs,
-                                             const typename Vec2<T>::type *__restrict__ mus,
-                                             double *__restrict__ out) {
-  __shared__ T sx[kPairChunk], sy[kPairChunk], smx[kPairChunk], smy[kPairChunk];
-  __shared__ int sid[kPairChunk];
-  __shared__ T tx[64], ty[64], ax[64], ay[64], cx[64], cy[64];
-  __shared__ int qbuf[128];
-  __shared__ T tab[kE1Int * (DEG + 3)];
+// ---------------------------------------------------------------- neighbour lists
+// Per configuration the in-range (target, source) pairs are stored in an ELL
+// layout grouped by 64 consecutive cell-sorted targets (one wavefront): group g
+// owns slots [goff[g], goff[g] + 64 (nn_g + nf_g)); slot i of target lane l is
+// goff[g] + 64 i + l.  The first nn_g rows hold near pairs (xi^2 r^2 <= 2), the
+// next nf_g rows far pairs; empty slots are -1.  An entry packs the source's
+// sorted index (27 bits) and its neighbour-cell code (dcx+1)*3 + (dcy+1).
+constexpr int kCodeShift = 27;
+constexpr int kIndexMask = (1 << kCodeShift) - 1;
 
+// mode 0: count near / far pairs per target; mode 1: write the ELL entries
+__global__ __launch_bounds__(64) void k_pair_lists(const int *__restrict__ cell_start, int nb, int nbatch,
+                                                   double cell, double rc2, double r2near,
+                                                   const double2 *__restrict__ xs, int *__restrict__ cnt_near,
+                                                   int *__restrict__ cnt_far, const int *__restrict__ goff,
+                                                   const int *__restrict__ gnn, int *__restrict__ ell, int mode) {
+  __shared__ double sx[kPairChunk], sy[kPairChunk];
+  __shared__ int sid[kPairChunk];
+  __shared__ double tx[64], ty[64];
+  __shared__ int ncnt[64], fcnt[64];
   const int lane = threadIdx.x;
   const int w = xcd_remap(blockIdx.x, gridDim.x);
   const int c = w / nbatch, bt = w % nbatch;
   const int cs = cell_start[c], ce = cell_start[c + 1];
   const int t0 = cs + bt * 64;
-  if (t0 >= ce) return;  // uniform over the work group
+  if (t0 >= ce) return;
   const int nt = min(64, ce - t0);
-  for (int i = lane; i < kE1Int * (DEG + 3); i += 64) tab[i] = e1tab[i];
   if (lane < nt) {
-    const auto p = xs[t0 + lane];
+    const double2 p = xs[t0 + lane];
     tx[lane] = p.x;
     ty[lane] = p.y;
   }
-  ax[lane] = ay[lane] = cx[lane] = cy[lane] = T(0);
-
-  // the 3x3 neighbourhood (n_box >= 3, so the nine cells are distinct)
+  ncnt[lane] = fcnt[lane] = 0;
   const int ccx = c % nb, ccy = c / nb;
   int nstart[9], pre[10];
   pre[0] = 0;
@@ -89,57 +88,7 @@ __global__ __launch_bounds__(64) void k_pair(const int *__restrict__ cell_start,
     pre[k + 1] = pre[k] + cell_start[cc + 1] - cell_start[cc];
   }
   const int ns = pre[9];
-  const T invL = T(1) / L;
-  int qn = 0;
   __syncthreads();
-
-  // evaluate queued (target, source) pairs and reduce them per target
-  auto process = [&](int cnt) {
-    __syncthreads();
-    const int e = lane < cnt ? qbuf[lane] : -1;
-    const int t = e >= 0 ? (e >> 16) : -1;
-    T vx = 0, vy = 0;
-    if (e >= 0) {
-      const int s = e & 0xffff;
-      T dx = tx[t] - sx[s], dy = ty[t] - sy[s];
-      dx -= L * dev_rint(dx * invL);
-      dy -= L * dev_rint(dy * invL);
-      const T r2 = dx * dx + dy * dy;
-      const T z = xi2 * r2;
-      const T lz = dev_log(z);
-      const T ez = dev_exp(-z);
-      const T e1 = e1_eval<T, DEG>(z, lz, ez, tab);
-      const T a = T(0.5) * e1 - ez;
-      const T mx = smx[s], my = smy[s];
-      const T sdot = ez * (dx * mx + dy * my) / r2;
-      vx = a * mx + sdot * dx;
-      vy = a * my + sdot * dy;
-    }
-    // segmented suffix sums over lanes; the queue is ordered by target
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const T ox = __shfl_down(vx, off), oy = __shfl_down(vy, off);
-      const int ot = __shfl_down(t, off);
-      if (lane + off < 64 && ot == t) {
-        vx += ox;
-        vy += oy;
-      }
-    }
-    const int tp = __shfl_up(t, 1);
-    if (t >= 0 && (lane == 0 || tp != t)) {
-      // compensated accumulation (exact ordering: one head per target per batch)
-      T y = vx - cx[t];
-      T s2 = ax[t] + y;
-      cx[t] = (s2 - ax[t]) - y;
-      ax[t] = s2;
-      y = vy - cy[t];
-      s2 = ay[t] + y;
-      cy[t] = (s2 - ay[t]) - y;
-      ay[t] = s2;
-    }
-    __syncthreads();
-  };
-
   for (int v0 = 0; v0 < ns; v0 += kPairChunk) {
     const int len = min(kPairChunk, ns - v0);
     for (int i = lane; i < len; i += 64) {
@@ -147,73 +96,174 @@ __global__ __launch_bounds__(64) void k_pair(const int *__restrict__ cell_start,
       int k = 0;
       while (k < 8 && v >= pre[k + 1]) ++k;
       const int g = nstart[k] + (v - pre[k]);
-      const auto p = xs[g];
-      const auto m = mus[g];
-      sx[i] = p.x;
-      sy[i] = p.y;
-      smx[i] = m.x;
-      smy[i] = m.y;
-      sid[i] = g;
+      const double2 p = xs[g];
+      sx[i] = p.x + (k % 3 - 1) * cell;
+      sy[i] = p.y + (k / 3 - 1) * cell;
+      // entry code: (dcx+1)*3 + (dcy+1) with dcx = k%3-1, dcy = k/3-1
+      sid[i] = g | (((k % 3) * 3 + k / 3) << kCodeShift);
     }
     __syncthreads();
     for (int t = 0; t < nt; ++t) {
-      const T px = tx[t], py = ty[t];
+      const double px = tx[t], py = ty[t];
       const int gt = t0 + t;
+      int cn = ncnt[t], cf = fcnt[t];
+      const int grp = gt >> 6, gl = gt & 63;
+      const int base = mode ? goff[grp] : 0, nn = mode ? gnn[grp] : 0;
       for (int s0 = 0; s0 < len; s0 += 64) {
         const int s = s0 + lane;
-        bool ok = false;
+        bool ok = false, near = false;
+        int code = 0;
         if (s < len) {
-          T dx = px - sx[s], dy = py - sy[s];
-          dx -= L * dev_rint(dx * invL);
-          dy -= L * dev_rint(dy * invL);
-          ok = (dx * dx + dy * dy <= rc2) && (sid[s] != gt);
+          const double dx = px - sx[s], dy = py - sy[s];
+          const double r2 = dx * dx + dy * dy;
+          code = sid[s];
+          ok = (r2 <= rc2) && ((code & kIndexMask) != gt);
+          near = r2 <= r2near;
         }
-        const unsigned long long m = __ballot(ok);
-        if (ok) qbuf[qn + __popcll(m & ((1ull << lane) - 1ull))] = (t << 16) | s;
-        qn += __popcll(m);
-        if (qn >= 64) {
-          process(64);
-          const int rest = qn - 64;
-          const int keep = lane < rest ? qbuf[64 + lane] : 0;
-          __syncthreads();
-          if (lane < rest) qbuf[lane] = keep;
-          qn = rest;
-          __syncthreads();
+        const unsigned long long mn = __ballot(ok && near), mf = __ballot(ok && !near);
+        if (mode) {
+          const unsigned long long below = (1ull << lane) - 1ull;
+          if (ok && near) ell[base + (size_t)(cn + __popcll(mn & below)) * 64 + gl] = code;
+          if (ok && !near) ell[base + (size_t)(nn + cf + __popcll(mf & below)) * 64 + gl] = code;
         }
+        cn += __popcll(mn);
+        cf += __popcll(mf);
       }
-    }
-    if (qn > 0) {
-      process(qn);
-      qn = 0;
+      __syncthreads();
+      if (lane == 0) {
+        ncnt[t] = cn;
+        fcnt[t] = cf;
+      }
+      __syncthreads();
     }
     __syncthreads();
   }
-  if (lane < nt) {
-    const int node = perm[t0 + lane];
-    out[2 * node] = (double)(cG * ax[lane]);
-    out[2 * node + 1] = (double)(cG * ay[lane]);
+  if (mode == 0 && lane < nt) {
+    cnt_near[t0 + lane] = ncnt[lane];
+    cnt_far[t0 + lane] = fcnt[lane];
+  }
+}
+
+// per group of 64 targets: row counts (max over lanes) and the slot total
+__global__ void k_group_rows(int N, int ngroups, const int *__restrict__ cnt_near, const int *__restrict__ cnt_far,
+                             int *__restrict__ gnn, int *__restrict__ gnf, int *__restrict__ gsize) {
+  const int g = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (g >= ngroups) return;
+  const int t = g * 64 + lane;
+  int a = t < N ? cnt_near[t] : 0, b = t < N ? cnt_far[t] : 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a = max(a, __shfl_down(a, o));
+    b = max(b, __shfl_down(b, o));
+  }
+  if (lane == 0) {
+    gnn[g] = a;
+    gnf[g] = b;
+    gsize[g] = 64 * (a + b);
+  }
+}
+
+// real-space pair sum over the neighbour lists: one thread per cell-sorted target
+template <typename T, int DEG>
+__global__ __launch_bounds__(256) void k_pair_ell(int N, int ngroups, const int *__restrict__ perm,
+                                                  const int *__restrict__ goff, const int *__restrict__ gnn,
+                                                  const int *__restrict__ gnf, const int *__restrict__ ell, T cell,
+                                                  T xi2, T cG, const T *__restrict__ e1tab,
+                                                  const typename Vec2<T>::type *__restrict__ xs,
+                                                  const typename Vec2<T>::type *__restrict__ mus,
+                                                  double *__restrict__ out) {
+  __shared__ T tab[kE1Int * (DEG + 3)];
+  for (int i = threadIdx.x; i < kE1Int * (DEG + 3); i += 256) tab[i] = e1tab[i];
+  __syncthreads();
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int g = t >> 6, lane = t & 63;
+  if (g >= ngroups) return;  // whole wave
+  T tx = 0, ty = 0;
+  if (t < N) {
+    const auto p = xs[t];
+    tx = p.x;
+    ty = p.y;
+  }
+  const int base = goff[g], nn = gnn[g], nf = gnf[g];
+  T vx = 0, vy = 0, kx = 0, ky = 0;  // Kahan-compensated sums
+  auto add = [&](T a, T b) {
+    T y = a - kx;
+    T s2 = vx + y;
+    kx = (s2 - vx) - y;
+    vx = s2;
+    y = b - ky;
+    s2 = vy + y;
+    ky = (s2 - vy) - y;
+    vy = s2;
+  };
+  for (int i = 0; i < nn + nf; ++i) {
+    const int code = ell[base + (size_t)i * 64 + lane];
+    if (code < 0) continue;
+    const int s = code & kIndexMask, oc = code >> kCodeShift;
+    const auto p = xs[s];
+    const auto m = mus[s];
+    const T dx = tx - (p.x + T(oc / 3 - 1) * cell), dy = ty - (p.y + T(oc % 3 - 1) * cell);
+    const T r2 = dx * dx + dy * dy;
+    const T z = xi2 * r2;
+    const T ez = dev_exp(-z);
+    T e1;
+    if (i < nn) {  // near rows: E1 + ln z on [0, 2]
+      e1 = cheb<T, DEG>(tab, z) - dev_log(z);
+    } else {  // far rows: e^z E1 on [2*1.5^(k-1), 2*1.5^k]
+      int k = 1;
+      k += (z > T(3.0)) + (z > T(4.5)) + (z > T(6.75)) + (z > T(10.125)) + (z > T(15.1875)) +
+           (z > T(22.78125)) + (z > T(34.171875));
+      e1 = ez * cheb<T, DEG>(tab + k * (DEG + 3), z);
+    }
+    const T a = T(0.5) * e1 - ez;
+    const T sdot = ez * (dx * m.x + dy * m.y) / r2;
+    add(a * m.x + sdot * dx, a * m.y + sdot * dy);
+  }
+  if (t < N) {
+    const int node = perm[t];
+    out[2 * node] = (double)(cG * vx);
+    out[2 * node + 1] = (double)(cG * vy);
   }
 }
 
 template <typename T, int DEG>
-hipError_t pair_launch(const PairArgs &a, const T *xs, const T *mus, const T *tab, double *out, hipStream_t s) {
-  const int ncell = a.nb * a.nb;
-  const int nwg = ncell * a.nbatch;
-  if (nwg == 0) return hipSuccess;
+hipError_t pair_ell_launch(const PairLists &pl, const PairArgs &a, const T *xs, const T *mus, const T *tab,
+                           double *out, hipStream_t s) {
+  if (pl.N == 0) return hipSuccess;
   using V = typename Vec2<T>::type;
-  hipLaunchKernelGGL((k_pair<T, DEG>), dim3(nwg), dim3(64), 0, s, a.cell_start, a.perm, a.nb, a.nbatch, (T)a.L,
-                     (T)a.rc2, (T)a.xi2, (T)a.cG, tab, (const V *)xs, (const V *)mus, out);
+  hipLaunchKernelGGL((k_pair_ell<T, DEG>), dim3((pl.ngroups * 64 + 255) / 256), dim3(256), 0, s, pl.N, pl.ngroups,
+                     a.perm, pl.goff, pl.gnn, pl.gnf, pl.ell, (T)a.cell, (T)a.xi2, (T)a.cG, tab, (const V *)xs,
+                     (const V *)mus, out);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_pair_f64(const PairArgs &a, const double *xs, const double *mus, double *out, hipStream_t s) {
-  return pair_launch<double, 16>(a, xs, mus, a.e1tab, out, s);
+hipError_t launch_pair_lists(const PairArgs &a, PairLists &pl, const double *xs, int mode, hipStream_t s) {
+  const int ncell = a.nb * a.nb;
+  const int nwg = ncell * a.nbatch;
+  if (nwg == 0 || pl.N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pair_lists, dim3(nwg), dim3(64), 0, s, a.cell_start, a.nb, a.nbatch, a.cell, a.rc2,
+                     2.0 / a.xi2, (const double2 *)xs, pl.cnt_near, pl.cnt_far, pl.goff, pl.gnn, pl.ell, mode);
+  return hipGetLastError();
 }
 
-hipError_t launch_pair_f32(const PairArgs &a, const float *xs, const float *mus, double *out, hipStream_t s) {
-  return pair_launch<float, 9>(a, xs, mus, a.e1tab32, out, s);
+hipError_t launch_group_rows(PairLists &pl, int *gsize, hipStream_t s) {
+  if (pl.ngroups == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_group_rows, dim3((pl.ngroups + 3) / 4), dim3(256), 0, s, pl.N, pl.ngroups, pl.cnt_near,
+                     pl.cnt_far, pl.gnn, pl.gnf, gsize);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_f64(const PairLists &pl, const PairArgs &a, const double *xs, const double *mus, double *out,
+                           hipStream_t s) {
+  return pair_ell_launch<double, 16>(pl, a, xs, mus, a.e1tab, out, s);
+}
+
+hipError_t launch_pair_f32(const PairLists &pl, const PairArgs &a, const float *xs, const float *mus, double *out,
+                           hipStream_t s) {
+  return pair_ell_launch<float, 9>(pl, a, xs, mus, a.e1tab32, out, s);
 }
 
 // ------------------------------------------------------------------ Alpert band

@@ -21,7 +21,6 @@ __device__ inline float dev_exp(float x) { return __expf(x); }
 
 constexpr int kTmax = 32;
 constexpr int kPmax = 15;
-constexpr int kList = 768;
 
 __device__ inline int wrapi(int i, int M) {
   i %= M;
@@ -34,6 +33,18 @@ __device__ inline int xcd_remap(int b, int n) {
   return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
+// One 256-thread work group per T x T grid tile, accumulated in LDS (no global
+// atomics).  Candidate nodes (binned in the 3 x 3 neighbouring tiles) whose
+// stencil touches the tile are compacted into chunks of up to kSpreadChunk;
+// per chunk the P x- and P y-weights of every node are computed once, then the
+// (node, stencil row) items are spread over the threads and added with LDS
+// atomics.
+constexpr int kSpreadChunk = 128;
+
+__device__ inline int wrap_near(int i, int M) {  // valid for -M <= i < 2M
+  return i < 0 ? i + M : (i >= M ? i - M : i);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_spread(int M, int TT, int P, int nts, T h, T ag, T cg,
                                                 const int *__restrict__ tile_start,
@@ -42,7 +53,10 @@ __global__ __launch_bounds__(256) void k_spread(int M, int TT, int P, int nts, T
                                                 const typename Vec2<T>::type *__restrict__ mut,
                                                 T *__restrict__ grid) {
   __shared__ T acc[2][kTmax * kTmax];
-  __shared__ int lst[kList];
+  __shared__ T wgx[kSpreadChunk][kPmax], wgy[kSpreadChunk][kPmax];
+  __shared__ T nmx[kSpreadChunk], nmy[kSpreadChunk];
+  __shared__ int nbx[kSpreadChunk], nby[kSpreadChunk];
+  __shared__ int lst[kSpreadChunk + 256];
   __shared__ int lcount;
   const int tid = threadIdx.x;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -56,38 +70,49 @@ __global__ __launch_bounds__(256) void k_spread(int M, int TT, int P, int nts, T
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
     const int dx = k % 3 - 1, dy = k / 3 - 1;
-    const int tt = wrapi(tyi + dy, nts) * nts + wrapi(txi + dx, nts);
+    const int tt = wrap_near(tyi + dy, nts) * nts + wrap_near(txi + dx, nts);
     nstart[k] = tile_start[tt];
     pre[k + 1] = pre[k] + tile_start[tt + 1] - tile_start[tt];
   }
   const int ncand = pre[9];
   __syncthreads();
 
-  auto process = [&]() {
-    const int cnt = lcount;
-    const int items = cnt * P;
-    for (int it = tid; it < items; it += 256) {
-      const int j = it / P, qrow = it - j * P;
-      const int g = lst[j];
+  auto process = [&](int cnt) {
+    // per-node weights: the stencil's first column / row relative to the tile
+    if (tid < cnt) {
+      const int g = lst[tid];
       const auto p = xt[g];
-      const auto m = mut[g];
+      const auto mu = mut[g];
       const int2 an = anchor[g];
-      const int ixn = an.x, iyn = an.y;
-      const int iy = iyn - half + qrow;
-      const int ry = wrapi(iy - gy0, M);
-      if (ry >= TT) continue;
-      const T dy = p.y - iy * h;
-      const T wy = cg * dev_exp(-ag * dy * dy);
-      for (int pc = 0; pc < P; ++pc) {
-        const int ix = ixn - half + pc;
-        const int rx = wrapi(ix - gx0, M);
-        if (rx >= TT) continue;
-        const T dx = p.x - ix * h;
-        const T wgt = wy * dev_exp(-ag * dx * dx);
-        atomicAdd(&acc[0][ry * TT + rx], wgt * m.x);
-        atomicAdd(&acc[1][ry * TT + rx], wgt * m.y);
+      nbx[tid] = wrap_near((an.x - half) - gx0 + (an.x - half < 0 ? M : 0), M);
+      nby[tid] = wrap_near((an.y - half) - gy0 + (an.y - half < 0 ? M : 0), M);
+      nmx[tid] = mu.x;
+      nmy[tid] = mu.y;
+      for (int k = 0; k < P; ++k) {
+        const T d = T(half - k) * h;
+        const T dx = p.x + d, dy = p.y + d;  // offsets from the nearest grid point
+        wgx[tid][k] = dev_exp(-ag * dx * dx);
+        wgy[tid][k] = cg * dev_exp(-ag * dy * dy);
       }
     }
+    __syncthreads();
+    for (int it = tid; it < cnt * P; it += 256) {
+      const int j = it / P, q = it - j * P;
+      int ry = nby[j] + q;
+      ry = ry >= M ? ry - M : ry;
+      if (ry >= TT) continue;
+      const T wy = wgy[j][q];
+      const T ux = wy * nmx[j], uy = wy * nmy[j];
+      int rx = nbx[j];
+      for (int pc = 0; pc < P; ++pc, ++rx) {
+        const int xx = rx >= M ? rx - M : rx;
+        if (xx < TT) {
+          atomicAdd(&acc[0][ry * TT + xx], ux * wgx[j][pc]);
+          atomicAdd(&acc[1][ry * TT + xx], uy * wgx[j][pc]);
+        }
+      }
+    }
+    __syncthreads();
   };
 
   for (int v0 = 0; v0 < ncand; v0 += 256) {
@@ -97,18 +122,27 @@ __global__ __launch_bounds__(256) void k_spread(int M, int TT, int P, int nts, T
       while (k < 8 && v >= pre[k + 1]) ++k;
       const int g = nstart[k] + (v - pre[k]);
       const int2 an = anchor[g];
-      const int ixn = an.x, iyn = an.y;
-      const int ux = wrapi(ixn - half - gx0, M), uy = wrapi(iyn - half - gy0, M);
-      const bool hitx = ux < TT || ux + P - 1 >= M;
-      const bool hity = uy < TT || uy + P - 1 >= M;
-      if (hitx && hity) lst[atomicAdd(&lcount, 1)] = g;
+      const int ux = wrap_near((an.x - half) - gx0 + (an.x - half < 0 ? M : 0), M);
+      const int uy = wrap_near((an.y - half) - gy0 + (an.y - half < 0 ? M : 0), M);
+      if ((ux < TT || ux + P - 1 >= M) && (uy < TT || uy + P - 1 >= M)) lst[atomicAdd(&lcount, 1)] = g;
     }
     __syncthreads();
-    if (lcount > kList - 256 || v0 + 256 >= ncand) {
-      process();
+    // every thread takes its copy of the counter between two barriers, so the
+    // loop below (which contains barriers) is entered and left uniformly
+    int lc = lcount;
+    __syncthreads();
+    const bool last = v0 + 256 >= ncand;
+    // consume full chunks; the remainder (< kSpreadChunk) waits for more candidates
+    while (lc >= kSpreadChunk || (last && lc > 0)) {
+      const int cnt = min(lc, kSpreadChunk);
+      process(cnt);
+      const int rest = lc - cnt;
+      const int keep = tid < rest ? lst[cnt + tid] : 0;
       __syncthreads();
-      if (tid == 0) lcount = 0;
+      if (tid < rest) lst[tid] = keep;
+      if (tid == 0) lcount = rest;
       __syncthreads();
+      lc = rest;
     }
   }
   for (int i = tid; i < TT * TT; i += 256) {
@@ -150,12 +184,12 @@ __global__ __launch_bounds__(256) void k_interp(int M, int TT, int P, int nts, T
     const int by = wrapi(iyn - half - (gy0 - half), M);
     T wx[kPmax];
     for (int pc = 0; pc < P; ++pc) {
-      const T dx = p.x - (ixn - half + pc) * h;
+      const T dx = p.x + T(half - pc) * h;  // offsets from the nearest grid point
       wx[pc] = dev_exp(-ag * dx * dx);
     }
     T sx = 0, sy = 0;
     for (int qr = 0; qr < P; ++qr) {
-      const T dy = p.y - (iyn - half + qr) * h;
+      const T dy = p.y + T(half - qr) * h;
       const T wy = dev_exp(-ag * dy * dy);
       const T *r0 = &win[0][(by + qr) * w + bx];
       const T *r1 = &win[1][(by + qr) * w + bx];
