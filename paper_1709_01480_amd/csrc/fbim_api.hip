@@ -109,9 +109,11 @@ struct fbim_ctx {
   int kn = -1;
   double *d_V = nullptr;      // (restart+1) * ntot  (also Lanczos basis)
   double *d_w = nullptr, *d_t1 = nullptr, *d_t2 = nullptr, *d_b = nullptr, *d_x2 = nullptr, *d_r = nullptr;
-  unsigned *d_counter = nullptr;
   double *d_partial = nullptr, *d_h = nullptr, *d_h2 = nullptr, *d_nrm = nullptr, *d_c = nullptr;
-  int nblk = 1024;
+  // chunk tables of the Krylov vectors: saddle vectors (2N + 3n) and node vectors (2N)
+  Segs seg_sad{}, seg_nod{};
+  int2 *d_chunks = nullptr;
+  int *d_chunk_sys = nullptr, *d_sys_chunk = nullptr;
   double *d_irx = nullptr, *d_irr = nullptr, *d_ird = nullptr;
   double *d_vec_a = nullptr, *d_vec_b = nullptr, *d_U3 = nullptr, *d_U4 = nullptr, *d_U5 = nullptr;
 
@@ -323,7 +325,21 @@ fbim_status ensure_krylov(fbim_ctx *c) {
     HIPCHK(c, dalloc(c->d_irr, ntot));
     HIPCHK(c, dalloc(c->d_ird, ntot));
   }
-  HIPCHK(c, dalloc(c->d_partial, (size_t)c->nblk * cols));
+  // chunk tables (one system): saddle chunks first, then node chunks
+  std::vector<int2> ch;
+  auto cut = [&](size_t n) {
+    for (size_t x = 0; x < n; x += kChunk) ch.push_back(make_int2((int)x, (int)std::min(n, x + kChunk)));
+  };
+  cut(ntot);
+  const int nsad = (int)ch.size();
+  cut(2 * (size_t)c->N);
+  const int nnod = (int)ch.size() - nsad;
+  STCHK(upload(c, c->d_chunks, ch));
+  STCHK(upload(c, c->d_chunk_sys, std::vector<int>(ch.size(), 0)));
+  STCHK(upload(c, c->d_sys_chunk, std::vector<int>{0, nsad, 0, nnod}));
+  c->seg_sad = Segs{c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, nsad, 1};
+  c->seg_nod = Segs{c->d_chunks + nsad, c->d_chunk_sys + nsad, c->d_sys_chunk + 2, nnod, 1};
+  HIPCHK(c, dalloc(c->d_partial, (size_t)std::max(nsad, 1) * (cols + 1)));
   HIPCHK(c, dalloc(c->d_h, cols));
   HIPCHK(c, dalloc(c->d_h2, cols));
   HIPCHK(c, dalloc(c->d_nrm, 4));
@@ -537,55 +553,75 @@ fbim_status apply_precond(fbim_ctx *c, const double *z, double *y) {
   return FBIM_OK;
 }
 
-// dots out[0..k) = V[:, 0..k)^T w (device); out[k] = w^T w if with_norm
-fbim_status dots(fbim_ctx *c, const double *V, int k, const double *w, size_t n, double *out, int with_norm = 0,
-                 const double *cond = nullptr) {
+const Segs &segs_for(const fbim_ctx *c, size_t n) { return n == c->ntot ? c->seg_sad : c->seg_nod; }
+
+// one Gram-Schmidt pass (launch_orth) over vectors of length n
+fbim_status orth_pass(fbim_ctx *c, int mode, size_t n, const double *V, int k, double *w, const double *h,
+                      const double *cond, double *out) {
   Timer t(c, "blas");
-  HIPCHK(c, launch_dots(V, c->ntot, k, w, n, with_norm, cond, c->d_partial, c->nblk, c->d_counter, out, c->stream));
+  OrthArgs a;
+  a.seg = segs_for(c, n);
+  a.V = V;
+  a.ld = c->ntot;
+  a.k = k;
+  a.w = w;
+  a.h = h;
+  a.hstride = (int)c->capV + 1;
+  a.cond = cond;
+  a.partial = c->d_partial;
+  a.out = out;
+  a.ostride = (int)c->capV + 1;
+  HIPCHK(c, launch_orth(mode, a, c->stream));
   return FBIM_OK;
 }
 
-// Classical Gram-Schmidt of w against the k columns of V with a second pass
-// only when the first one cancels more than half of ||w||^2 (Daniel, Gragg,
-// Kaufman, Stewart criterion).  The decision is taken on the device, so one
-// host synchronisation per call suffices.  On return h[0..k) holds the
-// projection coefficients (host), hn = ||w|| after orthogonalisation, and
-// d_nrm[0] = hn^2.
+// Classical Gram-Schmidt of w against the k columns of V, twice (CGS2), or with
+// the second pass only when the first one cancels more than half of ||w||^2
+// (Daniel-Gragg-Kaufman-Stewart criterion, FBIM_FLAG_SELECTIVE_REORTH).  For
+// k <= kOrthFused the first subtraction and the second projection share one
+// read of V.  The decision is taken on the device, so one host
+// synchronisation per call suffices.  On return h[0..k) holds the projection
+// coefficients (host) and hn = ||w|| after orthogonalisation.
 fbim_status orthogonalise(fbim_ctx *c, const double *V, int k, double *w, size_t n, double *h, double &hn) {
   hipStream_t s = c->stream;
   double *flag = c->d_nrm + 1, *nrm2 = c->d_nrm + 2;
-  STCHK(dots(c, V, k, w, n, c->d_h, 1));
-  {
-    Timer t(c, "blas");
-    HIPCHK(c, launch_sub_Vh(V, c->ntot, k, c->d_h, w, n, nullptr, c->d_partial, c->nblk, c->d_counter, c->d_nrm, s));
-    if (c->p.flags & FBIM_FLAG_SELECTIVE_REORTH)
-      HIPCHK(c, launch_need_second_pass(c->d_nrm, c->d_h + k, flag, s));
+  const bool selective = (c->p.flags & FBIM_FLAG_SELECTIVE_REORTH) != 0;
+  const bool fused = k <= kOrthFused;
+  STCHK(orth_pass(c, 0, n, V, k, w, nullptr, nullptr, c->d_h));  // h, h[k] = ||w||^2
+  if (fused) {
+    STCHK(orth_pass(c, 1, n, V, k, w, c->d_h, nullptr, c->d_h2));  // w1 = w - V h; h2 = V^T w1, h2[k] = ||w1||^2
+    if (selective)
+      HIPCHK(c, launch_need_second_pass(1, c->d_h2 + k, 0, c->d_h + k, 0, flag, s));
     else
       HIPCHK(c, launch_fill(1, 1.0, flag, s));
+    STCHK(orth_pass(c, 2, n, V, k, w, c->d_h2, flag, nrm2));  // w2 = w1 - V h2
+  } else {
+    STCHK(orth_pass(c, 2, n, V, k, w, c->d_h, nullptr, c->d_nrm));  // w1, ||w1||^2
+    if (selective)
+      HIPCHK(c, launch_need_second_pass(1, c->d_nrm, 0, c->d_h + k, 0, flag, s));
+    else
+      HIPCHK(c, launch_fill(1, 1.0, flag, s));
+    STCHK(orth_pass(c, 0, n, V, k, w, nullptr, flag, c->d_h2));
+    STCHK(orth_pass(c, 2, n, V, k, w, c->d_h2, flag, nrm2));
   }
-  STCHK(dots(c, V, k, w, n, c->d_h2, 0, flag));
-  {
-    Timer t(c, "blas");
-    HIPCHK(c, launch_sub_Vh(V, c->ntot, k, c->d_h2, w, n, flag, c->d_partial, c->nblk, c->d_counter, nrm2, s));
-  }
-  std::vector<double> h2(k + 3);
+  std::vector<double> h2(k + 1), nr(3);
   HIPCHK(c, hipMemcpyAsync(h, c->d_h, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipMemcpyAsync(h2.data(), c->d_h2, k * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipMemcpyAsync(h2.data() + k, c->d_nrm, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(h2.data(), c->d_h2, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(nr.data(), c->d_nrm, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
-  double after = h2[k];
-  if (h2[k + 1] != 0.0) {
+  double after;
+  if (nr[1] != 0.0) {
     for (int i = 0; i < k; ++i) h[i] += h2[i];
-    after = h2[k + 2];
-    // keep d_nrm[0] = ||w||^2 for the normalisation kernels
-    HIPCHK(c, hipMemcpyAsync(c->d_nrm, c->d_nrm + 2, sizeof(double), hipMemcpyDeviceToDevice, s));
+    after = nr[2];
+  } else {
+    after = fused ? h2[k] : nr[0];
   }
   hn = std::sqrt(std::max(after, 0.0));
   return FBIM_OK;
 }
 
 fbim_status norm2(fbim_ctx *c, const double *x, size_t n, double &out) {
-  STCHK(dots(c, x, 1, x, n, c->d_nrm, 0));
+  STCHK(orth_pass(c, 0, n, x, 0, const_cast<double *>(x), nullptr, nullptr, c->d_nrm));
   double v;
   HIPCHK(c, hipMemcpyAsync(&v, c->d_nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -637,7 +673,7 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
       hcol[j + 1] = hn;
       if (hn > 0) {
         Timer t(c, "blas");
-        HIPCHK(c, launch_scale_copy(nt, w, c->d_nrm, 1, w, s));
+        HIPCHK(c, launch_scale(nt, 1.0 / hn, w, s));
       }
       for (int i = 0; i < j; ++i) {  // previous rotations
         const double t1 = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
@@ -766,7 +802,7 @@ fbim_status lanczos_sqrt(fbim_ctx *c, const double *b, double *out, int &iters, 
       break;
     }
     beta.push_back(bk);
-    HIPCHK(c, launch_scale_copy(n2, w, c->d_nrm, 1, w, s));
+    HIPCHK(c, launch_scale(n2, 1.0 / bk, w, s));
   }
   HIPCHK(c, hipMemcpyAsync(c->d_c, cur.data(), cur.size() * sizeof(double), hipMemcpyHostToDevice, s));
   {
@@ -932,8 +968,6 @@ fbim_status fbim_create(const fbim_params *params, fbim_ctx **out) {
   std::vector<float> t32(t32d.begin(), t32d.end());
   if ((st = upload(c, c->d_e1tab, t64)) != FBIM_OK || (st = upload(c, c->d_e1tab32, t32)) != FBIM_OK ||
       hipMalloc((void **)&c->d_scal_int, 8 * sizeof(int)) != hipSuccess ||
-      hipMalloc((void **)&c->d_counter, sizeof(unsigned)) != hipSuccess ||
-      hipMemset(c->d_counter, 0, sizeof(unsigned)) != hipSuccess ||
       dalloc(c->d_ccount, c->ncell) != hipSuccess || dalloc(c->d_ccursor, c->ncell) != hipSuccess ||
       dalloc(c->d_cstart, c->ncell + 1) != hipSuccess || dalloc(c->d_tcount, c->ntile) != hipSuccess ||
       dalloc(c->d_tcursor, c->ntile) != hipSuccess || dalloc(c->d_tstart, c->ntile + 1) != hipSuccess) {
@@ -973,8 +1007,8 @@ void fbim_destroy(fbim_ctx *c) {
                   c->d_tcount, c->d_tstart, c->d_tperm, c->d_tcursor, c->d_xt, c->d_anchor, c->d_scal_int, c->d_mus,
                   c->d_mut, c->d_xs32, c->d_mus32, c->d_xt32, c->d_mut32, c->d_grid, c->d_spec, c->d_grid32,
                   c->d_spec32, c->d_e1tab, c->d_e1tab32, c->d_V, c->d_w, c->d_t1, c->d_t2, c->d_b, c->d_x2,
-                  c->d_r, c->d_counter, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
-                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell};
+                  c->d_r, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
+                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk};
   for (void *p : ptrs)
     if (p) hipFree(p);
   delete c;

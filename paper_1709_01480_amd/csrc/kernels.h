@@ -113,23 +113,45 @@ hipError_t launch_body_apply(const GeomDev &g, const BodyMats &m, int which, con
                              hipStream_t s);
 
 // Krylov helpers (FP64)
-// out[j] = V[:, j]^T w (j < k) and, if with_norm, out[k] = w^T w.  partial holds
-// nblk * (k + 1) doubles; counter is a zero-initialised device word reserved for
-// this stream (the last block to finish reduces and resets it).
-// If cond is given and cond[0] == 0 the kernel does nothing (conditional second pass).
-hipError_t launch_dots(const double *V, size_t ld, int k, const double *w, size_t n, int with_norm,
-                       const double *cond, double *partial, int nblk, unsigned *counter, double *out, hipStream_t s);
-// w[i] -= sum_j V[j*ld + i] * h[j] (h on device, k <= 512); nrm[0] = ||w||^2 afterwards
-hipError_t launch_sub_Vh(const double *V, size_t ld, int k, const double *h, double *w, size_t n,
-                         const double *cond, double *partial, int nblk, unsigned *counter, double *nrm,
-                         hipStream_t s);
-// flag[0] = 1 if nrm[0] < before[0] / 2 (classical Gram-Schmidt lost more than half of ||w||^2)
-hipError_t launch_need_second_pass(const double *nrm, const double *before, double *flag, hipStream_t s);
+// A batch vector is cut into chunks of at most kChunk elements, each inside one
+// system; the chunks of a system are contiguous (sys_chunk[s] .. sys_chunk[s+1]).
+constexpr int kChunk = 2048;
+constexpr int kOrthMaxCols = 512;  // largest column count k + 1 of one orthogonalisation
+constexpr int kOrthFused = 32;     // largest k of the fused subtract-and-project pass
+struct Segs {
+  const int2 *chunk;     // [nchunk] element ranges [x, y)
+  const int *chunk_sys;  // [nchunk]
+  const int *sys_chunk;  // [S + 1]
+  int nchunk, S;
+};
+// Gram-Schmidt passes over the k columns of V (leading dimension ld) and w:
+//   mode 0: out[s][j] = V_j . w (j < k), out[s][k] = w . w
+//   mode 1: w -= V h[s]; then out[s][j] = V_j . w (j < k), out[s][k] = w . w   (k <= kOrthFused)
+//   mode 2: w -= V h[s]; out[s][0] = w . w
+// h[s][j] = h[s * hstride + j] on the device; out[s][j] = out[s * ostride + j].
+// If cond is given, systems with cond[s] == 0 are skipped (conditional second pass).
+// partial holds nchunk * (k + 1) doubles (reduced by a second launch).
+struct OrthArgs {
+  Segs seg;
+  const double *V;
+  size_t ld;
+  int k;
+  double *w;
+  const double *h;
+  int hstride;
+  const double *cond;
+  double *partial;
+  double *out;
+  int ostride;
+};
+hipError_t launch_orth(int mode, const OrthArgs &a, hipStream_t s);
+// flag[s] = 1 if nrm[s * ns] < before[s * nb] / 2 (the pass lost more than half of ||w||^2)
+hipError_t launch_need_second_pass(int S, const double *nrm, int ns, const double *before, int nb, double *flag,
+                                   hipStream_t s);
 // y[i] = sum_j V[j*ld + i] * c[j]
 hipError_t launch_Vc(const double *V, size_t ld, int k, const double *c, double *y, size_t n, hipStream_t s);
 hipError_t launch_axpby(size_t n, double a, const double *x, double b, double *y, hipStream_t s);  // y = a x + b y
-hipError_t launch_scale_copy(size_t n, const double *x, const double *alpha_dev, int invert, double *y,
-                             hipStream_t s);  // y = x * alpha (or / alpha)
+hipError_t launch_scale(size_t n, double a, double *y, hipStream_t s);  // y *= a
 hipError_t launch_vec_add(int k, const double *a, double *b, hipStream_t s);  // b += a
 hipError_t launch_cast_f32(size_t n, const double *x, float *y, hipStream_t s);
 hipError_t launch_fill(size_t n, double v, double *y, hipStream_t s);

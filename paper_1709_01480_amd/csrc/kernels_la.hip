@@ -212,121 +212,222 @@ hipError_t launch_body_apply(const GeomDev &g, const BodyMats &m, int which, con
 }
 
 // ------------------------------------------------------------------ Krylov vector kernels
-constexpr int kDotCols = 8;
+// A batch vector is cut into chunks of at most kChunk elements, each inside one
+// system; the chunks of a system are contiguous in the chunk table.  One work
+// group reduces one chunk into partial[chunk][j]; a second launch with one work
+// group per (column, system) sums the system's chunk rows in a fixed order, so
+// every result is deterministic.  (A last-block-done reduction inside the first
+// launch would need an agent-scope release fence per work group, which writes
+// back the XCD's L2 each time; the second launch is far cheaper.)
 
-// Column sums of a block-partial array partial[j * nblk + b] by the last block to
-// finish (fixed summation order, so the result is deterministic).
-__device__ void last_block_reduce(double *__restrict__ partial, int nblk, int k, unsigned *__restrict__ counter,
-                                  double *__restrict__ out) {
-  __shared__ bool last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int j = wv; j < k; j += nw) {
-    double s = 0.0;
-    for (int b = lane; b < nblk; b += 64)
-      s += __hip_atomic_load(&partial[(size_t)j * nblk + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__global__ __launch_bounds__(256) void k_orth_finish(Segs seg, int kk, const double *__restrict__ cond,
+                                                     const double *__restrict__ partial, double *__restrict__ out,
+                                                     int ostride) {
+  __shared__ double red[4];
+  const int j = blockIdx.x, sys = blockIdx.y;
+  if (cond && cond[sys] == 0.0) return;
+  const int c0 = seg.sys_chunk[sys], c1 = seg.sys_chunk[sys + 1];
+  double s = 0.0;
+  for (int c = c0 + (int)threadIdx.x; c < c1; c += 256) s += partial[(size_t)c * kk + j];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o);
-    if (lane == 0) out[j] = s;
-  }
-  if (threadIdx.x == 0) *counter = 0u;  // ready for the next launch on this stream
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[(size_t)sys * ostride + j] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// out[j] = V[:, j]^T w for j < k, and out[k] = w^T w if with_norm
-__global__ __launch_bounds__(256) void k_dots(const double *__restrict__ V, size_t ld, int k,
-                                              const double *__restrict__ w, size_t n, int with_norm,
-                                              const double *__restrict__ cond, double *__restrict__ partial,
-                                              unsigned *__restrict__ counter, double *__restrict__ out) {
-  __shared__ double red[kDotCols][4];
-  if (cond && cond[0] == 0.0) return;  // conditional pass not requested
+template <int NV>
+__device__ inline void block_sum_store(const double (&acc)[NV], int nv, double *__restrict__ dst) {
+  __shared__ double red[4][NV];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int kk = k + (with_norm ? 1 : 0);
-  for (int j0 = 0; j0 < kk; j0 += kDotCols) {
-    double acc[kDotCols];
 #pragma unroll
-    for (int c = 0; c < kDotCols; ++c) acc[c] = 0.0;
-    for (size_t i = (size_t)blockIdx.x * 256 + tid; i < n; i += (size_t)gridDim.x * 256) {
-      const double wi = w[i];
+  for (int c = 0; c < NV; ++c) {
+    double v = acc[c];
 #pragma unroll
-      for (int c = 0; c < kDotCols; ++c) {
-        const int j = j0 + c;
-        if (j < k)
-          acc[c] += V[(size_t)j * ld + i] * wi;
-        else if (j == k && with_norm)
-          acc[c] += wi * wi;
-      }
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    if (lane == 0) red[wv][c] = v;
+  }
+  __syncthreads();
+  for (int c = tid; c < nv; c += 256) dst[c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+  __syncthreads();
+}
+
+// Exact column count K (0..kOrthFused), fully unrolled:
+//   MODE 0: out[j] = V_j . w (j < K), out[K] = w . w
+//   MODE 1: w -= V h; out[j] = V_j . w (j < K), out[K] = w . w
+//   MODE 2: w -= V h; out[0] = w . w
+// E elements per thread and iteration keep E (K + 1) loads in flight.
+template <int MODE, int K>
+__global__ __launch_bounds__(256) void k_orth(OrthArgs a) {
+  constexpr int E = K <= 4 ? 4 : (K <= 12 ? 2 : 1);
+  constexpr int NV = MODE == 2 ? 1 : K + 1;
+  const int cidx = blockIdx.x;
+  const int sys = a.seg.chunk_sys[cidx];
+  if (a.cond && a.cond[sys] == 0.0) return;  // conditional pass not requested for this system
+  const int2 rg = a.seg.chunk[cidx];
+  const int tid = threadIdx.x;
+  double hr[K > 0 ? K : 1];
+  if (MODE != 0) {
+    const double *h = a.h + (size_t)sys * a.hstride;
+#pragma unroll
+    for (int j = 0; j < K; ++j) hr[j] = h[j];
+  }
+  const double *__restrict__ V = a.V;
+  double *__restrict__ w = a.w;
+  const size_t ld = a.ld;
+  double acc[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) acc[c] = 0.0;
+  for (int i0 = rg.x + tid; i0 < rg.y; i0 += 256 * E) {
+    double vv[E][K > 0 ? K : 1], wv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = min(i0 + 256 * e, rg.y - 1);  // clamped: out-of-chunk lanes reload a valid element
+      wv[e] = w[i];
+#pragma unroll
+      for (int j = 0; j < K; ++j) vv[e][j] = V[(size_t)j * ld + i];
     }
 #pragma unroll
-    for (int c = 0; c < kDotCols; ++c) {
+    for (int e = 0; e < E; ++e) {
+      const bool ok = i0 + 256 * e < rg.y;
+      double x = wv[e];
+      if (MODE != 0) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          if (j & 1)
+            s1 += vv[e][j] * hr[j];
+          else
+            s0 += vv[e][j] * hr[j];
+        }
+        x -= s0 + s1;
+        if (ok) w[i0 + 256 * e] = x;
+      }
+      if (!ok) x = 0.0;
+      if (MODE != 2) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc[j] += vv[e][j] * x;
+      }
+      acc[NV - 1] += x * x;
+    }
+  }
+  block_sum_store<NV>(acc, NV, a.partial + (size_t)cidx * NV);
+}
+
+// Runtime column count k (any k < kOrthMaxCols): MODE 0 in passes of 32 columns,
+// MODE 2 with a runtime loop.  Used beyond the unrolled range.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_orth_any(OrthArgs a) {
+  constexpr int KR = 32;
+  const int cidx = blockIdx.x;
+  const int sys = a.seg.chunk_sys[cidx];
+  if (a.cond && a.cond[sys] == 0.0) return;
+  const int2 rg = a.seg.chunk[cidx];
+  const int tid = threadIdx.x;
+  const int k = a.k;
+  const double *__restrict__ V = a.V;
+  double *__restrict__ w = a.w;
+  const size_t ld = a.ld;
+  if (MODE == 2) {
+    __shared__ double hs[kOrthMaxCols];
+    const double *h = a.h + (size_t)sys * a.hstride;
+    for (int j = tid; j < k; j += 256) hs[j] = h[j];
+    __syncthreads();
+    double acc[1] = {0.0};
+    for (int i = rg.x + tid; i < rg.y; i += 256) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int j = 0;
+      for (; j + 3 < k; j += 4) {
+        s0 += V[(size_t)j * ld + i] * hs[j];
+        s1 += V[(size_t)(j + 1) * ld + i] * hs[j + 1];
+        s2 += V[(size_t)(j + 2) * ld + i] * hs[j + 2];
+        s3 += V[(size_t)(j + 3) * ld + i] * hs[j + 3];
+      }
+      for (; j < k; ++j) s0 += V[(size_t)j * ld + i] * hs[j];
+      const double v = w[i] - ((s0 + s1) + (s2 + s3));
+      w[i] = v;
+      acc[0] += v * v;
+    }
+    block_sum_store<1>(acc, 1, a.partial + cidx);
+    return;
+  }
+  const int kk = k + 1;
+  double *part = a.partial + (size_t)cidx * kk;
+  for (int j0 = 0; j0 == 0 || j0 < k; j0 += KR) {
+    double acc[KR + 1];
+#pragma unroll
+    for (int c = 0; c <= KR; ++c) acc[c] = 0.0;
+    const int nc = min(KR, k - j0);
+    for (int i = rg.x + tid; i < rg.y; i += 256) {
+      const double wi = w[i];
+#pragma unroll
+      for (int c = 0; c < KR; ++c)
+        if (c < nc) acc[c] += V[(size_t)(j0 + c) * ld + i] * wi;
+      if (j0 == 0) acc[KR] += wi * wi;
+    }
+    __shared__ double red[4][KR + 1];
+    const int lane = tid & 63, wvi = tid >> 6;
+#pragma unroll
+    for (int c = 0; c <= KR; ++c) {
       double v = acc[c];
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
-      if (lane == 0) red[c][wv] = v;
+      if (lane == 0) red[wvi][c] = v;
     }
     __syncthreads();
-    if (tid < kDotCols && j0 + tid < kk)
-      partial[(size_t)(j0 + tid) * gridDim.x + blockIdx.x] = red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
+    if (tid < nc) part[j0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+    if (j0 == 0 && tid == 0) part[k] = (red[0][KR] + red[1][KR]) + (red[2][KR] + red[3][KR]);
     __syncthreads();
   }
-  last_block_reduce(partial, gridDim.x, kk, counter, out);
 }
 
-hipError_t launch_dots(const double *V, size_t ld, int k, const double *w, size_t n, int with_norm,
-                       const double *cond, double *partial, int nblk, unsigned *counter, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_dots, dim3(nblk), dim3(256), 0, s, V, ld, k, w, n, with_norm, cond, partial, counter, out);
+hipError_t finish(int kk, const OrthArgs &a, hipStream_t s) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_orth_finish, dim3(kk, a.seg.S), dim3(256), 0, s, a.seg, kk, a.cond, a.partial, a.out,
+                     a.ostride);
   return hipGetLastError();
 }
 
-// w[i] -= sum_j V[j*ld + i] h[j]; nrm[0] = ||w||^2 afterwards and, if before is
-// given, nrm[1] = 1 when nrm[0] < before[0] / 2 (a second pass is needed), else 0
-__global__ __launch_bounds__(256) void k_sub_Vh(const double *__restrict__ V, size_t ld, int k,
-                                                const double *__restrict__ h, double *__restrict__ w, size_t n,
-                                                const double *__restrict__ cond, const double *__restrict__ before,
-                                                double *__restrict__ partial, unsigned *__restrict__ counter,
-                                                double *__restrict__ nrm) {
-  __shared__ double red[4];
-  __shared__ double hs[512];
-  const int tid = threadIdx.x;
-  if (cond && cond[0] == 0.0) return;
-  for (int j = tid; j < k && j < 512; j += 256) hs[j] = h[j];
-  __syncthreads();
-  double acc2 = 0.0;
-  for (size_t i = (size_t)blockIdx.x * 256 + tid; i < n; i += (size_t)gridDim.x * 256) {
-    double acc = 0.0;
-    for (int j = 0; j < k; ++j) acc += V[(size_t)j * ld + i] * hs[j];
-    const double v = w[i] - acc;
-    w[i] = v;
-    acc2 += v * v;
+template <int MODE, int K>
+hipError_t launch_orth_k(const OrthArgs &a, hipStream_t s) {
+  if constexpr (K > kOrthFused) {
+    return hipErrorInvalidValue;
+  } else {
+    if (a.k == K) {
+      hipLaunchKernelGGL((k_orth<MODE, K>), dim3(a.seg.nchunk), dim3(256), 0, s, a);
+      return finish(MODE == 2 ? 1 : K + 1, a, s);
+    }
+    return launch_orth_k<MODE, K + 1>(a, s);
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) acc2 += __shfl_down(acc2, o);
-  if ((tid & 63) == 0) red[tid >> 6] = acc2;
-  __syncthreads();
-  if (tid == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-  last_block_reduce(partial, gridDim.x, 1, counter, nrm);
 }
 
-// flag[0] = nrm[0] < before[0] / 2 ? 1 : 0
-__global__ void k_need_second_pass(const double *__restrict__ nrm, const double *__restrict__ before,
-                                   double *__restrict__ flag) {
-  flag[0] = nrm[0] < 0.5 * before[0] ? 1.0 : 0.0;
+hipError_t launch_orth(int mode, const OrthArgs &a, hipStream_t s) {
+  if (a.seg.nchunk == 0) return hipSuccess;
+  if (a.k < 0 || a.k + 1 > kOrthMaxCols || (mode == 1 && a.k > kOrthFused)) return hipErrorInvalidValue;
+  if (a.k <= kOrthFused) {
+    if (mode == 0) return launch_orth_k<0, 0>(a, s);
+    if (mode == 1) return launch_orth_k<1, 0>(a, s);
+    return launch_orth_k<2, 0>(a, s);
+  }
+  if (mode == 0) {
+    hipLaunchKernelGGL((k_orth_any<0>), dim3(a.seg.nchunk), dim3(256), 0, s, a);
+    return finish(a.k + 1, a, s);
+  }
+  hipLaunchKernelGGL((k_orth_any<2>), dim3(a.seg.nchunk), dim3(256), 0, s, a);
+  return finish(1, a, s);
 }
 
-hipError_t launch_sub_Vh(const double *V, size_t ld, int k, const double *h, double *w, size_t n,
-                         const double *cond, double *partial, int nblk, unsigned *counter, double *nrm,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_sub_Vh, dim3(nblk), dim3(256), 0, s, V, ld, k, h, w, n, cond, (const double *)nullptr,
-                     partial, counter, nrm);
-  return hipGetLastError();
+// flag[s] = nrm[s * ns] < before[s * nb] / 2 ? 1 : 0
+__global__ void k_need_second_pass(int S, const double *__restrict__ nrm, int ns, const double *__restrict__ before,
+                                   int nb, double *__restrict__ flag) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < S) flag[s] = nrm[(size_t)s * ns] < 0.5 * before[(size_t)s * nb] ? 1.0 : 0.0;
 }
 
-hipError_t launch_need_second_pass(const double *nrm, const double *before, double *flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_need_second_pass, dim3(1), dim3(1), 0, s, nrm, before, flag);
+hipError_t launch_need_second_pass(int S, const double *nrm, int ns, const double *before, int nb, double *flag,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(k_need_second_pass, dim3((S + 63) / 64), dim3(64), 0, s, S, nrm, ns, before, nb, flag);
   return hipGetLastError();
 }
 
@@ -356,18 +457,15 @@ hipError_t launch_axpby(size_t n, double a, const double *x, double b, double *y
   return hipGetLastError();
 }
 
-__global__ void k_scale_copy(size_t n, const double *__restrict__ x, const double *__restrict__ alpha, int invert,
-                             double *__restrict__ y) {
-  const double a = invert ? 1.0 / sqrt(alpha[0]) : alpha[0];
+__global__ void k_scale(size_t n, double a, double *__restrict__ y) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    y[i] = a * x[i];
+    y[i] *= a;
 }
 
-// invert != 0: y = x / sqrt(alpha[0]) (normalise by a squared norm kept on the device)
-hipError_t launch_scale_copy(size_t n, const double *x, const double *alpha_dev, int invert, double *y,
-                             hipStream_t s) {
+hipError_t launch_scale(size_t n, double a, double *y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
   const int nb = (int)std::min<size_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_scale_copy, dim3(nb), dim3(256), 0, s, n, x, alpha_dev, invert, y);
+  hipLaunchKernelGGL(k_scale, dim3(nb), dim3(256), 0, s, n, a, y);
   return hipGetLastError();
 }
 

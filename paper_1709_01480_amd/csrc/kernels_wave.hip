@@ -45,14 +45,16 @@ __device__ inline int wrap_near(int i, int M) {  // valid for -M <= i < 2M
   return i < 0 ? i + M : (i >= M ? i - M : i);
 }
 
-template <typename T>
+// T: weights and positions; A: LDS accumulator (FP64 for both precisions: FP64
+// LDS atomics measured faster than FP32 ones here, and they add no rounding)
+template <typename T, typename A>
 __global__ __launch_bounds__(256) void k_spread(int M, int TT, int P, int nts, T h, T ag, T cg,
                                                 const int *__restrict__ tile_start,
                                                 const typename Vec2<T>::type *__restrict__ xt,
                                                 const int2 *__restrict__ anchor,
                                                 const typename Vec2<T>::type *__restrict__ mut,
                                                 T *__restrict__ grid) {
-  __shared__ T acc[2][kTmax * kTmax];
+  __shared__ A acc[2][kTmax * (kTmax + 1)];  // rows padded by one: a node's P rows fall in distinct banks
   __shared__ T wgx[kSpreadChunk][kPmax], wgy[kSpreadChunk][kPmax];
   __shared__ T nmx[kSpreadChunk], nmy[kSpreadChunk];
   __shared__ int nbx[kSpreadChunk], nby[kSpreadChunk];
@@ -63,7 +65,8 @@ __global__ __launch_bounds__(256) void k_spread(int M, int TT, int P, int nts, T
   const int tyi = tile / nts, txi = tile % nts;
   const int gx0 = txi * TT, gy0 = tyi * TT;
   const int half = (P - 1) / 2;
-  for (int i = tid; i < TT * TT; i += 256) acc[0][i] = acc[1][i] = T(0);
+  const int ST = TT + 1;
+  for (int i = tid; i < TT * ST; i += 256) acc[0][i] = acc[1][i] = A(0);
   if (tid == 0) lcount = 0;
   int nstart[9], pre[10];
   pre[0] = 0;
@@ -107,8 +110,8 @@ __global__ __launch_bounds__(256) void k_spread(int M, int TT, int P, int nts, T
       for (int pc = 0; pc < P; ++pc, ++rx) {
         const int xx = rx >= M ? rx - M : rx;
         if (xx < TT) {
-          atomicAdd(&acc[0][ry * TT + xx], ux * wgx[j][pc]);
-          atomicAdd(&acc[1][ry * TT + xx], uy * wgx[j][pc]);
+          atomicAdd(&acc[0][ry * ST + xx], (A)(ux * wgx[j][pc]));
+          atomicAdd(&acc[1][ry * ST + xx], (A)(uy * wgx[j][pc]));
         }
       }
     }
@@ -148,8 +151,8 @@ __global__ __launch_bounds__(256) void k_spread(int M, int TT, int P, int nts, T
   for (int i = tid; i < TT * TT; i += 256) {
     const int ry = i / TT, rx = i - ry * TT;
     const size_t gidx = (size_t)(gy0 + ry) * M + gx0 + rx;
-    grid[gidx] = acc[0][i];
-    grid[(size_t)M * M + gidx] = acc[1][i];
+    grid[gidx] = (T)acc[0][ry * ST + rx];
+    grid[(size_t)M * M + gidx] = (T)acc[1][ry * ST + rx];
   }
 }
 
@@ -247,14 +250,14 @@ __global__ void k_multiplier(int M, T twopi_L, T inv4xi2, T one_m_eta, T scale, 
 
 hipError_t launch_spread_f64(const WaveArgs &w, const double *xt, const double *mut, double *grid, hipStream_t s) {
   const int nt = w.nts * w.nts;
-  hipLaunchKernelGGL(k_spread<double>, dim3(nt), dim3(256), 0, s, w.M, w.T, w.P, w.nts, w.h, w.ag, w.cg,
+  hipLaunchKernelGGL((k_spread<double, double>), dim3(nt), dim3(256), 0, s, w.M, w.T, w.P, w.nts, w.h, w.ag, w.cg,
                      w.tile_start, (const double2 *)xt, (const int2 *)w.anchor, (const double2 *)mut, grid);
   return hipGetLastError();
 }
 
 hipError_t launch_spread_f32(const WaveArgs &w, const float *xt, const float *mut, float *grid, hipStream_t s) {
   const int nt = w.nts * w.nts;
-  hipLaunchKernelGGL(k_spread<float>, dim3(nt), dim3(256), 0, s, w.M, w.T, w.P, w.nts, (float)w.h, (float)w.ag,
+  hipLaunchKernelGGL((k_spread<float, double>), dim3(nt), dim3(256), 0, s, w.M, w.T, w.P, w.nts, (float)w.h, (float)w.ag,
                      (float)w.cg, w.tile_start, (const float2 *)xt, (const int2 *)w.anchor, (const float2 *)mut,
                      grid);
   return hipGetLastError();
