@@ -72,6 +72,11 @@ struct fbim_ctx {
   std::vector<int> h_shape, h_off;
   std::vector<double> h_q, h_theta;
   int *d_shape = nullptr, *d_off = nullptr, *d_body = nullptr;
+  // tiles of same-shape bodies for the per-body dense operators
+  BodyTiles bt{};
+  int4 *d_btile = nullptr;
+  int *d_blist = nullptr;
+  double *d_dN = nullptr;  // learned per-body correction of N_ref, [n][6] (null: plain preconditioner)
   double *d_q = nullptr, *d_theta = nullptr, *d_x = nullptr;
   bool have_bodies = false;
 
@@ -352,6 +357,27 @@ fbim_status ensure_krylov(fbim_ctx *c) {
   return FBIM_OK;
 }
 
+// tiles of up to kBodyTile same-shape bodies (kBodyTile / 4 when 2 n_p > 256)
+fbim_status build_body_tiles(fbim_ctx *c) {
+  std::vector<int> list;
+  std::vector<int4> tiles;
+  size_t lds = 0;
+  for (int sh = 0; sh < (int)c->shapes.size(); ++sh) {
+    const int n2 = 2 * c->shapes[sh].h.n_p;
+    const int per = n2 > 256 ? kBodyTile / 4 : kBodyTile;
+    const int first = (int)list.size();
+    for (int b = 0; b < c->n; ++b)
+      if (c->h_shape[b] == sh) list.push_back(b);
+    const int cnt = (int)list.size() - first;
+    for (int t = 0; t < cnt; t += per) tiles.push_back(make_int4(sh, first + t, std::min(per, cnt - t), 0));
+    if (cnt > 0) lds = std::max(lds, (size_t)per * n2 * sizeof(double));
+  }
+  STCHK(upload(c, c->d_blist, list));
+  STCHK(upload(c, c->d_btile, tiles));
+  c->bt = BodyTiles{c->d_btile, c->d_blist, (int)tiles.size(), lds};
+  return FBIM_OK;
+}
+
 // ------------------------------------------------------------------ geometry
 fbim_status build_geometry(fbim_ctx *c) {
   const int N = c->N, n = c->n;
@@ -549,7 +575,7 @@ fbim_status apply_saddle(fbim_ctx *c, const double *x, double *y) {
 
 fbim_status apply_precond(fbim_ctx *c, const double *z, double *y) {
   Timer t(c, "precond");
-  HIPCHK(c, launch_precond(c->geom(), c->mats(), z, y, c->stream));
+  HIPCHK(c, launch_precond(c->geom(), c->mats(), c->bt, c->d_dN, z, y, c->stream));
   return FBIM_OK;
 }
 
@@ -765,9 +791,9 @@ fbim_status lanczos_sqrt(fbim_ctx *c, const double *b, double *out, int &iters, 
   for (;; ++k) {
     double *vk = c->d_V + (size_t)k * c->ntot;
     double *w = c->d_V + (size_t)(k + 1) * c->ntot;
-    HIPCHK(c, launch_body_apply(c->geom(), c->mats(), 0, vk, c->d_vec_a, s));
+    HIPCHK(c, launch_body_apply(c->geom(), c->mats(), c->bt, 0, vk, c->d_vec_a, s));
     STCHK(apply_M(c, c->d_vec_a, c->d_vec_b, FBIM_PART_REAL | FBIM_PART_ALPERT));
-    HIPCHK(c, launch_body_apply(c->geom(), c->mats(), 0, c->d_vec_b, w, s));
+    HIPCHK(c, launch_body_apply(c->geom(), c->mats(), c->bt, 0, c->d_vec_b, w, s));
     double bk = 0;
     STCHK(orthogonalise(c, c->d_V, k + 1, w, n2, hbuf.data(), bk));
     alpha.push_back(hbuf[k]);
@@ -809,7 +835,7 @@ fbim_status lanczos_sqrt(fbim_ctx *c, const double *b, double *out, int &iters, 
     Timer t(c, "blas");
     HIPCHK(c, launch_Vc(c->d_V, c->ntot, (int)cur.size(), c->d_c, c->d_vec_a, n2, s));
   }
-  HIPCHK(c, launch_body_apply(c->geom(), c->mats(), 1, c->d_vec_a, out, s));
+  HIPCHK(c, launch_body_apply(c->geom(), c->mats(), c->bt, 1, c->d_vec_a, out, s));
   return st;
 }
 
@@ -1008,7 +1034,7 @@ void fbim_destroy(fbim_ctx *c) {
                   c->d_mut, c->d_xs32, c->d_mus32, c->d_xt32, c->d_mut32, c->d_grid, c->d_spec, c->d_grid32,
                   c->d_spec32, c->d_e1tab, c->d_e1tab32, c->d_V, c->d_w, c->d_t1, c->d_t2, c->d_b, c->d_x2,
                   c->d_r, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
-                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk};
+                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN};
   for (void *p : ptrs)
     if (p) hipFree(p);
   delete c;
@@ -1056,6 +1082,12 @@ fbim_status fbim_set_bodies(fbim_ctx *c, int32_t n, const int32_t *shape_id, con
   }
   const int N = off[n];
   if (N >= (1 << 30) / 4) return fail(c, FBIM_EINVAL, "too many nodes");
+  if (c->have_bodies && n == c->n && std::equal(shape_id, shape_id + n, c->h_shape.begin())) {
+    // same bodies moved: only positions and angles change
+    c->h_q.assign(q, q + 2 * n);
+    c->h_theta.assign(theta, theta + n);
+    return build_geometry(c);
+  }
   const bool realloc_n = n != c->capn, realloc_N = N != c->capN;
   c->h_shape.assign(shape_id, shape_id + n);
   c->h_off = off;
@@ -1103,6 +1135,7 @@ fbim_status fbim_set_bodies(fbim_ctx *c, int32_t n, const int32_t *shape_id, con
   HIPCHK(c, hipMemcpy(c->d_shape, c->h_shape.data(), n * sizeof(int), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->d_off, off.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->d_body, body.data(), N * sizeof(int), hipMemcpyHostToDevice));
+  STCHK(build_body_tiles(c));
   c->have_bodies = true;
   STCHK(ensure_krylov(c));
   return build_geometry(c);

@@ -106,11 +106,24 @@ struct BodyMats {
   const double *const *Gp;    // per shape
   int max_np;
 };
-// block-diagonal saddle preconditioner: z = [a (2N) | b (3n)] -> y = [mu | U]
-hipError_t launch_precond(const GeomDev &g, const BodyMats &m, const double *z, double *y, hipStream_t s);
+// Tiles of up to kBodyTile bodies of one shape (host-built): tile = (shape, first
+// index into list, count, 0); list holds body indices grouped by shape.
+// kBodyTile bodies x 2 n_p doubles must fit lds_bytes; for 2 n_p > 256 a tile
+// holds at most kBodyTile / 4 bodies and 2 n_p <= 1024.
+constexpr int kBodyTile = 16;
+struct BodyTiles {
+  const int4 *tile;
+  const int *list;
+  int ntile;
+  size_t lds_bytes;
+};
+// block-diagonal saddle preconditioner: z = [a (2N) | b (3n)] -> y = [mu | U];
+// dN (optional, [n][6] = xx, yy, tt, xy, xt, yt) corrects N_ref per body in the body frame
+hipError_t launch_precond(const GeomDev &g, const BodyMats &m, const BodyTiles &bt, const double *dN,
+                          const double *z, double *y, hipStream_t s);
 // y_b = R_b X_ref R_b^T x_b with X = G (which = 0) or G^+ (which = 1)
-hipError_t launch_body_apply(const GeomDev &g, const BodyMats &m, int which, const double *x, double *y,
-                             hipStream_t s);
+hipError_t launch_body_apply(const GeomDev &g, const BodyMats &m, const BodyTiles &bt, int which, const double *x,
+                             double *y, hipStream_t s);
 
 // Krylov helpers (FP64)
 // A batch vector is cut into chunks of at most kChunk elements, each inside one

@@ -71,143 +71,185 @@ hipError_t launch_KT(const GeomDev &g, const double *mu, double sgn, double *out
 }
 
 // ------------------------------------------------------------------ per-body dense operators
-// Block-diagonal preconditioner (eqs. 3.31-3.37) with all bodies of a shape
-// sharing M_ref^+: in the body frame a~ = R^T a,
-//   c = M_ref^+ a~,  U_ref = -N_ref (R'^T b + K_ref^T c),  mu_ref = c + (M_ref^+ K_ref) U_ref,
-// then mu = R mu_ref, U = R' U_ref.
-__global__ __launch_bounds__(1024) void k_precond(const int *__restrict__ off, const int *__restrict__ shape,
-                                                  const double *__restrict__ theta, const double *const *ref,
-                                                  const int *__restrict__ np, const double *const *Mp,
-                                                  const double *const *Pref, const double *const *Nt, int N,
-                                                  const double *__restrict__ z, double *__restrict__ y) {
-  __shared__ double at[1024];
-  __shared__ double red[3][32];
-  __shared__ double Ur[3];
-  const int b = blockIdx.x;
+// All bodies of a shape share their reference matrices, so in the body frame the
+// per-body products are one matrix times a batch of vectors.  A work group takes
+// a tile of up to kBodyTile bodies of one shape: it rotates their inputs into
+// the body frame in LDS, multiplies them by the shared (2 n_p) x (2 n_p) matrix
+// (read once per tile instead of once per body), then finishes each body.
+//
+// MODE 0: y_b = R_b X_ref R_b^T x_b, X = G_ref or G_ref^+ (eqs. 3.40-3.42).
+// MODE 1: block-diagonal preconditioner (eqs. 3.31-3.37): in the body frame
+//   c = M_ref^+ a~,  U_ref = -N_b (R'^T b + K_ref^T c),  mu_ref = c + (M_ref^+ K_ref) U_ref,
+//   mu = R mu_ref, U = R' U_ref, with N_b = N_ref (+ a learned symmetric
+//   correction dN_b in the body frame, when given).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_body_tile(BodyTiles bt, const int *__restrict__ off,
+                                                   const double *__restrict__ theta, const double *const *ref,
+                                                   const int *__restrict__ np, const double *const *X,
+                                                   const double *const *Pref, const double *const *Nt,
+                                                   const double *__restrict__ dN, int N,
+                                                   const double *__restrict__ z, double *__restrict__ y) {
+  extern __shared__ double sm[];  // [nb][n2] body-frame inputs, then outputs
+  __shared__ double Ur[kBodyTile][3];
+  __shared__ double cs_[kBodyTile], sn_[kBodyTile];
+  __shared__ int base_[kBodyTile], body_[kBodyTile];
+  const int4 tl = bt.tile[blockIdx.x];
+  const int sh = tl.x, nb = tl.z;
+  const int npt = np[sh], n2 = 2 * npt;
   const int tid = threadIdx.x;
-  const int sh = shape[b];
-  const int n2 = 2 * np[sh];
-  const int base = off[b];
-  const double *r = ref[sh];
-  double sn, cs;
-  sincos(theta[b], &sn, &cs);
-  if (tid < n2 / 2) {
-    const double ax = z[2 * (base + tid)], ay = z[2 * (base + tid) + 1];
-    at[2 * tid] = cs * ax + sn * ay;
-    at[2 * tid + 1] = -sn * ax + cs * ay;
+  if (tid < nb) {
+    const int b = bt.list[tl.y + tid];
+    double sn, cs;
+    sincos(theta[b], &sn, &cs);
+    cs_[tid] = cs;
+    sn_[tid] = sn;
+    base_[tid] = off[b];
+    body_[tid] = b;
   }
   __syncthreads();
-  double c = 0.0;
-  if (tid < n2) {
-    const double *A = Mp[sh];
-    for (int k = 0; k < n2; ++k) c += A[(size_t)k * n2 + tid] * at[k];
+  for (int idx = tid; idx < nb * npt; idx += 256) {
+    const int j = idx / npt, t = idx - j * npt;
+    const size_t gi = 2 * (size_t)(base_[j] + t);
+    const double ax = z[gi], ay = z[gi + 1];
+    sm[j * n2 + 2 * t] = cs_[j] * ax + sn_[j] * ay;
+    sm[j * n2 + 2 * t + 1] = -sn_[j] * ax + cs_[j] * ay;
   }
-  // f = K_ref^T c
-  double f0 = 0, f1 = 0, f2 = 0;
-  if (tid < n2) {
-    const int t = tid >> 1;
-    if (tid & 1) {
-      f1 = c;
-      f2 = r[2 * t] * c;
-    } else {
-      f0 = c;
-      f2 = -r[2 * t + 1] * c;
-    }
-  }
+  __syncthreads();
+  // c[j][r] = sum_k X[k * n2 + r] a~[j][k]
+  const double *__restrict__ A = X[sh];
+  const int RP = min(n2, 256), G = 256 / RP;
+  const int g = tid / RP, rr = tid - g * RP;
+  double acc[kBodyTile];
+  double cres[4][kBodyTile / 4 > 0 ? kBodyTile / 4 : 1];  // outputs of later row passes (n2 > 256)
+  int npass = (n2 + RP - 1) / RP;
+  for (int pss = 0; pss < npass; ++pss) {
+    const int r = pss * RP + rr;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    f0 += __shfl_down(f0, o);
-    f1 += __shfl_down(f1, o);
-    f2 += __shfl_down(f2, o);
-  }
-  const int wv = tid >> 6, lane = tid & 63;
-  if (lane == 0) {
-    red[0][wv] = f0;
-    red[1][wv] = f1;
-    red[2][wv] = f2;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double s0 = 0, s1 = 0, s2 = 0;
-    const int nw = (blockDim.x + 63) / 64;
-    for (int k = 0; k < nw; ++k) {
-      s0 += red[0][k];
-      s1 += red[1][k];
-      s2 += red[2][k];
+    for (int q = 0; q < kBodyTile; ++q) acc[q] = 0.0;
+    if (g < G && r < n2) {
+      // n2 is a multiple of 4: four matrix loads in flight, body-frame inputs
+      // read from LDS two at a time
+      for (int k = 0; k < n2; k += 4) {
+        const double x0 = A[(size_t)k * n2 + r], x1 = A[(size_t)(k + 1) * n2 + r];
+        const double x2 = A[(size_t)(k + 2) * n2 + r], x3 = A[(size_t)(k + 3) * n2 + r];
+#pragma unroll
+        for (int q = 0; q < kBodyTile; ++q) {
+          const int j = g + G * q;
+          if (j < nb) {
+            const double2 a01 = *reinterpret_cast<const double2 *>(&sm[j * n2 + k]);
+            const double2 a23 = *reinterpret_cast<const double2 *>(&sm[j * n2 + k + 2]);
+            acc[q] += x0 * a01.x + x1 * a01.y + x2 * a23.x + x3 * a23.y;
+          }
+        }
+      }
     }
-    const double *bb = z + 2 * (size_t)N + 3 * (size_t)b;
-    const double g0 = cs * bb[0] + sn * bb[1] + s0;  // R'^T b + K^T c
-    const double g1 = -sn * bb[0] + cs * bb[1] + s1;
-    const double g2 = bb[2] + s2;
-    const double *Nm = Nt[sh];
-    Ur[0] = -(Nm[0] * g0 + Nm[1] * g1 + Nm[2] * g2);
-    Ur[1] = -(Nm[3] * g0 + Nm[4] * g1 + Nm[5] * g2);
-    Ur[2] = -(Nm[6] * g0 + Nm[7] * g1 + Nm[8] * g2);
-    double *yU = y + 2 * (size_t)N + 3 * (size_t)b;
-    yU[0] = cs * Ur[0] - sn * Ur[1];
-    yU[1] = sn * Ur[0] + cs * Ur[1];
-    yU[2] = Ur[2];
+    if (npass == 1) break;
+    // n2 > 256: G == 1 and nb <= kBodyTile / 4; park this pass's outputs
+#pragma unroll
+    for (int q = 0; q < (kBodyTile / 4 > 0 ? kBodyTile / 4 : 1); ++q) cres[pss][q] = acc[q];
+  }
+  __syncthreads();  // every thread is done reading the inputs
+  if (npass == 1) {
+    if (g < G && rr < n2) {
+#pragma unroll
+      for (int q = 0; q < kBodyTile; ++q) {
+        const int j = g + G * q;
+        if (j < nb) sm[j * n2 + rr] = acc[q];
+      }
+    }
+  } else {
+    for (int pss = 0; pss < npass; ++pss) {
+      const int r = pss * RP + rr;
+      if (r < n2) {
+#pragma unroll
+        for (int q = 0; q < (kBodyTile / 4 > 0 ? kBodyTile / 4 : 1); ++q)
+          if (q < nb) sm[q * n2 + r] = cres[pss][q];
+      }
+    }
   }
   __syncthreads();
-  if (tid < n2) {
+  if (MODE == 1) {
+    // per body: f = K_ref^T c (one wave per body), U_ref = -N_b (R'^T b + f)
+    const int lane = tid & 63, wv = tid >> 6;
+    const double *rf = ref[sh];
+    for (int j = wv; j < nb; j += 4) {
+      double f0 = 0, f1 = 0, f2 = 0;
+      for (int t = lane; t < npt; t += 64) {
+        const double c0 = sm[j * n2 + 2 * t], c1 = sm[j * n2 + 2 * t + 1];
+        f0 += c0;
+        f1 += c1;
+        f2 += rf[2 * t] * c1 - rf[2 * t + 1] * c0;
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        f0 += __shfl_down(f0, o);
+        f1 += __shfl_down(f1, o);
+        f2 += __shfl_down(f2, o);
+      }
+      if (lane == 0) {
+        const int b = body_[j];
+        const double cs = cs_[j], sn = sn_[j];
+        const double *bb = z + 2 * (size_t)N + 3 * (size_t)b;
+        const double g0 = cs * bb[0] + sn * bb[1] + f0;
+        const double g1 = -sn * bb[0] + cs * bb[1] + f1;
+        const double g2 = bb[2] + f2;
+        const double *Nm = Nt[sh];
+        double n00 = Nm[0], n01 = Nm[1], n02 = Nm[2], n11 = Nm[4], n12 = Nm[5], n22 = Nm[8];
+        double n10 = Nm[3], n20 = Nm[6], n21 = Nm[7];
+        if (dN) {
+          const double *d = dN + 6 * (size_t)b;  // (xx, yy, tt, xy, xt, yt)
+          n00 += d[0];
+          n11 += d[1];
+          n22 += d[2];
+          n01 += d[3];
+          n10 += d[3];
+          n02 += d[4];
+          n20 += d[4];
+          n12 += d[5];
+          n21 += d[5];
+        }
+        const double u0 = -(n00 * g0 + n01 * g1 + n02 * g2);
+        const double u1 = -(n10 * g0 + n11 * g1 + n12 * g2);
+        const double u2 = -(n20 * g0 + n21 * g1 + n22 * g2);
+        Ur[j][0] = u0;
+        Ur[j][1] = u1;
+        Ur[j][2] = u2;
+        double *yU = y + 2 * (size_t)N + 3 * (size_t)b;
+        yU[0] = cs * u0 - sn * u1;
+        yU[1] = sn * u0 + cs * u1;
+        yU[2] = u2;
+      }
+    }
+    __syncthreads();
     const double *Pm = Pref[sh];
-    at[tid] = c + Pm[tid] * Ur[0] + Pm[n2 + tid] * Ur[1] + Pm[2 * n2 + tid] * Ur[2];
+    for (int idx = tid; idx < nb * n2; idx += 256) {
+      const int j = idx / n2, r = idx - j * n2;
+      sm[idx] += Pm[r] * Ur[j][0] + Pm[n2 + r] * Ur[j][1] + Pm[2 * n2 + r] * Ur[j][2];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (tid < n2 / 2) {
-    const double mx = at[2 * tid], my = at[2 * tid + 1];
-    y[2 * (base + tid)] = cs * mx - sn * my;
-    y[2 * (base + tid) + 1] = sn * mx + cs * my;
+  for (int idx = tid; idx < nb * npt; idx += 256) {
+    const int j = idx / npt, t = idx - j * npt;
+    const double mx = sm[j * n2 + 2 * t], my = sm[j * n2 + 2 * t + 1];
+    const size_t gi = 2 * (size_t)(base_[j] + t);
+    y[gi] = cs_[j] * mx - sn_[j] * my;
+    y[gi + 1] = sn_[j] * mx + cs_[j] * my;
   }
 }
 
-hipError_t launch_precond(const GeomDev &g, const BodyMats &m, const double *z, double *y, hipStream_t s) {
+hipError_t launch_precond(const GeomDev &g, const BodyMats &m, const BodyTiles &bt, const double *dN,
+                          const double *z, double *y, hipStream_t s) {
   if (g.n == 0) return hipSuccess;
-  const int threads = ((2 * m.max_np + 63) / 64) * 64;
-  hipLaunchKernelGGL(k_precond, dim3(g.n), dim3(threads), 0, s, g.off, g.shape, g.theta, g.ref, g.np, m.Mp,
-                     m.Pref, m.Nt, g.N, z, y);
+  hipLaunchKernelGGL(k_body_tile<1>, dim3(bt.ntile), dim3(256), bt.lds_bytes, s, bt, g.off, g.theta, g.ref, g.np,
+                     m.Mp, m.Pref, m.Nt, dN, g.N, z, y);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(1024) void k_body_apply(const int *__restrict__ off, const int *__restrict__ shape,
-                                                     const double *__restrict__ theta, const int *__restrict__ np,
-                                                     const double *const *X, const double *__restrict__ x,
-                                                     double *__restrict__ y) {
-  __shared__ double at[1024];
-  const int b = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int sh = shape[b];
-  const int n2 = 2 * np[sh];
-  const int base = off[b];
-  double sn, cs;
-  sincos(theta[b], &sn, &cs);
-  if (tid < n2 / 2) {
-    const double ax = x[2 * (base + tid)], ay = x[2 * (base + tid) + 1];
-    at[2 * tid] = cs * ax + sn * ay;
-    at[2 * tid + 1] = -sn * ax + cs * ay;
-  }
-  __syncthreads();
-  double c = 0.0;
-  if (tid < n2) {
-    const double *A = X[sh];
-    for (int k = 0; k < n2; ++k) c += A[(size_t)k * n2 + tid] * at[k];
-  }
-  __syncthreads();
-  if (tid < n2) at[tid] = c;
-  __syncthreads();
-  if (tid < n2 / 2) {
-    const double mx = at[2 * tid], my = at[2 * tid + 1];
-    y[2 * (base + tid)] = cs * mx - sn * my;
-    y[2 * (base + tid) + 1] = sn * mx + cs * my;
-  }
-}
-
-hipError_t launch_body_apply(const GeomDev &g, const BodyMats &m, int which, const double *x, double *y,
-                             hipStream_t s) {
+hipError_t launch_body_apply(const GeomDev &g, const BodyMats &m, const BodyTiles &bt, int which, const double *x,
+                             double *y, hipStream_t s) {
   if (g.n == 0) return hipSuccess;
-  const int threads = ((2 * m.max_np + 63) / 64) * 64;
-  hipLaunchKernelGGL(k_body_apply, dim3(g.n), dim3(threads), 0, s, g.off, g.shape, g.theta, g.np,
-                     which ? m.Gp : m.G, x, y);
+  hipLaunchKernelGGL(k_body_tile<0>, dim3(bt.ntile), dim3(256), bt.lds_bytes, s, bt, g.off, g.theta, g.ref, g.np,
+                     which ? m.Gp : m.G, m.Pref, m.Nt, (const double *)nullptr, g.N, x, y);
   return hipGetLastError();
 }
 
