@@ -201,10 +201,82 @@ fbim_status fbim_derive_params(const fbim_params *in, fbim_derived *out);
  * singularity.  HOST chi, w must hold 8 doubles. */
 fbim_status fbim_alpert_rule(int32_t order, int32_t *j, int32_t *a, double *chi, double *w);
 
+/* ---- Learned correction of the block-diagonal preconditioner ----------------
+ * A per-body MLP 32 -> 128 -> 128 -> 6 with tanh hidden layers maps features
+ * of a body's neighbourhood (in its body frame) to a symmetric correction dN
+ * of the isolated-body mobility N_ref that the preconditioner of Section 3.4
+ * (eqs. 3.31-3.37) applies.  GMRES's true residual still decides convergence:
+ * the correction changes iteration counts, not solutions.  Matrix products
+ * run on the MFMA units in BF16 with FP32 accumulation; weights are FP32.
+ *
+ * Weights: FBIM_MLP_NPARAM floats, flat, in the order W1 (32 x 128, row-major
+ * input x output), b1 (128), W2 (128 x 128), b2 (128), W3 (128 x 6), b3 (6).
+ * Features (FBIM_MLP_IN per body).  Neighbours of body b are the other bodies
+ * whose tracking points lie closer than R = 3 r_max (minimum image; r_max =
+ * largest distance of a reference node from its tracking point over all
+ * shapes), nearest first, ties by index, at most 6.  For slot k < 6 (zeros
+ * when empty): [5k, 5k+1] = neighbour offset rotated into b's frame / R;
+ * 5k+2 = r_max / distance; [5k+3, 5k+4] = cos, sin of sym (theta_c - theta_b).
+ * 30 = neighbour count / 6; 31 = clamp((d_min - 2 r_max) / r_max, -2, 2) with
+ * d_min the nearest distance (R if none).
+ * Output y (6 per body) gives, in the body frame,
+ *   dN = [[y0 sx, y3 sxy, y4 sxt], [y3 sxy, y1 sy, y5 syt], [y4 sxt, y5 syt, y2 st]],
+ * s. the diagonal of N_ref and sxy = sqrt(sx sy), sxt = sqrt(sx st), syt = sqrt(sy st).
+ * Training target: for forces with independent standard-normal components the
+ * solve gives U = N F, and E[U_b F_b^T] = N_bb, so the loss
+ *   mean over samples s and bodies b of sum_i (r_i / N_ref,ii)^2,
+ *   r = (N_ref + dN_b) R_b^T F_b - R_b^T U_b   (R_b rotates the translational part)
+ * is minimised by dN_b = N_bb - N_ref in expectation. */
+#define FBIM_MLP_IN 32
+#define FBIM_MLP_HID 128
+#define FBIM_MLP_OUT 6
+#define FBIM_MLP_NPARAM (32 * 128 + 128 + 128 * 128 + 128 + 128 * 6 + 6)
+
+typedef struct {
+  int32_t n_solves; /* random-force mobility solves on the current configuration (>= 1) */
+  int32_t epochs;   /* Adam steps over those samples (>= 0) */
+  float lr;         /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8) */
+  uint64_t seed;    /* forces: independent standard normals from this seed (host generator) */
+} fbim_train_cfg;
+
+typedef struct {
+  float loss_first;     /* loss before the first Adam step */
+  float loss_last;      /* loss after the last Adam step */
+  int32_t gmres_iters;  /* GMRES iterations of the sample solves */
+  int32_t samples;      /* body samples used (n_solves x bodies) */
+} fbim_train_info;
+
+/* Initialise the weights (Glorot-uniform from a host generator seeded with
+ * `seed`; biases zero; last layer scaled by 1e-2 so that dN starts near 0)
+ * and set the angular symmetry order used by the features (5 for a five-arm
+ * starfish; 1 for a shape without rotational symmetry). */
+fbim_status fbim_mlp_init(fbim_ctx *ctx, uint64_t seed, int32_t sym_order);
+/* HOST w[n], n == FBIM_MLP_NPARAM. */
+fbim_status fbim_mlp_set_weights(fbim_ctx *ctx, const float *w, size_t n);
+fbim_status fbim_mlp_get_weights(fbim_ctx *ctx, float *w, size_t n);
+/* DEVICE X[n_bodies][FBIM_MLP_IN] <- features of the current bodies. */
+fbim_status fbim_mlp_features(fbim_ctx *ctx, float *X);
+/* DEVICE Y[n][6] = MLP(DEVICE X[n][32]) with the current weights. */
+fbim_status fbim_mlp_forward(fbim_ctx *ctx, const float *X, int32_t n, float *Y);
+/* DEVICE grad[FBIM_MLP_NPARAM] = d (sum_ij dY_ij Y_ij) / d w at DEVICE X[n][32],
+ * DEVICE dY[n][6] (grad is overwritten, same layout as the weights). */
+fbim_status fbim_mlp_backward(fbim_ctx *ctx, const float *X, const float *dY, int32_t n, float *grad);
+/* Loss above for the current bodies from DEVICE Y[n][6] and ns samples of
+ * DEVICE F[ns][3n], U[ns][3n]; HOST *loss, DEVICE dY[n][6] = d loss / d Y. */
+fbim_status fbim_mlp_loss(fbim_ctx *ctx, const float *Y, int32_t ns, const double *F, const double *U,
+                          float *loss, float *dY);
+/* Generate cfg->n_solves random-force solves on the current configuration
+ * (with the preconditioner currently in use) and take cfg->epochs Adam steps
+ * on the loss over them. */
+fbim_status fbim_mlp_train(fbim_ctx *ctx, const fbim_train_cfg *cfg, fbim_train_info *info);
+/* on != 0: the preconditioner applies N_ref + dN_b (recomputed whenever the
+ * bodies change); 0: the plain block-diagonal preconditioner. */
+fbim_status fbim_mlp_use(fbim_ctx *ctx, int32_t on);
+
 /* Kernel timing (for measurement): when enabled, device events bracket each
  * launch of the named kernel class; fbim_kernel_time returns the summed
  * milliseconds and launch count since the last reset.  Classes: "pair",
- * "alpert", "spread", "interp", "fft", "multiplier", "precond", "blas". */
+ * "alpert", "spread", "interp", "fft", "multiplier", "precond", "blas", "mlp". */
 fbim_status fbim_set_timing(fbim_ctx *ctx, int32_t enable);
 fbim_status fbim_kernel_time(fbim_ctx *ctx, const char *name, double *ms, int64_t *count);
 

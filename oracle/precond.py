@@ -1,0 +1,72 @@
+"""FP64 reference of the block-diagonal preconditioner of the saddle system
+(Section 3.4, eqs. 3.31-3.37) and of its corrected form, with a plain
+right-preconditioned GMRES (TEST INFRASTRUCTURE).
+
+Block inverse per body b for the system [M -K; -K^T 0][mu; U] = [a; c]:
+  g = c_b + K_b^T M_bb^+ a_b,  U_b = -N_b g,  mu_b = M_bb^+ (a_b + K_b U_b),
+  N_b = (K_b^T M_bb^+ K_b)^-1  (= N_ref of the body).
+Corrected form: the exact inverse of the block with M_bb replaced by
+M_bb + K_b C K_b^T for a symmetric 3 x 3 C; by the Woodbury identity the
+body's mobility becomes N_b + C, mu_b is unchanged and U_b gains -C c_b.
+"""
+import numpy as np
+
+
+def pinv_sym(A, tau=1e-8):
+    lam, V = np.linalg.eigh(0.5 * (A + A.T))
+    keep = np.abs(lam) > tau * np.max(np.abs(lam))
+    return (V[:, keep] / lam[keep]) @ V[:, keep].T
+
+
+def block_preconditioner(M, K, offsets, C=None, tau=1e-8):
+    """Returns z -> P^-1 z for the saddle vector z = [a (2N); c (3n)].
+    offsets: node offsets per body (n + 1); C: optional [n, 3, 3] corrections."""
+    n = len(offsets) - 1
+    N2 = 2 * offsets[-1]
+    blocks = []
+    for b in range(n):
+        sl = slice(2 * offsets[b], 2 * offsets[b + 1])
+        Mp = pinv_sym(M[sl, sl], tau)
+        Kb = K[sl, 3 * b:3 * b + 3]
+        blocks.append((sl, Mp, Kb, np.linalg.inv(Kb.T @ Mp @ Kb)))
+
+    def apply(z):
+        a, c = z[:N2], z[N2:]
+        mu, U = np.zeros(N2), np.zeros(3 * n)
+        for b, (sl, Mp, Kb, Nb) in enumerate(blocks):
+            cb = c[3 * b:3 * b + 3]
+            u = -Nb @ (cb + Kb.T @ (Mp @ a[sl]))
+            mu[sl] = Mp @ (a[sl] + Kb @ u)
+            if C is not None:
+                u = u - C[b] @ cb
+            U[3 * b:3 * b + 3] = u
+        return np.concatenate([mu, U])
+
+    return apply, [bl[3] for bl in blocks]
+
+
+def gmres(A, rhs, Pinv, tol=1e-8, maxit=500):
+    """Right-preconditioned GMRES (x0 = 0, no restart, CGS2 Arnoldi); returns
+    (x, iterations) with ||rhs - A x|| <= tol ||rhs||."""
+    n = len(rhs)
+    nb = np.linalg.norm(rhs)
+    V = np.zeros((n, maxit + 1))
+    Z = np.zeros((n, maxit))
+    H = np.zeros((maxit + 1, maxit))
+    V[:, 0] = rhs / nb
+    for j in range(maxit):
+        Z[:, j] = Pinv(V[:, j])
+        w = A @ Z[:, j]
+        for _ in range(2):
+            h = V[:, :j + 1].T @ w
+            w -= V[:, :j + 1] @ h
+            H[:j + 1, j] += h
+        H[j + 1, j] = np.linalg.norm(w)
+        if H[j + 1, j] > 0:
+            V[:, j + 1] = w / H[j + 1, j]
+        e1 = np.zeros(j + 2)
+        e1[0] = nb
+        y = np.linalg.lstsq(H[:j + 2, :j + 1], e1, rcond=None)[0]
+        if np.linalg.norm(e1 - H[:j + 2, :j + 1] @ y) <= tol * nb or H[j + 1, j] == 0:
+            return Z[:, :j + 1] @ y, j + 1
+    return Z @ y, maxit

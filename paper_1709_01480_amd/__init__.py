@@ -12,12 +12,14 @@ import os
 
 __all__ = ["Params", "Derived", "Info", "Context", "lib", "derive_params", "alpert_rule", "starfish",
            "PART_REAL", "PART_ALPERT", "PART_WAVE", "PART_ALL", "PREC_FP64", "PREC_MIXED", "FbimError",
-           "LIB_PATH"]
+           "LIB_PATH", "MLP_IN", "MLP_OUT", "MLP_NPARAM"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfbim.so")
 
 PART_REAL, PART_ALPERT, PART_WAVE, PART_ALL = 1, 2, 4, 7
 PREC_FP64, PREC_MIXED = 0, 1
+MLP_IN, MLP_HID, MLP_OUT = 32, 128, 6
+MLP_NPARAM = 32 * 128 + 128 + 128 * 128 + 128 + 128 * 6 + 6
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EOVERLAP", 4: "ENOCONV", 5: "EDEVICE", 6: "ENOTSUP",
           7: "WACCURACY"}
 
@@ -59,6 +61,19 @@ class Info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("n_solves", ctypes.c_int32), ("epochs", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+class TrainInfo(ctypes.Structure):
+    _fields_ = [("loss_first", ctypes.c_float), ("loss_last", ctypes.c_float), ("gmres_iters", ctypes.c_int32),
+                ("samples", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 def _load():
     # torch first: the process must use the HIP runtime torch was built with;
     # libfbim.so then binds to that already-loaded runtime by soname
@@ -88,6 +103,15 @@ def _load():
         "fbim_step_em_rfd": (i32, [p, d, d, p, p, p, p, p, i32, P(Info)]),
         "fbim_derive_params": (i32, [P(Params), P(Derived)]),
         "fbim_alpert_rule": (i32, [i32, P(i32), P(i32), p, p]),
+        "fbim_mlp_init": (i32, [p, ctypes.c_uint64, i32]),
+        "fbim_mlp_set_weights": (i32, [p, p, ctypes.c_size_t]),
+        "fbim_mlp_get_weights": (i32, [p, p, ctypes.c_size_t]),
+        "fbim_mlp_features": (i32, [p, p]),
+        "fbim_mlp_forward": (i32, [p, p, i32, p]),
+        "fbim_mlp_backward": (i32, [p, p, p, i32, p]),
+        "fbim_mlp_loss": (i32, [p, p, i32, p, p, P(ctypes.c_float), p]),
+        "fbim_mlp_train": (i32, [p, P(TrainCfg), P(TrainInfo)]),
+        "fbim_mlp_use": (i32, [p, i32]),
         "fbim_set_timing": (i32, [p, i32]),
         "fbim_kernel_time": (i32, [p, ctypes.c_char_p, P(d), P(ctypes.c_int64)]),
     }
@@ -145,6 +169,16 @@ def _dptr(t, n=None):
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
         raise TypeError("expected a contiguous float64 GPU tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError("expected %d elements, got %d" % (n, t.numel()))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _fptr(t, n=None):
+    """Device pointer of a float32 contiguous GPU tensor (checked)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float32 GPU tensor")
     if n is not None and t.numel() != n:
         raise ValueError("expected %d elements, got %d" % (n, t.numel()))
     return ctypes.c_void_p(t.data_ptr())
@@ -244,6 +278,49 @@ class Context:
                                          _dptr(W_grid, 2 * M * M), _dptr(W_tilde, 3 * self.n),
                                          _dptr(dQ, 3 * self.n), 1 if apply else 0, ctypes.byref(info)))
         return info.as_dict()
+
+    # -- learned preconditioner correction
+    def mlp_init(self, seed=0, sym_order=1):
+        self._check(lib.fbim_mlp_init(self._ctx, seed, sym_order))
+
+    def mlp_set_weights(self, w):
+        import numpy as np
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._check(lib.fbim_mlp_set_weights(self._ctx, w.ctypes.data_as(ctypes.c_void_p), w.size))
+
+    def mlp_get_weights(self):
+        import numpy as np
+        w = np.zeros(MLP_NPARAM, dtype=np.float32)
+        self._check(lib.fbim_mlp_get_weights(self._ctx, w.ctypes.data_as(ctypes.c_void_p), w.size))
+        return w
+
+    def mlp_features(self, X):
+        self._check(lib.fbim_mlp_features(self._ctx, _fptr(X, self.n * MLP_IN)))
+
+    def mlp_forward(self, X, Y):
+        n = X.numel() // MLP_IN
+        self._check(lib.fbim_mlp_forward(self._ctx, _fptr(X, n * MLP_IN), n, _fptr(Y, n * MLP_OUT)))
+
+    def mlp_backward(self, X, dY, grad):
+        n = X.numel() // MLP_IN
+        self._check(lib.fbim_mlp_backward(self._ctx, _fptr(X, n * MLP_IN), _fptr(dY, n * MLP_OUT), n,
+                                          _fptr(grad, MLP_NPARAM)))
+
+    def mlp_loss(self, Y, F, U, dY):
+        ns = F.numel() // (3 * self.n)
+        loss = ctypes.c_float()
+        self._check(lib.fbim_mlp_loss(self._ctx, _fptr(Y, self.n * MLP_OUT), ns, _dptr(F, ns * 3 * self.n),
+                                      _dptr(U, ns * 3 * self.n), ctypes.byref(loss), _fptr(dY, self.n * MLP_OUT)))
+        return loss.value
+
+    def mlp_train(self, n_solves, epochs, lr=1e-3, seed=0):
+        cfg = TrainCfg(n_solves, epochs, lr, seed)
+        info = TrainInfo()
+        self._check(lib.fbim_mlp_train(self._ctx, ctypes.byref(cfg), ctypes.byref(info)), allow=(4,))
+        return info.as_dict()
+
+    def mlp_use(self, on=True):
+        self._check(lib.fbim_mlp_use(self._ctx, 1 if on else 0))
 
     # -- measurement
     def set_timing(self, enable=True):

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -76,7 +77,16 @@ struct fbim_ctx {
   BodyTiles bt{};
   int4 *d_btile = nullptr;
   int *d_blist = nullptr;
-  double *d_dN = nullptr;  // learned per-body correction of N_ref, [n][6] (null: plain preconditioner)
+  double *d_dN = nullptr;  // learned per-body correction of N_ref, [n][6]
+
+  // learned preconditioner correction
+  bool mlp_init = false, mlp_on = false;
+  int mlp_sym = 1, mlp_cap = 0, mlp_t = 0;
+  size_t train_cap = 0;
+  float *d_mw = nullptr, *d_am = nullptr, *d_av = nullptr, *d_g = nullptr;
+  float *d_X = nullptr, *d_H1 = nullptr, *d_H2 = nullptr, *d_Y = nullptr, *d_dY = nullptr, *d_Z2 = nullptr,
+        *d_Z1 = nullptr, *d_ones = nullptr, *d_loss = nullptr;
+  double *d_trF = nullptr, *d_trU = nullptr;
   double *d_q = nullptr, *d_theta = nullptr, *d_x = nullptr;
   bool have_bodies = false;
 
@@ -378,6 +388,122 @@ fbim_status build_body_tiles(fbim_ctx *c) {
   return FBIM_OK;
 }
 
+// ------------------------------------------------------------------ learned preconditioner correction
+constexpr int kNParam = FBIM_MLP_NPARAM;
+constexpr int kOffW1 = 0, kOffB1 = kMlpIn * kMlpHid, kOffW2 = kOffB1 + kMlpHid, kOffB2 = kOffW2 + kMlpHid * kMlpHid,
+              kOffW3 = kOffB2 + kMlpHid, kOffB3 = kOffW3 + kMlpHid * kMlpOut;
+static_assert(kOffB3 + kMlpOut == kNParam, "weight layout");
+
+double shapes_r_max(const fbim_ctx *c) {
+  double r = 0.0;
+  for (auto &sh : c->shapes)
+    for (int j = 0; j < sh.h.n_p; ++j) r = std::max(r, std::hypot(sh.h.ref_xy[2 * j], sh.h.ref_xy[2 * j + 1]));
+  return r;
+}
+
+fbim_status ensure_mlp(fbim_ctx *c, int n) {
+  if (!c->d_mw) {
+    HIPCHK(c, dalloc(c->d_mw, kNParam));
+    HIPCHK(c, dalloc(c->d_am, kNParam));
+    HIPCHK(c, dalloc(c->d_av, kNParam));
+    HIPCHK(c, dalloc(c->d_g, kNParam));
+    HIPCHK(c, dalloc(c->d_loss, 1));
+  }
+  if (n > c->mlp_cap) {
+    HIPCHK(c, dalloc(c->d_X, (size_t)n * kMlpIn));
+    HIPCHK(c, dalloc(c->d_H1, (size_t)n * kMlpHid));
+    HIPCHK(c, dalloc(c->d_H2, (size_t)n * kMlpHid));
+    HIPCHK(c, dalloc(c->d_Z1, (size_t)n * kMlpHid));
+    HIPCHK(c, dalloc(c->d_Z2, (size_t)n * kMlpHid));
+    HIPCHK(c, dalloc(c->d_Y, (size_t)n * kMlpOut));
+    HIPCHK(c, dalloc(c->d_dY, (size_t)n * kMlpOut));
+    HIPCHK(c, dalloc(c->d_dN, (size_t)n * kMlpOut));
+    HIPCHK(c, dalloc(c->d_ones, (size_t)n));
+    HIPCHK(c, launch_fill_f32((size_t)n, 1.0f, c->d_ones, c->stream));
+    c->mlp_cap = n;
+  }
+  return FBIM_OK;
+}
+
+GemmArgs gemm(int M, int N, int K, const float *A, size_t sam, size_t sak, const float *B, size_t sbk, size_t sbn,
+              float *C, size_t ldc, int epi, const float *bias = nullptr, const float *aux = nullptr) {
+  GemmArgs g;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.A = A;
+  g.sam = sam;
+  g.sak = sak;
+  g.B = B;
+  g.sbk = sbk;
+  g.sbn = sbn;
+  g.C = C;
+  g.ldc = ldc;
+  g.bias = bias;
+  g.aux = aux;
+  g.epi = epi;
+  return g;
+}
+
+// Y = MLP(X); hidden activations kept in d_H1, d_H2
+fbim_status mlp_forward(fbim_ctx *c, const float *X, int n, float *Y) {
+  Timer t(c, "mlp");
+  hipStream_t s = c->stream;
+  const float *w = c->d_mw;
+  HIPCHK(c, launch_gemm_bf16(gemm(n, kMlpHid, kMlpIn, X, kMlpIn, 1, w + kOffW1, kMlpHid, 1, c->d_H1, kMlpHid,
+                                  kGemmBiasTanh, w + kOffB1), 1, s));
+  HIPCHK(c, launch_gemm_bf16(gemm(n, kMlpHid, kMlpHid, c->d_H1, kMlpHid, 1, w + kOffW2, kMlpHid, 1, c->d_H2, kMlpHid,
+                                  kGemmBiasTanh, w + kOffB2), 1, s));
+  HIPCHK(c, launch_gemm_bf16(gemm(n, kMlpOut, kMlpHid, c->d_H2, kMlpHid, 1, w + kOffW3, kMlpOut, 1, Y, kMlpOut,
+                                  kGemmBias, w + kOffB3), 1, s));
+  return FBIM_OK;
+}
+
+// grad = d(sum dY . Y)/dw at X (recomputes the forward activations)
+fbim_status mlp_backward(fbim_ctx *c, const float *X, const float *dY, int n, float *grad) {
+  STCHK(mlp_forward(c, X, n, c->d_Y));
+  Timer t(c, "mlp");
+  hipStream_t s = c->stream;
+  const float *w = c->d_mw;
+  const int ks = std::max(1, std::min(64, n / 256));  // split of the sums over bodies
+  HIPCHK(c, launch_fill_f32(kNParam, 0.0f, grad, s));
+  // layer 3
+  HIPCHK(c, launch_gemm_bf16(gemm(kMlpHid, kMlpOut, n, c->d_H2, 1, kMlpHid, dY, kMlpOut, 1, grad + kOffW3, kMlpOut,
+                                  kGemmAtomic), ks, s));
+  HIPCHK(c, launch_gemm_bf16(gemm(1, kMlpOut, n, c->d_ones, 0, 1, dY, kMlpOut, 1, grad + kOffB3, kMlpOut,
+                                  kGemmAtomic), ks, s));
+  HIPCHK(c, launch_gemm_bf16(gemm(n, kMlpHid, kMlpOut, dY, kMlpOut, 1, w + kOffW3, 1, kMlpOut, c->d_Z2, kMlpHid,
+                                  kGemmTanhGrad, nullptr, c->d_H2), 1, s));
+  // layer 2
+  HIPCHK(c, launch_gemm_bf16(gemm(kMlpHid, kMlpHid, n, c->d_H1, 1, kMlpHid, c->d_Z2, kMlpHid, 1, grad + kOffW2,
+                                  kMlpHid, kGemmAtomic), ks, s));
+  HIPCHK(c, launch_gemm_bf16(gemm(1, kMlpHid, n, c->d_ones, 0, 1, c->d_Z2, kMlpHid, 1, grad + kOffB2, kMlpHid,
+                                  kGemmAtomic), ks, s));
+  HIPCHK(c, launch_gemm_bf16(gemm(n, kMlpHid, kMlpHid, c->d_Z2, kMlpHid, 1, w + kOffW2, 1, kMlpHid, c->d_Z1, kMlpHid,
+                                  kGemmTanhGrad, nullptr, c->d_H1), 1, s));
+  // layer 1
+  HIPCHK(c, launch_gemm_bf16(gemm(kMlpIn, kMlpHid, n, X, 1, kMlpIn, c->d_Z1, kMlpHid, 1, grad + kOffW1, kMlpHid,
+                                  kGemmAtomic), ks, s));
+  HIPCHK(c, launch_gemm_bf16(gemm(1, kMlpHid, n, c->d_ones, 0, 1, c->d_Z1, kMlpHid, 1, grad + kOffB1, kMlpHid,
+                                  kGemmAtomic), ks, s));
+  return FBIM_OK;
+}
+
+fbim_status mlp_features(fbim_ctx *c, float *X) {
+  Timer t(c, "mlp");
+  HIPCHK(c, launch_mlp_features(c->n, c->d_q, c->d_theta, c->d.L, shapes_r_max(c), c->mlp_sym, X, c->stream));
+  return FBIM_OK;
+}
+
+// d_dN for the current bodies (called whenever the bodies change while in use)
+fbim_status mlp_refresh(fbim_ctx *c) {
+  STCHK(ensure_mlp(c, c->n));
+  STCHK(mlp_features(c, c->d_X));
+  STCHK(mlp_forward(c, c->d_X, c->n, c->d_Y));
+  HIPCHK(c, launch_mlp_correction(c->n, c->d_shape, c->d_Nt_arr, c->d_Y, c->d_dN, c->stream));
+  return FBIM_OK;
+}
+
 // ------------------------------------------------------------------ geometry
 fbim_status build_geometry(fbim_ctx *c) {
   const int N = c->N, n = c->n;
@@ -438,6 +564,7 @@ fbim_status build_geometry(fbim_ctx *c) {
   }
   HIPCHK(c, launch_fill_int((size_t)total, -1, c->d_ell, s));
   HIPCHK(c, launch_pair_lists(pa, pl, c->d_xs, 1, s));
+  if (c->mlp_on) STCHK(mlp_refresh(c));
   return FBIM_OK;
 }
 
@@ -575,7 +702,7 @@ fbim_status apply_saddle(fbim_ctx *c, const double *x, double *y) {
 
 fbim_status apply_precond(fbim_ctx *c, const double *z, double *y) {
   Timer t(c, "precond");
-  HIPCHK(c, launch_precond(c->geom(), c->mats(), c->bt, c->d_dN, z, y, c->stream));
+  HIPCHK(c, launch_precond(c->geom(), c->mats(), c->bt, c->mlp_on ? c->d_dN : nullptr, z, y, c->stream));
   return FBIM_OK;
 }
 
@@ -1034,7 +1161,7 @@ void fbim_destroy(fbim_ctx *c) {
                   c->d_mut, c->d_xs32, c->d_mus32, c->d_xt32, c->d_mut32, c->d_grid, c->d_spec, c->d_grid32,
                   c->d_spec32, c->d_e1tab, c->d_e1tab32, c->d_V, c->d_w, c->d_t1, c->d_t2, c->d_b, c->d_x2,
                   c->d_r, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
-                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN};
+                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU};
   for (void *p : ptrs)
     if (p) hipFree(p);
   delete c;
@@ -1289,6 +1416,143 @@ fbim_status fbim_step_em_rfd(fbim_ctx *c, double dt, double delta, const double 
     info->ms_total = now_ms() - t0;
   }
   return worst;
+}
+
+fbim_status fbim_mlp_init(fbim_ctx *c, uint64_t seed, int32_t sym_order) {
+  if (!c || sym_order < 1) return fail(c, FBIM_EINVAL, "invalid MLP initialisation");
+  STCHK(ensure_mlp(c, std::max(c->n, 1)));
+  std::vector<float> w(kNParam, 0.0f);
+  std::mt19937_64 gen(seed);
+  auto glorot = [&](int off, int fan_in, int fan_out, float scale) {
+    const float a = scale * std::sqrt(6.0f / (float)(fan_in + fan_out));
+    std::uniform_real_distribution<float> u(-a, a);
+    for (int i = 0; i < fan_in * fan_out; ++i) w[off + i] = u(gen);
+  };
+  glorot(kOffW1, kMlpIn, kMlpHid, 1.0f);
+  glorot(kOffW2, kMlpHid, kMlpHid, 1.0f);
+  glorot(kOffW3, kMlpHid, kMlpOut, 1e-2f);
+  HIPCHK(c, hipMemcpy(c->d_mw, w.data(), kNParam * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(c, launch_fill_f32(kNParam, 0.0f, c->d_am, c->stream));
+  HIPCHK(c, launch_fill_f32(kNParam, 0.0f, c->d_av, c->stream));
+  c->mlp_t = 0;
+  c->mlp_sym = sym_order;
+  c->mlp_init = true;
+  if (c->mlp_on && c->have_bodies) STCHK(mlp_refresh(c));
+  return FBIM_OK;
+}
+
+fbim_status fbim_mlp_set_weights(fbim_ctx *c, const float *w, size_t n) {
+  if (!c || !w || n != (size_t)kNParam) return fail(c, FBIM_EINVAL, "weights must hold FBIM_MLP_NPARAM floats");
+  if (!c->mlp_init) return fail(c, FBIM_EINVAL, "fbim_mlp_init first");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(c->d_mw, w, n * sizeof(float), hipMemcpyHostToDevice));
+  if (c->mlp_on && c->have_bodies) STCHK(mlp_refresh(c));
+  return FBIM_OK;
+}
+
+fbim_status fbim_mlp_get_weights(fbim_ctx *c, float *w, size_t n) {
+  if (!c || !w || n != (size_t)kNParam) return fail(c, FBIM_EINVAL, "weights must hold FBIM_MLP_NPARAM floats");
+  if (!c->mlp_init) return fail(c, FBIM_EINVAL, "fbim_mlp_init first");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(w, c->d_mw, n * sizeof(float), hipMemcpyDeviceToHost));
+  return FBIM_OK;
+}
+
+fbim_status fbim_mlp_features(fbim_ctx *c, float *X) {
+  if (!c || !X) return fail(c, FBIM_EINVAL, "null argument");
+  if (!c->have_bodies) return fail(c, FBIM_EINVAL, "no bodies set");
+  return mlp_features(c, X);
+}
+
+fbim_status fbim_mlp_forward(fbim_ctx *c, const float *X, int32_t n, float *Y) {
+  if (!c || !X || !Y || n < 0) return fail(c, FBIM_EINVAL, "invalid argument");
+  if (!c->mlp_init) return fail(c, FBIM_EINVAL, "fbim_mlp_init first");
+  STCHK(ensure_mlp(c, n));
+  return mlp_forward(c, X, n, Y);
+}
+
+fbim_status fbim_mlp_backward(fbim_ctx *c, const float *X, const float *dY, int32_t n, float *grad) {
+  if (!c || !X || !dY || !grad || n < 0) return fail(c, FBIM_EINVAL, "invalid argument");
+  if (!c->mlp_init) return fail(c, FBIM_EINVAL, "fbim_mlp_init first");
+  STCHK(ensure_mlp(c, n));
+  return mlp_backward(c, X, dY, n, grad);
+}
+
+fbim_status fbim_mlp_loss(fbim_ctx *c, const float *Y, int32_t ns, const double *F, const double *U, float *loss,
+                          float *dY) {
+  if (!c || !Y || !F || !U || !loss || !dY || ns < 1) return fail(c, FBIM_EINVAL, "invalid argument");
+  if (!c->have_bodies) return fail(c, FBIM_EINVAL, "no bodies set");
+  STCHK(ensure_mlp(c, c->n));
+  HIPCHK(c, launch_fill_f32(1, 0.0f, c->d_loss, c->stream));
+  HIPCHK(c, launch_mlp_loss(c->n, ns, c->d_shape, c->d_theta, c->d_Nt_arr, Y, F, U, dY, c->d_loss, c->stream));
+  HIPCHK(c, hipMemcpyAsync(loss, c->d_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FBIM_OK;
+}
+
+fbim_status fbim_mlp_train(fbim_ctx *c, const fbim_train_cfg *cfg, fbim_train_info *info) {
+  if (!c || !cfg || cfg->n_solves < 1 || cfg->epochs < 0 || !(cfg->lr > 0.0f))
+    return fail(c, FBIM_EINVAL, "invalid training configuration");
+  if (!c->mlp_init || !c->have_bodies) return fail(c, FBIM_EINVAL, "fbim_mlp_init and fbim_set_bodies first");
+  const int n = c->n, ns = cfg->n_solves;
+  const size_t n3 = 3 * (size_t)n;
+  hipStream_t s = c->stream;
+  STCHK(ensure_mlp(c, n));
+  if ((size_t)ns * n3 > c->train_cap) {
+    HIPCHK(c, dalloc(c->d_trF, (size_t)ns * n3));
+    HIPCHK(c, dalloc(c->d_trU, (size_t)ns * n3));
+    c->train_cap = (size_t)ns * n3;
+  }
+  fbim_train_info inf{};
+  std::mt19937_64 gen(cfg->seed);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  std::vector<double> F(n3);
+  fbim_status worst = FBIM_OK;
+  for (int k = 0; k < ns; ++k) {
+    for (auto &v : F) v = nd(gen);
+    HIPCHK(c, hipMemcpyAsync(c->d_trF + k * n3, F.data(), n3 * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    int its = 0;
+    double res = 0;
+    fbim_status st = mobility(c, c->d_trF + k * n3, nullptr, c->d_trU + k * n3, nullptr, its, res);
+    if (st != FBIM_OK && st != FBIM_ENOCONV) return st;
+    if (st != FBIM_OK) worst = st;
+    inf.gmres_iters += its;
+  }
+  inf.samples = ns * n;
+  STCHK(mlp_features(c, c->d_X));
+  float l = 0.0f;
+  for (int e = 0; e <= cfg->epochs; ++e) {
+    STCHK(mlp_forward(c, c->d_X, n, c->d_Y));
+    {
+      Timer t(c, "mlp");
+      HIPCHK(c, launch_fill_f32(1, 0.0f, c->d_loss, s));
+      HIPCHK(c, launch_mlp_loss(n, ns, c->d_shape, c->d_theta, c->d_Nt_arr, c->d_Y, c->d_trF, c->d_trU, c->d_dY,
+                                c->d_loss, s));
+    }
+    if (e == 0 || e == cfg->epochs) {
+      HIPCHK(c, hipMemcpyAsync(&l, c->d_loss, sizeof(float), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      if (e == 0) inf.loss_first = l;
+      inf.loss_last = l;
+    }
+    if (e == cfg->epochs) break;
+    STCHK(mlp_backward(c, c->d_X, c->d_dY, n, c->d_g));
+    Timer t(c, "mlp");
+    HIPCHK(c, launch_adam(kNParam, cfg->lr, 0.9f, 0.999f, 1e-8f, ++c->mlp_t, c->d_g, c->d_am, c->d_av, c->d_mw, s));
+  }
+  if (c->mlp_on) STCHK(mlp_refresh(c));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (info) *info = inf;
+  return worst;
+}
+
+fbim_status fbim_mlp_use(fbim_ctx *c, int32_t on) {
+  if (!c) return FBIM_EINVAL;
+  if (on && !c->mlp_init) return fail(c, FBIM_EINVAL, "fbim_mlp_init first");
+  c->mlp_on = on != 0;
+  if (c->mlp_on && c->have_bodies) STCHK(mlp_refresh(c));
+  return FBIM_OK;
 }
 
 fbim_status fbim_set_timing(fbim_ctx *c, int32_t enable) {

@@ -169,4 +169,32 @@ hipError_t launch_vec_add(int k, const double *a, double *b, hipStream_t s);  //
 hipError_t launch_cast_f32(size_t n, const double *x, float *y, hipStream_t s);
 hipError_t launch_fill(size_t n, double v, double *y, hipStream_t s);
 
+// learned preconditioner correction (MLP 32 -> 128 -> 128 -> 6, tanh)
+constexpr int kMlpNeighbours = 6, kMlpIn = 32, kMlpHid = 128, kMlpOut = 6;
+// features [n][32] of each body's neighbourhood in its body frame
+hipError_t launch_mlp_features(int n, const double *q, const double *theta, double L, double r_max, int sym,
+                               float *X, hipStream_t s);
+enum { kGemmStore = 0, kGemmBiasTanh = 1, kGemmBias = 2, kGemmAtomic = 3, kGemmTanhGrad = 4 };
+// C = op(A) op(B) in BF16 MFMA with FP32 accumulation; epilogues: store, tanh(. + bias[j]),
+// . + bias[j], atomic add (split K), . * (1 - aux[i][j]^2) (aux has leading dimension ldc)
+struct GemmArgs {
+  int M, N, K;
+  const float *A;
+  size_t sam, sak;
+  const float *B;
+  size_t sbk, sbn;
+  float *C;
+  size_t ldc;
+  const float *bias, *aux;
+  int epi;
+};
+hipError_t launch_gemm_bf16(const GemmArgs &g, int ksplit, hipStream_t s);
+hipError_t launch_mlp_loss(int n, int ns, const int *shape, const double *theta, const double *const *Nt,
+                           const float *Y, const double *F, const double *U, float *dY, float *loss, hipStream_t s);
+hipError_t launch_mlp_correction(int n, const int *shape, const double *const *Nt, const float *Y, double *dN,
+                                 hipStream_t s);
+hipError_t launch_adam(int n, float lr, float b1, float b2, float eps, int t, const float *g, float *m, float *v,
+                       float *w, hipStream_t s);
+hipError_t launch_fill_f32(size_t n, float v, float *y, hipStream_t s);
+
 }  // namespace fbim

@@ -79,9 +79,11 @@ hipError_t launch_KT(const GeomDev &g, const double *mu, double sgn, double *out
 //
 // MODE 0: y_b = R_b X_ref R_b^T x_b, X = G_ref or G_ref^+ (eqs. 3.40-3.42).
 // MODE 1: block-diagonal preconditioner (eqs. 3.31-3.37): in the body frame
-//   c = M_ref^+ a~,  U_ref = -N_b (R'^T b + K_ref^T c),  mu_ref = c + (M_ref^+ K_ref) U_ref,
-//   mu = R mu_ref, U = R' U_ref, with N_b = N_ref (+ a learned symmetric
-//   correction dN_b in the body frame, when given).
+//   c = M_ref^+ a~,  U_ref = -N_ref (R'^T b + K_ref^T c),  mu_ref = c + (M_ref^+ K_ref) U_ref,
+//   mu = R mu_ref, U = R' U_ref.  With a learned symmetric correction C = dN_b
+//   (body frame) it applies the exact inverse of the body block whose M_bb is
+//   replaced by M_bb + K C K^T: by the Woodbury identity that body's mobility
+//   becomes N_ref + C, mu is unchanged and U_ref gains -C R'^T b.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_body_tile(BodyTiles bt, const int *__restrict__ off,
                                                    const double *__restrict__ theta, const double *const *ref,
@@ -169,7 +171,7 @@ __global__ __launch_bounds__(256) void k_body_tile(BodyTiles bt, const int *__re
   }
   __syncthreads();
   if (MODE == 1) {
-    // per body: f = K_ref^T c (one wave per body), U_ref = -N_b (R'^T b + f)
+    // per body: f = K_ref^T c (one wave per body), U_ref = -N_ref (R'^T b + f)
     const int lane = tid & 63, wv = tid >> 6;
     const double *rf = ref[sh];
     for (int j = wv; j < nb; j += 4) {
@@ -194,30 +196,26 @@ __global__ __launch_bounds__(256) void k_body_tile(BodyTiles bt, const int *__re
         const double g1 = -sn * bb[0] + cs * bb[1] + f1;
         const double g2 = bb[2] + f2;
         const double *Nm = Nt[sh];
-        double n00 = Nm[0], n01 = Nm[1], n02 = Nm[2], n11 = Nm[4], n12 = Nm[5], n22 = Nm[8];
-        double n10 = Nm[3], n20 = Nm[6], n21 = Nm[7];
-        if (dN) {
-          const double *d = dN + 6 * (size_t)b;  // (xx, yy, tt, xy, xt, yt)
-          n00 += d[0];
-          n11 += d[1];
-          n22 += d[2];
-          n01 += d[3];
-          n10 += d[3];
-          n02 += d[4];
-          n20 += d[4];
-          n12 += d[5];
-          n21 += d[5];
-        }
-        const double u0 = -(n00 * g0 + n01 * g1 + n02 * g2);
-        const double u1 = -(n10 * g0 + n11 * g1 + n12 * g2);
-        const double u2 = -(n20 * g0 + n21 * g1 + n22 * g2);
+        const double u0 = -(Nm[0] * g0 + Nm[1] * g1 + Nm[2] * g2);
+        const double u1 = -(Nm[3] * g0 + Nm[4] * g1 + Nm[5] * g2);
+        const double u2 = -(Nm[6] * g0 + Nm[7] * g1 + Nm[8] * g2);
         Ur[j][0] = u0;
         Ur[j][1] = u1;
         Ur[j][2] = u2;
+        // learned correction C = dN_b: the exact inverse of the body block with
+        // M_bb replaced by M_bb + K C K^T keeps mu and adds -C R'^T b to U
+        double v0 = u0, v1 = u1, v2 = u2;
+        if (dN) {
+          const double *d = dN + 6 * (size_t)b;  // (xx, yy, tt, xy, xt, yt)
+          const double b0 = cs * bb[0] + sn * bb[1], b1 = -sn * bb[0] + cs * bb[1], b2 = bb[2];
+          v0 -= d[0] * b0 + d[3] * b1 + d[4] * b2;
+          v1 -= d[3] * b0 + d[1] * b1 + d[5] * b2;
+          v2 -= d[4] * b0 + d[5] * b1 + d[2] * b2;
+        }
         double *yU = y + 2 * (size_t)N + 3 * (size_t)b;
-        yU[0] = cs * u0 - sn * u1;
-        yU[1] = sn * u0 + cs * u1;
-        yU[2] = u2;
+        yU[0] = cs * v0 - sn * v1;
+        yU[1] = sn * v0 + cs * v1;
+        yU[2] = v2;
       }
     }
     __syncthreads();

@@ -50,6 +50,8 @@ class Workload:
     tol_gmres: float = 1e-6
     tol_lanczos: float = 1e-6
     tau_spurious: float = 1e-8
+    placement: str = "auto"   # "rsa", "lattice" (jittered square lattice) or "auto" (lattice from 2000 bodies)
+    gap: float = -1.0         # minimum gap between bounding circles / r_s (negative: two node spacings)
     # filled by make()
     q: Optional[np.ndarray] = None       # (n, 2)
     theta: Optional[np.ndarray] = None   # (n,)
@@ -97,6 +99,12 @@ CONFIGS = {
     "starfish10k": dict(n_bodies=10000, n_p=64, r_s=_rs_for_fraction(10000, 1.0, 0.3, 0.3),
                         b=0.3, n_arm=5, L=1.0, tol_ewald=1e-6, grid_M=2048,
                         alpert_order=4),
+    # dense suspensions (area fraction 0.4, bounding-circle gaps down to 0.05 r_s) for the
+    # learned preconditioner: 1000 x 128 nodes, grid 1024^2, and a 200 x 64 training size
+    "dense1000": dict(n_bodies=1000, n_p=128, r_s=_rs_for_fraction(1000, 1.0, 0.3, 0.4), b=0.3, n_arm=5,
+                      L=1.0, tol_ewald=1e-6, grid_M=1024, alpert_order=4, placement="lattice", gap=0.05),
+    "dense200": dict(n_bodies=200, n_p=64, r_s=_rs_for_fraction(200, 1.0, 0.3, 0.4), b=0.3, n_arm=5,
+                     L=1.0, tol_ewald=1e-6, grid_M=256, alpert_order=4, placement="lattice", gap=0.05),
     # small cases for fast tests
     "tiny2": dict(n_bodies=2, n_p=32, r_s=0.08, b=0.3, n_arm=5, L=1.0,
                   tol_ewald=1e-8, xi=14.0, n_box=3, grid_M=48, P=13),
@@ -105,7 +113,7 @@ CONFIGS = {
 }
 
 _SEEDS = {"starfish4": 0, "starfish100": 1, "small12": 10, "tiny2": 11,
-          "starfish10k": 4}
+          "starfish10k": 4, "dense1000": 3, "dense200": 12}
 
 
 def _node_spacing(r_s, b, n_p):
@@ -168,8 +176,8 @@ def make(name: str, seed: Optional[int] = None, **overrides) -> Workload:
     s = 1709 + (_SEEDS.get(name, 99) if seed is None else seed)
     rng = np.random.default_rng(s)
     a = wl.a
-    dmin = 2 * a + 2 * _node_spacing(wl.r_s, wl.b, wl.n_p)
-    if wl.n_bodies >= 2000:
+    dmin = 2 * a + (2 * _node_spacing(wl.r_s, wl.b, wl.n_p) if wl.gap < 0 else wl.gap * wl.r_s)
+    if wl.placement == "lattice" or (wl.placement == "auto" and wl.n_bodies >= 2000):
         wl.q = _place_lattice(rng, wl.n_bodies, wl.L, dmin)
     else:
         wl.q = _place_rsa(rng, wl.n_bodies, wl.L, dmin)
