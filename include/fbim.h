@@ -58,7 +58,10 @@ enum { FBIM_PREC_FP64 = 0, FBIM_PREC_MIXED = 1 };
 enum {
   /* Arnoldi / Lanczos: second Gram-Schmidt pass only when the first cancels more than
      half of ||w||^2 (default: always two passes) */
-  FBIM_FLAG_SELECTIVE_REORTH = 1u
+  FBIM_FLAG_SELECTIVE_REORTH = 1u,
+  /* fbim_step_em_rfd: the three mobility solves in one lockstep batch (two
+     internal copies of the context hold the configurations Q +- delta/2 Wt) */
+  FBIM_FLAG_BATCH_RFD = 2u
 };
 
 /* bits of `parts` in fbim_apply_M */
@@ -200,6 +203,50 @@ fbim_status fbim_derive_params(const fbim_params *in, fbim_derived *out);
  * and weights w[j] replacing the a - 1 trapezoid points next to the
  * singularity.  HOST chi, w must hold 8 doubles. */
 fbim_status fbim_alpert_rule(int32_t order, int32_t *j, int32_t *a, double *chi, double *w);
+
+/* ---- Batches of independent systems ------------------------------------------
+ * A batch advances S independent systems (suspensions of any sizes, same
+ * precision) together: every stage of the matvec (gathers, pair sum, Alpert
+ * band, spreading, multiplier, interpolation), the rigid-body terms, the
+ * preconditioner and the Krylov vector operations of all systems run as one
+ * launch per stage, with the FFTs batched per grid size; GMRES runs in
+ * lockstep, each system with its own Krylov space, Hessenberg matrix and
+ * stopping test, and leaves the batch when it converges.  With
+ * FBIM_BATCH_GRAPH the preconditioner + saddle-operator launch sequence of a
+ * GMRES iteration is captured once into a HIP graph and replayed.
+ * Members are ordinary contexts owned by the batch (fbim_batch_member): give
+ * them shapes and bodies with fbim_add_shape / fbim_set_bodies; every
+ * single-system call keeps working on them.  All members use the batch's
+ * stream. */
+typedef struct fbim_batch fbim_batch;
+enum { FBIM_BATCH_GRAPH = 1u };
+
+/* HOST params[S] (one per system).  Fails with FBIM_EINVAL if the precisions differ. */
+fbim_status fbim_batch_create(int32_t S, const fbim_params *params, fbim_batch **out);
+void fbim_batch_destroy(fbim_batch *batch);
+const char *fbim_batch_last_error(const fbim_batch *batch);  /* never NULL */
+fbim_ctx *fbim_batch_member(fbim_batch *batch, int32_t s);  /* NULL if s is out of range */
+fbim_status fbim_batch_set_stream(fbim_batch *batch, void *stream);
+fbim_status fbim_batch_set_flags(fbim_batch *batch, uint32_t flags);  /* FBIM_BATCH_* bits */
+
+/* out[s] = M_s mu[s] (all parts) for every member: HOST arrays of S DEVICE
+ * pointers, each 2 N_s doubles. */
+fbim_status fbim_batch_apply_M(fbim_batch *batch, const double *const *mu, double *const *out);
+
+/* Mobility solves of eq. 3.8 for every member at once: HOST arrays of S DEVICE
+ * pointers F[s] (3 n_s), slip[s] (2 N_s, or NULL entries / NULL array for zero
+ * slip), U[s] (3 n_s); HOST info[S] or NULL.  Returns FBIM_ENOCONV if any
+ * system hit its iteration limit (all outputs still written). */
+fbim_status fbim_batch_mobility(fbim_batch *batch, const double *const *F, const double *const *slip,
+                                double *const *U, fbim_info *info);
+
+/* One EM-RFD step (eq. 4.3) of every member, with the three mobility solves of
+ * every member (at Q, Q + delta/2 Wt, Q - delta/2 Wt) in one batched GMRES.
+ * Arguments as fbim_step_em_rfd, as HOST arrays of S DEVICE pointers. */
+fbim_status fbim_batch_step_em_rfd(fbim_batch *batch, double dt, double delta, const double *const *F,
+                                   const double *const *W_r, const double *const *W_grid,
+                                   const double *const *W_tilde, double *const *dQ, int32_t apply,
+                                   fbim_info *info);
 
 /* ---- Learned correction of the block-diagonal preconditioner ----------------
  * A per-body MLP 32 -> 128 -> 128 -> 6 with tanh hidden layers maps features

@@ -17,6 +17,8 @@ __all__ = ["Params", "Derived", "Info", "Context", "lib", "derive_params", "alpe
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfbim.so")
 
 PART_REAL, PART_ALPERT, PART_WAVE, PART_ALL = 1, 2, 4, 7
+FLAG_SELECTIVE_REORTH, FLAG_BATCH_RFD = 1, 2
+BATCH_GRAPH = 1
 PREC_FP64, PREC_MIXED = 0, 1
 MLP_IN, MLP_HID, MLP_OUT = 32, 128, 6
 MLP_NPARAM = 32 * 128 + 128 + 128 * 128 + 128 + 128 * 6 + 6
@@ -112,6 +114,15 @@ def _load():
         "fbim_mlp_loss": (i32, [p, p, i32, p, p, P(ctypes.c_float), p]),
         "fbim_mlp_train": (i32, [p, P(TrainCfg), P(TrainInfo)]),
         "fbim_mlp_use": (i32, [p, i32]),
+        "fbim_batch_create": (i32, [i32, P(Params), P(p)]),
+        "fbim_batch_destroy": (None, [p]),
+        "fbim_batch_last_error": (ctypes.c_char_p, [p]),
+        "fbim_batch_member": (p, [p, i32]),
+        "fbim_batch_set_stream": (i32, [p, p]),
+        "fbim_batch_set_flags": (i32, [p, u32]),
+        "fbim_batch_apply_M": (i32, [p, p, p]),
+        "fbim_batch_mobility": (i32, [p, p, p, p, P(Info)]),
+        "fbim_batch_step_em_rfd": (i32, [p, d, d, p, p, p, p, p, i32, P(Info)]),
         "fbim_set_timing": (i32, [p, i32]),
         "fbim_kernel_time": (i32, [p, ctypes.c_char_p, P(d), P(ctypes.c_int64)]),
     }
@@ -187,16 +198,21 @@ def _fptr(t, n=None):
 class Context:
     """One library context (fbim_ctx) bound to torch's current stream."""
 
-    def __init__(self, **params):
+    def __init__(self, _handle=None, **params):
         import torch
+        self.n = 0
+        self.N = 0
+        if _handle is not None:  # a member of a Batch (owned by the batch)
+            self._ctx = ctypes.c_void_p(_handle)
+            self._owned = False
+            return
         self._ctx = ctypes.c_void_p()
+        self._owned = True
         self.params = make_params(**params)
         st = lib.fbim_create(ctypes.byref(self.params), ctypes.byref(self._ctx))
         if st != 0:
             raise FbimError(st, "fbim_create failed")
         self._check(lib.fbim_set_stream(self._ctx, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
-        self.n = 0
-        self.N = 0
 
     def _check(self, st, allow=()):
         if st != 0 and st not in allow:
@@ -204,9 +220,9 @@ class Context:
         return st
 
     def close(self):
-        if self._ctx:
+        if self._ctx and self._owned:
             lib.fbim_destroy(self._ctx)
-            self._ctx = ctypes.c_void_p()
+        self._ctx = ctypes.c_void_p()
 
     def __del__(self):
         try:
@@ -330,3 +346,74 @@ class Context:
         ms, cnt = ctypes.c_double(), ctypes.c_int64()
         self._check(lib.fbim_kernel_time(self._ctx, name.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
         return ms.value, cnt.value
+
+
+def _ptr_array(tensors, check):
+    arr = (ctypes.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = None if t is None else check(t)
+    return arr
+
+
+class Batch:
+    """Several independent systems advanced together (fbim_batch)."""
+
+    def __init__(self, params_list, graph=False):
+        import torch
+        prm = (Params * len(params_list))(*[make_params(**p) for p in params_list])
+        self._b = ctypes.c_void_p()
+        st = lib.fbim_batch_create(len(params_list), prm, ctypes.byref(self._b))
+        if st != 0:
+            raise FbimError(st, "fbim_batch_create failed")
+        self._check(lib.fbim_batch_set_stream(self._b, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        self.members = [Context(_handle=lib.fbim_batch_member(self._b, i)) for i in range(len(params_list))]
+        if graph:
+            self._check(lib.fbim_batch_set_flags(self._b, BATCH_GRAPH))
+
+    def _check(self, st, allow=()):
+        if st != 0 and st not in allow:
+            raise FbimError(st, lib.fbim_batch_last_error(self._b).decode())
+        return st
+
+    def close(self):
+        for m in getattr(self, "members", []):
+            m._ctx = ctypes.c_void_p()
+        if self._b:
+            lib.fbim_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_graph(self, on=True):
+        self._check(lib.fbim_batch_set_flags(self._b, BATCH_GRAPH if on else 0))
+
+    def apply_M(self, mus, outs):
+        m = self.members
+        self._check(lib.fbim_batch_apply_M(
+            self._b, _ptr_array([_dptr(x, 2 * c.N) for x, c in zip(mus, m)], lambda v: v.value),
+            _ptr_array([_dptr(x, 2 * c.N) for x, c in zip(outs, m)], lambda v: v.value)))
+
+    def mobility(self, Fs, Us, slips=None):
+        m = self.members
+        info = (Info * len(m))()
+        F = _ptr_array([_dptr(x, 3 * c.n).value for x, c in zip(Fs, m)], lambda v: v)
+        U = _ptr_array([_dptr(x, 3 * c.n).value for x, c in zip(Us, m)], lambda v: v)
+        S = None if slips is None else _ptr_array(
+            [None if x is None else _dptr(x, 2 * c.N).value for x, c in zip(slips, m)], lambda v: v)
+        self._check(lib.fbim_batch_mobility(self._b, F, S, U, info), allow=(4,))
+        return [i.as_dict() for i in info]
+
+    def step_em_rfd(self, dt, delta, Fs, W_rs, W_grids, W_tildes, dQs, apply=False):
+        m = self.members
+        info = (Info * len(m))()
+        Ms = [c.get_derived()["grid_M"] for c in m]
+        arr = lambda xs, sizes: _ptr_array([_dptr(x, k).value for x, k in zip(xs, sizes)], lambda v: v)  # noqa: E731
+        self._check(lib.fbim_batch_step_em_rfd(
+            self._b, dt, delta, arr(Fs, [3 * c.n for c in m]), arr(W_rs, [2 * c.N for c in m]),
+            arr(W_grids, [2 * M * M for M in Ms]), arr(W_tildes, [3 * c.n for c in m]),
+            arr(dQs, [3 * c.n for c in m]), 1 if apply else 0, info), allow=(4,))
+        return [i.as_dict() for i in info]

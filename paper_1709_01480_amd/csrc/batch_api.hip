@@ -1,0 +1,1179 @@
+// Batches of independent systems: one launch per stage for all systems, FFTs
+// batched per grid size, lockstep GMRES with per-system Krylov spaces, and a
+// HIP graph of the preconditioner + saddle-operator sequence.
+#include "ctx.h"
+
+namespace fbim {
+namespace {
+
+template <class T>
+T *carve(char *base, size_t &off, size_t n) {
+  off = (off + 255) & ~(size_t)255;
+  T *p = reinterpret_cast<T *>(base + off);
+  off += n * sizeof(T);
+  return p;
+}
+
+// FFT size class: systems sharing the grid size M transform together
+struct SizeClass {
+  int M = 0;
+  std::vector<int> sys;  // engine system indices
+  rocfft_plan fwd = nullptr, inv = nullptr, fwd32 = nullptr, inv32 = nullptr;
+  double *grid = nullptr, *spec = nullptr;
+  float *grid32 = nullptr, *spec32 = nullptr;
+};
+
+// Device job tables of one list of systems (the systems of one batched launch set).
+struct Tables {
+  int S = 0;
+  std::vector<int> list;  // engine system indices, in table order
+  GatherJob *gcell[2], *gtile[2];  // [0] FP64, [1] FP32 destinations
+  PairJob *pair[2];
+  AlpertJob *alp;
+  SpreadJob *spr[2];
+  MultJob *mul[2];
+  InterpJob *itp[2];
+  RigidJob *rig;
+  PrecondJob *pre;
+  BatchGrid bg_nodes{}, bg_pair{}, bg_tiles{}, bg_spec{}, bg_bodies4{}, bg_prec{};
+  size_t prec_lds = 0;
+  Segs seg{};
+  // per-system vectors (pointer tables) and leading dimension of the basis
+  const double **V, **bx, **by, **t1, **b, **x2, **r, **irr, **ird;
+  size_t *ld;
+  double *ones, *zeros, *mones;
+  char *dev = nullptr;
+  size_t cap = 0;
+  int signature = -1;
+};
+
+}  // namespace
+
+struct BatchEngine {
+  std::vector<fbim_ctx *> sys;
+  hipStream_t stream = nullptr;
+  bool mixed = false;
+  uint32_t flags = 0;
+  std::vector<SizeClass> classes;
+  std::vector<int> cls_of, slot_of;
+  rocfft_execution_info einfo = nullptr;
+  void *work = nullptr;
+  size_t work_bytes = 0;
+  Tables full, sub;
+  double *d_sc = nullptr;  // per-system scalars: [a | h | h2 | nrm | flag | c] blocks
+  size_t sc_cap = 0;
+  int hs = 0;
+  double *d_partial = nullptr;
+  size_t partial_cap = 0;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int graph_sig[2] = {-1, -1};
+  hipStream_t cap_stream = nullptr;  // private stream for graph capture (the null stream cannot capture)
+  std::string err;
+};
+
+namespace {
+
+fbim_status efail(BatchEngine *E, fbim_status s, const std::string &m) {
+  E->err = m;
+  return s;
+}
+
+#define EHIP(E, expr)                                                                             \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess) return efail(E, FBIM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define EFFT(E, expr)                                                                             \
+  do {                                                                                            \
+    rocfft_status e_ = (expr);                                                                    \
+    if (e_ != rocfft_status_success)                                                              \
+      return efail(E, FBIM_EDEVICE, std::string(#expr) + ": rocfft status " + std::to_string((int)e_)); \
+  } while (0)
+
+#define EST(expr)                 \
+  do {                            \
+    fbim_status s_ = (expr);      \
+    if (s_ != FBIM_OK) return s_; \
+  } while (0)
+
+WaveArgs wave_args(const fbim_ctx *c) {
+  WaveArgs w;
+  w.M = c->d.M;
+  w.T = c->d.tile;
+  w.P = c->d.P;
+  w.nts = c->nts;
+  w.h = c->d.h;
+  w.L = c->d.L;
+  w.ag = 2.0 * c->d.xi * c->d.xi / c->d.eta_s;
+  w.cg = 2.0 * c->d.xi * c->d.xi / (kPi * c->d.eta_s);
+  w.tile_start = c->d_tstart;
+  w.anchor = c->d_anchor;
+  return w;
+}
+
+void destroy_classes(BatchEngine *E) {
+  for (auto &k : E->classes) {
+    if (k.fwd) rocfft_plan_destroy(k.fwd);
+    if (k.inv) rocfft_plan_destroy(k.inv);
+    if (k.fwd32) rocfft_plan_destroy(k.fwd32);
+    if (k.inv32) rocfft_plan_destroy(k.inv32);
+    dfree(k.grid);
+    dfree(k.spec);
+    dfree(k.grid32);
+    dfree(k.spec32);
+  }
+  E->classes.clear();
+}
+
+void destroy_graphs(BatchEngine *E) {
+  for (int i = 0; i < 2; ++i) {
+    if (E->gexec[i]) hipGraphExecDestroy(E->gexec[i]);
+    E->gexec[i] = nullptr;
+    E->graph_sig[i] = -1;
+  }
+}
+
+// FFT size classes and their plans (rebuilt only when the grouping changes)
+fbim_status setup_classes(BatchEngine *E) {
+  std::vector<int> Ms;
+  for (auto *c : E->sys) Ms.push_back(c->d.M);
+  std::vector<SizeClass> want;
+  std::vector<int> cls(E->sys.size()), slot(E->sys.size());
+  for (size_t i = 0; i < E->sys.size(); ++i) {
+    int k = -1;
+    for (size_t j = 0; j < want.size(); ++j)
+      if (want[j].M == Ms[i]) k = (int)j;
+    if (k < 0) {
+      want.push_back(SizeClass{});
+      want.back().M = Ms[i];
+      k = (int)want.size() - 1;
+    }
+    cls[i] = k;
+    slot[i] = (int)want[k].sys.size();
+    want[k].sys.push_back((int)i);
+  }
+  bool same = want.size() == E->classes.size();
+  for (size_t j = 0; same && j < want.size(); ++j)
+    same = want[j].M == E->classes[j].M && want[j].sys == E->classes[j].sys;
+  E->cls_of = cls;
+  E->slot_of = slot;
+  if (same) return FBIM_OK;
+  destroy_graphs(E);
+  destroy_classes(E);
+  if (!g_rocfft_ready) {
+    EFFT(E, rocfft_setup());
+    g_rocfft_ready = true;
+  }
+  size_t wmax = 0;
+  for (auto &k : want) {
+    const size_t M = k.M, cnt = k.sys.size();
+    const size_t len[2] = {M, M};
+    auto plan = [&](rocfft_plan *p, rocfft_transform_type t, rocfft_precision pr) -> fbim_status {
+      EFFT(E, rocfft_plan_create(p, rocfft_placement_notinplace, t, pr, 2, len, 2 * cnt, nullptr));
+      size_t w = 0;
+      EFFT(E, rocfft_plan_get_work_buffer_size(*p, &w));
+      wmax = std::max(wmax, w);
+      return FBIM_OK;
+    };
+    EST(plan(&k.fwd, rocfft_transform_type_real_forward, rocfft_precision_double));
+    EST(plan(&k.inv, rocfft_transform_type_real_inverse, rocfft_precision_double));
+    EHIP(E, dalloc(k.grid, 2 * M * M * cnt));
+    EHIP(E, dalloc(k.spec, 4 * M * (M / 2 + 1) * cnt));
+    if (E->mixed) {
+      EST(plan(&k.fwd32, rocfft_transform_type_real_forward, rocfft_precision_single));
+      EST(plan(&k.inv32, rocfft_transform_type_real_inverse, rocfft_precision_single));
+      EHIP(E, dalloc(k.grid32, 2 * M * M * cnt));
+      EHIP(E, dalloc(k.spec32, 4 * M * (M / 2 + 1) * cnt));
+    }
+  }
+  E->classes = want;
+  if (!E->einfo) EFFT(E, rocfft_execution_info_create(&E->einfo));
+  if (wmax > E->work_bytes) {
+    if (E->work) hipFree(E->work);
+    E->work = nullptr;
+    EHIP(E, hipMalloc(&E->work, wmax));
+    E->work_bytes = wmax;
+  }
+  if (E->work_bytes) EFFT(E, rocfft_execution_info_set_work_buffer(E->einfo, E->work, E->work_bytes));
+  EFFT(E, rocfft_execution_info_set_stream(E->einfo, E->stream));
+  return FBIM_OK;
+}
+
+// build (and upload) the job tables of the systems `list` (engine indices)
+fbim_status build_tables(BatchEngine *E, const std::vector<int> &list, Tables &T) {
+  const int S = (int)list.size();
+  // host images
+  std::vector<GatherJob> gc[2], gt[2];
+  std::vector<PairJob> pj[2];
+  std::vector<AlpertJob> aj;
+  std::vector<SpreadJob> sj[2];
+  std::vector<MultJob> mj[2];
+  std::vector<InterpJob> ij[2];
+  std::vector<RigidJob> rj;
+  std::vector<PrecondJob> pr;
+  std::vector<int> b_nodes{0}, b_pair{0}, b_tiles{0}, b_spec{0}, b_bod{0}, b_prec{0};
+  std::vector<int2> chunks;
+  std::vector<int> chunk_sys, sys_chunk{0};
+  std::vector<const double *> V, bx, by, t1, bb, x2, r, irr, ird;
+  std::vector<size_t> ld;
+  size_t lds = 0;
+  for (int q = 0; q < S; ++q) {
+    fbim_ctx *c = E->sys[list[q]];
+    const SizeClass &k = E->classes[E->cls_of[list[q]]];
+    const int slot = E->slot_of[list[q]];
+    const size_t M = c->d.M, gsz = 2 * M * M, ssz = 4 * M * (M / 2 + 1);
+    for (int p = 0; p < 2; ++p) {
+      const bool f = p == 1;
+      gc[p].push_back(GatherJob{c->N, c->d_cperm, c->d_t1, f ? (void *)c->d_mus32 : (void *)c->d_mus});
+      gt[p].push_back(GatherJob{c->N, c->d_tperm, c->d_t1, f ? (void *)c->d_mut32 : (void *)c->d_mut});
+      PairJob j;
+      j.N = c->N;
+      j.ngroups = c->ngroups;
+      j.perm = c->d_cperm;
+      j.goff = c->d_goff;
+      j.gnn = c->d_gnn;
+      j.gnf = c->d_gnf;
+      j.ell = c->d_ell;
+      j.cell = c->d.L / c->d.n_box;
+      j.xi2 = c->d.xi * c->d.xi;
+      j.cG = 1.0 / (4.0 * kPi * c->p.eta);
+      j.xs = f ? (const void *)c->d_xs32 : (const void *)c->d_xs;
+      j.mus = f ? (const void *)c->d_mus32 : (const void *)c->d_mus;
+      j.out = c->d_by;
+      pj[p].push_back(j);
+      const WaveArgs w = wave_args(c);
+      void *grid = f ? (void *)(k.grid32 + slot * gsz) : (void *)(k.grid + slot * gsz);
+      void *spec = f ? (void *)(k.spec32 + slot * ssz) : (void *)(k.spec + slot * ssz);
+      sj[p].push_back(SpreadJob{w, f ? (const void *)c->d_xt32 : (const void *)c->d_xt,
+                                f ? (const void *)c->d_mut32 : (const void *)c->d_mut, grid});
+      mj[p].push_back(MultJob{(int)M, c->d.L, c->d.xi, c->d.eta_s, c->d.h * c->d.h / (c->p.eta * c->d.L * c->d.L),
+                              spec});
+      ij[p].push_back(InterpJob{w, f ? (const void *)c->d_xt32 : (const void *)c->d_xt, c->d_tperm, grid, c->d_by});
+    }
+    aj.push_back(AlpertJob{c->geom(), c->d_band_arr, c->d_band, c->d_t1, c->d_by});
+    rj.push_back(RigidJob{c->geom(), c->d_t1, c->d_by});
+    pr.push_back(PrecondJob{c->geom(), c->mats(), c->bt, c->mlp_on ? c->d_dN : nullptr, c->d_bx, c->d_t1});
+    b_nodes.push_back(b_nodes.back() + (c->N + 255) / 256);
+    b_pair.push_back(b_pair.back() + (c->ngroups * 64 + 255) / 256);
+    b_tiles.push_back(b_tiles.back() + c->nts * c->nts);
+    b_spec.push_back(b_spec.back() + (int)((M * (M / 2 + 1) + 255) / 256));
+    b_bod.push_back(b_bod.back() + (c->n + 3) / 4);
+    b_prec.push_back(b_prec.back() + c->bt.ntile);
+    lds = std::max(lds, c->bt.lds_bytes);
+    for (size_t x = 0; x < c->ntot; x += kChunk) {
+      chunks.push_back(make_int2((int)x, (int)std::min(c->ntot, x + kChunk)));
+      chunk_sys.push_back(q);
+    }
+    sys_chunk.push_back((int)chunks.size());
+    V.push_back(c->d_V);
+    bx.push_back(c->d_bx);
+    by.push_back(c->d_by);
+    t1.push_back(c->d_t1);
+    bb.push_back(c->d_b);
+    x2.push_back(c->d_x2);
+    r.push_back(c->d_r);
+    irr.push_back(c->d_irr);
+    ird.push_back(c->d_ird);
+    ld.push_back(c->ntot);
+  }
+  // pack: sizes first
+  size_t off = 0;
+  char *null = nullptr;
+  auto plan_layout = [&](char *base) {
+    off = 0;
+    for (int p = 0; p < 2; ++p) {
+      T.gcell[p] = carve<GatherJob>(base, off, S);
+      T.gtile[p] = carve<GatherJob>(base, off, S);
+      T.pair[p] = carve<PairJob>(base, off, S);
+      T.spr[p] = carve<SpreadJob>(base, off, S);
+      T.mul[p] = carve<MultJob>(base, off, S);
+      T.itp[p] = carve<InterpJob>(base, off, S);
+    }
+    T.alp = carve<AlpertJob>(base, off, S);
+    T.rig = carve<RigidJob>(base, off, S);
+    T.pre = carve<PrecondJob>(base, off, S);
+    T.bg_nodes.begin = carve<int>(base, off, S + 1);
+    T.bg_pair.begin = carve<int>(base, off, S + 1);
+    T.bg_tiles.begin = carve<int>(base, off, S + 1);
+    T.bg_spec.begin = carve<int>(base, off, S + 1);
+    T.bg_bodies4.begin = carve<int>(base, off, S + 1);
+    T.bg_prec.begin = carve<int>(base, off, S + 1);
+    T.seg.chunk = carve<int2>(base, off, chunks.size());
+    T.seg.chunk_sys = carve<int>(base, off, chunks.size());
+    T.seg.sys_chunk = carve<int>(base, off, S + 1);
+    T.V = carve<const double *>(base, off, S);
+    T.bx = carve<const double *>(base, off, S);
+    T.by = carve<const double *>(base, off, S);
+    T.t1 = carve<const double *>(base, off, S);
+    T.b = carve<const double *>(base, off, S);
+    T.x2 = carve<const double *>(base, off, S);
+    T.r = carve<const double *>(base, off, S);
+    T.irr = carve<const double *>(base, off, S);
+    T.ird = carve<const double *>(base, off, S);
+    T.ld = carve<size_t>(base, off, S);
+    T.ones = carve<double>(base, off, S);
+    T.zeros = carve<double>(base, off, S);
+    T.mones = carve<double>(base, off, S);
+  };
+  plan_layout(null);
+  const size_t bytes = off + 256;
+  if (bytes > T.cap) {
+    if (T.dev) hipFree(T.dev);
+    T.dev = nullptr;
+    EHIP(E, hipMalloc((void **)&T.dev, bytes));
+    T.cap = bytes;
+  }
+  std::vector<char> host(bytes, 0);
+  plan_layout(host.data());
+  auto put = [&](const void *dst_in_host, const void *src, size_t n) {
+    std::memcpy(const_cast<void *>(dst_in_host), src, n);
+  };
+  for (int p = 0; p < 2; ++p) {
+    put(T.gcell[p], gc[p].data(), S * sizeof(GatherJob));
+    put(T.gtile[p], gt[p].data(), S * sizeof(GatherJob));
+    put(T.pair[p], pj[p].data(), S * sizeof(PairJob));
+    put(T.spr[p], sj[p].data(), S * sizeof(SpreadJob));
+    put(T.mul[p], mj[p].data(), S * sizeof(MultJob));
+    put(T.itp[p], ij[p].data(), S * sizeof(InterpJob));
+  }
+  put(T.alp, aj.data(), S * sizeof(AlpertJob));
+  put(T.rig, rj.data(), S * sizeof(RigidJob));
+  put(T.pre, pr.data(), S * sizeof(PrecondJob));
+  put(T.bg_nodes.begin, b_nodes.data(), (S + 1) * sizeof(int));
+  put(T.bg_pair.begin, b_pair.data(), (S + 1) * sizeof(int));
+  put(T.bg_tiles.begin, b_tiles.data(), (S + 1) * sizeof(int));
+  put(T.bg_spec.begin, b_spec.data(), (S + 1) * sizeof(int));
+  put(T.bg_bodies4.begin, b_bod.data(), (S + 1) * sizeof(int));
+  put(T.bg_prec.begin, b_prec.data(), (S + 1) * sizeof(int));
+  put(T.seg.chunk, chunks.data(), chunks.size() * sizeof(int2));
+  put(T.seg.chunk_sys, chunk_sys.data(), chunks.size() * sizeof(int));
+  put(T.seg.sys_chunk, sys_chunk.data(), (S + 1) * sizeof(int));
+  put(T.V, V.data(), S * sizeof(double *));
+  put(T.bx, bx.data(), S * sizeof(double *));
+  put(T.by, by.data(), S * sizeof(double *));
+  put(T.t1, t1.data(), S * sizeof(double *));
+  put(T.b, bb.data(), S * sizeof(double *));
+  put(T.x2, x2.data(), S * sizeof(double *));
+  put(T.r, r.data(), S * sizeof(double *));
+  put(T.irr, irr.data(), S * sizeof(double *));
+  put(T.ird, ird.data(), S * sizeof(double *));
+  put(T.ld, ld.data(), S * sizeof(size_t));
+  std::vector<double> ones(S, 1.0), zeros(S, 0.0), mones(S, -1.0);
+  put(T.ones, ones.data(), S * sizeof(double));
+  put(T.zeros, zeros.data(), S * sizeof(double));
+  put(T.mones, mones.data(), S * sizeof(double));
+  EHIP(E, hipMemcpyAsync(T.dev, host.data(), bytes, hipMemcpyHostToDevice, E->stream));
+  EHIP(E, hipStreamSynchronize(E->stream));  // the host image is released on return
+  // rebase the layout onto the device allocation
+  plan_layout(T.dev);
+  T.S = S;
+  T.list = list;
+  T.bg_nodes.S = T.bg_pair.S = T.bg_tiles.S = T.bg_spec.S = T.bg_bodies4.S = T.bg_prec.S = S;
+  T.bg_nodes.nblocks = b_nodes.back();
+  T.bg_pair.nblocks = b_pair.back();
+  T.bg_tiles.nblocks = b_tiles.back();
+  T.bg_spec.nblocks = b_spec.back();
+  T.bg_bodies4.nblocks = b_bod.back();
+  T.bg_prec.nblocks = b_prec.back();
+  T.prec_lds = lds;
+  T.seg.nchunk = (int)chunks.size();
+  T.seg.S = S;
+  return FBIM_OK;
+}
+
+fbim_status ensure_batch_buffers(BatchEngine *E, fbim_ctx *c) {
+  if (!c->have_bodies) return efail(E, FBIM_EINVAL, "a batch system has no bodies");
+  if (c->mixed != E->mixed) return efail(E, FBIM_EINVAL, "batch systems must share the precision");
+  if (c->cap_bxy != c->ntot) {
+    EHIP(E, dalloc(c->d_bx, c->ntot));
+    EHIP(E, dalloc(c->d_by, c->ntot));
+    c->cap_bxy = c->ntot;
+  }
+  return FBIM_OK;
+}
+
+// (re)build everything for the engine's current system list
+fbim_status engine_prepare(BatchEngine *E) {
+  if (E->sys.empty()) return efail(E, FBIM_EINVAL, "empty batch");
+  E->mixed = E->sys[0]->mixed;
+  for (auto *c : E->sys) {
+    c->stream = E->stream;
+    if (c->einfo) rocfft_execution_info_set_stream(c->einfo, E->stream);
+    EST(ensure_batch_buffers(E, c));
+  }
+  EST(setup_classes(E));
+  std::vector<int> all(E->sys.size());
+  for (size_t i = 0; i < all.size(); ++i) all[i] = (int)i;
+  const void *old = E->full.dev;
+  const int oldS = E->full.S;
+  const int oldb[3] = {E->full.bg_pair.nblocks, E->full.bg_tiles.nblocks, E->full.bg_prec.nblocks};
+  EST(build_tables(E, all, E->full));
+  E->sub.list.clear();
+  // per-system scalar blocks (sized for the full list) and reduction partials
+  E->hs = 0;
+  for (auto *c : E->sys) E->hs = std::max(E->hs, (int)c->capV + 2);
+  const size_t need = E->sys.size() * (3 * (size_t)E->hs + 8);
+  if (need > E->sc_cap) {
+    EHIP(E, dalloc(E->d_sc, need));
+    E->sc_cap = need;
+  }
+  const size_t pneed = (size_t)std::max(E->full.seg.nchunk, 1) * (E->hs + 1);
+  if (pneed > E->partial_cap) {
+    EHIP(E, dalloc(E->d_partial, pneed));
+    E->partial_cap = pneed;
+  }
+  const bool same = old == E->full.dev && oldS == E->full.S && oldb[0] == E->full.bg_pair.nblocks &&
+                    oldb[1] == E->full.bg_tiles.nblocks && oldb[2] == E->full.bg_prec.nblocks;
+  if (!same) destroy_graphs(E);
+  return FBIM_OK;
+}
+
+Tables &tables_for(BatchEngine *E, const std::vector<int> &list, fbim_status &st) {
+  st = FBIM_OK;
+  if (list == E->full.list) return E->full;
+  if (list != E->sub.list) st = build_tables(E, list, E->sub);
+  return E->sub;
+}
+
+// ---------------------------------------------------------------- batched operators
+// y = P^-1 bx for every system of T (into t1)
+fbim_status run_precond(BatchEngine *E, Tables &T) {
+  Timer t(E->sys[0], "precond");
+  EHIP(E, launch_precond_batch(T.pre, T.bg_prec, T.prec_lds, E->stream));
+  return FBIM_OK;
+}
+
+// by = M t1 (and the rigid-body rows of the saddle operator when saddle != 0)
+fbim_status run_operator(BatchEngine *E, Tables &T, bool f32, bool saddle) {
+  hipStream_t s = E->stream;
+  fbim_ctx *tc = E->sys[0];
+  const int p = f32 ? 1 : 0;
+  EHIP(E, launch_gather2_batch(T.gcell[p], T.bg_nodes, p, s));
+  {
+    Timer t(tc, "pair");
+    EHIP(E, launch_pair_batch(T.pair[p], T.bg_pair, p, tc->d_e1tab, tc->d_e1tab32, s));
+  }
+  {
+    Timer t(tc, "alpert");
+    EHIP(E, launch_alpert_batch(T.alp, T.bg_nodes, s));
+  }
+  EHIP(E, launch_gather2_batch(T.gtile[p], T.bg_nodes, p, s));
+  {
+    Timer t(tc, "spread");
+    EHIP(E, launch_spread_batch(T.spr[p], T.bg_tiles, p, s));
+  }
+  {
+    Timer t(tc, "fft");
+    for (auto &k : E->classes) {
+      void *in[1] = {f32 ? (void *)k.grid32 : (void *)k.grid}, *o[1] = {f32 ? (void *)k.spec32 : (void *)k.spec};
+      EFFT(E, rocfft_execute(f32 ? k.fwd32 : k.fwd, in, o, E->einfo));
+    }
+  }
+  {
+    Timer t(tc, "multiplier");
+    EHIP(E, launch_multiplier_batch(T.mul[p], T.bg_spec, p, 0, s));
+  }
+  {
+    Timer t(tc, "fft");
+    for (auto &k : E->classes) {
+      void *in[1] = {f32 ? (void *)k.spec32 : (void *)k.spec}, *o[1] = {f32 ? (void *)k.grid32 : (void *)k.grid};
+      EFFT(E, rocfft_execute(f32 ? k.inv32 : k.inv, in, o, E->einfo));
+    }
+  }
+  {
+    Timer t(tc, "interp");
+    EHIP(E, launch_interp_batch(T.itp[p], T.bg_tiles, p, s));
+  }
+  if (saddle) EHIP(E, launch_rigid_batch(T.rig, T.bg_nodes, T.bg_bodies4, s));
+  return FBIM_OK;
+}
+
+// t1 = P^-1 bx, by = A t1 for every system of T; replayed from a HIP graph for
+// the full system list when enabled
+fbim_status run_precond_saddle(BatchEngine *E, Tables &T, bool f32) {
+  const bool graph = (E->flags & FBIM_BATCH_GRAPH) && &T == &E->full && !E->sys[0]->timing;
+  if (!graph) {
+    EST(run_precond(E, T));
+    return run_operator(E, T, f32, true);
+  }
+  const int gi = f32 ? 1 : 0;
+  if (!E->gexec[gi]) {
+    if (!E->cap_stream) EHIP(E, hipStreamCreateWithFlags(&E->cap_stream, hipStreamNonBlocking));
+    // capture on the private stream (nothing runs during capture), then launch on ours
+    EHIP(E, hipStreamSynchronize(E->stream));
+    hipStream_t user = E->stream;
+    E->stream = E->cap_stream;
+    if (E->einfo) rocfft_execution_info_set_stream(E->einfo, E->stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(E->stream, hipStreamCaptureModeThreadLocal);
+    fbim_status st = e == hipSuccess ? run_precond(E, T) : FBIM_EDEVICE;
+    if (st == FBIM_OK) st = run_operator(E, T, f32, true);
+    const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(E->stream, &g) : e;
+    E->stream = user;
+    if (E->einfo) rocfft_execution_info_set_stream(E->einfo, E->stream);
+    if (st != FBIM_OK) {
+      if (g) hipGraphDestroy(g);
+      return st == FBIM_EDEVICE && e != hipSuccess ? efail(E, st, "hipStreamBeginCapture failed") : st;
+    }
+    EHIP(E, e2);
+    // memset nodes replay unreliably here: keep such a graph out and run eagerly
+    size_t nn = 0;
+    EHIP(E, hipGraphGetNodes(g, nullptr, &nn));
+    std::vector<hipGraphNode_t> nodes(nn);
+    if (nn) EHIP(E, hipGraphGetNodes(g, nodes.data(), &nn));
+    bool memset_node = false;
+    for (auto nd : nodes) {
+      hipGraphNodeType ty;
+      if (hipGraphNodeGetType(nd, &ty) == hipSuccess && ty == hipGraphNodeTypeMemset) memset_node = true;
+    }
+    if (memset_node) {
+      hipGraphDestroy(g);
+      E->flags &= ~FBIM_BATCH_GRAPH;
+      EST(run_precond(E, T));
+      return run_operator(E, T, f32, true);
+    }
+    e = hipGraphInstantiate(&E->gexec[gi], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    EHIP(E, e);
+  }
+  EHIP(E, hipGraphLaunch(E->gexec[gi], E->stream));
+  return FBIM_OK;
+}
+
+// ---------------------------------------------------------------- Krylov helpers
+VecRef vref(const double **base, int col = 0, const size_t *ld = nullptr) {
+  VecRef v;
+  v.base = base;
+  v.ld = ld;
+  v.col = col;
+  return v;
+}
+
+fbim_status seg_axpby(BatchEngine *E, Tables &T, VecRef x, VecRef y, const double *a, const double *b) {
+  Timer t(E->sys[0], "blas");
+  EHIP(E, launch_seg_axpby(T.seg, x, y, a, b, E->stream));
+  return FBIM_OK;
+}
+
+struct Scal {
+  double *a, *h, *h2, *nrm, *flag, *c;
+};
+// per-system scalar blocks for a table of S systems (table order)
+Scal scalars(BatchEngine *E, int S) {
+  Scal q;
+  double *p = E->d_sc;
+  q.a = p;
+  p += S;
+  q.h = p;
+  p += (size_t)S * E->hs;
+  q.h2 = p;
+  p += (size_t)S * E->hs;
+  q.nrm = p;
+  p += (size_t)S * 4;
+  q.flag = p;
+  p += S;
+  q.c = p;
+  return q;
+}
+
+fbim_status orth_pass_b(BatchEngine *E, Tables &T, int mode, int k, const double **w, const double *h,
+                        const double *cond, double *out, int ostride) {
+  Timer t(E->sys[0], "blas");
+  OrthArgs a;
+  a.seg = T.seg;
+  a.V = nullptr;
+  a.ld = 0;
+  a.k = k;
+  a.w = nullptr;
+  a.Vs = T.V;
+  a.ws = const_cast<double *const *>(w);
+  a.lds = T.ld;
+  a.h = h;
+  a.hstride = E->hs;
+  a.cond = cond;
+  a.partial = E->d_partial;
+  a.out = out;
+  a.ostride = ostride;
+  EHIP(E, launch_orth(mode, a, E->stream));
+  return FBIM_OK;
+}
+
+// squared norms of w_s, host, table order
+fbim_status norms_b(BatchEngine *E, Tables &T, const double **w, std::vector<double> &nrm2) {
+  Scal q = scalars(E, T.S);
+  EST(orth_pass_b(E, T, 0, 0, w, nullptr, nullptr, q.nrm, 4));
+  std::vector<double> h((size_t)T.S * 4);
+  EHIP(E, hipMemcpyAsync(h.data(), q.nrm, h.size() * sizeof(double), hipMemcpyDeviceToHost, E->stream));
+  EHIP(E, hipStreamSynchronize(E->stream));
+  nrm2.resize(T.S);
+  for (int i = 0; i < T.S; ++i) nrm2[i] = h[(size_t)i * 4];
+  return FBIM_OK;
+}
+
+fbim_status upload_a(BatchEngine *E, const std::vector<double> &a) {
+  EHIP(E, hipMemcpyAsync(E->d_sc, a.data(), a.size() * sizeof(double), hipMemcpyHostToDevice, E->stream));
+  EHIP(E, hipStreamSynchronize(E->stream));  // the host vector may be released on return
+  return FBIM_OK;
+}
+
+// CGS2 (or DGKS-selective) orthogonalisation of by_s against V_s[:, 0..k) for
+// every system of T; h[q][0..k) (host) and hn[q] = ||by_s|| afterwards
+fbim_status orthogonalise_b(BatchEngine *E, Tables &T, int k, std::vector<std::vector<double>> &h,
+                            std::vector<double> &hn) {
+  const int S = T.S, hs = E->hs;
+  Scal q = scalars(E, S);
+  const bool selective = (E->sys[0]->p.flags & FBIM_FLAG_SELECTIVE_REORTH) != 0;
+  const bool fused = k <= kOrthFused;
+  EST(orth_pass_b(E, T, 0, k, T.by, nullptr, nullptr, q.h, hs));
+  if (fused) {
+    EST(orth_pass_b(E, T, 1, k, T.by, q.h, nullptr, q.h2, hs));
+    if (selective)
+      EHIP(E, launch_need_second_pass(S, q.h2 + k, hs, q.h + k, hs, q.flag, E->stream));
+    else
+      EHIP(E, launch_fill((size_t)S, 1.0, q.flag, E->stream));
+    EST(orth_pass_b(E, T, 2, k, T.by, q.h2, q.flag, q.nrm + 2, 4));
+  } else {
+    EST(orth_pass_b(E, T, 2, k, T.by, q.h, nullptr, q.nrm, 4));
+    if (selective)
+      EHIP(E, launch_need_second_pass(S, q.nrm, 4, q.h + k, hs, q.flag, E->stream));
+    else
+      EHIP(E, launch_fill((size_t)S, 1.0, q.flag, E->stream));
+    EST(orth_pass_b(E, T, 0, k, T.by, nullptr, q.flag, q.h2, hs));
+    EST(orth_pass_b(E, T, 2, k, T.by, q.h2, q.flag, q.nrm + 2, 4));
+  }
+  const size_t cnt = (size_t)S * (2 * hs + 5);  // h, h2, nrm, flag are contiguous
+  std::vector<double> buf(cnt);
+  EHIP(E, hipMemcpyAsync(buf.data(), q.h, cnt * sizeof(double), hipMemcpyDeviceToHost, E->stream));
+  EHIP(E, hipStreamSynchronize(E->stream));
+  const double *H = buf.data(), *H2 = H + (size_t)S * hs, *NR = H2 + (size_t)S * hs, *FL = NR + (size_t)S * 4;
+  h.assign(S, std::vector<double>(k));
+  hn.assign(S, 0.0);
+  for (int i = 0; i < S; ++i) {
+    for (int j = 0; j < k; ++j) h[i][j] = H[(size_t)i * hs + j];
+    double after;
+    if (FL[i] != 0.0) {
+      for (int j = 0; j < k; ++j) h[i][j] += H2[(size_t)i * hs + j];
+      after = NR[(size_t)i * 4 + 2];
+    } else {
+      after = fused ? H2[(size_t)i * hs + k] : NR[(size_t)i * 4];
+    }
+    hn[i] = std::sqrt(std::max(after, 0.0));
+  }
+  return FBIM_OK;
+}
+
+std::vector<int> pick(const std::vector<int> &v, const std::vector<int> &pos) {
+  std::vector<int> out;
+  for (int p : pos) out.push_back(v[p]);
+  return out;
+}
+
+// Lockstep right-preconditioned restarted GMRES of the saddle systems `sysl`
+// (engine indices): A_s x_s = rhs_s, rhs / x = (d_b, d_x2), or (d_irr, d_ird)
+// when `ir`.  Every system keeps its own Krylov space, Hessenberg matrix and
+// stopping test ||rhs - A x|| <= tol_s ||rhs||, and leaves the launches once
+// it has converged.  Outputs per system (sysl order).
+fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool f32, const std::vector<double> &tol,
+                    const std::vector<int> &maxit, std::vector<int> &iters, std::vector<double> &relres,
+                    std::vector<int> &status) {
+  const int S0 = (int)sysl.size();
+  iters.assign(S0, 0);
+  relres.assign(S0, 0.0);
+  status.assign(S0, FBIM_OK);
+  int m = 1 << 30;
+  for (int i : sysl) m = std::min(m, E->sys[i]->restart);
+  fbim_status st;
+  auto rhs = [&](Tables &T) { return ir ? T.irr : T.b; };
+  auto sol = [&](Tables &T) { return ir ? T.ird : T.x2; };
+  Tables *T = &tables_for(E, sysl, st);
+  EST(st);
+  std::vector<double> nb2;
+  EST(norms_b(E, *T, rhs(*T), nb2));
+  std::vector<double> nb(S0);
+  for (int i = 0; i < S0; ++i) nb[i] = std::sqrt(std::max(nb2[i], 0.0));
+  EST(seg_axpby(E, *T, vref(sol(*T)), vref(sol(*T)), T->zeros, T->zeros));  // x = 0
+  std::vector<int> running;  // positions in sysl
+  for (int i = 0; i < S0; ++i)
+    if (nb[i] > 0.0) running.push_back(i);
+  // per-system Arnoldi state
+  std::vector<std::vector<double>> H(S0), g(S0), cs(S0), sn(S0);
+  bool first = true;
+  while (!running.empty()) {
+    T = &tables_for(E, pick(sysl, running), st);
+    EST(st);
+    // r = rhs - A x
+    EST(seg_axpby(E, *T, vref(rhs(*T)), vref(T->r), T->ones, T->zeros));
+    if (!first) {
+      EST(seg_axpby(E, *T, vref(sol(*T)), vref(T->t1), T->ones, T->zeros));
+      EST(run_operator(E, *T, f32, true));
+      EST(seg_axpby(E, *T, vref(T->by), vref(T->r), T->mones, T->ones));
+    }
+    first = false;
+    std::vector<double> r2;
+    EST(norms_b(E, *T, T->r, r2));
+    std::vector<int> cyc;  // positions in sysl that iterate in this cycle
+    std::vector<double> inv;
+    for (size_t q = 0; q < running.size(); ++q) {
+      const int i = running[q];
+      const double beta = std::sqrt(std::max(r2[q], 0.0));
+      relres[i] = beta / nb[i];
+      if (relres[i] <= tol[i]) continue;
+      if (iters[i] >= maxit[i]) {
+        status[i] = FBIM_ENOCONV;
+        continue;
+      }
+      cyc.push_back(i);
+      inv.push_back(1.0 / beta);
+      H[i].assign((size_t)(m + 1) * m, 0.0);
+      g[i].assign(m + 1, 0.0);
+      cs[i].assign(m, 0.0);
+      sn[i].assign(m, 0.0);
+      g[i][0] = beta;
+    }
+    if (cyc.empty()) break;
+    T = &tables_for(E, pick(sysl, cyc), st);
+    EST(st);
+    EST(upload_a(E, inv));
+    EST(seg_axpby(E, *T, vref(T->r), vref(T->V, 0, T->ld), scalars(E, T->S).a, T->zeros));  // V_0 = r / beta
+    std::vector<int> jend(S0, 0);
+    std::vector<int> act = cyc;
+    for (int j = 0; j < m && !act.empty(); ++j) {
+      T = &tables_for(E, pick(sysl, act), st);
+      EST(st);
+      EST(seg_axpby(E, *T, vref(T->V, j, T->ld), vref(T->bx), T->ones, T->zeros));
+      EST(run_precond_saddle(E, *T, f32));
+      std::vector<std::vector<double>> hc;
+      std::vector<double> hn;
+      EST(orthogonalise_b(E, *T, j + 1, hc, hn));
+      std::vector<double> scale(act.size());
+      std::vector<int> next;
+      for (size_t q = 0; q < act.size(); ++q) {
+        const int i = act[q];
+        std::vector<double> col(j + 2);
+        for (int r = 0; r <= j; ++r) col[r] = hc[q][r];
+        col[j + 1] = hn[q];
+        for (int r = 0; r < j; ++r) {  // previous rotations
+          const double t1 = cs[i][r] * col[r] + sn[i][r] * col[r + 1];
+          col[r + 1] = -sn[i][r] * col[r] + cs[i][r] * col[r + 1];
+          col[r] = t1;
+        }
+        const double den = std::hypot(col[j], col[j + 1]);
+        cs[i][j] = den > 0 ? col[j] / den : 1.0;
+        sn[i][j] = den > 0 ? col[j + 1] / den : 0.0;
+        col[j] = den;
+        g[i][j + 1] = -sn[i][j] * g[i][j];
+        g[i][j] = cs[i][j] * g[i][j];
+        for (int r = 0; r <= j; ++r) H[i][(size_t)r * m + j] = col[r];
+        ++iters[i];
+        jend[i] = j + 1;
+        scale[q] = hn[q] > 0 ? 1.0 / hn[q] : 0.0;
+        const bool done = std::fabs(g[i][j + 1]) <= tol[i] * nb[i] || iters[i] >= maxit[i] || hn[q] == 0.0;
+        if (!done) next.push_back(i);
+      }
+      EST(upload_a(E, scale));
+      EST(seg_axpby(E, *T, vref(T->by), vref(T->V, j + 1, T->ld), scalars(E, T->S).a, T->zeros));
+      act = next;
+    }
+    // x += P^-1 V y for the systems of this cycle
+    T = &tables_for(E, pick(sysl, cyc), st);
+    EST(st);
+    int kmax = 0;
+    for (int i : cyc) kmax = std::max(kmax, jend[i]);
+    std::vector<double> c((size_t)T->S * E->hs, 0.0);
+    for (size_t q = 0; q < cyc.size(); ++q) {
+      const int i = cyc[q], je = jend[i];
+      std::vector<double> y(je);
+      for (int r = je - 1; r >= 0; --r) {
+        double acc = g[i][r];
+        for (int k2 = r + 1; k2 < je; ++k2) acc -= H[i][(size_t)r * m + k2] * y[k2];
+        y[r] = acc / H[i][(size_t)r * m + r];
+      }
+      for (int r = 0; r < je; ++r) c[q * E->hs + r] = y[r];
+    }
+    Scal sq = scalars(E, T->S);
+    EHIP(E, hipMemcpyAsync(sq.c, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, E->stream));
+    {
+      Timer t(E->sys[0], "blas");
+      EHIP(E, launch_seg_Vc(T->seg, vref(T->V, 0, T->ld), kmax, sq.c, E->hs, vref(T->bx), E->stream));
+    }
+    EHIP(E, hipStreamSynchronize(E->stream));  // c is released on return
+    EST(run_precond(E, *T));
+    EST(seg_axpby(E, *T, vref(T->t1), vref(sol(*T)), T->ones, T->ones));
+    running = cyc;
+  }
+  return FBIM_OK;
+}
+
+// Solve the saddle systems `sysl` with RHS d_b into d_x2.  FP64 engines: lockstep
+// GMRES.  Mixed engines: iterative refinement as for one system -- FP64
+// residuals, corrections by lockstep GMRES on the FP32 operator to 1e-3.
+fbim_status solve_b(BatchEngine *E, const std::vector<int> &sysl, std::vector<int> &iters, std::vector<double> &res,
+                    std::vector<int> &status) {
+  const int S0 = (int)sysl.size();
+  std::vector<double> tol(S0);
+  std::vector<int> maxit(S0);
+  for (int i = 0; i < S0; ++i) {
+    tol[i] = E->sys[sysl[i]]->p.tol_gmres;
+    maxit[i] = E->sys[sysl[i]]->gmres_max;
+  }
+  if (!E->mixed) return gmres_b(E, sysl, false, false, tol, maxit, iters, res, status);
+  fbim_status st;
+  iters.assign(S0, 0);
+  res.assign(S0, 1.0);
+  status.assign(S0, FBIM_ENOCONV);
+  Tables *T = &tables_for(E, sysl, st);
+  EST(st);
+  std::vector<double> nb2;
+  EST(norms_b(E, *T, T->b, nb2));
+  EST(seg_axpby(E, *T, vref(T->x2), vref(T->x2), T->zeros, T->zeros));
+  EST(seg_axpby(E, *T, vref(T->b), vref(T->irr), T->ones, T->zeros));
+  std::vector<int> running;
+  for (int i = 0; i < S0; ++i) {
+    if (nb2[i] > 0.0) {
+      running.push_back(i);
+    } else {
+      res[i] = 0.0;
+      status[i] = FBIM_OK;
+    }
+  }
+  for (int outer = 0; outer < 20 && !running.empty(); ++outer) {
+    std::vector<int> sl = pick(sysl, running);
+    std::vector<double> itol(running.size(), 1e-3);
+    std::vector<int> imax;
+    for (int i : running) imax.push_back(std::max(1, maxit[i] - iters[i]));
+    std::vector<int> it, ist;
+    std::vector<double> ir;
+    EST(gmres_b(E, sl, true, true, itol, imax, it, ir, ist));
+    T = &tables_for(E, sl, st);
+    EST(st);
+    for (size_t q = 0; q < running.size(); ++q) iters[running[q]] += it[q];
+    EST(seg_axpby(E, *T, vref(T->ird), vref(T->x2), T->ones, T->ones));
+    // FP64 residual of the refined solutions
+    EST(seg_axpby(E, *T, vref(T->x2), vref(T->t1), T->ones, T->zeros));
+    EST(run_operator(E, *T, false, true));
+    EST(seg_axpby(E, *T, vref(T->b), vref(T->irr), T->ones, T->zeros));
+    EST(seg_axpby(E, *T, vref(T->by), vref(T->irr), T->mones, T->ones));
+    std::vector<double> r2;
+    EST(norms_b(E, *T, T->irr, r2));
+    std::vector<int> next;
+    for (size_t q = 0; q < running.size(); ++q) {
+      const int i = running[q];
+      res[i] = std::sqrt(std::max(r2[q], 0.0) / nb2[i]);
+      if (res[i] <= tol[i]) {
+        status[i] = FBIM_OK;
+      } else if (iters[i] < maxit[i]) {
+        next.push_back(i);
+      }
+    }
+    running = next;
+  }
+  return FBIM_OK;
+}
+
+// b_s = -[slip_s; F_s] for one system
+fbim_status rhs_one(fbim_ctx *c, const double *F, const double *slip) {
+  const size_t twoN = 2 * (size_t)c->N;
+  hipStream_t s = c->stream;
+  if (slip)
+    HIPCHK(c, launch_axpby(twoN, -1.0, slip, 0.0, c->d_b, s));
+  else
+    HIPCHK(c, launch_fill(twoN, 0.0, c->d_b, s));
+  HIPCHK(c, launch_axpby(3 * (size_t)c->n, -1.0, F, 0.0, c->d_b + twoN, s));
+  return FBIM_OK;
+}
+
+void engine_destroy(BatchEngine *E) {
+  if (!E) return;
+  destroy_graphs(E);
+  if (E->cap_stream) hipStreamDestroy(E->cap_stream);
+  destroy_classes(E);
+  if (E->einfo) rocfft_execution_info_destroy(E->einfo);
+  if (E->work) hipFree(E->work);
+  if (E->full.dev) hipFree(E->full.dev);
+  if (E->sub.dev) hipFree(E->sub.dev);
+  dfree(E->d_sc);
+  dfree(E->d_partial);
+  delete E;
+}
+
+fbim_status copy_out(BatchEngine *E, fbim_ctx *c, double *U) {
+  EHIP(E, hipMemcpyAsync(U, c->d_x2 + 2 * (size_t)c->N, 3 * (size_t)c->n * sizeof(double), hipMemcpyDeviceToDevice,
+                         E->stream));
+  return FBIM_OK;
+}
+
+// a copy of c's shapes and parameters (for the RFD configurations)
+fbim_status clone_ctx(fbim_ctx *c, fbim_ctx **out) {
+  fbim_params p = c->p;
+  fbim_status st = fbim_create(&p, out);
+  if (st != FBIM_OK) return fail(c, st, "creating an RFD configuration failed");
+  fbim_set_stream(*out, c->stream);
+  for (auto &sh : c->shapes) {
+    int32_t id = 0;
+    st = fbim_add_shape(*out, sh.h.n_p, sh.h.ref_xy.data(), &id);
+    if (st != FBIM_OK && st != FBIM_WACCURACY) return fail(c, st, fbim_last_error(*out));
+  }
+  return FBIM_OK;
+}
+
+}  // namespace
+
+BatchEngine *engine_new() { return new BatchEngine(); }
+void engine_delete(BatchEngine *E) { engine_destroy(E); }
+const char *engine_error(const BatchEngine *E) { return E ? E->err.c_str() : ""; }
+void engine_set_stream(BatchEngine *E, hipStream_t s) {
+  if (E->stream != s) destroy_graphs(E);
+  E->stream = s;
+  if (E->einfo) rocfft_execution_info_set_stream(E->einfo, s);
+}
+
+// Batched EM-RFD solves of a list of systems: for member i, its RFD copies are
+// rfd[0] (at Q + delta/2 Wt) and rfd[1] (at Q - delta/2 Wt).  U0 = N(Q) F +
+// slip response, U+ / U- = N(Q +- delta/2 Wt) Wt, all in one lockstep solve.
+fbim_status em_rfd_batch(BatchEngine *E, const std::vector<fbim_ctx *> &mem, double dt, double delta,
+                         const double *const *F, const double *const *W_r, const double *const *W_grid,
+                         const double *const *W_tilde, double *const *dQ, int32_t apply, fbim_info *info) {
+  const int S = (int)mem.size();
+  std::vector<fbim_info> inf(S);
+  std::vector<std::vector<double>> q0(S), th0(S), wt(S);
+  fbim_status worst = FBIM_OK;
+  for (int i = 0; i < S; ++i) {
+    fbim_ctx *c = mem[i];
+    std::memset(&inf[i], 0, sizeof(fbim_info));
+    // slip of the Brownian velocity (Lanczos + random field) into d_w
+    fbim_status st = brownian_slip(c, dt, W_r[i], W_grid[i], c->d_w, &inf[i]);
+    if (st != FBIM_OK && st != FBIM_ENOCONV) return efail(E, st, c->err);
+    if (st != FBIM_OK) worst = st;
+    for (int k = 0; k < 2; ++k)
+      if (!c->rfd[k]) {
+        EST(clone_ctx(c, &c->rfd[k]));
+        c->rfd[k]->mlp_on = false;
+      }
+    const int n = c->n;
+    wt[i].resize(3 * (size_t)n);
+    EHIP(E, hipMemcpyAsync(wt[i].data(), W_tilde[i], wt[i].size() * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+    EHIP(E, hipStreamSynchronize(c->stream));
+    q0[i] = c->h_q;
+    th0[i] = c->h_theta;
+    std::vector<double> qs(2 * (size_t)n), ths(n);
+    for (int k = 0; k < 2; ++k) {
+      const double sg = k == 0 ? 0.5 * delta : -0.5 * delta;
+      for (int b = 0; b < n; ++b) {
+        qs[2 * b] = q0[i][2 * b] + sg * wt[i][3 * b];
+        qs[2 * b + 1] = q0[i][2 * b + 1] + sg * wt[i][3 * b + 1];
+        ths[b] = th0[i][b] + sg * wt[i][3 * b + 2];
+      }
+      fbim_ctx *r = c->rfd[k];
+      r->stream = c->stream;
+      st = fbim_set_bodies(r, n, c->h_shape.data(), qs.data(), ths.data());
+      if (st != FBIM_OK) return efail(E, st, fbim_last_error(r));
+    }
+  }
+  // one engine over members and their RFD copies
+  E->sys.clear();
+  for (auto *c : mem) E->sys.push_back(c);
+  for (auto *c : mem) E->sys.push_back(c->rfd[0]);
+  for (auto *c : mem) E->sys.push_back(c->rfd[1]);
+  EST(engine_prepare(E));
+  for (int i = 0; i < S; ++i) {
+    fbim_ctx *c = mem[i];
+    if (rhs_one(c, F[i], c->d_w) != FBIM_OK) return efail(E, FBIM_EDEVICE, c->err);
+    for (int k = 0; k < 2; ++k)
+      if (rhs_one(c->rfd[k], W_tilde[i], nullptr) != FBIM_OK) return efail(E, FBIM_EDEVICE, c->rfd[k]->err);
+  }
+  std::vector<int> all(3 * S);
+  for (int i = 0; i < 3 * S; ++i) all[i] = i;
+  std::vector<int> its, sts;
+  std::vector<double> res;
+  EST(solve_b(E, all, its, res, sts));
+  for (int i = 0; i < S; ++i) {
+    fbim_ctx *c = mem[i];
+    const size_t n3 = 3 * (size_t)c->n, twoN = 2 * (size_t)c->N;
+    hipStream_t s = c->stream;
+    const double *U0 = c->d_x2 + twoN, *Up = c->rfd[0]->d_x2 + twoN, *Um = c->rfd[1]->d_x2 + twoN;
+    EHIP(E, launch_axpby(n3, dt, U0, 0.0, dQ[i], s));
+    EHIP(E, launch_axpby(n3, dt * c->p.kT / delta, Up, 1.0, dQ[i], s));
+    EHIP(E, launch_axpby(n3, -dt * c->p.kT / delta, Um, 1.0, dQ[i], s));
+    for (int k = 0; k < 3; ++k) {
+      const int j = i + k * S;
+      inf[i].gmres_iters += its[j];
+      inf[i].gmres_solves += 1;
+      inf[i].gmres_residual = std::max(inf[i].gmres_residual, res[j]);
+      if (sts[j] != FBIM_OK) worst = (fbim_status)sts[j];
+    }
+    if (apply) {
+      std::vector<double> dq(n3);
+      EHIP(E, hipMemcpyAsync(dq.data(), dQ[i], n3 * sizeof(double), hipMemcpyDeviceToHost, s));
+      EHIP(E, hipStreamSynchronize(s));
+      std::vector<double> qs(2 * (size_t)c->n), ths(c->n);
+      for (int b = 0; b < c->n; ++b) {
+        qs[2 * b] = q0[i][2 * b] + dq[3 * b];
+        qs[2 * b + 1] = q0[i][2 * b + 1] + dq[3 * b + 1];
+        ths[b] = th0[i][b] + dq[3 * b + 2];
+      }
+      const fbim_status st = fbim_set_bodies(c, c->n, c->h_shape.data(), qs.data(), ths.data());
+      if (st != FBIM_OK) return efail(E, st, c->err);
+    }
+    inf[i].status = sts[i];
+  }
+  EHIP(E, hipStreamSynchronize(E->stream));
+  if (info)
+    for (int i = 0; i < S; ++i) info[i] = inf[i];
+  return worst;
+}
+
+}  // namespace fbim
+
+struct fbim_batch {
+  std::vector<fbim_ctx *> mem;
+  fbim::BatchEngine *eng = nullptr, *rfd = nullptr;
+  hipStream_t stream = nullptr;
+  uint32_t flags = 0;
+  std::string err;
+};
+
+namespace {
+fbim_status bfail(fbim_batch *b, fbim_status s, const std::string &m) {
+  if (b) b->err = m;
+  return s;
+}
+fbim_status from_engine(fbim_batch *b, fbim::BatchEngine *E, fbim_status s) {
+  if (s != FBIM_OK) b->err = E->err;
+  return s;
+}
+}  // namespace
+
+extern "C" {
+
+fbim_status fbim_batch_create(int32_t S, const fbim_params *params, fbim_batch **out) {
+  if (S < 1 || !params || !out) return FBIM_EINVAL;
+  *out = nullptr;
+  for (int i = 1; i < S; ++i)
+    if (params[i].precision != params[0].precision) return FBIM_EINVAL;
+  auto *b = new fbim_batch();
+  for (int i = 0; i < S; ++i) {
+    fbim_ctx *c = nullptr;
+    const fbim_status st = fbim_create(&params[i], &c);
+    if (st != FBIM_OK) {
+      fbim_batch_destroy(b);
+      return st;
+    }
+    b->mem.push_back(c);
+  }
+  b->eng = fbim::engine_new();
+  b->rfd = fbim::engine_new();
+  *out = b;
+  return FBIM_OK;
+}
+
+void fbim_batch_destroy(fbim_batch *b) {
+  if (!b) return;
+  fbim::engine_destroy(b->eng);
+  fbim::engine_destroy(b->rfd);
+  for (auto *c : b->mem) fbim_destroy(c);
+  delete b;
+}
+
+const char *fbim_batch_last_error(const fbim_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+fbim_ctx *fbim_batch_member(fbim_batch *b, int32_t s) {
+  if (!b || s < 0 || s >= (int32_t)b->mem.size()) return nullptr;
+  return b->mem[s];
+}
+
+fbim_status fbim_batch_set_stream(fbim_batch *b, void *stream) {
+  if (!b) return FBIM_EINVAL;
+  b->stream = (hipStream_t)stream;
+  for (auto *c : b->mem) {
+    const fbim_status st = fbim_set_stream(c, stream);
+    if (st != FBIM_OK) return bfail(b, st, c->err);
+  }
+  fbim::engine_set_stream(b->eng, b->stream);
+  fbim::engine_set_stream(b->rfd, b->stream);
+  return FBIM_OK;
+}
+
+fbim_status fbim_batch_set_flags(fbim_batch *b, uint32_t flags) {
+  if (!b || (flags & ~FBIM_BATCH_GRAPH)) return bfail(b, FBIM_EINVAL, "unknown batch flag");
+  b->flags = b->eng->flags = b->rfd->flags = flags;
+  return FBIM_OK;
+}
+
+fbim_status fbim_batch_apply_M(fbim_batch *b, const double *const *mu, double *const *out) {
+  if (!b || !mu || !out) return bfail(b, FBIM_EINVAL, "null argument");
+  fbim::BatchEngine *E = b->eng;
+  E->sys = b->mem;
+  fbim_status st = fbim::engine_prepare(E);
+  if (st != FBIM_OK) return from_engine(b, E, st);
+  const int S = (int)b->mem.size();
+  for (int i = 0; i < S; ++i) {
+    fbim_ctx *c = b->mem[i];
+    if (hipMemcpyAsync(c->d_t1, mu[i], 2 * (size_t)c->N * sizeof(double), hipMemcpyDeviceToDevice, E->stream) !=
+        hipSuccess)
+      return bfail(b, FBIM_EDEVICE, "copy of mu failed");
+  }
+  st = fbim::run_operator(E, E->full, E->mixed && b->mem[0]->cur32, false);
+  if (st != FBIM_OK) return from_engine(b, E, st);
+  for (int i = 0; i < S; ++i) {
+    fbim_ctx *c = b->mem[i];
+    if (hipMemcpyAsync(out[i], c->d_by, 2 * (size_t)c->N * sizeof(double), hipMemcpyDeviceToDevice, E->stream) !=
+        hipSuccess)
+      return bfail(b, FBIM_EDEVICE, "copy of the result failed");
+  }
+  return FBIM_OK;
+}
+
+fbim_status fbim_batch_mobility(fbim_batch *b, const double *const *F, const double *const *slip, double *const *U,
+                                fbim_info *info) {
+  if (!b || !F || !U) return bfail(b, FBIM_EINVAL, "null argument");
+  const double t0 = fbim::now_ms();
+  fbim::BatchEngine *E = b->eng;
+  E->sys = b->mem;
+  fbim_status st = fbim::engine_prepare(E);
+  if (st != FBIM_OK) return from_engine(b, E, st);
+  const int S = (int)b->mem.size();
+  for (int i = 0; i < S; ++i)
+    if (fbim::rhs_one(b->mem[i], F[i], slip ? slip[i] : nullptr) != FBIM_OK)
+      return bfail(b, FBIM_EDEVICE, b->mem[i]->err);
+  std::vector<int> all(S), its, sts;
+  std::vector<double> res;
+  for (int i = 0; i < S; ++i) all[i] = i;
+  st = fbim::solve_b(E, all, its, res, sts);
+  if (st != FBIM_OK) return from_engine(b, E, st);
+  fbim_status worst = FBIM_OK;
+  for (int i = 0; i < S; ++i) {
+    st = fbim::copy_out(E, b->mem[i], U[i]);
+    if (st != FBIM_OK) return from_engine(b, E, st);
+    if (sts[i] != FBIM_OK) worst = (fbim_status)sts[i];
+  }
+  if (hipStreamSynchronize(E->stream) != hipSuccess) return bfail(b, FBIM_EDEVICE, "stream synchronisation failed");
+  if (info)
+    for (int i = 0; i < S; ++i) {
+      std::memset(&info[i], 0, sizeof(fbim_info));
+      info[i].gmres_iters = its[i];
+      info[i].gmres_solves = 1;
+      info[i].gmres_residual = res[i];
+      info[i].status = sts[i];
+      info[i].ms_total = fbim::now_ms() - t0;
+    }
+  if (worst != FBIM_OK) b->err = "GMRES iteration limit reached in a batch system";
+  return worst;
+}
+
+fbim_status fbim_batch_step_em_rfd(fbim_batch *b, double dt, double delta, const double *const *F,
+                                   const double *const *W_r, const double *const *W_grid,
+                                   const double *const *W_tilde, double *const *dQ, int32_t apply,
+                                   fbim_info *info) {
+  if (!b || !F || !W_r || !W_grid || !W_tilde || !dQ || !(dt > 0) || !(delta > 0))
+    return bfail(b, FBIM_EINVAL, "invalid arguments");
+  const double t0 = fbim::now_ms();
+  const fbim_status st = fbim::em_rfd_batch(b->rfd, b->mem, dt, delta, F, W_r, W_grid, W_tilde, dQ, apply, info);
+  if (info)
+    for (size_t i = 0; i < b->mem.size(); ++i) info[i].ms_total = fbim::now_ms() - t0;
+  if (st != FBIM_OK) b->err = b->rfd->err;
+  return st;
+}
+
+}  // extern "C"

@@ -1,239 +1,9 @@
 // C ABI of the FBIM library: context, geometry, the single-layer matvec
 // pipeline, GMRES (mobility), Lanczos ((M^(r))^(1/2)), Brownian velocity and
 // the EM-RFD step.  Host code driving the gfx950 kernels and rocFFT.
-#include <hip/hip_runtime.h>
-#include <rocfft/rocfft.h>
+#include "ctx.h"
 
-#include <algorithm>
-#include <chrono>
-#include <cmath>
-#include <cstdio>
-#include <cstring>
-#include <map>
-#include <random>
-#include <string>
-#include <vector>
-
-#include "../../include/fbim.h"
-#include "host_math.h"
-#include "kernels.h"
-
-using namespace fbim;
-
-namespace {
-
-struct ShapeDev {
-  ShapeHost h;
-  double *ref = nullptr, *band = nullptr, *Mp = nullptr, *Pref = nullptr, *Nt = nullptr, *G = nullptr,
-         *Gp = nullptr;
-};
-
-template <class T>
-hipError_t dalloc(T *&p, size_t n) {
-  if (p) {
-    hipFree(p);
-    p = nullptr;
-  }
-  if (n == 0) return hipSuccess;
-  return hipMalloc((void **)&p, n * sizeof(T));
-}
-
-template <class T>
-void dfree(T *&p) {
-  if (p) hipFree(p);
-  p = nullptr;
-}
-
-struct TimedLaunch {
-  hipEvent_t a, b;
-};
-
-bool g_rocfft_ready = false;
-
-}  // namespace
-
-struct fbim_ctx {
-  fbim_params p{};
-  Derived d{};
-  int order = 4, aj = 0, aa = 0;
-  double chi[8]{}, w[8]{};
-  std::string err;
-  hipStream_t stream = nullptr;
-  bool mixed = false;
-  bool cur32 = true;  // in a mixed context: matvecs use the FP32 kernels
-
-  std::vector<ShapeDev> shapes;
-  double **d_ref_arr = nullptr, **d_band_arr = nullptr, **d_Mp_arr = nullptr, **d_Pref_arr = nullptr,
-         **d_Nt_arr = nullptr, **d_G_arr = nullptr, **d_Gp_arr = nullptr;
-  int *d_band = nullptr, *d_np = nullptr;
-  int max_np = 0;
-
-  // geometry
-  int n = 0, N = 0, capN = 0, capn = 0;
-  std::vector<int> h_shape, h_off;
-  std::vector<double> h_q, h_theta;
-  int *d_shape = nullptr, *d_off = nullptr, *d_body = nullptr;
-  // tiles of same-shape bodies for the per-body dense operators
-  BodyTiles bt{};
-  int4 *d_btile = nullptr;
-  int *d_blist = nullptr;
-  double *d_dN = nullptr;  // learned per-body correction of N_ref, [n][6]
-
-  // learned preconditioner correction
-  bool mlp_init = false, mlp_on = false;
-  int mlp_sym = 1, mlp_cap = 0, mlp_t = 0;
-  size_t train_cap = 0;
-  float *d_mw = nullptr, *d_am = nullptr, *d_av = nullptr, *d_g = nullptr;
-  float *d_X = nullptr, *d_H1 = nullptr, *d_H2 = nullptr, *d_Y = nullptr, *d_dY = nullptr, *d_Z2 = nullptr,
-        *d_Z1 = nullptr, *d_ones = nullptr, *d_loss = nullptr;
-  double *d_trF = nullptr, *d_trU = nullptr;
-  double *d_q = nullptr, *d_theta = nullptr, *d_x = nullptr;
-  bool have_bodies = false;
-
-  // cell list
-  int ncell = 0, max_cell = 0, nbatch = 0;
-  int *d_ckey = nullptr, *d_ccount = nullptr, *d_cstart = nullptr, *d_cperm = nullptr, *d_ccursor = nullptr;
-  double *d_xs = nullptr;
-  // tiles
-  int nts = 0, ntile = 0, max_tile = 0;
-  int *d_tkey = nullptr, *d_tcount = nullptr, *d_tstart = nullptr, *d_tperm = nullptr, *d_tcursor = nullptr;
-  double *d_xt = nullptr;
-  int *d_anchor = nullptr;
-  int *d_scal_int = nullptr;  // [0] max count, [1] overlap flag
-  // neighbour lists of the real-space sum
-  int ngroups = 0;
-  size_t ell_cap = 0;
-  int *d_cnt_near = nullptr, *d_cnt_far = nullptr, *d_gnn = nullptr, *d_gnf = nullptr, *d_goff = nullptr,
-      *d_gsize = nullptr, *d_ell = nullptr;
-
-  // matvec scratch
-  double *d_mus = nullptr, *d_mut = nullptr;
-  float *d_xs32 = nullptr, *d_mus32 = nullptr, *d_xt32 = nullptr, *d_mut32 = nullptr;
-  double *d_grid = nullptr, *d_spec = nullptr;
-  float *d_grid32 = nullptr, *d_spec32 = nullptr;
-  rocfft_plan fwd = nullptr, inv = nullptr, fwd32 = nullptr, inv32 = nullptr;
-  rocfft_execution_info einfo = nullptr;
-  void *fft_work = nullptr;
-  size_t fft_work_bytes = 0;
-  double *d_e1tab = nullptr;
-  float *d_e1tab32 = nullptr;
-
-  // Krylov
-  int restart = 100, gmres_max = 1000, lanczos_max = 200;
-  size_t ntot = 0, capV = 0;
-  int kn = -1;
-  double *d_V = nullptr;      // (restart+1) * ntot  (also Lanczos basis)
-  double *d_w = nullptr, *d_t1 = nullptr, *d_t2 = nullptr, *d_b = nullptr, *d_x2 = nullptr, *d_r = nullptr;
-  double *d_partial = nullptr, *d_h = nullptr, *d_h2 = nullptr, *d_nrm = nullptr, *d_c = nullptr;
-  // chunk tables of the Krylov vectors: saddle vectors (2N + 3n) and node vectors (2N)
-  Segs seg_sad{}, seg_nod{};
-  int2 *d_chunks = nullptr;
-  int *d_chunk_sys = nullptr, *d_sys_chunk = nullptr;
-  double *d_irx = nullptr, *d_irr = nullptr, *d_ird = nullptr;
-  double *d_vec_a = nullptr, *d_vec_b = nullptr, *d_U3 = nullptr, *d_U4 = nullptr, *d_U5 = nullptr;
-
-  // timing
-  bool timing = false;
-  std::map<std::string, std::vector<TimedLaunch>> pending;
-  std::map<std::string, std::pair<double, int64_t>> acc;
-
-  PairArgs pair_args() const {
-    PairArgs a;
-    a.cell_start = d_cstart;
-    a.perm = d_cperm;
-    a.nb = d.n_box;
-    a.nbatch = nbatch;
-    a.cell = d.L / d.n_box;
-    a.rc2 = d.r_c * d.r_c;
-    a.xi2 = d.xi * d.xi;
-    a.cG = 1.0 / (4.0 * kPi * p.eta);
-    a.e1tab = d_e1tab;
-    a.e1tab32 = d_e1tab32;
-    return a;
-  }
-  PairLists lists() const {
-    PairLists pl;
-    pl.N = N;
-    pl.ngroups = ngroups;
-    pl.cnt_near = d_cnt_near;
-    pl.cnt_far = d_cnt_far;
-    pl.gnn = d_gnn;
-    pl.gnf = d_gnf;
-    pl.goff = d_goff;
-    pl.ell = d_ell;
-    return pl;
-  }
-  GeomDev geom() const {
-    GeomDev g;
-    g.n = n;
-    g.N = N;
-    g.shape = d_shape;
-    g.off = d_off;
-    g.body = d_body;
-    g.q = d_q;
-    g.theta = d_theta;
-    g.ref = d_ref_arr;
-    g.np = d_np;
-    return g;
-  }
-  BodyMats mats() const {
-    BodyMats m;
-    m.Mp = d_Mp_arr;
-    m.Pref = d_Pref_arr;
-    m.Nt = d_Nt_arr;
-    m.G = d_G_arr;
-    m.Gp = d_Gp_arr;
-    m.max_np = max_np;
-    return m;
-  }
-};
-
-namespace {
-
-fbim_status fail(fbim_ctx *c, fbim_status s, const std::string &msg) {
-  if (c) c->err = msg;
-  return s;
-}
-
-#define HIPCHK(ctx, expr)                                                                        \
-  do {                                                                                           \
-    hipError_t e_ = (expr);                                                                      \
-    if (e_ != hipSuccess)                                                                        \
-      return fail(ctx, FBIM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));         \
-  } while (0)
-
-#define FFTCHK(ctx, expr)                                                                        \
-  do {                                                                                           \
-    rocfft_status e_ = (expr);                                                                   \
-    if (e_ != rocfft_status_success)                                                             \
-      return fail(ctx, FBIM_EDEVICE, std::string(#expr) + ": rocfft status " + std::to_string((int)e_)); \
-  } while (0)
-
-#define STCHK(expr)                    \
-  do {                                 \
-    fbim_status s_ = (expr);           \
-    if (s_ != FBIM_OK) return s_;      \
-  } while (0)
-
-// RAII timing bracket of one launch class
-struct Timer {
-  fbim_ctx *c;
-  const char *name;
-  TimedLaunch t{};
-  Timer(fbim_ctx *c_, const char *n_) : c(c_), name(n_) {
-    if (c->timing) {
-      hipEventCreate(&t.a);
-      hipEventCreate(&t.b);
-      hipEventRecord(t.a, c->stream);
-    }
-  }
-  ~Timer() {
-    if (c->timing) {
-      hipEventRecord(t.b, c->stream);
-      c->pending[name].push_back(t);
-    }
-  }
-};
+namespace fbim {
 
 void resolve_timing(fbim_ctx *c) {
   if (c->pending.empty()) return;
@@ -250,13 +20,6 @@ void resolve_timing(fbim_ctx *c) {
     }
   }
   c->pending.clear();
-}
-
-template <class T>
-fbim_status upload(fbim_ctx *c, T *&dst, const std::vector<T> &src) {
-  HIPCHK(c, dalloc(dst, src.size()));
-  if (!src.empty()) HIPCHK(c, hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
-  return FBIM_OK;
 }
 
 fbim_status rebuild_shape_arrays(fbim_ctx *c) {
@@ -984,25 +747,35 @@ fbim_status mobility(fbim_ctx *c, const double *F, const double *slip, double *U
   return st;
 }
 
-fbim_status brownian(fbim_ctx *c, double dt, const double *F, const double *W_r, const double *W_grid, double *U,
-                     fbim_info *info) {
+// slip_out[2N] = sqrt(2 kT / dt) (v^(r) + v^(w)) of eq. 3.27 (slip_out must not be d_r)
+fbim_status brownian_slip(fbim_ctx *c, double dt, const double *W_r, const double *W_grid, double *slip_out,
+                          fbim_info *info) {
   hipStream_t s = c->stream;
   const size_t twoN = 2 * (size_t)c->N;
-  int li = 0, gi = 0;
-  double lc = 0, gr = 0;
-  // v^(r) into d_U? no: use d_r's leading 2N as the slip accumulator
-  double *slip = c->d_r;  // reused; gmres copies b before touching d_r
-  fbim_status st = lanczos_sqrt(c, W_r, slip, li, lc);
+  int li = 0;
+  double lc = 0;
+  double *acc = c->d_r;  // scratch outside GMRES
+  fbim_status st = lanczos_sqrt(c, W_r, acc, li, lc);
   if (st != FBIM_OK && st != FBIM_ENOCONV) return st;
   STCHK(random_field(c, W_grid, c->d_vec_b));
   const double amp = std::sqrt(2.0 * c->p.kT / dt);
-  // slip = amp (v_r + v_w); store in d_w (free outside GMRES) then pass to mobility
-  HIPCHK(c, launch_axpby(twoN, 1.0, c->d_vec_b, 1.0, slip, s));
-  HIPCHK(c, launch_axpby(twoN, amp, slip, 0.0, c->d_w, s));
-  fbim_status st2 = mobility(c, F, c->d_w, U, nullptr, gi, gr);
+  HIPCHK(c, launch_axpby(twoN, 1.0, c->d_vec_b, 1.0, acc, s));
+  HIPCHK(c, launch_axpby(twoN, amp, acc, 0.0, slip_out, s));
   if (info) {
     info->lanczos_iters += li;
     info->lanczos_change = lc;
+  }
+  return st;
+}
+
+fbim_status brownian(fbim_ctx *c, double dt, const double *F, const double *W_r, const double *W_grid, double *U,
+                     fbim_info *info) {
+  int gi = 0;
+  double gr = 0;
+  fbim_status st = brownian_slip(c, dt, W_r, W_grid, c->d_w, info);
+  if (st != FBIM_OK && st != FBIM_ENOCONV) return st;
+  fbim_status st2 = mobility(c, F, c->d_w, U, nullptr, gi, gr);
+  if (info) {
     info->gmres_iters += gi;
     info->gmres_solves += 1;
     info->gmres_residual = std::max(info->gmres_residual, gr);
@@ -1011,16 +784,7 @@ fbim_status brownian(fbim_ctx *c, double dt, const double *F, const double *W_r,
   return st;
 }
 
-void info_reset(fbim_info *info) {
-  if (!info) return;
-  std::memset(info, 0, sizeof(*info));
-}
-
-double now_ms() {
-  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
-}  // namespace
+}  // namespace fbim
 
 // ====================================================================== C ABI
 extern "C" {
@@ -1161,7 +925,10 @@ void fbim_destroy(fbim_ctx *c) {
                   c->d_mut, c->d_xs32, c->d_mus32, c->d_xt32, c->d_mut32, c->d_grid, c->d_spec, c->d_grid32,
                   c->d_spec32, c->d_e1tab, c->d_e1tab32, c->d_V, c->d_w, c->d_t1, c->d_t2, c->d_b, c->d_x2,
                   c->d_r, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
-                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU};
+                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU, c->d_bx, c->d_by};
+  engine_delete(c->rfd_engine);
+  for (fbim_ctx *r : c->rfd)
+    if (r) fbim_destroy(r);
   for (void *p : ptrs)
     if (p) hipFree(p);
   delete c;
@@ -1363,6 +1130,15 @@ fbim_status fbim_step_em_rfd(fbim_ctx *c, double dt, double delta, const double 
     return fail(c, FBIM_EINVAL, "invalid arguments");
   info_reset(info);
   const double t0 = now_ms();
+  if (c->p.flags & FBIM_FLAG_BATCH_RFD) {
+    // the three solves in one lockstep batch with two copies of the context
+    if (!c->rfd_engine) c->rfd_engine = engine_new();
+    engine_set_stream(c->rfd_engine, c->stream);
+    fbim_status st = em_rfd_batch(c->rfd_engine, {c}, dt, delta, &F, &W_r, &W_grid, &W_tilde, &dQ, apply, info);
+    if (st != FBIM_OK) c->err = engine_error(c->rfd_engine);
+    if (info) info->ms_total = now_ms() - t0;
+    return st;
+  }
   hipStream_t s = c->stream;
   const int n = c->n;
   const size_t n3 = 3 * (size_t)n;

@@ -150,6 +150,10 @@ struct OrthArgs {
   size_t ld;
   int k;
   double *w;
+  // batches: per-system basis, vector and leading dimension (used when Vs is set)
+  const double *const *Vs = nullptr;
+  double *const *ws = nullptr;
+  const size_t *lds = nullptr;
   const double *h;
   int hstride;
   const double *cond;
@@ -158,6 +162,18 @@ struct OrthArgs {
   int ostride;
 };
 hipError_t launch_orth(int mode, const OrthArgs &a, hipStream_t s);
+// vector of system s in a batch: base[s] + col * ld[s] (ld may be null: col ignored)
+struct VecRef {
+  const double *const *base;
+  const size_t *ld;
+  int col;
+};
+// y_s = a[s] x_s + b[s] y_s over the chunks of each system (a, b: device, [S])
+hipError_t launch_seg_axpby(const Segs &seg, const VecRef &x, const VecRef &y, const double *a, const double *b,
+                            hipStream_t s);
+// y_s = V_s[:, 0..k) c_s with c_s = c + s * cstride (device)
+hipError_t launch_seg_Vc(const Segs &seg, const VecRef &V, int k, const double *c, int cstride, const VecRef &y,
+                         hipStream_t s);
 // flag[s] = 1 if nrm[s * ns] < before[s * nb] / 2 (the pass lost more than half of ||w||^2)
 hipError_t launch_need_second_pass(int S, const double *nrm, int ns, const double *before, int nb, double *flag,
                                    hipStream_t s);
@@ -168,6 +184,90 @@ hipError_t launch_scale(size_t n, double a, double *y, hipStream_t s);  // y *= 
 hipError_t launch_vec_add(int k, const double *a, double *b, hipStream_t s);  // b += a
 hipError_t launch_cast_f32(size_t n, const double *x, float *y, hipStream_t s);
 hipError_t launch_fill(size_t n, double v, double *y, hipStream_t s);
+
+// ---------------------------------------------------------------- batched launches
+// Several independent systems (suspensions) go through one launch per stage:
+// system s owns blocks [begin[s], begin[s+1]) of the grid, and each block reads
+// its system's job description (pointers and parameters) from a device table.
+struct BatchGrid {
+  const int *begin;  // [S + 1] block offsets
+  int S, nblocks;
+};
+// last s < S with begin[s] <= blk (empty systems own no block)
+__device__ inline int batch_system(const int *begin, int S, int blk) {
+  int lo = 0, hi = S - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= blk)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+struct GatherJob {  // dst[i] = src[perm[i]] for N (x, y) pairs; dst FP64 or FP32 per launch
+  int N;
+  const int *perm;
+  const double *src;
+  void *dst;
+};
+struct PairJob {  // one system's real-space pair sum (launch_pair_f64 / _f32 arguments)
+  int N, ngroups;
+  const int *perm, *goff, *gnn, *gnf, *ell;
+  double cell, xi2, cG;
+  const void *xs, *mus;
+  double *out;
+};
+struct AlpertJob {
+  GeomDev g;
+  const double *const *band_tab;
+  const int *band;
+  const double *mu;
+  double *out;
+};
+struct SpreadJob {
+  WaveArgs w;
+  const void *xt, *mut;
+  void *grid;
+};
+struct InterpJob {
+  WaveArgs w;
+  const void *xt;
+  const int *tperm;
+  const void *grid;
+  double *out;
+};
+struct MultJob {  // multiplier on one system's half spectrum
+  int M;
+  double L, xi, eta_s, scale;
+  void *spec;
+};
+struct RigidJob {  // saddle rigid-body terms: y_mu -= K x_U, y_U = -K^T x_mu
+  GeomDev g;
+  const double *x;
+  double *y;
+};
+struct PrecondJob {
+  GeomDev g;
+  BodyMats m;
+  BodyTiles bt;
+  const double *dN;
+  const double *z;
+  double *y;
+};
+// grids: blocks of 256 threads per system as listed with each launcher
+hipError_t launch_gather2_batch(const GatherJob *jobs, BatchGrid bg, int f32, hipStream_t s);   // ceil(N/256)
+hipError_t launch_pair_batch(const PairJob *jobs, BatchGrid bg, int f32, const double *tab64, const float *tab32,
+                             hipStream_t s);                                                     // ceil(64 ngroups/256)
+hipError_t launch_alpert_batch(const AlpertJob *jobs, BatchGrid bg, hipStream_t s);              // ceil(N/256)
+hipError_t launch_spread_batch(const SpreadJob *jobs, BatchGrid bg, int f32, hipStream_t s);     // nts^2
+hipError_t launch_interp_batch(const InterpJob *jobs, BatchGrid bg, int f32, hipStream_t s);     // nts^2
+hipError_t launch_multiplier_batch(const MultJob *jobs, BatchGrid bg, int f32, int mode,
+                                   hipStream_t s);                                                // ceil(M(M/2+1)/256)
+hipError_t launch_rigid_batch(const RigidJob *jobs, BatchGrid bg_nodes, BatchGrid bg_bodies, hipStream_t s);
+                                                                        // ceil(N/256); bodies: ceil(n/4) (64 per body)
+// bt.ntile blocks per system; lds_bytes = the largest bt.lds_bytes of the systems
+hipError_t launch_precond_batch(const PrecondJob *jobs, BatchGrid bg, size_t lds_bytes, hipStream_t s);
 
 // learned preconditioner correction (MLP 32 -> 128 -> 128 -> 6, tanh)
 constexpr int kMlpNeighbours = 6, kMlpIn = 32, kMlpHid = 128, kMlpOut = 6;

@@ -194,6 +194,24 @@ hipError_t launch_gather2f(int N, const int *perm, const double *src, float *dst
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_gather2_batch(const GatherJob *__restrict__ jobs, BatchGrid bg, int f32) {
+  const int s = batch_system(bg.begin, bg.S, blockIdx.x);
+  const GatherJob j = jobs[s];
+  const int i = (blockIdx.x - bg.begin[s]) * 256 + threadIdx.x;
+  if (i >= j.N) return;
+  const double2 v = reinterpret_cast<const double2 *>(j.src)[j.perm[i]];
+  if (f32)
+    reinterpret_cast<float2 *>(j.dst)[i] = make_float2((float)v.x, (float)v.y);
+  else
+    reinterpret_cast<double2 *>(j.dst)[i] = v;
+}
+
+hipError_t launch_gather2_batch(const GatherJob *jobs, BatchGrid bg, int f32, hipStream_t s) {
+  if (bg.nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather2_batch, dim3(bg.nblocks), dim3(256), 0, s, jobs, bg, f32);
+  return hipGetLastError();
+}
+
 // Tile-ordered stencil data: nearest grid indices a = floor(x/h + 1/2) (unwrapped)
 // and the FP64 offsets x - a h, |offset| <= h/2 (also stored in FP32).
 __global__ void k_anchors(int N, const int *__restrict__ tperm, const double *__restrict__ x, double h,

@@ -70,6 +70,70 @@ hipError_t launch_KT(const GeomDev &g, const double *mu, double sgn, double *out
   return hipGetLastError();
 }
 
+// batched saddle rigid-body terms: y_mu -= K x_U over the nodes, then
+// y_U = -K^T x_mu with one wave per body (4 bodies per 256-thread block)
+__global__ __launch_bounds__(256) void k_sub_KU_batch(const RigidJob *__restrict__ jobs, BatchGrid bg) {
+  const int s = batch_system(bg.begin, bg.S, blockIdx.x);
+  const RigidJob &j = jobs[s];
+  const GeomDev &g = j.g;
+  const int i = (blockIdx.x - bg.begin[s]) * 256 + threadIdx.x;
+  if (i >= g.N) return;
+  const int b = g.body[i];
+  const int t = i - g.off[b];
+  const double *r = g.ref[g.shape[b]];
+  double sn, cs;
+  sincos(g.theta[b], &sn, &cs);
+  const double rx = cs * r[2 * t] - sn * r[2 * t + 1];
+  const double ry = sn * r[2 * t] + cs * r[2 * t + 1];
+  const double *U = j.x + 2 * (size_t)g.N;
+  const double w = U[3 * b + 2];
+  j.y[2 * i] -= U[3 * b] - w * ry;
+  j.y[2 * i + 1] -= U[3 * b + 1] + w * rx;
+}
+
+__global__ __launch_bounds__(256) void k_KT_batch(const RigidJob *__restrict__ jobs, BatchGrid bg) {
+  const int s = batch_system(bg.begin, bg.S, blockIdx.x);
+  const RigidJob &j = jobs[s];
+  const GeomDev &g = j.g;
+  const int b = (blockIdx.x - bg.begin[s]) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (b >= g.n) return;  // whole wave
+  const int a = g.off[b], e = g.off[b + 1];
+  const double *r = g.ref[g.shape[b]];
+  double sn, cs;
+  sincos(g.theta[b], &sn, &cs);
+  double fx = 0, fy = 0, tq = 0;
+  for (int i = a + lane; i < e; i += 64) {
+    const int t = i - a;
+    const double rx = cs * r[2 * t] - sn * r[2 * t + 1];
+    const double ry = sn * r[2 * t] + cs * r[2 * t + 1];
+    const double mx = j.x[2 * i], my = j.x[2 * i + 1];
+    fx += mx;
+    fy += my;
+    tq += rx * my - ry * mx;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    fx += __shfl_down(fx, o);
+    fy += __shfl_down(fy, o);
+    tq += __shfl_down(tq, o);
+  }
+  if (lane == 0) {
+    double *out = j.y + 2 * (size_t)g.N + 3 * (size_t)b;
+    out[0] = -fx;
+    out[1] = -fy;
+    out[2] = -tq;
+  }
+}
+
+hipError_t launch_rigid_batch(const RigidJob *jobs, BatchGrid bg_nodes, BatchGrid bg_bodies, hipStream_t s) {
+  if (bg_nodes.nblocks > 0) hipLaunchKernelGGL(k_sub_KU_batch, dim3(bg_nodes.nblocks), dim3(256), 0, s, jobs, bg_nodes);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (bg_bodies.nblocks > 0) hipLaunchKernelGGL(k_KT_batch, dim3(bg_bodies.nblocks), dim3(256), 0, s, jobs, bg_bodies);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ per-body dense operators
 // All bodies of a shape share their reference matrices, so in the body frame the
 // per-body products are one matrix times a batch of vectors.  A work group takes
@@ -85,7 +149,7 @@ hipError_t launch_KT(const GeomDev &g, const double *mu, double sgn, double *out
 //   replaced by M_bb + K C K^T: by the Woodbury identity that body's mobility
 //   becomes N_ref + C, mu is unchanged and U_ref gains -C R'^T b.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_body_tile(BodyTiles bt, const int *__restrict__ off,
+__device__ void body_tile(const BodyTiles &bt, int tile, const int *__restrict__ off,
                                                    const double *__restrict__ theta, const double *const *ref,
                                                    const int *__restrict__ np, const double *const *X,
                                                    const double *const *Pref, const double *const *Nt,
@@ -95,7 +159,7 @@ __global__ __launch_bounds__(256) void k_body_tile(BodyTiles bt, const int *__re
   __shared__ double Ur[kBodyTile][3];
   __shared__ double cs_[kBodyTile], sn_[kBodyTile];
   __shared__ int base_[kBodyTile], body_[kBodyTile];
-  const int4 tl = bt.tile[blockIdx.x];
+  const int4 tl = bt.tile[tile];
   const int sh = tl.x, nb = tl.z;
   const int npt = np[sh], n2 = 2 * npt;
   const int tid = threadIdx.x;
@@ -235,6 +299,29 @@ __global__ __launch_bounds__(256) void k_body_tile(BodyTiles bt, const int *__re
   }
 }
 
+template <int MODE>
+__global__ __launch_bounds__(256) void k_body_tile(BodyTiles bt, const int *__restrict__ off,
+                                                   const double *__restrict__ theta, const double *const *ref,
+                                                   const int *__restrict__ np, const double *const *X,
+                                                   const double *const *Pref, const double *const *Nt,
+                                                   const double *__restrict__ dN, int N,
+                                                   const double *__restrict__ z, double *__restrict__ y) {
+  body_tile<MODE>(bt, blockIdx.x, off, theta, ref, np, X, Pref, Nt, dN, N, z, y);
+}
+
+__global__ __launch_bounds__(256) void k_precond_batch(const PrecondJob *__restrict__ jobs, BatchGrid bg) {
+  const int s = batch_system(bg.begin, bg.S, blockIdx.x);
+  const PrecondJob &j = jobs[s];
+  body_tile<1>(j.bt, blockIdx.x - bg.begin[s], j.g.off, j.g.theta, j.g.ref, j.g.np, j.m.Mp, j.m.Pref, j.m.Nt, j.dN,
+               j.g.N, j.z, j.y);
+}
+
+hipError_t launch_precond_batch(const PrecondJob *jobs, BatchGrid bg, size_t lds_bytes, hipStream_t s) {
+  if (bg.nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_precond_batch, dim3(bg.nblocks), dim3(256), lds_bytes, s, jobs, bg);
+  return hipGetLastError();
+}
+
 hipError_t launch_precond(const GeomDev &g, const BodyMats &m, const BodyTiles &bt, const double *dN,
                           const double *z, double *y, hipStream_t s) {
   if (g.n == 0) return hipSuccess;
@@ -312,9 +399,9 @@ __global__ __launch_bounds__(256) void k_orth(OrthArgs a) {
 #pragma unroll
     for (int j = 0; j < K; ++j) hr[j] = h[j];
   }
-  const double *__restrict__ V = a.V;
-  double *__restrict__ w = a.w;
-  const size_t ld = a.ld;
+  const double *__restrict__ V = a.Vs ? a.Vs[sys] : a.V;
+  double *__restrict__ w = a.ws ? a.ws[sys] : a.w;
+  const size_t ld = a.lds ? a.lds[sys] : a.ld;
   double acc[NV];
 #pragma unroll
   for (int c = 0; c < NV; ++c) acc[c] = 0.0;
@@ -365,9 +452,9 @@ __global__ __launch_bounds__(256) void k_orth_any(OrthArgs a) {
   const int2 rg = a.seg.chunk[cidx];
   const int tid = threadIdx.x;
   const int k = a.k;
-  const double *__restrict__ V = a.V;
-  double *__restrict__ w = a.w;
-  const size_t ld = a.ld;
+  const double *__restrict__ V = a.Vs ? a.Vs[sys] : a.V;
+  double *__restrict__ w = a.ws ? a.ws[sys] : a.w;
+  const size_t ld = a.lds ? a.lds[sys] : a.ld;
   if (MODE == 2) {
     __shared__ double hs[kOrthMaxCols];
     const double *h = a.h + (size_t)sys * a.hstride;
@@ -456,6 +543,56 @@ hipError_t launch_orth(int mode, const OrthArgs &a, hipStream_t s) {
   }
   hipLaunchKernelGGL((k_orth_any<2>), dim3(a.seg.nchunk), dim3(256), 0, s, a);
   return finish(1, a, s);
+}
+
+// ------------------------------------------------------------------ segmented vector kernels (batches)
+__device__ inline const double *vec_ptr(const VecRef &v, int s) {
+  return v.base[s] + (size_t)v.col * (v.ld ? v.ld[s] : 0);
+}
+
+// y_s = a[s] x_s + b[s] y_s (x_s not read when a[s] == 0, y_s not when b[s] == 0); one work group per chunk
+__global__ __launch_bounds__(256) void k_seg_axpby(Segs seg, VecRef x, VecRef y, const double *__restrict__ a,
+                                                   const double *__restrict__ b) {
+  const int c = blockIdx.x;
+  const int s = seg.chunk_sys[c];
+  const int2 rg = seg.chunk[c];
+  const double *xp = vec_ptr(x, s);
+  double *yp = const_cast<double *>(vec_ptr(y, s));
+  const double as = a[s], bs = b[s];
+  // a zero coefficient reads nothing, so uninitialised vectors can be cleared
+  for (int i = rg.x + threadIdx.x; i < rg.y; i += 256)
+    yp[i] = (as == 0.0 ? 0.0 : as * xp[i]) + (bs == 0.0 ? 0.0 : bs * yp[i]);
+}
+
+hipError_t launch_seg_axpby(const Segs &seg, const VecRef &x, const VecRef &y, const double *a, const double *b,
+                            hipStream_t s) {
+  if (seg.nchunk == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seg_axpby, dim3(seg.nchunk), dim3(256), 0, s, seg, x, y, a, b);
+  return hipGetLastError();
+}
+
+// y_s = sum_{j < k} V_s[:, j] c[s * cstride + j]
+__global__ __launch_bounds__(256) void k_seg_Vc(Segs seg, VecRef V, int k, const double *__restrict__ c, int cstride,
+                                                VecRef y) {
+  const int ci = blockIdx.x;
+  const int s = seg.chunk_sys[ci];
+  const int2 rg = seg.chunk[ci];
+  const double *Vp = V.base[s];
+  const size_t ld = V.ld[s];
+  const double *cs = c + (size_t)s * cstride;
+  double *yp = const_cast<double *>(vec_ptr(y, s));
+  for (int i = rg.x + threadIdx.x; i < rg.y; i += 256) {
+    double acc = 0.0;
+    for (int j = 0; j < k; ++j) acc += Vp[(size_t)j * ld + i] * cs[j];
+    yp[i] = acc;
+  }
+}
+
+hipError_t launch_seg_Vc(const Segs &seg, const VecRef &V, int k, const double *c, int cstride, const VecRef &y,
+                         hipStream_t s) {
+  if (seg.nchunk == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seg_Vc, dim3(seg.nchunk), dim3(256), 0, s, seg, V, k, c, cstride, y);
+  return hipGetLastError();
 }
 
 // flag[s] = nrm[s * ns] < before[s * nb] / 2 ? 1 : 0

@@ -164,28 +164,24 @@ __global__ void k_group_rows(int N, int ngroups, const int *__restrict__ cnt_nea
   }
 }
 
-// real-space pair sum over the neighbour lists: one thread per cell-sorted target
+// real-space pair sum over the neighbour lists: one thread per cell-sorted
+// target; `blk` is the block's index within its system (256 threads = 4 groups)
 template <typename T, int DEG>
-__global__ __launch_bounds__(256) void k_pair_ell(int N, int ngroups, const int *__restrict__ perm,
-                                                  const int *__restrict__ goff, const int *__restrict__ gnn,
-                                                  const int *__restrict__ gnf, const int *__restrict__ ell, T cell,
-                                                  T xi2, T cG, const T *__restrict__ e1tab,
-                                                  const typename Vec2<T>::type *__restrict__ xs,
-                                                  const typename Vec2<T>::type *__restrict__ mus,
-                                                  double *__restrict__ out) {
-  __shared__ T tab[kE1Int * (DEG + 3)];
-  for (int i = threadIdx.x; i < kE1Int * (DEG + 3); i += 256) tab[i] = e1tab[i];
-  __syncthreads();
-  const int t = blockIdx.x * 256 + threadIdx.x;
+__device__ void pair_ell_body(const PairJob &j, const T *__restrict__ tab, int blk) {
+  using V2 = typename Vec2<T>::type;
+  const V2 *__restrict__ xs = reinterpret_cast<const V2 *>(j.xs);
+  const V2 *__restrict__ mus = reinterpret_cast<const V2 *>(j.mus);
+  const T cell = (T)j.cell, xi2 = (T)j.xi2, cG = (T)j.cG;
+  const int t = blk * 256 + threadIdx.x;
   const int g = t >> 6, lane = t & 63;
-  if (g >= ngroups) return;  // whole wave
+  if (g >= j.ngroups) return;  // whole wave
   T tx = 0, ty = 0;
-  if (t < N) {
+  if (t < j.N) {
     const auto p = xs[t];
     tx = p.x;
     ty = p.y;
   }
-  const int base = goff[g], nn = gnn[g], nf = gnf[g];
+  const int base = j.goff[g], nn = j.gnn[g], nf = j.gnf[g];
   T vx = 0, vy = 0, kx = 0, ky = 0;  // Kahan-compensated sums
   auto add = [&](T a, T b) {
     T y = a - kx;
@@ -198,7 +194,7 @@ __global__ __launch_bounds__(256) void k_pair_ell(int N, int ngroups, const int 
     vy = s2;
   };
   for (int i = 0; i < nn + nf; ++i) {
-    const int code = ell[base + (size_t)i * 64 + lane];
+    const int code = j.ell[base + (size_t)i * 64 + lane];
     if (code < 0) continue;
     const int s = code & kIndexMask, oc = code >> kCodeShift;
     const auto p = xs[s];
@@ -220,21 +216,54 @@ __global__ __launch_bounds__(256) void k_pair_ell(int N, int ngroups, const int 
     const T sdot = ez * (dx * m.x + dy * m.y) / r2;
     add(a * m.x + sdot * dx, a * m.y + sdot * dy);
   }
-  if (t < N) {
-    const int node = perm[t];
-    out[2 * node] = (double)(cG * vx);
-    out[2 * node + 1] = (double)(cG * vy);
+  if (t < j.N) {
+    const int node = j.perm[t];
+    j.out[2 * node] = (double)(cG * vx);
+    j.out[2 * node + 1] = (double)(cG * vy);
   }
+}
+
+template <typename T, int DEG>
+__device__ inline void load_table(T *tab, const T *__restrict__ e1tab) {
+  for (int i = threadIdx.x; i < kE1Int * (DEG + 3); i += 256) tab[i] = e1tab[i];
+  __syncthreads();
+}
+
+template <typename T, int DEG>
+__global__ __launch_bounds__(256) void k_pair_ell(PairJob j, const T *__restrict__ e1tab) {
+  __shared__ T tab[kE1Int * (DEG + 3)];
+  load_table<T, DEG>(tab, e1tab);
+  pair_ell_body<T, DEG>(j, tab, blockIdx.x);
+}
+
+template <typename T, int DEG>
+__global__ __launch_bounds__(256) void k_pair_ell_batch(const PairJob *__restrict__ jobs, BatchGrid bg,
+                                                        const T *__restrict__ e1tab) {
+  __shared__ T tab[kE1Int * (DEG + 3)];
+  load_table<T, DEG>(tab, e1tab);
+  const int s = batch_system(bg.begin, bg.S, blockIdx.x);
+  pair_ell_body<T, DEG>(jobs[s], tab, blockIdx.x - bg.begin[s]);
 }
 
 template <typename T, int DEG>
 hipError_t pair_ell_launch(const PairLists &pl, const PairArgs &a, const T *xs, const T *mus, const T *tab,
                            double *out, hipStream_t s) {
   if (pl.N == 0) return hipSuccess;
-  using V = typename Vec2<T>::type;
-  hipLaunchKernelGGL((k_pair_ell<T, DEG>), dim3((pl.ngroups * 64 + 255) / 256), dim3(256), 0, s, pl.N, pl.ngroups,
-                     a.perm, pl.goff, pl.gnn, pl.gnf, pl.ell, (T)a.cell, (T)a.xi2, (T)a.cG, tab, (const V *)xs,
-                     (const V *)mus, out);
+  PairJob j;
+  j.N = pl.N;
+  j.ngroups = pl.ngroups;
+  j.perm = a.perm;
+  j.goff = pl.goff;
+  j.gnn = pl.gnn;
+  j.gnf = pl.gnf;
+  j.ell = pl.ell;
+  j.cell = a.cell;
+  j.xi2 = a.xi2;
+  j.cG = a.cG;
+  j.xs = xs;
+  j.mus = mus;
+  j.out = out;
+  hipLaunchKernelGGL((k_pair_ell<T, DEG>), dim3((pl.ngroups * 64 + 255) / 256), dim3(256), 0, s, j, tab);
   return hipGetLastError();
 }
 
@@ -267,20 +296,17 @@ hipError_t launch_pair_f32(const PairLists &pl, const PairArgs &a, const float *
 }
 
 // ------------------------------------------------------------------ Alpert band
-__global__ void k_alpert(int N, const int *__restrict__ body, const int *__restrict__ off,
-                         const int *__restrict__ shape, const double *__restrict__ theta,
-                         const double *const *band_tab, const int *__restrict__ band, const int *__restrict__ np,
-                         const double2 *__restrict__ mu, double2 *__restrict__ out, int accumulate) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const int b = body[i];
-  const int base = off[b];
+__device__ void alpert_body(const GeomDev &g, const double *const *band_tab, const int *__restrict__ band,
+                            const double2 *__restrict__ mu, double2 *__restrict__ out, int accumulate, int i) {
+  if (i >= g.N) return;
+  const int b = g.body[i];
+  const int base = g.off[b];
   const int t = i - base;
-  const int sh = shape[b];
-  const int B = band[sh], n_p = np[sh];
+  const int sh = g.shape[b];
+  const int B = band[sh], n_p = g.np[sh];
   const double *A = band_tab[sh] + (size_t)t * (2 * B + 1) * 4;
   double sn, cs;
-  sincos(theta[b], &sn, &cs);
+  sincos(g.theta[b], &sn, &cs);
   double ax = 0.0, ay = 0.0;
   for (int o = -B; o <= B; ++o) {
     int l = t + o;
@@ -301,11 +327,40 @@ __global__ void k_alpert(int N, const int *__restrict__ body, const int *__restr
   }
 }
 
+__global__ __launch_bounds__(256) void k_alpert(GeomDev g, const double *const *band_tab, const int *__restrict__ band,
+                                                const double2 *__restrict__ mu, double2 *__restrict__ out,
+                                                int accumulate) {
+  alpert_body(g, band_tab, band, mu, out, accumulate, blockIdx.x * 256 + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_alpert_batch(const AlpertJob *__restrict__ jobs, BatchGrid bg) {
+  const int s = batch_system(bg.begin, bg.S, blockIdx.x);
+  const AlpertJob &j = jobs[s];
+  alpert_body(j.g, j.band_tab, j.band, reinterpret_cast<const double2 *>(j.mu), reinterpret_cast<double2 *>(j.out),
+              1, (blockIdx.x - bg.begin[s]) * 256 + threadIdx.x);
+}
+
 hipError_t launch_alpert(const GeomDev &g, const double *const *band_tab, const int *band, const double *mu,
                          double *out, int accumulate, hipStream_t s) {
   if (g.N == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_alpert, dim3((g.N + 255) / 256), dim3(256), 0, s, g.N, g.body, g.off, g.shape, g.theta,
-                     band_tab, band, g.np, (const double2 *)mu, (double2 *)out, accumulate);
+  hipLaunchKernelGGL(k_alpert, dim3((g.N + 255) / 256), dim3(256), 0, s, g, band_tab, band, (const double2 *)mu,
+                     (double2 *)out, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_alpert_batch(const AlpertJob *jobs, BatchGrid bg, hipStream_t s) {
+  if (bg.nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_alpert_batch, dim3(bg.nblocks), dim3(256), 0, s, jobs, bg);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_batch(const PairJob *jobs, BatchGrid bg, int f32, const double *tab64, const float *tab32,
+                             hipStream_t s) {
+  if (bg.nblocks == 0) return hipSuccess;
+  if (f32)
+    hipLaunchKernelGGL((k_pair_ell_batch<float, 9>), dim3(bg.nblocks), dim3(256), 0, s, jobs, bg, tab32);
+  else
+    hipLaunchKernelGGL((k_pair_ell_batch<double, 16>), dim3(bg.nblocks), dim3(256), 0, s, jobs, bg, tab64);
   return hipGetLastError();
 }
 

@@ -48,12 +48,9 @@ __device__ inline int wrap_near(int i, int M) {  // valid for -M <= i < 2M
 // T: weights and positions; A: LDS accumulator (FP64 for both precisions: FP64
 // LDS atomics measured faster than FP32 ones here, and they add no rounding)
 template <typename T, typename A>
-__global__ __launch_bounds__(256) void k_spread(int M, int TT, int P, int nts, T h, T ag, T cg,
-                                                const int *__restrict__ tile_start,
-                                                const typename Vec2<T>::type *__restrict__ xt,
-                                                const int2 *__restrict__ anchor,
-                                                const typename Vec2<T>::type *__restrict__ mut,
-                                                T *__restrict__ grid) {
+__device__ void spread_body(int M, int TT, int P, int nts, T h, T ag, T cg, const int *__restrict__ tile_start,
+                            const typename Vec2<T>::type *__restrict__ xt, const int2 *__restrict__ anchor,
+                            const typename Vec2<T>::type *__restrict__ mut, T *__restrict__ grid, int tile) {
   __shared__ A acc[2][kTmax * (kTmax + 1)];  // rows padded by one: a node's P rows fall in distinct banks
   __shared__ T wgx[kSpreadChunk][kPmax], wgy[kSpreadChunk][kPmax];
   __shared__ T nmx[kSpreadChunk], nmy[kSpreadChunk];
@@ -61,7 +58,6 @@ __global__ __launch_bounds__(256) void k_spread(int M, int TT, int P, int nts, T
   __shared__ int lst[kSpreadChunk + 256];
   __shared__ int lcount;
   const int tid = threadIdx.x;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int tyi = tile / nts, txi = tile % nts;
   const int gx0 = txi * TT, gy0 = tyi * TT;
   const int half = (P - 1) / 2;
@@ -157,16 +153,13 @@ __global__ __launch_bounds__(256) void k_spread(int M, int TT, int P, int nts, T
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_interp(int M, int TT, int P, int nts, T h, T ag, T scale,
-                                                const int *__restrict__ tile_start,
-                                                const typename Vec2<T>::type *__restrict__ xt,
-                                                const int2 *__restrict__ anchor,
-                                                const int *__restrict__ tperm, const T *__restrict__ grid,
-                                                double *__restrict__ out) {
+__device__ void interp_body(int M, int TT, int P, int nts, T h, T ag, T scale, const int *__restrict__ tile_start,
+                            const typename Vec2<T>::type *__restrict__ xt, const int2 *__restrict__ anchor,
+                            const int *__restrict__ tperm, const T *__restrict__ grid, double *__restrict__ out,
+                            int tile) {
   constexpr int W = kTmax + kPmax - 1;
   __shared__ T win[2][W * W];
   const int tid = threadIdx.x;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int tyi = tile / nts, txi = tile % nts;
   const int gx0 = txi * TT, gy0 = tyi * TT;
   const int half = (P - 1) / 2;
@@ -216,10 +209,9 @@ __global__ __launch_bounds__(256) void k_interp(int M, int TT, int P, int nts, T
 // column the off-diagonal term is dropped, which makes the complex-to-real
 // inverse transform equal to the real part of the full inverse transform.
 template <typename T>
-__global__ void k_multiplier(int M, T twopi_L, T inv4xi2, T one_m_eta, T scale, int mode,
-                             typename Vec2<T>::type *__restrict__ spec) {
+__device__ void multiplier_body(int M, T twopi_L, T inv4xi2, T one_m_eta, T scale, int mode,
+                                typename Vec2<T>::type *__restrict__ spec, int idx) {
   const int nh = M / 2 + 1;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= M * nh) return;
   const int row = idx / nh, col = idx - row * nh;
   const T kx = twopi_L * col;
@@ -246,7 +238,94 @@ __global__ void k_multiplier(int M, T twopi_L, T inv4xi2, T one_m_eta, T scale, 
   Fy.y = s * (pxy * fx.y + pyy * fy.y);
 }
 
+template <typename T, typename A>
+__global__ __launch_bounds__(256) void k_spread(int M, int TT, int P, int nts, T h, T ag, T cg,
+                                                const int *__restrict__ tile_start,
+                                                const typename Vec2<T>::type *__restrict__ xt,
+                                                const int2 *__restrict__ anchor,
+                                                const typename Vec2<T>::type *__restrict__ mut,
+                                                T *__restrict__ grid) {
+  spread_body<T, A>(M, TT, P, nts, h, ag, cg, tile_start, xt, anchor, mut, grid, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_interp(int M, int TT, int P, int nts, T h, T ag, T scale,
+                                                const int *__restrict__ tile_start,
+                                                const typename Vec2<T>::type *__restrict__ xt,
+                                                const int2 *__restrict__ anchor,
+                                                const int *__restrict__ tperm, const T *__restrict__ grid,
+                                                double *__restrict__ out) {
+  interp_body<T>(M, TT, P, nts, h, ag, scale, tile_start, xt, anchor, tperm, grid, out,
+                 xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <typename T>
+__global__ void k_multiplier(int M, T twopi_L, T inv4xi2, T one_m_eta, T scale, int mode,
+                             typename Vec2<T>::type *__restrict__ spec) {
+  multiplier_body<T>(M, twopi_L, inv4xi2, one_m_eta, scale, mode, spec, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// batched forms: the XCD-aware order is taken over the whole grid, then the
+// block's system and its tile within that system are found
+template <typename T, typename A>
+__global__ __launch_bounds__(256) void k_spread_batch(const SpreadJob *__restrict__ jobs, BatchGrid bg) {
+  using V2 = typename Vec2<T>::type;
+  const int gb = xcd_remap(blockIdx.x, gridDim.x);
+  const int s = batch_system(bg.begin, bg.S, gb);
+  const SpreadJob &j = jobs[s];
+  spread_body<T, A>(j.w.M, j.w.T, j.w.P, j.w.nts, (T)j.w.h, (T)j.w.ag, (T)j.w.cg, j.w.tile_start,
+                    reinterpret_cast<const V2 *>(j.xt), reinterpret_cast<const int2 *>(j.w.anchor),
+                    reinterpret_cast<const V2 *>(j.mut), reinterpret_cast<T *>(j.grid), gb - bg.begin[s]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_interp_batch(const InterpJob *__restrict__ jobs, BatchGrid bg) {
+  using V2 = typename Vec2<T>::type;
+  const int gb = xcd_remap(blockIdx.x, gridDim.x);
+  const int s = batch_system(bg.begin, bg.S, gb);
+  const InterpJob &j = jobs[s];
+  interp_body<T>(j.w.M, j.w.T, j.w.P, j.w.nts, (T)j.w.h, (T)j.w.ag, (T)(j.w.h * j.w.h * j.w.cg), j.w.tile_start,
+                 reinterpret_cast<const V2 *>(j.xt), reinterpret_cast<const int2 *>(j.w.anchor), j.tperm,
+                 reinterpret_cast<const T *>(j.grid), j.out, gb - bg.begin[s]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_multiplier_batch(const MultJob *__restrict__ jobs, BatchGrid bg, int mode) {
+  const int s = batch_system(bg.begin, bg.S, blockIdx.x);
+  const MultJob &j = jobs[s];
+  multiplier_body<T>(j.M, (T)(2.0 * M_PI / j.L), (T)(1.0 / (4.0 * j.xi * j.xi)), (T)(1.0 - j.eta_s), (T)j.scale,
+                     mode, reinterpret_cast<typename Vec2<T>::type *>(j.spec),
+                     (blockIdx.x - bg.begin[s]) * 256 + threadIdx.x);
+}
+
 }  // namespace
+
+hipError_t launch_spread_batch(const SpreadJob *jobs, BatchGrid bg, int f32, hipStream_t s) {
+  if (bg.nblocks == 0) return hipSuccess;
+  if (f32)
+    hipLaunchKernelGGL((k_spread_batch<float, double>), dim3(bg.nblocks), dim3(256), 0, s, jobs, bg);
+  else
+    hipLaunchKernelGGL((k_spread_batch<double, double>), dim3(bg.nblocks), dim3(256), 0, s, jobs, bg);
+  return hipGetLastError();
+}
+
+hipError_t launch_interp_batch(const InterpJob *jobs, BatchGrid bg, int f32, hipStream_t s) {
+  if (bg.nblocks == 0) return hipSuccess;
+  if (f32)
+    hipLaunchKernelGGL((k_interp_batch<float>), dim3(bg.nblocks), dim3(256), 0, s, jobs, bg);
+  else
+    hipLaunchKernelGGL((k_interp_batch<double>), dim3(bg.nblocks), dim3(256), 0, s, jobs, bg);
+  return hipGetLastError();
+}
+
+hipError_t launch_multiplier_batch(const MultJob *jobs, BatchGrid bg, int f32, int mode, hipStream_t s) {
+  if (bg.nblocks == 0) return hipSuccess;
+  if (f32)
+    hipLaunchKernelGGL((k_multiplier_batch<float>), dim3(bg.nblocks), dim3(256), 0, s, jobs, bg, mode);
+  else
+    hipLaunchKernelGGL((k_multiplier_batch<double>), dim3(bg.nblocks), dim3(256), 0, s, jobs, bg, mode);
+  return hipGetLastError();
+}
 
 hipError_t launch_spread_f64(const WaveArgs &w, const double *xt, const double *mut, double *grid, hipStream_t s) {
   const int nt = w.nts * w.nts;

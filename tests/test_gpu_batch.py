@@ -1,0 +1,151 @@
+"""GPU parity of the batched entry points: several independent systems of
+different sizes (and grid sizes) through one launch per stage must give each
+system's own single-system results.
+
+Bars: the batched matvec runs the same per-system arithmetic (only the
+spreading's LDS-atomic order differs), so 1e-12 relative; batched GMRES runs
+each system's own Krylov iteration, so solutions agree to the solver
+tolerance (GMRES at 1e-10 here: 1e-8 relative); the EM-RFD step as the
+single-system step (1e-6, the step's parity bar against the oracle)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import dev, host, log, make_ctx, relerr, zeros
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ["tiny2", "starfish4", "small12"]
+
+
+def _setup_member(ctx, wl):
+    import paper_1709_01480_amd as fb
+    sid = ctx.add_shape(fb.starfish(wl.r_s, wl.b, wl.n_arm, wl.n_p))
+    ctx.set_bodies(np.full(wl.n_bodies, sid), wl.q, wl.theta)
+
+
+def _batch(wls, graph=False, **over):
+    import paper_1709_01480_amd as fb
+    prms = []
+    for wl in wls:
+        p = wl.params()
+        p.update(over)
+        prms.append(p)
+    b = fb.Batch(prms, graph=graph)
+    for m, wl in zip(b.members, wls):
+        _setup_member(m, wl)
+    return b
+
+
+def test_batched_matvec_matches_each_system():
+    wls = [W.make(n) for n in NAMES]
+    log("batch matvec %s" % NAMES)
+    b = _batch(wls)
+    rng = np.random.default_rng(3)
+    mus = [dev(rng.standard_normal(2 * wl.n_nodes)) for wl in wls]
+    outs = [zeros(2 * wl.n_nodes) for wl in wls]
+    b.apply_M(mus, outs)
+    for wl, mu, out in zip(wls, mus, outs):
+        ctx = make_ctx(wl)
+        ref = zeros(2 * wl.n_nodes)
+        ctx.apply_M(mu, ref)
+        assert relerr(host(out), host(ref)) < 1e-12, wl.name
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batched_mobility_matches_each_system(graph):
+    wls = [W.make(n) for n in NAMES]
+    log("batch mobility graph=%s" % graph)
+    b = _batch(wls, graph=graph, tol_gmres=1e-10)
+    Fs = [dev(wl.F) for wl in wls]
+    for rep in range(2):  # the second call replays the captured graph
+        Us = [zeros(3 * wl.n_bodies) for wl in wls]
+        infos = b.mobility(Fs, Us)
+        log("rep %d infos %s" % (rep, [(i["gmres_iters"], i["gmres_residual"]) for i in infos]))
+        for wl, U, info in zip(wls, Us, infos):
+            ctx = make_ctx(wl, tol_gmres=1e-10)
+            ref = zeros(3 * wl.n_bodies)
+            ri = ctx.mobility(dev(wl.F), ref)
+            assert info["gmres_residual"] <= 1e-10
+            assert abs(info["gmres_iters"] - ri["gmres_iters"]) <= 1
+            assert relerr(host(U), host(ref)) < 1e-8, wl.name
+
+
+def test_uneven_suspensions_batched_mobility():
+    """Eight suspensions of 6..40 bodies with 32..64 nodes per body, different
+    grids, in one batch."""
+    rng = np.random.default_rng(11)
+    wls = []
+    for k in range(8):
+        n = int(rng.integers(6, 41))
+        n_p = int(rng.choice([32, 48, 64]))
+        r_s = float(np.sqrt(0.15 / (n * np.pi * 1.045)))
+        wls.append(W.make("small12", seed=50 + k, n_bodies=n, n_p=n_p, r_s=r_s,
+                          n_box=4, grid_M=int(rng.choice([64, 96, 128])), tol_ewald=1e-8))
+    log("uneven batch %s" % [(w.n_bodies, w.n_p, w.grid_M) for w in wls])
+    b = _batch(wls, tol_gmres=1e-10)
+    Fs = [dev(wl.F) for wl in wls]
+    Us = [zeros(3 * wl.n_bodies) for wl in wls]
+    infos = b.mobility(Fs, Us)
+    for wl, U, info in zip(wls, Us, infos):
+        ctx = make_ctx(wl, tol_gmres=1e-10)
+        ref = zeros(3 * wl.n_bodies)
+        ctx.mobility(dev(wl.F), ref)
+        assert info["gmres_residual"] <= 1e-10
+        assert relerr(host(U), host(ref)) < 1e-8
+
+
+def test_batched_mixed_mobility_reaches_fp64_tolerance():
+    import paper_1709_01480_amd as fb
+    wls = [W.make(n) for n in NAMES]
+    b = _batch(wls, precision=fb.PREC_MIXED, tol_gmres=1e-8)
+    Fs = [dev(wl.F) for wl in wls]
+    Us = [zeros(3 * wl.n_bodies) for wl in wls]
+    infos = b.mobility(Fs, Us)
+    for wl, U, info in zip(wls, Us, infos):
+        assert info["gmres_residual"] <= 1e-8
+        ctx = make_ctx(wl, tol_gmres=1e-10)
+        ref = zeros(3 * wl.n_bodies)
+        ctx.mobility(dev(wl.F), ref)
+        assert relerr(host(U), host(ref)) < 1e-6
+
+
+def test_batched_em_rfd_matches_each_system():
+    wls = [W.make(n) for n in NAMES[:2]]
+    log("batch em-rfd")
+    b = _batch(wls, tol_gmres=1e-10, tol_lanczos=1e-10)
+    args = []
+    for m, wl in zip(b.members, wls):
+        M = m.get_derived()["grid_M"]
+        Wr, Wg, Wt = W.noise(wl, M)
+        args.append((dev(wl.F), dev(Wr), dev(Wg), dev(Wt)))
+    dQs = [zeros(3 * wl.n_bodies) for wl in wls]
+    delta = 1e-2 * wls[0].a
+    infos = b.step_em_rfd(1e-3, delta, [a[0] for a in args], [a[1] for a in args], [a[2] for a in args],
+                          [a[3] for a in args], dQs)
+    for wl, a, dQ, info in zip(wls, args, dQs, infos):
+        assert info["gmres_solves"] == 3
+        ctx = make_ctx(wl, tol_gmres=1e-10, tol_lanczos=1e-10)
+        ref = zeros(3 * wl.n_bodies)
+        ctx.step_em_rfd(1e-3, delta, a[0], a[1], a[2], a[3], ref)
+        assert relerr(host(dQ), host(ref)) < 1e-6, wl.name
+
+
+def test_single_context_batched_rfd_flag():
+    import paper_1709_01480_amd as fb
+    wl = W.make("starfish4")
+    ctx0 = make_ctx(wl, tol_gmres=1e-10, tol_lanczos=1e-10)
+    ctx1 = make_ctx(wl, tol_gmres=1e-10, tol_lanczos=1e-10, flags=fb.FLAG_BATCH_RFD)
+    Wr, Wg, Wt = W.noise(wl, ctx0.get_derived()["grid_M"])
+    d0, d1 = zeros(3 * wl.n_bodies), zeros(3 * wl.n_bodies)
+    delta = 1e-2 * wl.a
+    i0 = ctx0.step_em_rfd(1e-3, delta, dev(wl.F), dev(Wr), dev(Wg), dev(Wt), d0)
+    i1 = ctx1.step_em_rfd(1e-3, delta, dev(wl.F), dev(Wr), dev(Wg), dev(Wt), d1)
+    assert i1["gmres_solves"] == 3
+    assert relerr(host(d1), host(d0)) < 1e-6
+    # the configuration is restored in both
+    U0, U1 = zeros(3 * wl.n_bodies), zeros(3 * wl.n_bodies)
+    ctx0.mobility(dev(wl.F), U0)
+    ctx1.mobility(dev(wl.F), U1)
+    assert relerr(host(U1), host(U0)) < 1e-8
+    del i0
