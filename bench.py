@@ -7,7 +7,12 @@ seeded, and resident in HBM before timing starts.  One step = one
 Euler-Maruyama random-finite-difference step (Lanczos square root, random
 Fourier field, three GMRES mobility solves, geometry rebuilds).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms fp64,mixed+batched+learned]
+
+Two forms are timed on the same inputs: the plain FP64 method and the
+mixed-precision form with batched EM-RFD solves and the learned preconditioner
+correction (trained, untimed, on other seeded configurations of the workload).
+`value` is the second form's steps/s; both forms are reported under "forms".
 """
 import argparse
 import json
@@ -80,17 +85,162 @@ def cpu_baseline(wl, X_nodes, prm, matvecs_per_step, budget_s=20.0):
     }
 
 
+FORMS = {
+    # plain method: FP64 everywhere, block-diagonal preconditioner, solves one after another
+    "fp64": dict(precision="fp64", batch_rfd=False, learned=False),
+    # FP32 matvec inside FP64 Krylov (iterative refinement), the three EM-RFD solves in one
+    # batched launch set, learned preconditioner correction trained beforehand on solves
+    "mixed+batched+learned": dict(precision="mixed", batch_rfd=True, learned=True),
+}
+
+
+def run_form(name, form, wl, args, fb, W, np, torch):
+    prec = fb.PREC_FP64 if form["precision"] == "fp64" else fb.PREC_MIXED
+    flags = fb.FLAG_BATCH_RFD if form["batch_rfd"] else 0
+    ctx = fb.Context(**wl.params(), precision=prec, flags=flags)
+    sid = ctx.add_shape(fb.starfish(wl.r_s, wl.b, wl.n_arm, wl.n_p))
+    ctx.set_bodies(np.full(wl.n_bodies, sid), wl.q, wl.theta)
+    d = ctx.get_derived()
+    M, N = d["grid_M"], d["n_nodes"]
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+    train = None
+    if form["learned"]:
+        # untimed: train the correction on random-force solves of other configurations of the workload
+        ctx.mlp_init(seed=7, sym_order=wl.n_arm)
+        t0 = time.perf_counter()
+        for k in range(args.train_configs):
+            w2 = W.make(args.config, seed=500 + k)
+            ctx.set_bodies(np.full(w2.n_bodies, sid), w2.q, w2.theta)
+            train = ctx.mlp_train(n_solves=2, epochs=20, lr=2e-3, seed=k)
+        ctx.set_bodies(np.full(wl.n_bodies, sid), wl.q, wl.theta)
+        ctx.mlp_use(True)
+        log("%s: trained on %d configurations in %.1f s (last: %s)"
+            % (name, args.train_configs, time.perf_counter() - t0, train))
+    W_r, W_grid, W_t = W.noise(wl, M)
+    F, Wr, Wg, Wt = dev(wl.F), dev(W_r), dev(W_grid), dev(W_t)
+    dQ = torch.zeros(3 * wl.n_bodies, dtype=torch.float64, device="cuda")
+    delta = wl.a * wl.tol_gmres ** (1.0 / 3.0)
+    # matvec throughput
+    mu = dev(np.random.default_rng(1).standard_normal(2 * N))
+    out = torch.zeros(2 * N, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        ctx.apply_M(mu, out, fb.PART_ALL)
+    ctx.set_timing(True)  # per-kernel events of single-system launches (roofline)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.matvecs):
+        ctx.apply_M(mu, out, fb.PART_ALL)
+    torch.cuda.synchronize()
+    t_mv = (time.perf_counter() - t0) / args.matvecs
+    kt_mv = {k: ctx.kernel_time(k) for k in KERNEL_CLASSES}
+    log("%s matvec: %.3f ms (%.1f Mnodes/s)" % (name, 1e3 * t_mv, N / t_mv / 1e6))
+    # EM-RFD steps
+    for i in range(args.warmup):
+        info = ctx.step_em_rfd(wl.dt, delta, F, Wr, Wg, Wt, dQ)
+        log("%s warmup step %d: %s" % (name, i, info))
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for i in range(args.steps):
+        infos.append(ctx.step_em_rfd(wl.dt, delta, F, Wr, Wg, Wt, dQ))
+        log("%s step %d: %s" % (name, i, infos[-1]))
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / args.steps
+    kt = {k: ctx.kernel_time(k) for k in KERNEL_CLASSES}
+    ctx.set_timing(False)
+    matvecs = (sum(i["gmres_iters"] + i["gmres_solves"] + 1 for i in infos) + sum(i["lanczos_iters"] for i in infos))
+    log("%s kernel ms per step: %s" % (name, {k: round(v[0] / args.steps, 3) for k, v in kt.items()}))
+    x = torch.zeros(2 * N, dtype=torch.float64, device="cuda")
+    ctx.get_nodes(x)
+    res = {
+        "steps_per_s": 1.0 / t_step, "ms_per_step": 1e3 * t_step,
+        "matvec": {"value": N / t_mv / 1e6, "unit": "Mnodes/s", "ms": 1e3 * t_mv},
+        "solver": {"gmres_iters_per_solve": sum(i["gmres_iters"] for i in infos)
+                   / max(1, sum(i["gmres_solves"] for i in infos)),
+                   "lanczos_iters": sum(i["lanczos_iters"] for i in infos) / args.steps,
+                   "matvecs_per_step": matvecs / args.steps,
+                   "max_residual": max(i["gmres_residual"] for i in infos)},
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
+        "dtype": "f64" if prec == fb.PREC_FP64 else "f32+f64",
+    }
+    if train:
+        res["training"] = train
+    ctx.close()
+    return res, kt_mv, x.cpu().numpy(), d
+
+
+def kernel_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if
+    the kernel source is unchanged since the counters were taken (else None)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "%s_counters.md" % kernel)
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    h = re.search(r"source_sha256:\s*([0-9a-f]+)", txt)
+    src = os.path.join(ROOT, "paper_1709_01480_amd", "csrc", KERNEL_SOURCE.get(kernel, ""))
+    if not (m and h and os.path.exists(src)):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
+        return None
+    return float(m.group(1))
+
+
+KERNEL_CLASSES = ("pair", "pair32", "alpert", "spread", "spread32", "interp", "interp32", "fft", "fft32",
+                  "multiplier", "multiplier32", "precond", "blas", "mlp")
+# classes timed as exactly one kernel (candidates for the roofline line) and their sources
+KERNEL_SOURCE = {"pair": "kernels_real.hip", "pair32": "kernels_real.hip", "spread": "kernels_wave.hip",
+                 "spread32": "kernels_wave.hip", "interp": "kernels_wave.hip", "interp32": "kernels_wave.hip",
+                 "alpert": "kernels_real.hip", "precond": "kernels_la.hip", "multiplier": "kernels_wave.hip",
+                 "multiplier32": "kernels_wave.hip"}
+
+
+def roofline(kt, xh, wl, d):
+    """Dominant single kernel of the single-layer matvec (one system per launch,
+    HIP events on the context's stream around every launch of the timed matvecs)."""
+    N, M = d["n_nodes"], d["grid_M"]
+    dom = max(KERNEL_SOURCE, key=lambda k: kt[k][0])
+    f32 = dom.endswith("32")
+    ms, cnt = kt[dom]
+    avg_s = ms / max(cnt, 1) / 1e3
+    traffic = kernel_traffic(dom)
+    if dom.startswith("pair"):
+        npair, ncand = count_pairs(xh, wl.L, d["r_c"], d["n_box"])
+        flops = FLOP_PER_PAIR * npair + FLOP_PER_CANDIDATE * ncand
+        peak = PEAK["fp32_vec"] if f32 else PEAK["fp64_vec"]
+        ach = flops / avg_s / 1e12
+        return {"kernel": "%s (k_pair_ell<%s>)" % (dom, "float, 9" if f32 else "double, 16"), "bound": "alu",
+                "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak, "traffic": traffic,
+                "avg_launch_ms": avg_s * 1e3, "pairs": npair, "candidates": ncand,
+                "flop_per_launch": flops}
+    wb = 4 if f32 else 8
+    grid_bytes = 2 * M * M * wb
+    per = {"spread": 2 * N * 2 * wb + 2 * N * 4 + grid_bytes,
+           "interp": grid_bytes + 2 * N * 2 * wb + 2 * N * 4 + 2 * N * 8 * 2,
+           "multiplier": 2 * 2 * M * (M // 2 + 1) * 2 * wb,
+           "precond": 4 * (2 * N + 3 * wl.n_bodies) * 8,
+           "alpert": 2 * N * 8 * 3}
+    b = per[dom.rstrip("32")]
+    ach = b / avg_s / 1e9
+    return {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK["hbm"], "unit": "GB/s",
+            "frac": ach / PEAK["hbm"], "traffic": traffic, "avg_launch_ms": avg_s * 1e3, "bytes_per_launch": b}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--forms", default=",".join(FORMS), help="comma-separated subset of %s" % list(FORMS))
     ap.add_argument("--config", default="starfish10k")
     ap.add_argument("--matvecs", type=int, default=20)
+    ap.add_argument("--train-configs", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="step", choices=["step", "matvec", "copy"],
-                    help="step: the EM-RFD benchmark; matvec: only single-layer matvecs "
+                    help="step: the EM-RFD benchmark; matvec: only single-layer matvecs of the first form "
                          "(short runs for counter collection); copy: a plain 1 GiB device copy "
                          "used to calibrate the HBM byte counters")
     args = ap.parse_args()
@@ -116,114 +266,52 @@ def main():
         print(json.dumps({"mode": "copy", "bytes_read": 8 * n, "bytes_written": 8 * n, "copies": args.steps}))
         return
     wl = W.make(args.config)
-    prec = fb.PREC_FP64 if args.precision == "fp64" else fb.PREC_MIXED
+    names = [f for f in args.forms.split(",") if f]
     log("workload %s: %d bodies x %d nodes" % (args.config, wl.n_bodies, wl.n_p))
-    ctx = fb.Context(**wl.params(), precision=prec)
-    sid = ctx.add_shape(fb.starfish(wl.r_s, wl.b, wl.n_arm, wl.n_p))
-    ctx.set_bodies(np.full(wl.n_bodies, sid), wl.q, wl.theta)
-    d = ctx.get_derived()
-    M = d["grid_M"]
-    N = d["n_nodes"]
-    log("derived: %s" % d)
-    W_r, W_grid, W_t = W.noise(wl, M)
-    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
-    F, Wr, Wg, Wt = dev(wl.F), dev(W_r), dev(W_grid), dev(W_t)
-    dQ = torch.zeros(3 * wl.n_bodies, dtype=torch.float64, device="cuda")
-    delta = wl.a * wl.tol_gmres ** (1.0 / 3.0)
-
-    # ---- matvec throughput
-    mu = dev(np.random.default_rng(1).standard_normal(2 * N))
-    out = torch.zeros(2 * N, dtype=torch.float64, device="cuda")
-    for _ in range(3):
-        ctx.apply_M(mu, out, fb.PART_ALL)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.matvecs):
-        ctx.apply_M(mu, out, fb.PART_ALL)
-    torch.cuda.synchronize()
-    t_mv = (time.perf_counter() - t0) / args.matvecs
-    log("matvec: %.3f ms (%.1f Mnodes/s)" % (1e3 * t_mv, N / t_mv / 1e6))
     if args.mode == "matvec":
-        print(json.dumps({"mode": "matvec", "nodes": N, "ms": 1e3 * t_mv, "Mnodes/s": N / t_mv / 1e6}))
+        form = FORMS[names[0]]
+        prec = fb.PREC_FP64 if form["precision"] == "fp64" else fb.PREC_MIXED
+        ctx = fb.Context(**wl.params(), precision=prec)
+        sid = ctx.add_shape(fb.starfish(wl.r_s, wl.b, wl.n_arm, wl.n_p))
+        ctx.set_bodies(np.full(wl.n_bodies, sid), wl.q, wl.theta)
+        N = ctx.get_derived()["n_nodes"]
+        mu = torch.as_tensor(np.random.default_rng(1).standard_normal(2 * N)).cuda()
+        out = torch.zeros(2 * N, dtype=torch.float64, device="cuda")
+        for _ in range(args.matvecs):
+            ctx.apply_M(mu, out, fb.PART_ALL)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "matvec", "form": names[0], "nodes": N, "matvecs": args.matvecs}))
         ctx.close()
         return
-
-    # ---- EM-RFD steps
-    for i in range(args.warmup):
-        info = ctx.step_em_rfd(wl.dt, delta, F, Wr, Wg, Wt, dQ)
-        log("warmup step %d: %s" % (i, info))
-    ctx.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = []
-    for i in range(args.steps):
-        infos.append(ctx.step_em_rfd(wl.dt, delta, F, Wr, Wg, Wt, dQ))
-        log("step %d: %s" % (i, infos[-1]))
-    torch.cuda.synchronize()
-    t_step = (time.perf_counter() - t0) / args.steps
-    kt = {k: ctx.kernel_time(k) for k in ("pair", "alpert", "spread", "interp", "fft", "multiplier",
-                                          "precond", "blas")}
-    ctx.set_timing(False)
-    matvecs = (sum(i["gmres_iters"] + i["gmres_solves"] + 1 for i in infos) + sum(i["lanczos_iters"] for i in infos))
-    matvecs_per_step = matvecs / args.steps
-    log("kernel ms per step: %s" % {k: round(v[0] / args.steps, 3) for k, v in kt.items()})
-
-    # ---- roofline of the dominant kernel
-    dom = max(kt, key=lambda k: kt[k][0])
-    ms, cnt = kt[dom]
-    avg_s = ms / max(cnt, 1) / 1e3
-    x = torch.zeros(2 * N, dtype=torch.float64, device="cuda")
-    ctx.get_nodes(x)
-    xh = x.cpu().numpy()
-    roof = None
-    if dom == "pair":
-        npair, ncand = count_pairs(xh, wl.L, d["r_c"], d["n_box"])
-        flops = FLOP_PER_PAIR * npair + FLOP_PER_CANDIDATE * ncand
-        peak = PEAK["fp64_vec"] if prec == fb.PREC_FP64 else PEAK["fp32_vec"]
-        ach = flops / avg_s / 1e12
-        roof = {"kernel": "pair", "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": None, "avg_launch_ms": avg_s * 1e3,
-                "pairs": npair, "candidates": ncand}
-    else:
-        wb = 8 if prec == fb.PREC_FP64 else 4
-        grid_bytes = 2 * M * M * wb
-        per = {"spread": 2 * N * 2 * wb + 2 * N * 4 + grid_bytes,     # positions, mu, anchors in; grid out
-               "interp": grid_bytes + 2 * N * 2 * wb + 2 * N * 4 + 2 * N * 8 * 2,
-               "fft": 2 * grid_bytes + 2 * grid_bytes,
-               "multiplier": 2 * 2 * M * (M // 2 + 1) * 2 * wb,
-               "precond": 4 * (2 * N + 3 * wl.n_bodies) * 8,
-               "blas": 2 * (2 * N + 3 * wl.n_bodies) * 8,
-               "alpert": 2 * N * 8 * 3}
-        b = per.get(dom, 0)
-        ach = b / avg_s / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK["hbm"], "unit": "GB/s",
-                "frac": ach / PEAK["hbm"], "traffic": None, "avg_launch_ms": avg_s * 1e3}
-
+    results, kts = {}, {}
+    for nm in names:
+        results[nm], kts[nm], xh, d = run_form(nm, FORMS[nm], wl, args, fb, W, np, torch)
+    head = names[-1]
+    N, M = d["n_nodes"], d["grid_M"]
     res = {
-        "metric": METRIC, "value": 1.0 / t_step, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * t_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if prec == fb.PREC_FP64 else "f32+f64", "data": "synthetic",
+        "metric": METRIC, "value": results[head]["steps_per_s"], "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": results[head]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": results[head]["dtype"],
+        "data": "synthetic",
         "config": {"workload": "%s: %d five-arm starfish x %d nodes (%d nodes), area fraction 0.3, grid %d^2, "
                                "tol 1e-6, EM-RFD step (Lanczos + random field + 3 GMRES solves)"
                                % (args.config, wl.n_bodies, wl.n_p, N, M),
-                   "precision": args.precision, "gmres_tol": wl.tol_gmres, "lanczos_tol": wl.tol_lanczos},
-        "matvec": {"value": N / t_mv / 1e6, "unit": "Mnodes/s", "ms": 1e3 * t_mv},
-        "solver": {"gmres_iters_per_solve": sum(i["gmres_iters"] for i in infos) / max(1, sum(i["gmres_solves"] for i in infos)),
-                   "lanczos_iters": sum(i["lanczos_iters"] for i in infos) / args.steps,
-                   "matvecs_per_step": matvecs_per_step},
-        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
-        "roofline": roof,
+                   "form": head, "gmres_tol": wl.tol_gmres, "lanczos_tol": wl.tol_lanczos},
+        "matvec": results[head]["matvec"],
+        "forms": results,
+        "roofline": roofline(kts[head], xh, wl, d),
         "cpu_baseline": None,
     }
+    if "fp64" in results and head != "fp64":
+        res["speedup_vs_fp64_form"] = results[head]["steps_per_s"] / results["fp64"]["steps_per_s"]
     if not args.no_cpu_baseline:
         from oracle import fbim as OF
         prm = OF.derive_params(wl.L, wl.tol_ewald, n_box=wl.n_box, grid_M=wl.grid_M, xi=wl.xi, P=wl.P)
         geo = OF.geometry_from_workload(wl)
         Xn, _ = OF.nodes(geo)
         log("cpu baseline ...")
-        res["cpu_baseline"] = cpu_baseline(wl, Xn, prm, matvecs_per_step)
+        res["cpu_baseline"] = cpu_baseline(wl, Xn, prm, results[head]["solver"]["matvecs_per_step"])
     print(json.dumps(res), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

@@ -323,7 +323,9 @@ fbim_status fbim_mlp_use(fbim_ctx *ctx, int32_t on);
 /* Kernel timing (for measurement): when enabled, device events bracket each
  * launch of the named kernel class; fbim_kernel_time returns the summed
  * milliseconds and launch count since the last reset.  Classes: "pair",
- * "alpert", "spread", "interp", "fft", "multiplier", "precond", "blas", "mlp". */
+ * "alpert", "spread", "interp", "fft", "multiplier", "precond", "blas", "mlp"; in a mixed
+ * context the FP32 launches are counted separately as "pair32", "spread32",
+ * "interp32", "fft32" and "multiplier32". */
 fbim_status fbim_set_timing(fbim_ctx *ctx, int32_t enable);
 fbim_status fbim_kernel_time(fbim_ctx *ctx, const char *name, double *ms, int64_t *count);
 

@@ -451,7 +451,7 @@ fbim_status run_operator(BatchEngine *E, Tables &T, bool f32, bool saddle) {
   const int p = f32 ? 1 : 0;
   EHIP(E, launch_gather2_batch(T.gcell[p], T.bg_nodes, p, s));
   {
-    Timer t(tc, "pair");
+    Timer t(tc, f32 ? "pair32" : "pair");
     EHIP(E, launch_pair_batch(T.pair[p], T.bg_pair, p, tc->d_e1tab, tc->d_e1tab32, s));
   }
   {
@@ -460,29 +460,29 @@ fbim_status run_operator(BatchEngine *E, Tables &T, bool f32, bool saddle) {
   }
   EHIP(E, launch_gather2_batch(T.gtile[p], T.bg_nodes, p, s));
   {
-    Timer t(tc, "spread");
+    Timer t(tc, f32 ? "spread32" : "spread");
     EHIP(E, launch_spread_batch(T.spr[p], T.bg_tiles, p, s));
   }
   {
-    Timer t(tc, "fft");
+    Timer t(tc, f32 ? "fft32" : "fft");
     for (auto &k : E->classes) {
       void *in[1] = {f32 ? (void *)k.grid32 : (void *)k.grid}, *o[1] = {f32 ? (void *)k.spec32 : (void *)k.spec};
       EFFT(E, rocfft_execute(f32 ? k.fwd32 : k.fwd, in, o, E->einfo));
     }
   }
   {
-    Timer t(tc, "multiplier");
+    Timer t(tc, f32 ? "multiplier32" : "multiplier");
     EHIP(E, launch_multiplier_batch(T.mul[p], T.bg_spec, p, 0, s));
   }
   {
-    Timer t(tc, "fft");
+    Timer t(tc, f32 ? "fft32" : "fft");
     for (auto &k : E->classes) {
       void *in[1] = {f32 ? (void *)k.spec32 : (void *)k.spec}, *o[1] = {f32 ? (void *)k.grid32 : (void *)k.grid};
       EFFT(E, rocfft_execute(f32 ? k.inv32 : k.inv, in, o, E->einfo));
     }
   }
   {
-    Timer t(tc, "interp");
+    Timer t(tc, f32 ? "interp32" : "interp");
     EHIP(E, launch_interp_batch(T.itp[p], T.bg_tiles, p, s));
   }
   if (saddle) EHIP(E, launch_rigid_batch(T.rig, T.bg_nodes, T.bg_bodies4, s));

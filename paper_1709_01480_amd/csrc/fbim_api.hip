@@ -342,7 +342,7 @@ fbim_status apply_M(fbim_ctx *c, const double *mu, double *out, unsigned parts) 
     const PairLists pl = c->lists();
     if (f32) {
       HIPCHK(c, launch_gather2f(N, c->d_cperm, mu, c->d_mus32, s));
-      Timer t(c, "pair");
+      Timer t(c, "pair32");
       HIPCHK(c, launch_pair_f32(pl, a, c->d_xs32, c->d_mus32, out, s));
     } else {
       HIPCHK(c, launch_gather2(N, c->d_cperm, mu, c->d_mus, s));
@@ -372,24 +372,24 @@ fbim_status apply_M(fbim_ctx *c, const double *mu, double *out, unsigned parts) 
     if (f32) {
       HIPCHK(c, launch_gather2f(N, c->d_tperm, mu, c->d_mut32, s));
       {
-        Timer t(c, "spread");
+        Timer t(c, "spread32");
         HIPCHK(c, launch_spread_f32(w, c->d_xt32, c->d_mut32, c->d_grid32, s));
       }
       {
-        Timer t(c, "fft");
+        Timer t(c, "fft32");
         void *in[1] = {c->d_grid32}, *o[1] = {c->d_spec32};
         FFTCHK(c, rocfft_execute(c->fwd32, in, o, c->einfo));
       }
       {
-        Timer t(c, "multiplier");
+        Timer t(c, "multiplier32");
         HIPCHK(c, launch_multiplier_f32(c->d.M, c->d.L, c->d.xi, c->d.eta_s, scale, 0, c->d_spec32, s));
       }
       {
-        Timer t(c, "fft");
+        Timer t(c, "fft32");
         void *in[1] = {c->d_spec32}, *o[1] = {c->d_grid32};
         FFTCHK(c, rocfft_execute(c->inv32, in, o, c->einfo));
       }
-      Timer t(c, "interp");
+      Timer t(c, "interp32");
       HIPCHK(c, launch_interp_f32(w, c->d_xt32, c->d_tperm, c->d_grid32, out, s));
     } else {
       HIPCHK(c, launch_gather2(N, c->d_tperm, mu, c->d_mut, s));
