@@ -186,7 +186,9 @@ fbim_status fbim_brownian_velocity(fbim_ctx *ctx, double dt, const double *F, co
 
 /* One Euler-Maruyama step with the centred random finite difference (eq. 4.3):
  *   dQ = dt U0 + dt kT/delta [N(Q + delta/2 Wt) Wt - N(Q - delta/2 Wt) Wt]
- * with U0 from fbim_brownian_velocity at Q.  DEVICE F[3n], W_r[2N],
+ * with U0 from fbim_brownian_velocity at Q.  Without FBIM_FLAG_BATCH_RFD the solve
+ * at Q - delta/2 Wt starts from the solution at Q + delta/2 Wt (same right-hand
+ * side, configurations delta apart); every solve stops on its own true residual.  DEVICE F[3n], W_r[2N],
  * W_grid[2MM], W_tilde[3n]; DEVICE dQ[3n] = (dq_x, dq_y, dtheta) per body.
  * If apply != 0 the bodies are moved by dQ afterwards; otherwise the
  * configuration is restored to Q. */

@@ -225,8 +225,8 @@ fbim_status build_tables(BatchEngine *E, const std::vector<int> &list, Tables &T
     const size_t M = c->d.M, gsz = 2 * M * M, ssz = 4 * M * (M / 2 + 1);
     for (int p = 0; p < 2; ++p) {
       const bool f = p == 1;
-      gc[p].push_back(GatherJob{c->N, c->d_cperm, c->d_t1, f ? (void *)c->d_mus32 : (void *)c->d_mus});
-      gt[p].push_back(GatherJob{c->N, c->d_tperm, c->d_t1, f ? (void *)c->d_mut32 : (void *)c->d_mut});
+      gc[p].push_back(GatherJob{c->N, c->d_cperm, c->d_t1, f ? (void *)c->d_src32 : (void *)c->d_src64, 1});
+      gt[p].push_back(GatherJob{c->N, c->d_tperm, c->d_t1, f ? (void *)c->d_mut32 : (void *)c->d_mut, 0});
       PairJob j;
       j.N = c->N;
       j.ngroups = c->ngroups;
@@ -238,8 +238,7 @@ fbim_status build_tables(BatchEngine *E, const std::vector<int> &list, Tables &T
       j.cell = c->d.L / c->d.n_box;
       j.xi2 = c->d.xi * c->d.xi;
       j.cG = 1.0 / (4.0 * kPi * c->p.eta);
-      j.xs = f ? (const void *)c->d_xs32 : (const void *)c->d_xs;
-      j.mus = f ? (const void *)c->d_mus32 : (const void *)c->d_mus;
+      j.src = f ? (const void *)c->d_src32 : (const void *)c->d_src64;
       j.out = c->d_by;
       pj[p].push_back(j);
       const WaveArgs w = wave_args(c);

@@ -110,8 +110,9 @@ struct fbim_ctx {
       *d_gsize = nullptr, *d_ell = nullptr;
 
   // matvec scratch
-  double *d_mus = nullptr, *d_mut = nullptr;
-  float *d_xs32 = nullptr, *d_mus32 = nullptr, *d_xt32 = nullptr, *d_mut32 = nullptr;
+  double *d_mut = nullptr;
+  double *d_src64 = nullptr;  // packed pair sources (x, y, mu_x, mu_y), cell order
+  float *d_src32 = nullptr, *d_xt32 = nullptr, *d_mut32 = nullptr;
   double *d_grid = nullptr, *d_spec = nullptr;
   float *d_grid32 = nullptr, *d_spec32 = nullptr;
   rocfft_plan fwd = nullptr, inv = nullptr, fwd32 = nullptr, inv32 = nullptr;

@@ -282,7 +282,7 @@ fbim_status build_geometry(fbim_ctx *c) {
   HIPCHK(c, launch_scatter(N, c->d_ckey, c->d_cstart, c->d_ccursor, c->d_cperm, s));
   HIPCHK(c, launch_sort_bins(c->ncell, c->d_cstart, c->d_cperm, s));
   HIPCHK(c, launch_cell_local(N, c->d_cperm, c->d_ckey, c->d_x, c->d.n_box, c->d.L / c->d.n_box, c->d_xs,
-                              c->mixed ? c->d_xs32 : nullptr, s));
+                              c->d_src64, c->mixed ? c->d_src32 : nullptr, s));
   // tiles
   HIPCHK(c, hipMemsetAsync(c->d_tcount, 0, c->ntile * sizeof(int), s));
   HIPCHK(c, hipMemsetAsync(c->d_tcursor, 0, c->ntile * sizeof(int), s));
@@ -341,13 +341,13 @@ fbim_status apply_M(fbim_ctx *c, const double *mu, double *out, unsigned parts) 
     const PairArgs a = c->pair_args();
     const PairLists pl = c->lists();
     if (f32) {
-      HIPCHK(c, launch_gather2f(N, c->d_cperm, mu, c->d_mus32, s));
+      HIPCHK(c, launch_gather_src(N, c->d_cperm, mu, nullptr, c->d_src32, s));
       Timer t(c, "pair32");
-      HIPCHK(c, launch_pair_f32(pl, a, c->d_xs32, c->d_mus32, out, s));
+      HIPCHK(c, launch_pair_f32(pl, a, c->d_src32, out, s));
     } else {
-      HIPCHK(c, launch_gather2(N, c->d_cperm, mu, c->d_mus, s));
+      HIPCHK(c, launch_gather_src(N, c->d_cperm, mu, c->d_src64, nullptr, s));
       Timer t(c, "pair");
-      HIPCHK(c, launch_pair_f64(pl, a, c->d_xs, c->d_mus, out, s));
+      HIPCHK(c, launch_pair_f64(pl, a, c->d_src64, out, s));
     }
   } else {
     HIPCHK(c, launch_fill(2 * (size_t)N, 0.0, out, s));
@@ -546,7 +546,9 @@ fbim_status norm2(fbim_ctx *c, const double *x, size_t n, double &out) {
 }
 
 // right-preconditioned restarted GMRES for the saddle system; b, x device (ntot)
-fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iters, double &relres, int maxit) {
+// warm: start from the x given (else x0 = 0)
+fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iters, double &relres, int maxit,
+                  bool warm = false) {
   const size_t nt = c->ntot;
   hipStream_t s = c->stream;
   const int m = c->restart;
@@ -554,10 +556,10 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
   relres = 0;
   double nb;
   STCHK(norm2(c, b, nt, nb));
-  HIPCHK(c, launch_fill(nt, 0.0, x, s));
+  if (!warm || nb == 0.0) HIPCHK(c, launch_fill(nt, 0.0, x, s));
   if (nb == 0.0) return FBIM_OK;
   std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), hcol(m + 3), y(m);
-  bool first = true;
+  bool first = !warm;
   for (;;) {
     // r = b - A x
     if (first) {
@@ -628,16 +630,30 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
 // contexts: iterative refinement -- the residual b - A x is formed with the
 // FP64 matvec, and each correction solves A d = r with GMRES on the FP32
 // matvec to a relative tolerance of 1e-3.
-fbim_status solve_saddle(fbim_ctx *c, const double *b, double *x, double tol, int &iters, double &relres) {
-  if (!c->mixed) return gmres(c, b, x, tol, iters, relres, c->gmres_max);
+fbim_status solve_saddle(fbim_ctx *c, const double *b, double *x, double tol, int &iters, double &relres,
+                         bool warm = false) {
+  if (!c->mixed) return gmres(c, b, x, tol, iters, relres, c->gmres_max, warm);
   const size_t nt = c->ntot;
   hipStream_t s = c->stream;
   iters = 0;
   double nb;
   STCHK(norm2(c, b, nt, nb));
-  HIPCHK(c, launch_fill(nt, 0.0, x, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_irr, b, nt * sizeof(double), hipMemcpyDeviceToDevice, s));
   relres = nb > 0 ? 1.0 : 0.0;
+  if (warm && nb > 0.0) {
+    // residual of the initial guess, FP64
+    c->cur32 = false;
+    fbim_status st0 = apply_saddle(c, x, c->d_irr);
+    c->cur32 = true;
+    STCHK(st0);
+    HIPCHK(c, launch_axpby(nt, 1.0, b, -1.0, c->d_irr, s));
+    double nr;
+    STCHK(norm2(c, c->d_irr, nt, nr));
+    relres = nr / nb;
+    if (relres <= tol) return FBIM_OK;
+  } else {
+    HIPCHK(c, launch_fill(nt, 0.0, x, s));
+    HIPCHK(c, hipMemcpyAsync(c->d_irr, b, nt * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
   if (nb == 0.0) return FBIM_OK;
   for (int outer = 0; outer < 20; ++outer) {
     int it = 0;
@@ -729,8 +745,9 @@ fbim_status lanczos_sqrt(fbim_ctx *c, const double *b, double *out, int &iters, 
   return st;
 }
 
+// warm: start GMRES from the solution of the previous solve of this context
 fbim_status mobility(fbim_ctx *c, const double *F, const double *slip, double *U, double *mu_out, int &its,
-                     double &res) {
+                     double &res, bool warm = false) {
   const size_t twoN = 2 * (size_t)c->N, nt = c->ntot;
   hipStream_t s = c->stream;
   // b = -[slip; F]
@@ -739,7 +756,7 @@ fbim_status mobility(fbim_ctx *c, const double *F, const double *slip, double *U
   else
     HIPCHK(c, launch_fill(twoN, 0.0, c->d_b, s));
   HIPCHK(c, launch_axpby(3 * (size_t)c->n, -1.0, F, 0.0, c->d_b + twoN, s));
-  fbim_status st = solve_saddle(c, c->d_b, c->d_x2, c->p.tol_gmres, its, res);
+  fbim_status st = solve_saddle(c, c->d_b, c->d_x2, c->p.tol_gmres, its, res, warm);
   if (st != FBIM_OK && st != FBIM_ENOCONV) return st;
   HIPCHK(c, hipMemcpyAsync(U, c->d_x2 + twoN, 3 * (size_t)c->n * sizeof(double), hipMemcpyDeviceToDevice, s));
   if (mu_out) HIPCHK(c, hipMemcpyAsync(mu_out, c->d_x2, twoN * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -921,8 +938,8 @@ void fbim_destroy(fbim_ctx *c) {
   void *ptrs[] = {c->d_ref_arr, c->d_band_arr, c->d_Mp_arr, c->d_Pref_arr, c->d_Nt_arr, c->d_G_arr, c->d_Gp_arr,
                   c->d_band, c->d_np, c->d_shape, c->d_off, c->d_body, c->d_q, c->d_theta, c->d_x,
                   c->d_ckey, c->d_ccount, c->d_cstart, c->d_cperm, c->d_ccursor, c->d_xs, c->d_tkey,
-                  c->d_tcount, c->d_tstart, c->d_tperm, c->d_tcursor, c->d_xt, c->d_anchor, c->d_scal_int, c->d_mus,
-                  c->d_mut, c->d_xs32, c->d_mus32, c->d_xt32, c->d_mut32, c->d_grid, c->d_spec, c->d_grid32,
+                  c->d_tcount, c->d_tstart, c->d_tperm, c->d_tcursor, c->d_xt, c->d_anchor, c->d_scal_int, c->d_src64,
+                  c->d_mut, c->d_src32, c->d_xt32, c->d_mut32, c->d_grid, c->d_spec, c->d_grid32,
                   c->d_spec32, c->d_e1tab, c->d_e1tab32, c->d_V, c->d_w, c->d_t1, c->d_t2, c->d_b, c->d_x2,
                   c->d_r, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
                   c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU, c->d_bx, c->d_by};
@@ -1006,7 +1023,7 @@ fbim_status fbim_set_bodies(fbim_ctx *c, int32_t n, const int32_t *shape_id, con
     HIPCHK(c, dalloc(c->d_tperm, N));
     HIPCHK(c, dalloc(c->d_xt, 2 * N));
     HIPCHK(c, dalloc(c->d_anchor, 2 * N));
-    HIPCHK(c, dalloc(c->d_mus, 2 * N));
+    HIPCHK(c, dalloc(c->d_src64, 4 * N));
     HIPCHK(c, dalloc(c->d_mut, 2 * N));
     c->ngroups = (N + 63) / 64;
     HIPCHK(c, dalloc(c->d_cnt_near, N));
@@ -1016,8 +1033,7 @@ fbim_status fbim_set_bodies(fbim_ctx *c, int32_t n, const int32_t *shape_id, con
     HIPCHK(c, dalloc(c->d_gsize, c->ngroups));
     HIPCHK(c, dalloc(c->d_goff, c->ngroups + 1));
     if (c->mixed) {
-      HIPCHK(c, dalloc(c->d_xs32, 2 * N));
-      HIPCHK(c, dalloc(c->d_mus32, 2 * N));
+      HIPCHK(c, dalloc(c->d_src32, 4 * N));
       HIPCHK(c, dalloc(c->d_xt32, 2 * N));
       HIPCHK(c, dalloc(c->d_mut32, 2 * N));
     }
@@ -1160,7 +1176,9 @@ fbim_status fbim_step_em_rfd(fbim_ctx *c, double dt, double delta, const double 
     STCHK(fbim_set_bodies(c, n, sid.data(), qs.data(), ths.data()));
     int it = 0;
     double res = 0;
-    fbim_status s2 = mobility(c, W_tilde, nullptr, sgn > 0 ? c->d_U4 : c->d_U5, nullptr, it, res);
+    // the second configuration starts from the first one's solution (same right-hand
+    // side, configurations delta apart): the initial residual is O(delta)
+    fbim_status s2 = mobility(c, W_tilde, nullptr, sgn > 0 ? c->d_U4 : c->d_U5, nullptr, it, res, sgn < 0);
     if (s2 != FBIM_OK && s2 != FBIM_ENOCONV) return s2;
     if (s2 != FBIM_OK) worst = s2;
     if (info) {

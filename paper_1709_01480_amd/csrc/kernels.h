@@ -32,9 +32,13 @@ hipError_t launch_gather2f(int N, const int *perm, const double *src, float *dst
 // tile order: nearest grid indices a = floor(x / h + 1/2) and offsets x - a h (FP64, and FP32 if off32)
 hipError_t launch_anchors(int N, const int *tperm, const double *x, double h, int *anchor, double *off64,
                           float *off32, hipStream_t s);
-// cell order: coordinates relative to the node's cell corner (FP64, and FP32 if loc32)
+// cell order: coordinates relative to the node's cell corner (loc64 FP64 pairs; and the
+// (x, y) halves of the packed source records src64 and, if given, src32)
 hipError_t launch_cell_local(int N, const int *cperm, const int *key, const double *x, int nb, double cell,
-                             double *loc64, float *loc32, hipStream_t s);
+                             double *loc64, double *src64, float *src32, hipStream_t s);
+// packed pair-kernel sources: (x, y) from launch_cell_local, densities here:
+// src[i].zw = mu[perm[i]] (src64: double4 records, src32: float4 records)
+hipError_t launch_gather_src(int N, const int *perm, const double *mu, double *src64, float *src32, hipStream_t s);
 
 // closest approach of nodes of distinct bodies (cell list, absolute positions xa); flag set if < thresh
 hipError_t launch_overlap(int N, const int *cell_start, const int *perm, const double *xa, const int *body,
@@ -61,10 +65,9 @@ struct PairLists {
 hipError_t launch_pair_lists(const PairArgs &a, PairLists &pl, const double *xs, int mode, hipStream_t s);
 // gnn, gnf and gsize[g] = 64 (gnn + gnf) from the counts
 hipError_t launch_group_rows(PairLists &pl, int *gsize, hipStream_t s);
-hipError_t launch_pair_f64(const PairLists &pl, const PairArgs &a, const double *xs, const double *mus, double *out,
-                           hipStream_t s);
-hipError_t launch_pair_f32(const PairLists &pl, const PairArgs &a, const float *xs, const float *mus, double *out,
-                           hipStream_t s);
+// src: packed (x, y, mu_x, mu_y) records in cell order (launch_cell_local + launch_gather_src)
+hipError_t launch_pair_f64(const PairLists &pl, const PairArgs &a, const double *src, double *out, hipStream_t s);
+hipError_t launch_pair_f32(const PairLists &pl, const PairArgs &a, const float *src, double *out, hipStream_t s);
 hipError_t launch_fill_int(size_t n, int v, int *y, hipStream_t s);
 
 // Alpert band: out[i] += R_b A_ref R_b^T mu (per node); accumulate=1 adds
@@ -210,12 +213,13 @@ struct GatherJob {  // dst[i] = src[perm[i]] for N (x, y) pairs; dst FP64 or FP3
   const int *perm;
   const double *src;
   void *dst;
+  int packed;  // 1: dst holds 4-vector records and receives their (z, w) halves
 };
 struct PairJob {  // one system's real-space pair sum (launch_pair_f64 / _f32 arguments)
   int N, ngroups;
   const int *perm, *goff, *gnn, *gnf, *ell;
   double cell, xi2, cG;
-  const void *xs, *mus;
+  const void *src;  // packed (x, y, mu_x, mu_y) records in cell order (double4 or float4)
   double *out;
 };
 struct AlpertJob {

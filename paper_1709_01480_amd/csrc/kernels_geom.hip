@@ -200,10 +200,11 @@ __global__ __launch_bounds__(256) void k_gather2_batch(const GatherJob *__restri
   const int i = (blockIdx.x - bg.begin[s]) * 256 + threadIdx.x;
   if (i >= j.N) return;
   const double2 v = reinterpret_cast<const double2 *>(j.src)[j.perm[i]];
+  const int k = j.packed ? 2 * i + 1 : i;  // packed records: the (z, w) half of record i
   if (f32)
-    reinterpret_cast<float2 *>(j.dst)[i] = make_float2((float)v.x, (float)v.y);
+    reinterpret_cast<float2 *>(j.dst)[k] = make_float2((float)v.x, (float)v.y);
   else
-    reinterpret_cast<double2 *>(j.dst)[i] = v;
+    reinterpret_cast<double2 *>(j.dst)[k] = v;
 }
 
 hipError_t launch_gather2_batch(const GatherJob *jobs, BatchGrid bg, int f32, hipStream_t s) {
@@ -238,21 +239,45 @@ hipError_t launch_anchors(int N, const int *tperm, const double *x, double h, in
 // Cell-ordered coordinates relative to the lower-left corner of the node's cell.
 __global__ void k_cell_local(int N, const int *__restrict__ cperm, const int *__restrict__ key,
                              const double *__restrict__ x, int nb, double cell, double2 *__restrict__ loc64,
-                             float2 *__restrict__ loc32) {
+                             double2 *__restrict__ src64, float4 *__restrict__ src32) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
   const int i = cperm[k];
   const int c = key[i];
   const double lx = x[2 * i] - (c % nb) * cell, ly = x[2 * i + 1] - (c / nb) * cell;
   loc64[k] = make_double2(lx, ly);
-  if (loc32) loc32[k] = make_float2((float)lx, (float)ly);
+  src64[2 * k] = make_double2(lx, ly);
+  if (src32) {
+    float4 r = src32[k];
+    r.x = (float)lx;
+    r.y = (float)ly;
+    src32[k] = r;
+  }
 }
 
 hipError_t launch_cell_local(int N, const int *cperm, const int *key, const double *x, int nb, double cell,
-                             double *loc64, float *loc32, hipStream_t s) {
+                             double *loc64, double *src64, float *src32, hipStream_t s) {
   if (N == 0) return hipSuccess;
   hipLaunchKernelGGL(k_cell_local, dim3((N + 255) / 256), dim3(256), 0, s, N, cperm, key, x, nb, cell,
-                     (double2 *)loc64, (float2 *)loc32);
+                     (double2 *)loc64, (double2 *)src64, (float4 *)src32);
+  return hipGetLastError();
+}
+
+__global__ void k_gather_src(int N, const int *__restrict__ perm, const double2 *__restrict__ mu,
+                             double2 *__restrict__ src64, float2 *__restrict__ src32) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double2 v = mu[perm[i]];
+  if (src32)
+    src32[2 * i + 1] = make_float2((float)v.x, (float)v.y);
+  else
+    src64[2 * i + 1] = v;
+}
+
+hipError_t launch_gather_src(int N, const int *perm, const double *mu, double *src64, float *src32, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_src, dim3((N + 255) / 256), dim3(256), 0, s, N, perm, (const double2 *)mu,
+                     (double2 *)src64, (float2 *)src32);
   return hipGetLastError();
 }
 

@@ -166,39 +166,57 @@ __global__ void k_group_rows(int N, int ngroups, const int *__restrict__ cnt_nea
 
 // real-space pair sum over the neighbour lists: one thread per cell-sorted
 // target; `blk` is the block's index within its system (256 threads = 4 groups)
+// Packed source records: (x, y, mu_x, mu_y) in one 16-byte (FP32) or 32-byte
+// (FP64) record per cell-sorted node, so a pair gathers one record.
+template <typename T> struct Rec;
+template <> struct Rec<float> {
+  __device__ static inline float4 load(const void *p, int i) { return reinterpret_cast<const float4 *>(p)[i]; }
+};
+template <> struct Rec<double> {
+  __device__ static inline double4 load(const void *p, int i) {
+    const double2 *q = reinterpret_cast<const double2 *>(p) + 2 * i;
+    const double2 a = q[0], b = q[1];
+    return make_double4(a.x, a.y, b.x, b.y);
+  }
+};
+
+// FP32 sums are compensated (Kahan); FP64 sums of ~50 terms need not be
 template <typename T, int DEG>
 __device__ void pair_ell_body(const PairJob &j, const T *__restrict__ tab, int blk) {
-  using V2 = typename Vec2<T>::type;
-  const V2 *__restrict__ xs = reinterpret_cast<const V2 *>(j.xs);
-  const V2 *__restrict__ mus = reinterpret_cast<const V2 *>(j.mus);
+  constexpr bool kKahan = sizeof(T) == 4;
   const T cell = (T)j.cell, xi2 = (T)j.xi2, cG = (T)j.cG;
   const int t = blk * 256 + threadIdx.x;
   const int g = t >> 6, lane = t & 63;
   if (g >= j.ngroups) return;  // whole wave
   T tx = 0, ty = 0;
   if (t < j.N) {
-    const auto p = xs[t];
+    const auto p = Rec<T>::load(j.src, t);
     tx = p.x;
     ty = p.y;
   }
   const int base = j.goff[g], nn = j.gnn[g], nf = j.gnf[g];
-  T vx = 0, vy = 0, kx = 0, ky = 0;  // Kahan-compensated sums
+  T vx = 0, vy = 0, kx = 0, ky = 0;
   auto add = [&](T a, T b) {
-    T y = a - kx;
-    T s2 = vx + y;
-    kx = (s2 - vx) - y;
-    vx = s2;
-    y = b - ky;
-    s2 = vy + y;
-    ky = (s2 - vy) - y;
-    vy = s2;
+    if (kKahan) {
+      T y = a - kx;
+      T s2 = vx + y;
+      kx = (s2 - vx) - y;
+      vx = s2;
+      y = b - ky;
+      s2 = vy + y;
+      ky = (s2 - vy) - y;
+      vy = s2;
+    } else {
+      vx += a;
+      vy += b;
+    }
   };
   for (int i = 0; i < nn + nf; ++i) {
     const int code = j.ell[base + (size_t)i * 64 + lane];
     if (code < 0) continue;
     const int s = code & kIndexMask, oc = code >> kCodeShift;
-    const auto p = xs[s];
-    const auto m = mus[s];
+    const auto r = Rec<T>::load(j.src, s);
+    const struct { T x, y; } p = {r.x, r.y}, m = {r.z, r.w};
     const T dx = tx - (p.x + T(oc / 3 - 1) * cell), dy = ty - (p.y + T(oc % 3 - 1) * cell);
     const T r2 = dx * dx + dy * dy;
     const T z = xi2 * r2;
@@ -246,8 +264,8 @@ __global__ __launch_bounds__(256) void k_pair_ell_batch(const PairJob *__restric
 }
 
 template <typename T, int DEG>
-hipError_t pair_ell_launch(const PairLists &pl, const PairArgs &a, const T *xs, const T *mus, const T *tab,
-                           double *out, hipStream_t s) {
+hipError_t pair_ell_launch(const PairLists &pl, const PairArgs &a, const T *src, const T *tab, double *out,
+                           hipStream_t s) {
   if (pl.N == 0) return hipSuccess;
   PairJob j;
   j.N = pl.N;
@@ -260,8 +278,7 @@ hipError_t pair_ell_launch(const PairLists &pl, const PairArgs &a, const T *xs, 
   j.cell = a.cell;
   j.xi2 = a.xi2;
   j.cG = a.cG;
-  j.xs = xs;
-  j.mus = mus;
+  j.src = src;
   j.out = out;
   hipLaunchKernelGGL((k_pair_ell<T, DEG>), dim3((pl.ngroups * 64 + 255) / 256), dim3(256), 0, s, j, tab);
   return hipGetLastError();
@@ -285,14 +302,12 @@ hipError_t launch_group_rows(PairLists &pl, int *gsize, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_pair_f64(const PairLists &pl, const PairArgs &a, const double *xs, const double *mus, double *out,
-                           hipStream_t s) {
-  return pair_ell_launch<double, 16>(pl, a, xs, mus, a.e1tab, out, s);
+hipError_t launch_pair_f64(const PairLists &pl, const PairArgs &a, const double *src, double *out, hipStream_t s) {
+  return pair_ell_launch<double, 16>(pl, a, src, a.e1tab, out, s);
 }
 
-hipError_t launch_pair_f32(const PairLists &pl, const PairArgs &a, const float *xs, const float *mus, double *out,
-                           hipStream_t s) {
-  return pair_ell_launch<float, 9>(pl, a, xs, mus, a.e1tab32, out, s);
+hipError_t launch_pair_f32(const PairLists &pl, const PairArgs &a, const float *src, double *out, hipStream_t s) {
+  return pair_ell_launch<float, 9>(pl, a, src, a.e1tab32, out, s);
 }
 
 // ------------------------------------------------------------------ Alpert band
