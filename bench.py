@@ -90,13 +90,13 @@ FORMS = {
     "fp64": dict(precision="fp64", batch_rfd=False, learned=False),
     # FP32 matvec inside FP64 Krylov (iterative refinement), the three EM-RFD solves in one
     # batched launch set, learned preconditioner correction trained beforehand on solves
-    "mixed+batched+learned": dict(precision="mixed", batch_rfd=True, learned=True),
+    "mixed+batched+learned": dict(precision="mixed", batch_rfd=True, graph=True, learned=True),
 }
 
 
 def run_form(name, form, wl, args, fb, W, np, torch):
     prec = fb.PREC_FP64 if form["precision"] == "fp64" else fb.PREC_MIXED
-    flags = fb.FLAG_BATCH_RFD if form["batch_rfd"] else 0
+    flags = (fb.FLAG_BATCH_RFD if form["batch_rfd"] else 0) | (fb.FLAG_GRAPH if form.get("graph") else 0)
     ctx = fb.Context(**wl.params(), precision=prec, flags=flags)
     sid = ctx.add_shape(fb.starfish(wl.r_s, wl.b, wl.n_arm, wl.n_p))
     ctx.set_bodies(np.full(wl.n_bodies, sid), wl.q, wl.theta)
@@ -138,7 +138,7 @@ def run_form(name, form, wl, args, fb, W, np, torch):
     for i in range(args.warmup):
         info = ctx.step_em_rfd(wl.dt, delta, F, Wr, Wg, Wt, dQ)
         log("%s warmup step %d: %s" % (name, i, info))
-    ctx.set_timing(True)
+    ctx.set_timing(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
@@ -147,10 +147,14 @@ def run_form(name, form, wl, args, fb, W, np, torch):
         log("%s step %d: %s" % (name, i, infos[-1]))
     torch.cuda.synchronize()
     t_step = (time.perf_counter() - t0) / args.steps
+    # one more step with per-kernel events for the breakdown (outside the timed steps;
+    # events bracket every launch and keep graphs off)
+    ctx.set_timing(True)
+    ctx.step_em_rfd(wl.dt, delta, F, Wr, Wg, Wt, dQ)
     kt = {k: ctx.kernel_time(k) for k in KERNEL_CLASSES}
     ctx.set_timing(False)
     matvecs = (sum(i["gmres_iters"] + i["gmres_solves"] + 1 for i in infos) + sum(i["lanczos_iters"] for i in infos))
-    log("%s kernel ms per step: %s" % (name, {k: round(v[0] / args.steps, 3) for k, v in kt.items()}))
+    log("%s kernel ms per step: %s" % (name, {k: round(v[0], 3) for k, v in kt.items()}))
     x = torch.zeros(2 * N, dtype=torch.float64, device="cuda")
     ctx.get_nodes(x)
     res = {
@@ -161,7 +165,7 @@ def run_form(name, form, wl, args, fb, W, np, torch):
                    "lanczos_iters": sum(i["lanczos_iters"] for i in infos) / args.steps,
                    "matvecs_per_step": matvecs / args.steps,
                    "max_residual": max(i["gmres_residual"] for i in infos)},
-        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
+        "kernel_ms_per_step": {k: v[0] for k, v in kt.items()},
         "dtype": "f64" if prec == fb.PREC_FP64 else "f32+f64",
     }
     if train:

@@ -61,7 +61,10 @@ enum {
   FBIM_FLAG_SELECTIVE_REORTH = 1u,
   /* fbim_step_em_rfd: the three mobility solves in one lockstep batch (two
      internal copies of the context hold the configurations Q +- delta/2 Wt) */
-  FBIM_FLAG_BATCH_RFD = 2u
+  FBIM_FLAG_BATCH_RFD = 2u,
+  /* with FBIM_FLAG_BATCH_RFD: replay the batch's preconditioner + saddle operator
+     from a HIP graph (as FBIM_BATCH_GRAPH for batches) */
+  FBIM_FLAG_GRAPH = 4u
 };
 
 /* bits of `parts` in fbim_apply_M */

@@ -921,6 +921,7 @@ fbim_status clone_ctx(fbim_ctx *c, fbim_ctx **out) {
 BatchEngine *engine_new() { return new BatchEngine(); }
 void engine_delete(BatchEngine *E) { engine_destroy(E); }
 const char *engine_error(const BatchEngine *E) { return E ? E->err.c_str() : ""; }
+void engine_set_flags(BatchEngine *E, uint32_t flags) { E->flags = flags; }
 void engine_set_stream(BatchEngine *E, hipStream_t s) {
   if (E->stream != s) destroy_graphs(E);
   E->stream = s;

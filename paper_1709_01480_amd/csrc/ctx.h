@@ -272,6 +272,7 @@ BatchEngine *engine_new();
 void engine_delete(BatchEngine *E);
 const char *engine_error(const BatchEngine *E);
 void engine_set_stream(BatchEngine *E, hipStream_t s);
+void engine_set_flags(BatchEngine *E, uint32_t flags);
 fbim_status em_rfd_batch(BatchEngine *E, const std::vector<fbim_ctx *> &mem, double dt, double delta,
                          const double *const *F, const double *const *W_r, const double *const *W_grid,
                          const double *const *W_tilde, double *const *dQ, int32_t apply, fbim_info *info);

@@ -1150,6 +1150,7 @@ fbim_status fbim_step_em_rfd(fbim_ctx *c, double dt, double delta, const double 
     // the three solves in one lockstep batch with two copies of the context
     if (!c->rfd_engine) c->rfd_engine = engine_new();
     engine_set_stream(c->rfd_engine, c->stream);
+    engine_set_flags(c->rfd_engine, (c->p.flags & FBIM_FLAG_GRAPH) ? FBIM_BATCH_GRAPH : 0u);
     fbim_status st = em_rfd_batch(c->rfd_engine, {c}, dt, delta, &F, &W_r, &W_grid, &W_tilde, &dQ, apply, info);
     if (st != FBIM_OK) c->err = engine_error(c->rfd_engine);
     if (info) info->ms_total = now_ms() - t0;

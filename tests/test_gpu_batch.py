@@ -131,18 +131,21 @@ def test_batched_em_rfd_matches_each_system():
         assert relerr(host(dQ), host(ref)) < 1e-6, wl.name
 
 
-def test_single_context_batched_rfd_flag():
+@pytest.mark.parametrize("graph", [False, True])
+def test_single_context_batched_rfd_flag(graph):
     import paper_1709_01480_amd as fb
     wl = W.make("starfish4")
     ctx0 = make_ctx(wl, tol_gmres=1e-10, tol_lanczos=1e-10)
-    ctx1 = make_ctx(wl, tol_gmres=1e-10, tol_lanczos=1e-10, flags=fb.FLAG_BATCH_RFD)
+    ctx1 = make_ctx(wl, tol_gmres=1e-10, tol_lanczos=1e-10,
+                    flags=fb.FLAG_BATCH_RFD | (fb.FLAG_GRAPH if graph else 0))
     Wr, Wg, Wt = W.noise(wl, ctx0.get_derived()["grid_M"])
     d0, d1 = zeros(3 * wl.n_bodies), zeros(3 * wl.n_bodies)
     delta = 1e-2 * wl.a
     i0 = ctx0.step_em_rfd(1e-3, delta, dev(wl.F), dev(Wr), dev(Wg), dev(Wt), d0)
-    i1 = ctx1.step_em_rfd(1e-3, delta, dev(wl.F), dev(Wr), dev(Wg), dev(Wt), d1)
-    assert i1["gmres_solves"] == 3
-    assert relerr(host(d1), host(d0)) < 1e-6
+    for rep in range(2):  # with a graph the second step replays the captured graph
+        i1 = ctx1.step_em_rfd(1e-3, delta, dev(wl.F), dev(Wr), dev(Wg), dev(Wt), d1)
+        assert i1["gmres_solves"] == 3
+        assert relerr(host(d1), host(d0)) < 1e-6
     # the configuration is restored in both
     U0, U1 = zeros(3 * wl.n_bodies), zeros(3 * wl.n_bodies)
     ctx0.mobility(dev(wl.F), U0)
