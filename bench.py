@@ -88,6 +88,8 @@ def cpu_baseline(wl, X_nodes, prm, matvecs_per_step, budget_s=20.0):
 FORMS = {
     # plain method: FP64 everywhere, block-diagonal preconditioner, solves one after another
     "fp64": dict(precision="fp64", batch_rfd=False, learned=False),
+    # mixed precision only (FP32 matvecs in FP64 Krylov), solves one after another
+    "mixed": dict(precision="mixed", batch_rfd=False, learned=False),
     # FP32 matvec inside FP64 Krylov (iterative refinement), the three EM-RFD solves in one
     # batched launch set, learned preconditioner correction trained beforehand on solves
     "mixed+batched+learned": dict(precision="mixed", batch_rfd=True, graph=True, learned=True),

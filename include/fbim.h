@@ -64,7 +64,11 @@ enum {
   FBIM_FLAG_BATCH_RFD = 2u,
   /* with FBIM_FLAG_BATCH_RFD: replay the batch's preconditioner + saddle operator
      from a HIP graph (as FBIM_BATCH_GRAPH for batches) */
-  FBIM_FLAG_GRAPH = 4u
+  FBIM_FLAG_GRAPH = 4u,
+  /* mixed contexts: iterative refinement (FP64 residuals, FP32 GMRES corrections to
+     1e-3) instead of the default relaxed-matvec GMRES (FP64 operator until the residual
+     estimate falls below 1e-2 ||b||, then the FP32 operator; FP64 restart residuals) */
+  FBIM_FLAG_REFINEMENT = 8u
 };
 
 /* bits of `parts` in fbim_apply_M */

@@ -673,9 +673,12 @@ std::vector<int> pick(const std::vector<int> &v, const std::vector<int> &pos) {
 // when `ir`.  Every system keeps its own Krylov space, Hessenberg matrix and
 // stopping test ||rhs - A x|| <= tol_s ||rhs||, and leaves the launches once
 // it has converged.  Outputs per system (sysl order).
+// relax > 0 (mixed engines): relaxed-matvec GMRES -- an iteration uses the FP32
+// operator once every active system's residual estimate is below relax ||rhs||;
+// restart residuals are FP64 (f32 is then ignored).
 fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool f32, const std::vector<double> &tol,
                     const std::vector<int> &maxit, std::vector<int> &iters, std::vector<double> &relres,
-                    std::vector<int> &status) {
+                    std::vector<int> &status, double relax = 0.0) {
   const int S0 = (int)sysl.size();
   iters.assign(S0, 0);
   relres.assign(S0, 0.0);
@@ -705,7 +708,7 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
     EST(seg_axpby(E, *T, vref(rhs(*T)), vref(T->r), T->ones, T->zeros));
     if (!first) {
       EST(seg_axpby(E, *T, vref(sol(*T)), vref(T->t1), T->ones, T->zeros));
-      EST(run_operator(E, *T, f32, true));
+      EST(run_operator(E, *T, relax > 0 ? false : f32, true));
       EST(seg_axpby(E, *T, vref(T->by), vref(T->r), T->mones, T->ones));
     }
     first = false;
@@ -741,7 +744,12 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
       T = &tables_for(E, pick(sysl, act), st);
       EST(st);
       EST(seg_axpby(E, *T, vref(T->V, j, T->ld), vref(T->bx), T->ones, T->zeros));
-      EST(run_precond_saddle(E, *T, f32));
+      bool use32 = f32;
+      if (relax > 0) {
+        use32 = true;
+        for (int i : act) use32 = use32 && std::fabs(g[i][j]) <= relax * nb[i];
+      }
+      EST(run_precond_saddle(E, *T, use32));
       std::vector<std::vector<double>> hc;
       std::vector<double> hn;
       EST(orthogonalise_b(E, *T, j + 1, hc, hn));
@@ -804,8 +812,11 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
   return FBIM_OK;
 }
 
+constexpr double kRelaxB = 1e-2;  // relaxed-matvec threshold (as for one system)
+
 // Solve the saddle systems `sysl` with RHS d_b into d_x2.  FP64 engines: lockstep
-// GMRES.  Mixed engines: iterative refinement as for one system -- FP64
+// GMRES.  Mixed engines: relaxed-matvec lockstep GMRES, or with
+// FBIM_FLAG_REFINEMENT iterative refinement as for one system -- FP64
 // residuals, corrections by lockstep GMRES on the FP32 operator to 1e-3.
 fbim_status solve_b(BatchEngine *E, const std::vector<int> &sysl, std::vector<int> &iters, std::vector<double> &res,
                     std::vector<int> &status) {
@@ -817,6 +828,8 @@ fbim_status solve_b(BatchEngine *E, const std::vector<int> &sysl, std::vector<in
     maxit[i] = E->sys[sysl[i]]->gmres_max;
   }
   if (!E->mixed) return gmres_b(E, sysl, false, false, tol, maxit, iters, res, status);
+  if (!(E->sys[sysl[0]]->p.flags & FBIM_FLAG_REFINEMENT))
+    return gmres_b(E, sysl, false, false, tol, maxit, iters, res, status, kRelaxB);
   fbim_status st;
   iters.assign(S0, 0);
   res.assign(S0, 1.0);

@@ -545,10 +545,17 @@ fbim_status norm2(fbim_ctx *c, const double *x, size_t n, double &out) {
   return FBIM_OK;
 }
 
+constexpr double kRelax = 1e-2;  // relaxed-matvec threshold of mixed contexts
+
 // right-preconditioned restarted GMRES for the saddle system; b, x device (ntot)
 // warm: start from the x given (else x0 = 0)
+// relax > 0 (mixed contexts): inexact Krylov with a relaxed matvec -- an
+// iteration uses the FP32 operator once the residual estimate is below
+// relax ||b|| (the matvec error may grow as the residual falls, Bouras and
+// Fraysse; Simoncini and Szyld), the FP64 operator before; restart residuals,
+// and with them the stopping test, are always FP64.
 fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iters, double &relres, int maxit,
-                  bool warm = false) {
+                  bool warm = false, double relax = 0.0) {
   const size_t nt = c->ntot;
   hipStream_t s = c->stream;
   const int m = c->restart;
@@ -560,11 +567,18 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
   if (nb == 0.0) return FBIM_OK;
   std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), hcol(m + 3), y(m);
   bool first = !warm;
+  const bool saved32 = c->cur32;
+  struct Restore {
+    fbim_ctx *c;
+    bool v;
+    ~Restore() { c->cur32 = v; }
+  } restore{c, saved32};
   for (;;) {
     // r = b - A x
     if (first) {
       HIPCHK(c, hipMemcpyAsync(c->d_r, b, nt * sizeof(double), hipMemcpyDeviceToDevice, s));
     } else {
+      if (relax > 0) c->cur32 = false;
       STCHK(apply_saddle(c, x, c->d_r));
       HIPCHK(c, launch_axpby(nt, 1.0, b, -1.0, c->d_r, s));
     }
@@ -584,6 +598,7 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
     for (int j = 0; j < m; ++j) {
       double *vj = c->d_V + (size_t)j * nt;
       double *w = c->d_V + (size_t)(j + 1) * nt;
+      if (relax > 0) c->cur32 = std::fabs(g[j]) <= relax * nb;
       STCHK(apply_precond(c, vj, c->d_t1));
       STCHK(apply_saddle(c, c->d_t1, w));
       double hn = 0;
@@ -633,6 +648,7 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
 fbim_status solve_saddle(fbim_ctx *c, const double *b, double *x, double tol, int &iters, double &relres,
                          bool warm = false) {
   if (!c->mixed) return gmres(c, b, x, tol, iters, relres, c->gmres_max, warm);
+  if (!(c->p.flags & FBIM_FLAG_REFINEMENT)) return gmres(c, b, x, tol, iters, relres, c->gmres_max, warm, kRelax);
   const size_t nt = c->ntot;
   hipStream_t s = c->stream;
   iters = 0;

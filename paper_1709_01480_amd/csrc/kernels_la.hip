@@ -581,9 +581,12 @@ __global__ __launch_bounds__(256) void k_seg_Vc(Segs seg, VecRef V, int k, const
   const size_t ld = V.ld[s];
   const double *cs = c + (size_t)s * cstride;
   double *yp = const_cast<double *>(vec_ptr(y, s));
+  // zero coefficients are skipped: a system that stopped earlier pads its
+  // coefficients with zeros, and its basis columns beyond that are not written
   for (int i = rg.x + threadIdx.x; i < rg.y; i += 256) {
     double acc = 0.0;
-    for (int j = 0; j < k; ++j) acc += Vp[(size_t)j * ld + i] * cs[j];
+    for (int j = 0; j < k; ++j)
+      if (cs[j] != 0.0) acc += Vp[(size_t)j * ld + i] * cs[j];
     yp[i] = acc;
   }
 }
