@@ -726,7 +726,7 @@ fbim_status lanczos_sqrt(fbim_ctx *c, const double *b, double *out, int &iters, 
       T[(size_t)i * m + i] = alpha[i];
       if (i + 1 < m) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = beta[i];
     }
-    jacobi_eigh(m, T, lam, Q);
+    eigh_sym(m, T, lam, Q);
     cur.assign(m, 0.0);
     for (int r = 0; r < m; ++r) {
       double sacc = 0;

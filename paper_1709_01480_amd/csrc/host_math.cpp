@@ -74,10 +74,22 @@ long double e1l(long double z) {
     }
     return -g - logl(z) - acc;
   }
-  const int depth = 400;
-  long double t = z + 2.0L * depth + 1.0L;
-  for (int k = depth; k >= 1; --k) t = z + 2.0L * k - 1.0L - (long double)k * k / t;
-  return expl(-z) / t;
+  // continued fraction E1(z) = e^-z / (z+1 - 1/(z+3 - 4/(z+5 - ...))), evaluated
+  // forward by the modified Lentz method until a step changes it by < 1e-19
+  const long double tiny = 1e-300L;
+  long double f = z + 1.0L, C = f, D = 0.0L;
+  for (int k = 1; k < 2000; ++k) {
+    const long double a = -(long double)k * k, b = z + 2.0L * k + 1.0L;
+    D = b + a * D;
+    if (D == 0.0L) D = tiny;
+    D = 1.0L / D;
+    C = b + a / C;
+    if (C == 0.0L) C = tiny;
+    const long double delta = C * D;
+    f *= delta;
+    if (fabsl(delta - 1.0L) < 1e-19L) break;
+  }
+  return expl(-z) / f;
 }
 
 static void interval(int k, double &lo, double &hi) {
@@ -383,51 +395,106 @@ void G_wave(double dx, double dy, double xi, double L, double eta, double g[3]) 
         g[2] += c * a;
         continue;
       }
-      double g1[3], g2[3];
-      G_real(rx, ry, xip, eta, g1);
-      G_real(rx, ry, xi, eta, g2);
+      // a term whose Gaussian exponent exceeds 60 is below e^-60 of the kernel's scale
+      double g1[3] = {0.0, 0.0, 0.0}, g2[3] = {0.0, 0.0, 0.0};
+      if (xip * xip * r2 <= 60.0) G_real(rx, ry, xip, eta, g1);
+      if (xi * xi * r2 <= 60.0) G_real(rx, ry, xi, eta, g2);
       for (int k = 0; k < 3; ++k) g[k] += g1[k] - g2[k];
     }
 }
 
-// ---------------------------------------------------------------- Jacobi
-void jacobi_eigh(int n, std::vector<double> A, std::vector<double> &lam, std::vector<double> &V) {
+// ---------------------------------------------------------------- symmetric eigensolver
+// A = V diag(lam) V^T for a symmetric row-major n x n A: Householder reduction to
+// tridiagonal form (reflectors accumulated into V), then implicit symmetric QR
+// steps with the Wilkinson shift on the tridiagonal matrix, rotations
+// accumulated into V (Golub and Van Loan, Matrix Computations, Sections 8.3.1-8.3.3).
+void eigh_sym(int n, std::vector<double> A, std::vector<double> &lam, std::vector<double> &V) {
   V.assign((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0, diag = 0;
-    for (int i = 0; i < n; ++i) {
-      diag += A[(size_t)i * n + i] * A[(size_t)i * n + i];
-      for (int k = i + 1; k < n; ++k) off += A[(size_t)i * n + k] * A[(size_t)i * n + k];
+  lam.assign(n, 0.0);
+  if (n == 0) return;
+  std::vector<double> d(n), e(n, 0.0), v(n), p(n), w(n);
+  auto at = [&](int i, int j) -> double & { return A[(size_t)i * n + j]; };
+  // Householder: zero A[k+2.., k] with H = I - beta v v^T acting on rows / columns k+1..
+  for (int k = 0; k + 2 < n; ++k) {
+    double xn = 0.0;
+    for (int i = k + 1; i < n; ++i) xn += at(i, k) * at(i, k);
+    xn = std::sqrt(xn);
+    if (xn == 0.0) continue;
+    const double alpha = at(k + 1, k) > 0 ? -xn : xn;
+    double vn = 0.0;
+    for (int i = k + 1; i < n; ++i) {
+      v[i] = at(i, k) - (i == k + 1 ? alpha : 0.0);
+      vn += v[i] * v[i];
     }
-    if (off <= 1e-34 * diag) break;
-    for (int p = 0; p < n; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        const double apq = A[(size_t)p * n + q];
-        if (std::fabs(apq) < 1e-300) continue;
-        const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
-        const double theta = (aqq - app) / (2.0 * apq);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
-        for (int k = 0; k < n; ++k) {  // columns p, q
-          const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
-          A[(size_t)k * n + p] = cs * akp - sn * akq;
-          A[(size_t)k * n + q] = sn * akp + cs * akq;
-        }
-        for (int k = 0; k < n; ++k) {  // rows p, q
-          const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
-          A[(size_t)p * n + k] = cs * apk - sn * aqk;
-          A[(size_t)q * n + k] = sn * apk + cs * aqk;
-        }
-        for (int k = 0; k < n; ++k) {
-          const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
-          V[(size_t)k * n + p] = cs * vkp - sn * vkq;
-          V[(size_t)k * n + q] = sn * vkp + cs * vkq;
-        }
-      }
+    if (vn == 0.0) continue;
+    const double beta = 2.0 / vn;
+    double pv = 0.0;
+    for (int i = k + 1; i < n; ++i) {
+      double acc = 0.0;
+      for (int j = k + 1; j < n; ++j) acc += at(i, j) * v[j];
+      p[i] = beta * acc;
+      pv += p[i] * v[i];
+    }
+    const double K = 0.5 * beta * pv;
+    for (int i = k + 1; i < n; ++i) w[i] = p[i] - K * v[i];
+    for (int i = k + 1; i < n; ++i)
+      for (int j = k + 1; j < n; ++j) at(i, j) -= v[i] * w[j] + w[i] * v[j];
+    at(k + 1, k) = at(k, k + 1) = alpha;
+    for (int i = k + 2; i < n; ++i) at(i, k) = at(k, i) = 0.0;
+    for (int r = 0; r < n; ++r) {  // V <- V H
+      double acc = 0.0;
+      for (int j = k + 1; j < n; ++j) acc += V[(size_t)r * n + j] * v[j];
+      acc *= beta;
+      for (int j = k + 1; j < n; ++j) V[(size_t)r * n + j] -= acc * v[j];
+    }
   }
-  lam.resize(n);
-  for (int i = 0; i < n; ++i) lam[i] = A[(size_t)i * n + i];
+  for (int i = 0; i < n; ++i) d[i] = at(i, i);
+  for (int i = 0; i + 1 < n; ++i) e[i] = at(i + 1, i);
+  // the rotations act on column pairs of V: work on its transpose, whose rows are contiguous
+  std::vector<double> &Vt = A;
+  for (int r = 0; r < n; ++r)
+    for (int j = 0; j < n; ++j) Vt[(size_t)j * n + r] = V[(size_t)r * n + j];
+  // implicit QR steps on the unreduced block [lo, hi]
+  const double eps = 2.220446049250313e-16;
+  int hi = n - 1, guard = 0;
+  while (hi > 0 && guard < 64 * n) {
+    if (std::fabs(e[hi - 1]) <= eps * (std::fabs(d[hi - 1]) + std::fabs(d[hi]))) {
+      e[hi - 1] = 0.0;
+      --hi;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 && std::fabs(e[lo - 1]) > eps * (std::fabs(d[lo - 1]) + std::fabs(d[lo]))) --lo;
+    ++guard;
+    const double dl = 0.5 * (d[hi - 1] - d[hi]);
+    const double eh = e[hi - 1];
+    const double mu = d[hi] - eh * eh / (dl + (dl >= 0 ? 1.0 : -1.0) * std::hypot(dl, eh));
+    double x = d[lo] - mu, z = e[lo];
+    for (int k = lo; k < hi; ++k) {
+      const double r = std::hypot(x, z);
+      const double c = r > 0 ? x / r : 1.0, s = r > 0 ? -z / r : 0.0;
+      if (k > lo) e[k - 1] = r;  // the bulge is chased down
+      const double a = d[k], b = e[k], dd = d[k + 1];
+      d[k] = c * c * a - 2.0 * c * s * b + s * s * dd;
+      d[k + 1] = s * s * a + 2.0 * c * s * b + c * c * dd;
+      e[k] = c * s * (a - dd) + (c * c - s * s) * b;
+      if (k + 1 < hi) {
+        x = e[k];
+        z = -s * e[k + 1];
+        e[k + 1] *= c;
+      }
+      double *vk = &Vt[(size_t)k * n], *vk1 = vk + n;
+      for (int rr = 0; rr < n; ++rr) {
+        const double a0 = vk[rr], a1 = vk1[rr];
+        vk[rr] = c * a0 - s * a1;
+        vk1[rr] = s * a0 + c * a1;
+      }
+    }
+  }
+  for (int r = 0; r < n; ++r)
+    for (int j = 0; j < n; ++j) V[(size_t)r * n + j] = Vt[(size_t)j * n + r];
+  lam = d;
 }
 
 // ---------------------------------------------------------------- shape data
@@ -479,7 +546,7 @@ inline double wrapd(double d, double L) { return d - L * std::nearbyint(d / L); 
 void sym_functions(int n, const std::vector<double> &A, double tau, std::vector<double> &finv_half,
                    std::vector<double> &fhalf, std::vector<double> &finv) {
   std::vector<double> lam, V;
-  jacobi_eigh(n, A, lam, V);
+  eigh_sym(n, A, lam, V);
   double lmax = 0;
   for (double l : lam) lmax = std::max(lmax, l);
   std::vector<double> d1(n), d2(n), d3(n);

@@ -20,7 +20,7 @@ struct Derived {
 // Parameter rule of eq. 3.26; returns an error message or "".
 std::string derive(const fbim_params &p, Derived &d);
 
-// E1 in long double (series for z <= 2, continued fraction beyond).
+// E1 in long double (series for z <= 2, continued fraction by modified Lentz beyond).
 long double e1l(long double z);
 
 // Piecewise Chebyshev tables for the device E1 evaluation.
@@ -42,9 +42,10 @@ void G_real(double dx, double dy, double xi, double eta, double g[3]);
 // of the split: G^(w)_xi = G^(w)_xi' + sum_p [G^(r)_xi'(r+pL) - G^(r)_xi(r+pL)].
 void G_wave(double dx, double dy, double xi, double L, double eta, double g[3]);
 
-// Symmetric eigen-decomposition by cyclic Jacobi: A (n x n, row-major) ->
+// Symmetric eigen-decomposition (Householder tridiagonalisation, then implicit
+// QR with the Wilkinson shift): A (n x n, row-major) ->
 // eigenvalues lam[n], eigenvectors as columns of V (row-major).
-void jacobi_eigh(int n, std::vector<double> A, std::vector<double> &lam, std::vector<double> &V);
+void eigh_sym(int n, std::vector<double> A, std::vector<double> &lam, std::vector<double> &V);
 
 struct ShapeHost {
   int n_p = 0;
