@@ -130,20 +130,20 @@ fbim_status ensure_krylov(fbim_ctx *c) {
   return FBIM_OK;
 }
 
-// tiles of up to kBodyTile same-shape bodies (kBodyTile / 4 when 2 n_p > 256)
+// tiles of up to body_tile_cap(2 n_p) same-shape bodies
 fbim_status build_body_tiles(fbim_ctx *c) {
   std::vector<int> list;
   std::vector<int4> tiles;
   size_t lds = 0;
   for (int sh = 0; sh < (int)c->shapes.size(); ++sh) {
     const int n2 = 2 * c->shapes[sh].h.n_p;
-    const int per = n2 > 256 ? kBodyTile / 4 : kBodyTile;
+    const int per = body_tile_cap(n2);
     const int first = (int)list.size();
     for (int b = 0; b < c->n; ++b)
       if (c->h_shape[b] == sh) list.push_back(b);
     const int cnt = (int)list.size() - first;
     for (int t = 0; t < cnt; t += per) tiles.push_back(make_int4(sh, first + t, std::min(per, cnt - t), 0));
-    if (cnt > 0) lds = std::max(lds, (size_t)per * n2 * sizeof(double));
+    if (cnt > 0) lds = std::max(lds, body_tile_lds(n2));
   }
   STCHK(upload(c, c->d_blist, list));
   STCHK(upload(c, c->d_btile, tiles));

@@ -118,17 +118,33 @@ std::vector<double> e1_table(int deg) {
       long double x = cosl(3.14159265358979323846264338327950288L * (j + 0.5L) / n);
       f[j] = e1_target(k, c + hw * x);
     }
-    double *row = &tab[k * stride];
-    row[0] = (double)c;
-    row[1] = (double)(1.0L / hw);
+    std::vector<long double> cc(n);
     for (int m = 0; m < n; ++m) {
       long double s = 0;
       for (int j = 0; j < n; ++j)
         s += f[j] * cosl(3.14159265358979323846264338327950288L * m * (j + 0.5L) / n);
       s *= 2.0L / n;
       if (m == 0) s *= 0.5L;
-      row[2 + m] = (double)s;
+      cc[m] = s;
     }
+    // Chebyshev series -> power series in x (T_{m+1} = 2x T_m - T_{m-1}); the
+    // power coefficients decay like the Taylor coefficients of the target about
+    // the interval centre, so Horner's rule loses nothing
+    std::vector<long double> a(n, 0.0L), tp(n, 0.0L), tc(n, 0.0L), tn(n);
+    tp[0] = 1.0L;   // T_0
+    if (n > 1) tc[1] = 1.0L;  // T_1
+    a[0] += cc[0];
+    if (n > 1) a[1] += cc[1];
+    for (int m = 2; m < n; ++m) {
+      for (int q = 0; q < n; ++q) tn[q] = (q > 0 ? 2.0L * tc[q - 1] : 0.0L) - tp[q];
+      for (int q = 0; q < n; ++q) a[q] += cc[m] * tn[q];
+      tp = tc;
+      tc = tn;
+    }
+    double *row = &tab[k * stride];
+    row[0] = (double)c;
+    row[1] = (double)(1.0L / hw);
+    for (int m = 0; m < n; ++m) row[2 + m] = (double)a[m];
   }
   return tab;
 }
@@ -139,13 +155,8 @@ double e1_table_eval(const std::vector<double> &tab, int deg, double z) {
   if (z > 2.0) k = std::min(kE1Intervals - 1, 1 + (int)std::floor(std::log(z / 2.0) / std::log(1.5)));
   const double *row = &tab[k * stride];
   const double x = (z - row[0]) * row[1];
-  double b1 = 0, b2 = 0;
-  for (int m = deg; m >= 1; --m) {
-    double b0 = row[2 + m] + 2.0 * x * b1 - b2;
-    b2 = b1;
-    b1 = b0;
-  }
-  const double f = row[2] + x * b1 - b2;
+  double f = row[2 + deg];
+  for (int m = deg - 1; m >= 0; --m) f = std::fma(f, x, row[2 + m]);
   return k == 0 ? f - std::log(z) : std::exp(-z) * f;
 }
 

@@ -23,10 +23,12 @@ std::string derive(const fbim_params &p, Derived &d);
 // E1 in long double (series for z <= 2, continued fraction by modified Lentz beyond).
 long double e1l(long double z);
 
-// Piecewise Chebyshev tables for the device E1 evaluation.
+// Piecewise polynomial tables for the device E1 evaluation: per interval the
+// centre c, 1 / half-width, then deg + 1 power-series coefficients in
+// x = (z - c) / half-width of the interval's Chebyshev interpolant.
 //   interval 0: [0, 2],              f = E1(z) + ln z
 //   interval k: [2*1.5^(k-1), 2*1.5^k], f = e^z E1(z)
-// Layout per interval: {center, 1/halfwidth, c_0/2, c_1, ..., c_deg}.
+// Layout per interval: {centre, 1/half-width, a_0, a_1, ..., a_deg}, f = sum a_m x^m.
 constexpr int kE1Intervals = 9;
 constexpr int kE1Deg64 = 16;
 constexpr int kE1Deg32 = 9;

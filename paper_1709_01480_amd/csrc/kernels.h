@@ -109,11 +109,24 @@ struct BodyMats {
   const double *const *Gp;    // per shape
   int max_np;
 };
-// Tiles of up to kBodyTile bodies of one shape (host-built): tile = (shape, first
-// index into list, count, 0); list holds body indices grouped by shape.
-// kBodyTile bodies x 2 n_p doubles must fit lds_bytes; for 2 n_p > 256 a tile
-// holds at most kBodyTile / 4 bodies and 2 n_p <= 1024.
-constexpr int kBodyTile = 16;
+// Tiles of bodies of one shape (host-built): tile = (shape, first index into
+// list, count, 0); list holds body indices grouped by shape.  A tile of a shape
+// with n2 = 2 n_p unknowns (n2 a multiple of 4, 32 <= n2 <= 1024) holds up to
+// body_tile_cap(n2) bodies, so that (n2 / 4) x (cap / 4) <= 256 threads each own
+// a 4 x 4 output block; the matrix streams through LDS body_tile_kc(n2) rows at
+// a time, and body_tile_lds(n2) bytes of dynamic LDS hold both.
+constexpr int kBodyTileMax = 64;
+__host__ __device__ inline int body_tile_cap(int n2) {
+  const int c = 4 * (1024 / n2);
+  return c < 4 ? 4 : (c > kBodyTileMax ? kBodyTileMax : c);
+}
+__host__ __device__ inline int body_tile_kc(int n2) {  // KC * n2 <= 2048 (16 KB of LDS)
+  const int c = 2048 / n2;
+  return c < 2 ? 2 : (c > 16 ? 16 : c);
+}
+__host__ __device__ inline size_t body_tile_lds(int n2) {
+  return ((size_t)n2 * body_tile_cap(n2) + (size_t)body_tile_kc(n2) * n2) * sizeof(double);
+}
 struct BodyTiles {
   const int4 *tile;
   const int *list;

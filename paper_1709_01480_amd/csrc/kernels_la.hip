@@ -136,10 +136,13 @@ hipError_t launch_rigid_batch(const RigidJob *jobs, BatchGrid bg_nodes, BatchGri
 
 // ------------------------------------------------------------------ per-body dense operators
 // All bodies of a shape share their reference matrices, so in the body frame the
-// per-body products are one matrix times a batch of vectors.  A work group takes
-// a tile of up to kBodyTile bodies of one shape: it rotates their inputs into
-// the body frame in LDS, multiplies them by the shared (2 n_p) x (2 n_p) matrix
-// (read once per tile instead of once per body), then finishes each body.
+// per-body products are one matrix times a batch of vectors: C = X A with X the
+// shared (2 n_p) x (2 n_p) matrix and A the body-frame inputs of a tile of up to
+// body_tile_cap(2 n_p) bodies of one shape, one column per body.  A work group
+// rotates its bodies' inputs into A (LDS, k-major), streams X through LDS in
+// chunks of body_tile_kc rows (the two chunks after the current one are in flight
+// in registers while it is used), and each thread accumulates a 4 x 4 block of C
+// (four rows, four bodies) in registers; then it finishes each body.
 //
 // MODE 0: y_b = R_b X_ref R_b^T x_b, X = G_ref or G_ref^+ (eqs. 3.40-3.42).
 // MODE 1: block-diagonal preconditioner (eqs. 3.31-3.37): in the body frame
@@ -149,20 +152,43 @@ hipError_t launch_rigid_batch(const RigidJob *jobs, BatchGrid bg_nodes, BatchGri
 //   replaced by M_bb + K C K^T: by the Woodbury identity that body's mobility
 //   becomes N_ref + C, mu is unchanged and U_ref gains -C R'^T b.
 template <int MODE>
-__device__ void body_tile(const BodyTiles &bt, int tile, const int *__restrict__ off,
-                                                   const double *__restrict__ theta, const double *const *ref,
-                                                   const int *__restrict__ np, const double *const *X,
-                                                   const double *const *Pref, const double *const *Nt,
-                                                   const double *__restrict__ dN, int N,
-                                                   const double *__restrict__ z, double *__restrict__ y) {
-  extern __shared__ double sm[];  // [nb][n2] body-frame inputs, then outputs
-  __shared__ double Ur[kBodyTile][3];
-  __shared__ double cs_[kBodyTile], sn_[kBodyTile];
-  __shared__ int base_[kBodyTile], body_[kBodyTile];
+__device__ __forceinline__ void body_tile(const BodyTiles &bt, int tile, const int *__restrict__ off,
+                                          const double *__restrict__ theta, const double *const *ref,
+                                          const int *__restrict__ np, const double *const *X,
+                                          const double *const *Pref, const double *const *Nt,
+                                          const double *__restrict__ dN, int N, const double *__restrict__ z,
+                                          double *__restrict__ y) {
+  extern __shared__ double sm[];  // A (n2 x NB, k-major), later C ([NB][n2]); then the X chunk (KC x n2)
+  __shared__ double cs_[kBodyTileMax], sn_[kBodyTileMax];
+  __shared__ int base_[kBodyTileMax], body_[kBodyTileMax];
+  // MODE 1: rigid-body data per body, the shape's reference nodes and N_ref
+  __shared__ double Ur[MODE == 1 ? kBodyTileMax : 1][3], bb_[MODE == 1 ? kBodyTileMax : 1][3];
+  __shared__ double dn_[MODE == 1 ? kBodyTileMax : 1][6], f_[MODE == 1 ? kBodyTileMax : 1][3];
+  __shared__ double rf_[MODE == 1 ? 1024 : 1], Nm_[9];
   const int4 tl = bt.tile[tile];
   const int sh = tl.x, nb = tl.z;
   const int npt = np[sh], n2 = 2 * npt;
+  const int NB = body_tile_cap(n2), KC = body_tile_kc(n2);
+  double *__restrict__ Xs = sm + (size_t)n2 * NB;
   const int tid = threadIdx.x;
+  // the first matrix chunk is requested before anything else (KC * n2 <= 2048:
+  // at most 1024 double2, four per thread)
+  const double2 *__restrict__ A2 = reinterpret_cast<const double2 *>(X[sh]);
+  // two chunks in flight: p0..p3 hold the chunk stored next, p4..p7 the one after
+  double2 p0 = make_double2(0.0, 0.0), p1 = p0, p2 = p0, p3 = p0, p4 = p0, p5 = p0, p6 = p0, p7 = p0;
+  int lim = min(KC, n2) * n2 / 2;
+  int lim1 = max(0, min(KC, n2 - KC)) * n2 / 2;
+  if (tid < lim) p0 = A2[tid];
+  if (tid + 256 < lim) p1 = A2[tid + 256];
+  if (tid + 512 < lim) p2 = A2[tid + 512];
+  if (tid + 768 < lim) p3 = A2[tid + 768];
+  {
+    const double2 *__restrict__ src = A2 + (size_t)KC * n2 / 2;
+    if (tid < lim1) p4 = src[tid];
+    if (tid + 256 < lim1) p5 = src[tid + 256];
+    if (tid + 512 < lim1) p6 = src[tid + 512];
+    if (tid + 768 < lim1) p7 = src[tid + 768];
+  }
   if (tid < nb) {
     const int b = bt.list[tl.y + tid];
     double sn, cs;
@@ -171,80 +197,114 @@ __device__ void body_tile(const BodyTiles &bt, int tile, const int *__restrict__
     sn_[tid] = sn;
     base_[tid] = off[b];
     body_[tid] = b;
+    if (MODE == 1) {  // the body's rigid-body right-hand side and its correction (zero without one)
+      const double *bb = z + 2 * (size_t)N + 3 * (size_t)b;
+      bb_[tid][0] = bb[0];
+      bb_[tid][1] = bb[1];
+      bb_[tid][2] = bb[2];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) dn_[tid][q] = dN ? dN[6 * (size_t)b + q] : 0.0;
+    }
+  }
+  if (MODE == 1) {
+    if (tid < 9) Nm_[tid] = Nt[sh][tid];
+    for (int i = tid; i < n2; i += 256) rf_[i] = ref[sh][i];
   }
   __syncthreads();
-  for (int idx = tid; idx < nb * npt; idx += 256) {
-    const int j = idx / npt, t = idx - j * npt;
-    const size_t gi = 2 * (size_t)(base_[j] + t);
-    const double ax = z[gi], ay = z[gi + 1];
-    sm[j * n2 + 2 * t] = cs_[j] * ax + sn_[j] * ay;
-    sm[j * n2 + 2 * t + 1] = -sn_[j] * ax + cs_[j] * ay;
-  }
-  __syncthreads();
-  // c[j][r] = sum_k X[k * n2 + r] a~[j][k]
-  const double *__restrict__ A = X[sh];
-  const int RP = min(n2, 256), G = 256 / RP;
-  const int g = tid / RP, rr = tid - g * RP;
-  double acc[kBodyTile];
-  double cres[4][kBodyTile / 4 > 0 ? kBodyTile / 4 : 1];  // outputs of later row passes (n2 > 256)
-  int npass = (n2 + RP - 1) / RP;
-  for (int pss = 0; pss < npass; ++pss) {
-    const int r = pss * RP + rr;
+  // body-frame inputs into A, four elements per thread in flight
+  for (int i0 = 0; i0 < NB * npt; i0 += 1024) {
+    double zx[4], zy[4];
 #pragma unroll
-    for (int q = 0; q < kBodyTile; ++q) acc[q] = 0.0;
-    if (g < G && r < n2) {
-      // n2 is a multiple of 4: four matrix loads in flight, body-frame inputs
-      // read from LDS two at a time
-      for (int k = 0; k < n2; k += 4) {
-        const double x0 = A[(size_t)k * n2 + r], x1 = A[(size_t)(k + 1) * n2 + r];
-        const double x2 = A[(size_t)(k + 2) * n2 + r], x3 = A[(size_t)(k + 3) * n2 + r];
-#pragma unroll
-        for (int q = 0; q < kBodyTile; ++q) {
-          const int j = g + G * q;
-          if (j < nb) {
-            const double2 a01 = *reinterpret_cast<const double2 *>(&sm[j * n2 + k]);
-            const double2 a23 = *reinterpret_cast<const double2 *>(&sm[j * n2 + k + 2]);
-            acc[q] += x0 * a01.x + x1 * a01.y + x2 * a23.x + x3 * a23.y;
-          }
-        }
+    for (int q = 0; q < 4; ++q) {
+      const int idx = i0 + q * 256 + tid;
+      const int j = idx / npt, t = idx - j * npt;
+      zx[q] = zy[q] = 0.0;
+      if (idx < NB * npt && j < nb) {
+        const size_t gi = 2 * (size_t)(base_[j] + t);
+        zx[q] = z[gi];
+        zy[q] = z[gi + 1];
       }
     }
-    if (npass == 1) break;
-    // n2 > 256: G == 1 and nb <= kBodyTile / 4; park this pass's outputs
 #pragma unroll
-    for (int q = 0; q < (kBodyTile / 4 > 0 ? kBodyTile / 4 : 1); ++q) cres[pss][q] = acc[q];
-  }
-  __syncthreads();  // every thread is done reading the inputs
-  if (npass == 1) {
-    if (g < G && rr < n2) {
-#pragma unroll
-      for (int q = 0; q < kBodyTile; ++q) {
-        const int j = g + G * q;
-        if (j < nb) sm[j * n2 + rr] = acc[q];
+    for (int q = 0; q < 4; ++q) {
+      const int idx = i0 + q * 256 + tid;
+      const int j = idx / npt, t = idx - j * npt;
+      if (idx < NB * npt) {
+        const double c = j < nb ? cs_[j] : 0.0, sn = j < nb ? sn_[j] : 0.0;
+        sm[(2 * t) * NB + j] = c * zx[q] + sn * zy[q];
+        sm[(2 * t + 1) * NB + j] = -sn * zx[q] + c * zy[q];
       }
     }
-  } else {
-    for (int pss = 0; pss < npass; ++pss) {
-      const int r = pss * RP + rr;
-      if (r < n2) {
+  }
+  // C = X A: thread (rq, jq) owns rows rq + m n2 / 4 (m < 4) and bodies 4 jq .. 4 jq + 3
+  // (X is stored k-major: X[k * n2 + r] multiplies input k of output r)
+  const int RQ = n2 / 4, JQ = NB / 4;
+  const int rq = tid % RQ, jq = tid / RQ;
+  const bool active = jq < JQ;
+  double acc[4][4];
 #pragma unroll
-        for (int q = 0; q < (kBodyTile / 4 > 0 ? kBodyTile / 4 : 1); ++q)
-          if (q < nb) sm[q * n2 + r] = cres[pss][q];
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[r][b] = 0.0;
+  double2 *__restrict__ X2 = reinterpret_cast<double2 *>(Xs);
+  for (int kc = 0; kc < n2; kc += KC) {
+    __syncthreads();  // the previous chunk has been used (and A is complete)
+    if (tid < lim) X2[tid] = p0;
+    if (tid + 256 < lim) X2[tid + 256] = p1;
+    if (tid + 512 < lim) X2[tid + 512] = p2;
+    if (tid + 768 < lim) X2[tid + 768] = p3;
+    __syncthreads();
+    p0 = p4;
+    p1 = p5;
+    p2 = p6;
+    p3 = p7;
+    lim = lim1;
+    if (kc + 2 * KC < n2) {  // fetch the chunk after next while this one is used
+      const double2 *__restrict__ src = A2 + (size_t)(kc + 2 * KC) * n2 / 2;
+      lim1 = min(KC, n2 - kc - 2 * KC) * n2 / 2;
+      if (tid < lim1) p4 = src[tid];
+      if (tid + 256 < lim1) p5 = src[tid + 256];
+      if (tid + 512 < lim1) p6 = src[tid + 512];
+      if (tid + 768 < lim1) p7 = src[tid + 768];
+    } else {
+      lim1 = 0;
+    }
+    if (active) {
+      const int kn = min(KC, n2 - kc);
+      for (int kk = 0; kk < kn; ++kk) {
+        // rows rq + m RQ: consecutive lanes read consecutive doubles (no bank conflicts)
+        const double *xr = &Xs[kk * n2 + rq];
+        const double2 a01 = *reinterpret_cast<const double2 *>(&sm[(kc + kk) * NB + 4 * jq]);
+        const double2 a23 = *reinterpret_cast<const double2 *>(&sm[(kc + kk) * NB + 4 * jq + 2]);
+        const double xv[4] = {xr[0], xr[RQ], xr[2 * RQ], xr[3 * RQ]}, av[4] = {a01.x, a01.y, a23.x, a23.y};
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[r][b] = fma(xv[r], av[b], acc[r][b]);
       }
+    }
+  }
+  __syncthreads();  // every thread is done reading A
+  if (active) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      double *row = &sm[(size_t)(4 * jq + b) * n2 + rq];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) row[r * RQ] = acc[r][b];
     }
   }
   __syncthreads();
   if (MODE == 1) {
-    // per body: f = K_ref^T c (one wave per body), U_ref = -N_ref (R'^T b + f)
+    // per body: f = K_ref^T c (one wave per body), then U_ref = -N_ref (R'^T b + f)
+    // (one thread per body)
     const int lane = tid & 63, wv = tid >> 6;
-    const double *rf = ref[sh];
     for (int j = wv; j < nb; j += 4) {
       double f0 = 0, f1 = 0, f2 = 0;
       for (int t = lane; t < npt; t += 64) {
         const double c0 = sm[j * n2 + 2 * t], c1 = sm[j * n2 + 2 * t + 1];
         f0 += c0;
         f1 += c1;
-        f2 += rf[2 * t] * c1 - rf[2 * t + 1] * c0;
+        f2 += rf_[2 * t] * c1 - rf_[2 * t + 1] * c0;
       }
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
@@ -253,40 +313,54 @@ __device__ void body_tile(const BodyTiles &bt, int tile, const int *__restrict__
         f2 += __shfl_down(f2, o);
       }
       if (lane == 0) {
-        const int b = body_[j];
-        const double cs = cs_[j], sn = sn_[j];
-        const double *bb = z + 2 * (size_t)N + 3 * (size_t)b;
-        const double g0 = cs * bb[0] + sn * bb[1] + f0;
-        const double g1 = -sn * bb[0] + cs * bb[1] + f1;
-        const double g2 = bb[2] + f2;
-        const double *Nm = Nt[sh];
-        const double u0 = -(Nm[0] * g0 + Nm[1] * g1 + Nm[2] * g2);
-        const double u1 = -(Nm[3] * g0 + Nm[4] * g1 + Nm[5] * g2);
-        const double u2 = -(Nm[6] * g0 + Nm[7] * g1 + Nm[8] * g2);
-        Ur[j][0] = u0;
-        Ur[j][1] = u1;
-        Ur[j][2] = u2;
-        // learned correction C = dN_b: the exact inverse of the body block with
-        // M_bb replaced by M_bb + K C K^T keeps mu and adds -C R'^T b to U
-        double v0 = u0, v1 = u1, v2 = u2;
-        if (dN) {
-          const double *d = dN + 6 * (size_t)b;  // (xx, yy, tt, xy, xt, yt)
-          const double b0 = cs * bb[0] + sn * bb[1], b1 = -sn * bb[0] + cs * bb[1], b2 = bb[2];
-          v0 -= d[0] * b0 + d[3] * b1 + d[4] * b2;
-          v1 -= d[3] * b0 + d[1] * b1 + d[5] * b2;
-          v2 -= d[4] * b0 + d[5] * b1 + d[2] * b2;
-        }
-        double *yU = y + 2 * (size_t)N + 3 * (size_t)b;
-        yU[0] = cs * v0 - sn * v1;
-        yU[1] = sn * v0 + cs * v1;
-        yU[2] = v2;
+        f_[j][0] = f0;
+        f_[j][1] = f1;
+        f_[j][2] = f2;
       }
     }
     __syncthreads();
+    if (tid < nb) {
+      const int j = tid, b = body_[j];
+      const double cs = cs_[j], sn = sn_[j];
+      const double b0 = cs * bb_[j][0] + sn * bb_[j][1], b1 = -sn * bb_[j][0] + cs * bb_[j][1], b2 = bb_[j][2];
+      const double g0 = b0 + f_[j][0], g1 = b1 + f_[j][1], g2 = b2 + f_[j][2];
+      const double u0 = -(Nm_[0] * g0 + Nm_[1] * g1 + Nm_[2] * g2);
+      const double u1 = -(Nm_[3] * g0 + Nm_[4] * g1 + Nm_[5] * g2);
+      const double u2 = -(Nm_[6] * g0 + Nm_[7] * g1 + Nm_[8] * g2);
+      Ur[j][0] = u0;
+      Ur[j][1] = u1;
+      Ur[j][2] = u2;
+      // learned correction C = dN_b (xx, yy, tt, xy, xt, yt): the exact inverse of
+      // the body block with M_bb replaced by M_bb + K C K^T keeps mu and adds
+      // -C R'^T b to U
+      const double *d = dn_[j];
+      const double v0 = u0 - (d[0] * b0 + d[3] * b1 + d[4] * b2);
+      const double v1 = u1 - (d[3] * b0 + d[1] * b1 + d[5] * b2);
+      const double v2 = u2 - (d[4] * b0 + d[5] * b1 + d[2] * b2);
+      double *yU = y + 2 * (size_t)N + 3 * (size_t)b;
+      yU[0] = cs * v0 - sn * v1;
+      yU[1] = sn * v0 + cs * v1;
+      yU[2] = v2;
+    }
+    // mu_ref = c + (M_ref^+ K_ref) U_ref: each thread keeps its rows of P
     const double *Pm = Pref[sh];
-    for (int idx = tid; idx < nb * n2; idx += 256) {
-      const int j = idx / n2, r = idx - j * n2;
-      sm[idx] += Pm[r] * Ur[j][0] + Pm[n2 + r] * Ur[j][1] + Pm[2 * n2 + r] * Ur[j][2];
+    double q0[4], q1[4], q2[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int r = tid + 256 * m;
+      q0[m] = q1[m] = q2[m] = 0.0;
+      if (r < n2) {
+        q0[m] = Pm[r];
+        q1[m] = Pm[n2 + r];
+        q2[m] = Pm[2 * n2 + r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int r = tid + 256 * m;
+      if (r < n2)
+        for (int j = 0; j < nb; ++j) sm[j * n2 + r] += q0[m] * Ur[j][0] + q1[m] * Ur[j][1] + q2[m] * Ur[j][2];
     }
     __syncthreads();
   }

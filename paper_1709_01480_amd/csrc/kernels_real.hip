@@ -26,22 +26,20 @@ __device__ inline int xcd_remap(int b, int n) {
 __device__ inline double dev_exp(double x) { return exp(x); }
 __device__ inline float dev_exp(float x) { return __expf(x); }
 __device__ inline double dev_log(double x) { return log(x); }
-__device__ inline float dev_log(float x) { return __logf(x); }
+// arguments here are normal numbers, so the hardware log2 needs no rescaling
+__device__ inline float dev_log(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
 
-// E1(z) from the piecewise Chebyshev table: interval 0 holds E1 + ln z on [0, 2],
-// interval k >= 1 holds e^z E1(z) on [2*1.5^(k-1), 2*1.5^k].
-// Chebyshev series of interval k of the E1 table (Clenshaw).
+// E1(z) from the piecewise polynomial table: interval 0 holds E1 + ln z on [0, 2],
+// interval k >= 1 holds e^z E1(z) on [2*1.5^(k-1), 2*1.5^k]; a row is
+// {centre, 1 / half-width, a_0 .. a_DEG} of the power series in
+// x = (z - centre) / half-width, evaluated by Horner's rule.
 template <typename T, int DEG>
-__device__ inline T cheb(const T *row, T z) {
+__device__ inline T poly(const T *row, T z) {
   const T x = (z - row[0]) * row[1];
-  T b1 = 0, b2 = 0;
+  T f = row[2 + DEG];
 #pragma unroll
-  for (int m = DEG; m >= 1; --m) {
-    const T b0 = row[2 + m] + T(2) * x * b1 - b2;
-    b2 = b1;
-    b1 = b0;
-  }
-  return row[2] + x * b1 - b2;
+  for (int m = DEG - 1; m >= 0; --m) f = fma(f, x, row[2 + m]);
+  return f;
 }
 
 // ---------------------------------------------------------------- neighbour lists
@@ -50,7 +48,8 @@ __device__ inline T cheb(const T *row, T z) {
 // owns slots [goff[g], goff[g] + 64 (nn_g + nf_g)); slot i of target lane l is
 // goff[g] + 64 i + l.  The first nn_g rows hold near pairs (xi^2 r^2 <= 2), the
 // next nf_g rows far pairs; empty slots are -1.  An entry packs the source's
-// sorted index (27 bits) and its neighbour-cell code (dcx+1)*3 + (dcy+1).
+// sorted index (bits 0-26) and its neighbour-cell offset dcx+1 (bits 27-28) and
+// dcy+1 (bits 29-30), so a valid entry is non-negative.
 constexpr int kCodeShift = 27;
 constexpr int kIndexMask = (1 << kCodeShift) - 1;
 
@@ -99,8 +98,8 @@ __global__ __launch_bounds__(64) void k_pair_lists(const int *__restrict__ cell_
       const double2 p = xs[g];
       sx[i] = p.x + (k % 3 - 1) * cell;
       sy[i] = p.y + (k / 3 - 1) * cell;
-      // entry code: (dcx+1)*3 + (dcy+1) with dcx = k%3-1, dcy = k/3-1
-      sid[i] = g | (((k % 3) * 3 + k / 3) << kCodeShift);
+      // entry code: dcx+1 = k%3 and dcy+1 = k/3 above the index
+      sid[i] = g | ((k % 3) << kCodeShift) | ((k / 3) << (kCodeShift + 2));
     }
     __syncthreads();
     for (int t = 0; t < nt; ++t) {
@@ -180,7 +179,27 @@ template <> struct Rec<double> {
   }
 };
 
-// FP32 sums are compensated (Kahan); FP64 sums of ~50 terms need not be
+__device__ inline float dev_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double dev_rcp(double x) {
+  // hardware reciprocal estimate refined by two Newton steps to FP64 accuracy
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(fma(-x, y, 1.0), y, y);
+  return fma(fma(-x, y, 1.0), y, y);
+}
+
+// interval of a far argument z > 2 of the E1 table: k = 1 + floor(log_1.5(z / 2)),
+// clamped to [1, 8]; taken in FP32 for either precision (an argument within
+// rounding of an interval end may take the neighbouring interval, whose series
+// is accurate there too)
+template <typename T>
+__device__ inline int far_interval(T z) {
+  const float l = __log2f((float)z * 0.5f) * 1.7095112913514547f;  // 1 / log2(1.5)
+  return min(8, max(1, 1 + (int)l));
+}
+
+// FP32 sums are compensated (Kahan); FP64 sums of ~50 terms need not be.
+// The loop keeps two loads in flight: the entry of slot i+2 and the source
+// record of slot i+1 are requested before slot i is evaluated.
 template <typename T, int DEG>
 __device__ void pair_ell_body(const PairJob &j, const T *__restrict__ tab, int blk) {
   constexpr bool kKahan = sizeof(T) == 4;
@@ -194,7 +213,8 @@ __device__ void pair_ell_body(const PairJob &j, const T *__restrict__ tab, int b
     tx = p.x;
     ty = p.y;
   }
-  const int base = j.goff[g], nn = j.gnn[g], nf = j.gnf[g];
+  const int base = j.goff[g], nn = j.gnn[g], rows = nn + j.gnf[g];
+  const int *__restrict__ col = j.ell + base + lane;
   T vx = 0, vy = 0, kx = 0, ky = 0;
   auto add = [&](T a, T b) {
     if (kKahan) {
@@ -211,28 +231,33 @@ __device__ void pair_ell_body(const PairJob &j, const T *__restrict__ tab, int b
       vy += b;
     }
   };
-  for (int i = 0; i < nn + nf; ++i) {
-    const int code = j.ell[base + (size_t)i * 64 + lane];
+  // empty slots and slots past the last row read record 0 (always present) and add nothing
+  int c_cur = rows > 0 ? col[0] : -1;
+  int c_nxt = rows > 1 ? col[64] : -1;
+  auto rec_cur = Rec<T>::load(j.src, c_cur < 0 ? 0 : (c_cur & kIndexMask));
+  for (int i = 0; i < rows; ++i) {
+    const int c_far = i + 2 < rows ? col[(size_t)(i + 2) * 64] : -1;
+    const auto rec_nxt = Rec<T>::load(j.src, c_nxt < 0 ? 0 : (c_nxt & kIndexMask));
+    const int code = c_cur;
+    const auto r = rec_cur;
+    c_cur = c_nxt;
+    c_nxt = c_far;
+    rec_cur = rec_nxt;
     if (code < 0) continue;
-    const int s = code & kIndexMask, oc = code >> kCodeShift;
-    const auto r = Rec<T>::load(j.src, s);
-    const struct { T x, y; } p = {r.x, r.y}, m = {r.z, r.w};
-    const T dx = tx - (p.x + T(oc / 3 - 1) * cell), dy = ty - (p.y + T(oc % 3 - 1) * cell);
+    const T ox = (T)((code >> kCodeShift) & 3) - T(1), oy = (T)((code >> (kCodeShift + 2)) & 3) - T(1);
+    const T dx = tx - (r.x + ox * cell), dy = ty - (r.y + oy * cell);
     const T r2 = dx * dx + dy * dy;
     const T z = xi2 * r2;
     const T ez = dev_exp(-z);
     T e1;
     if (i < nn) {  // near rows: E1 + ln z on [0, 2]
-      e1 = cheb<T, DEG>(tab, z) - dev_log(z);
+      e1 = poly<T, DEG>(tab, z) - dev_log(z);
     } else {  // far rows: e^z E1 on [2*1.5^(k-1), 2*1.5^k]
-      int k = 1;
-      k += (z > T(3.0)) + (z > T(4.5)) + (z > T(6.75)) + (z > T(10.125)) + (z > T(15.1875)) +
-           (z > T(22.78125)) + (z > T(34.171875));
-      e1 = ez * cheb<T, DEG>(tab + k * (DEG + 3), z);
+      e1 = ez * poly<T, DEG>(tab + far_interval(z) * (DEG + 3), z);
     }
     const T a = T(0.5) * e1 - ez;
-    const T sdot = ez * (dx * m.x + dy * m.y) / r2;
-    add(a * m.x + sdot * dx, a * m.y + sdot * dy);
+    const T sdot = ez * (dx * r.z + dy * r.w) * dev_rcp(r2);
+    add(a * r.z + sdot * dx, a * r.w + sdot * dy);
   }
   if (t < j.N) {
     const int node = j.perm[t];
