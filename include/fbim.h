@@ -68,7 +68,11 @@ enum {
   /* mixed contexts: iterative refinement (FP64 residuals, FP32 GMRES corrections to
      1e-3) instead of the default relaxed-matvec GMRES (FP64 operator until the residual
      estimate falls below 1e-2 ||b||, then the FP32 operator; FP64 restart residuals) */
-  FBIM_FLAG_REFINEMENT = 8u
+  FBIM_FLAG_REFINEMENT = 8u,
+  /* wave-space transforms through rocFFT plans (real-to-complex, multiplier kernel,
+     complex-to-real) even where the fused transform kernels apply; those serve
+     power-of-two grids 64 <= M <= 2048 and every other M uses rocFFT anyway */
+  FBIM_FLAG_LIBRARY_FFT = 16u
 };
 
 /* bits of `parts` in fbim_apply_M */
@@ -166,7 +170,9 @@ fbim_status fbim_get_nodes(fbim_ctx *ctx, double *x);
 /* DEVICE out[2N] = M mu (Section 3.2, eq. 3.20) restricted to `parts`
  * (FBIM_PART_REAL: trapezoid pairs within r_c, FBIM_PART_ALPERT: symmetrised
  * Alpert correction, FBIM_PART_WAVE: spectral-Ewald M^(w)).  mu, out: DEVICE,
- * 2N doubles, must not alias.  Precision follows the context. */
+ * 2N doubles, must not alias.  Precision follows the context: in a mixed
+ * context the real-space pair sum and the wave-space part run in FP32 (the
+ * mixed solver's inner operator). */
 fbim_status fbim_apply_M(fbim_ctx *ctx, const double *mu, double *out, uint32_t parts);
 
 /* DEVICE out[2N] = (M^(w))^(1/2) W^(w) by eq. 3.30 from DEVICE W_grid[2 M M]

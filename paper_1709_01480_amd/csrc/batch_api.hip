@@ -53,6 +53,7 @@ struct BatchEngine {
   std::vector<fbim_ctx *> sys;
   hipStream_t stream = nullptr;
   bool mixed = false;
+  bool conv = false;  // fused transform kernels for every system (else rocFFT plans per class)
   uint32_t flags = 0;
   std::vector<SizeClass> classes;
   std::vector<int> cls_of, slot_of;
@@ -153,7 +154,10 @@ fbim_status setup_classes(BatchEngine *E) {
     slot[i] = (int)want[k].sys.size();
     want[k].sys.push_back((int)i);
   }
-  bool same = want.size() == E->classes.size();
+  // the fused transform kernels serve the batch when they serve every system
+  bool conv = true;
+  for (auto *c : E->sys) conv = conv && c->conv;
+  bool same = want.size() == E->classes.size() && conv == E->conv;
   for (size_t j = 0; same && j < want.size(); ++j)
     same = want[j].M == E->classes[j].M && want[j].sys == E->classes[j].sys;
   E->cls_of = cls;
@@ -161,6 +165,20 @@ fbim_status setup_classes(BatchEngine *E) {
   if (same) return FBIM_OK;
   destroy_graphs(E);
   destroy_classes(E);
+  E->conv = conv;
+  if (conv) {
+    for (auto &k : want) {
+      const size_t M = k.M, cnt = k.sys.size();
+      EHIP(E, dalloc(k.grid, 2 * M * M * cnt));
+      EHIP(E, dalloc(k.spec, 4 * M * (M / 2 + 1) * cnt));
+      if (E->mixed) {
+        EHIP(E, dalloc(k.grid32, 2 * M * M * cnt));
+        EHIP(E, dalloc(k.spec32, 4 * M * (M / 2 + 1) * cnt));
+      }
+    }
+    E->classes = want;
+    return FBIM_OK;
+  }
   if (!g_rocfft_ready) {
     EFFT(E, rocfft_setup());
     g_rocfft_ready = true;
@@ -462,18 +480,31 @@ fbim_status run_operator(BatchEngine *E, Tables &T, bool f32, bool saddle) {
     Timer t(tc, f32 ? "spread32" : "spread");
     EHIP(E, launch_spread_batch(T.spr[p], T.bg_tiles, p, s));
   }
-  {
+  if (E->conv) {
+    // fused transform kernels, per listed system on its slot of the class buffers
     Timer t(tc, f32 ? "fft32" : "fft");
-    for (auto &k : E->classes) {
-      void *in[1] = {f32 ? (void *)k.grid32 : (void *)k.grid}, *o[1] = {f32 ? (void *)k.spec32 : (void *)k.spec};
-      EFFT(E, rocfft_execute(f32 ? k.fwd32 : k.fwd, in, o, E->einfo));
+    for (int q = 0; q < T.S; ++q) {
+      fbim_ctx *c = E->sys[T.list[q]];
+      const SizeClass &k = E->classes[E->cls_of[T.list[q]]];
+      const size_t M = c->d.M, slot = E->slot_of[T.list[q]], gsz = 2 * M * M, ssz = 4 * M * (M / 2 + 1);
+      const WaveConvArgs a{c->d.M, 0, c->d.L, c->d.xi, c->d.eta_s, c->d.h * c->d.h / (c->p.eta * c->d.L * c->d.L)};
+      if (f32)
+        EHIP(E, launch_wave_conv_f32(a, k.grid32 + slot * gsz, k.spec32 + slot * ssz, c->d_tw32, s));
+      else
+        EHIP(E, launch_wave_conv_f64(a, k.grid + slot * gsz, k.spec + slot * ssz, c->d_tw, s));
     }
-  }
-  {
-    Timer t(tc, f32 ? "multiplier32" : "multiplier");
-    EHIP(E, launch_multiplier_batch(T.mul[p], T.bg_spec, p, 0, s));
-  }
-  {
+  } else {
+    {
+      Timer t(tc, f32 ? "fft32" : "fft");
+      for (auto &k : E->classes) {
+        void *in[1] = {f32 ? (void *)k.grid32 : (void *)k.grid}, *o[1] = {f32 ? (void *)k.spec32 : (void *)k.spec};
+        EFFT(E, rocfft_execute(f32 ? k.fwd32 : k.fwd, in, o, E->einfo));
+      }
+    }
+    {
+      Timer t(tc, f32 ? "multiplier32" : "multiplier");
+      EHIP(E, launch_multiplier_batch(T.mul[p], T.bg_spec, p, 0, s));
+    }
     Timer t(tc, f32 ? "fft32" : "fft");
     for (auto &k : E->classes) {
       void *in[1] = {f32 ? (void *)k.spec32 : (void *)k.spec}, *o[1] = {f32 ? (void *)k.grid32 : (void *)k.grid};

@@ -49,6 +49,27 @@ fbim_status rebuild_shape_arrays(fbim_ctx *c) {
 }
 
 fbim_status setup_fft(fbim_ctx *c) {
+  const size_t M = c->d.M;
+  HIPCHK(c, dalloc(c->d_grid, 2 * M * M));
+  HIPCHK(c, dalloc(c->d_spec, 2 * 2 * M * (M / 2 + 1)));
+  if (c->mixed) {
+    HIPCHK(c, dalloc(c->d_grid32, 2 * M * M));
+    HIPCHK(c, dalloc(c->d_spec32, 2 * 2 * M * (M / 2 + 1)));
+  }
+  c->conv = wave_conv_supported(c->d.M) && !(c->p.flags & FBIM_FLAG_LIBRARY_FFT);
+  if (c->conv) {
+    // twiddles exp(-2 pi i k / M), evaluated in long double
+    std::vector<double> tw(2 * M);
+    for (size_t k = 0; k < M; ++k) {
+      const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)M;
+      tw[2 * k] = (double)cosl(a);
+      tw[2 * k + 1] = (double)-sinl(a);
+    }
+    std::vector<float> tw32(tw.begin(), tw.end());
+    STCHK(upload(c, c->d_tw, tw));
+    STCHK(upload(c, c->d_tw32, tw32));
+    return FBIM_OK;
+  }
   if (!g_rocfft_ready) {
     FFTCHK(c, rocfft_setup());
     g_rocfft_ready = true;
@@ -74,13 +95,6 @@ fbim_status setup_fft(fbim_ctx *c) {
   FFTCHK(c, rocfft_execution_info_create(&c->einfo));
   if (c->fft_work_bytes) FFTCHK(c, rocfft_execution_info_set_work_buffer(c->einfo, c->fft_work, c->fft_work_bytes));
   FFTCHK(c, rocfft_execution_info_set_stream(c->einfo, c->stream));
-  const size_t M = c->d.M;
-  HIPCHK(c, dalloc(c->d_grid, 2 * M * M));
-  HIPCHK(c, dalloc(c->d_spec, 2 * 2 * M * (M / 2 + 1)));
-  if (c->mixed) {
-    HIPCHK(c, dalloc(c->d_grid32, 2 * M * M));
-    HIPCHK(c, dalloc(c->d_spec32, 2 * 2 * M * (M / 2 + 1)));
-  }
   return FBIM_OK;
 }
 
@@ -375,16 +389,20 @@ fbim_status apply_M(fbim_ctx *c, const double *mu, double *out, unsigned parts) 
         Timer t(c, "spread32");
         HIPCHK(c, launch_spread_f32(w, c->d_xt32, c->d_mut32, c->d_grid32, s));
       }
-      {
+      if (c->conv) {
         Timer t(c, "fft32");
-        void *in[1] = {c->d_grid32}, *o[1] = {c->d_spec32};
-        FFTCHK(c, rocfft_execute(c->fwd32, in, o, c->einfo));
-      }
-      {
-        Timer t(c, "multiplier32");
-        HIPCHK(c, launch_multiplier_f32(c->d.M, c->d.L, c->d.xi, c->d.eta_s, scale, 0, c->d_spec32, s));
-      }
-      {
+        HIPCHK(c, launch_wave_conv_f32(WaveConvArgs{c->d.M, 0, c->d.L, c->d.xi, c->d.eta_s, scale}, c->d_grid32,
+                                       c->d_spec32, c->d_tw32, s));
+      } else {
+        {
+          Timer t(c, "fft32");
+          void *in[1] = {c->d_grid32}, *o[1] = {c->d_spec32};
+          FFTCHK(c, rocfft_execute(c->fwd32, in, o, c->einfo));
+        }
+        {
+          Timer t(c, "multiplier32");
+          HIPCHK(c, launch_multiplier_f32(c->d.M, c->d.L, c->d.xi, c->d.eta_s, scale, 0, c->d_spec32, s));
+        }
         Timer t(c, "fft32");
         void *in[1] = {c->d_spec32}, *o[1] = {c->d_grid32};
         FFTCHK(c, rocfft_execute(c->inv32, in, o, c->einfo));
@@ -397,16 +415,20 @@ fbim_status apply_M(fbim_ctx *c, const double *mu, double *out, unsigned parts) 
         Timer t(c, "spread");
         HIPCHK(c, launch_spread_f64(w, c->d_xt, c->d_mut, c->d_grid, s));
       }
-      {
+      if (c->conv) {
         Timer t(c, "fft");
-        void *in[1] = {c->d_grid}, *o[1] = {c->d_spec};
-        FFTCHK(c, rocfft_execute(c->fwd, in, o, c->einfo));
-      }
-      {
-        Timer t(c, "multiplier");
-        HIPCHK(c, launch_multiplier_f64(c->d.M, c->d.L, c->d.xi, c->d.eta_s, scale, 0, c->d_spec, s));
-      }
-      {
+        HIPCHK(c, launch_wave_conv_f64(WaveConvArgs{c->d.M, 0, c->d.L, c->d.xi, c->d.eta_s, scale}, c->d_grid,
+                                       c->d_spec, c->d_tw, s));
+      } else {
+        {
+          Timer t(c, "fft");
+          void *in[1] = {c->d_grid}, *o[1] = {c->d_spec};
+          FFTCHK(c, rocfft_execute(c->fwd, in, o, c->einfo));
+        }
+        {
+          Timer t(c, "multiplier");
+          HIPCHK(c, launch_multiplier_f64(c->d.M, c->d.L, c->d.xi, c->d.eta_s, scale, 0, c->d_spec, s));
+        }
         Timer t(c, "fft");
         void *in[1] = {c->d_spec}, *o[1] = {c->d_grid};
         FFTCHK(c, rocfft_execute(c->inv, in, o, c->einfo));
@@ -435,16 +457,20 @@ fbim_status random_field(fbim_ctx *c, const double *W_grid, double *out) {
   const double scale = 1.0 / ((double)M * std::sqrt(c->p.eta * c->d.L * c->d.L));
   HIPCHK(c, launch_fill(2 * (size_t)c->N, 0.0, out, s));
   HIPCHK(c, hipMemcpyAsync(c->d_grid, W_grid, 2 * M * M * sizeof(double), hipMemcpyDeviceToDevice, s));
-  {
+  if (c->conv) {
     Timer t(c, "fft");
-    void *in[1] = {c->d_grid}, *o[1] = {c->d_spec};
-    FFTCHK(c, rocfft_execute(c->fwd, in, o, c->einfo));
-  }
-  {
-    Timer t(c, "multiplier");
-    HIPCHK(c, launch_multiplier_f64(c->d.M, c->d.L, c->d.xi, c->d.eta_s, scale, 1, c->d_spec, s));
-  }
-  {
+    HIPCHK(c, launch_wave_conv_f64(WaveConvArgs{c->d.M, 1, c->d.L, c->d.xi, c->d.eta_s, scale}, c->d_grid, c->d_spec,
+                                   c->d_tw, s));
+  } else {
+    {
+      Timer t(c, "fft");
+      void *in[1] = {c->d_grid}, *o[1] = {c->d_spec};
+      FFTCHK(c, rocfft_execute(c->fwd, in, o, c->einfo));
+    }
+    {
+      Timer t(c, "multiplier");
+      HIPCHK(c, launch_multiplier_f64(c->d.M, c->d.L, c->d.xi, c->d.eta_s, scale, 1, c->d_spec, s));
+    }
     Timer t(c, "fft");
     void *in[1] = {c->d_spec}, *o[1] = {c->d_grid};
     FFTCHK(c, rocfft_execute(c->inv, in, o, c->einfo));
@@ -958,7 +984,7 @@ void fbim_destroy(fbim_ctx *c) {
                   c->d_mut, c->d_src32, c->d_xt32, c->d_mut32, c->d_grid, c->d_spec, c->d_grid32,
                   c->d_spec32, c->d_e1tab, c->d_e1tab32, c->d_V, c->d_w, c->d_t1, c->d_t2, c->d_b, c->d_x2,
                   c->d_r, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
-                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU, c->d_bx, c->d_by};
+                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU, c->d_bx, c->d_by, c->d_tw, c->d_tw32};
   engine_delete(c->rfd_engine);
   for (fbim_ctx *r : c->rfd)
     if (r) fbim_destroy(r);

@@ -90,8 +90,45 @@ hipError_t launch_interp_f32(const WaveArgs &w, const float *xt, const int *tper
                              double *out, hipStream_t s);
 // multiplier on the half spectrum [2][M][M/2+1]: mode 0 = M^(w) (eq. 3.23-3.25),
 // mode 1 = random field B^(1/2) (eq. 3.28-3.30)
+// Fourier multiplier of the wave-space operator at grid frequency (row, col),
+// row = ky index in [0, M), col = kx index in [0, M/2]:
+//   mode 0: (1+u) exp(-(1-eta_s) u) / k^2 (I - k k^T/k^2)          (M^(w), eq. 3.23)
+//   mode 1: sqrt(1+u) exp(-(1-eta_s) u/2) / k (I - k k^T/k^2)       (B^(1/2), eq. 3.29)
+// with u = k^2 / 4 xi^2, times `scale`, as s * [[pxx, pxy], [pxy, pyy]]; false
+// (multiplier zero) at k = 0.  On the Nyquist row and column the off-diagonal
+// term is dropped, which makes the complex-to-real inverse transform equal to
+// the real part of the full inverse transform.
+template <typename T>
+__device__ inline bool wave_multiplier(int M, int row, int col, T twopi_L, T inv4xi2, T one_m_eta, T scale, int mode,
+                                       T &s, T &pxx, T &pxy, T &pyy) {
+  const T kx = twopi_L * col;
+  const T ky = twopi_L * (row < M / 2 ? row : row - M);
+  const T k2 = kx * kx + ky * ky;
+  if (k2 == T(0)) return false;
+  const T u = k2 * inv4xi2;
+  if (mode == 0)
+    s = (T(1) + u) * exp(-one_m_eta * u) / k2 * scale;
+  else
+    s = sqrt(T(1) + u) * exp(T(-0.5) * one_m_eta * u) / sqrt(k2) * scale;
+  pxx = T(1) - kx * kx / k2;
+  pyy = T(1) - ky * ky / k2;
+  pxy = (col == M / 2 || row == M / 2) ? T(0) : -kx * ky / k2;
+  return true;
+}
+
 hipError_t launch_multiplier_f64(int M, double L, double xi, double eta_s, double scale, int mode, double *spec,
                                  hipStream_t s);
+// Fused wave-space convolution (kernels_fft.hip) for power-of-two 64 <= M <= 2048:
+// grid planes [2][M][M] -> same planes after transform, multiplier (mode, scale as
+// launch_multiplier) and inverse transform; spec is scratch of 4 M (M/2+1) reals
+// (the half spectra, kx-major); tw holds exp(-2 pi i k / M), k < M (interleaved).
+struct WaveConvArgs {
+  int M, mode;
+  double L, xi, eta_s, scale;
+};
+bool wave_conv_supported(int M);
+hipError_t launch_wave_conv_f64(const WaveConvArgs &a, double *grid, double *spec, const double *tw, hipStream_t s);
+hipError_t launch_wave_conv_f32(const WaveConvArgs &a, float *grid, float *spec, const float *tw, hipStream_t s);
 hipError_t launch_multiplier_f32(int M, double L, double xi, double eta_s, double scale, int mode, float *spec,
                                  hipStream_t s);
 

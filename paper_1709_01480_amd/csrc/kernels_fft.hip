@@ -1,0 +1,333 @@
+// Fused wave-space convolution on power-of-two grids (Section 3.2, eqs. 3.21-3.25,
+// and the random Fourier field of Section 3.3): the two real grid planes are
+// transformed, multiplied and transformed back by three kernels that hold whole
+// 1D transforms in LDS:
+//   rows forward : per grid row y, one complex FFT of g_x + i g_y along x, split
+//                  into the two half spectra H_c(kx, y), kx <= M/2, and written
+//                  transposed: S[kx][y] = (H_x, H_y);
+//   columns      : per kx, the two length-M columns of S are transformed along
+//                  y, multiplied by the 2 x 2 Fourier multiplier, transformed back;
+//   rows inverse : per row, the Hermitian extension of both half spectra packed
+//                  as U_x + i U_y, one inverse complex FFT whose real and imaginary
+//                  parts are the two grid planes.
+// Up to rounding this is the real-to-complex 2D transform, the multiplier and the
+// complex-to-real 2D transform (the imaginary parts of the kx = 0 and kx = M/2
+// terms are dropped, as a complex-to-real transform does).  Each 1D transform is
+// a Stockham autosort FFT (radix-8 stages, then one radix-2 or radix-4 stage)
+// over a block's sequences in LDS, with twiddles from a table W[k] = exp(-2 pi i k / M);
+// LDS indices are padded by one element per 16 (FP64) or 32 (FP32) so that the
+// strided stores of the early stages spread over the banks.
+#include "kernels.h"
+
+namespace fbim {
+
+namespace {
+
+template <typename T> struct Cx;
+template <> struct Cx<double> { using type = double2; };
+template <> struct Cx<float> { using type = float2; };
+
+// complex elements per work group (256 threads, 16 or 32 per thread) and LDS padding
+template <typename T> constexpr int kElems = sizeof(T) == 8 ? 4096 : 8192;
+// elements of a row-kernel work group: whole rows, at most the grid
+template <typename T, int M> constexpr int kRowElems = kElems<T> < M * M ? kElems<T> : M * M;
+template <typename T> constexpr int kPadShift = sizeof(T) == 8 ? 4 : 5;
+template <typename T> __device__ __forceinline__ int pad(int i) { return i + (i >> kPadShift<T>); }
+
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+  V r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) {
+  a.x += b.x;
+  a.y += b.y;
+  return a;
+}
+template <typename V> __device__ __forceinline__ V csub(V a, V b) {
+  a.x -= b.x;
+  a.y -= b.y;
+  return a;
+}
+// a * (-i) for the forward transform, a * (+i) for the inverse
+template <typename V, bool INV> __device__ __forceinline__ V rot(V a) {
+  V r;
+  if (INV) {
+    r.x = -a.y;
+    r.y = a.x;
+  } else {
+    r.x = a.y;
+    r.y = -a.x;
+  }
+  return r;
+}
+
+// in-register DFT of length R (natural order in and out), sign - (forward) or + (inverse)
+template <typename V, bool INV> __device__ __forceinline__ void dft2(V &a, V &b) {
+  const V t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+template <typename V, bool INV> __device__ __forceinline__ void dft4(V &v0, V &v1, V &v2, V &v3) {
+  const V t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3), t3 = rot<V, INV>(csub(v1, v3));
+  v0 = cadd(t0, t2);
+  v2 = csub(t0, t2);
+  v1 = cadd(t1, t3);
+  v3 = csub(t1, t3);
+}
+template <typename V, int R, bool INV> __device__ __forceinline__ void dft(V (&v)[R]) {
+  if constexpr (R == 2) {
+    dft2<V, INV>(v[0], v[1]);
+  } else if constexpr (R == 4) {
+    dft4<V, INV>(v[0], v[1], v[2], v[3]);
+  } else {
+    static_assert(R == 8, "radix 2, 4 or 8");
+    // even / odd halves, then X[k] = E[k] + W8^k O[k], X[k+4] = E[k] - W8^k O[k]
+    V e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6], o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<V, INV>(e0, e1, e2, e3);
+    dft4<V, INV>(o0, o1, o2, o3);
+    using T = decltype(o0.x);
+    const T c = T(0.70710678118654752440);
+    V w1, w3;  // W8 o1 and W8^3 o3; W8 = (1 -+ i) / sqrt(2)
+    if (INV) {
+      w1.x = c * (o1.x - o1.y);
+      w1.y = c * (o1.x + o1.y);
+      w3.x = -c * (o3.x + o3.y);
+      w3.y = c * (o3.x - o3.y);
+    } else {
+      w1.x = c * (o1.x + o1.y);
+      w1.y = c * (o1.y - o1.x);
+      w3.x = c * (o3.y - o3.x);
+      w3.y = -c * (o3.x + o3.y);
+    }
+    const V w2 = rot<V, INV>(o2);
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, w1);
+    v[5] = csub(e1, w1);
+    v[2] = cadd(e2, w2);
+    v[6] = csub(e2, w2);
+    v[3] = cadd(e3, w3);
+    v[7] = csub(e3, w3);
+  }
+}
+
+// One Stockham stage of radix R over NSEQ sequences of length N in LDS; Ns is the
+// length of the sub-transforms already combined.  Butterfly j of a sequence reads
+// elements j + r N/R, applies the twiddles W_N^{(j mod Ns) r N/(Ns R)}, takes the
+// length-R DFT and writes element (j / Ns) Ns R + (j mod Ns) + r Ns.  All reads of
+// the stage complete (barrier) before its writes.
+template <typename T, int N, int R, int NSEQ, bool INV>
+__device__ __forceinline__ void fft_stage(typename Cx<T>::type *buf, int Ns, const typename Cx<T>::type *__restrict__ tw) {
+  using V = typename Cx<T>::type;
+  constexpr int NB = NSEQ * N / R, PER = NB / 256;
+  static_assert(NB % 256 == 0, "whole butterflies per thread");
+  const int tid = threadIdx.x;
+  V v[PER][R];
+  int dst[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int b = tid + 256 * q;
+    const int seq = b / (N / R), j = b % (N / R);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[q][r] = buf[pad<T>(seq * N + j + r * (N / R))];
+    const int k = j & (Ns - 1);
+    if (Ns > 1) {
+      const int step = N / (Ns * R);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        V w = tw[k * r * step];
+        if (INV) w.y = -w.y;
+        v[q][r] = cmul(v[q][r], w);
+      }
+    }
+    dft<V, R, INV>(v[q]);
+    dst[q] = seq * N + (j / Ns) * Ns * R + k;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q)
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf[pad<T>(dst[q] + r * Ns)] = v[q][r];
+  __syncthreads();
+}
+
+// unnormalised FFT (INV: exponent sign +) of NSEQ sequences of length 2^LOG2N in LDS
+template <typename T, int LOG2N, int NSEQ, bool INV>
+__device__ __forceinline__ void fft_lds(typename Cx<T>::type *buf, const typename Cx<T>::type *__restrict__ tw) {
+  constexpr int N = 1 << LOG2N;
+  int Ns = 1;
+#pragma unroll
+  for (int s = 0; s < LOG2N / 3; ++s) {
+    fft_stage<T, N, 8, NSEQ, INV>(buf, Ns, tw);
+    Ns *= 8;
+  }
+  if constexpr (LOG2N % 3 == 1) fft_stage<T, N, 2, NSEQ, INV>(buf, Ns, tw);
+  if constexpr (LOG2N % 3 == 2) fft_stage<T, N, 4, NSEQ, INV>(buf, Ns, tw);
+}
+
+// rows forward: grid planes [2][M][M] -> S[kx][y] = (H_x, H_y), kx <= M/2
+template <typename T, int LOG2M>
+__global__ __launch_bounds__(256) void k_rows_fwd(const T *__restrict__ grid, typename Cx<T>::type *__restrict__ S,
+                                                  const typename Cx<T>::type *__restrict__ tw) {
+  using V = typename Cx<T>::type;
+  constexpr int M = 1 << LOG2M, E = kRowElems<T, M>, B = E / M;
+  __shared__ V buf[E + (E >> kPadShift<T>)];
+  const int tid = threadIdx.x;
+  const int y0 = blockIdx.x * B;
+  const size_t plane = (size_t)M * M;
+  for (int e = tid; e < E; e += 256) {
+    const size_t g = (size_t)y0 * M + e;  // rows y0 .. y0 + B - 1 are contiguous
+    V z;
+    z.x = grid[g];
+    z.y = grid[plane + g];
+    buf[pad<T>(e)] = z;
+  }
+  __syncthreads();
+  fft_lds<T, LOG2M, B, false>(buf, tw);
+  // H_x = (Z[k] + conj Z[M-k]) / 2, H_y = (Z[k] - conj Z[M-k]) / 2i; row index fastest
+  for (int e = tid; e < (M / 2 + 1) * B; e += 256) {
+    const int r = e % B, kx = e / B;
+    const V Z = buf[pad<T>(r * M + kx)], Zm = buf[pad<T>(r * M + ((M - kx) & (M - 1)))];
+    V h0, h1;
+    h0.x = T(0.5) * (Z.x + Zm.x);
+    h0.y = T(0.5) * (Z.y - Zm.y);
+    h1.x = T(0.5) * (Z.y + Zm.y);
+    h1.y = T(-0.5) * (Z.x - Zm.x);
+    V *dst = S + 2 * ((size_t)kx * M + y0 + r);
+    dst[0] = h0;
+    dst[1] = h1;
+  }
+}
+
+// columns: per kx, FFT along y of both components, multiplier, inverse FFT
+template <typename T, int LOG2M>
+__global__ __launch_bounds__(256) void k_cols(typename Cx<T>::type *__restrict__ S,
+                                              const typename Cx<T>::type *__restrict__ tw, T twopi_L, T inv4xi2,
+                                              T one_m_eta, T scale, int mode) {
+  using V = typename Cx<T>::type;
+  constexpr int M = 1 << LOG2M, E = kElems<T>, CB = E / (2 * M), NCOL = M / 2 + 1;
+  __shared__ V buf[E + (E >> kPadShift<T>)];
+  const int tid = threadIdx.x;
+  const int c0 = blockIdx.x * CB;
+  for (int e = tid; e < CB * M; e += 256) {
+    const int c = e >> LOG2M, y = e & (M - 1);
+    V a, b;
+    a.x = a.y = b.x = b.y = T(0);
+    if (c0 + c < NCOL) {
+      const V *src = S + 2 * ((size_t)(c0 + c) * M + y);
+      a = src[0];
+      b = src[1];
+    }
+    buf[pad<T>(2 * c * M + y)] = a;
+    buf[pad<T>((2 * c + 1) * M + y)] = b;
+  }
+  __syncthreads();
+  fft_lds<T, LOG2M, 2 * CB, false>(buf, tw);
+  for (int e = tid; e < CB * M; e += 256) {
+    const int c = e >> LOG2M, ky = e & (M - 1);
+    if (c0 + c >= NCOL) continue;
+    V &f0 = buf[pad<T>(2 * c * M + ky)];
+    V &f1 = buf[pad<T>((2 * c + 1) * M + ky)];
+    T sc, pxx, pxy, pyy;
+    V g0, g1;
+    if (wave_multiplier<T>(M, ky, c0 + c, twopi_L, inv4xi2, one_m_eta, scale, mode, sc, pxx, pxy, pyy)) {
+      g0.x = sc * (pxx * f0.x + pxy * f1.x);
+      g0.y = sc * (pxx * f0.y + pxy * f1.y);
+      g1.x = sc * (pxy * f0.x + pyy * f1.x);
+      g1.y = sc * (pxy * f0.y + pyy * f1.y);
+    } else {
+      g0.x = g0.y = g1.x = g1.y = T(0);
+    }
+    f0 = g0;
+    f1 = g1;
+  }
+  __syncthreads();
+  fft_lds<T, LOG2M, 2 * CB, true>(buf, tw);
+  for (int e = tid; e < CB * M; e += 256) {
+    const int c = e >> LOG2M, y = e & (M - 1);
+    if (c0 + c >= NCOL) continue;
+    V *dst = S + 2 * ((size_t)(c0 + c) * M + y);
+    dst[0] = buf[pad<T>(2 * c * M + y)];
+    dst[1] = buf[pad<T>((2 * c + 1) * M + y)];
+  }
+}
+
+// rows inverse: S -> grid planes; Z[k] = U_x[k] + i U_y[k] over the Hermitian extension
+template <typename T, int LOG2M>
+__global__ __launch_bounds__(256) void k_rows_inv(const typename Cx<T>::type *__restrict__ S, T *__restrict__ grid,
+                                                  const typename Cx<T>::type *__restrict__ tw) {
+  using V = typename Cx<T>::type;
+  constexpr int M = 1 << LOG2M, E = kRowElems<T, M>, B = E / M;
+  __shared__ V buf[E + (E >> kPadShift<T>)];
+  const int tid = threadIdx.x;
+  const int y0 = blockIdx.x * B;
+  for (int e = tid; e < (M / 2 + 1) * B; e += 256) {
+    const int r = e % B, k = e / B;
+    const V *src = S + 2 * ((size_t)k * M + y0 + r);
+    V g0 = src[0], g1 = src[1];
+    if (k == 0 || k == M / 2) g0.y = g1.y = T(0);
+    V z;
+    z.x = g0.x - g1.y;
+    z.y = g0.y + g1.x;
+    buf[pad<T>(r * M + k)] = z;
+    if (k > 0 && k < M / 2) {  // conj(U_x[k]) + i conj(U_y[k]) at M - k
+      V zc;
+      zc.x = g0.x + g1.y;
+      zc.y = g1.x - g0.y;
+      buf[pad<T>(r * M + M - k)] = zc;
+    }
+  }
+  __syncthreads();
+  fft_lds<T, LOG2M, B, true>(buf, tw);
+  const size_t plane = (size_t)M * M;
+  for (int e = tid; e < E; e += 256) {
+    const V z = buf[pad<T>(e)];
+    const size_t g = (size_t)y0 * M + e;
+    grid[g] = z.x;
+    grid[plane + g] = z.y;
+  }
+}
+
+template <typename T, int LOG2M>
+hipError_t conv_launch(const WaveConvArgs &a, T *grid, typename Cx<T>::type *spec,
+                       const typename Cx<T>::type *tw, hipStream_t s) {
+  constexpr int M = 1 << LOG2M, E = kElems<T>, ER = kRowElems<T, M>;
+  constexpr int rows_blocks = M / (ER / M), col_blocks = (M / 2 + 1 + E / (2 * M) - 1) / (E / (2 * M));
+  hipLaunchKernelGGL((k_rows_fwd<T, LOG2M>), dim3(rows_blocks), dim3(256), 0, s, grid, spec, tw);
+  hipLaunchKernelGGL((k_cols<T, LOG2M>), dim3(col_blocks), dim3(256), 0, s, spec, tw, (T)(2.0 * M_PI / a.L),
+                     (T)(1.0 / (4.0 * a.xi * a.xi)), (T)(1.0 - a.eta_s), (T)a.scale, a.mode);
+  hipLaunchKernelGGL((k_rows_inv<T, LOG2M>), dim3(rows_blocks), dim3(256), 0, s, spec, grid, tw);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t conv_dispatch(const WaveConvArgs &a, T *grid, T *spec, const T *tw, hipStream_t s) {
+  using V = typename Cx<T>::type;
+  V *sp = reinterpret_cast<V *>(spec);
+  const V *t = reinterpret_cast<const V *>(tw);
+  switch (a.M) {
+    case 64: return conv_launch<T, 6>(a, grid, sp, t, s);
+    case 128: return conv_launch<T, 7>(a, grid, sp, t, s);
+    case 256: return conv_launch<T, 8>(a, grid, sp, t, s);
+    case 512: return conv_launch<T, 9>(a, grid, sp, t, s);
+    case 1024: return conv_launch<T, 10>(a, grid, sp, t, s);
+    case 2048: return conv_launch<T, 11>(a, grid, sp, t, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool wave_conv_supported(int M) { return M >= 64 && M <= 2048 && (M & (M - 1)) == 0; }
+
+hipError_t launch_wave_conv_f64(const WaveConvArgs &a, double *grid, double *spec, const double *tw, hipStream_t s) {
+  return conv_dispatch<double>(a, grid, spec, tw, s);
+}
+
+hipError_t launch_wave_conv_f32(const WaveConvArgs &a, float *grid, float *spec, const float *tw, hipStream_t s) {
+  return conv_dispatch<float>(a, grid, spec, tw, s);
+}
+
+}  // namespace fbim

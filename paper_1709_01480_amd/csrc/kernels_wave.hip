@@ -203,39 +203,26 @@ __device__ void interp_body(int M, int TT, int P, int nts, T h, T ag, T scale, c
   }
 }
 
-// mode 0: (1+u) exp(-(1-eta_s) u) / k^2 (I - k k^T/k^2)          (M^(w), eq. 3.23)
-// mode 1: sqrt(1+u) exp(-(1-eta_s) u/2) / k (I - k k^T/k^2)       (B^(1/2), eq. 3.29)
-// with u = k^2 / 4 xi^2, times `scale`; zero at k = 0.  On the Nyquist row and
-// column the off-diagonal term is dropped, which makes the complex-to-real
-// inverse transform equal to the real part of the full inverse transform.
+// multiplier on the rocFFT half spectrum (plane c at [c][row][col], col <= M/2),
+// coefficients from wave_multiplier
 template <typename T>
 __device__ void multiplier_body(int M, T twopi_L, T inv4xi2, T one_m_eta, T scale, int mode,
                                 typename Vec2<T>::type *__restrict__ spec, int idx) {
   const int nh = M / 2 + 1;
   if (idx >= M * nh) return;
   const int row = idx / nh, col = idx - row * nh;
-  const T kx = twopi_L * col;
-  const T ky = twopi_L * (row < M / 2 ? row : row - M);
-  const T k2 = kx * kx + ky * ky;
   auto &Fx = spec[idx];
   auto &Fy = spec[(size_t)M * nh + idx];
-  if (k2 == T(0)) {
+  T sc, pxx, pxy, pyy;
+  if (!wave_multiplier<T>(M, row, col, twopi_L, inv4xi2, one_m_eta, scale, mode, sc, pxx, pxy, pyy)) {
     Fx.x = Fx.y = Fy.x = Fy.y = T(0);
     return;
   }
-  const T u = k2 * inv4xi2;
-  T s;
-  if (mode == 0)
-    s = (T(1) + u) * exp(-one_m_eta * u) / k2 * scale;
-  else
-    s = sqrt(T(1) + u) * exp(T(-0.5) * one_m_eta * u) / sqrt(k2) * scale;
-  const T pxx = T(1) - kx * kx / k2, pyy = T(1) - ky * ky / k2;
-  const T pxy = (col == M / 2 || row == M / 2) ? T(0) : -kx * ky / k2;
   const auto fx = Fx, fy = Fy;
-  Fx.x = s * (pxx * fx.x + pxy * fy.x);
-  Fx.y = s * (pxx * fx.y + pxy * fy.y);
-  Fy.x = s * (pxy * fx.x + pyy * fy.x);
-  Fy.y = s * (pxy * fx.y + pyy * fy.y);
+  Fx.x = sc * (pxx * fx.x + pxy * fy.x);
+  Fx.y = sc * (pxx * fx.y + pxy * fy.y);
+  Fy.x = sc * (pxy * fx.x + pyy * fy.x);
+  Fy.y = sc * (pxy * fx.y + pyy * fy.y);
 }
 
 template <typename T, typename A>
