@@ -489,9 +489,9 @@ fbim_status run_operator(BatchEngine *E, Tables &T, bool f32, bool saddle) {
       const size_t M = c->d.M, slot = E->slot_of[T.list[q]], gsz = 2 * M * M, ssz = 4 * M * (M / 2 + 1);
       const WaveConvArgs a{c->d.M, 0, c->d.L, c->d.xi, c->d.eta_s, c->d.h * c->d.h / (c->p.eta * c->d.L * c->d.L)};
       if (f32)
-        EHIP(E, launch_wave_conv_f32(a, k.grid32 + slot * gsz, k.spec32 + slot * ssz, c->d_tw32, s));
+        EHIP(E, launch_wave_conv_f32(a, k.grid32 + slot * gsz, k.spec32 + slot * ssz, c->d_tw32, c->d_ey32, s));
       else
-        EHIP(E, launch_wave_conv_f64(a, k.grid + slot * gsz, k.spec + slot * ssz, c->d_tw, s));
+        EHIP(E, launch_wave_conv_f64(a, k.grid + slot * gsz, k.spec + slot * ssz, c->d_tw, c->d_ey, s));
     }
   } else {
     {

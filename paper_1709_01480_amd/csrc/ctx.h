@@ -117,8 +117,8 @@ struct fbim_ctx {
   float *d_grid32 = nullptr, *d_spec32 = nullptr;
   rocfft_plan fwd = nullptr, inv = nullptr, fwd32 = nullptr, inv32 = nullptr;
   bool conv = false;  // fused transform kernels (else the rocFFT plans)
-  double *d_tw = nullptr;
-  float *d_tw32 = nullptr;
+  double *d_tw = nullptr, *d_ey = nullptr;  // twiddles; Gaussian factors per frequency index
+  float *d_tw32 = nullptr, *d_ey32 = nullptr;
   rocfft_execution_info einfo = nullptr;
   void *fft_work = nullptr;
   size_t fft_work_bytes = 0;

@@ -68,6 +68,14 @@ fbim_status setup_fft(fbim_ctx *c) {
     std::vector<float> tw32(tw.begin(), tw.end());
     STCHK(upload(c, c->d_tw, tw));
     STCHK(upload(c, c->d_tw32, tw32));
+    std::vector<double> ey(M);
+    for (size_t i = 0; i < M; ++i) {
+      const double k = 2.0 * kPi / c->d.L * (i < M / 2 ? (double)i : (double)i - (double)M);
+      ey[i] = std::exp(-(1.0 - c->d.eta_s) * k * k / (4.0 * c->d.xi * c->d.xi));
+    }
+    std::vector<float> ey32(ey.begin(), ey.end());
+    STCHK(upload(c, c->d_ey, ey));
+    STCHK(upload(c, c->d_ey32, ey32));
     return FBIM_OK;
   }
   if (!g_rocfft_ready) {
@@ -392,7 +400,7 @@ fbim_status apply_M(fbim_ctx *c, const double *mu, double *out, unsigned parts) 
       if (c->conv) {
         Timer t(c, "fft32");
         HIPCHK(c, launch_wave_conv_f32(WaveConvArgs{c->d.M, 0, c->d.L, c->d.xi, c->d.eta_s, scale}, c->d_grid32,
-                                       c->d_spec32, c->d_tw32, s));
+                                       c->d_spec32, c->d_tw32, c->d_ey32, s));
       } else {
         {
           Timer t(c, "fft32");
@@ -418,7 +426,7 @@ fbim_status apply_M(fbim_ctx *c, const double *mu, double *out, unsigned parts) 
       if (c->conv) {
         Timer t(c, "fft");
         HIPCHK(c, launch_wave_conv_f64(WaveConvArgs{c->d.M, 0, c->d.L, c->d.xi, c->d.eta_s, scale}, c->d_grid,
-                                       c->d_spec, c->d_tw, s));
+                                       c->d_spec, c->d_tw, c->d_ey, s));
       } else {
         {
           Timer t(c, "fft");
@@ -460,7 +468,7 @@ fbim_status random_field(fbim_ctx *c, const double *W_grid, double *out) {
   if (c->conv) {
     Timer t(c, "fft");
     HIPCHK(c, launch_wave_conv_f64(WaveConvArgs{c->d.M, 1, c->d.L, c->d.xi, c->d.eta_s, scale}, c->d_grid, c->d_spec,
-                                   c->d_tw, s));
+                                   c->d_tw, c->d_ey, s));
   } else {
     {
       Timer t(c, "fft");
@@ -984,7 +992,7 @@ void fbim_destroy(fbim_ctx *c) {
                   c->d_mut, c->d_src32, c->d_xt32, c->d_mut32, c->d_grid, c->d_spec, c->d_grid32,
                   c->d_spec32, c->d_e1tab, c->d_e1tab32, c->d_V, c->d_w, c->d_t1, c->d_t2, c->d_b, c->d_x2,
                   c->d_r, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
-                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU, c->d_bx, c->d_by, c->d_tw, c->d_tw32};
+                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU, c->d_bx, c->d_by, c->d_tw, c->d_tw32, c->d_ey, c->d_ey32};
   engine_delete(c->rfd_engine);
   for (fbim_ctx *r : c->rfd)
     if (r) fbim_destroy(r);

@@ -121,14 +121,17 @@ hipError_t launch_multiplier_f64(int M, double L, double xi, double eta_s, doubl
 // Fused wave-space convolution (kernels_fft.hip) for power-of-two 64 <= M <= 2048:
 // grid planes [2][M][M] -> same planes after transform, multiplier (mode, scale as
 // launch_multiplier) and inverse transform; spec is scratch of 4 M (M/2+1) reals
-// (the half spectra, kx-major); tw holds exp(-2 pi i k / M), k < M (interleaved).
+// (the half spectra, kx-major); tw holds exp(-2 pi i k / M), k < M (interleaved);
+// ey[i] = exp(-(1 - eta_s) k_i^2 / 4 xi^2) with k_i = 2 pi / L (i < M/2 ? i : i - M).
 struct WaveConvArgs {
   int M, mode;
   double L, xi, eta_s, scale;
 };
 bool wave_conv_supported(int M);
-hipError_t launch_wave_conv_f64(const WaveConvArgs &a, double *grid, double *spec, const double *tw, hipStream_t s);
-hipError_t launch_wave_conv_f32(const WaveConvArgs &a, float *grid, float *spec, const float *tw, hipStream_t s);
+hipError_t launch_wave_conv_f64(const WaveConvArgs &a, double *grid, double *spec, const double *tw, const double *ey,
+                                hipStream_t s);
+hipError_t launch_wave_conv_f32(const WaveConvArgs &a, float *grid, float *spec, const float *tw, const float *ey,
+                                hipStream_t s);
 hipError_t launch_multiplier_f32(int M, double L, double xi, double eta_s, double scale, int mode, float *spec,
                                  hipStream_t s);
 

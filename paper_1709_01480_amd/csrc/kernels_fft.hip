@@ -27,7 +27,8 @@ template <typename T> struct Cx;
 template <> struct Cx<double> { using type = double2; };
 template <> struct Cx<float> { using type = float2; };
 
-// complex elements per work group (256 threads, 16 or 32 per thread) and LDS padding
+// threads and complex elements per work group (8 or 16 per thread) and LDS padding
+constexpr int kThreads = 512;
 template <typename T> constexpr int kElems = sizeof(T) == 8 ? 4096 : 8192;
 // elements of a row-kernel work group: whole rows, at most the grid
 template <typename T, int M> constexpr int kRowElems = kElems<T> < M * M ? kElems<T> : M * M;
@@ -113,22 +114,37 @@ template <typename V, int R, bool INV> __device__ __forceinline__ void dft(V (&v
   }
 }
 
+// Twiddles W_N^m = exp(-2 pi i m / N) from a two-level table in LDS: lo[i] = W_N^i
+// (i < 64) and hi[i] = W_N^(64 i) (i < N / 64), W_N^m = hi[m >> 6] lo[m & 63].
+template <typename V> struct TwLds {
+  V lo[64], hi[32];
+};
+template <typename V, int N> __device__ __forceinline__ void tw_fill(TwLds<V> &t, const V *__restrict__ tw) {
+  const int tid = threadIdx.x;
+  if (tid < (N < 64 ? N : 64)) t.lo[tid] = tw[tid];
+  if (tid < (N >= 64 ? N / 64 : 0)) t.hi[tid] = tw[64 * tid];
+}
+template <typename V, int N> __device__ __forceinline__ V tw_get(const TwLds<V> &t, int m) {
+  if constexpr (N <= 64) return t.lo[m];
+  else return cmul(t.hi[m >> 6], t.lo[m & 63]);
+}
+
 // One Stockham stage of radix R over NSEQ sequences of length N in LDS; Ns is the
 // length of the sub-transforms already combined.  Butterfly j of a sequence reads
 // elements j + r N/R, applies the twiddles W_N^{(j mod Ns) r N/(Ns R)}, takes the
 // length-R DFT and writes element (j / Ns) Ns R + (j mod Ns) + r Ns.  All reads of
 // the stage complete (barrier) before its writes.
 template <typename T, int N, int R, int NSEQ, bool INV>
-__device__ __forceinline__ void fft_stage(typename Cx<T>::type *buf, int Ns, const typename Cx<T>::type *__restrict__ tw) {
+__device__ __forceinline__ void fft_stage(typename Cx<T>::type *buf, int Ns, const TwLds<typename Cx<T>::type> &tw) {
   using V = typename Cx<T>::type;
-  constexpr int NB = NSEQ * N / R, PER = NB / 256;
-  static_assert(NB % 256 == 0, "whole butterflies per thread");
+  constexpr int NB = NSEQ * N / R, PER = NB / kThreads;
+  static_assert(NB % kThreads == 0, "whole butterflies per thread");
   const int tid = threadIdx.x;
   V v[PER][R];
   int dst[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int b = tid + 256 * q;
+    const int b = tid + kThreads * q;
     const int seq = b / (N / R), j = b % (N / R);
 #pragma unroll
     for (int r = 0; r < R; ++r) v[q][r] = buf[pad<T>(seq * N + j + r * (N / R))];
@@ -137,7 +153,7 @@ __device__ __forceinline__ void fft_stage(typename Cx<T>::type *buf, int Ns, con
       const int step = N / (Ns * R);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        V w = tw[k * r * step];
+        V w = tw_get<V, N>(tw, k * r * step);
         if (INV) w.y = -w.y;
         v[q][r] = cmul(v[q][r], w);
       }
@@ -155,7 +171,7 @@ __device__ __forceinline__ void fft_stage(typename Cx<T>::type *buf, int Ns, con
 
 // unnormalised FFT (INV: exponent sign +) of NSEQ sequences of length 2^LOG2N in LDS
 template <typename T, int LOG2N, int NSEQ, bool INV>
-__device__ __forceinline__ void fft_lds(typename Cx<T>::type *buf, const typename Cx<T>::type *__restrict__ tw) {
+__device__ __forceinline__ void fft_lds(typename Cx<T>::type *buf, const TwLds<typename Cx<T>::type> &tw) {
   constexpr int N = 1 << LOG2N;
   int Ns = 1;
 #pragma unroll
@@ -169,25 +185,31 @@ __device__ __forceinline__ void fft_lds(typename Cx<T>::type *buf, const typenam
 
 // rows forward: grid planes [2][M][M] -> S[kx][y] = (H_x, H_y), kx <= M/2
 template <typename T, int LOG2M>
-__global__ __launch_bounds__(256) void k_rows_fwd(const T *__restrict__ grid, typename Cx<T>::type *__restrict__ S,
+__global__ __launch_bounds__(kThreads) void k_rows_fwd(const T *__restrict__ grid, typename Cx<T>::type *__restrict__ S,
                                                   const typename Cx<T>::type *__restrict__ tw) {
   using V = typename Cx<T>::type;
   constexpr int M = 1 << LOG2M, E = kRowElems<T, M>, B = E / M;
   __shared__ V buf[E + (E >> kPadShift<T>)];
+  __shared__ TwLds<V> twl;
   const int tid = threadIdx.x;
   const int y0 = blockIdx.x * B;
   const size_t plane = (size_t)M * M;
-  for (int e = tid; e < E; e += 256) {
-    const size_t g = (size_t)y0 * M + e;  // rows y0 .. y0 + B - 1 are contiguous
-    V z;
-    z.x = grid[g];
-    z.y = grid[plane + g];
-    buf[pad<T>(e)] = z;
+  constexpr int NL = E / kThreads;  // every load of the thread in flight before the first store
+  static_assert(E % kThreads == 0, "whole rows per work group");
+  V z[NL];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const size_t g = (size_t)y0 * M + tid + q * kThreads;  // rows y0 .. y0 + B - 1 are contiguous
+    z[q].x = grid[g];
+    z[q].y = grid[plane + g];
   }
+  tw_fill<V, M>(twl, tw);
+#pragma unroll
+  for (int q = 0; q < NL; ++q) buf[pad<T>(tid + q * kThreads)] = z[q];
   __syncthreads();
-  fft_lds<T, LOG2M, B, false>(buf, tw);
+  fft_lds<T, LOG2M, B, false>(buf, twl);
   // H_x = (Z[k] + conj Z[M-k]) / 2, H_y = (Z[k] - conj Z[M-k]) / 2i; row index fastest
-  for (int e = tid; e < (M / 2 + 1) * B; e += 256) {
+  for (int e = tid; e < (M / 2 + 1) * B; e += kThreads) {
     const int r = e % B, kx = e / B;
     const V Z = buf[pad<T>(r * M + kx)], Zm = buf[pad<T>(r * M + ((M - kx) & (M - 1)))];
     V h0, h1;
@@ -202,37 +224,64 @@ __global__ __launch_bounds__(256) void k_rows_fwd(const T *__restrict__ grid, ty
 }
 
 // columns: per kx, FFT along y of both components, multiplier, inverse FFT
-template <typename T, int LOG2M>
-__global__ __launch_bounds__(256) void k_cols(typename Cx<T>::type *__restrict__ S,
-                                              const typename Cx<T>::type *__restrict__ tw, T twopi_L, T inv4xi2,
-                                              T one_m_eta, T scale, int mode) {
+template <typename T, int LOG2M, int MODE>
+__global__ __launch_bounds__(kThreads) void k_cols(typename Cx<T>::type *__restrict__ S,
+                                              const typename Cx<T>::type *__restrict__ tw,
+                                              const T *__restrict__ ey, T twopi_L, T inv4xi2, T one_m_eta, T scale) {
   using V = typename Cx<T>::type;
   constexpr int M = 1 << LOG2M, E = kElems<T>, CB = E / (2 * M), NCOL = M / 2 + 1;
   __shared__ V buf[E + (E >> kPadShift<T>)];
+  __shared__ TwLds<V> twl;
   const int tid = threadIdx.x;
   const int c0 = blockIdx.x * CB;
-  for (int e = tid; e < CB * M; e += 256) {
-    const int c = e >> LOG2M, y = e & (M - 1);
-    V a, b;
-    a.x = a.y = b.x = b.y = T(0);
+  constexpr int NL = CB * M / kThreads;
+  static_assert((CB * M) % kThreads == 0, "whole columns per work group");
+  V a[NL], b[NL];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int e = tid + q * kThreads, c = e >> LOG2M, y = e & (M - 1);
+    a[q].x = a[q].y = b[q].x = b[q].y = T(0);
     if (c0 + c < NCOL) {
       const V *src = S + 2 * ((size_t)(c0 + c) * M + y);
-      a = src[0];
-      b = src[1];
+      a[q] = src[0];
+      b[q] = src[1];
     }
-    buf[pad<T>(2 * c * M + y)] = a;
-    buf[pad<T>((2 * c + 1) * M + y)] = b;
+  }
+  tw_fill<V, M>(twl, tw);
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int e = tid + q * kThreads, c = e >> LOG2M, y = e & (M - 1);
+    buf[pad<T>(2 * c * M + y)] = a[q];
+    buf[pad<T>((2 * c + 1) * M + y)] = b[q];
   }
   __syncthreads();
-  fft_lds<T, LOG2M, 2 * CB, false>(buf, tw);
-  for (int e = tid; e < CB * M; e += 256) {
+  fft_lds<T, LOG2M, 2 * CB, false>(buf, twl);
+  for (int e = tid; e < CB * M; e += kThreads) {
     const int c = e >> LOG2M, ky = e & (M - 1);
     if (c0 + c >= NCOL) continue;
     V &f0 = buf[pad<T>(2 * c * M + ky)];
     V &f1 = buf[pad<T>((2 * c + 1) * M + ky)];
     T sc, pxx, pxy, pyy;
     V g0, g1;
-    if (wave_multiplier<T>(M, ky, c0 + c, twopi_L, inv4xi2, one_m_eta, scale, mode, sc, pxx, pxy, pyy)) {
+    bool nz;
+    if (MODE == 0) {
+      // M^(w): the Gaussian factor exp(-(1-eta_s) k^2 / 4 xi^2) is the product of
+      // its kx and ky factors, both read from the table ey (indexed by frequency index)
+      const int kxi = c0 + c;
+      const T kx = twopi_L * kxi, kyv = twopi_L * (ky < M / 2 ? ky : ky - M);
+      const T k2 = kx * kx + kyv * kyv;
+      nz = k2 != T(0);
+      if (nz) {
+        const T ik2 = T(1) / k2;
+        sc = (T(1) + k2 * inv4xi2) * ey[kxi] * ey[ky] * ik2 * scale;
+        pxx = T(1) - kx * kx * ik2;
+        pyy = T(1) - kyv * kyv * ik2;
+        pxy = (kxi == M / 2 || ky == M / 2) ? T(0) : -kx * kyv * ik2;
+      }
+    } else {
+      nz = wave_multiplier<T>(M, ky, c0 + c, twopi_L, inv4xi2, one_m_eta, scale, MODE, sc, pxx, pxy, pyy);
+    }
+    if (nz) {
       g0.x = sc * (pxx * f0.x + pxy * f1.x);
       g0.y = sc * (pxx * f0.y + pxy * f1.y);
       g1.x = sc * (pxy * f0.x + pyy * f1.x);
@@ -244,8 +293,8 @@ __global__ __launch_bounds__(256) void k_cols(typename Cx<T>::type *__restrict__
     f1 = g1;
   }
   __syncthreads();
-  fft_lds<T, LOG2M, 2 * CB, true>(buf, tw);
-  for (int e = tid; e < CB * M; e += 256) {
+  fft_lds<T, LOG2M, 2 * CB, true>(buf, twl);
+  for (int e = tid; e < CB * M; e += kThreads) {
     const int c = e >> LOG2M, y = e & (M - 1);
     if (c0 + c >= NCOL) continue;
     V *dst = S + 2 * ((size_t)(c0 + c) * M + y);
@@ -256,17 +305,31 @@ __global__ __launch_bounds__(256) void k_cols(typename Cx<T>::type *__restrict__
 
 // rows inverse: S -> grid planes; Z[k] = U_x[k] + i U_y[k] over the Hermitian extension
 template <typename T, int LOG2M>
-__global__ __launch_bounds__(256) void k_rows_inv(const typename Cx<T>::type *__restrict__ S, T *__restrict__ grid,
+__global__ __launch_bounds__(kThreads) void k_rows_inv(const typename Cx<T>::type *__restrict__ S, T *__restrict__ grid,
                                                   const typename Cx<T>::type *__restrict__ tw) {
   using V = typename Cx<T>::type;
   constexpr int M = 1 << LOG2M, E = kRowElems<T, M>, B = E / M;
   __shared__ V buf[E + (E >> kPadShift<T>)];
+  __shared__ TwLds<V> twl;
   const int tid = threadIdx.x;
   const int y0 = blockIdx.x * B;
-  for (int e = tid; e < (M / 2 + 1) * B; e += 256) {
-    const int r = e % B, k = e / B;
-    const V *src = S + 2 * ((size_t)k * M + y0 + r);
-    V g0 = src[0], g1 = src[1];
+  constexpr int NI = (M / 2 + 1) * B, NL = (NI + kThreads - 1) / kThreads;
+  V a[NL], b[NL];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int e = tid + q * kThreads, r = e % B, k = e / B;
+    if (e < NI) {
+      const V *src = S + 2 * ((size_t)k * M + y0 + r);
+      a[q] = src[0];
+      b[q] = src[1];
+    }
+  }
+  tw_fill<V, M>(twl, tw);
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int e = tid + q * kThreads, r = e % B, k = e / B;
+    if (e >= NI) continue;
+    V g0 = a[q], g1 = b[q];
     if (k == 0 || k == M / 2) g0.y = g1.y = T(0);
     V z;
     z.x = g0.x - g1.y;
@@ -280,9 +343,9 @@ __global__ __launch_bounds__(256) void k_rows_inv(const typename Cx<T>::type *__
     }
   }
   __syncthreads();
-  fft_lds<T, LOG2M, B, true>(buf, tw);
+  fft_lds<T, LOG2M, B, true>(buf, twl);
   const size_t plane = (size_t)M * M;
-  for (int e = tid; e < E; e += 256) {
+  for (int e = tid; e < E; e += kThreads) {
     const V z = buf[pad<T>(e)];
     const size_t g = (size_t)y0 * M + e;
     grid[g] = z.x;
@@ -292,28 +355,33 @@ __global__ __launch_bounds__(256) void k_rows_inv(const typename Cx<T>::type *__
 
 template <typename T, int LOG2M>
 hipError_t conv_launch(const WaveConvArgs &a, T *grid, typename Cx<T>::type *spec,
-                       const typename Cx<T>::type *tw, hipStream_t s) {
+                       const typename Cx<T>::type *tw, const T *ey, hipStream_t s) {
   constexpr int M = 1 << LOG2M, E = kElems<T>, ER = kRowElems<T, M>;
   constexpr int rows_blocks = M / (ER / M), col_blocks = (M / 2 + 1 + E / (2 * M) - 1) / (E / (2 * M));
-  hipLaunchKernelGGL((k_rows_fwd<T, LOG2M>), dim3(rows_blocks), dim3(256), 0, s, grid, spec, tw);
-  hipLaunchKernelGGL((k_cols<T, LOG2M>), dim3(col_blocks), dim3(256), 0, s, spec, tw, (T)(2.0 * M_PI / a.L),
-                     (T)(1.0 / (4.0 * a.xi * a.xi)), (T)(1.0 - a.eta_s), (T)a.scale, a.mode);
-  hipLaunchKernelGGL((k_rows_inv<T, LOG2M>), dim3(rows_blocks), dim3(256), 0, s, spec, grid, tw);
+  hipLaunchKernelGGL((k_rows_fwd<T, LOG2M>), dim3(rows_blocks), dim3(kThreads), 0, s, grid, spec, tw);
+  const T twopi_L = (T)(2.0 * M_PI / a.L), inv4xi2 = (T)(1.0 / (4.0 * a.xi * a.xi)), ome = (T)(1.0 - a.eta_s);
+  if (a.mode == 0)
+    hipLaunchKernelGGL((k_cols<T, LOG2M, 0>), dim3(col_blocks), dim3(kThreads), 0, s, spec, tw, ey, twopi_L, inv4xi2,
+                       ome, (T)a.scale);
+  else
+    hipLaunchKernelGGL((k_cols<T, LOG2M, 1>), dim3(col_blocks), dim3(kThreads), 0, s, spec, tw, ey, twopi_L, inv4xi2,
+                       ome, (T)a.scale);
+  hipLaunchKernelGGL((k_rows_inv<T, LOG2M>), dim3(rows_blocks), dim3(kThreads), 0, s, spec, grid, tw);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t conv_dispatch(const WaveConvArgs &a, T *grid, T *spec, const T *tw, hipStream_t s) {
+hipError_t conv_dispatch(const WaveConvArgs &a, T *grid, T *spec, const T *tw, const T *ey, hipStream_t s) {
   using V = typename Cx<T>::type;
   V *sp = reinterpret_cast<V *>(spec);
   const V *t = reinterpret_cast<const V *>(tw);
   switch (a.M) {
-    case 64: return conv_launch<T, 6>(a, grid, sp, t, s);
-    case 128: return conv_launch<T, 7>(a, grid, sp, t, s);
-    case 256: return conv_launch<T, 8>(a, grid, sp, t, s);
-    case 512: return conv_launch<T, 9>(a, grid, sp, t, s);
-    case 1024: return conv_launch<T, 10>(a, grid, sp, t, s);
-    case 2048: return conv_launch<T, 11>(a, grid, sp, t, s);
+    case 64: return conv_launch<T, 6>(a, grid, sp, t, ey, s);
+    case 128: return conv_launch<T, 7>(a, grid, sp, t, ey, s);
+    case 256: return conv_launch<T, 8>(a, grid, sp, t, ey, s);
+    case 512: return conv_launch<T, 9>(a, grid, sp, t, ey, s);
+    case 1024: return conv_launch<T, 10>(a, grid, sp, t, ey, s);
+    case 2048: return conv_launch<T, 11>(a, grid, sp, t, ey, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -322,12 +390,14 @@ hipError_t conv_dispatch(const WaveConvArgs &a, T *grid, T *spec, const T *tw, h
 
 bool wave_conv_supported(int M) { return M >= 64 && M <= 2048 && (M & (M - 1)) == 0; }
 
-hipError_t launch_wave_conv_f64(const WaveConvArgs &a, double *grid, double *spec, const double *tw, hipStream_t s) {
-  return conv_dispatch<double>(a, grid, spec, tw, s);
+hipError_t launch_wave_conv_f64(const WaveConvArgs &a, double *grid, double *spec, const double *tw, const double *ey,
+                                hipStream_t s) {
+  return conv_dispatch<double>(a, grid, spec, tw, ey, s);
 }
 
-hipError_t launch_wave_conv_f32(const WaveConvArgs &a, float *grid, float *spec, const float *tw, hipStream_t s) {
-  return conv_dispatch<float>(a, grid, spec, tw, s);
+hipError_t launch_wave_conv_f32(const WaveConvArgs &a, float *grid, float *spec, const float *tw, const float *ey,
+                                hipStream_t s) {
+  return conv_dispatch<float>(a, grid, spec, tw, ey, s);
 }
 
 }  // namespace fbim
