@@ -98,20 +98,7 @@ fbim_status efail(BatchEngine *E, fbim_status s, const std::string &m) {
     if (s_ != FBIM_OK) return s_; \
   } while (0)
 
-WaveArgs wave_args(const fbim_ctx *c) {
-  WaveArgs w;
-  w.M = c->d.M;
-  w.T = c->d.tile;
-  w.P = c->d.P;
-  w.nts = c->nts;
-  w.h = c->d.h;
-  w.L = c->d.L;
-  w.ag = 2.0 * c->d.xi * c->d.xi / c->d.eta_s;
-  w.cg = 2.0 * c->d.xi * c->d.xi / (kPi * c->d.eta_s);
-  w.tile_start = c->d_tstart;
-  w.anchor = c->d_anchor;
-  return w;
-}
+WaveArgs wave_args(const fbim_ctx *c) { return c->wave(); }
 
 void destroy_classes(BatchEngine *E) {
   for (auto &k : E->classes) {

@@ -106,6 +106,9 @@ struct fbim_ctx {
   // neighbour lists of the real-space sum
   int ngroups = 0;
   size_t ell_cap = 0;
+  // spreading lists: per tile, the tile-sorted nodes whose stencil touches it
+  int *d_scount = nullptr, *d_sstart = nullptr, *d_slist = nullptr;
+  size_t slist_cap = 0;
   int *d_cnt_near = nullptr, *d_cnt_far = nullptr, *d_gnn = nullptr, *d_gnf = nullptr, *d_goff = nullptr,
       *d_gsize = nullptr, *d_ell = nullptr;
 
@@ -148,6 +151,22 @@ struct fbim_ctx {
   std::map<std::string, std::vector<TimedLaunch>> pending;
   std::map<std::string, std::pair<double, int64_t>> acc;
 
+  WaveArgs wave() const {
+    WaveArgs w;
+    w.M = d.M;
+    w.T = d.tile;
+    w.P = d.P;
+    w.nts = nts;
+    w.h = d.h;
+    w.L = d.L;
+    w.ag = 2.0 * d.xi * d.xi / d.eta_s;
+    w.cg = 2.0 * d.xi * d.xi / (kPi * d.eta_s);
+    w.tile_start = d_tstart;
+    w.anchor = d_anchor;
+    w.slist_start = d_sstart;
+    w.slist = d_slist;
+    return w;
+  }
   PairArgs pair_args() const {
     PairArgs a;
     a.cell_start = d_cstart;

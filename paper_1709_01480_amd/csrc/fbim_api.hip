@@ -332,23 +332,33 @@ fbim_status build_geometry(fbim_ctx *c) {
   c->nbatch = std::max(1, (hv[0] + 63) / 64);
   c->max_tile = hv[2];
   if (hv[1]) return fail(c, FBIM_EOVERLAP, "nodes of distinct bodies closer than 5% of the node spacing");
-  // neighbour lists of the real-space sum: count, group rows, offsets, fill
+  // neighbour lists of the real-space sum (count, group rows, offsets, fill) and
+  // spreading lists of the tiles (count, offsets, fill); one read of both totals
   PairArgs pa = c->pair_args();
   PairLists pl = c->lists();
   HIPCHK(c, launch_pair_lists(pa, pl, c->d_xs, 0, s));
   HIPCHK(c, launch_group_rows(pl, c->d_gsize, s));
   HIPCHK(c, launch_scan(c->ngroups, c->d_gsize, c->d_goff, c->d_scal_int + 3, s));
-  int total = 0;
-  HIPCHK(c, hipMemcpyAsync(&total, c->d_goff + c->ngroups, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, launch_spread_lists(c->wave(), c->d_scount, nullptr, nullptr, 0, s));
+  HIPCHK(c, launch_scan(c->ntile, c->d_scount, c->d_sstart, c->d_scal_int + 4, s));
+  int total[2] = {0, 0};
+  HIPCHK(c, hipMemcpyAsync(&total[0], c->d_goff + c->ngroups, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(&total[1], c->d_sstart + c->ntile, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
-  if ((size_t)total > c->ell_cap) {
-    const size_t cap = (size_t)total + total / 4 + 64;
+  if ((size_t)total[0] > c->ell_cap) {
+    const size_t cap = (size_t)total[0] + total[0] / 4 + 64;
     HIPCHK(c, dalloc(c->d_ell, cap));
     c->ell_cap = cap;
     pl.ell = c->d_ell;
   }
-  HIPCHK(c, launch_fill_int((size_t)total, -1, c->d_ell, s));
+  HIPCHK(c, launch_fill_int((size_t)total[0], -1, c->d_ell, s));
   HIPCHK(c, launch_pair_lists(pa, pl, c->d_xs, 1, s));
+  if ((size_t)total[1] > c->slist_cap) {
+    const size_t cap = (size_t)total[1] + total[1] / 4 + 64;
+    HIPCHK(c, dalloc(c->d_slist, cap));
+    c->slist_cap = cap;
+  }
+  HIPCHK(c, launch_spread_lists(c->wave(), nullptr, c->d_sstart, c->d_slist, 1, s));
   if (c->mlp_on) STCHK(mlp_refresh(c));
   return FBIM_OK;
 }
@@ -379,17 +389,7 @@ fbim_status apply_M(fbim_ctx *c, const double *mu, double *out, unsigned parts) 
     HIPCHK(c, launch_alpert(c->geom(), c->d_band_arr, c->d_band, mu, out, 1, s));
   }
   if (parts & FBIM_PART_WAVE) {
-    WaveArgs w;
-    w.M = c->d.M;
-    w.T = c->d.tile;
-    w.P = c->d.P;
-    w.nts = c->nts;
-    w.h = c->d.h;
-    w.L = c->d.L;
-    w.ag = 2.0 * c->d.xi * c->d.xi / c->d.eta_s;
-    w.cg = 2.0 * c->d.xi * c->d.xi / (kPi * c->d.eta_s);
-    w.tile_start = c->d_tstart;
-    w.anchor = c->d_anchor;
+    const WaveArgs w = c->wave();
     const double scale = c->d.h * c->d.h / (c->p.eta * c->d.L * c->d.L);
     if (f32) {
       HIPCHK(c, launch_gather2f(N, c->d_tperm, mu, c->d_mut32, s));
@@ -451,17 +451,7 @@ fbim_status apply_M(fbim_ctx *c, const double *mu, double *out, unsigned parts) 
 fbim_status random_field(fbim_ctx *c, const double *W_grid, double *out) {
   hipStream_t s = c->stream;
   const size_t M = c->d.M;
-  WaveArgs w;
-  w.M = c->d.M;
-  w.T = c->d.tile;
-  w.P = c->d.P;
-  w.nts = c->nts;
-  w.h = c->d.h;
-  w.L = c->d.L;
-  w.ag = 2.0 * c->d.xi * c->d.xi / c->d.eta_s;
-  w.cg = 2.0 * c->d.xi * c->d.xi / (kPi * c->d.eta_s);
-  w.tile_start = c->d_tstart;
-  w.anchor = c->d_anchor;
+  const WaveArgs w = c->wave();
   const double scale = 1.0 / ((double)M * std::sqrt(c->p.eta * c->d.L * c->d.L));
   HIPCHK(c, launch_fill(2 * (size_t)c->N, 0.0, out, s));
   HIPCHK(c, hipMemcpyAsync(c->d_grid, W_grid, 2 * M * M * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -954,7 +944,8 @@ fbim_status fbim_create(const fbim_params *params, fbim_ctx **out) {
       hipMalloc((void **)&c->d_scal_int, 8 * sizeof(int)) != hipSuccess ||
       dalloc(c->d_ccount, c->ncell) != hipSuccess || dalloc(c->d_ccursor, c->ncell) != hipSuccess ||
       dalloc(c->d_cstart, c->ncell + 1) != hipSuccess || dalloc(c->d_tcount, c->ntile) != hipSuccess ||
-      dalloc(c->d_tcursor, c->ntile) != hipSuccess || dalloc(c->d_tstart, c->ntile + 1) != hipSuccess) {
+      dalloc(c->d_tcursor, c->ntile) != hipSuccess || dalloc(c->d_tstart, c->ntile + 1) != hipSuccess ||
+      dalloc(c->d_scount, c->ntile) != hipSuccess || dalloc(c->d_sstart, c->ntile + 1) != hipSuccess) {
     fbim_destroy(c);
     return FBIM_EDEVICE;
   }
@@ -992,7 +983,7 @@ void fbim_destroy(fbim_ctx *c) {
                   c->d_mut, c->d_src32, c->d_xt32, c->d_mut32, c->d_grid, c->d_spec, c->d_grid32,
                   c->d_spec32, c->d_e1tab, c->d_e1tab32, c->d_V, c->d_w, c->d_t1, c->d_t2, c->d_b, c->d_x2,
                   c->d_r, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
-                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU, c->d_bx, c->d_by, c->d_tw, c->d_tw32, c->d_ey, c->d_ey32};
+                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU, c->d_bx, c->d_by, c->d_tw, c->d_tw32, c->d_ey, c->d_ey32, c->d_scount, c->d_sstart, c->d_slist};
   engine_delete(c->rfd_engine);
   for (fbim_ctx *r : c->rfd)
     if (r) fbim_destroy(r);

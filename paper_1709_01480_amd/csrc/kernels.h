@@ -80,7 +80,13 @@ struct WaveArgs {
   double h, L, ag, cg;  // Gaussian exp(-ag r^2) * cg
   const int *tile_start;
   const int *anchor;    // per tile-sorted node: nearest grid indices (ix, iy), unwrapped, from FP64 positions
+  const int *slist_start, *slist;  // spreading lists (launch_spread_lists)
 };
+// Spreading lists: per grid tile, the tile-sorted indices of the nodes whose
+// P x P stencil touches the tile (all in the 3 x 3 neighbouring tiles), in a
+// fixed order (neighbour tile, then node order).  mode 0: count[tile] = their
+// number; mode 1: list[start[tile] + rank] = node.
+hipError_t launch_spread_lists(const WaveArgs &w, int *count, const int *start, int *list, int mode, hipStream_t s);
 // xt are the tile-ordered offsets from the nearest grid point (launch_anchors)
 hipError_t launch_spread_f64(const WaveArgs &w, const double *xt, const double *mut, double *grid, hipStream_t s);
 hipError_t launch_spread_f32(const WaveArgs &w, const float *xt, const float *mut, float *grid, hipStream_t s);

@@ -201,7 +201,7 @@ __device__ inline int far_interval(T z) {
 // The loop keeps two loads in flight: the entry of slot i+2 and the source
 // record of slot i+1 are requested before slot i is evaluated.
 template <typename T, int DEG>
-__device__ void pair_ell_body(const PairJob &j, const T *__restrict__ tab, int blk) {
+__device__ __forceinline__ void pair_ell_body(const PairJob &j, const T *__restrict__ tab, int blk) {
   constexpr bool kKahan = sizeof(T) == 4;
   const T cell = (T)j.cell, xi2 = (T)j.xi2, cG = (T)j.cG;
   const int t = blk * 256 + threadIdx.x;
@@ -336,7 +336,7 @@ hipError_t launch_pair_f32(const PairLists &pl, const PairArgs &a, const float *
 }
 
 // ------------------------------------------------------------------ Alpert band
-__device__ void alpert_body(const GeomDev &g, const double *const *band_tab, const int *__restrict__ band,
+__device__ __forceinline__ void alpert_body(const GeomDev &g, const double *const *band_tab, const int *__restrict__ band,
                             const double2 *__restrict__ mu, double2 *__restrict__ out, int accumulate, int i) {
   if (i >= g.N) return;
   const int b = g.body[i];

@@ -34,36 +34,34 @@ __device__ inline int xcd_remap(int b, int n) {
 }
 
 // One 256-thread work group per T x T grid tile, accumulated in LDS (no global
-// atomics).  Candidate nodes (binned in the 3 x 3 neighbouring tiles) whose
-// stencil touches the tile are compacted into chunks of up to kSpreadChunk;
-// per chunk the P x- and P y-weights of every node are computed once, then the
-// (node, stencil row) items are spread over the threads and added with LDS
-// atomics.
+// atomics).  The nodes whose stencil touches the tile come from the tile's
+// spreading list (built once per configuration); they are taken in chunks of
+// kSpreadChunk: per chunk the P x- and P y-weights of every node are computed
+// once (x and y weights by two threads), then the (node, stencil row) items are
+// spread over the threads and added with LDS atomics.  The node data of the first
+// kSpreadPre chunks is requested before any of them is used.
 constexpr int kSpreadChunk = 128;
+constexpr int kSpreadPre = 4;
 
 __device__ inline int wrap_near(int i, int M) {  // valid for -M <= i < 2M
   return i < 0 ? i + M : (i >= M ? i - M : i);
 }
 
-// T: weights and positions; A: LDS accumulator (FP64 for both precisions: FP64
-// LDS atomics measured faster than FP32 ones here, and they add no rounding)
-template <typename T, typename A>
-__device__ void spread_body(int M, int TT, int P, int nts, T h, T ag, T cg, const int *__restrict__ tile_start,
-                            const typename Vec2<T>::type *__restrict__ xt, const int2 *__restrict__ anchor,
-                            const typename Vec2<T>::type *__restrict__ mut, T *__restrict__ grid, int tile) {
-  __shared__ A acc[2][kTmax * (kTmax + 1)];  // rows padded by one: a node's P rows fall in distinct banks
-  __shared__ T wgx[kSpreadChunk][kPmax], wgy[kSpreadChunk][kPmax];
-  __shared__ T nmx[kSpreadChunk], nmy[kSpreadChunk];
-  __shared__ int nbx[kSpreadChunk], nby[kSpreadChunk];
-  __shared__ int lst[kSpreadChunk + 256];
-  __shared__ int lcount;
-  const int tid = threadIdx.x;
+// stencil origin (first column or row) of a node relative to the tile origin g0, in [0, M)
+__device__ inline int stencil_origin(int a, int half, int g0, int M) {
+  return wrap_near((a - half) - g0 + (a - half < 0 ? M : 0), M);
+}
+
+__global__ __launch_bounds__(256) void k_spread_lists(int M, int TT, int P, int nts, const int *__restrict__ tile_start,
+                                                      const int2 *__restrict__ anchor, int *__restrict__ count,
+                                                      const int *__restrict__ start, int *__restrict__ list,
+                                                      int mode) {
+  __shared__ int wsum[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tile = blockIdx.x;
   const int tyi = tile / nts, txi = tile % nts;
   const int gx0 = txi * TT, gy0 = tyi * TT;
   const int half = (P - 1) / 2;
-  const int ST = TT + 1;
-  for (int i = tid; i < TT * ST; i += 256) acc[0][i] = acc[1][i] = A(0);
-  if (tid == 0) lcount = 0;
   int nstart[9], pre[10];
   pre[0] = 0;
 #pragma unroll
@@ -74,75 +72,156 @@ __device__ void spread_body(int M, int TT, int P, int nts, T h, T ag, T cg, cons
     pre[k + 1] = pre[k] + tile_start[tt + 1] - tile_start[tt];
   }
   const int ncand = pre[9];
-  __syncthreads();
-
-  auto process = [&](int cnt) {
-    // per-node weights: the stencil's first column / row relative to the tile
-    if (tid < cnt) {
-      const int g = lst[tid];
-      const auto p = xt[g];
-      const auto mu = mut[g];
-      const int2 an = anchor[g];
-      nbx[tid] = wrap_near((an.x - half) - gx0 + (an.x - half < 0 ? M : 0), M);
-      nby[tid] = wrap_near((an.y - half) - gy0 + (an.y - half < 0 ? M : 0), M);
-      nmx[tid] = mu.x;
-      nmy[tid] = mu.y;
-      for (int k = 0; k < P; ++k) {
-        const T d = T(half - k) * h;
-        const T dx = p.x + d, dy = p.y + d;  // offsets from the nearest grid point
-        wgx[tid][k] = dev_exp(-ag * dx * dx);
-        wgy[tid][k] = cg * dev_exp(-ag * dy * dy);
-      }
-    }
-    __syncthreads();
-    for (int it = tid; it < cnt * P; it += 256) {
-      const int j = it / P, q = it - j * P;
-      int ry = nby[j] + q;
-      ry = ry >= M ? ry - M : ry;
-      if (ry >= TT) continue;
-      const T wy = wgy[j][q];
-      const T ux = wy * nmx[j], uy = wy * nmy[j];
-      int rx = nbx[j];
-      for (int pc = 0; pc < P; ++pc, ++rx) {
-        const int xx = rx >= M ? rx - M : rx;
-        if (xx < TT) {
-          atomicAdd(&acc[0][ry * ST + xx], (A)(ux * wgx[j][pc]));
-          atomicAdd(&acc[1][ry * ST + xx], (A)(uy * wgx[j][pc]));
-        }
-      }
-    }
-    __syncthreads();
-  };
-
+  const int base = mode ? start[tile] : 0;
+  int running = 0;
   for (int v0 = 0; v0 < ncand; v0 += 256) {
     const int v = v0 + tid;
+    bool ok = false;
+    int g = 0;
     if (v < ncand) {
       int k = 0;
       while (k < 8 && v >= pre[k + 1]) ++k;
-      const int g = nstart[k] + (v - pre[k]);
+      g = nstart[k] + (v - pre[k]);
       const int2 an = anchor[g];
-      const int ux = wrap_near((an.x - half) - gx0 + (an.x - half < 0 ? M : 0), M);
-      const int uy = wrap_near((an.y - half) - gy0 + (an.y - half < 0 ? M : 0), M);
-      if ((ux < TT || ux + P - 1 >= M) && (uy < TT || uy + P - 1 >= M)) lst[atomicAdd(&lcount, 1)] = g;
+      const int ux = stencil_origin(an.x, half, gx0, M), uy = stencil_origin(an.y, half, gy0, M);
+      ok = (ux < TT || ux + P - 1 >= M) && (uy < TT || uy + P - 1 >= M);
+    }
+    const unsigned long long m = __ballot(ok);
+    if (lane == 0) wsum[wv] = __popcll(m);
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      off += q < wv ? wsum[q] : 0;
+      tot += wsum[q];
+    }
+    if (mode && ok) list[base + running + off + __popcll(m & ((1ull << lane) - 1ull))] = g;
+    running += tot;
+    __syncthreads();
+  }
+  if (mode == 0 && tid == 0) count[tile] = running;
+}
+
+// Gaussian weights w_k = scale exp(-ag d_k^2) on the stencil, d_k = x + (half - k) h.
+// FP64 uses the product recurrence of fast Gaussian gridding: with d0 = x + half h,
+// w_{k+1} = w_k exp(2 ag d0 h) exp(-ag h^2 (2k + 1)), the last factors being the
+// per-kernel constants ck[k] = gauss_step(k): two exponentials per node and
+// direction instead of P, at most P more roundings (~1e-15).  FP32 evaluates each
+// weight directly (the hardware exponential is cheap and the recurrence's
+// roundings would be ~1e-6).
+template <typename T>
+__device__ inline T gauss_step(T ag, T h, int k) {
+  return dev_exp(-ag * h * h * T(2 * k + 1));
+}
+template <typename T>
+__device__ inline void gauss_row(T x, T scale, T ag, T h, int half, int P, const T *ck, T *w) {
+  if constexpr (sizeof(T) == 8) {
+    const T d0 = x + T(half) * h;
+    const T e1 = dev_exp(T(2) * ag * d0 * h);
+    T v = scale * dev_exp(-ag * d0 * d0);
+    for (int k = 0; k < P; ++k) {
+      w[k] = v;
+      v = v * e1 * ck[k];
+    }
+  } else {
+    for (int k = 0; k < P; ++k) {
+      const T d = x + T(half - k) * h;
+      w[k] = scale * dev_exp(-ag * d * d);
+    }
+  }
+}
+
+// T: weights and positions; A: LDS accumulator (FP64 for both precisions: FP64
+// LDS atomics measured faster than FP32 ones here, and they add no rounding)
+template <typename T, typename A>
+__device__ __forceinline__ void spread_body(int M, int TT, int P, int nts, T h, T ag, T cg, const int *__restrict__ slist_start,
+                            const int *__restrict__ slist, const typename Vec2<T>::type *__restrict__ xt,
+                            const int2 *__restrict__ anchor, const typename Vec2<T>::type *__restrict__ mut,
+                            T *__restrict__ grid, int tile) {
+  using V2 = typename Vec2<T>::type;
+  __shared__ A acc[2][kTmax * (kTmax + 1)];  // rows padded by one: a node's P rows fall in distinct banks
+  __shared__ T wgx[kSpreadChunk][kPmax], wgy[kSpreadChunk][kPmax];
+  __shared__ T nmx[kSpreadChunk], nmy[kSpreadChunk], ck[kPmax];
+  __shared__ int nbx[kSpreadChunk], nby[kSpreadChunk], ncol[kSpreadChunk];
+  const int tid = threadIdx.x;
+  const int tyi = tile / nts, txi = tile % nts;
+  const int gx0 = txi * TT, gy0 = tyi * TT;
+  const int half = (P - 1) / 2;
+  const int ST = TT + 1;
+  const int ls = slist_start[tile], n = slist_start[tile + 1] - ls;
+  // thread t serves entry (chunk base + t % 128): its x weights (t < 128) or y weights
+  const int e0 = tid & (kSpreadChunk - 1);
+  const bool ycomp = tid >= kSpreadChunk;
+  V2 pr[kSpreadPre], mr[kSpreadPre];
+  int2 ar[kSpreadPre];
+#pragma unroll
+  for (int r = 0; r < kSpreadPre; ++r) {
+    const int e = e0 + kSpreadChunk * r;
+    if (e < n) {
+      const int g = slist[ls + e];
+      pr[r] = xt[g];
+      mr[r] = mut[g];
+      ar[r] = anchor[g];
+    }
+  }
+  for (int i = tid; i < TT * ST; i += 256) acc[0][i] = acc[1][i] = A(0);
+  if (tid < P) ck[tid] = gauss_step<T>(ag, h, tid);
+  __syncthreads();  // ck (and the zeroed accumulator) before any use
+
+  // per entry: the stencil's first row / column relative to the tile (negative when
+  // it starts in the neighbouring tile across a periodic edge), the columns
+  // [pc0, pc1) that fall in the tile, and the P weights per direction
+  auto weights = [&](V2 p, V2 mu, int2 an) {
+    if (!ycomp) {
+      const int ox = stencil_origin(an.x, half, gx0, M);
+      const int xs = ox < TT ? ox : ox - M;
+      nbx[e0] = xs;
+      ncol[e0] = max(0, -xs) | (min(P, TT - xs) << 8);
+      nmx[e0] = mu.x;
+      nmy[e0] = mu.y;
+      gauss_row<T>(p.x, T(1), ag, h, half, P, ck, wgx[e0]);
+    } else {
+      const int oy = stencil_origin(an.y, half, gy0, M);
+      nby[e0] = oy < TT ? oy : oy - M;
+      gauss_row<T>(p.y, cg, ag, h, half, P, ck, wgy[e0]);
+    }
+  };
+  const float invP = 1.0f / (float)P;
+  auto items = [&](int cnt) {
+    for (int it = tid; it < cnt * P; it += 256) {
+      const int j = (int)(((float)it + 0.5f) * invP), q = it - j * P;  // it / P, exact for it < 2^20
+      const int ry = nby[j] + q;
+      if (ry < 0 || ry >= TT) continue;
+      const T wy = wgy[j][q];
+      const T ux = wy * nmx[j], uy = wy * nmy[j];
+      const int cr = ncol[j], xs = nbx[j];
+      A *a0 = &acc[0][ry * ST + xs], *a1 = &acc[1][ry * ST + xs];
+      for (int pc = cr & 255; pc < (cr >> 8); ++pc) {
+        const T wx = wgx[j][pc];
+        atomicAdd(a0 + pc, (A)(ux * wx));
+        atomicAdd(a1 + pc, (A)(uy * wx));
+      }
+    }
+  };
+#pragma unroll
+  for (int r = 0; r < kSpreadPre; ++r) {
+    const int c = kSpreadChunk * r;
+    if (c >= n) break;  // n is uniform over the work group
+    const int cnt = min(kSpreadChunk, n - c);
+    if (e0 < cnt) weights(pr[r], mr[r], ar[r]);
+    __syncthreads();
+    items(cnt);
+    __syncthreads();
+  }
+  for (int c = kSpreadChunk * kSpreadPre; c < n; c += kSpreadChunk) {  // rare: crowded tiles
+    const int cnt = min(kSpreadChunk, n - c);
+    if (e0 < cnt) {
+      const int g = slist[ls + c + e0];
+      weights(xt[g], mut[g], anchor[g]);
     }
     __syncthreads();
-    // every thread takes its copy of the counter between two barriers, so the
-    // loop below (which contains barriers) is entered and left uniformly
-    int lc = lcount;
+    items(cnt);
     __syncthreads();
-    const bool last = v0 + 256 >= ncand;
-    // consume full chunks; the remainder (< kSpreadChunk) waits for more candidates
-    while (lc >= kSpreadChunk || (last && lc > 0)) {
-      const int cnt = min(lc, kSpreadChunk);
-      process(cnt);
-      const int rest = lc - cnt;
-      const int keep = tid < rest ? lst[cnt + tid] : 0;
-      __syncthreads();
-      if (tid < rest) lst[tid] = keep;
-      if (tid == 0) lcount = rest;
-      __syncthreads();
-      lc = rest;
-    }
   }
   for (int i = tid; i < TT * TT; i += 256) {
     const int ry = i / TT, rx = i - ry * TT;
@@ -153,12 +232,13 @@ __device__ void spread_body(int M, int TT, int P, int nts, T h, T ag, T cg, cons
 }
 
 template <typename T>
-__device__ void interp_body(int M, int TT, int P, int nts, T h, T ag, T scale, const int *__restrict__ tile_start,
+__device__ __forceinline__ void interp_body(int M, int TT, int P, int nts, T h, T ag, T scale, const int *__restrict__ tile_start,
                             const typename Vec2<T>::type *__restrict__ xt, const int2 *__restrict__ anchor,
                             const int *__restrict__ tperm, const T *__restrict__ grid, double *__restrict__ out,
                             int tile) {
   constexpr int W = kTmax + kPmax - 1;
   __shared__ T win[2][W * W];
+  __shared__ T ck[kPmax];
   const int tid = threadIdx.x;
   const int tyi = tile / nts, txi = tile % nts;
   const int gx0 = txi * TT, gy0 = tyi * TT;
@@ -170,6 +250,7 @@ __device__ void interp_body(int M, int TT, int P, int nts, T h, T ag, T scale, c
     win[0][i] = grid[gidx];
     win[1][i] = grid[(size_t)M * M + gidx];
   }
+  if (tid < P) ck[tid] = gauss_step<T>(ag, h, tid);
   __syncthreads();
   const int a = tile_start[tile], b = tile_start[tile + 1];
   for (int k = a + tid; k < b; k += 256) {
@@ -178,15 +259,14 @@ __device__ void interp_body(int M, int TT, int P, int nts, T h, T ag, T scale, c
     const int ixn = an.x, iyn = an.y;
     const int bx = wrapi(ixn - half - (gx0 - half), M);  // window column of the first stencil point
     const int by = wrapi(iyn - half - (gy0 - half), M);
-    T wx[kPmax];
-    for (int pc = 0; pc < P; ++pc) {
-      const T dx = p.x + T(half - pc) * h;  // offsets from the nearest grid point
-      wx[pc] = dev_exp(-ag * dx * dx);
-    }
+    // weights of the stencil's columns and rows (offsets p + (half - k) h from the
+    // nearest grid point) by the product recurrence
+    T wx[kPmax], wyr[kPmax];
+    gauss_row<T>(p.x, T(1), ag, h, half, P, ck, wx);
+    gauss_row<T>(p.y, T(1), ag, h, half, P, ck, wyr);
     T sx = 0, sy = 0;
     for (int qr = 0; qr < P; ++qr) {
-      const T dy = p.y + T(half - qr) * h;
-      const T wy = dev_exp(-ag * dy * dy);
+      const T wy = wyr[qr];
       const T *r0 = &win[0][(by + qr) * w + bx];
       const T *r1 = &win[1][(by + qr) * w + bx];
       T rx0 = 0, rx1 = 0;
@@ -206,7 +286,7 @@ __device__ void interp_body(int M, int TT, int P, int nts, T h, T ag, T scale, c
 // multiplier on the rocFFT half spectrum (plane c at [c][row][col], col <= M/2),
 // coefficients from wave_multiplier
 template <typename T>
-__device__ void multiplier_body(int M, T twopi_L, T inv4xi2, T one_m_eta, T scale, int mode,
+__device__ __forceinline__ void multiplier_body(int M, T twopi_L, T inv4xi2, T one_m_eta, T scale, int mode,
                                 typename Vec2<T>::type *__restrict__ spec, int idx) {
   const int nh = M / 2 + 1;
   if (idx >= M * nh) return;
@@ -227,12 +307,13 @@ __device__ void multiplier_body(int M, T twopi_L, T inv4xi2, T one_m_eta, T scal
 
 template <typename T, typename A>
 __global__ __launch_bounds__(256) void k_spread(int M, int TT, int P, int nts, T h, T ag, T cg,
-                                                const int *__restrict__ tile_start,
+                                                const int *__restrict__ slist_start, const int *__restrict__ slist,
                                                 const typename Vec2<T>::type *__restrict__ xt,
                                                 const int2 *__restrict__ anchor,
                                                 const typename Vec2<T>::type *__restrict__ mut,
                                                 T *__restrict__ grid) {
-  spread_body<T, A>(M, TT, P, nts, h, ag, cg, tile_start, xt, anchor, mut, grid, xcd_remap(blockIdx.x, gridDim.x));
+  spread_body<T, A>(M, TT, P, nts, h, ag, cg, slist_start, slist, xt, anchor, mut, grid,
+                    xcd_remap(blockIdx.x, gridDim.x));
 }
 
 template <typename T>
@@ -260,7 +341,7 @@ __global__ __launch_bounds__(256) void k_spread_batch(const SpreadJob *__restric
   const int gb = xcd_remap(blockIdx.x, gridDim.x);
   const int s = batch_system(bg.begin, bg.S, gb);
   const SpreadJob &j = jobs[s];
-  spread_body<T, A>(j.w.M, j.w.T, j.w.P, j.w.nts, (T)j.w.h, (T)j.w.ag, (T)j.w.cg, j.w.tile_start,
+  spread_body<T, A>(j.w.M, j.w.T, j.w.P, j.w.nts, (T)j.w.h, (T)j.w.ag, (T)j.w.cg, j.w.slist_start, j.w.slist,
                     reinterpret_cast<const V2 *>(j.xt), reinterpret_cast<const int2 *>(j.w.anchor),
                     reinterpret_cast<const V2 *>(j.mut), reinterpret_cast<T *>(j.grid), gb - bg.begin[s]);
 }
@@ -314,17 +395,25 @@ hipError_t launch_multiplier_batch(const MultJob *jobs, BatchGrid bg, int f32, i
   return hipGetLastError();
 }
 
+hipError_t launch_spread_lists(const WaveArgs &w, int *count, const int *start, int *list, int mode, hipStream_t s) {
+  const int nt = w.nts * w.nts;
+  if (nt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_spread_lists, dim3(nt), dim3(256), 0, s, w.M, w.T, w.P, w.nts, w.tile_start,
+                     (const int2 *)w.anchor, count, start, list, mode);
+  return hipGetLastError();
+}
+
 hipError_t launch_spread_f64(const WaveArgs &w, const double *xt, const double *mut, double *grid, hipStream_t s) {
   const int nt = w.nts * w.nts;
   hipLaunchKernelGGL((k_spread<double, double>), dim3(nt), dim3(256), 0, s, w.M, w.T, w.P, w.nts, w.h, w.ag, w.cg,
-                     w.tile_start, (const double2 *)xt, (const int2 *)w.anchor, (const double2 *)mut, grid);
+                     w.slist_start, w.slist, (const double2 *)xt, (const int2 *)w.anchor, (const double2 *)mut, grid);
   return hipGetLastError();
 }
 
 hipError_t launch_spread_f32(const WaveArgs &w, const float *xt, const float *mut, float *grid, hipStream_t s) {
   const int nt = w.nts * w.nts;
   hipLaunchKernelGGL((k_spread<float, double>), dim3(nt), dim3(256), 0, s, w.M, w.T, w.P, w.nts, (float)w.h, (float)w.ag,
-                     (float)w.cg, w.tile_start, (const float2 *)xt, (const int2 *)w.anchor, (const float2 *)mut,
+                     (float)w.cg, w.slist_start, w.slist, (const float2 *)xt, (const int2 *)w.anchor, (const float2 *)mut,
                      grid);
   return hipGetLastError();
 }
