@@ -322,29 +322,37 @@ fbim_status build_geometry(fbim_ctx *c) {
       spacing = std::min(spacing, std::sqrt(dx * dx + dy * dy));
     }
   }
+  // the count pass of the neighbour lists sees every pair within r_c, so it takes
+  // the check when the threshold is below r_c; otherwise a pass of its own does
+  const double thresh = 0.05 * spacing;
+  const bool fused = thresh < c->d.r_c;
   HIPCHK(c, hipMemsetAsync(c->d_scal_int + 1, 0, sizeof(int), s));
-  HIPCHK(c, launch_overlap(N, c->d_cstart, c->d_cperm, c->d_x, c->d_body, c->d.n_box, c->d.L, 0.05 * spacing,
-                           c->d_scal_int + 1, s));
+  if (!fused)
+    HIPCHK(c, launch_overlap(N, c->d_cstart, c->d_cperm, c->d_x, c->d_body, c->d.n_box, c->d.L, thresh,
+                             c->d_scal_int + 1, s));
   int hv[3];
   HIPCHK(c, hipMemcpyAsync(hv, c->d_scal_int, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   c->max_cell = hv[0];
   c->nbatch = std::max(1, (hv[0] + 63) / 64);
   c->max_tile = hv[2];
-  if (hv[1]) return fail(c, FBIM_EOVERLAP, "nodes of distinct bodies closer than 5% of the node spacing");
+  const char *overlap_msg = "nodes of distinct bodies closer than 5% of the node spacing";
+  if (hv[1]) return fail(c, FBIM_EOVERLAP, overlap_msg);
   // neighbour lists of the real-space sum (count, group rows, offsets, fill) and
   // spreading lists of the tiles (count, offsets, fill); one read of both totals
   PairArgs pa = c->pair_args();
   PairLists pl = c->lists();
-  HIPCHK(c, launch_pair_lists(pa, pl, c->d_xs, 0, s));
+  HIPCHK(c, launch_pair_lists(pa, pl, c->d_xs, 0, s, c->d_body, thresh * thresh, fused ? c->d_scal_int + 1 : nullptr));
   HIPCHK(c, launch_group_rows(pl, c->d_gsize, s));
   HIPCHK(c, launch_scan(c->ngroups, c->d_gsize, c->d_goff, c->d_scal_int + 3, s));
   HIPCHK(c, launch_spread_lists(c->wave(), c->d_scount, nullptr, nullptr, 0, s));
   HIPCHK(c, launch_scan(c->ntile, c->d_scount, c->d_sstart, c->d_scal_int + 4, s));
-  int total[2] = {0, 0};
+  int total[2] = {0, 0}, olap = 0;
   HIPCHK(c, hipMemcpyAsync(&total[0], c->d_goff + c->ngroups, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipMemcpyAsync(&total[1], c->d_sstart + c->ntile, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(&olap, c->d_scal_int + 1, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
+  if (olap) return fail(c, FBIM_EOVERLAP, overlap_msg);
   if ((size_t)total[0] > c->ell_cap) {
     const size_t cap = (size_t)total[0] + total[0] / 4 + 64;
     HIPCHK(c, dalloc(c->d_ell, cap));

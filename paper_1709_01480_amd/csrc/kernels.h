@@ -61,8 +61,11 @@ struct PairLists {
   int *gnn, *gnf, *goff;    // [ngroups], goff [ngroups + 1]
   int *ell;                 // [goff[ngroups]]
 };
-// mode 0: per-target near / far counts; mode 1: fill pl.ell (pre-set to -1)
-hipError_t launch_pair_lists(const PairArgs &a, PairLists &pl, const double *xs, int mode, hipStream_t s);
+// mode 0: per-target near / far counts; mode 1: fill pl.ell (pre-set to -1).
+// With `flag` (mode 0), *flag is set when nodes of distinct bodies (body[] per
+// original node index) are closer than sqrt(thresh2) (which must not exceed r_c).
+hipError_t launch_pair_lists(const PairArgs &a, PairLists &pl, const double *xs, int mode, hipStream_t s,
+                             const int *body = nullptr, double thresh2 = 0.0, int *flag = nullptr);
 // gnn, gnf and gsize[g] = 64 (gnn + gnf) from the counts
 hipError_t launch_group_rows(PairLists &pl, int *gsize, hipStream_t s);
 // src: packed (x, y, mu_x, mu_y) records in cell order (launch_cell_local + launch_gather_src)

@@ -33,6 +33,16 @@ template <typename T> constexpr int kElems = sizeof(T) == 8 ? 4096 : 8192;
 // elements of a row-kernel work group: whole rows, at most the grid
 template <typename T, int M> constexpr int kRowElems = kElems<T> < M * M ? kElems<T> : M * M;
 template <typename T> constexpr int kPadShift = sizeof(T) == 8 ? 4 : 5;
+
+// blockIdx -> work item such that consecutive items run on the same XCD (work
+// groups are dealt round-robin over the 8 XCDs): the row kernels of neighbouring
+// row groups then share the L2 lines of the kx-major spectrum (each group reads or
+// writes part of a line)
+__device__ inline int xcd_remap(int b, int n) {
+  const int q = n / 8, r = n % 8;
+  const int xcd = b % 8, idx = b / 8;
+  return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
 template <typename T> __device__ __forceinline__ int pad(int i) { return i + (i >> kPadShift<T>); }
 
 template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
@@ -192,7 +202,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_fwd(const T *__restrict__ gri
   __shared__ V buf[E + (E >> kPadShift<T>)];
   __shared__ TwLds<V> twl;
   const int tid = threadIdx.x;
-  const int y0 = blockIdx.x * B;
+  const int y0 = xcd_remap(blockIdx.x, gridDim.x) * B;
   const size_t plane = (size_t)M * M;
   constexpr int NL = E / kThreads;  // every load of the thread in flight before the first store
   static_assert(E % kThreads == 0, "whole rows per work group");
@@ -312,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(const typename Cx<T>::typ
   __shared__ V buf[E + (E >> kPadShift<T>)];
   __shared__ TwLds<V> twl;
   const int tid = threadIdx.x;
-  const int y0 = blockIdx.x * B;
+  const int y0 = xcd_remap(blockIdx.x, gridDim.x) * B;
   constexpr int NI = (M / 2 + 1) * B, NL = (NI + kThreads - 1) / kThreads;
   V a[NL], b[NL];
 #pragma unroll

@@ -58,7 +58,9 @@ __global__ __launch_bounds__(64) void k_pair_lists(const int *__restrict__ cell_
                                                    double cell, double rc2, double r2near,
                                                    const double2 *__restrict__ xs, int *__restrict__ cnt_near,
                                                    int *__restrict__ cnt_far, const int *__restrict__ goff,
-                                                   const int *__restrict__ gnn, int *__restrict__ ell, int mode) {
+                                                   const int *__restrict__ gnn, int *__restrict__ ell, int mode,
+                                                   const int *__restrict__ perm, const int *__restrict__ body,
+                                                   double thresh2, int *__restrict__ flag) {
   __shared__ double sx[kPairChunk], sy[kPairChunk];
   __shared__ int sid[kPairChunk];
   __shared__ double tx[64], ty[64];
@@ -118,6 +120,8 @@ __global__ __launch_bounds__(64) void k_pair_lists(const int *__restrict__ cell_
           code = sid[s];
           ok = (r2 <= rc2) && ((code & kIndexMask) != gt);
           near = r2 <= r2near;
+          // overlap check (rare branch): nodes of distinct bodies closer than the threshold
+          if (flag && ok && r2 < thresh2 && body[perm[gt]] != body[perm[code & kIndexMask]]) atomicOr(flag, 1);
         }
         const unsigned long long mn = __ballot(ok && near), mf = __ballot(ok && !near);
         if (mode) {
@@ -311,12 +315,14 @@ hipError_t pair_ell_launch(const PairLists &pl, const PairArgs &a, const T *src,
 
 }  // namespace
 
-hipError_t launch_pair_lists(const PairArgs &a, PairLists &pl, const double *xs, int mode, hipStream_t s) {
+hipError_t launch_pair_lists(const PairArgs &a, PairLists &pl, const double *xs, int mode, hipStream_t s,
+                             const int *body, double thresh2, int *flag) {
   const int ncell = a.nb * a.nb;
   const int nwg = ncell * a.nbatch;
   if (nwg == 0 || pl.N == 0) return hipSuccess;
   hipLaunchKernelGGL(k_pair_lists, dim3(nwg), dim3(64), 0, s, a.cell_start, a.nb, a.nbatch, a.cell, a.rc2,
-                     2.0 / a.xi2, (const double2 *)xs, pl.cnt_near, pl.cnt_far, pl.goff, pl.gnn, pl.ell, mode);
+                     2.0 / a.xi2, (const double2 *)xs, pl.cnt_near, pl.cnt_far, pl.goff, pl.gnn, pl.ell, mode,
+                     a.perm, body, thresh2, mode == 0 ? flag : nullptr);
   return hipGetLastError();
 }
 

@@ -146,3 +146,21 @@ def test_em_rfd_step_matches_oracle(name):
     ctx.mobility(dev(wl.F), U)
     Uo, _ = OF.DenseFBIM(geo, prm, order=wl.alpert_order).mobility(wl.F)
     assert relerr(host(U), Uo) < 1e-6
+
+
+@pytest.mark.parametrize("shift", [3e-7, 1e-4])
+def test_overlap_detection(shift):
+    """Two copies of one body a tiny shift apart: their nodes are closer than 5% of
+    the node spacing, which set_bodies refuses (EOVERLAP); the same copies one
+    body diameter apart are accepted.  (The check rides on the count pass of the
+    neighbour lists.)"""
+    import paper_1709_01480_amd as fb
+    wl = workload("starfish4")
+    ctx = fb.Context(**wl.params())
+    sid = ctx.add_shape(fb.starfish(wl.r_s, wl.b, wl.n_arm, wl.n_p))
+    q = np.array([[0.3, 0.3], [0.3 + shift, 0.3]])
+    with pytest.raises(fb.FbimError) as e:
+        ctx.set_bodies(np.full(2, sid), q, np.zeros(2))
+    assert e.value.status == 3
+    q[1] = [0.3 + 3.0 * wl.r_s, 0.3]
+    ctx.set_bodies(np.full(2, sid), q, np.zeros(2))
