@@ -645,19 +645,13 @@ fbim_status orthogonalise_b(BatchEngine *E, Tables &T, int k, std::vector<std::v
   EST(orth_pass_b(E, T, 0, k, T.by, nullptr, nullptr, q.h, hs));
   if (fused) {
     EST(orth_pass_b(E, T, 1, k, T.by, q.h, nullptr, q.h2, hs));
-    if (selective)
-      EHIP(E, launch_need_second_pass(S, q.h2 + k, hs, q.h + k, hs, q.flag, E->stream));
-    else
-      EHIP(E, launch_fill((size_t)S, 1.0, q.flag, E->stream));
-    EST(orth_pass_b(E, T, 2, k, T.by, q.h2, q.flag, q.nrm + 2, 4));
+    if (selective) EHIP(E, launch_need_second_pass(S, q.h2 + k, hs, q.h + k, hs, q.flag, E->stream));
+    EST(orth_pass_b(E, T, 2, k, T.by, q.h2, selective ? q.flag : nullptr, q.nrm + 2, 4));
   } else {
     EST(orth_pass_b(E, T, 2, k, T.by, q.h, nullptr, q.nrm, 4));
-    if (selective)
-      EHIP(E, launch_need_second_pass(S, q.nrm, 4, q.h + k, hs, q.flag, E->stream));
-    else
-      EHIP(E, launch_fill((size_t)S, 1.0, q.flag, E->stream));
-    EST(orth_pass_b(E, T, 0, k, T.by, nullptr, q.flag, q.h2, hs));
-    EST(orth_pass_b(E, T, 2, k, T.by, q.h2, q.flag, q.nrm + 2, 4));
+    if (selective) EHIP(E, launch_need_second_pass(S, q.nrm, 4, q.h + k, hs, q.flag, E->stream));
+    EST(orth_pass_b(E, T, 0, k, T.by, nullptr, selective ? q.flag : nullptr, q.h2, hs));
+    EST(orth_pass_b(E, T, 2, k, T.by, q.h2, selective ? q.flag : nullptr, q.nrm + 2, 4));
   }
   const size_t cnt = (size_t)S * (2 * hs + 5);  // h, h2, nrm, flag are contiguous
   std::vector<double> buf(cnt);
@@ -669,7 +663,7 @@ fbim_status orthogonalise_b(BatchEngine *E, Tables &T, int k, std::vector<std::v
   for (int i = 0; i < S; ++i) {
     for (int j = 0; j < k; ++j) h[i][j] = H[(size_t)i * hs + j];
     double after;
-    if (FL[i] != 0.0) {
+    if (!selective || FL[i] != 0.0) {  // the second pass ran
       for (int j = 0; j < k; ++j) h[i][j] += H2[(size_t)i * hs + j];
       after = NR[(size_t)i * 4 + 2];
     } else {

@@ -94,7 +94,7 @@ struct fbim_ctx {
   bool have_bodies = false;
 
   // cell list
-  int ncell = 0, max_cell = 0, nbatch = 0;
+  int ncell = 0, max_cell = 0;
   int *d_ckey = nullptr, *d_ccount = nullptr, *d_cstart = nullptr, *d_cperm = nullptr, *d_ccursor = nullptr;
   double *d_xs = nullptr;
   // tiles
@@ -171,8 +171,8 @@ struct fbim_ctx {
     PairArgs a;
     a.cell_start = d_cstart;
     a.perm = d_cperm;
+    a.ckey = d_ckey;
     a.nb = d.n_box;
-    a.nbatch = nbatch;
     a.cell = d.L / d.n_box;
     a.rc2 = d.r_c * d.r_c;
     a.xi2 = d.xi * d.xi;

@@ -334,7 +334,6 @@ fbim_status build_geometry(fbim_ctx *c) {
   HIPCHK(c, hipMemcpyAsync(hv, c->d_scal_int, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   c->max_cell = hv[0];
-  c->nbatch = std::max(1, (hv[0] + 63) / 64);
   c->max_tile = hv[2];
   const char *overlap_msg = "nodes of distinct bodies closer than 5% of the node spacing";
   if (hv[1]) return fail(c, FBIM_EOVERLAP, overlap_msg);
@@ -347,8 +346,9 @@ fbim_status build_geometry(fbim_ctx *c) {
   HIPCHK(c, launch_scan(c->ngroups, c->d_gsize, c->d_goff, c->d_scal_int + 3, s));
   HIPCHK(c, launch_spread_lists(c->wave(), c->d_scount, nullptr, nullptr, 0, s));
   HIPCHK(c, launch_scan(c->ntile, c->d_scount, c->d_sstart, c->d_scal_int + 4, s));
-  int total[2] = {0, 0}, olap = 0;
+  int total[2] = {0, 0}, olap = 0, maxslots = 0;
   HIPCHK(c, hipMemcpyAsync(&total[0], c->d_goff + c->ngroups, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(&maxslots, c->d_scal_int + 3, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipMemcpyAsync(&total[1], c->d_sstart + c->ntile, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipMemcpyAsync(&olap, c->d_scal_int + 1, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
@@ -359,8 +359,9 @@ fbim_status build_geometry(fbim_ctx *c) {
     c->ell_cap = cap;
     pl.ell = c->d_ell;
   }
-  HIPCHK(c, launch_fill_int((size_t)total[0], -1, c->d_ell, s));
-  HIPCHK(c, launch_pair_lists(pa, pl, c->d_xs, 1, s));
+  const int stage = pair_lists_stage_rows(maxslots / 64);
+  if (!stage) HIPCHK(c, launch_fill_int((size_t)total[0], -1, c->d_ell, s));
+  HIPCHK(c, launch_pair_lists(pa, pl, c->d_xs, 1, s, nullptr, 0.0, nullptr, stage));
   if ((size_t)total[1] > c->slist_cap) {
     const size_t cap = (size_t)total[1] + total[1] / 4 + 64;
     HIPCHK(c, dalloc(c->d_slist, cap));
@@ -538,19 +539,13 @@ fbim_status orthogonalise(fbim_ctx *c, const double *V, int k, double *w, size_t
   STCHK(orth_pass(c, 0, n, V, k, w, nullptr, nullptr, c->d_h));  // h, h[k] = ||w||^2
   if (fused) {
     STCHK(orth_pass(c, 1, n, V, k, w, c->d_h, nullptr, c->d_h2));  // w1 = w - V h; h2 = V^T w1, h2[k] = ||w1||^2
-    if (selective)
-      HIPCHK(c, launch_need_second_pass(1, c->d_h2 + k, 0, c->d_h + k, 0, flag, s));
-    else
-      HIPCHK(c, launch_fill(1, 1.0, flag, s));
-    STCHK(orth_pass(c, 2, n, V, k, w, c->d_h2, flag, nrm2));  // w2 = w1 - V h2
+    if (selective) HIPCHK(c, launch_need_second_pass(1, c->d_h2 + k, 0, c->d_h + k, 0, flag, s));
+    STCHK(orth_pass(c, 2, n, V, k, w, c->d_h2, selective ? flag : nullptr, nrm2));  // w2 = w1 - V h2
   } else {
     STCHK(orth_pass(c, 2, n, V, k, w, c->d_h, nullptr, c->d_nrm));  // w1, ||w1||^2
-    if (selective)
-      HIPCHK(c, launch_need_second_pass(1, c->d_nrm, 0, c->d_h + k, 0, flag, s));
-    else
-      HIPCHK(c, launch_fill(1, 1.0, flag, s));
-    STCHK(orth_pass(c, 0, n, V, k, w, nullptr, flag, c->d_h2));
-    STCHK(orth_pass(c, 2, n, V, k, w, c->d_h2, flag, nrm2));
+    if (selective) HIPCHK(c, launch_need_second_pass(1, c->d_nrm, 0, c->d_h + k, 0, flag, s));
+    STCHK(orth_pass(c, 0, n, V, k, w, nullptr, selective ? flag : nullptr, c->d_h2));
+    STCHK(orth_pass(c, 2, n, V, k, w, c->d_h2, selective ? flag : nullptr, nrm2));
   }
   std::vector<double> h2(k + 1), nr(3);
   HIPCHK(c, hipMemcpyAsync(h, c->d_h, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -558,7 +553,7 @@ fbim_status orthogonalise(fbim_ctx *c, const double *V, int k, double *w, size_t
   HIPCHK(c, hipMemcpyAsync(nr.data(), c->d_nrm, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   double after;
-  if (nr[1] != 0.0) {
+  if (!selective || nr[1] != 0.0) {  // the second pass ran
     for (int i = 0; i < k; ++i) h[i] += h2[i];
     after = nr[2];
   } else {

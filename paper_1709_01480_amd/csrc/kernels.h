@@ -49,7 +49,8 @@ hipError_t launch_overlap(int N, const int *cell_start, const int *perm, const d
 struct PairArgs {
   const int *cell_start;
   const int *perm;
-  int nb, nbatch;
+  const int *ckey;      // cell of each original node
+  int nb;
   double cell, rc2, xi2, cG;  // cell side L / n_box
   const double *e1tab;  // FP64 table
   const float *e1tab32; // FP32 table
@@ -61,11 +62,16 @@ struct PairLists {
   int *gnn, *gnf, *goff;    // [ngroups], goff [ngroups + 1]
   int *ell;                 // [goff[ngroups]]
 };
-// mode 0: per-target near / far counts; mode 1: fill pl.ell (pre-set to -1).
-// With `flag` (mode 0), *flag is set when nodes of distinct bodies (body[] per
-// original node index) are closer than sqrt(thresh2) (which must not exceed r_c).
+// mode 0: per-target near / far counts; mode 1: fill pl.ell.  With `flag`
+// (mode 0), *flag is set when nodes of distinct bodies (body[] per original node
+// index) are closer than sqrt(thresh2) (which must not exceed r_c).  Mode 1 with
+// maxrows (the longest group, from pair_lists_stage_rows) > 0 writes every slot
+// (empty ones -1) through LDS; with maxrows = 0 pl.ell must be pre-set to -1.
+constexpr size_t kListStageBytes = 64 * 1024;
+int pair_lists_stage_rows(int maxrows);  // maxrows if its staging fits kListStageBytes, else 0
 hipError_t launch_pair_lists(const PairArgs &a, PairLists &pl, const double *xs, int mode, hipStream_t s,
-                             const int *body = nullptr, double thresh2 = 0.0, int *flag = nullptr);
+                             const int *body = nullptr, double thresh2 = 0.0, int *flag = nullptr,
+                             int maxrows = 0);
 // gnn, gnf and gsize[g] = 64 (gnn + gnf) from the counts
 hipError_t launch_group_rows(PairLists &pl, int *gsize, hipStream_t s);
 // src: packed (x, y, mu_x, mu_y) records in cell order (launch_cell_local + launch_gather_src)

@@ -33,16 +33,40 @@ hipError_t launch_nodes(const GeomDev &g, double L, double *x, hipStream_t s) {
   return hipGetLastError();
 }
 
+// counter[k] += 1 for every active lane of the wave, with one atomic per distinct
+// key k among the wave's lanes (nodes of one body share few bins); returns what a
+// per-lane atomicAdd(&counter[k], 1) would, the lanes of one key taking
+// consecutive values in lane order.  Every lane of the wave must call it.
+__device__ inline int wave_atomic_inc(int *counter, int k, bool active) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long todo = __ballot(active);
+  int result = 0;
+  while (todo) {
+    const int leader = __builtin_ctzll(todo);
+    const int kl = __shfl(k, leader);
+    const unsigned long long peers = __ballot(active && k == kl) & todo;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counter[kl], (int)__popcll(peers));
+    base = __shfl(base, leader);
+    if ((peers >> lane) & 1ull) result = base + (int)__popcll(peers & ((1ull << lane) - 1ull));
+    todo &= ~peers;
+  }
+  return result;
+}
+
 __global__ void k_cell_keys(int N, const double *__restrict__ x, double inv_cell, int nb, int *__restrict__ key,
                             int *__restrict__ count) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  int cx = (int)floor(x[2 * i] * inv_cell), cy = (int)floor(x[2 * i + 1] * inv_cell);
-  cx = min(max(cx, 0), nb - 1);
-  cy = min(max(cy, 0), nb - 1);
-  const int c = cy * nb + cx;
-  key[i] = c;
-  atomicAdd(&count[c], 1);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool on = i < N;
+  int c = 0;
+  if (on) {
+    int cx = (int)floor(x[2 * i] * inv_cell), cy = (int)floor(x[2 * i + 1] * inv_cell);
+    cx = min(max(cx, 0), nb - 1);
+    cy = min(max(cy, 0), nb - 1);
+    c = cy * nb + cx;
+    key[i] = c;
+  }
+  wave_atomic_inc(count, c, on);
 }
 
 hipError_t launch_cell_keys(int N, const double *x, double L, int nb, int *key, int *count, hipStream_t s) {
@@ -54,15 +78,18 @@ hipError_t launch_cell_keys(int N, const double *x, double L, int nb, int *key, 
 // tile of the grid point nearest to the node (the centre of its spreading stencil)
 __global__ void k_tile_keys(int N, const double *__restrict__ x, double inv_h, int M, int T,
                             int *__restrict__ key, int *__restrict__ count) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  int ix = (int)floor(x[2 * i] * inv_h + 0.5), iy = (int)floor(x[2 * i + 1] * inv_h + 0.5);
-  ix = ((ix % M) + M) % M;
-  iy = ((iy % M) + M) % M;
-  const int nts = M / T;
-  const int c = (iy / T) * nts + ix / T;
-  key[i] = c;
-  atomicAdd(&count[c], 1);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool on = i < N;
+  int c = 0;
+  if (on) {
+    int ix = (int)floor(x[2 * i] * inv_h + 0.5), iy = (int)floor(x[2 * i + 1] * inv_h + 0.5);
+    ix = ((ix % M) + M) % M;
+    iy = ((iy % M) + M) % M;
+    const int nts = M / T;
+    c = (iy / T) * nts + ix / T;
+    key[i] = c;
+  }
+  wave_atomic_inc(count, c, on);
 }
 
 hipError_t launch_tile_keys(int N, const double *x, double h, int M, int T, int *key, int *count, hipStream_t s) {
@@ -115,10 +142,11 @@ hipError_t launch_scan(int n, const int *count, int *start, int *maxcount, hipSt
 
 __global__ void k_scatter(int N, const int *__restrict__ key, const int *__restrict__ start, int *__restrict__ cursor,
                           int *__restrict__ perm) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const int c = key[i];
-  perm[start[c] + atomicAdd(&cursor[c], 1)] = i;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool on = i < N;
+  const int c = on ? key[i] : 0;
+  const int slot = wave_atomic_inc(cursor, c, on);
+  if (on) perm[start[c] + slot] = i;
 }
 
 hipError_t launch_scatter(int N, const int *key, const int *start, int *cursor, int *perm, hipStream_t s) {

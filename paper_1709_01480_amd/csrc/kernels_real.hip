@@ -12,7 +12,6 @@ template <typename T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
 
-constexpr int kPairChunk = 128;   // sources staged in LDS per pass
 constexpr int kE1Int = 9;         // intervals of the E1 table
 
 // blockIdx -> work item such that consecutive items land on the same XCD
@@ -53,97 +52,77 @@ __device__ inline T poly(const T *row, T z) {
 constexpr int kCodeShift = 27;
 constexpr int kIndexMask = (1 << kCodeShift) - 1;
 
-// mode 0: count near / far pairs per target; mode 1: write the ELL entries
-__global__ __launch_bounds__(64) void k_pair_lists(const int *__restrict__ cell_start, int nb, int nbatch,
-                                                   double cell, double rc2, double r2near,
-                                                   const double2 *__restrict__ xs, int *__restrict__ cnt_near,
-                                                   int *__restrict__ cnt_far, const int *__restrict__ goff,
-                                                   const int *__restrict__ gnn, int *__restrict__ ell, int mode,
-                                                   const int *__restrict__ perm, const int *__restrict__ body,
-                                                   double thresh2, int *__restrict__ flag) {
-  __shared__ double sx[kPairChunk], sy[kPairChunk];
-  __shared__ int sid[kPairChunk];
-  __shared__ double tx[64], ty[64];
-  __shared__ int ncnt[64], fcnt[64];
-  const int lane = threadIdx.x;
-  const int w = xcd_remap(blockIdx.x, gridDim.x);
-  const int c = w / nbatch, bt = w % nbatch;
-  const int cs = cell_start[c], ce = cell_start[c + 1];
-  const int t0 = cs + bt * 64;
-  if (t0 >= ce) return;
-  const int nt = min(64, ce - t0);
-  if (lane < nt) {
-    const double2 p = xs[t0 + lane];
-    tx[lane] = p.x;
-    ty[lane] = p.y;
+// One thread per cell-sorted target: it scans the nodes of the 3 x 3 neighbouring
+// cells (cell by cell, node order -- the order of its list rows), counts its near
+// and far pairs (mode 0) or writes them into its ELL slots (mode 1).  With `flag`
+// (mode 0) it also flags nodes of distinct bodies closer than sqrt(thresh2).
+// Mode 1 with maxrows > 0 stages each group's rows in LDS (a lane writes only its
+// own column, empty slots -1) and stores them as whole contiguous rows; with
+// maxrows = 0 it writes the slots directly (ell pre-set to -1).
+constexpr int kListBlock = 128;  // two groups of 64 targets
+
+__global__ __launch_bounds__(kListBlock) void k_pair_lists(int N, int ngroups, const int *__restrict__ cell_start,
+                                                           const int *__restrict__ ckey,
+                                                           const int *__restrict__ perm, int nb, double cell,
+                                                           double rc2, double r2near, const double2 *__restrict__ xs,
+                                                           int *__restrict__ cnt_near, int *__restrict__ cnt_far,
+                                                           const int *__restrict__ goff, const int *__restrict__ gnn,
+                                                           const int *__restrict__ gnf, int *__restrict__ ell,
+                                                           int mode, int maxrows, const int *__restrict__ body,
+                                                           double thresh2, int *__restrict__ flag) {
+  extern __shared__ int stile[];  // mode 1 staged: [kListBlock / 64][maxrows][64]
+  const int gt = xcd_remap(blockIdx.x, gridDim.x) * kListBlock + threadIdx.x;
+  const int grp = gt >> 6, gl = gt & 63;
+  const bool staged = mode && maxrows > 0;
+  int nn = 0, rows = 0;
+  if (mode && grp < ngroups) {
+    nn = gnn[grp];
+    rows = nn + gnf[grp];
   }
-  ncnt[lane] = fcnt[lane] = 0;
-  const int ccx = c % nb, ccy = c / nb;
-  int nstart[9], pre[10];
-  pre[0] = 0;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    const int dx = k % 3 - 1, dy = k / 3 - 1;
-    const int cc = ((ccy + dy + nb) % nb) * nb + (ccx + dx + nb) % nb;
-    nstart[k] = cell_start[cc];
-    pre[k + 1] = pre[k] + cell_start[cc + 1] - cell_start[cc];
-  }
-  const int ns = pre[9];
-  __syncthreads();
-  for (int v0 = 0; v0 < ns; v0 += kPairChunk) {
-    const int len = min(kPairChunk, ns - v0);
-    for (int i = lane; i < len; i += 64) {
-      const int v = v0 + i;
-      int k = 0;
-      while (k < 8 && v >= pre[k + 1]) ++k;
-      const int g = nstart[k] + (v - pre[k]);
-      const double2 p = xs[g];
-      sx[i] = p.x + (k % 3 - 1) * cell;
-      sy[i] = p.y + (k / 3 - 1) * cell;
-      // entry code: dcx+1 = k%3 and dcy+1 = k/3 above the index
-      sid[i] = g | ((k % 3) << kCodeShift) | ((k / 3) << (kCodeShift + 2));
-    }
-    __syncthreads();
-    for (int t = 0; t < nt; ++t) {
-      const double px = tx[t], py = ty[t];
-      const int gt = t0 + t;
-      int cn = ncnt[t], cf = fcnt[t];
-      const int grp = gt >> 6, gl = gt & 63;
-      const int base = mode ? goff[grp] : 0, nn = mode ? gnn[grp] : 0;
-      for (int s0 = 0; s0 < len; s0 += 64) {
-        const int s = s0 + lane;
-        bool ok = false, near = false;
-        int code = 0;
-        if (s < len) {
-          const double dx = px - sx[s], dy = py - sy[s];
-          const double r2 = dx * dx + dy * dy;
-          code = sid[s];
-          ok = (r2 <= rc2) && ((code & kIndexMask) != gt);
-          near = r2 <= r2near;
-          // overlap check (rare branch): nodes of distinct bodies closer than the threshold
-          if (flag && ok && r2 < thresh2 && body[perm[gt]] != body[perm[code & kIndexMask]]) atomicOr(flag, 1);
-        }
-        const unsigned long long mn = __ballot(ok && near), mf = __ballot(ok && !near);
-        if (mode) {
-          const unsigned long long below = (1ull << lane) - 1ull;
-          if (ok && near) ell[base + (size_t)(cn + __popcll(mn & below)) * 64 + gl] = code;
-          if (ok && !near) ell[base + (size_t)(nn + cf + __popcll(mf & below)) * 64 + gl] = code;
-        }
-        cn += __popcll(mn);
-        cf += __popcll(mf);
+  int *col = stile + (threadIdx.x >> 6) * maxrows * 64 + gl;
+  if (staged)
+    for (int r = 0; r < rows; ++r) col[r * 64] = -1;
+  if (gt < N) {
+    const int c = ckey[perm[gt]];
+    const int ccx = c % nb, ccy = c / nb;
+    const double2 p = xs[gt];
+    const int base = (mode && !staged) ? goff[grp] : 0;
+    int cn = 0, cf = 0;
+    for (int k = 0; k < 9; ++k) {
+      const int dx = k % 3 - 1, dy = k / 3 - 1;
+      const int cc = ((ccy + dy + nb) % nb) * nb + (ccx + dx + nb) % nb;
+      const double ox = p.x - dx * cell, oy = p.y - dy * cell;  // target relative to cell cc's corner frame
+      const int code = ((k % 3) << kCodeShift) | ((k / 3) << (kCodeShift + 2));
+      const int g1 = cell_start[cc + 1];
+#pragma unroll 4
+      for (int g = cell_start[cc]; g < g1; ++g) {
+        const double2 q = xs[g];
+        const double ex = ox - q.x, ey = oy - q.y;
+        const double r2 = ex * ex + ey * ey;
+        if (r2 > rc2 || g == gt) continue;
+        if (flag && r2 < thresh2 && body[perm[gt]] != body[perm[g]]) atomicOr(flag, 1);
+        const bool near = r2 <= r2near;
+        const int row = near ? cn : nn + cf;
+        if (staged)
+          col[row * 64] = g | code;
+        else if (mode)
+          ell[base + (size_t)row * 64 + gl] = g | code;
+        cn += near;
+        cf += !near;
       }
-      __syncthreads();
-      if (lane == 0) {
-        ncnt[t] = cn;
-        fcnt[t] = cf;
-      }
-      __syncthreads();
     }
-    __syncthreads();
+    if (mode == 0) {
+      cnt_near[gt] = cn;
+      cnt_far[gt] = cf;
+    }
   }
-  if (mode == 0 && lane < nt) {
-    cnt_near[t0 + lane] = ncnt[lane];
-    cnt_far[t0 + lane] = fcnt[lane];
+  if (staged) {
+    __syncthreads();
+    if (grp < ngroups) {  // the group's rows, contiguous
+      const int *tile = stile + (threadIdx.x >> 6) * maxrows * 64;
+      int *dst = ell + goff[grp];
+      for (int i = gl; i < rows * 64; i += 64) dst[i] = tile[i];
+    }
   }
 }
 
@@ -315,14 +294,18 @@ hipError_t pair_ell_launch(const PairLists &pl, const PairArgs &a, const T *src,
 
 }  // namespace
 
+int pair_lists_stage_rows(int maxrows) {
+  return (size_t)(kListBlock / 64) * maxrows * 64 * sizeof(int) <= kListStageBytes ? maxrows : 0;
+}
+
 hipError_t launch_pair_lists(const PairArgs &a, PairLists &pl, const double *xs, int mode, hipStream_t s,
-                             const int *body, double thresh2, int *flag) {
-  const int ncell = a.nb * a.nb;
-  const int nwg = ncell * a.nbatch;
-  if (nwg == 0 || pl.N == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pair_lists, dim3(nwg), dim3(64), 0, s, a.cell_start, a.nb, a.nbatch, a.cell, a.rc2,
-                     2.0 / a.xi2, (const double2 *)xs, pl.cnt_near, pl.cnt_far, pl.goff, pl.gnn, pl.ell, mode,
-                     a.perm, body, thresh2, mode == 0 ? flag : nullptr);
+                             const int *body, double thresh2, int *flag, int maxrows) {
+  if (pl.N == 0) return hipSuccess;
+  const size_t lds = (mode && maxrows > 0) ? (size_t)(kListBlock / 64) * maxrows * 64 * sizeof(int) : 0;
+  hipLaunchKernelGGL(k_pair_lists, dim3((pl.N + kListBlock - 1) / kListBlock), dim3(kListBlock), lds, s, pl.N,
+                     pl.ngroups, a.cell_start, a.ckey, a.perm, a.nb, a.cell, a.rc2, 2.0 / a.xi2, (const double2 *)xs,
+                     pl.cnt_near, pl.cnt_far, pl.goff, pl.gnn, pl.gnf, pl.ell, mode, mode ? maxrows : 0, body,
+                     thresh2, mode == 0 ? flag : nullptr);
   return hipGetLastError();
 }
 
