@@ -181,13 +181,13 @@ def kernel_traffic(kernel):
     the kernel source is unchanged since the counters were taken (else None)."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", COUNTER_FILE.get(kernel, "none"))
-    if not os.path.exists(path):
+    path = os.path.join(ROOT, "profiles", COUNTER_FILE)
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCE:
         return None
     txt = open(path).read()
     m = re.search(r"traffic_bytes_per_launch\[%s\]:\s*([0-9.eE+]+)" % re.escape(kernel), txt)
-    h = re.search(r"source_sha256:\s*([0-9a-f]+)", txt)
-    src = os.path.join(ROOT, "paper_1709_01480_amd", "csrc", KERNEL_SOURCE.get(kernel, ""))
+    h = re.search(r"source_sha256\[%s\]:\s*([0-9a-f]+)" % re.escape(KERNEL_SOURCE[kernel]), txt)
+    src = os.path.join(ROOT, "paper_1709_01480_amd", "csrc", KERNEL_SOURCE[kernel])
     if not (m and h and os.path.exists(src)):
         return None
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
@@ -195,7 +195,7 @@ def kernel_traffic(kernel):
     return float(m.group(1))
 
 
-COUNTER_FILE = {"pair": "k_pair_ell_starfish10k_counters.md", "pair32": "k_pair_ell_starfish10k_counters.md"}
+COUNTER_FILE = "matvec_kernels_starfish10k_counters.md"
 KERNEL_CLASSES = ("pair", "pair32", "alpert", "spread", "spread32", "interp", "interp32", "fft", "fft32",
                   "multiplier", "multiplier32", "precond", "blas", "mlp")
 # classes timed as exactly one kernel (candidates for the roofline line) and their sources

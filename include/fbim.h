@@ -67,7 +67,7 @@ enum {
   FBIM_FLAG_GRAPH = 4u,
   /* mixed contexts: iterative refinement (FP64 residuals, FP32 GMRES corrections to
      1e-3) instead of the default relaxed-matvec GMRES (FP64 operator until the residual
-     estimate falls below 1e-2 ||b||, then the FP32 operator; FP64 restart residuals) */
+     estimate falls below 1e-1 ||b||, then the FP32 operator; FP64 restart residuals) */
   FBIM_FLAG_REFINEMENT = 8u,
   /* wave-space transforms through rocFFT plans (real-to-complex, multiplier kernel,
      complex-to-real) even where the fused transform kernels apply; those serve

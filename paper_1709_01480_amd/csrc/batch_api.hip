@@ -824,7 +824,7 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
   return FBIM_OK;
 }
 
-constexpr double kRelaxB = 1e-2;  // relaxed-matvec threshold (as for one system)
+constexpr double kRelaxB = 1e-1;  // relaxed-matvec threshold (as for one system)
 
 // Solve the saddle systems `sysl` with RHS d_b into d_x2.  FP64 engines: lockstep
 // GMRES.  Mixed engines: relaxed-matvec lockstep GMRES, or with

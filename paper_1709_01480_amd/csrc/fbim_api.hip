@@ -572,7 +572,7 @@ fbim_status norm2(fbim_ctx *c, const double *x, size_t n, double &out) {
   return FBIM_OK;
 }
 
-constexpr double kRelax = 1e-2;  // relaxed-matvec threshold of mixed contexts
+constexpr double kRelax = 1e-1;  // relaxed-matvec threshold of mixed contexts
 
 // right-preconditioned restarted GMRES for the saddle system; b, x device (ntot)
 // warm: start from the x given (else x0 = 0)
