@@ -90,7 +90,7 @@ FORMS = {
     "fp64": dict(precision="fp64", batch_rfd=False, learned=False),
     # mixed precision only (FP32 matvecs in FP64 Krylov), solves one after another
     "mixed": dict(precision="mixed", batch_rfd=False, learned=False),
-    # FP32 matvec inside FP64 Krylov (iterative refinement), the three EM-RFD solves in one
+    # relaxed-matvec GMRES (FP32 operator once the residual is small), the three EM-RFD solves in one
     # batched launch set, learned preconditioner correction trained beforehand on solves
     "mixed+batched+learned": dict(precision="mixed", batch_rfd=True, graph=True, learned=True),
 }

@@ -437,20 +437,56 @@ __global__ __launch_bounds__(256) void k_orth_finish(Segs seg, int kk, const dou
   if (threadIdx.x == 0) out[(size_t)sys * ostride + j] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+constexpr int pow2_ceil(int n) { return n <= 1 ? 1 : 2 * pow2_ceil((n + 1) / 2); }
+constexpr int log2_exact(int n) { return n <= 1 ? 0 : 1 + log2_exact(n / 2); }
+
+// Column sums of a 256-thread block: dst[c] = sum over threads of acc[c], c < nv.
+// Few columns: one shuffle reduction per column.  More: a halving exchange across
+// the wave (at offset o the lanes with bit o set keep the upper half of their
+// padded columns, the others the lower half, each adding the partner's copy), so
+// that after log2(P) rounds lane l holds column l >> (6 - log2 P) summed over the
+// lanes that differ in the high bits; the low bits are reduced by plain shuffles.
+// P - 1 + 6 - log2 P shuffles per wave instead of 6 NV; the order is fixed.
 template <int NV>
 __device__ inline void block_sum_store(const double (&acc)[NV], int nv, double *__restrict__ dst) {
-  __shared__ double red[4][NV];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if constexpr (NV <= 4) {
+    __shared__ double red[4][NV];
 #pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    double v = acc[c];
+    for (int c = 0; c < NV; ++c) {
+      double v = acc[c];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
-    if (lane == 0) red[wv][c] = v;
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+      if (lane == 0) red[wv][c] = v;
+    }
+    __syncthreads();
+    for (int c = tid; c < nv; c += 256) dst[c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+    __syncthreads();
+  } else {
+    constexpr int P = pow2_ceil(NV), LP = log2_exact(P);
+    static_assert(P <= 64, "at most 64 columns");
+    __shared__ double red[4][P];
+    double v[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) v[c] = c < NV ? acc[c] : 0.0;
+#pragma unroll
+    for (int r = 0; r < LP; ++r) {
+      const int o = 32 >> r, h = P >> (r + 1);
+      const bool upper = (lane & o) != 0;
+#pragma unroll
+      for (int i = 0; i < h; ++i) {
+        const double send = upper ? v[i] : v[i + h];
+        const double recv = __shfl_xor(send, o);
+        v[i] = (upper ? v[i + h] : v[i]) + recv;
+      }
+    }
+#pragma unroll
+    for (int o = 32 >> LP; o >= 1; o >>= 1) v[0] += __shfl_xor(v[0], o);
+    if ((lane & ((64 >> LP) - 1)) == 0) red[wv][lane >> (6 - LP)] = v[0];
+    __syncthreads();
+    for (int c = tid; c < nv; c += 256) dst[c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+    __syncthreads();
   }
-  __syncthreads();
-  for (int c = tid; c < nv; c += 256) dst[c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
-  __syncthreads();
 }
 
 // Exact column count K (0..kOrthFused), fully unrolled:
