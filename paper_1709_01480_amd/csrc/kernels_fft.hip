@@ -161,11 +161,25 @@ __device__ __forceinline__ void fft_stage(typename Cx<T>::type *buf, int Ns, con
     const int k = j & (Ns - 1);
     if (Ns > 1) {
       const int step = N / (Ns * R);
+      if constexpr (sizeof(T) == 8) {
+        // FP64: one table twiddle per butterfly, its powers by products (at most
+        // R - 1 more roundings, ~1e-15); the per-r table reads of FP64 entries
+        // were the kernels' main LDS bank conflicts
+        V w1 = tw_get<V, N>(tw, k * step);
+        if (INV) w1.y = -w1.y;
+        V w = w1;
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        V w = tw_get<V, N>(tw, k * r * step);
-        if (INV) w.y = -w.y;
-        v[q][r] = cmul(v[q][r], w);
+        for (int r = 1; r < R; ++r) {
+          v[q][r] = cmul(v[q][r], w);
+          if (r + 1 < R) w = cmul(w, w1);
+        }
+      } else {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          V w = tw_get<V, N>(tw, k * r * step);
+          if (INV) w.y = -w.y;
+          v[q][r] = cmul(v[q][r], w);
+        }
       }
     }
     dft<V, R, INV>(v[q]);
