@@ -79,3 +79,22 @@ def test_invalid_parameters_rejected():
         fb.derive_params(L=-1.0, tol_ewald=1e-9, n_box=4)
     with pytest.raises(fb.FbimError):
         fb.alpert_rule(6)
+
+
+def test_uneven_suspension_draws_are_valid_systems():
+    """The uneven-batch workload: sizes in range, node counts from the set, the
+    library's parameter rule accepts every suspension with a power-of-two grid,
+    and the bounding circles of each suspension do not overlap."""
+    wls = W.uneven_suspensions(16)
+    assert len(wls) == 16
+    for w in wls:
+        assert 16 <= w.n_bodies <= 512 and w.n_p in (64, 128, 256)
+        d = fb.derive_params(**w.params())
+        assert d["grid_M"] == w.grid_M and (w.grid_M & (w.grid_M - 1)) == 0
+        dq = w.q[:, None, :] - w.q[None, :, :]
+        dq -= w.L * np.round(dq / w.L)
+        dist = np.sqrt((dq ** 2).sum(-1)) + np.eye(w.n_bodies) * 1e9
+        assert dist.min() > 2 * w.a
+    # the draw is seeded: the same call gives the same systems
+    again = W.uneven_suspensions(16)
+    assert all(np.array_equal(a.q, b.q) and a.n_p == b.n_p for a, b in zip(wls, again))

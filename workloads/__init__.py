@@ -26,7 +26,7 @@ from typing import Optional
 import numpy as np
 
 __all__ = ["Workload", "CONFIGS", "make", "noise", "starfish_area",
-           "disk_lattice", "single_starfish"]
+           "disk_lattice", "single_starfish", "uneven_suspensions"]
 
 
 @dataclasses.dataclass
@@ -184,6 +184,30 @@ def make(name: str, seed: Optional[int] = None, **overrides) -> Workload:
     wl.theta = rng.uniform(0.0, 2 * math.pi, wl.n_bodies)
     wl.F = rng.standard_normal(3 * wl.n_bodies)
     return wl
+
+
+def uneven_suspensions(count: int, seed: int = 0, n_min: int = 16, n_max: int = 512,
+                       n_ps=(64, 128, 256), phi: float = 0.2, tol: float = 1e-6) -> list:
+    """Independent suspensions of uneven size for batches: bodies per suspension
+    log-uniform in [n_min, n_max], nodes per body drawn from n_ps, unit box,
+    area fraction phi, Ewald parameters derived from tol; suspension k uses
+    geometry seed 3000 + 97 seed + k.  The cell count per side gives about 16 nodes
+    per cell (at least 3); the grid is the power of two at or above the one the
+    parameter rule needs for that cutoff (xi L ~ n_box sqrt(ln(C_r / tol)),
+    k_max = pi M / L with exp(-k_max^2 / 4 xi^2) <= tol)."""
+    rng = np.random.default_rng(0xB47C + seed)
+    out = []
+    for k in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        n_p = int(rng.choice(n_ps))
+        n_box = max(3, int(math.sqrt(n * n_p / 16.0)))
+        xi = n_box * math.sqrt(math.log(100.0 / tol))
+        m_need = 2.0 * xi * math.sqrt(math.log(1.0 / tol)) / math.pi
+        grid_M = 1 << max(6, int(math.ceil(math.log2(m_need))))
+        out.append(make("starfish4", seed=3000 + 97 * seed + k, n_bodies=n, n_p=n_p,
+                        r_s=_rs_for_fraction(n, 1.0, 0.3, phi), tol_ewald=tol, xi=0.0, n_box=n_box,
+                        grid_M=grid_M, P=0))
+    return out
 
 
 def noise(wl: Workload, grid_M: int, seed: Optional[int] = None):
