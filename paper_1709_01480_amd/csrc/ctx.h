@@ -135,6 +135,7 @@ struct fbim_ctx {
   double *d_V = nullptr;      // (restart+1) * ntot  (also Lanczos basis)
   double *d_w = nullptr, *d_t1 = nullptr, *d_t2 = nullptr, *d_b = nullptr, *d_x2 = nullptr, *d_r = nullptr;
   double *d_partial = nullptr, *d_h = nullptr, *d_h2 = nullptr, *d_nrm = nullptr, *d_c = nullptr;
+  HostPub pub;  // orthogonalisation coefficients and norms read by the host
   // chunk tables of the Krylov vectors: saddle vectors (2N + 3n) and node vectors (2N)
   Segs seg_sad{}, seg_nod{};
   int2 *d_chunks = nullptr;

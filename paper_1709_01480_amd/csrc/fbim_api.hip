@@ -143,6 +143,7 @@ fbim_status ensure_krylov(fbim_ctx *c) {
   HIPCHK(c, dalloc(c->d_h, cols));
   HIPCHK(c, dalloc(c->d_h2, cols));
   HIPCHK(c, dalloc(c->d_nrm, 4));
+  HIPCHK(c, pub_alloc(c->pub, cols + 1));
   HIPCHK(c, dalloc(c->d_c, cols));
   HIPCHK(c, dalloc(c->d_vec_a, 2 * (size_t)c->N));
   HIPCHK(c, dalloc(c->d_vec_b, 2 * (size_t)c->N));
@@ -528,10 +529,13 @@ fbim_status orth_pass(fbim_ctx *c, int mode, size_t n, const double *V, int k, d
 // the second pass only when the first one cancels more than half of ||w||^2
 // (Daniel-Gragg-Kaufman-Stewart criterion, FBIM_FLAG_SELECTIVE_REORTH).  For
 // k <= kOrthFused the first subtraction and the second projection share one
-// read of V.  The decision is taken on the device, so one host
-// synchronisation per call suffices.  On return h[0..k) holds the projection
-// coefficients (host) and hn = ||w|| after orthogonalisation.
-fbim_status orthogonalise(fbim_ctx *c, const double *V, int k, double *w, size_t n, double *h, double &hn) {
+// read of V.  The decision is taken on the device, which also writes the
+// combined coefficients and ||w|| to host memory, so the host waits once per
+// call and copies nothing.  On return h[0..k) holds the projection
+// coefficients and hn = ||w|| after orthogonalisation; with `normalise`, w has
+// been scaled by 1 / hn (by 0 when hn = 0).
+fbim_status orthogonalise(fbim_ctx *c, const double *V, int k, double *w, size_t n, double *h, double &hn,
+                          bool normalise = false) {
   hipStream_t s = c->stream;
   double *flag = c->d_nrm + 1, *nrm2 = c->d_nrm + 2;
   const bool selective = (c->p.flags & FBIM_FLAG_SELECTIVE_REORTH) != 0;
@@ -547,28 +551,34 @@ fbim_status orthogonalise(fbim_ctx *c, const double *V, int k, double *w, size_t
     STCHK(orth_pass(c, 0, n, V, k, w, nullptr, selective ? flag : nullptr, c->d_h2));
     STCHK(orth_pass(c, 2, n, V, k, w, c->d_h2, selective ? flag : nullptr, nrm2));
   }
-  std::vector<double> h2(k + 1), nr(3);
-  HIPCHK(c, hipMemcpyAsync(h, c->d_h, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipMemcpyAsync(h2.data(), c->d_h2, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipMemcpyAsync(nr.data(), c->d_nrm, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipStreamSynchronize(s));
-  double after;
-  if (!selective || nr[1] != 0.0) {  // the second pass ran
-    for (int i = 0; i < k; ++i) h[i] += h2[i];
-    after = nr[2];
-  } else {
-    after = fused ? h2[k] : nr[0];
+  OrthPublish o;
+  o.k = k;
+  o.fused = fused;
+  o.selective = selective;
+  o.h = c->d_h;
+  o.h2 = c->d_h2;
+  o.nrm_a = c->d_nrm;
+  o.nrm_b = nrm2;
+  o.flag = flag;
+  o.a = c->d_nrm + 3;  // 1 / ||w||
+  const unsigned long long tag = ++c->pub.seq;
+  HIPCHK(c, launch_orth_publish(o, c->pub, tag, s));
+  if (normalise) {
+    Timer t(c, "blas");
+    HIPCHK(c, launch_scale_dev(n, c->d_nrm + 3, w, s));
   }
-  hn = std::sqrt(std::max(after, 0.0));
+  HIPCHK(c, pub_wait(c->pub, tag, s));
+  std::memcpy(h, c->pub.v, k * sizeof(double));
+  hn = c->pub.v[k];
   return FBIM_OK;
 }
 
 fbim_status norm2(fbim_ctx *c, const double *x, size_t n, double &out) {
   STCHK(orth_pass(c, 0, n, x, 0, const_cast<double *>(x), nullptr, nullptr, c->d_nrm));
-  double v;
-  HIPCHK(c, hipMemcpyAsync(&v, c->d_nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  out = std::sqrt(std::max(v, 0.0));
+  const unsigned long long tag = ++c->pub.seq;
+  HIPCHK(c, launch_publish(1, c->d_nrm, 1, c->pub, tag, c->stream));
+  HIPCHK(c, pub_wait(c->pub, tag, c->stream));
+  out = std::sqrt(std::max(c->pub.v[0], 0.0));
   return FBIM_OK;
 }
 
@@ -629,12 +639,8 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
       STCHK(apply_precond(c, vj, c->d_t1));
       STCHK(apply_saddle(c, c->d_t1, w));
       double hn = 0;
-      STCHK(orthogonalise(c, c->d_V, j + 1, w, nt, hcol.data(), hn));
+      STCHK(orthogonalise(c, c->d_V, j + 1, w, nt, hcol.data(), hn, true));
       hcol[j + 1] = hn;
-      if (hn > 0) {
-        Timer t(c, "blas");
-        HIPCHK(c, launch_scale(nt, 1.0 / hn, w, s));
-      }
       for (int i = 0; i < j; ++i) {  // previous rotations
         const double t1 = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
         hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];
@@ -744,7 +750,7 @@ fbim_status lanczos_sqrt(fbim_ctx *c, const double *b, double *out, int &iters, 
     STCHK(apply_M(c, c->d_vec_a, c->d_vec_b, FBIM_PART_REAL | FBIM_PART_ALPERT));
     HIPCHK(c, launch_body_apply(c->geom(), c->mats(), c->bt, 0, c->d_vec_b, w, s));
     double bk = 0;
-    STCHK(orthogonalise(c, c->d_V, k + 1, w, n2, hbuf.data(), bk));
+    STCHK(orthogonalise(c, c->d_V, k + 1, w, n2, hbuf.data(), bk, true));  // w / bk: next basis vector
     alpha.push_back(hbuf[k]);
     // coefficients c = beta0 Q sqrt(max(L, 0)) Q^T e1 of the (k+1) x (k+1) tridiagonal
     const int m = k + 1;
@@ -777,7 +783,6 @@ fbim_status lanczos_sqrt(fbim_ctx *c, const double *b, double *out, int &iters, 
       break;
     }
     beta.push_back(bk);
-    HIPCHK(c, launch_scale(n2, 1.0 / bk, w, s));
   }
   HIPCHK(c, hipMemcpyAsync(c->d_c, cur.data(), cur.size() * sizeof(double), hipMemcpyHostToDevice, s));
   {
@@ -987,6 +992,7 @@ void fbim_destroy(fbim_ctx *c) {
                   c->d_spec32, c->d_e1tab, c->d_e1tab32, c->d_V, c->d_w, c->d_t1, c->d_t2, c->d_b, c->d_x2,
                   c->d_r, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
                   c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU, c->d_bx, c->d_by, c->d_tw, c->d_tw32, c->d_ey, c->d_ey32, c->d_scount, c->d_sstart, c->d_slist};
+  pub_free(c->pub);
   engine_delete(c->rfd_engine);
   for (fbim_ctx *r : c->rfd)
     if (r) fbim_destroy(r);

@@ -248,6 +248,37 @@ hipError_t launch_seg_Vc(const Segs &seg, const VecRef &V, int k, const double *
 // flag[s] = 1 if nrm[s * ns] < before[s * nb] / 2 (the pass lost more than half of ||w||^2)
 hipError_t launch_need_second_pass(int S, const double *nrm, int ns, const double *before, int nb, double *flag,
                                    hipStream_t s);
+// Host-visible results (pinned, fine-grained host memory read by the host
+// without a copy): `v` holds the values, `tag` is written after them, so the
+// host that sees the tag it waits for may read the values.
+struct HostPub {
+  unsigned long long *tag = nullptr, *tag_dev = nullptr;
+  double *v = nullptr, *v_dev = nullptr;
+  size_t cap = 0;
+  unsigned long long seq = 0;
+};
+hipError_t pub_alloc(HostPub &p, size_t n);  // room for n values
+void pub_free(HostPub &p);
+// Blocks the host until the launches that publish `tag` on stream s have written
+// it (a spin on host memory, then a stream synchronisation as the fallback).
+hipError_t pub_wait(const HostPub &p, unsigned long long tag, hipStream_t s);
+// Orthogonalisation results of S systems (CGS2 / selective second pass):
+// second = !selective || flag[s fs] != 0; for j < k
+// v[s (k+1) + j] = h[s hs + j] + (second ? h2[s hs + j] : 0);
+// after = second ? nrm_b[s ns] : (fused ? h2[s hs + k] : nrm_a[s ns]);
+// v[s (k+1) + k] = sqrt(max(after, 0)) = hn_s and a[s as] = hn_s > 0 ? 1 / hn_s : 0
+// (device), the scale that normalises w_s; then the tag.
+struct OrthPublish {
+  int S = 1, k = 0, hs = 0, ns = 0, fs = 0, as = 0;
+  bool fused = true, selective = false;
+  const double *h = nullptr, *h2 = nullptr, *nrm_a = nullptr, *nrm_b = nullptr, *flag = nullptr;
+  double *a = nullptr;
+};
+hipError_t launch_orth_publish(const OrthPublish &o, HostPub &p, unsigned long long tag, hipStream_t s);
+// v[i] = src[i stride] for i < n, then the tag
+hipError_t launch_publish(int n, const double *src, int stride, HostPub &p, unsigned long long tag, hipStream_t s);
+// y *= a[0] with a on the device
+hipError_t launch_scale_dev(size_t n, const double *a, double *y, hipStream_t s);
 // y[i] = sum_j V[j*ld + i] * c[j]
 hipError_t launch_Vc(const double *V, size_t ld, int k, const double *c, double *y, size_t n, hipStream_t s);
 hipError_t launch_axpby(size_t n, double a, const double *x, double b, double *y, hipStream_t s);  // y = a x + b y

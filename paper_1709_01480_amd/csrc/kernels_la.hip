@@ -1,6 +1,8 @@
 // Rigid-body maps K, K^T (Section 3.1), the block-diagonal preconditioner and
 // the per-body G / G^+ applies (Section 3.4), and FP64 Krylov vector kernels.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 
 #include "kernels.h"
 
@@ -756,6 +758,106 @@ hipError_t launch_scale(size_t n, double a, double *y, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int nb = (int)std::min<size_t>((n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_scale, dim3(nb), dim3(256), 0, s, n, a, y);
+  return hipGetLastError();
+}
+
+hipError_t pub_alloc(HostPub &p, size_t n) {
+  if (p.tag && n <= p.cap) return hipSuccess;
+  pub_free(p);
+  void *h = nullptr, *d = nullptr;
+  hipError_t e = hipHostMalloc(&h, (n + 1) * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent);
+  if (e != hipSuccess) return e;
+  e = hipHostGetDevicePointer(&d, h, 0);
+  if (e != hipSuccess) {
+    hipHostFree(h);
+    return e;
+  }
+  p.tag = static_cast<unsigned long long *>(h);
+  p.tag_dev = static_cast<unsigned long long *>(d);
+  p.v = static_cast<double *>(h) + 1;
+  p.v_dev = static_cast<double *>(d) + 1;
+  *p.tag = 0;  // the sequence keeps counting, so no tag it waits for is 0
+  p.cap = n;
+  return hipSuccess;
+}
+
+void pub_free(HostPub &p) {
+  if (p.tag) hipHostFree(p.tag);
+  p.tag = p.tag_dev = nullptr;
+  p.v = p.v_dev = nullptr;
+  p.cap = 0;
+}
+
+hipError_t pub_wait(const HostPub &p, unsigned long long tag, hipStream_t s) {
+  const volatile unsigned long long *t = p.tag;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (unsigned spins = 1; *t != tag; ++spins) {
+    // long queues (or a failed launch) end in the stream synchronisation
+    if ((spins & 1023u) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) {
+      const hipError_t e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return e;
+      if (*t != tag) return hipErrorUnknown;
+      break;
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  return hipSuccess;
+}
+
+// one work group: the values, a system-scope fence, then the tag
+__global__ __launch_bounds__(256) void k_orth_publish(OrthPublish o, double *__restrict__ v, unsigned long long *tag_out,
+                                                      unsigned long long tag) {
+  const int k1 = o.k + 1, total = o.S * k1;
+  for (int i = threadIdx.x; i < total; i += blockDim.x) {
+    const int sys = i / k1, j = i - sys * k1;
+    const bool second = !o.selective || o.flag[(size_t)sys * o.fs] != 0.0;
+    const size_t hb = (size_t)sys * o.hs;
+    double x;
+    if (j < o.k) {
+      x = o.h[hb + j] + (second ? o.h2[hb + j] : 0.0);
+    } else {
+      const double after = second ? o.nrm_b[(size_t)sys * o.ns] : (o.fused ? o.h2[hb + o.k] : o.nrm_a[(size_t)sys * o.ns]);
+      x = sqrt(fmax(after, 0.0));
+      o.a[(size_t)sys * o.as] = x > 0.0 ? 1.0 / x : 0.0;
+    }
+    v[i] = x;
+  }
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) *reinterpret_cast<volatile unsigned long long *>(tag_out) = tag;
+}
+
+hipError_t launch_orth_publish(const OrthPublish &o, HostPub &p, unsigned long long tag, hipStream_t s) {
+  if (o.S <= 0 || o.k < 0 || (size_t)o.S * (o.k + 1) > p.cap || !p.tag) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_orth_publish, dim3(1), dim3(256), 0, s, o, p.v_dev, p.tag_dev, tag);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_publish(int n, const double *__restrict__ src, int stride,
+                                                 double *__restrict__ v, unsigned long long *tag_out,
+                                                 unsigned long long tag) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] = src[(size_t)i * stride];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) *reinterpret_cast<volatile unsigned long long *>(tag_out) = tag;
+}
+
+hipError_t launch_publish(int n, const double *src, int stride, HostPub &p, unsigned long long tag, hipStream_t s) {
+  if (n < 0 || (size_t)n > p.cap || !p.tag) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(256), 0, s, n, src, stride, p.v_dev, p.tag_dev, tag);
+  return hipGetLastError();
+}
+
+__global__ void k_scale_dev(size_t n, const double *__restrict__ a, double *__restrict__ y) {
+  const double f = a[0];
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] *= f;
+}
+
+hipError_t launch_scale_dev(size_t n, const double *a, double *y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int nb = (int)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_scale_dev, dim3(nb), dim3(256), 0, s, n, a, y);
   return hipGetLastError();
 }
 
