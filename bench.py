@@ -90,15 +90,16 @@ FORMS = {
     "fp64": dict(precision="fp64", batch_rfd=False, learned=False),
     # mixed precision only (FP32 matvecs in FP64 Krylov), solves one after another
     "mixed": dict(precision="mixed", batch_rfd=False, learned=False),
-    # relaxed-matvec GMRES (FP32 operator once the residual is small), the three EM-RFD solves in one
-    # batched launch set, learned preconditioner correction trained beforehand on solves
-    "mixed+batched+learned": dict(precision="mixed", batch_rfd=True, graph=True, learned=True),
+    # relaxed-matvec GMRES (FP32 operator once the residual is small) with an FP32 Krylov basis, the
+    # EM-RFD solves in batched launch sets, learned preconditioner correction trained beforehand on solves
+    "mixed+batched+learned": dict(precision="mixed", batch_rfd=True, graph=True, learned=True, basis32=True),
 }
 
 
 def run_form(name, form, wl, args, fb, W, np, torch):
     prec = fb.PREC_FP64 if form["precision"] == "fp64" else fb.PREC_MIXED
-    flags = (fb.FLAG_BATCH_RFD if form["batch_rfd"] else 0) | (fb.FLAG_GRAPH if form.get("graph") else 0)
+    flags = ((fb.FLAG_BATCH_RFD if form["batch_rfd"] else 0) | (fb.FLAG_GRAPH if form.get("graph") else 0)
+             | (fb.FLAG_BASIS32 if form.get("basis32") else 0))
     ctx = fb.Context(**wl.params(), precision=prec, flags=flags)
     sid = ctx.add_shape(fb.starfish(wl.r_s, wl.b, wl.n_arm, wl.n_p))
     ctx.set_bodies(np.full(wl.n_bodies, sid), wl.q, wl.theta)
@@ -239,8 +240,8 @@ def roofline(kt, xh, wl, d):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--forms", default=",".join(FORMS), help="comma-separated subset of %s" % list(FORMS))
     ap.add_argument("--config", default="starfish10k")
     ap.add_argument("--matvecs", type=int, default=20)

@@ -72,7 +72,13 @@ enum {
   /* wave-space transforms through rocFFT plans (real-to-complex, multiplier kernel,
      complex-to-real) even where the fused transform kernels apply; those serve
      power-of-two grids 64 <= M <= 2048 and every other M uses rocFFT anyway */
-  FBIM_FLAG_LIBRARY_FFT = 16u
+  FBIM_FLAG_LIBRARY_FFT = 16u,
+  /* mixed contexts, batched solves (batches and FBIM_FLAG_BATCH_RFD): the GMRES
+     basis is stored in FP32 (half the Gram-Schmidt traffic); projections, Hessenberg
+     entries, residuals and solution updates stay FP64, and every restart residual is
+     the FP64 one, so the stopping test is unchanged.  Ignored by FP64 contexts and
+     by single-context solves.  Applies to a batch when all of its members set it. */
+  FBIM_FLAG_BASIS32 = 32u
 };
 
 /* bits of `parts` in fbim_apply_M */

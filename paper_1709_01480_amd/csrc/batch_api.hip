@@ -53,6 +53,7 @@ struct BatchEngine {
   std::vector<fbim_ctx *> sys;
   hipStream_t stream = nullptr;
   bool mixed = false;
+  bool basis32 = false;  // GMRES basis columns stored as FP32 (mixed engines, FBIM_FLAG_BASIS32)
   bool conv = false;  // fused transform kernels for every system (else rocFFT plans per class)
   uint32_t flags = 0;
   std::vector<SizeClass> classes;
@@ -407,6 +408,8 @@ fbim_status ensure_batch_buffers(BatchEngine *E, fbim_ctx *c) {
 fbim_status engine_prepare(BatchEngine *E) {
   if (E->sys.empty()) return efail(E, FBIM_EINVAL, "empty batch");
   E->mixed = E->sys[0]->mixed;
+  E->basis32 = E->mixed;
+  for (auto *c : E->sys) E->basis32 = E->basis32 && (c->p.flags & FBIM_FLAG_BASIS32);
   for (auto *c : E->sys) {
     c->stream = E->stream;
     if (c->einfo) rocfft_execution_info_set_stream(c->einfo, E->stream);
@@ -647,6 +650,14 @@ VecRef vref(const double **base, int col = 0, const size_t *ld = nullptr) {
   return v;
 }
 
+// column `col` of every system's GMRES basis (FP32 columns on FP32-basis engines;
+// the leading dimension then counts floats, so the columns fill half the storage)
+VecRef vbasis(const BatchEngine *E, const Tables &T, int col) {
+  VecRef v = vref(T.V, col, T.ld);
+  v.f32 = E->basis32 ? 1 : 0;
+  return v;
+}
+
 fbim_status seg_axpby(BatchEngine *E, Tables &T, VecRef x, VecRef y, const double *a, const double *b) {
   Timer t(E->sys[0], "blas");
   EHIP(E, launch_seg_axpby(T.seg, x, y, a, b, E->stream));
@@ -684,6 +695,7 @@ fbim_status orth_pass_b(BatchEngine *E, Tables &T, int mode, int k, const double
   a.k = k;
   a.w = nullptr;
   a.Vs = T.V;
+  a.v32 = E->basis32 ? 1 : 0;
   a.ws = const_cast<double *const *>(w);
   a.lds = T.ld;
   a.h = h;
@@ -715,7 +727,8 @@ fbim_status upload_a(BatchEngine *E, const std::vector<double> &a) {
 
 // CGS2 (or DGKS-selective) orthogonalisation of by_s against V_s[:, 0..k) for
 // every system of T; h[q][0..k) (host) and hn[q] = ||by_s|| afterwards.  With
-// `next`, next_s = by_s / hn_s (0 where hn_s = 0) is written before the host
+// `next`, next_s = by_s / hn_s (0 where hn_s = 0) is written, and its FP64 copy
+// into bx_s (the preconditioner's input of the next iteration), before the host
 // waits: the device finds the scales itself.
 fbim_status orthogonalise_b(BatchEngine *E, Tables &T, int k, std::vector<std::vector<double>> &h,
                             std::vector<double> &hn, const VecRef *next = nullptr) {
@@ -751,7 +764,10 @@ fbim_status orthogonalise_b(BatchEngine *E, Tables &T, int k, std::vector<std::v
   o.a = q.a;
   const unsigned long long tag = ++E->pub.seq;
   EHIP(E, launch_orth_publish(o, E->pub, tag, E->stream));
-  if (next) EST(seg_axpby(E, T, vref(T.by), *next, q.a, T.zeros));
+  if (next) {
+    Timer t(E->sys[0], "blas");
+    EHIP(E, launch_seg_scale2(T.seg, vref(T.by), *next, vref(T.bx), q.a, E->stream));
+  }
   EHIP(E, pub_wait(E->pub, tag, E->stream));
   const double *v = E->pub.v;
   h.assign(S, std::vector<double>(k));
@@ -839,13 +855,16 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
     T = &tables_for(E, pick(sysl, cyc), st);
     EST(st);
     EST(upload_a(E, inv));
-    EST(seg_axpby(E, *T, vref(T->r), vref(T->V, 0, T->ld), scalars(E, T->S).a, T->zeros));  // V_0 = r / beta
+    {  // V_0 = r / beta, and its FP64 copy into bx
+      Timer t(E->sys[0], "blas");
+      EHIP(E, launch_seg_scale2(T->seg, vref(T->r), vbasis(E, *T, 0), vref(T->bx), scalars(E, T->S).a, E->stream));
+    }
     std::vector<int> jend(S0, 0);
     std::vector<int> act = cyc;
     for (int j = 0; j < m && !act.empty(); ++j) {
       T = &tables_for(E, pick(sysl, act), st);
       EST(st);
-      EST(seg_axpby(E, *T, vref(T->V, j, T->ld), vref(T->bx), T->ones, T->zeros));
+      // bx_s holds V_s[:, j] (written with the column)
       bool use32 = f32;
       if (relax > 0) {
         use32 = true;
@@ -854,7 +873,7 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
       EST(run_precond_saddle(E, *T, use32));
       std::vector<std::vector<double>> hc;
       std::vector<double> hn;
-      const VecRef vnext = vref(T->V, j + 1, T->ld);
+      const VecRef vnext = vbasis(E, *T, j + 1);
       EST(orthogonalise_b(E, *T, j + 1, hc, hn, &vnext));  // V_{j+1} = w / ||w||
       std::vector<int> next;
       for (size_t q = 0; q < act.size(); ++q) {
@@ -901,7 +920,7 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
     EHIP(E, hipMemcpyAsync(sq.c, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, E->stream));
     {
       Timer t(E->sys[0], "blas");
-      EHIP(E, launch_seg_Vc(T->seg, vref(T->V, 0, T->ld), kmax, sq.c, E->hs, vref(T->bx), E->stream));
+      EHIP(E, launch_seg_Vc(T->seg, vbasis(E, *T, 0), kmax, sq.c, E->hs, vref(T->bx), E->stream));
     }
     EHIP(E, hipStreamSynchronize(E->stream));  // c is released on return
     EST(run_precond(E, *T));

@@ -231,6 +231,7 @@ struct OrthArgs {
   double *partial;
   double *out;
   int ostride;
+  int v32 = 0;  // V / Vs address FP32 columns (widened to FP64 for the arithmetic)
 };
 hipError_t launch_orth(int mode, const OrthArgs &a, hipStream_t s);
 // vector of system s in a batch: base[s] + col * ld[s] (ld may be null: col ignored)
@@ -238,10 +239,15 @@ struct VecRef {
   const double *const *base;
   const size_t *ld;
   int col;
+  int f32 = 0;  // the vectors are FP32 (base pointers address floats; ld counts floats)
 };
 // y_s = a[s] x_s + b[s] y_s over the chunks of each system (a, b: device, [S])
 hipError_t launch_seg_axpby(const Segs &seg, const VecRef &x, const VecRef &y, const double *a, const double *b,
                             hipStream_t s);
+// y_s = a[s] x_s (rounded to y's precision) and z_s = the same values in FP64
+// (z FP64; x_s not read when a[s] == 0): a basis column and its FP64 copy in one pass
+hipError_t launch_seg_scale2(const Segs &seg, const VecRef &x, const VecRef &y, const VecRef &z, const double *a,
+                             hipStream_t s);
 // y_s = V_s[:, 0..k) c_s with c_s = c + s * cstride (device)
 hipError_t launch_seg_Vc(const Segs &seg, const VecRef &V, int k, const double *c, int cstride, const VecRef &y,
                          hipStream_t s);

@@ -496,7 +496,7 @@ __device__ inline void block_sum_store(const double (&acc)[NV], int nv, double *
 //   MODE 1: w -= V h; out[j] = V_j . w (j < K), out[K] = w . w
 //   MODE 2: w -= V h; out[0] = w . w
 // E elements per thread and iteration keep E (K + 1) loads in flight.
-template <int MODE, int K>
+template <int MODE, int K, typename VT>
 __global__ __launch_bounds__(256) void k_orth(OrthArgs a) {
   constexpr int E = K <= 4 ? 4 : (K <= 12 ? 2 : 1);
   constexpr int NV = MODE == 2 ? 1 : K + 1;
@@ -511,7 +511,7 @@ __global__ __launch_bounds__(256) void k_orth(OrthArgs a) {
 #pragma unroll
     for (int j = 0; j < K; ++j) hr[j] = h[j];
   }
-  const double *__restrict__ V = a.Vs ? a.Vs[sys] : a.V;
+  const VT *__restrict__ V = reinterpret_cast<const VT *>(a.Vs ? a.Vs[sys] : a.V);
   double *__restrict__ w = a.ws ? a.ws[sys] : a.w;
   const size_t ld = a.lds ? a.lds[sys] : a.ld;
   double acc[NV];
@@ -524,7 +524,7 @@ __global__ __launch_bounds__(256) void k_orth(OrthArgs a) {
       const int i = min(i0 + 256 * e, rg.y - 1);  // clamped: out-of-chunk lanes reload a valid element
       wv[e] = w[i];
 #pragma unroll
-      for (int j = 0; j < K; ++j) vv[e][j] = V[(size_t)j * ld + i];
+      for (int j = 0; j < K; ++j) vv[e][j] = (double)V[(size_t)j * ld + i];
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(256) void k_orth(OrthArgs a) {
 
 // Runtime column count k (any k < kOrthMaxCols): MODE 0 in passes of 32 columns,
 // MODE 2 with a runtime loop.  Used beyond the unrolled range.
-template <int MODE>
+template <int MODE, typename VT>
 __global__ __launch_bounds__(256) void k_orth_any(OrthArgs a) {
   constexpr int KR = 32;
   const int cidx = blockIdx.x;
@@ -564,7 +564,7 @@ __global__ __launch_bounds__(256) void k_orth_any(OrthArgs a) {
   const int2 rg = a.seg.chunk[cidx];
   const int tid = threadIdx.x;
   const int k = a.k;
-  const double *__restrict__ V = a.Vs ? a.Vs[sys] : a.V;
+  const VT *__restrict__ V = reinterpret_cast<const VT *>(a.Vs ? a.Vs[sys] : a.V);
   double *__restrict__ w = a.ws ? a.ws[sys] : a.w;
   const size_t ld = a.lds ? a.lds[sys] : a.ld;
   if (MODE == 2) {
@@ -577,12 +577,12 @@ __global__ __launch_bounds__(256) void k_orth_any(OrthArgs a) {
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
       int j = 0;
       for (; j + 3 < k; j += 4) {
-        s0 += V[(size_t)j * ld + i] * hs[j];
-        s1 += V[(size_t)(j + 1) * ld + i] * hs[j + 1];
-        s2 += V[(size_t)(j + 2) * ld + i] * hs[j + 2];
-        s3 += V[(size_t)(j + 3) * ld + i] * hs[j + 3];
+        s0 += (double)V[(size_t)j * ld + i] * hs[j];
+        s1 += (double)V[(size_t)(j + 1) * ld + i] * hs[j + 1];
+        s2 += (double)V[(size_t)(j + 2) * ld + i] * hs[j + 2];
+        s3 += (double)V[(size_t)(j + 3) * ld + i] * hs[j + 3];
       }
-      for (; j < k; ++j) s0 += V[(size_t)j * ld + i] * hs[j];
+      for (; j < k; ++j) s0 += (double)V[(size_t)j * ld + i] * hs[j];
       const double v = w[i] - ((s0 + s1) + (s2 + s3));
       w[i] = v;
       acc[0] += v * v;
@@ -601,7 +601,7 @@ __global__ __launch_bounds__(256) void k_orth_any(OrthArgs a) {
       const double wi = w[i];
 #pragma unroll
       for (int c = 0; c < KR; ++c)
-        if (c < nc) acc[c] += V[(size_t)(j0 + c) * ld + i] * wi;
+        if (c < nc) acc[c] += (double)V[(size_t)(j0 + c) * ld + i] * wi;
       if (j0 == 0) acc[KR] += wi * wi;
     }
     __shared__ double red[4][KR + 1];
@@ -628,77 +628,122 @@ hipError_t finish(int kk, const OrthArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int MODE, int K>
+template <int MODE, int K, typename VT>
 hipError_t launch_orth_k(const OrthArgs &a, hipStream_t s) {
   if constexpr (K > kOrthFused) {
     return hipErrorInvalidValue;
   } else {
     if (a.k == K) {
-      hipLaunchKernelGGL((k_orth<MODE, K>), dim3(a.seg.nchunk), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_orth<MODE, K, VT>), dim3(a.seg.nchunk), dim3(256), 0, s, a);
       return finish(MODE == 2 ? 1 : K + 1, a, s);
     }
-    return launch_orth_k<MODE, K + 1>(a, s);
+    return launch_orth_k<MODE, K + 1, VT>(a, s);
   }
+}
+
+template <typename VT>
+hipError_t launch_orth_t(int mode, const OrthArgs &a, hipStream_t s) {
+  if (a.k <= kOrthFused) {
+    if (mode == 0) return launch_orth_k<0, 0, VT>(a, s);
+    if (mode == 1) return launch_orth_k<1, 0, VT>(a, s);
+    return launch_orth_k<2, 0, VT>(a, s);
+  }
+  if (mode == 0) {
+    hipLaunchKernelGGL((k_orth_any<0, VT>), dim3(a.seg.nchunk), dim3(256), 0, s, a);
+    return finish(a.k + 1, a, s);
+  }
+  hipLaunchKernelGGL((k_orth_any<2, VT>), dim3(a.seg.nchunk), dim3(256), 0, s, a);
+  return finish(1, a, s);
 }
 
 hipError_t launch_orth(int mode, const OrthArgs &a, hipStream_t s) {
   if (a.seg.nchunk == 0) return hipSuccess;
   if (a.k < 0 || a.k + 1 > kOrthMaxCols || (mode == 1 && a.k > kOrthFused)) return hipErrorInvalidValue;
-  if (a.k <= kOrthFused) {
-    if (mode == 0) return launch_orth_k<0, 0>(a, s);
-    if (mode == 1) return launch_orth_k<1, 0>(a, s);
-    return launch_orth_k<2, 0>(a, s);
-  }
-  if (mode == 0) {
-    hipLaunchKernelGGL((k_orth_any<0>), dim3(a.seg.nchunk), dim3(256), 0, s, a);
-    return finish(a.k + 1, a, s);
-  }
-  hipLaunchKernelGGL((k_orth_any<2>), dim3(a.seg.nchunk), dim3(256), 0, s, a);
-  return finish(1, a, s);
+  return a.v32 ? launch_orth_t<float>(mode, a, s) : launch_orth_t<double>(mode, a, s);
 }
 
 // ------------------------------------------------------------------ segmented vector kernels (batches)
-__device__ inline const double *vec_ptr(const VecRef &v, int s) {
-  return v.base[s] + (size_t)v.col * (v.ld ? v.ld[s] : 0);
+template <typename T>
+__device__ inline T *vec_ptr(const VecRef &v, int s) {
+  return reinterpret_cast<T *>(const_cast<double *>(v.base[s])) + (size_t)v.col * (v.ld ? v.ld[s] : 0);
 }
 
-// y_s = a[s] x_s + b[s] y_s (x_s not read when a[s] == 0, y_s not when b[s] == 0); one work group per chunk
+// y_s = a[s] x_s + b[s] y_s (x_s not read when a[s] == 0, y_s not when b[s] == 0); one work group per chunk;
+// FP64 arithmetic, FP32 vectors widened on load and rounded on store
+template <typename XT, typename YT>
 __global__ __launch_bounds__(256) void k_seg_axpby(Segs seg, VecRef x, VecRef y, const double *__restrict__ a,
                                                    const double *__restrict__ b) {
   const int c = blockIdx.x;
   const int s = seg.chunk_sys[c];
   const int2 rg = seg.chunk[c];
-  const double *xp = vec_ptr(x, s);
-  double *yp = const_cast<double *>(vec_ptr(y, s));
+  const XT *xp = vec_ptr<XT>(x, s);
+  YT *yp = vec_ptr<YT>(y, s);
   const double as = a[s], bs = b[s];
   // a zero coefficient reads nothing, so uninitialised vectors can be cleared
   for (int i = rg.x + threadIdx.x; i < rg.y; i += 256)
-    yp[i] = (as == 0.0 ? 0.0 : as * xp[i]) + (bs == 0.0 ? 0.0 : bs * yp[i]);
+    yp[i] = (YT)((as == 0.0 ? 0.0 : as * (double)xp[i]) + (bs == 0.0 ? 0.0 : bs * (double)yp[i]));
 }
 
 hipError_t launch_seg_axpby(const Segs &seg, const VecRef &x, const VecRef &y, const double *a, const double *b,
                             hipStream_t s) {
   if (seg.nchunk == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_seg_axpby, dim3(seg.nchunk), dim3(256), 0, s, seg, x, y, a, b);
+  const dim3 g(seg.nchunk), t(256);
+  if (!x.f32 && !y.f32)
+    hipLaunchKernelGGL((k_seg_axpby<double, double>), g, t, 0, s, seg, x, y, a, b);
+  else if (x.f32 && !y.f32)
+    hipLaunchKernelGGL((k_seg_axpby<float, double>), g, t, 0, s, seg, x, y, a, b);
+  else if (!x.f32 && y.f32)
+    hipLaunchKernelGGL((k_seg_axpby<double, float>), g, t, 0, s, seg, x, y, a, b);
+  else
+    hipLaunchKernelGGL((k_seg_axpby<float, float>), g, t, 0, s, seg, x, y, a, b);
+  return hipGetLastError();
+}
+
+template <typename YT>
+__global__ __launch_bounds__(256) void k_seg_scale2(Segs seg, VecRef x, VecRef y, VecRef z,
+                                                    const double *__restrict__ a) {
+  const int c = blockIdx.x;
+  const int s = seg.chunk_sys[c];
+  const int2 rg = seg.chunk[c];
+  const double *xp = vec_ptr<double>(x, s);
+  YT *yp = vec_ptr<YT>(y, s);
+  double *zp = vec_ptr<double>(z, s);
+  const double as = a[s];
+  for (int i = rg.x + threadIdx.x; i < rg.y; i += 256) {
+    const YT v = (YT)(as == 0.0 ? 0.0 : as * xp[i]);
+    yp[i] = v;
+    zp[i] = (double)v;
+  }
+}
+
+hipError_t launch_seg_scale2(const Segs &seg, const VecRef &x, const VecRef &y, const VecRef &z, const double *a,
+                             hipStream_t s) {
+  if (seg.nchunk == 0) return hipSuccess;
+  if (x.f32 || z.f32) return hipErrorInvalidValue;
+  if (y.f32)
+    hipLaunchKernelGGL((k_seg_scale2<float>), dim3(seg.nchunk), dim3(256), 0, s, seg, x, y, z, a);
+  else
+    hipLaunchKernelGGL((k_seg_scale2<double>), dim3(seg.nchunk), dim3(256), 0, s, seg, x, y, z, a);
   return hipGetLastError();
 }
 
 // y_s = sum_{j < k} V_s[:, j] c[s * cstride + j]
+template <typename VT>
 __global__ __launch_bounds__(256) void k_seg_Vc(Segs seg, VecRef V, int k, const double *__restrict__ c, int cstride,
                                                 VecRef y) {
   const int ci = blockIdx.x;
   const int s = seg.chunk_sys[ci];
   const int2 rg = seg.chunk[ci];
-  const double *Vp = V.base[s];
+  const VT *Vp = reinterpret_cast<const VT *>(V.base[s]);
   const size_t ld = V.ld[s];
   const double *cs = c + (size_t)s * cstride;
-  double *yp = const_cast<double *>(vec_ptr(y, s));
+  double *yp = vec_ptr<double>(y, s);
   // zero coefficients are skipped: a system that stopped earlier pads its
   // coefficients with zeros, and its basis columns beyond that are not written
   for (int i = rg.x + threadIdx.x; i < rg.y; i += 256) {
     double acc = 0.0;
     for (int j = 0; j < k; ++j)
-      if (cs[j] != 0.0) acc += Vp[(size_t)j * ld + i] * cs[j];
+      if (cs[j] != 0.0) acc += (double)Vp[(size_t)j * ld + i] * cs[j];
     yp[i] = acc;
   }
 }
@@ -706,7 +751,11 @@ __global__ __launch_bounds__(256) void k_seg_Vc(Segs seg, VecRef V, int k, const
 hipError_t launch_seg_Vc(const Segs &seg, const VecRef &V, int k, const double *c, int cstride, const VecRef &y,
                          hipStream_t s) {
   if (seg.nchunk == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_seg_Vc, dim3(seg.nchunk), dim3(256), 0, s, seg, V, k, c, cstride, y);
+  if (y.f32) return hipErrorInvalidValue;
+  if (V.f32)
+    hipLaunchKernelGGL((k_seg_Vc<float>), dim3(seg.nchunk), dim3(256), 0, s, seg, V, k, c, cstride, y);
+  else
+    hipLaunchKernelGGL((k_seg_Vc<double>), dim3(seg.nchunk), dim3(256), 0, s, seg, V, k, c, cstride, y);
   return hipGetLastError();
 }
 

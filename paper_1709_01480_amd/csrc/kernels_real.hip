@@ -232,11 +232,19 @@ __device__ __forceinline__ void pair_ell_body(const PairJob &j, const T *__restr
     const T r2 = dx * dx + dy * dy;
     const T z = xi2 * r2;
     const T ez = dev_exp(-z);
+    // near rows: E1 + ln z on [0, 2]; far rows: e^z E1 on [2*1.5^(k-1), 2*1.5^k].
+    // FP64: one series evaluation on the selected row (fewer registers for the
+    // degree-16 coefficients: occupancy 5 instead of 4); FP32: one per branch.
+    const bool near = i < nn;
     T e1;
-    if (i < nn) {  // near rows: E1 + ln z on [0, 2]
-      e1 = poly<T, DEG>(tab, z) - dev_log(z);
-    } else {  // far rows: e^z E1 on [2*1.5^(k-1), 2*1.5^k]
-      e1 = ez * poly<T, DEG>(tab + far_interval(z) * (DEG + 3), z);
+    if constexpr (sizeof(T) == 8) {
+      const T p = poly<T, DEG>(tab + (near ? 0 : far_interval(z) * (DEG + 3)), z);
+      e1 = near ? p - dev_log(z) : ez * p;
+    } else {
+      if (near)
+        e1 = poly<T, DEG>(tab, z) - dev_log(z);
+      else
+        e1 = ez * poly<T, DEG>(tab + far_interval(z) * (DEG + 3), z);
     }
     const T a = T(0.5) * e1 - ez;
     const T sdot = ez * (dx * r.z + dy * r.w) * dev_rcp(r2);
@@ -255,16 +263,19 @@ __device__ inline void load_table(T *tab, const T *__restrict__ e1tab) {
   __syncthreads();
 }
 
+// FP64: registers capped for six waves per SIMD (two 8-byte values spill to
+// scratch; 182 vs 188 us at five waves, 640k nodes)
 template <typename T, int DEG>
-__global__ __launch_bounds__(256) void k_pair_ell(PairJob j, const T *__restrict__ e1tab) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 6 : 1)))
+void k_pair_ell(PairJob j, const T *__restrict__ e1tab) {
   __shared__ T tab[kE1Int * (DEG + 3)];
   load_table<T, DEG>(tab, e1tab);
   pair_ell_body<T, DEG>(j, tab, blockIdx.x);
 }
 
 template <typename T, int DEG>
-__global__ __launch_bounds__(256) void k_pair_ell_batch(const PairJob *__restrict__ jobs, BatchGrid bg,
-                                                        const T *__restrict__ e1tab) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 6 : 1)))
+void k_pair_ell_batch(const PairJob *__restrict__ jobs, BatchGrid bg, const T *__restrict__ e1tab) {
   __shared__ T tab[kE1Int * (DEG + 3)];
   load_table<T, DEG>(tab, e1tab);
   const int s = batch_system(bg.begin, bg.S, blockIdx.x);

@@ -95,14 +95,20 @@ def test_uneven_suspensions_batched_mobility():
         assert relerr(host(U), host(ref)) < 1e-8
 
 
-def test_batched_mixed_mobility_reaches_fp64_tolerance():
+@pytest.mark.parametrize("basis32", [False, True])
+def test_batched_mixed_mobility_reaches_fp64_tolerance(basis32):
+    """Relaxed-matvec GMRES, with the Krylov basis in FP64 or FP32: the FP64
+    restart residual meets the tolerance, and the solution matches the FP64
+    context's to the accuracy that tolerance allows."""
     import paper_1709_01480_amd as fb
     wls = [W.make(n) for n in NAMES]
-    b = _batch(wls, precision=fb.PREC_MIXED, tol_gmres=1e-8)
+    b = _batch(wls, precision=fb.PREC_MIXED, tol_gmres=1e-8, flags=fb.FLAG_BASIS32 if basis32 else 0)
     Fs = [dev(wl.F) for wl in wls]
     Us = [zeros(3 * wl.n_bodies) for wl in wls]
     infos = b.mobility(Fs, Us)
+    log("basis32 %s iterations %s" % (basis32, [i["gmres_iters"] for i in infos]))
     for wl, U, info in zip(wls, Us, infos):
+        assert info["status"] == 0
         assert info["gmres_residual"] <= 1e-8
         ctx = make_ctx(wl, tol_gmres=1e-10)
         ref = zeros(3 * wl.n_bodies)
@@ -171,3 +177,25 @@ def test_uneven_suspension_batch_of_sixteen():
         ref = zeros(3 * wl.n_bodies)
         ctx.mobility(dev(wl.F), ref)
         assert relerr(host(U), host(ref)) < 1e-6, (wl.n_bodies, wl.n_p)
+
+
+@pytest.mark.parametrize("basis32", [False, True])
+def test_mixed_batched_rfd_step_matches_sequential(basis32):
+    """Mixed contexts: the EM-RFD step with the batched solves (U0 and U+ in one
+    lockstep solve, then U- from U+), graphs on, with an FP64 or FP32 Krylov
+    basis, against the same context type solving one system after another."""
+    import paper_1709_01480_amd as fb
+    wl = W.make("small12")
+    flags = fb.FLAG_BATCH_RFD | fb.FLAG_GRAPH | (fb.FLAG_BASIS32 if basis32 else 0)
+    ctx0 = make_ctx(wl, precision=fb.PREC_MIXED, tol_gmres=1e-9, tol_lanczos=1e-10)
+    ctx1 = make_ctx(wl, precision=fb.PREC_MIXED, tol_gmres=1e-9, tol_lanczos=1e-10, flags=flags)
+    Wr, Wg, Wt = W.noise(wl, ctx0.get_derived()["grid_M"])
+    d0, d1 = zeros(3 * wl.n_bodies), zeros(3 * wl.n_bodies)
+    delta = 1e-2 * wl.a
+    i0 = ctx0.step_em_rfd(1e-3, delta, dev(wl.F), dev(Wr), dev(Wg), dev(Wt), d0)
+    for rep in range(3):  # replays of the captured graphs
+        i1 = ctx1.step_em_rfd(1e-3, delta, dev(wl.F), dev(Wr), dev(Wg), dev(Wt), d1)
+        log("basis32 %s rep %d iterations %d (sequential %d)" % (basis32, rep, i1["gmres_iters"], i0["gmres_iters"]))
+        assert i1["status"] == 0 and i1["gmres_solves"] == 3
+        assert i1["gmres_residual"] <= 1e-9
+        assert relerr(host(d1), host(d0)) < 1e-6
