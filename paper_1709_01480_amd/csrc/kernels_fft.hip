@@ -247,13 +247,19 @@ __global__ __launch_bounds__(kThreads) void k_rows_fwd(const T *__restrict__ gri
   }
 }
 
-// columns: per kx, FFT along y of both components, multiplier, inverse FFT
+// columns: per kx, FFT along y of both components, multiplier, inverse FFT.
+// The M/2 + 1 columns kx = 0 .. M/2 occupy M/2 column slots: H_c(0, y) and
+// H_c(M/2, y) are real (sums of real data along x), so slot 0 carries them as
+// one complex column H_c(0, y) + i H_c(M/2, y), whose spectrum splits by
+// Hermitian symmetry into the two columns' spectra (as the row transform splits
+// g_x + i g_y).  Without that, the one column past M/2 slots would run as an
+// extra round of work groups after all the others.
 template <typename T, int LOG2M, int MODE>
 __global__ __launch_bounds__(kThreads) void k_cols(typename Cx<T>::type *__restrict__ S,
                                               const typename Cx<T>::type *__restrict__ tw,
                                               const T *__restrict__ ey, T twopi_L, T inv4xi2, T one_m_eta, T scale) {
   using V = typename Cx<T>::type;
-  constexpr int M = 1 << LOG2M, E = kElems<T>, CB = E / (2 * M), NCOL = M / 2 + 1;
+  constexpr int M = 1 << LOG2M, E = kElems<T>, CB = E / (2 * M), NSLOT = M / 2;
   __shared__ V buf[E + (E >> kPadShift<T>)];
   __shared__ TwLds<V> twl;
   const int tid = threadIdx.x;
@@ -263,10 +269,16 @@ __global__ __launch_bounds__(kThreads) void k_cols(typename Cx<T>::type *__restr
   V a[NL], b[NL];
 #pragma unroll
   for (int q = 0; q < NL; ++q) {
-    const int e = tid + q * kThreads, c = e >> LOG2M, y = e & (M - 1);
+    const int e = tid + q * kThreads, c = e >> LOG2M, y = e & (M - 1), kxi = c0 + c;
     a[q].x = a[q].y = b[q].x = b[q].y = T(0);
-    if (c0 + c < NCOL) {
-      const V *src = S + 2 * ((size_t)(c0 + c) * M + y);
+    if (kxi == 0) {  // packed slot: real parts of the kx = 0 and kx = M/2 columns
+      const V *s0 = S + 2 * (size_t)y, *sn = S + 2 * ((size_t)(M / 2) * M + y);
+      a[q].x = s0[0].x;
+      a[q].y = sn[0].x;
+      b[q].x = s0[1].x;
+      b[q].y = sn[1].x;
+    } else if (kxi < NSLOT) {
+      const V *src = S + 2 * ((size_t)kxi * M + y);
       a[q] = src[0];
       b[q] = src[1];
     }
@@ -280,18 +292,13 @@ __global__ __launch_bounds__(kThreads) void k_cols(typename Cx<T>::type *__restr
   }
   __syncthreads();
   fft_lds<T, LOG2M, 2 * CB, false>(buf, twl);
-  for (int e = tid; e < CB * M; e += kThreads) {
-    const int c = e >> LOG2M, ky = e & (M - 1);
-    if (c0 + c >= NCOL) continue;
-    V &f0 = buf[pad<T>(2 * c * M + ky)];
-    V &f1 = buf[pad<T>((2 * c + 1) * M + ky)];
+  // (g0, g1) = multiplier(kxi, ky) (f0, f1)
+  auto mult = [&](int kxi, int ky, const V &f0, const V &f1, V &g0, V &g1) {
     T sc, pxx, pxy, pyy;
-    V g0, g1;
     bool nz;
     if (MODE == 0) {
       // M^(w): the Gaussian factor exp(-(1-eta_s) k^2 / 4 xi^2) is the product of
       // its kx and ky factors, both read from the table ey (indexed by frequency index)
-      const int kxi = c0 + c;
       const T kx = twopi_L * kxi, kyv = twopi_L * (ky < M / 2 ? ky : ky - M);
       const T k2 = kx * kx + kyv * kyv;
       nz = k2 != T(0);
@@ -303,7 +310,7 @@ __global__ __launch_bounds__(kThreads) void k_cols(typename Cx<T>::type *__restr
         pxy = (kxi == M / 2 || ky == M / 2) ? T(0) : -kx * kyv * ik2;
       }
     } else {
-      nz = wave_multiplier<T>(M, ky, c0 + c, twopi_L, inv4xi2, one_m_eta, scale, MODE, sc, pxx, pxy, pyy);
+      nz = wave_multiplier<T>(M, ky, kxi, twopi_L, inv4xi2, one_m_eta, scale, MODE, sc, pxx, pxy, pyy);
     }
     if (nz) {
       g0.x = sc * (pxx * f0.x + pxy * f1.x);
@@ -313,17 +320,76 @@ __global__ __launch_bounds__(kThreads) void k_cols(typename Cx<T>::type *__restr
     } else {
       g0.x = g0.y = g1.x = g1.y = T(0);
     }
-    f0 = g0;
-    f1 = g1;
+  };
+  for (int e = tid; e < CB * M; e += kThreads) {
+    const int c = e >> LOG2M, ky = e & (M - 1), kxi = c0 + c;
+    if (kxi >= NSLOT) continue;
+    V &f0 = buf[pad<T>(2 * c * M + ky)];
+    V &f1 = buf[pad<T>((2 * c + 1) * M + ky)];
+    if (kxi != 0) {
+      V g0, g1;
+      mult(kxi, ky, f0, f1, g0, g1);
+      f0 = g0;
+      f1 = g1;
+      continue;
+    }
+    // packed slot, by pairs (ky, M - ky): the spectra A (kx = 0) and B (kx = M/2)
+    // of each component are A = (Z(ky) + conj Z(-ky)) / 2, B = (Z(ky) - conj Z(-ky)) / 2i;
+    // both stay Hermitian under their multipliers, so Z' = A' + i B' at ky and
+    // conj A' + i conj B' at -ky
+    if (ky > M / 2) continue;
+    const int km = (M - ky) & (M - 1);
+    V &m0 = buf[pad<T>(2 * c * M + km)];
+    V &m1 = buf[pad<T>((2 * c + 1) * M + km)];
+    V A0, B0, A1, B1;
+    A0.x = T(0.5) * (f0.x + m0.x);
+    A0.y = T(0.5) * (f0.y - m0.y);
+    B0.x = T(0.5) * (f0.y + m0.y);
+    B0.y = T(-0.5) * (f0.x - m0.x);
+    A1.x = T(0.5) * (f1.x + m1.x);
+    A1.y = T(0.5) * (f1.y - m1.y);
+    B1.x = T(0.5) * (f1.y + m1.y);
+    B1.y = T(-0.5) * (f1.x - m1.x);
+    V a0, a1, b0, b1;
+    mult(0, ky, A0, A1, a0, a1);
+    mult(M / 2, ky, B0, B1, b0, b1);
+    V z0, z1, w0, w1;
+    z0.x = a0.x - b0.y;
+    z0.y = a0.y + b0.x;
+    z1.x = a1.x - b1.y;
+    z1.y = a1.y + b1.x;
+    w0.x = a0.x + b0.y;
+    w0.y = b0.x - a0.y;
+    w1.x = a1.x + b1.y;
+    w1.y = b1.x - a1.y;
+    m0 = w0;  // ky = 0 and M/2 are their own partners; there z and w agree
+    m1 = w1;
+    f0 = z0;
+    f1 = z1;
   }
   __syncthreads();
   fft_lds<T, LOG2M, 2 * CB, true>(buf, twl);
   for (int e = tid; e < CB * M; e += kThreads) {
-    const int c = e >> LOG2M, y = e & (M - 1);
-    if (c0 + c >= NCOL) continue;
-    V *dst = S + 2 * ((size_t)(c0 + c) * M + y);
-    dst[0] = buf[pad<T>(2 * c * M + y)];
-    dst[1] = buf[pad<T>((2 * c + 1) * M + y)];
+    const int c = e >> LOG2M, y = e & (M - 1), kxi = c0 + c;
+    if (kxi >= NSLOT) continue;
+    const V u0 = buf[pad<T>(2 * c * M + y)], u1 = buf[pad<T>((2 * c + 1) * M + y)];
+    if (kxi == 0) {  // real parts: kx = 0; imaginary parts: kx = M/2
+      V *d0 = S + 2 * (size_t)y, *dn = S + 2 * ((size_t)(M / 2) * M + y);
+      V r;
+      r.y = T(0);
+      r.x = u0.x;
+      d0[0] = r;
+      r.x = u1.x;
+      d0[1] = r;
+      r.x = u0.y;
+      dn[0] = r;
+      r.x = u1.y;
+      dn[1] = r;
+    } else {
+      V *dst = S + 2 * ((size_t)kxi * M + y);
+      dst[0] = u0;
+      dst[1] = u1;
+    }
   }
 }
 
@@ -381,7 +447,7 @@ template <typename T, int LOG2M>
 hipError_t conv_launch(const WaveConvArgs &a, T *grid, typename Cx<T>::type *spec,
                        const typename Cx<T>::type *tw, const T *ey, hipStream_t s) {
   constexpr int M = 1 << LOG2M, E = kElems<T>, ER = kRowElems<T, M>;
-  constexpr int rows_blocks = M / (ER / M), col_blocks = (M / 2 + 1 + E / (2 * M) - 1) / (E / (2 * M));
+  constexpr int rows_blocks = M / (ER / M), col_blocks = (M / 2 + E / (2 * M) - 1) / (E / (2 * M));
   hipLaunchKernelGGL((k_rows_fwd<T, LOG2M>), dim3(rows_blocks), dim3(kThreads), 0, s, grid, spec, tw);
   const T twopi_L = (T)(2.0 * M_PI / a.L), inv4xi2 = (T)(1.0 / (4.0 * a.xi * a.xi)), ome = (T)(1.0 - a.eta_s);
   if (a.mode == 0)
