@@ -37,6 +37,7 @@ struct Tables {
   PrecondJob *pre;
   BatchGrid bg_nodes{}, bg_pair{}, bg_tiles{}, bg_spec{}, bg_bodies4{}, bg_prec{};
   size_t prec_lds = 0;
+  int spread_pmax = 1;  // largest stencil width P of the list
   Segs seg{};
   // per-system vectors (pointer tables) and leading dimension of the basis
   const double **V, **bx, **by, **t1, **b, **x2, **r, **irr, **ird;
@@ -388,6 +389,8 @@ fbim_status build_tables(BatchEngine *E, const std::vector<int> &list, Tables &T
   T.bg_bodies4.nblocks = b_bod.back();
   T.bg_prec.nblocks = b_prec.back();
   T.prec_lds = lds;
+  T.spread_pmax = 1;
+  for (int i : list) T.spread_pmax = std::max(T.spread_pmax, E->sys[i]->d.P);
   T.seg.nchunk = (int)chunks.size();
   T.seg.S = S;
   return FBIM_OK;
@@ -482,7 +485,7 @@ fbim_status run_operator(BatchEngine *E, Tables &T, bool f32, bool saddle) {
   EHIP(E, launch_gather2_batch(T.gtile[p], T.bg_nodes, p, s));
   {
     Timer t(tc, f32 ? "spread32" : "spread");
-    EHIP(E, launch_spread_batch(T.spr[p], T.bg_tiles, p, s));
+    EHIP(E, launch_spread_batch(T.spr[p], T.bg_tiles, p, T.spread_pmax, s));
   }
   if (E->conv) {
     // fused transform kernels, per listed system on its slot of the class buffers
@@ -553,6 +556,7 @@ std::vector<uint64_t> launch_signature(const BatchEngine *E, const Tables &T) {
     v.push_back(((uint64_t)(uint32_t)g->S << 32) | (uint32_t)g->nblocks);
   }
   v.push_back(T.prec_lds);
+  v.push_back((uint64_t)T.spread_pmax);
   P(E->sys[0]->d_e1tab);
   P(E->sys[0]->d_e1tab32);
   P(E->work);

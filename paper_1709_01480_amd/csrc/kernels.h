@@ -369,7 +369,8 @@ hipError_t launch_gather2_batch(const GatherJob *jobs, BatchGrid bg, int f32, hi
 hipError_t launch_pair_batch(const PairJob *jobs, BatchGrid bg, int f32, const double *tab64, const float *tab32,
                              hipStream_t s);                                                     // ceil(64 ngroups/256)
 hipError_t launch_alpert_batch(const AlpertJob *jobs, BatchGrid bg, hipStream_t s);              // ceil(N/256)
-hipError_t launch_spread_batch(const SpreadJob *jobs, BatchGrid bg, int f32, hipStream_t s);     // nts^2
+// pmax: the largest stencil width P of the batch (sizes the dynamic LDS)
+hipError_t launch_spread_batch(const SpreadJob *jobs, BatchGrid bg, int f32, int pmax, hipStream_t s);  // nts^2
 hipError_t launch_interp_batch(const InterpJob *jobs, BatchGrid bg, int f32, hipStream_t s);     // nts^2
 hipError_t launch_multiplier_batch(const MultJob *jobs, BatchGrid bg, int f32, int mode,
                                    hipStream_t s);                                                // ceil(M(M/2+1)/256)

@@ -42,6 +42,8 @@ __device__ inline int xcd_remap(int b, int n) {
 // kSpreadPre chunks is requested before any of them is used.
 constexpr int kSpreadChunk = 128;
 constexpr int kSpreadPre = 4;
+// dynamic LDS of the spreading kernels: x and y weights of a chunk, P per entry
+inline size_t spread_lds_bytes(int P, size_t elem) { return 2 * (size_t)kSpreadChunk * P * elem; }
 
 __device__ inline int wrap_near(int i, int M) {  // valid for -M <= i < 2M
   return i < 0 ? i + M : (i >= M ? i - M : i);
@@ -140,7 +142,11 @@ __device__ __forceinline__ void spread_body(int M, int TT, int P, int nts, T h, 
                             T *__restrict__ grid, int tile) {
   using V2 = typename Vec2<T>::type;
   __shared__ A acc[2][kTmax * (kTmax + 1)];  // rows padded by one: a node's P rows fall in distinct banks
-  __shared__ T wgx[kSpreadChunk][kPmax], wgy[kSpreadChunk][kPmax];
+  // the P x- and y-weights of each chunk entry, rows of P: dynamic LDS sized for
+  // the launch's P (spread_lds_bytes), so small stencils leave room for more
+  // work groups per CU
+  extern __shared__ double spread_wbuf[];
+  T *wgx = reinterpret_cast<T *>(spread_wbuf), *wgy = wgx + kSpreadChunk * P;
   __shared__ T nmx[kSpreadChunk], nmy[kSpreadChunk], ck[kPmax];
   __shared__ int nbx[kSpreadChunk], nby[kSpreadChunk], ncol[kSpreadChunk];
   const int tid = threadIdx.x;
@@ -179,11 +185,11 @@ __device__ __forceinline__ void spread_body(int M, int TT, int P, int nts, T h, 
       ncol[e0] = max(0, -xs) | (min(P, TT - xs) << 8);
       nmx[e0] = mu.x;
       nmy[e0] = mu.y;
-      gauss_row<T>(p.x, T(1), ag, h, half, P, ck, wgx[e0]);
+      gauss_row<T>(p.x, T(1), ag, h, half, P, ck, wgx + e0 * P);
     } else {
       const int oy = stencil_origin(an.y, half, gy0, M);
       nby[e0] = oy < TT ? oy : oy - M;
-      gauss_row<T>(p.y, cg, ag, h, half, P, ck, wgy[e0]);
+      gauss_row<T>(p.y, cg, ag, h, half, P, ck, wgy + e0 * P);
     }
   };
   const float invP = 1.0f / (float)P;
@@ -192,12 +198,12 @@ __device__ __forceinline__ void spread_body(int M, int TT, int P, int nts, T h, 
       const int j = (int)(((float)it + 0.5f) * invP), q = it - j * P;  // it / P, exact for it < 2^20
       const int ry = nby[j] + q;
       if (ry < 0 || ry >= TT) continue;
-      const T wy = wgy[j][q];
+      const T wy = wgy[j * P + q];
       const T ux = wy * nmx[j], uy = wy * nmy[j];
       const int cr = ncol[j], xs = nbx[j];
       A *a0 = &acc[0][ry * ST + xs], *a1 = &acc[1][ry * ST + xs];
       for (int pc = cr & 255; pc < (cr >> 8); ++pc) {
-        const T wx = wgx[j][pc];
+        const T wx = wgx[j * P + pc];
         atomicAdd(a0 + pc, (A)(ux * wx));
         atomicAdd(a1 + pc, (A)(uy * wx));
       }
@@ -368,12 +374,15 @@ __global__ __launch_bounds__(256) void k_multiplier_batch(const MultJob *__restr
 
 }  // namespace
 
-hipError_t launch_spread_batch(const SpreadJob *jobs, BatchGrid bg, int f32, hipStream_t s) {
+hipError_t launch_spread_batch(const SpreadJob *jobs, BatchGrid bg, int f32, int pmax, hipStream_t s) {
   if (bg.nblocks == 0) return hipSuccess;
+  if (pmax < 1 || pmax > kPmax) return hipErrorInvalidValue;
   if (f32)
-    hipLaunchKernelGGL((k_spread_batch<float, double>), dim3(bg.nblocks), dim3(256), 0, s, jobs, bg);
+    hipLaunchKernelGGL((k_spread_batch<float, double>), dim3(bg.nblocks), dim3(256), spread_lds_bytes(pmax, 4), s,
+                       jobs, bg);
   else
-    hipLaunchKernelGGL((k_spread_batch<double, double>), dim3(bg.nblocks), dim3(256), 0, s, jobs, bg);
+    hipLaunchKernelGGL((k_spread_batch<double, double>), dim3(bg.nblocks), dim3(256), spread_lds_bytes(pmax, 8), s,
+                       jobs, bg);
   return hipGetLastError();
 }
 
@@ -405,14 +414,14 @@ hipError_t launch_spread_lists(const WaveArgs &w, int *count, const int *start, 
 
 hipError_t launch_spread_f64(const WaveArgs &w, const double *xt, const double *mut, double *grid, hipStream_t s) {
   const int nt = w.nts * w.nts;
-  hipLaunchKernelGGL((k_spread<double, double>), dim3(nt), dim3(256), 0, s, w.M, w.T, w.P, w.nts, w.h, w.ag, w.cg,
+  hipLaunchKernelGGL((k_spread<double, double>), dim3(nt), dim3(256), spread_lds_bytes(w.P, 8), s, w.M, w.T, w.P, w.nts, w.h, w.ag, w.cg,
                      w.slist_start, w.slist, (const double2 *)xt, (const int2 *)w.anchor, (const double2 *)mut, grid);
   return hipGetLastError();
 }
 
 hipError_t launch_spread_f32(const WaveArgs &w, const float *xt, const float *mut, float *grid, hipStream_t s) {
   const int nt = w.nts * w.nts;
-  hipLaunchKernelGGL((k_spread<float, double>), dim3(nt), dim3(256), 0, s, w.M, w.T, w.P, w.nts, (float)w.h, (float)w.ag,
+  hipLaunchKernelGGL((k_spread<float, double>), dim3(nt), dim3(256), spread_lds_bytes(w.P, 4), s, w.M, w.T, w.P, w.nts, (float)w.h, (float)w.ag,
                      (float)w.cg, w.slist_start, w.slist, (const float2 *)xt, (const int2 *)w.anchor, (const float2 *)mut,
                      grid);
   return hipGetLastError();
