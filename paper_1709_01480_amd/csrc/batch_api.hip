@@ -267,7 +267,7 @@ fbim_status build_tables(BatchEngine *E, const std::vector<int> &list, Tables &T
     rj.push_back(RigidJob{c->geom(), c->d_t1, c->d_by});
     pr.push_back(PrecondJob{c->geom(), c->mats(), c->bt, c->mlp_on ? c->d_dN : nullptr, c->d_bx, c->d_t1});
     b_nodes.push_back(b_nodes.back() + (c->N + 255) / 256);
-    b_pair.push_back(b_pair.back() + (c->ngroups * 64 + 255) / 256);
+    b_pair.push_back(b_pair.back() + c->ngroups);  // one work group per group of 64 targets
     b_tiles.push_back(b_tiles.back() + c->nts * c->nts);
     b_spec.push_back(b_spec.back() + (int)((M * (M / 2 + 1) + 255) / 256));
     b_bod.push_back(b_bod.back() + (c->n + 3) / 4);

@@ -180,16 +180,24 @@ __device__ inline int far_interval(T z) {
   return min(8, max(1, 1 + (int)l));
 }
 
-// FP32 sums are compensated (Kahan); FP64 sums of ~50 terms need not be.
-// The loop keeps two loads in flight: the entry of slot i+2 and the source
-// record of slot i+1 are requested before slot i is evaluated.
+// One 256-thread work group per group of 64 targets: wave w takes rows w, w + 4,
+// w + 8, ... of the group's ELL block (near rows come first, so every wave gets a
+// share of both kinds) and the four partial sums meet in LDS.  Four short waves
+// per group instead of one long one: at 640k nodes the 10^4 groups fill the
+// chip's wave slots about five times over instead of 1.2 times (a second round
+// of 0.2 of the machine).
+// FP32 sums are compensated (Kahan); FP64 sums of ~15 terms per wave need not be.
+// The loop keeps two loads in flight: the entry two rows ahead and the source
+// record one row ahead are requested before the current row is evaluated.
+constexpr int kPairWaves = 4;
+
 template <typename T, int DEG>
-__device__ __forceinline__ void pair_ell_body(const PairJob &j, const T *__restrict__ tab, int blk) {
+__device__ __forceinline__ void pair_ell_body(const PairJob &j, const T *__restrict__ tab, int g) {
   constexpr bool kKahan = sizeof(T) == 4;
-  const T cell = (T)j.cell, xi2 = (T)j.xi2, cG = (T)j.cG;
-  const int t = blk * 256 + threadIdx.x;
-  const int g = t >> 6, lane = t & 63;
-  if (g >= j.ngroups) return;  // whole wave
+  __shared__ double part[kPairWaves - 1][64][2];
+  const T cell = (T)j.cell, xi2 = (T)j.xi2;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = g * 64 + lane;
   T tx = 0, ty = 0;
   if (t < j.N) {
     const auto p = Rec<T>::load(j.src, t);
@@ -215,11 +223,11 @@ __device__ __forceinline__ void pair_ell_body(const PairJob &j, const T *__restr
     }
   };
   // empty slots and slots past the last row read record 0 (always present) and add nothing
-  int c_cur = rows > 0 ? col[0] : -1;
-  int c_nxt = rows > 1 ? col[64] : -1;
+  int c_cur = wv < rows ? col[(size_t)wv * 64] : -1;
+  int c_nxt = wv + kPairWaves < rows ? col[(size_t)(wv + kPairWaves) * 64] : -1;
   auto rec_cur = Rec<T>::load(j.src, c_cur < 0 ? 0 : (c_cur & kIndexMask));
-  for (int i = 0; i < rows; ++i) {
-    const int c_far = i + 2 < rows ? col[(size_t)(i + 2) * 64] : -1;
+  for (int i = wv; i < rows; i += kPairWaves) {
+    const int c_far = i + 2 * kPairWaves < rows ? col[(size_t)(i + 2 * kPairWaves) * 64] : -1;
     const auto rec_nxt = Rec<T>::load(j.src, c_nxt < 0 ? 0 : (c_nxt & kIndexMask));
     const int code = c_cur;
     const auto r = rec_cur;
@@ -234,7 +242,7 @@ __device__ __forceinline__ void pair_ell_body(const PairJob &j, const T *__restr
     const T ez = dev_exp(-z);
     // near rows: E1 + ln z on [0, 2]; far rows: e^z E1 on [2*1.5^(k-1), 2*1.5^k].
     // FP64: one series evaluation on the selected row (fewer registers for the
-    // degree-16 coefficients: occupancy 5 instead of 4); FP32: one per branch.
+    // degree-16 coefficients); FP32: one per branch.
     const bool near = i < nn;
     T e1;
     if constexpr (sizeof(T) == 8) {
@@ -250,10 +258,21 @@ __device__ __forceinline__ void pair_ell_body(const PairJob &j, const T *__restr
     const T sdot = ez * (dx * r.z + dy * r.w) * dev_rcp(r2);
     add(a * r.z + sdot * dx, a * r.w + sdot * dy);
   }
-  if (t < j.N) {
+  if (wv > 0) {
+    part[wv - 1][lane][0] = (double)vx;
+    part[wv - 1][lane][1] = (double)vy;
+  }
+  __syncthreads();
+  if (wv == 0 && t < j.N) {
+    double sx = (double)vx, sy = (double)vy;
+#pragma unroll
+    for (int w = 0; w < kPairWaves - 1; ++w) {
+      sx += part[w][lane][0];
+      sy += part[w][lane][1];
+    }
     const int node = j.perm[t];
-    j.out[2 * node] = (double)(cG * vx);
-    j.out[2 * node + 1] = (double)(cG * vy);
+    j.out[2 * node] = j.cG * sx;
+    j.out[2 * node + 1] = j.cG * sy;
   }
 }
 
@@ -299,7 +318,7 @@ hipError_t pair_ell_launch(const PairLists &pl, const PairArgs &a, const T *src,
   j.cG = a.cG;
   j.src = src;
   j.out = out;
-  hipLaunchKernelGGL((k_pair_ell<T, DEG>), dim3((pl.ngroups * 64 + 255) / 256), dim3(256), 0, s, j, tab);
+  hipLaunchKernelGGL((k_pair_ell<T, DEG>), dim3(pl.ngroups), dim3(256), 0, s, j, tab);  // one group each
   return hipGetLastError();
 }
 
