@@ -240,7 +240,7 @@ def roofline(kt, xh, wl, d):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--forms", default=",".join(FORMS), help="comma-separated subset of %s" % list(FORMS))
     ap.add_argument("--config", default="starfish10k")
