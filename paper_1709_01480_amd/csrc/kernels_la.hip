@@ -818,7 +818,7 @@ hipError_t pub_alloc(HostPub &p, size_t n) {
   if (e != hipSuccess) return e;
   e = hipHostGetDevicePointer(&d, h, 0);
   if (e != hipSuccess) {
-    hipHostFree(h);
+    (void)hipHostFree(h);
     return e;
   }
   p.tag = static_cast<unsigned long long *>(h);
@@ -831,7 +831,7 @@ hipError_t pub_alloc(HostPub &p, size_t n) {
 }
 
 void pub_free(HostPub &p) {
-  if (p.tag) hipHostFree(p.tag);
+  if (p.tag) (void)hipHostFree(p.tag);  // teardown: nothing to report to
   p.tag = p.tag_dev = nullptr;
   p.v = p.v_dev = nullptr;
   p.cap = 0;
