@@ -1014,7 +1014,15 @@ fbim_status fbim_add_shape(fbim_ctx *c, int32_t n_p, const double *ref_xy, int32
   std::string err = build_shape(n_p, ref_xy, c->d, c->p.eta, c->order, c->p.tau_spurious, sd.h);
   if (!err.empty()) return fail(c, FBIM_EINVAL, err);
   STCHK(upload(c, sd.ref, sd.h.ref_xy));
-  STCHK(upload(c, sd.band, sd.h.alpert));
+  {  // the band o-major on the device, [o = -band..band][t][2 x 2], so that the
+     // nodes of a body (consecutive lanes) read consecutive blocks for each offset
+    const int nb = 2 * sd.h.band + 1;
+    std::vector<double> bt(sd.h.alpert.size());
+    for (int t = 0; t < n_p; ++t)
+      for (int o = 0; o < nb; ++o)
+        for (int q = 0; q < 4; ++q) bt[((size_t)o * n_p + t) * 4 + q] = sd.h.alpert[((size_t)t * nb + o) * 4 + q];
+    STCHK(upload(c, sd.band, bt));
+  }
   STCHK(upload(c, sd.Mp, sd.h.Mpinv));
   STCHK(upload(c, sd.Pref, sd.h.Pref));
   STCHK(upload(c, sd.Nt, sd.h.Nt));

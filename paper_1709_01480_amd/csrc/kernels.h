@@ -79,7 +79,8 @@ hipError_t launch_pair_f64(const PairLists &pl, const PairArgs &a, const double 
 hipError_t launch_pair_f32(const PairLists &pl, const PairArgs &a, const float *src, double *out, hipStream_t s);
 hipError_t launch_fill_int(size_t n, int v, int *y, hipStream_t s);
 
-// Alpert band: out[i] += R_b A_ref R_b^T mu (per node); accumulate=1 adds
+// Alpert band: out[i] += R_b A_ref R_b^T mu (per node); accumulate=1 adds.  band_tab[shape]
+// holds the 2 x 2 blocks o-major: block (o, t) at ((o + band) n_p + t) 4
 hipError_t launch_alpert(const GeomDev &g, const double *const *band_tab, const int *band, const double *mu,
                          double *out, int accumulate, hipStream_t s);
 

@@ -363,7 +363,7 @@ __device__ __forceinline__ void alpert_body(const GeomDev &g, const double *cons
   const int t = i - base;
   const int sh = g.shape[b];
   const int B = band[sh], n_p = g.np[sh];
-  const double *A = band_tab[sh] + (size_t)t * (2 * B + 1) * 4;
+  const double *A = band_tab[sh] + (size_t)t * 4;  // o-major: block (o, t) at ((o + B) n_p + t) 4
   double sn, cs;
   sincos(g.theta[b], &sn, &cs);
   double ax = 0.0, ay = 0.0;
@@ -373,7 +373,7 @@ __device__ __forceinline__ void alpert_body(const GeomDev &g, const double *cons
     l -= (l >= n_p) ? n_p : 0;
     const double2 m = mu[base + l];
     const double rx = cs * m.x + sn * m.y, ry = -sn * m.x + cs * m.y;  // R^T mu
-    const double *blk = A + (o + B) * 4;
+    const double *blk = A + (size_t)(o + B) * n_p * 4;
     ax += blk[0] * rx + blk[1] * ry;
     ay += blk[2] * rx + blk[3] * ry;
   }
