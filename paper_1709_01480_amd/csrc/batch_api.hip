@@ -794,9 +794,9 @@ std::vector<int> pick(const std::vector<int> &v, const std::vector<int> &pos) {
 // when `ir`.  Every system keeps its own Krylov space, Hessenberg matrix and
 // stopping test ||rhs - A x|| <= tol_s ||rhs||, and leaves the launches once
 // it has converged.  Outputs per system (sysl order).
-// relax > 0 (mixed engines): relaxed-matvec GMRES -- an iteration uses the FP32
-// operator once every active system's residual estimate is below relax ||rhs||;
-// restart residuals are FP64 (f32 is then ignored).  warm: start from the x
+// relax > 0 (mixed engines): relaxed-matvec GMRES -- a system's iteration uses the
+// FP32 operator once its residual estimate is below relax ||rhs|| (systems of both
+// kinds run as two launch sets); restart residuals are FP64 (f32 is then ignored).  warm: start from the x
 // given (else x = 0).
 fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool f32, const std::vector<double> &tol,
                     const std::vector<int> &maxit, std::vector<int> &iters, std::vector<double> &relres,
@@ -869,12 +869,27 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
       T = &tables_for(E, pick(sysl, act), st);
       EST(st);
       // bx_s holds V_s[:, j] (written with the column)
-      bool use32 = f32;
-      if (relax > 0) {
-        use32 = true;
-        for (int i : act) use32 = use32 && std::fabs(g[i][j]) <= relax * nb[i];
+      // relaxed: each system takes the FP32 operator once its own residual estimate
+      // is below relax ||rhs|| (as it would alone); the two groups run as two launch
+      // sets.  With graphs and more than two systems every new grouping would capture
+      // new graphs, so there the group waits for its slowest system (FP64 until all
+      // are below the threshold).
+      std::vector<int> p64, p32;
+      if (relax > 0)
+        for (int i : act) (std::fabs(g[i][j]) <= relax * nb[i] ? p32 : p64).push_back(i);
+      const bool split = !(E->flags & FBIM_BATCH_GRAPH) || act.size() <= 2;
+      if (relax <= 0 || p64.empty() || p32.empty() || !split) {
+        EST(run_precond_saddle(E, *T, relax > 0 ? p64.empty() : f32));
+      } else {
+        Tables *Tg = &tables_for(E, pick(sysl, p64), st);
+        EST(st);
+        EST(run_precond_saddle(E, *Tg, false));
+        Tg = &tables_for(E, pick(sysl, p32), st);
+        EST(st);
+        EST(run_precond_saddle(E, *Tg, true));
+        T = &tables_for(E, pick(sysl, act), st);
+        EST(st);
       }
-      EST(run_precond_saddle(E, *T, use32));
       std::vector<std::vector<double>> hc;
       std::vector<double> hn;
       const VecRef vnext = vbasis(E, *T, j + 1);
