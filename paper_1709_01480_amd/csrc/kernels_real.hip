@@ -282,19 +282,16 @@ __device__ inline void load_table(T *tab, const T *__restrict__ e1tab) {
   __syncthreads();
 }
 
-// FP64: registers capped for six waves per SIMD (two 8-byte values spill to
-// scratch; 182 vs 188 us at five waves, 640k nodes)
 template <typename T, int DEG>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 6 : 1)))
-void k_pair_ell(PairJob j, const T *__restrict__ e1tab) {
+__global__ __launch_bounds__(256) void k_pair_ell(PairJob j, const T *__restrict__ e1tab) {
   __shared__ T tab[kE1Int * (DEG + 3)];
   load_table<T, DEG>(tab, e1tab);
   pair_ell_body<T, DEG>(j, tab, blockIdx.x);
 }
 
 template <typename T, int DEG>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 6 : 1)))
-void k_pair_ell_batch(const PairJob *__restrict__ jobs, BatchGrid bg, const T *__restrict__ e1tab) {
+__global__ __launch_bounds__(256) void k_pair_ell_batch(const PairJob *__restrict__ jobs, BatchGrid bg,
+                                                        const T *__restrict__ e1tab) {
   __shared__ T tab[kE1Int * (DEG + 3)];
   load_table<T, DEG>(tab, e1tab);
   const int s = batch_system(bg.begin, bg.S, blockIdx.x);
