@@ -473,7 +473,8 @@ fbim_status run_operator(BatchEngine *E, Tables &T, bool f32, bool saddle) {
   hipStream_t s = E->stream;
   fbim_ctx *tc = E->sys[0];
   const int p = f32 ? 1 : 0;
-  EHIP(E, launch_gather2_batch(T.gcell[p], T.bg_nodes, p, s));
+  // the input in cell order (pair kernel) and in tile order (spreading), one launch
+  EHIP(E, launch_gather2x2_batch(T.gcell[p], T.gtile[p], T.bg_nodes, p, s));
   {
     Timer t(tc, f32 ? "pair32" : "pair");
     EHIP(E, launch_pair_batch(T.pair[p], T.bg_pair, p, tc->d_e1tab, tc->d_e1tab32, s));
@@ -482,7 +483,6 @@ fbim_status run_operator(BatchEngine *E, Tables &T, bool f32, bool saddle) {
     Timer t(tc, "alpert");
     EHIP(E, launch_alpert_batch(T.alp, T.bg_nodes, s));
   }
-  EHIP(E, launch_gather2_batch(T.gtile[p], T.bg_nodes, p, s));
   {
     Timer t(tc, f32 ? "spread32" : "spread");
     EHIP(E, launch_spread_batch(T.spr[p], T.bg_tiles, p, T.spread_pmax, s));

@@ -366,7 +366,9 @@ struct PrecondJob {
   double *y;
 };
 // grids: blocks of 256 threads per system as listed with each launcher
-hipError_t launch_gather2_batch(const GatherJob *jobs, BatchGrid bg, int f32, hipStream_t s);   // ceil(N/256)
+hipError_t launch_gather2_batch(const GatherJob *jobs, BatchGrid bg, int f32, hipStream_t s);
+// both job tables (same node counts per system) in one launch
+hipError_t launch_gather2x2_batch(const GatherJob *ja, const GatherJob *jb, BatchGrid bg, int f32, hipStream_t s);   // ceil(N/256)
 hipError_t launch_pair_batch(const PairJob *jobs, BatchGrid bg, int f32, const double *tab64, const float *tab32,
                              hipStream_t s);                                                     // ceil(64 ngroups/256)
 hipError_t launch_alpert_batch(const AlpertJob *jobs, BatchGrid bg, hipStream_t s);              // ceil(N/256)

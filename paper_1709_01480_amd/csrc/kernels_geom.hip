@@ -241,6 +241,30 @@ hipError_t launch_gather2_batch(const GatherJob *jobs, BatchGrid bg, int f32, hi
   return hipGetLastError();
 }
 
+// the same for two job tables over the same node counts (one launch)
+__global__ __launch_bounds__(256) void k_gather2x2_batch(const GatherJob *__restrict__ ja,
+                                                         const GatherJob *__restrict__ jb, BatchGrid bg, int f32) {
+  const int s = batch_system(bg.begin, bg.S, blockIdx.x);
+  const int i = (blockIdx.x - bg.begin[s]) * 256 + threadIdx.x;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const GatherJob j = t == 0 ? ja[s] : jb[s];
+    if (i >= j.N) continue;
+    const double2 v = reinterpret_cast<const double2 *>(j.src)[j.perm[i]];
+    const int k = j.packed ? 2 * i + 1 : i;
+    if (f32)
+      reinterpret_cast<float2 *>(j.dst)[k] = make_float2((float)v.x, (float)v.y);
+    else
+      reinterpret_cast<double2 *>(j.dst)[k] = v;
+  }
+}
+
+hipError_t launch_gather2x2_batch(const GatherJob *ja, const GatherJob *jb, BatchGrid bg, int f32, hipStream_t s) {
+  if (bg.nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather2x2_batch, dim3(bg.nblocks), dim3(256), 0, s, ja, jb, bg, f32);
+  return hipGetLastError();
+}
+
 // Tile-ordered stencil data: nearest grid indices a = floor(x/h + 1/2) (unwrapped)
 // and the FP64 offsets x - a h, |offset| <= h/2 (also stored in FP32).
 __global__ void k_anchors(int N, const int *__restrict__ tperm, const double *__restrict__ x, double h,
