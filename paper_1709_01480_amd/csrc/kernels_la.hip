@@ -74,11 +74,11 @@ hipError_t launch_KT(const GeomDev &g, const double *mu, double sgn, double *out
 
 // batched saddle rigid-body terms: y_mu -= K x_U over the nodes, then
 // y_U = -K^T x_mu with one wave per body (4 bodies per 256-thread block)
-__global__ __launch_bounds__(256) void k_sub_KU_batch(const RigidJob *__restrict__ jobs, BatchGrid bg) {
-  const int s = batch_system(bg.begin, bg.S, blockIdx.x);
+__device__ __forceinline__ void sub_KU_batch_body(const RigidJob *__restrict__ jobs, const BatchGrid &bg, int blk) {
+  const int s = batch_system(bg.begin, bg.S, blk);
   const RigidJob &j = jobs[s];
   const GeomDev &g = j.g;
-  const int i = (blockIdx.x - bg.begin[s]) * 256 + threadIdx.x;
+  const int i = (blk - bg.begin[s]) * 256 + threadIdx.x;
   if (i >= g.N) return;
   const int b = g.body[i];
   const int t = i - g.off[b];
@@ -93,11 +93,11 @@ __global__ __launch_bounds__(256) void k_sub_KU_batch(const RigidJob *__restrict
   j.y[2 * i + 1] -= U[3 * b + 1] + w * rx;
 }
 
-__global__ __launch_bounds__(256) void k_KT_batch(const RigidJob *__restrict__ jobs, BatchGrid bg) {
-  const int s = batch_system(bg.begin, bg.S, blockIdx.x);
+__device__ __forceinline__ void KT_batch_body(const RigidJob *__restrict__ jobs, const BatchGrid &bg, int blk) {
+  const int s = batch_system(bg.begin, bg.S, blk);
   const RigidJob &j = jobs[s];
   const GeomDev &g = j.g;
-  const int b = (blockIdx.x - bg.begin[s]) * 4 + (threadIdx.x >> 6);
+  const int b = (blk - bg.begin[s]) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (b >= g.n) return;  // whole wave
   const int a = g.off[b], e = g.off[b + 1];
@@ -128,11 +128,19 @@ __global__ __launch_bounds__(256) void k_KT_batch(const RigidJob *__restrict__ j
   }
 }
 
+// the two rigid-body maps of the saddle operator touch disjoint rows of y and read
+// only x: one launch, the node blocks first, then the body blocks
+__global__ __launch_bounds__(256) void k_rigid_batch(const RigidJob *__restrict__ jobs, BatchGrid bg_nodes,
+                                                     BatchGrid bg_bodies) {
+  if ((int)blockIdx.x < bg_nodes.nblocks)
+    sub_KU_batch_body(jobs, bg_nodes, blockIdx.x);
+  else
+    KT_batch_body(jobs, bg_bodies, blockIdx.x - bg_nodes.nblocks);
+}
+
 hipError_t launch_rigid_batch(const RigidJob *jobs, BatchGrid bg_nodes, BatchGrid bg_bodies, hipStream_t s) {
-  if (bg_nodes.nblocks > 0) hipLaunchKernelGGL(k_sub_KU_batch, dim3(bg_nodes.nblocks), dim3(256), 0, s, jobs, bg_nodes);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (bg_bodies.nblocks > 0) hipLaunchKernelGGL(k_KT_batch, dim3(bg_bodies.nblocks), dim3(256), 0, s, jobs, bg_bodies);
+  const int nb = bg_nodes.nblocks + bg_bodies.nblocks;
+  if (nb > 0) hipLaunchKernelGGL(k_rigid_batch, dim3(nb), dim3(256), 0, s, jobs, bg_nodes, bg_bodies);
   return hipGetLastError();
 }
 

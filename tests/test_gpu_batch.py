@@ -95,14 +95,17 @@ def test_uneven_suspensions_batched_mobility():
         assert relerr(host(U), host(ref)) < 1e-8
 
 
-@pytest.mark.parametrize("basis32", [False, True])
-def test_batched_mixed_mobility_reaches_fp64_tolerance(basis32):
+@pytest.mark.parametrize("basis32,graph", [(False, False), (True, False), (True, True)])
+def test_batched_mixed_mobility_reaches_fp64_tolerance(basis32, graph):
     """Relaxed-matvec GMRES, with the Krylov basis in FP64 or FP32: the FP64
     restart residual meets the tolerance, and the solution matches the FP64
-    context's to the accuracy that tolerance allows."""
+    context's to the accuracy that tolerance allows.  Without graphs each system
+    switches to the FP32 operator on its own; with graphs (three systems) the
+    group switches together."""
     import paper_1709_01480_amd as fb
     wls = [W.make(n) for n in NAMES]
-    b = _batch(wls, precision=fb.PREC_MIXED, tol_gmres=1e-8, flags=fb.FLAG_BASIS32 if basis32 else 0)
+    b = _batch(wls, graph=graph, precision=fb.PREC_MIXED, tol_gmres=1e-8,
+               flags=fb.FLAG_BASIS32 if basis32 else 0)
     Fs = [dev(wl.F) for wl in wls]
     Us = [zeros(3 * wl.n_bodies) for wl in wls]
     infos = b.mobility(Fs, Us)
