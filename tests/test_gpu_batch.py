@@ -182,6 +182,30 @@ def test_uneven_suspension_batch_of_sixteen():
         assert relerr(host(U), host(ref)) < 1e-6, (wl.n_bodies, wl.n_p)
 
 
+def test_uneven_suspension_batch_full_size():
+    """The uneven-suspension batch at full size: 64 suspensions (bodies
+    log-uniform in [16, 512], 64 / 128 / 256 nodes per body, area fraction 0.2;
+    9824 bodies, 1.42e6 nodes, grids 128..1024), graphs on, one batched mobility
+    solve.  Every suspension meets the tolerance on its FP64 true residual, and
+    the smallest, the largest and two other suspensions match their own contexts."""
+    wls = W.uneven_suspensions(64)
+    log("full uneven batch: %d suspensions, %d nodes" % (len(wls), sum(w.n_nodes for w in wls)))
+    b = _batch(wls, graph=True, tol_gmres=1e-8)
+    Us = [zeros(3 * wl.n_bodies) for wl in wls]
+    infos = b.mobility([dev(wl.F) for wl in wls], Us)
+    log("iterations min %d max %d" % (min(i["gmres_iters"] for i in infos), max(i["gmres_iters"] for i in infos)))
+    for info in infos:
+        assert info["status"] == 0 and info["gmres_residual"] <= 1e-8
+    sizes = [wl.n_nodes for wl in wls]
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 7, 40})
+    for k in pick:
+        wl = wls[k]
+        ctx = make_ctx(wl, tol_gmres=1e-8)
+        ref = zeros(3 * wl.n_bodies)
+        ctx.mobility(dev(wl.F), ref)
+        assert relerr(host(Us[k]), host(ref)) < 1e-6, (k, wl.n_bodies, wl.n_p)
+
+
 @pytest.mark.parametrize("basis32", [False, True])
 def test_mixed_batched_rfd_step_matches_sequential(basis32):
     """Mixed contexts: the EM-RFD step with the batched solves (U0 and U+ in one
