@@ -237,6 +237,51 @@ def roofline(kt, xh, wl, d):
             "frac": ach / PEAK["hbm"], "traffic": traffic, "avg_launch_ms": avg_s * 1e3, "bytes_per_launch": b}
 
 
+def run_batch(args, fb, W, np, torch):
+    """The uneven-suspension batch (64 suspensions, bodies log-uniform in [16, 512],
+    64 / 128 / 256 nodes per body): one batched mobility solve of all of them
+    (graphs on) against the same member contexts solving one after another.
+    One JSON line per precision on stdout."""
+    wls = W.uneven_suspensions(64)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+    for prec, flags, label in ((fb.PREC_FP64, 0, "fp64"), (fb.PREC_MIXED, fb.FLAG_BASIS32, "mixed+basis32")):
+        prms = []
+        for wl in wls:
+            p = wl.params()
+            p.update(precision=prec, flags=flags)
+            prms.append(p)
+        b = fb.Batch(prms, graph=True)
+        for m, wl in zip(b.members, wls):
+            sid = m.add_shape(fb.starfish(wl.r_s, wl.b, wl.n_arm, wl.n_p))
+            m.set_bodies(np.full(wl.n_bodies, sid), wl.q, wl.theta)
+        Fs = [dev(wl.F) for wl in wls]
+        Us = [torch.zeros(3 * wl.n_bodies, dtype=torch.float64, device="cuda") for wl in wls]
+        for _ in range(max(1, args.warmup)):
+            b.mobility(Fs, Us)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            infos = b.mobility(Fs, Us)
+        torch.cuda.synchronize()
+        t_b = (time.perf_counter() - t0) / args.steps
+        for m, F, U in zip(b.members, Fs, Us):  # warm the single-system paths
+            m.mobility(F, U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = 0
+        for m, F, U in zip(b.members, Fs, Us):
+            its += m.mobility(F, U)["gmres_iters"]
+        torch.cuda.synchronize()
+        t_s = time.perf_counter() - t0
+        print(json.dumps({"mode": "batch", "precision": label, "suspensions": len(wls),
+                          "nodes": sum(w.n_nodes for w in wls), "ms_batched": 1e3 * t_b,
+                          "ms_one_after_another": 1e3 * t_s, "speedup": t_s / t_b,
+                          "gmres_iters_batched": sum(i["gmres_iters"] for i in infos),
+                          "gmres_iters_one_after_another": its,
+                          "max_residual": max(i["gmres_residual"] for i in infos)}))
+        b.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,10 +292,11 @@ def main():
     ap.add_argument("--matvecs", type=int, default=20)
     ap.add_argument("--train-configs", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="step", choices=["step", "matvec", "copy"],
+    ap.add_argument("--mode", default="step", choices=["step", "matvec", "copy", "batch"],
                     help="step: the EM-RFD benchmark; matvec: only single-layer matvecs of the first form "
                          "(short runs for counter collection); copy: a plain 1 GiB device copy "
-                         "used to calibrate the HBM byte counters")
+                         "used to calibrate the HBM byte counters; batch: mobility solves of the "
+                         "64-suspension uneven batch, batched against one after another")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -272,6 +318,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "copy", "bytes_read": 8 * n, "bytes_written": 8 * n, "copies": args.steps}))
+        return
+    if args.mode == "batch":
+        run_batch(args, fb, W, np, torch)
         return
     wl = W.make(args.config)
     names = [f for f in args.forms.split(",") if f]
