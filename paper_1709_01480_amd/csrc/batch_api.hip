@@ -62,7 +62,7 @@ struct BatchEngine {
   rocfft_execution_info einfo = nullptr;
   void *work = nullptr;
   size_t work_bytes = 0;
-  static constexpr int kSubSlots = 4;
+  static constexpr int kSubSlots = 8;
   Tables full, sub[kSubSlots];  // the full list and recent sub-lists (filled in turn)
   int sub_next = 0;
   double *d_sc = nullptr;  // per-system scalars: [a | h | h2 | nrm | flag | c] blocks
@@ -586,9 +586,9 @@ std::vector<uint64_t> launch_signature(const BatchEngine *E, const Tables &T) {
 }
 
 // t1 = P^-1 bx, by = A t1 for every system of T; replayed from a HIP graph
-// (one per table slot and precision) when enabled
-fbim_status run_precond_saddle(BatchEngine *E, Tables &T, bool f32) {
-  const bool graph = (E->flags & FBIM_BATCH_GRAPH) && !E->sys[0]->timing;
+// (one per table slot and precision) when enabled and graph_ok
+fbim_status run_precond_saddle(BatchEngine *E, Tables &T, bool f32, bool graph_ok = true) {
+  const bool graph = graph_ok && (E->flags & FBIM_BATCH_GRAPH) && !E->sys[0]->timing;
   if (!graph) {
     EST(run_precond(E, T));
     return run_operator(E, T, f32, true);
@@ -871,22 +871,21 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
       // bx_s holds V_s[:, j] (written with the column)
       // relaxed: each system takes the FP32 operator once its own residual estimate
       // is below relax ||rhs|| (as it would alone); the two groups run as two launch
-      // sets.  With graphs and more than two systems every new grouping would capture
-      // new graphs, so there the group waits for its slowest system (FP64 until all
-      // are below the threshold).
+      // sets.  With more than two systems the groupings keep changing, so their
+      // launch sets run without graphs (no capture per grouping).
       std::vector<int> p64, p32;
       if (relax > 0)
         for (int i : act) (std::fabs(g[i][j]) <= relax * nb[i] ? p32 : p64).push_back(i);
-      const bool split = !(E->flags & FBIM_BATCH_GRAPH) || act.size() <= 2;
-      if (relax <= 0 || p64.empty() || p32.empty() || !split) {
+      if (relax <= 0 || p64.empty() || p32.empty()) {
         EST(run_precond_saddle(E, *T, relax > 0 ? p64.empty() : f32));
       } else {
+        const bool graph_ok = act.size() <= 2;
         Tables *Tg = &tables_for(E, pick(sysl, p64), st);
         EST(st);
-        EST(run_precond_saddle(E, *Tg, false));
+        EST(run_precond_saddle(E, *Tg, false, graph_ok));
         Tg = &tables_for(E, pick(sysl, p32), st);
         EST(st);
-        EST(run_precond_saddle(E, *Tg, true));
+        EST(run_precond_saddle(E, *Tg, true, graph_ok));
         T = &tables_for(E, pick(sysl, act), st);
         EST(st);
       }
