@@ -99,9 +99,9 @@ def test_uneven_suspensions_batched_mobility():
 def test_batched_mixed_mobility_reaches_fp64_tolerance(basis32, graph):
     """Relaxed-matvec GMRES, with the Krylov basis in FP64 or FP32: the FP64
     restart residual meets the tolerance, and the solution matches the FP64
-    context's to the accuracy that tolerance allows.  Without graphs each system
-    switches to the FP32 operator on its own; with graphs (three systems) the
-    group switches together."""
+    context's to the accuracy that tolerance allows.  Each system switches to the
+    FP32 operator on its own; with graphs on (three systems) the launch sets of
+    mixed groupings run eagerly, the others from graphs."""
     import paper_1709_01480_amd as fb
     wls = [W.make(n) for n in NAMES]
     b = _batch(wls, graph=graph, precision=fb.PREC_MIXED, tol_gmres=1e-8,
