@@ -2,8 +2,9 @@
 different sizes (and grid sizes) through one launch per stage must give each
 system's own single-system results.
 
-Bars: the batched matvec runs the same per-system arithmetic (only the
-spreading's LDS-atomic order differs), so 1e-12 relative; batched GMRES runs
+Bars: the batched matvec runs the same per-system arithmetic (the spreading's
+sums are exact fixed-point integers, so the order of its LDS atomics does not
+matter), so 1e-12 relative; batched GMRES runs
 each system's own Krylov iteration, so solutions agree to the solver
 tolerance (GMRES at 1e-10 here: 1e-8 relative); the EM-RFD step as the
 single-system step (1e-6, the step's parity bar against the oracle)."""
