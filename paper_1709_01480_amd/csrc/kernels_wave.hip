@@ -186,27 +186,33 @@ __device__ __forceinline__ void spread_body(int M, int TT, int P, int nts, T h, 
   for (int i = tid; i < TT * ST; i += 256) acc[0][i] = acc[1][i] = A(0);
   if (tid < P) ck[tid] = gauss_step<T>(ag, h, tid);
   constexpr bool kFixed = std::is_same<A, unsigned long long>::value;
-  T S = T(1);  // fixed-point scale (kFixed)
+  T S = T(1);       // fixed-point scale (kFixed)
+  bool finite = true;  // a non-finite density makes the tile's grid NaN (as floating-point sums would)
   if constexpr (kFixed) {
     __shared__ T red[4];
+    // max |mu| over the list; any NaN or infinity (which fmax would skip) is flagged
     T m = T(0);
+    int bad = 0;
+    auto take = [&](V2 mu) {
+      const T a = fmax(fabs(mu.x), fabs(mu.y));
+      bad |= !(fabs(mu.x) <= T(3.0e38) && fabs(mu.y) <= T(3.0e38));
+      m = fmax(m, a);
+    };
 #pragma unroll
     for (int r = 0; r < kSpreadPre; ++r)
-      if (e0 + kSpreadChunk * r < n) m = fmax(m, fmax(fabs(mr[r].x), fabs(mr[r].y)));
-    for (int e = kSpreadChunk * kSpreadPre + tid; e < n; e += 256) {  // rare: crowded tiles
-      const V2 mu = mut[slist[ls + e]];
-      m = fmax(m, fmax(fabs(mu.x), fabs(mu.y)));
-    }
+      if (e0 + kSpreadChunk * r < n) take(mr[r]);
+    for (int e = kSpreadChunk * kSpreadPre + tid; e < n; e += 256) take(mut[slist[ls + e]]);  // rare: crowded tiles
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
     if ((tid & 63) == 0) red[tid >> 6] = m;
-    __syncthreads();
+    finite = __syncthreads_or(bad) == 0;  // also the barrier for red
     m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    const T B = T(2) * (T)n * cg * m;
-    if (B > T(0)) {
+    const double B = 2.0 * (double)n * (double)cg * (double)m;  // no overflow for finite FP32 inputs
+    if (finite && B > 0.0) {
       int k;
       frexp(B, &k);  // B < 2^k
-      S = ldexp(T(1), min(62 - k, sizeof(T) == 4 ? 126 : 1000));
+      constexpr int kMaxE = sizeof(T) == 4 ? 126 : 1000;
+      S = ldexp(T(1), max(min(62 - k, kMaxE), -kMaxE));
     }
   }
   __syncthreads();  // ck (and the zeroed accumulator) before any use
@@ -279,7 +285,7 @@ __device__ __forceinline__ void spread_body(int M, int TT, int P, int nts, T h, 
     const int ry = i / TT, rx = i - ry * TT;
     const size_t gidx = (size_t)(gy0 + ry) * M + gx0 + rx;
     if constexpr (kFixed) {
-      const T inv = T(1) / S;  // exact
+      const T inv = finite ? T(1) / S : T(NAN);  // exact power of two
       grid[gidx] = (T)(long long)acc[0][ry * ST + rx] * inv;
       grid[(size_t)M * M + gidx] = (T)(long long)acc[1][ry * ST + rx] * inv;
     } else {

@@ -136,3 +136,20 @@ def test_random_field_same_algorithm():
     # the Gaussian deconvolution scales the highest modes (and their FFT round-off)
     # by up to exp(eta_s u_max / 2) ~ 1e2, hence a looser bound than the matvec
     assert relerr(host(out), OF.random_field(X, Wg, prm)) < 1e-9
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_non_finite_density_reaches_the_wave_part(mixed):
+    """Spreading sums in fixed point: a NaN density must still come out as NaN
+    (as floating-point sums would carry it), not as a finite value."""
+    import paper_1709_01480_amd as fb
+    wl = workload("starfish4")
+    ctx = make_ctx(wl, precision=fb.PREC_MIXED if mixed else fb.PREC_FP64)
+    mu = np.random.default_rng(3).standard_normal(2 * wl.n_nodes)
+    mu[5] = np.nan
+    out = zeros(mu.size)
+    ctx.apply_M(dev(mu), out, fb.PART_WAVE)
+    assert np.isnan(host(out)).any()
+    mu[5] = 0.0
+    ctx.apply_M(dev(mu), out, fb.PART_WAVE)
+    assert np.isfinite(host(out)).all()
