@@ -500,9 +500,17 @@ class DenseFBIM:
     def mobility(self, F, slip=None):
         return saddle_solve(self.mats["M"], self.K, F, slip)
 
+    def real_root(self):
+        """A_r = G^+ (G M^(r) G^T)^(1/2), the dense map W^(r) -> v^(r) of eq. 3.38
+        (computed once per configuration)."""
+        if not hasattr(self, "_Ar"):
+            G, Gp = G_blocks(self.geo, self.prm, self.order, self.tau, self.eta)
+            self._Ar = Gp @ sqrt_psd(G @ self.mats["Mr"] @ G.T)
+        return self._Ar
+
     def slip(self, W_r, W_grid, kT, dt):
-        G, Gp = G_blocks(self.geo, self.prm, self.order, self.tau, self.eta)
-        vr = slip_real(self.mats["Mr"], G, Gp, W_r)
+        """v = sqrt(2 kT / dt) (v^(r) + v^(w)) (eq. 3.27) with independent W^(r), W^(w)."""
+        vr = self.real_root() @ W_r
         vw = random_field(self.X, W_grid, self.prm, self.eta)
         return math.sqrt(2 * kT / dt) * (vr + vw), vr, vw
 

@@ -81,7 +81,7 @@ def _load():
     # libfbim.so then binds to that already-loaded runtime by soname
     import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libfbim.so is not built; run `python -m paper_1709_01480_amd.build` "
+        raise ImportError("libfbim.so is not built; run `python paper_1709_01480_amd/build.py` "
                           "(no CPU fallback exists)")
     L = ctypes.CDLL(LIB_PATH)
     p, i32, u32, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double

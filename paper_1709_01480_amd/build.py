@@ -1,6 +1,6 @@
 """Build the HIP library libfbim.so for gfx950 (in-tree).
 
-    python -m paper_1709_01480_amd.build
+    python paper_1709_01480_amd/build.py
 """
 import concurrent.futures
 import os
