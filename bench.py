@@ -4,8 +4,10 @@ Workload: 10,000 five-arm starfish x 64 nodes (640,000 nodes), area fraction
 0.3, unit periodic box, grid 2048^2, tol_ewald 1e-6, 4th-order Alpert, GMRES and
 Lanczos tolerance 1e-6.  Inputs (geometry, forces, noise) are synthetic and
 seeded, and resident in HBM before timing starts.  One step = one
-Euler-Maruyama random-finite-difference step (Lanczos square root, random
-Fourier field, three GMRES mobility solves, geometry rebuilds).
+Brownian-dynamics step: Euler-Maruyama with the random finite difference
+(fresh noise drawn by the library, Lanczos square root, random Fourier field,
+three GMRES mobility solves, geometry of the two RFD configurations) and the
+move of the bodies to Q + dQ (geometry rebuild, learned-correction refresh).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms fp64,mixed+batched+learned]
 
@@ -100,7 +102,7 @@ def run_form(name, form, wl, args, fb, W, np, torch):
     prec = fb.PREC_FP64 if form["precision"] == "fp64" else fb.PREC_MIXED
     flags = ((fb.FLAG_BATCH_RFD if form["batch_rfd"] else 0) | (fb.FLAG_GRAPH if form.get("graph") else 0)
              | (fb.FLAG_BASIS32 if form.get("basis32") else 0))
-    ctx = fb.Context(**wl.params(), precision=prec, flags=flags)
+    ctx = fb.Context(**wl.params(), precision=prec, flags=flags, seed=W.noise_key(wl))
     sid = ctx.add_shape(fb.starfish(wl.r_s, wl.b, wl.n_arm, wl.n_p))
     ctx.set_bodies(np.full(wl.n_bodies, sid), wl.q, wl.theta)
     d = ctx.get_derived()
@@ -119,8 +121,7 @@ def run_form(name, form, wl, args, fb, W, np, torch):
         ctx.mlp_use(True)
         log("%s: trained on %d configurations in %.1f s (last: %s)"
             % (name, args.train_configs, time.perf_counter() - t0, train))
-    W_r, W_grid, W_t = W.noise(wl, M)
-    F, Wr, Wg, Wt = dev(wl.F), dev(W_r), dev(W_grid), dev(W_t)
+    F = dev(wl.F)
     dQ = torch.zeros(3 * wl.n_bodies, dtype=torch.float64, device="cuda")
     delta = wl.a * wl.tol_gmres ** (1.0 / 3.0)
     # matvec throughput
@@ -137,23 +138,28 @@ def run_form(name, form, wl, args, fb, W, np, torch):
     t_mv = (time.perf_counter() - t0) / args.matvecs
     kt_mv = {k: ctx.kernel_time(k) for k in KERNEL_CLASSES}
     log("%s matvec: %.3f ms (%.1f Mnodes/s)" % (name, 1e3 * t_mv, N / t_mv / 1e6))
-    # EM-RFD steps (warmup without per-kernel events, as the timed steps: graphs are captured here)
+    # Brownian dynamics: every step draws fresh noise in the library (W_r, W_grid, W~ from
+    # the context's generator), solves, and moves the bodies to Q + dQ (geometry rebuild and,
+    # with the learned correction, its refresh).  Warm-up steps run the same way, untimed
+    # (graphs are captured there).
     ctx.set_timing(False)
     for i in range(args.warmup):
-        info = ctx.step_em_rfd(wl.dt, delta, F, Wr, Wg, Wt, dQ)
+        info = ctx.step_em_rfd(wl.dt, delta, F, None, None, None, dQ, apply=True)
         log("%s warmup step %d: %s" % (name, i, info))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
     for i in range(args.steps):
-        infos.append(ctx.step_em_rfd(wl.dt, delta, F, Wr, Wg, Wt, dQ))
+        infos.append(ctx.step_em_rfd(wl.dt, delta, F, None, None, None, dQ, apply=True))
         log("%s step %d: %s" % (name, i, infos[-1]))
     torch.cuda.synchronize()
     t_step = (time.perf_counter() - t0) / args.steps
+    dq = dQ.cpu().numpy().reshape(-1, 3)
+    rms_move = float(np.sqrt(np.mean(dq[:, :2] ** 2)) / wl.a)
     # one more step with per-kernel events for the breakdown (outside the timed steps;
     # events bracket every launch and keep graphs off)
     ctx.set_timing(True)
-    ctx.step_em_rfd(wl.dt, delta, F, Wr, Wg, Wt, dQ)
+    ctx.step_em_rfd(wl.dt, delta, F, None, None, None, dQ, apply=True)
     kt = {k: ctx.kernel_time(k) for k in KERNEL_CLASSES}
     ctx.set_timing(False)
     matvecs = (sum(i["gmres_iters"] + i["gmres_solves"] + 1 for i in infos) + sum(i["lanczos_iters"] for i in infos))
@@ -165,6 +171,9 @@ def run_form(name, form, wl, args, fb, W, np, torch):
         "matvec": {"value": N / t_mv / 1e6, "unit": "Mnodes/s", "ms": 1e3 * t_mv},
         "solver": {"gmres_iters_per_solve": sum(i["gmres_iters"] for i in infos)
                    / max(1, sum(i["gmres_solves"] for i in infos)),
+                   "gmres_iters_per_step": [i["gmres_iters"] for i in infos],
+                   "lanczos_iters_per_step": [i["lanczos_iters"] for i in infos],
+                   "rms_displacement_over_a": rms_move,
                    "lanczos_iters": sum(i["lanczos_iters"] for i in infos) / args.steps,
                    "matvecs_per_step": matvecs / args.steps,
                    "max_residual": max(i["gmres_residual"] for i in infos)},

@@ -110,6 +110,7 @@ typedef struct {
   int32_t lanczos_maxiter; /* Lanczos iteration limit (0: 200) */
   int32_t tile;          /* spreading tile edge in grid points (0: choose) */
   uint32_t flags;        /* FBIM_FLAG_* bits */
+  uint64_t seed;         /* key of the context's noise generator (fbim_noise_normals) */
 } fbim_params;
 
 /* Derived quantities reported back by fbim_get_derived. */
@@ -199,11 +200,16 @@ fbim_status fbim_mobility(fbim_ctx *ctx, const double *F, const double *slip, do
 
 /* U = N F + sqrt(2 kT/dt) N^(1/2) W (eqs. 2.4 and 3.9), with the slip
  * sqrt(2 kT/dt) (v^(r) + v^(w)) built from DEVICE W_r[2N] and W_grid[2 M M]
- * standard normals (eq. 3.27). */
+ * standard normals (eq. 3.27).  A NULL W_r or W_grid is drawn by the
+ * context's generator (fbim_noise_normals, streams FBIM_NOISE_W_R and
+ * FBIM_NOISE_W_GRID) at the draw counter fbim_noise_counter reports, which the
+ * call then advances by one. */
 fbim_status fbim_brownian_velocity(fbim_ctx *ctx, double dt, const double *F, const double *W_r,
                                    const double *W_grid, double *U, fbim_info *info);
 
-/* One Euler-Maruyama step with the centred random finite difference (eq. 4.3):
+/* One Euler-Maruyama step with the centred random finite difference (eq. 4.3)
+ * (noise pointers that are NULL are drawn as in fbim_brownian_velocity, W_tilde
+ * from stream FBIM_NOISE_W_TILDE, all at one draw counter):
  *   dQ = dt U0 + dt kT/delta [N(Q + delta/2 Wt) Wt - N(Q - delta/2 Wt) Wt]
  * with U0 from fbim_brownian_velocity at Q.  Without FBIM_FLAG_BATCH_RFD the solve
  * at Q - delta/2 Wt starts from the solution at Q + delta/2 Wt (same right-hand
@@ -214,6 +220,29 @@ fbim_status fbim_brownian_velocity(fbim_ctx *ctx, double dt, const double *F, co
 fbim_status fbim_step_em_rfd(fbim_ctx *ctx, double dt, double delta, const double *F,
                              const double *W_r, const double *W_grid, const double *W_tilde,
                              double *dQ, int32_t apply, fbim_info *info);
+
+/* ---- Noise ----------------------------------------------------------------
+ * The method consumes independent standard normals (W^(r), W^(w): Sections
+ * 3.1 and 3.3; W, W~: Section 4.4).  Each context carries a counter-based
+ * generator keyed by fbim_params.seed: element i of stream s at draw counter k
+ * is a pure function of (seed, s, k, i), so draws are reproducible on any
+ * device and in any order.  Definition: Philox4x32-10 (Salmon, Moraes, Dror,
+ * Shaw, SC'11) with counter words (i / 2, s, k mod 2^32, k / 2^32) and key
+ * words (seed mod 2^32, seed / 2^32) gives (x0, x1, x2, x3);
+ * u1 = ((x0 2^32 + x1) / 2^11 (integer division) + 1) 2^-53 in (0, 1],
+ * u2 = ((x2 2^32 + x3) / 2^11) 2^-53 in [0, 1);
+ * element 2j = sqrt(-2 ln u1) cos(2 pi u2), element 2j + 1 = sqrt(-2 ln u1)
+ * sin(2 pi u2) for pair j (Box-Muller).  n / 2 must stay below 2^32. */
+enum { FBIM_NOISE_W_R = 0, FBIM_NOISE_W_GRID = 1, FBIM_NOISE_W_TILDE = 2 };
+/* DEVICE out[n] <- standard normals of stream `stream` at draw `counter`. */
+fbim_status fbim_noise_normals(fbim_ctx *ctx, uint32_t stream, uint64_t counter, size_t n, double *out);
+/* DEVICE out[4 n_pairs] <- the raw Philox words (x0, x1, x2, x3) of pairs
+ * j < n_pairs behind those normals (for verification of the generator). */
+fbim_status fbim_noise_words(fbim_ctx *ctx, uint32_t stream, uint64_t counter, size_t n_pairs, uint32_t *out);
+/* HOST *counter <- the draw counter the next call with NULL noise will use
+ * (0 for a new context); fbim_set_noise_counter sets it (to resume a run). */
+fbim_status fbim_noise_counter(const fbim_ctx *ctx, uint64_t *counter);
+fbim_status fbim_set_noise_counter(fbim_ctx *ctx, uint64_t counter);
 
 /* Host utility (no device needed): derive parameters as fbim_create does.
  * Writes the derived values into *out; returns FBIM_EINVAL on bad input. */
@@ -263,7 +292,8 @@ fbim_status fbim_batch_mobility(fbim_batch *batch, const double *const *F, const
 
 /* One EM-RFD step (eq. 4.3) of every member, with the three mobility solves of
  * every member (at Q, Q + delta/2 Wt, Q - delta/2 Wt) in one batched GMRES.
- * Arguments as fbim_step_em_rfd, as HOST arrays of S DEVICE pointers. */
+ * Arguments as fbim_step_em_rfd, as HOST arrays of S DEVICE pointers; a NULL
+ * noise array, or a NULL entry, is drawn by that member's generator. */
 fbim_status fbim_batch_step_em_rfd(fbim_batch *batch, double dt, double delta, const double *const *F,
                                    const double *const *W_r, const double *const *W_grid,
                                    const double *const *W_tilde, double *const *dQ, int32_t apply,

@@ -20,6 +20,7 @@ PART_REAL, PART_ALPERT, PART_WAVE, PART_ALL = 1, 2, 4, 7
 FLAG_SELECTIVE_REORTH, FLAG_BATCH_RFD, FLAG_GRAPH, FLAG_REFINEMENT, FLAG_LIBRARY_FFT, FLAG_BASIS32 = 1, 2, 4, 8, 16, 32
 BATCH_GRAPH = 1
 PREC_FP64, PREC_MIXED = 0, 1
+NOISE_W_R, NOISE_W_GRID, NOISE_W_TILDE = 0, 1, 2
 MLP_IN, MLP_HID, MLP_OUT = 32, 128, 6
 MLP_NPARAM = 32 * 128 + 128 + 128 * 128 + 128 + 128 * 6 + 6
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EOVERLAP", 4: "ENOCONV", 5: "EDEVICE", 6: "ENOTSUP",
@@ -39,7 +40,7 @@ class Params(ctypes.Structure):
                 ("alpert_order", ctypes.c_int32), ("n_box", ctypes.c_int32), ("grid_M", ctypes.c_int32),
                 ("P", ctypes.c_int32), ("precision", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
                 ("gmres_maxiter", ctypes.c_int32), ("lanczos_maxiter", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
 
 
 class Derived(ctypes.Structure):
@@ -123,6 +124,10 @@ def _load():
         "fbim_batch_apply_M": (i32, [p, p, p]),
         "fbim_batch_mobility": (i32, [p, p, p, p, P(Info)]),
         "fbim_batch_step_em_rfd": (i32, [p, d, d, p, p, p, p, p, i32, P(Info)]),
+        "fbim_noise_normals": (i32, [p, u32, ctypes.c_uint64, ctypes.c_size_t, p]),
+        "fbim_noise_words": (i32, [p, u32, ctypes.c_uint64, ctypes.c_size_t, p]),
+        "fbim_noise_counter": (i32, [p, P(ctypes.c_uint64)]),
+        "fbim_set_noise_counter": (i32, [p, ctypes.c_uint64]),
         "fbim_set_timing": (i32, [p, i32]),
         "fbim_kernel_time": (i32, [p, ctypes.c_char_p, P(d), P(ctypes.c_int64)]),
     }
@@ -183,6 +188,11 @@ def _dptr(t, n=None):
     if n is not None and t.numel() != n:
         raise ValueError("expected %d elements, got %d" % (n, t.numel()))
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _optr(t, n=None):
+    """_dptr, or a NULL pointer for None."""
+    return None if t is None else _dptr(t, n)
 
 
 def _fptr(t, n=None):
@@ -280,20 +290,43 @@ class Context:
         return info.as_dict()
 
     def brownian_velocity(self, dt, F, W_r, W_grid, U):
+        """W_r / W_grid None: drawn by the context's generator."""
         M = self.get_derived()["grid_M"]
         info = Info()
-        self._check(lib.fbim_brownian_velocity(self._ctx, dt, _dptr(F, 3 * self.n), _dptr(W_r, 2 * self.N),
-                                               _dptr(W_grid, 2 * M * M), _dptr(U, 3 * self.n),
+        self._check(lib.fbim_brownian_velocity(self._ctx, dt, _dptr(F, 3 * self.n), _optr(W_r, 2 * self.N),
+                                               _optr(W_grid, 2 * M * M), _dptr(U, 3 * self.n),
                                                ctypes.byref(info)))
         return info.as_dict()
 
     def step_em_rfd(self, dt, delta, F, W_r, W_grid, W_tilde, dQ, apply=False):
+        """Noise arguments that are None are drawn by the context's generator."""
         M = self.get_derived()["grid_M"]
         info = Info()
-        self._check(lib.fbim_step_em_rfd(self._ctx, dt, delta, _dptr(F, 3 * self.n), _dptr(W_r, 2 * self.N),
-                                         _dptr(W_grid, 2 * M * M), _dptr(W_tilde, 3 * self.n),
+        self._check(lib.fbim_step_em_rfd(self._ctx, dt, delta, _dptr(F, 3 * self.n), _optr(W_r, 2 * self.N),
+                                         _optr(W_grid, 2 * M * M), _optr(W_tilde, 3 * self.n),
                                          _dptr(dQ, 3 * self.n), 1 if apply else 0, ctypes.byref(info)))
         return info.as_dict()
+
+    # -- noise
+    def noise_normals(self, stream, counter, out):
+        self._check(lib.fbim_noise_normals(self._ctx, stream, counter, out.numel(), _dptr(out)))
+
+    def noise_words(self, stream, counter, out):
+        """out: int32 GPU tensor of 4 n_pairs elements (the 32-bit words, reinterpreted)."""
+        import torch
+        if not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != torch.int32 or \
+                not out.is_contiguous() or out.numel() % 4:
+            raise TypeError("expected a contiguous int32 GPU tensor of 4 n_pairs elements")
+        self._check(lib.fbim_noise_words(self._ctx, stream, counter, out.numel() // 4,
+                                         ctypes.c_void_p(out.data_ptr())))
+
+    def noise_counter(self):
+        v = ctypes.c_uint64()
+        self._check(lib.fbim_noise_counter(self._ctx, ctypes.byref(v)))
+        return v.value
+
+    def set_noise_counter(self, counter):
+        self._check(lib.fbim_set_noise_counter(self._ctx, counter))
 
     # -- learned preconditioner correction
     def mlp_init(self, seed=0, sym_order=1):
@@ -411,7 +444,10 @@ class Batch:
         m = self.members
         info = (Info * len(m))()
         Ms = [c.get_derived()["grid_M"] for c in m]
-        arr = lambda xs, sizes: _ptr_array([_dptr(x, k).value for x, k in zip(xs, sizes)], lambda v: v)  # noqa: E731
+        def arr(xs, sizes):  # None (or None entries): drawn by the member's generator
+            if xs is None:
+                return None
+            return _ptr_array([None if x is None else _dptr(x, k).value for x, k in zip(xs, sizes)], lambda v: v)
         self._check(lib.fbim_batch_step_em_rfd(
             self._b, dt, delta, arr(Fs, [3 * c.n for c in m]), arr(W_rs, [2 * c.N for c in m]),
             arr(W_grids, [2 * M * M for M in Ms]), arr(W_tildes, [3 * c.n for c in m]),

@@ -815,7 +815,10 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
   std::vector<double> nb2;
   EST(norms_b(E, *T, rhs(*T), nb2));
   std::vector<double> nb(S0);
-  for (int i = 0; i < S0; ++i) nb[i] = std::sqrt(std::max(nb2[i], 0.0));
+  for (int i = 0; i < S0; ++i) {
+    if (!std::isfinite(nb2[i])) return efail(E, FBIM_EINVAL, "non-finite right-hand side in a batch system");
+    nb[i] = std::sqrt(std::max(nb2[i], 0.0));
+  }
   if (!warm) EST(seg_axpby(E, *T, vref(sol(*T)), vref(sol(*T)), T->zeros, T->zeros));  // x = 0
   std::vector<int> running;  // positions in sysl
   for (int i = 0; i < S0; ++i)
@@ -840,6 +843,7 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
     std::vector<double> inv;
     for (size_t q = 0; q < running.size(); ++q) {
       const int i = running[q];
+      if (!std::isfinite(r2[q])) return efail(E, FBIM_EDEVICE, "non-finite GMRES residual in a batch system");
       const double beta = std::sqrt(std::max(r2[q], 0.0));
       relres[i] = beta / nb[i];
       if (relres[i] <= tol[i]) continue;
@@ -904,6 +908,7 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
           col[r + 1] = -sn[i][r] * col[r] + cs[i][r] * col[r + 1];
           col[r] = t1;
         }
+        if (!std::isfinite(hn[q])) return efail(E, FBIM_EDEVICE, "non-finite Krylov vector in a batch system");
         const double den = std::hypot(col[j], col[j + 1]);
         cs[i][j] = den > 0 ? col[j] / den : 1.0;
         sn[i][j] = den > 0 ? col[j + 1] / den : 0.0;
@@ -1176,10 +1181,17 @@ fbim_status em_rfd_batch(BatchEngine *E, const std::vector<fbim_ctx *> &mem, dou
       inf[i].gmres_residual = std::max(inf[i].gmres_residual, res[j]);
       if (sts[j] != FBIM_OK) worst = (fbim_status)sts[j];
     }
-    if (apply) {
+    inf[i].status = sts[i];
+  }
+  if (apply) {
+    // move every member to Q + dQ; if one move is rejected (its context stays at
+    // Q), the members moved before it go back to Q as well
+    for (int i = 0; i < S; ++i) {
+      fbim_ctx *c = mem[i];
+      const size_t n3 = 3 * (size_t)c->n;
       std::vector<double> dq(n3);
-      EHIP(E, hipMemcpyAsync(dq.data(), dQ[i], n3 * sizeof(double), hipMemcpyDeviceToHost, s));
-      EHIP(E, hipStreamSynchronize(s));
+      EHIP(E, hipMemcpyAsync(dq.data(), dQ[i], n3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      EHIP(E, hipStreamSynchronize(c->stream));
       std::vector<double> qs(2 * (size_t)c->n), ths(c->n);
       for (int b = 0; b < c->n; ++b) {
         qs[2 * b] = q0[i][2 * b] + dq[3 * b];
@@ -1187,9 +1199,13 @@ fbim_status em_rfd_batch(BatchEngine *E, const std::vector<fbim_ctx *> &mem, dou
         ths[b] = th0[i][b] + dq[3 * b + 2];
       }
       const fbim_status st = fbim_set_bodies(c, c->n, c->h_shape.data(), qs.data(), ths.data());
-      if (st != FBIM_OK) return efail(E, st, c->err);
+      if (st != FBIM_OK) {
+        const std::string msg = c->err;
+        for (int k = 0; k < i; ++k)
+          fbim_set_bodies(mem[k], mem[k]->n, mem[k]->h_shape.data(), q0[k].data(), th0[k].data());
+        return efail(E, st, msg);
+      }
     }
-    inf[i].status = sts[i];
   }
   EHIP(E, hipStreamSynchronize(E->stream));
   if (info)
@@ -1339,10 +1355,19 @@ fbim_status fbim_batch_step_em_rfd(fbim_batch *b, double dt, double delta, const
                                    const double *const *W_r, const double *const *W_grid,
                                    const double *const *W_tilde, double *const *dQ, int32_t apply,
                                    fbim_info *info) {
-  if (!b || !F || !W_r || !W_grid || !W_tilde || !dQ || !(dt > 0) || !(delta > 0))
-    return bfail(b, FBIM_EINVAL, "invalid arguments");
+  if (!b || !F || !dQ || !(dt > 0) || !(delta > 0)) return bfail(b, FBIM_EINVAL, "invalid arguments");
   const double t0 = fbim::now_ms();
-  const fbim_status st = fbim::em_rfd_batch(b->rfd, b->mem, dt, delta, F, W_r, W_grid, W_tilde, dQ, apply, info);
+  const size_t S = b->mem.size();
+  std::vector<const double *> wr(S), wg(S), wt(S);
+  for (size_t i = 0; i < S; ++i) {
+    wr[i] = W_r ? W_r[i] : nullptr;
+    wg[i] = W_grid ? W_grid[i] : nullptr;
+    wt[i] = W_tilde ? W_tilde[i] : nullptr;
+    const fbim_status sn = fbim::fill_noise(b->mem[i], wr[i], wg[i], &wt[i]);
+    if (sn != FBIM_OK) return bfail(b, sn, b->mem[i]->err);
+  }
+  const fbim_status st =
+      fbim::em_rfd_batch(b->rfd, b->mem, dt, delta, F, wr.data(), wg.data(), wt.data(), dQ, apply, info);
   if (info)
     for (size_t i = 0; i < b->mem.size(); ++i) info[i].ms_total = fbim::now_ms() - t0;
   if (st != FBIM_OK) b->err = b->rfd->err;

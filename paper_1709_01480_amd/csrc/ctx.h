@@ -90,6 +90,10 @@ struct fbim_ctx {
   float *d_X = nullptr, *d_H1 = nullptr, *d_H2 = nullptr, *d_Y = nullptr, *d_dY = nullptr, *d_Z2 = nullptr,
         *d_Z1 = nullptr, *d_ones = nullptr, *d_loss = nullptr;
   double *d_trF = nullptr, *d_trU = nullptr;
+  // body cell list of the MLP features
+  int *d_bc_key = nullptr, *d_bc_perm = nullptr, *d_bc_count = nullptr, *d_bc_cursor = nullptr,
+      *d_bc_start = nullptr;
+  size_t bc_cap_n = 0, bc_cap_c = 0;
   double *d_q = nullptr, *d_theta = nullptr, *d_x = nullptr;
   bool have_bodies = false;
 
@@ -146,6 +150,11 @@ struct fbim_ctx {
   fbim_ctx *rfd[2] = {nullptr, nullptr};     // copies at Q +- delta/2 Wt for batched EM-RFD solves
   fbim::BatchEngine *rfd_engine = nullptr;   // launch set of the batched EM-RFD solves
   double *d_vec_a = nullptr, *d_vec_b = nullptr, *d_U3 = nullptr, *d_U4 = nullptr, *d_U5 = nullptr;
+
+  // noise drawn by the context (NULL noise arguments): draw counter and buffers
+  uint64_t noise_next = 0;
+  double *d_nz_r = nullptr, *d_nz_g = nullptr, *d_nz_t = nullptr;
+  size_t nz_cap_r = 0, nz_cap_g = 0, nz_cap_t = 0;
 
   // timing
   bool timing = false;
@@ -289,6 +298,10 @@ fbim_status norm2(fbim_ctx *c, const double *x, size_t n, double &out);
 fbim_status brownian_slip(fbim_ctx *c, double dt, const double *W_r, const double *W_grid, double *slip_out,
                           fbim_info *info);
 fbim_status setup_fft(fbim_ctx *c);
+// fills the noise arrays a call did not receive (NULL pointers; W_tilde may be
+// null when the call takes none) from the context's generator at one draw
+// counter, which is then advanced; the pointers are redirected to the draws
+fbim_status fill_noise(fbim_ctx *c, const double *&W_r, const double *&W_grid, const double **W_tilde);
 
 // batches (batch_api.hip)
 BatchEngine *engine_new();

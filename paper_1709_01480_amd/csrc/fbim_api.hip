@@ -276,8 +276,29 @@ fbim_status mlp_backward(fbim_ctx *c, const float *X, const float *dY, int n, fl
 }
 
 fbim_status mlp_features(fbim_ctx *c, float *X) {
+  const double r_max = shapes_r_max(c);
+  MlpCells cells;
+  cells.nbc = mlp_body_cells(c->d.L, r_max);
+  const size_t nc = (size_t)cells.nbc * cells.nbc;
+  if (c->n > c->bc_cap_n) {
+    HIPCHK(c, dalloc(c->d_bc_key, (size_t)c->n));
+    HIPCHK(c, dalloc(c->d_bc_perm, (size_t)c->n));
+    c->bc_cap_n = c->n;
+  }
+  if (nc + 1 > c->bc_cap_c) {
+    HIPCHK(c, dalloc(c->d_bc_count, nc + 1));
+    HIPCHK(c, dalloc(c->d_bc_cursor, nc + 1));
+    HIPCHK(c, dalloc(c->d_bc_start, nc + 2));
+    c->bc_cap_c = nc + 1;
+  }
+  cells.key = c->d_bc_key;
+  cells.perm = c->d_bc_perm;
+  cells.count = c->d_bc_count;
+  cells.cursor = c->d_bc_cursor;
+  cells.start = c->d_bc_start;
+  cells.maxcount = c->d_bc_start + nc + 1;
   Timer t(c, "mlp");
-  HIPCHK(c, launch_mlp_features(c->n, c->d_q, c->d_theta, c->d.L, shapes_r_max(c), c->mlp_sym, X, c->stream));
+  HIPCHK(c, launch_mlp_features(c->n, c->d_q, c->d_theta, c->d.L, r_max, c->mlp_sym, cells, X, c->stream));
   return FBIM_OK;
 }
 
@@ -600,6 +621,7 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
   relres = 0;
   double nb;
   STCHK(norm2(c, b, nt, nb));
+  if (!std::isfinite(nb)) return fail(c, FBIM_EINVAL, "non-finite right-hand side");
   if (!warm || nb == 0.0) HIPCHK(c, launch_fill(nt, 0.0, x, s));
   if (nb == 0.0) return FBIM_OK;
   std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), hcol(m + 3), y(m);
@@ -621,6 +643,7 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
     }
     double beta;
     STCHK(norm2(c, c->d_r, nt, beta));
+    if (!std::isfinite(beta)) return fail(c, FBIM_EDEVICE, "non-finite GMRES residual");
     relres = beta / nb;
     if (relres <= tol) return FBIM_OK;
     if (iters >= maxit) return fail(c, FBIM_ENOCONV, "GMRES iteration limit reached");
@@ -640,6 +663,7 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
       STCHK(apply_saddle(c, c->d_t1, w));
       double hn = 0;
       STCHK(orthogonalise(c, c->d_V, j + 1, w, nt, hcol.data(), hn, true));
+      if (!std::isfinite(hn)) return fail(c, FBIM_EDEVICE, "non-finite Krylov vector");
       hcol[j + 1] = hn;
       for (int i = 0; i < j; ++i) {  // previous rotations
         const double t1 = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
@@ -734,6 +758,7 @@ fbim_status lanczos_sqrt(fbim_ctx *c, const double *b, double *out, int &iters, 
   change = 0;
   double beta0;
   STCHK(norm2(c, b, n2, beta0));
+  if (!std::isfinite(beta0)) return fail(c, FBIM_EINVAL, "non-finite Lanczos start vector");
   if (beta0 == 0.0) {
     HIPCHK(c, launch_fill(n2, 0.0, out, s));
     return FBIM_OK;
@@ -751,6 +776,7 @@ fbim_status lanczos_sqrt(fbim_ctx *c, const double *b, double *out, int &iters, 
     HIPCHK(c, launch_body_apply(c->geom(), c->mats(), c->bt, 0, c->d_vec_b, w, s));
     double bk = 0;
     STCHK(orthogonalise(c, c->d_V, k + 1, w, n2, hbuf.data(), bk, true));  // w / bk: next basis vector
+    if (!std::isfinite(bk) || !std::isfinite(hbuf[k])) return fail(c, FBIM_EDEVICE, "non-finite Lanczos vector");
     alpha.push_back(hbuf[k]);
     // coefficients c = beta0 Q sqrt(max(L, 0)) Q^T e1 of the (k+1) x (k+1) tridiagonal
     const int m = k + 1;
@@ -791,6 +817,43 @@ fbim_status lanczos_sqrt(fbim_ctx *c, const double *b, double *out, int &iters, 
   }
   HIPCHK(c, launch_body_apply(c->geom(), c->mats(), c->bt, 1, c->d_vec_a, out, s));
   return st;
+}
+
+fbim_status fill_noise(fbim_ctx *c, const double *&W_r, const double *&W_grid, const double **W_tilde) {
+  const bool need_t = W_tilde && !*W_tilde;
+  if (W_r && W_grid && !need_t) return FBIM_OK;
+  const uint64_t k = c->noise_next;
+  hipStream_t s = c->stream;
+  const uint64_t seed = c->p.seed;
+  if (!W_r) {
+    const size_t n = 2 * (size_t)c->N;
+    if (n > c->nz_cap_r) {
+      HIPCHK(c, dalloc(c->d_nz_r, n));
+      c->nz_cap_r = n;
+    }
+    HIPCHK(c, launch_normals(seed, FBIM_NOISE_W_R, k, n, c->d_nz_r, s));
+    W_r = c->d_nz_r;
+  }
+  if (!W_grid) {
+    const size_t n = 2 * (size_t)c->d.M * c->d.M;
+    if (n > c->nz_cap_g) {
+      HIPCHK(c, dalloc(c->d_nz_g, n));
+      c->nz_cap_g = n;
+    }
+    HIPCHK(c, launch_normals(seed, FBIM_NOISE_W_GRID, k, n, c->d_nz_g, s));
+    W_grid = c->d_nz_g;
+  }
+  if (need_t) {
+    const size_t n = 3 * (size_t)c->n;
+    if (n > c->nz_cap_t) {
+      HIPCHK(c, dalloc(c->d_nz_t, n));
+      c->nz_cap_t = n;
+    }
+    HIPCHK(c, launch_normals(seed, FBIM_NOISE_W_TILDE, k, n, c->d_nz_t, s));
+    *W_tilde = c->d_nz_t;
+  }
+  c->noise_next = k + 1;
+  return FBIM_OK;
 }
 
 // warm: start GMRES from the solution of the previous solve of this context
@@ -991,7 +1054,7 @@ void fbim_destroy(fbim_ctx *c) {
                   c->d_mut, c->d_src32, c->d_xt32, c->d_mut32, c->d_grid, c->d_spec, c->d_grid32,
                   c->d_spec32, c->d_e1tab, c->d_e1tab32, c->d_V, c->d_w, c->d_t1, c->d_t2, c->d_b, c->d_x2,
                   c->d_r, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
-                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU, c->d_bx, c->d_by, c->d_tw, c->d_tw32, c->d_ey, c->d_ey32, c->d_scount, c->d_sstart, c->d_slist};
+                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU, c->d_bx, c->d_by, c->d_tw, c->d_tw32, c->d_ey, c->d_ey32, c->d_scount, c->d_sstart, c->d_slist, c->d_nz_r, c->d_nz_g, c->d_nz_t, c->d_bc_key, c->d_bc_perm, c->d_bc_count, c->d_bc_cursor, c->d_bc_start};
   pub_free(c->pub);
   engine_delete(c->rfd_engine);
   for (fbim_ctx *r : c->rfd)
@@ -1052,10 +1115,21 @@ fbim_status fbim_set_bodies(fbim_ctx *c, int32_t n, const int32_t *shape_id, con
   const int N = off[n];
   if (N >= (1 << 30) / 4) return fail(c, FBIM_EINVAL, "too many nodes");
   if (c->have_bodies && n == c->n && std::equal(shape_id, shape_id + n, c->h_shape.begin())) {
-    // same bodies moved: only positions and angles change
+    // same bodies moved: only positions and angles change.  A rejected move
+    // (overlap, device error) rebuilds the previous configuration, so the
+    // context stays where it was.
+    std::vector<double> q_old = c->h_q, th_old = c->h_theta;
     c->h_q.assign(q, q + 2 * n);
     c->h_theta.assign(theta, theta + n);
-    return build_geometry(c);
+    const fbim_status st = build_geometry(c);
+    if (st != FBIM_OK) {
+      const std::string msg = c->err;
+      c->h_q.swap(q_old);
+      c->h_theta.swap(th_old);
+      if (build_geometry(c) != FBIM_OK) c->have_bodies = false;
+      c->err = msg;
+    }
+    return st;
   }
   const bool realloc_n = n != c->capn, realloc_N = N != c->capN;
   c->h_shape.assign(shape_id, shape_id + n);
@@ -1106,7 +1180,9 @@ fbim_status fbim_set_bodies(fbim_ctx *c, int32_t n, const int32_t *shape_id, con
   STCHK(build_body_tiles(c));
   c->have_bodies = true;
   STCHK(ensure_krylov(c));
-  return build_geometry(c);
+  const fbim_status st = build_geometry(c);
+  if (st != FBIM_OK) c->have_bodies = false;  // a new body set that failed leaves no bodies
+  return st;
 }
 
 fbim_status fbim_get_derived(const fbim_ctx *c, fbim_derived *out) {
@@ -1185,9 +1261,10 @@ fbim_status fbim_mobility(fbim_ctx *c, const double *F, const double *slip, doub
 
 fbim_status fbim_brownian_velocity(fbim_ctx *c, double dt, const double *F, const double *W_r,
                                    const double *W_grid, double *U, fbim_info *info) {
-  if (!c || !F || !W_r || !W_grid || !U || !(dt > 0) || !c->have_bodies) return fail(c, FBIM_EINVAL, "invalid arguments");
+  if (!c || !F || !U || !(dt > 0) || !c->have_bodies) return fail(c, FBIM_EINVAL, "invalid arguments");
   info_reset(info);
   const double t0 = now_ms();
+  STCHK(fill_noise(c, W_r, W_grid, nullptr));
   fbim_status st = brownian(c, dt, F, W_r, W_grid, U, info);
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (info) {
@@ -1200,10 +1277,11 @@ fbim_status fbim_brownian_velocity(fbim_ctx *c, double dt, const double *F, cons
 fbim_status fbim_step_em_rfd(fbim_ctx *c, double dt, double delta, const double *F, const double *W_r,
                              const double *W_grid, const double *W_tilde, double *dQ, int32_t apply,
                              fbim_info *info) {
-  if (!c || !F || !W_r || !W_grid || !W_tilde || !dQ || !(dt > 0) || !(delta > 0) || !c->have_bodies)
+  if (!c || !F || !dQ || !(dt > 0) || !(delta > 0) || !c->have_bodies)
     return fail(c, FBIM_EINVAL, "invalid arguments");
   info_reset(info);
   const double t0 = now_ms();
+  STCHK(fill_noise(c, W_r, W_grid, &W_tilde));
   if (c->p.flags & FBIM_FLAG_BATCH_RFD) {
     // the three solves in one lockstep batch with two copies of the context
     if (!c->rfd_engine) c->rfd_engine = engine_new();
@@ -1217,12 +1295,26 @@ fbim_status fbim_step_em_rfd(fbim_ctx *c, double dt, double delta, const double 
   hipStream_t s = c->stream;
   const int n = c->n;
   const size_t n3 = 3 * (size_t)n;
+  std::vector<double> wt(n3), q0 = c->h_q, th0 = c->h_theta, qs(2 * n), ths(n);
+  std::vector<int> sid = c->h_shape;
+  // any error after the configuration has left Q puts the bodies back at Q
+  struct BackToQ {
+    fbim_ctx *c;
+    const std::vector<int> &sid;
+    const std::vector<double> &q, &th;
+    bool armed = true;
+    ~BackToQ() {
+      if (!armed) return;
+      const std::string msg = c->err;
+      if (c->have_bodies && (c->h_q != q || c->h_theta != th))
+        fbim_set_bodies(c, (int)th.size(), sid.data(), q.data(), th.data());
+      c->err = msg;
+    }
+  } guard{c, sid, q0, th0};
   // U0 = N F + sqrt(2kT/dt) N^(1/2) W at Q
   fbim_status st = brownian(c, dt, F, W_r, W_grid, c->d_U3, info);
   if (st != FBIM_OK && st != FBIM_ENOCONV) return st;
   fbim_status worst = st;
-  std::vector<double> wt(n3), q0 = c->h_q, th0 = c->h_theta, qs(2 * n), ths(n);
-  std::vector<int> sid = c->h_shape;
   HIPCHK(c, hipMemcpyAsync(wt.data(), W_tilde, n3 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   // RFD solves N(Q +- delta/2 Wt) Wt
@@ -1263,12 +1355,39 @@ fbim_status fbim_step_em_rfd(fbim_ctx *c, double dt, double delta, const double 
   } else {
     STCHK(fbim_set_bodies(c, n, sid.data(), q0.data(), th0.data()));
   }
+  guard.armed = false;
   HIPCHK(c, hipStreamSynchronize(s));
   if (info) {
     info->status = worst;
     info->ms_total = now_ms() - t0;
   }
   return worst;
+}
+
+fbim_status fbim_noise_normals(fbim_ctx *c, uint32_t stream, uint64_t counter, size_t n, double *out) {
+  if (!c || (!out && n)) return fail(c, FBIM_EINVAL, "invalid arguments");
+  if ((n + 1) / 2 > 0xFFFFFFFFull) return fail(c, FBIM_EINVAL, "too many normals in one draw");
+  HIPCHK(c, launch_normals(c->p.seed, stream, counter, n, out, c->stream));
+  return FBIM_OK;
+}
+
+fbim_status fbim_noise_words(fbim_ctx *c, uint32_t stream, uint64_t counter, size_t n_pairs, uint32_t *out) {
+  if (!c || (!out && n_pairs)) return fail(c, FBIM_EINVAL, "invalid arguments");
+  if (n_pairs > 0xFFFFFFFFull) return fail(c, FBIM_EINVAL, "too many pairs in one draw");
+  HIPCHK(c, launch_philox_words(c->p.seed, stream, counter, n_pairs, out, c->stream));
+  return FBIM_OK;
+}
+
+fbim_status fbim_noise_counter(const fbim_ctx *c, uint64_t *counter) {
+  if (!c || !counter) return FBIM_EINVAL;
+  *counter = c->noise_next;
+  return FBIM_OK;
+}
+
+fbim_status fbim_set_noise_counter(fbim_ctx *c, uint64_t counter) {
+  if (!c) return FBIM_EINVAL;
+  c->noise_next = counter;
+  return FBIM_OK;
 }
 
 fbim_status fbim_mlp_init(fbim_ctx *c, uint64_t seed, int32_t sym_order) {

@@ -294,6 +294,13 @@ hipError_t launch_vec_add(int k, const double *a, double *b, hipStream_t s);  //
 hipError_t launch_cast_f32(size_t n, const double *x, float *y, hipStream_t s);
 hipError_t launch_fill(size_t n, double v, double *y, hipStream_t s);
 
+// counter-based standard normals (kernels_rng.hip): out[i] for i < n of stream
+// `stream` at draw `counter` (Philox4x32-10 keyed by seed, Box-Muller)
+hipError_t launch_normals(uint64_t seed, uint32_t stream, uint64_t counter, size_t n, double *out, hipStream_t s);
+// the raw Philox output words behind them: out[4 j .. 4 j + 3] of pair j < npairs
+hipError_t launch_philox_words(uint64_t seed, uint32_t stream, uint64_t counter, size_t npairs, uint32_t *out,
+                               hipStream_t s);
+
 // ---------------------------------------------------------------- batched launches
 // Several independent systems (suspensions) go through one launch per stage:
 // system s owns blocks [begin[s], begin[s+1]) of the grid, and each block reads
@@ -384,9 +391,15 @@ hipError_t launch_precond_batch(const PrecondJob *jobs, BatchGrid bg, size_t lds
 
 // learned preconditioner correction (MLP 32 -> 128 -> 128 -> 6, tanh)
 constexpr int kMlpNeighbours = 6, kMlpIn = 32, kMlpHid = 128, kMlpOut = 6;
-// features [n][32] of each body's neighbourhood in its body frame
+// features [n][32] of each body's neighbourhood in its body frame, found on a
+// cell list of the bodies (cells of side >= 3 r_max; device scratch below)
+struct MlpCells {
+  int nbc;  // cells per side (mlp_body_cells)
+  int *key, *count, *cursor, *start, *perm, *maxcount;  // [n], [nbc^2] x 2, [nbc^2 + 1], [n], [1]
+};
+int mlp_body_cells(double L, double r_max);
 hipError_t launch_mlp_features(int n, const double *q, const double *theta, double L, double r_max, int sym,
-                               float *X, hipStream_t s);
+                               const MlpCells &cells, float *X, hipStream_t s);
 enum { kGemmStore = 0, kGemmBiasTanh = 1, kGemmBias = 2, kGemmAtomic = 3, kGemmTanhGrad = 4 };
 // C = op(A) op(B) in BF16 MFMA with FP32 accumulation; epilogues: store, tanh(. + bias[j]),
 // . + bias[j], atomic add (split K), . * (1 - aux[i][j]^2) (aux has leading dimension ldc)

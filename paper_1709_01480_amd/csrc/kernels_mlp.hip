@@ -9,6 +9,9 @@
 // forces F with independent unit components, the mobility solve gives U = N F,
 // and E[U_b F_b^T] = N_bb, the body's own mobility block in the suspension, so
 // least squares of (N_ref + dN_b) F_b against U_b targets N_bb - N_ref.
+#include <algorithm>
+#include <cmath>
+
 #include "kernels.h"
 
 namespace fbim {
@@ -28,12 +31,27 @@ __device__ inline short to_bf16(float f) {
 }  // namespace
 
 // ------------------------------------------------------------------ features
-// One thread per body, all other bodies scanned (features are built once per
-// configuration).  Neighbours: bodies whose centre lies within R_nb = 3 r_max
-// (minimum image), nearest first (ties by index), at most kMlpNeighbours.
+// Neighbours: bodies whose centre lies within R_nb = 3 r_max (minimum image),
+// nearest first (ties by index), at most kMlpNeighbours.  Bodies are binned
+// into cells of side >= R_nb (k_body_keys, then the generic scan and scatter),
+// and one thread per body visits the 3 x 3 cells around its own (all bodies
+// when there are fewer than three cells per side).  The order of the visit
+// does not matter: the neighbour ranking is a total order.
+__global__ void k_body_keys(int n, const double *__restrict__ q, double L, int nbc, int *__restrict__ key,
+                            int *__restrict__ count) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  double x = q[2 * b] - L * floor(q[2 * b] / L), y = q[2 * b + 1] - L * floor(q[2 * b + 1] / L);
+  const int cx = min(max((int)(x * nbc / L), 0), nbc - 1), cy = min(max((int)(y * nbc / L), 0), nbc - 1);
+  key[b] = cy * nbc + cx;
+  atomicAdd(&count[cy * nbc + cx], 1);
+}
+
 __global__ __launch_bounds__(256) void k_mlp_features(int n, const double *__restrict__ q,
                                                       const double *__restrict__ theta, double L, double r_max,
-                                                      int sym, float *__restrict__ X) {
+                                                      int sym, int nbc, const int *__restrict__ key,
+                                                      const int *__restrict__ start, const int *__restrict__ perm,
+                                                      float *__restrict__ X) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n) return;
   const double R = 3.0 * r_max;
@@ -46,30 +64,37 @@ __global__ __launch_bounds__(256) void k_mlp_features(int n, const double *__res
     bi[k] = -1;
   }
   int count = 0;
-  for (int c = 0; c < n; ++c) {
-    if (c == b) continue;
-    double dx = q[2 * c] - qx, dy = q[2 * c + 1] - qy;
-    dx -= L * rint(dx / L);
-    dy -= L * rint(dy / L);
-    const double d = sqrt(dx * dx + dy * dy);
-    if (d >= R) continue;
-    ++count;
-    // insert (d, c) into the sorted list
-    double cd = d;
-    int ci = c;
+  const int kb = key[b], bx = kb % nbc, by = kb / nbc;
+  const int span = nbc >= 3 ? 1 : 0;  // fewer than three cells: one cell holds everything
+  for (int oy = -span; oy <= span; ++oy)
+    for (int ox = -span; ox <= span; ++ox) {
+      const int cell = ((by + oy + nbc) % nbc) * nbc + (bx + ox + nbc) % nbc;
+      for (int e = start[cell]; e < start[cell + 1]; ++e) {
+        const int c = perm[e];
+        if (c == b) continue;
+        double dx = q[2 * c] - qx, dy = q[2 * c + 1] - qy;
+        dx -= L * rint(dx / L);
+        dy -= L * rint(dy / L);
+        const double d = sqrt(dx * dx + dy * dy);
+        if (d >= R) continue;
+        ++count;
+        // insert (d, c) into the sorted list
+        double cd = d;
+        int ci = c;
 #pragma unroll
-    for (int k = 0; k < kMlpNeighbours; ++k) {
-      const bool less = cd < bd[k] || (cd == bd[k] && ci < bi[k]);
-      if (less) {
-        const double td = bd[k];
-        const int ti = bi[k];
-        bd[k] = cd;
-        bi[k] = ci;
-        cd = td;
-        ci = ti;
+        for (int k = 0; k < kMlpNeighbours; ++k) {
+          const bool less = cd < bd[k] || (cd == bd[k] && ci < bi[k]);
+          if (less) {
+            const double td = bd[k];
+            const int ti = bi[k];
+            bd[k] = cd;
+            bi[k] = ci;
+            cd = td;
+            ci = ti;
+          }
+        }
       }
     }
-  }
   double sn, cs;
   sincos(theta[b], &sn, &cs);
   float *f = X + (size_t)b * kMlpIn;
@@ -98,10 +123,25 @@ __global__ __launch_bounds__(256) void k_mlp_features(int n, const double *__res
   f[31] = (float)fmin(2.0, fmax(-2.0, (dmin - 2.0 * r_max) / r_max));
 }
 
+int mlp_body_cells(double L, double r_max) {
+  const int nbc = (int)std::floor(L / (3.0 * r_max));
+  return nbc >= 3 ? std::min(nbc, 256) : 1;  // cells of side >= R_nb; the scan is one work group
+}
+
 hipError_t launch_mlp_features(int n, const double *q, const double *theta, double L, double r_max, int sym,
-                               float *X, hipStream_t s) {
+                               const MlpCells &cells, float *X, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mlp_features, dim3((n + 255) / 256), dim3(256), 0, s, n, q, theta, L, r_max, sym, X);
+  const int nbc = cells.nbc, nc = nbc * nbc;
+  hipError_t e = launch_fill_int((size_t)nc, 0, cells.count, s);
+  if (e != hipSuccess) return e;
+  e = launch_fill_int((size_t)nc, 0, cells.cursor, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_body_keys, dim3((n + 255) / 256), dim3(256), 0, s, n, q, L, nbc, cells.key, cells.count);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_scan(nc, cells.count, cells.start, cells.maxcount, s)) != hipSuccess) return e;
+  if ((e = launch_scatter(n, cells.key, cells.start, cells.cursor, cells.perm, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mlp_features, dim3((n + 255) / 256), dim3(256), 0, s, n, q, theta, L, r_max, sym, nbc,
+                     cells.key, cells.start, cells.perm, X);
   return hipGetLastError();
 }
 

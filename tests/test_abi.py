@@ -98,3 +98,20 @@ def test_uneven_suspension_draws_are_valid_systems():
     # the draw is seeded: the same call gives the same systems
     again = W.uneven_suspensions(16)
     assert all(np.array_equal(a.q, b.q) and a.n_p == b.n_p for a, b in zip(wls, again))
+
+
+def test_params_struct_layout_matches_header(tmp_path):
+    # the binding's ctypes structures have the C compiler's size and field offsets
+    src = tmp_path / "layout.c"
+    fields = [f for f, _ in fb.Params._fields_]
+    body = "\n".join('  printf("%%zu ", offsetof(fbim_params, %s));' % f for f in fields)
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "fbim.h"\nint main(void) {\n%s\n'
+                   '  printf("%%zu %%zu %%zu\\n", sizeof(fbim_params), sizeof(fbim_info), sizeof(fbim_derived));\n'
+                   '  return 0;\n}\n' % body)
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    offs = [getattr(fb.Params, f).offset for f in fields]
+    assert vals[:len(fields)] == offs
+    assert vals[len(fields):] == [ctypes.sizeof(fb.Params), ctypes.sizeof(fb.Info), ctypes.sizeof(fb.Derived)]

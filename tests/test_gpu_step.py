@@ -1,0 +1,125 @@
+"""The EM-RFD step's update half (Q^{n+1} = Q^n + dQ, eq. 4.3) and the error
+paths around it: moved configurations against the oracle, rejected moves that
+leave the bodies where they were, and the solver's error reports."""
+import numpy as np
+import pytest
+
+from gpu_util import dev, host, log, make_ctx, oracle_params, relerr, workload, zeros
+from oracle import fbim as OF
+
+pytestmark = pytest.mark.gpu
+TIGHT = dict(tol_gmres=1e-12, tol_lanczos=1e-12)
+
+
+def nodes_of(ctx, wl):
+    x = zeros(2 * wl.n_nodes)
+    ctx.get_nodes(x)
+    return host(x)
+
+
+def oracle_nodes(geo, L):
+    X, _ = OF.nodes(geo)
+    return np.mod(X, L).ravel()
+
+
+def wrapped_diff(a, b, L):
+    d = a - b
+    return np.max(np.abs(d - L * np.round(d / L)))
+
+
+@pytest.mark.parametrize("name,flags", [("tiny2", 0), ("starfish4", 0), ("starfish4", "batch")])
+def test_apply_moves_bodies_to_Q_plus_dQ(name, flags):
+    import paper_1709_01480_amd as fb
+    wl = workload(name)
+    log("apply step %s %s" % (name, flags))
+    fl = (fb.FLAG_BATCH_RFD | fb.FLAG_GRAPH) if flags == "batch" else 0
+    ctx = make_ctx(wl, flags=fl, seed=3, **TIGHT)
+    geo = OF.geometry_from_workload(wl)
+    prm = oracle_params(wl)
+    delta = wl.a * 1e-2
+    dQ = zeros(3 * wl.n_bodies)
+    ctx.step_em_rfd(wl.dt, delta, dev(wl.F), None, None, None, dQ, apply=True)
+    dq = host(dQ)
+    g1 = OF.moved(geo, dq)
+    # node positions of the moved configuration
+    assert wrapped_diff(nodes_of(ctx, wl), oracle_nodes(g1, wl.L), wl.L) < 1e-13
+    # and the operator there: mobility at Q + dQ against the dense oracle
+    U = zeros(3 * wl.n_bodies)
+    ctx.mobility(dev(wl.F), U)
+    Uo, _ = OF.DenseFBIM(g1, prm, order=wl.alpert_order).mobility(wl.F)
+    assert relerr(host(U), Uo) < 1e-6
+
+
+def test_rejected_move_keeps_configuration():
+    import paper_1709_01480_amd as fb
+    wl = workload("starfish4")
+    ctx = make_ctx(wl)
+    x0 = nodes_of(ctx, wl)
+    q = wl.q.copy()
+    q[1] = q[0]  # body 1 on top of body 0, same angle: coincident nodes
+    th = wl.theta.copy()
+    th[1] = th[0]
+    with pytest.raises(fb.FbimError) as e:
+        ctx.set_bodies(np.zeros(wl.n_bodies, dtype=np.int32), q, th)
+    assert e.value.status == 3
+    assert np.array_equal(nodes_of(ctx, wl), x0)
+    U = zeros(3 * wl.n_bodies)
+    ctx.mobility(dev(wl.F), U)  # still usable
+
+
+@pytest.mark.parametrize("batch", [False, True])
+def test_step_rejected_at_rfd_configuration_stays_at_Q(batch):
+    # W~ that puts body 0 onto body 1 in the configuration Q + delta/2 W~: the
+    # step fails with EOVERLAP and the bodies stay at Q
+    import paper_1709_01480_amd as fb
+    wl = workload("starfish4")
+    ctx = make_ctx(wl, flags=(fb.FLAG_BATCH_RFD if batch else 0))
+    x0 = nodes_of(ctx, wl)
+    delta = wl.a * 1e-2
+    Wt = np.zeros(3 * wl.n_bodies)
+    Wt[0:2] = 2.0 * (wl.q[1] - wl.q[0]) / delta
+    Wt[2] = 2.0 * (wl.theta[1] - wl.theta[0]) / delta
+    M = ctx.get_derived()["grid_M"]
+    rng = np.random.default_rng(1)
+    dQ = zeros(3 * wl.n_bodies)
+    with pytest.raises(fb.FbimError) as e:
+        ctx.step_em_rfd(wl.dt, delta, dev(wl.F), dev(rng.standard_normal(2 * wl.n_nodes)),
+                        dev(rng.standard_normal(2 * M * M)), dev(Wt), dQ, apply=True)
+    assert e.value.status == 3
+    assert np.array_equal(nodes_of(ctx, wl), x0)
+    # a normal step still works from Q
+    ctx.step_em_rfd(wl.dt, delta, dev(wl.F), None, None, None, dQ)
+    assert np.array_equal(nodes_of(ctx, wl), x0)
+
+
+def test_iteration_limit_reports_enoconv_and_writes_outputs():
+    import paper_1709_01480_amd as fb
+    wl = workload("starfish4")
+    ctx = make_ctx(wl, tol_gmres=1e-14, gmres_maxiter=2)
+    U = zeros(3 * wl.n_bodies)
+    with pytest.raises(fb.FbimError) as e:
+        ctx.mobility(dev(wl.F), U)
+    assert e.value.status == 4
+    u = host(U)
+    assert np.all(np.isfinite(u)) and np.max(np.abs(u)) > 0
+
+
+def test_non_finite_inputs():
+    import paper_1709_01480_amd as fb
+    wl = workload("tiny2")
+    ctx = make_ctx(wl)
+    F = wl.F.copy()
+    F[1] = np.nan
+    U = zeros(3 * wl.n_bodies)
+    with pytest.raises(fb.FbimError) as e:
+        ctx.mobility(dev(F), U)
+    assert e.value.status == 1
+    # a NaN density gives NaN velocities (as floating-point sums would), no fault
+    mu = np.random.default_rng(2).standard_normal(2 * wl.n_nodes)
+    mu[5] = np.nan
+    out = zeros(2 * wl.n_nodes)
+    ctx.apply_M(dev(mu), out, fb.PART_ALL)
+    assert np.isnan(host(out)).any()
+    with pytest.raises(fb.FbimError):
+        ctx.set_bodies(np.zeros(wl.n_bodies, dtype=np.int32), np.full((wl.n_bodies, 2), np.nan), wl.theta)
+    ctx.mobility(dev(wl.F), U)  # the context is unchanged

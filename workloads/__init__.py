@@ -25,7 +25,7 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["Workload", "CONFIGS", "make", "noise", "starfish_area",
+__all__ = ["Workload", "CONFIGS", "make", "noise", "noise_key", "starfish_area",
            "disk_lattice", "single_starfish", "uneven_suspensions"]
 
 
@@ -96,9 +96,12 @@ CONFIGS = {
                         L=_box_for_fraction(100, 0.02, 0.3, 0.2),
                         tol_ewald=1e-8, grid_M=256),
     # 10,000 five-arm starfish x 64 nodes (640k nodes), area fraction 0.3, grid 2048^2.
+    # Time step of the Brownian dynamics runs: with kT = eta = 1 a body of this size has a
+    # translational mobility ~0.36 and a rotational one ~9e3, so dt = 2.5e-9 moves it by
+    # ~1.4% of its radius and turns it by ~7e-3 rad (RMS) per step.
     "starfish10k": dict(n_bodies=10000, n_p=64, r_s=_rs_for_fraction(10000, 1.0, 0.3, 0.3),
                         b=0.3, n_arm=5, L=1.0, tol_ewald=1e-6, grid_M=2048,
-                        alpert_order=4),
+                        alpert_order=4, dt=2.5e-9),
     # dense suspensions (area fraction 0.4, bounding-circle gaps down to 0.05 r_s) for the
     # learned preconditioner: 1000 x 128 nodes, grid 1024^2, and a 200 x 64 training size
     "dense1000": dict(n_bodies=1000, n_p=128, r_s=_rs_for_fraction(1000, 1.0, 0.3, 0.4), b=0.3, n_arm=5,
@@ -210,10 +213,15 @@ def uneven_suspensions(count: int, seed: int = 0, n_min: int = 16, n_max: int = 
     return out
 
 
+def noise_key(wl: Workload, seed: Optional[int] = None) -> int:
+    """Key of the noise of workload i (0xF81A + i): numpy draws below, and the seed
+    of the device generator when the library draws the noise itself."""
+    return 0xF81A + (_SEEDS.get(wl.name, 99) if seed is None else seed)
+
+
 def noise(wl: Workload, grid_M: int, seed: Optional[int] = None):
     """Standard normal arrays (W_r, W_grid, W_tilde); noise key 0xF81A+i."""
-    s = 0xF81A + (_SEEDS.get(wl.name, 99) if seed is None else seed)
-    rng = np.random.default_rng(s)
+    rng = np.random.default_rng(noise_key(wl, seed))
     W_r = rng.standard_normal(2 * wl.n_nodes)
     W_grid = rng.standard_normal(2 * grid_M * grid_M)
     W_tilde = rng.standard_normal(3 * wl.n_bodies)
