@@ -356,6 +356,17 @@ fbim_status fbim_mlp_get_weights(fbim_ctx *ctx, float *w, size_t n);
 fbim_status fbim_mlp_features(fbim_ctx *ctx, float *X);
 /* DEVICE Y[n][6] = MLP(DEVICE X[n][32]) with the current weights. */
 fbim_status fbim_mlp_forward(fbim_ctx *ctx, const float *X, int32_t n, float *Y);
+/* fbim_mlp_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels, with the hidden activations in a static device array of
+ * 2 x 128 x FBIM_NOALLOC_MAX_BODIES floats (8 MiB) that each GPU holds for the
+ * life of the process; the call itself allocates and frees nothing.
+ * n <= FBIM_NOALLOC_MAX_BODIES, else FBIM_EINVAL.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams, other
+ * host threads, other contexts) race and must be serialised by the caller.
+ * Requires fbim_mlp_init (the weights are the context's). */
+#define FBIM_NOALLOC_MAX_BODIES 8192
+fbim_status fbim_mlp_forward_noalloc(fbim_ctx *ctx, const float *X, int32_t n, float *Y);
 /* DEVICE grad[FBIM_MLP_NPARAM] = d (sum_ij dY_ij Y_ij) / d w at DEVICE X[n][32],
  * DEVICE dY[n][6] (grad is overwritten, same layout as the weights). */
 fbim_status fbim_mlp_backward(fbim_ctx *ctx, const float *X, const float *dY, int32_t n, float *grad);

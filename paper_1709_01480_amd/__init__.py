@@ -23,6 +23,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 NOISE_W_R, NOISE_W_GRID, NOISE_W_TILDE = 0, 1, 2
 MLP_IN, MLP_HID, MLP_OUT = 32, 128, 6
 MLP_NPARAM = 32 * 128 + 128 + 128 * 128 + 128 + 128 * 6 + 6
+NOALLOC_MAX_BODIES = 8192
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EOVERLAP", 4: "ENOCONV", 5: "EDEVICE", 6: "ENOTSUP",
           7: "WACCURACY"}
 
@@ -112,6 +113,7 @@ def _load():
         "fbim_mlp_features": (i32, [p, p]),
         "fbim_mlp_forward": (i32, [p, p, i32, p]),
         "fbim_mlp_backward": (i32, [p, p, p, i32, p]),
+        "fbim_mlp_forward_noalloc": (i32, [p, p, i32, p]),
         "fbim_mlp_loss": (i32, [p, p, i32, p, p, P(ctypes.c_float), p]),
         "fbim_mlp_train": (i32, [p, P(TrainCfg), P(TrainInfo)]),
         "fbim_mlp_use": (i32, [p, i32]),
@@ -349,6 +351,10 @@ class Context:
     def mlp_forward(self, X, Y):
         n = X.numel() // MLP_IN
         self._check(lib.fbim_mlp_forward(self._ctx, _fptr(X, n * MLP_IN), n, _fptr(Y, n * MLP_OUT)))
+
+    def mlp_forward_noalloc(self, X, Y):
+        n = X.numel() // MLP_IN
+        self._check(lib.fbim_mlp_forward_noalloc(self._ctx, _fptr(X, n * MLP_IN), n, _fptr(Y, n * MLP_OUT)))
 
     def mlp_backward(self, X, dY, grad):
         n = X.numel() // MLP_IN

@@ -62,6 +62,8 @@ struct fbim_ctx {
   double chi[8]{}, w[8]{};
   std::string err;
   hipStream_t stream = nullptr;
+  int device = 0;  // HIP device current at fbim_create
+  float *noalloc_scratch = nullptr;  // this device's copy of the no-allocation scratch array
   bool mixed = false;
   bool cur32 = true;  // in a mixed context: matvecs use the FP32 kernels
 

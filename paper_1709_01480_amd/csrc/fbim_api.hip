@@ -1,6 +1,8 @@
 // C ABI of the FBIM library: context, geometry, the single-layer matvec
 // pipeline, GMRES (mobility), Lanczos ((M^(r))^(1/2)), Brownian velocity and
 // the EM-RFD step.  Host code driving the gfx950 kernels and rocFFT.
+#include <mutex>
+
 #include "ctx.h"
 
 namespace fbim {
@@ -231,17 +233,47 @@ GemmArgs gemm(int M, int N, int K, const float *A, size_t sam, size_t sak, const
   return g;
 }
 
-// Y = MLP(X); hidden activations kept in d_H1, d_H2
-fbim_status mlp_forward(fbim_ctx *c, const float *X, int n, float *Y) {
-  Timer t(c, "mlp");
+// Y = MLP(X) with the hidden activations in H1, H2 ([n][kMlpHid] each)
+fbim_status mlp_forward_into(fbim_ctx *c, const float *X, int n, float *Y, float *H1, float *H2) {
   hipStream_t s = c->stream;
   const float *w = c->d_mw;
-  HIPCHK(c, launch_gemm_bf16(gemm(n, kMlpHid, kMlpIn, X, kMlpIn, 1, w + kOffW1, kMlpHid, 1, c->d_H1, kMlpHid,
+  HIPCHK(c, launch_gemm_bf16(gemm(n, kMlpHid, kMlpIn, X, kMlpIn, 1, w + kOffW1, kMlpHid, 1, H1, kMlpHid,
                                   kGemmBiasTanh, w + kOffB1), 1, s));
-  HIPCHK(c, launch_gemm_bf16(gemm(n, kMlpHid, kMlpHid, c->d_H1, kMlpHid, 1, w + kOffW2, kMlpHid, 1, c->d_H2, kMlpHid,
+  HIPCHK(c, launch_gemm_bf16(gemm(n, kMlpHid, kMlpHid, H1, kMlpHid, 1, w + kOffW2, kMlpHid, 1, H2, kMlpHid,
                                   kGemmBiasTanh, w + kOffB2), 1, s));
-  HIPCHK(c, launch_gemm_bf16(gemm(n, kMlpOut, kMlpHid, c->d_H2, kMlpHid, 1, w + kOffW3, kMlpOut, 1, Y, kMlpOut,
+  HIPCHK(c, launch_gemm_bf16(gemm(n, kMlpOut, kMlpHid, H2, kMlpHid, 1, w + kOffW3, kMlpOut, 1, Y, kMlpOut,
                                   kGemmBias, w + kOffB3), 1, s));
+  return FBIM_OK;
+}
+
+// Y = MLP(X); hidden activations kept in d_H1, d_H2 (the backward pass reads them)
+fbim_status mlp_forward(fbim_ctx *c, const float *X, int n, float *Y) {
+  Timer t(c, "mlp");
+  return mlp_forward_into(c, X, n, Y, c->d_H1, c->d_H2);
+}
+
+// ------------------------------------------------------------------ no-allocation scratch
+// Device scratch of fbim_mlp_forward_noalloc: the two hidden activation
+// arrays of up to FBIM_NOALLOC_MAX_BODIES bodies, one copy per GPU for the
+// life of the process.  Host code never uses the array's name as an address:
+// its device address is looked up once per device (hipGetSymbolAddress, at
+// fbim_create on that device) and kept in g_noalloc_ptr.
+constexpr size_t kNoAllocFloats = 2 * (size_t)kMlpHid * FBIM_NOALLOC_MAX_BODIES;
+__device__ __align__(256) float noalloc_scratch[kNoAllocFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mutex;
+float *g_noalloc_ptr[kMaxDevices] = {};
+
+fbim_status resolve_noalloc_scratch(fbim_ctx *c) {
+  if (c->device < 0 || c->device >= kMaxDevices) return fail(c, FBIM_ENOTSUP, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+  if (!g_noalloc_ptr[c->device]) {
+    void *ptr = nullptr;
+    HIPCHK(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc_scratch)));
+    g_noalloc_ptr[c->device] = static_cast<float *>(ptr);
+  }
+  c->noalloc_scratch = g_noalloc_ptr[c->device];
   return FBIM_OK;
 }
 
@@ -973,6 +1005,10 @@ fbim_status fbim_create(const fbim_params *params, fbim_ctx **out) {
   *out = nullptr;
   auto *c = new fbim_ctx();
   c->p = *params;
+  if (hipGetDevice(&c->device) != hipSuccess || resolve_noalloc_scratch(c) != FBIM_OK) {
+    fbim_destroy(c);
+    return FBIM_EDEVICE;
+  }
   if (c->p.eta <= 0) c->p.eta = 1.0;
   if (c->p.tau_spurious <= 0) c->p.tau_spurious = 1e-8;
   if (c->p.tol_gmres <= 0) c->p.tol_gmres = 1e-6;
@@ -1441,6 +1477,16 @@ fbim_status fbim_mlp_forward(fbim_ctx *c, const float *X, int32_t n, float *Y) {
   if (!c->mlp_init) return fail(c, FBIM_EINVAL, "fbim_mlp_init first");
   STCHK(ensure_mlp(c, n));
   return mlp_forward(c, X, n, Y);
+}
+
+fbim_status fbim_mlp_forward_noalloc(fbim_ctx *c, const float *X, int32_t n, float *Y) {
+  if (!c || !X || !Y || n < 0) return fail(c, FBIM_EINVAL, "invalid argument");
+  if (n > FBIM_NOALLOC_MAX_BODIES)
+    return fail(c, FBIM_EINVAL, "fbim_mlp_forward_noalloc: n exceeds FBIM_NOALLOC_MAX_BODIES");
+  if (!c->mlp_init) return fail(c, FBIM_EINVAL, "fbim_mlp_init first");
+  if (!c->noalloc_scratch) return fail(c, FBIM_EDEVICE, "no-allocation scratch not resolved");
+  float *H1 = c->noalloc_scratch, *H2 = c->noalloc_scratch + (size_t)kMlpHid * FBIM_NOALLOC_MAX_BODIES;
+  return mlp_forward_into(c, X, n, Y, H1, H2);
 }
 
 fbim_status fbim_mlp_backward(fbim_ctx *c, const float *X, const float *dY, int32_t n, float *grad) {
