@@ -192,6 +192,16 @@ fbim_status fbim_random_field(fbim_ctx *ctx, const double *W_grid, double *out);
  * full reorthogonalisation, from DEVICE W_r[2N]. */
 fbim_status fbim_sqrt_Mr(fbim_ctx *ctx, const double *W_r, double *out, fbim_info *info);
 
+/* DEVICE y[2N + 3n] = P^-1 z for DEVICE z[2N + 3n] = [a (node vector); c (body
+ * vector)]: the block-diagonal preconditioner of the saddle system (Section
+ * 3.4, eqs. 3.31-3.37).  Per body b, with M_bb^+ = R_b M_ref^+ R_b^T (the
+ * pseudo-inverse of the body's self block, eigenvalues |lambda| <= tau
+ * lambda_max dropped) and N_b = (K_b^T M_bb^+ K_b)^-1:
+ *   U_b = -N_b (c_b + K_b^T M_bb^+ a_b),  mu_b = M_bb^+ (a_b + K_b U_b);
+ * with the learned correction in use (fbim_mlp_use), U_b -= C_b c_b where C_b
+ * is the body's correction dN rotated into the lab frame.  z, y must not alias. */
+fbim_status fbim_apply_precond(fbim_ctx *ctx, const double *z, double *y);
+
 /* Mobility solve of eq. 3.8: [M -K; -K^T 0][mu; U] = -[slip; F].
  * DEVICE F[3n]; DEVICE slip[2N] or NULL (zero slip); DEVICE U[3n];
  * DEVICE mu_out[2N] or NULL.  FBIM_ENOCONV still writes U and mu. */

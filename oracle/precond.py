@@ -8,8 +8,19 @@ Block inverse per body b for the system [M -K; -K^T 0][mu; U] = [a; c]:
 Corrected form: the exact inverse of the block with M_bb replaced by
 M_bb + K_b C K_b^T for a symmetric 3 x 3 C; by the Woodbury identity the
 body's mobility becomes N_b + C, mu_b is unchanged and U_b gains -C c_b.
+
+Two forms of the blocks: block_preconditioner takes M_bb, the body's own
+diagonal block of the dense M; reference_preconditioner follows the paper's
+construction, M_bb^+ ~ R_b M_ref^+ R_b^T with M_ref the self block of the
+shape in its reference configuration (theta = 0) in the same periodic box
+(Section 3.4, the equation after eq. 3.37).  The two differ because the
+periodic lattice of images is not rotation invariant.
 """
+import math
+
 import numpy as np
+
+from . import fbim as F
 
 
 def pinv_sym(A, tau=1e-8):
@@ -70,3 +81,40 @@ def gmres(A, rhs, Pinv, tol=1e-8, maxit=500):
         if np.linalg.norm(e1 - H[:j + 2, :j + 1] @ y) <= tol * nb or H[j + 1, j] == 0:
             return Z[:, :j + 1] @ y, j + 1
     return Z @ y, maxit
+
+
+def reference_preconditioner(geo, prm, order=4, C=None, tau=1e-8, eta=1.0):
+    """z -> P^-1 z with every body block built from the reference configuration:
+    M_bb^+ = R_b M_ref^+ R_b^T, K_b from the body's own nodes (single shape).
+    C: optional [n, 3, 3] lab-frame corrections as in block_preconditioner.
+    Returns (apply, [N_b])."""
+    sh = geo.shapes[0]
+    ref = F.reference_geometry(sh, geo.L)
+    Mref = F.single_layer(ref, prm, order, eta)["M"]
+    Mref_p = pinv_sym(Mref, tau)
+    K = F.K_matrix(geo)
+    off = geo.offsets()
+    n = geo.n
+    N2 = 2 * off[-1]
+    blocks = []
+    for b in range(n):
+        sl = slice(2 * off[b], 2 * off[b + 1])
+        c, s = math.cos(geo.theta[b]), math.sin(geo.theta[b])
+        Rb = np.kron(np.eye(off[b + 1] - off[b]), np.array([[c, -s], [s, c]]))
+        Mp = Rb @ Mref_p @ Rb.T
+        Kb = K[sl, 3 * b:3 * b + 3]
+        blocks.append((sl, Mp, Kb, np.linalg.inv(Kb.T @ Mp @ Kb)))
+
+    def apply(z):
+        a, cz = z[:N2], z[N2:]
+        mu, U = np.zeros(N2), np.zeros(3 * n)
+        for b, (sl, Mp, Kb, Nb) in enumerate(blocks):
+            cb = cz[3 * b:3 * b + 3]
+            u = -Nb @ (cb + Kb.T @ (Mp @ a[sl]))
+            mu[sl] = Mp @ (a[sl] + Kb @ u)
+            if C is not None:
+                u = u - C[b] @ cb
+            U[3 * b:3 * b + 3] = u
+        return np.concatenate([mu, U])
+
+    return apply, [bl[3] for bl in blocks]

@@ -103,6 +103,7 @@ def _load():
         "fbim_random_field": (i32, [p, p, p]),
         "fbim_sqrt_Mr": (i32, [p, p, p, P(Info)]),
         "fbim_mobility": (i32, [p, p, p, p, p, P(Info)]),
+        "fbim_apply_precond": (i32, [p, p, p]),
         "fbim_brownian_velocity": (i32, [p, d, p, p, p, p, P(Info)]),
         "fbim_step_em_rfd": (i32, [p, d, d, p, p, p, p, p, i32, P(Info)]),
         "fbim_derive_params": (i32, [P(Params), P(Derived)]),
@@ -282,6 +283,10 @@ class Context:
         self._check(lib.fbim_sqrt_Mr(self._ctx, _dptr(W_r, 2 * self.N), _dptr(out, 2 * self.N),
                                      ctypes.byref(info)))
         return info.as_dict()
+
+    def apply_precond(self, z, y):
+        n = 2 * self.N + 3 * self.n
+        self._check(lib.fbim_apply_precond(self._ctx, _dptr(z, n), _dptr(y, n)))
 
     def mobility(self, F, U, slip=None, mu_out=None):
         info = Info()

@@ -1276,6 +1276,11 @@ fbim_status fbim_sqrt_Mr(fbim_ctx *c, const double *W_r, double *out, fbim_info 
   return st;
 }
 
+fbim_status fbim_apply_precond(fbim_ctx *c, const double *z, double *y) {
+  if (!c || !z || !y || z == y || !c->have_bodies) return fail(c, FBIM_EINVAL, "invalid arguments");
+  return apply_precond(c, z, y);
+}
+
 fbim_status fbim_mobility(fbim_ctx *c, const double *F, const double *slip, double *U, double *mu_out,
                           fbim_info *info) {
   if (!c || !F || !U || !c->have_bodies) return fail(c, FBIM_EINVAL, "invalid arguments");

@@ -73,3 +73,42 @@ def test_exact_self_mobility_correction_leaves_iterations_unchanged():
     # ... yet GMRES takes (within one) the same number of iterations, to the same solution
     assert abs(i1 - i0) <= 1
     assert np.max(np.abs(x1[N2:] - x0[N2:])) < 1e-6 * np.max(np.abs(x0[N2:]))
+
+
+def test_reference_preconditioner_is_exact_for_the_reference_orientation():
+    # one body at theta = 0 is its own reference configuration: the rotated
+    # reference block is the body's block, so both constructions coincide
+    wl, geo, M, K, A, N2 = _system(1, 32, 0.05, 1)
+    geo.theta[:] = 0.0
+    prm = OF.derive_params(wl.L, wl.tol_ewald, n_box=4)
+    M = OF.single_layer(geo, prm, order=4)["M"]
+    K = OF.K_matrix(geo)
+    P_ref, N_ref = OP.reference_preconditioner(geo, prm)
+    P_blk, N_blk = OP.block_preconditioner(M, K, geo.offsets())
+    z = np.random.default_rng(2).standard_normal(N2 + 3)
+    assert np.allclose(P_ref(z), P_blk(z), rtol=0, atol=1e-8 * np.max(np.abs(P_blk(z))))
+    assert np.max(np.abs(N_ref[0] - N_blk[0])) < 1e-10 * np.max(np.abs(N_blk[0]))
+
+
+def test_reference_preconditioner_rotates_with_the_body():
+    # the rotated reference block approximates each body's own block (the
+    # periodic lattice's anisotropy is small for a body much smaller than the
+    # box); planting the transposed rotation breaks the density part
+    wl, geo, M, K, A, N2 = _system(3, 32, 0.05, 4)
+    prm = OF.derive_params(wl.L, wl.tol_ewald, n_box=4)
+    P_ref, N_ref = OP.reference_preconditioner(geo, prm)
+    P_blk, N_blk = OP.block_preconditioner(M, K, geo.offsets())
+    for b in range(3):
+        assert np.max(np.abs(N_ref[b] - N_blk[b])) < 1e-4 * np.max(np.abs(N_blk[b]))
+    z = np.random.default_rng(3).standard_normal(A.shape[0])
+    yr, yb = P_ref(z), P_blk(z)
+    assert np.max(np.abs(yr - yb)) < 1e-3 * np.max(np.abs(yb))
+    _, its_ref = OP.gmres(A, z, P_ref, tol=1e-8)
+    _, its_blk = OP.gmres(A, z, P_blk, tol=1e-8)
+    assert abs(its_ref - its_blk) <= 2
+    g2 = OF.Geometry(geo.L, geo.shapes, geo.shape_id, geo.q, -geo.theta)  # planted: R^T in place of R
+    P_bad, _ = OP.reference_preconditioner(g2, prm)
+    Kb = OF.K_matrix(geo)
+    # same K (the body's own nodes), wrongly rotated reference block
+    y_bad = P_bad(z)
+    assert np.max(np.abs(y_bad[:N2] - yb[:N2])) > 1e-1 * np.max(np.abs(yb[:N2]))
