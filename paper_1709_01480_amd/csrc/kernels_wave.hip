@@ -35,18 +35,6 @@ __device__ inline int xcd_remap(int b, int n) {
   return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
-// One 256-thread work group per T x T grid tile, accumulated in LDS (no global
-// atomics).  The nodes whose stencil touches the tile come from the tile's
-// spreading list (built once per configuration); they are taken in chunks of
-// kSpreadChunk: per chunk the P x- and P y-weights of every node are computed
-// once (x and y weights by two threads), then the (node, stencil row) items are
-// spread over the threads and added with LDS atomics.  The node data of the first
-// kSpreadPre chunks is requested before any of them is used.
-constexpr int kSpreadChunk = 128;
-constexpr int kSpreadPre = 4;
-// dynamic LDS of the spreading kernels: x and y weights of a chunk, P per entry
-inline size_t spread_lds_bytes(int P, size_t elem) { return 2 * (size_t)kSpreadChunk * P * elem; }
-
 __device__ inline int wrap_near(int i, int M) {  // valid for -M <= i < 2M
   return i < 0 ? i + M : (i >= M ? i - M : i);
 }
@@ -135,162 +123,203 @@ __device__ inline void gauss_row(T x, T scale, T ag, T h, int half, int P, const
   }
 }
 
-__device__ __forceinline__ unsigned long long to_fixed(float v) { return (unsigned long long)__float2ll_rn(v); }
-__device__ __forceinline__ unsigned long long to_fixed(double v) { return (unsigned long long)__double2ll_rn(v); }
+// Spreading: one 256-thread work group per T x T grid tile, accumulated in LDS
+// (no global atomics) over the tile's spreading list (the nodes whose stencil
+// touches the tile, built once per configuration).  Per chunk of list entries
+// each entry's P x- and P y-weights are computed once into LDS; then every
+// (entry, stencil row) item loads its P x-weights into registers and adds its P
+// values to one accumulator row with back-to-back LDS atomics (no wait between
+// them: a load inside the column loop would wait for the atomics before it).
+// Accumulator rows are padded by PP - 1 columns on each side, so a stencil that
+// reaches past the tile needs no masks (those columns are discarded), and the
+// row stride is odd so that the P rows of one item fall in distinct banks.
+//
+// Accumulation is in fixed point with a power-of-two scale S per tile, in
+// 64-bit integer LDS atomics (the fast LDS atomic here: FP32 LDS atomic adds ran
+// about 8x slower), so the sums, and the spread grid, do not depend on the order
+// of the atomics.  S comes from a bound on every partial sum of the tile: per
+// 8 x 8 block of the tile, cg times the sum of max(|mu_x|, |mu_y|) over the
+// entries whose stencil meets the block (the weights are at most cg).
+//   FP32: both components in one 64-bit word as two 32-bit signed halves, with
+//     S B <= 2^30.  A half's sum stays within 31 bits, so the borrows of the low
+//     half into the high half are undone exactly when the word is read back:
+//     one atomic per grid point and entry, and a resolution of B / 2^30, below
+//     the FP32 rounding of the terms.
+//   FP64: one 64-bit word per component, S B <= 2^62.
+// Terms are converted to integers by rounding (FP32) or by a floor computed in
+// two 32-bit halves (FP64, within one unit of the scaled term).  A NaN or
+// infinite density makes its tile's grid NaN, as floating-point sums would.
+constexpr int kSpreadBlock = 8;  // side of the bound blocks
+constexpr int kSpreadMaxBlocks = (kTmax + kSpreadBlock - 1) / kSpreadBlock;
 
-// T: weights and positions; A: LDS accumulator.  FP64: double (FP64 LDS atomic
-// adds).  FP32: 64-bit fixed point (unsigned long long, two's complement) with a
-// per-tile power-of-two scale S: a grid point of the tile receives at most one
-// term per list entry, each at most cg max|mu| in magnitude (weights <= cg in y,
-// <= 1 in x), so with B = 2 n cg max|mu| (n entries, factor 2 for FP32 rounding)
-// and S B <= 2^62 no sum can overflow, and the resolution B / 2^62 is far below
-// the FP32 rounding of the terms: the sums are exact.  64-bit integer LDS atomics
-// ran at 83 us against 95 us for FP64 ones (FP32 LDS atomics: 550 us; 32-bit
-// fixed point, 65 us, was too coarse at B / 2^30 and cost GMRES iterations), and
-// integer sums do not depend on their order.
-template <typename T, typename A>
-__device__ __forceinline__ void spread_body(int M, int TT, int P, int nts, T h, T ag, T cg, const int *__restrict__ slist_start,
-                            const int *__restrict__ slist, const typename Vec2<T>::type *__restrict__ xt,
-                            const int2 *__restrict__ anchor, const typename Vec2<T>::type *__restrict__ mut,
-                            T *__restrict__ grid, int tile) {
+// list entries per chunk (weights in LDS) and accumulator words per grid point;
+// FP64 with the widest stencils takes smaller chunks to stay within 64 KB of LDS
+template <typename T, int PP>
+__host__ __device__ constexpr int spread_chunk() {
+  return sizeof(T) == 4 ? 256 : (PP >= 15 ? 64 : 128);
+}
+template <typename T>
+__host__ __device__ constexpr int spread_nacc() {
+  return sizeof(T) == 4 ? 1 : 2;
+}
+
+// padded accumulator row stride for tile edge TT and stencil bound PP (odd)
+__host__ __device__ inline int spread_stride(int TT, int PP) { return (TT + 2 * (PP - 1)) | 1; }
+template <typename T, int PP>
+inline size_t spread_lds_bytes() {
+  return (size_t)spread_nacc<T>() * kTmax * spread_stride(kTmax, PP) * sizeof(unsigned long long) +
+         2 * (size_t)spread_chunk<T, PP>() * PP * sizeof(T);
+}
+
+__device__ __forceinline__ unsigned long long fix64(double v) {  // floor-like integer of v, |v| < 2^62
+  const double hf = floor(v * 0x1p-32);
+  const double lf = fmin(fma(hf, -0x1p32, v), 4294967295.0);  // in [0, 2^32): rounding may reach 2^32
+  return ((unsigned long long)(unsigned)(int)hf << 32) + (unsigned long long)(unsigned)lf;
+}
+__device__ __forceinline__ unsigned long long pack32(float x, float y) {  // (round(y) << 32) + round(x)
+  const int tx = __float2int_rn(x), ty = __float2int_rn(y);
+  return ((unsigned long long)((unsigned)ty + (unsigned)(tx >> 31)) << 32) | (unsigned)tx;
+}
+
+template <typename T, int PP>
+__device__ __forceinline__ void spread_body(int M, int TT, int P, int nts, T h, T ag, T cg,
+                                            const int *__restrict__ slist_start, const int *__restrict__ slist,
+                                            const typename Vec2<T>::type *__restrict__ xt,
+                                            const int2 *__restrict__ anchor,
+                                            const typename Vec2<T>::type *__restrict__ mut, T *__restrict__ grid,
+                                            int tile) {
   using V2 = typename Vec2<T>::type;
-  __shared__ A acc[2][kTmax * (kTmax + 1)];  // rows padded by one: a node's P rows fall in distinct banks
-  // the P x- and y-weights of each chunk entry, rows of P: dynamic LDS sized for
-  // the launch's P (spread_lds_bytes), so small stencils leave room for more
-  // work groups per CU
-  extern __shared__ double spread_wbuf[];
-  T *wgx = reinterpret_cast<T *>(spread_wbuf), *wgy = wgx + kSpreadChunk * P;
-  __shared__ T nmx[kSpreadChunk], nmy[kSpreadChunk], ck[kPmax];
-  __shared__ int nbx[kSpreadChunk], nby[kSpreadChunk], ncol[kSpreadChunk];
-  const int tid = threadIdx.x;
+  constexpr bool F32 = sizeof(T) == 4;
+  constexpr int CH = spread_chunk<T, PP>(), NACC = spread_nacc<T>(), PADC = PP - 1;
+  extern __shared__ unsigned long long spread_lds[];
+  const int ST = spread_stride(TT, PP);
+  unsigned long long *acc0 = spread_lds, *acc1 = spread_lds + (size_t)TT * ST;  // acc1: FP64 only
+  T *wgx = reinterpret_cast<T *>(spread_lds + (size_t)NACC * TT * ST), *wgy = wgx + CH * PP;
+  __shared__ T nmx[CH], nmy[CH], ck[kPmax];
+  __shared__ int nbx[CH], nby[CH];
+  __shared__ unsigned s_max, s_bad, s_blk[kSpreadMaxBlocks * kSpreadMaxBlocks];
+  const int tid = threadIdx.x, lane = tid & 63;
   const int tyi = tile / nts, txi = tile % nts;
   const int gx0 = txi * TT, gy0 = tyi * TT;
   const int half = (P - 1) / 2;
-  const int ST = TT + 1;
   const int ls = slist_start[tile], n = slist_start[tile + 1] - ls;
-  // thread t serves entry (chunk base + t % 128): its x weights (t < 128) or y weights
-  const int e0 = tid & (kSpreadChunk - 1);
-  const bool ycomp = tid >= kSpreadChunk;
-  V2 pr[kSpreadPre], mr[kSpreadPre];
-  int2 ar[kSpreadPre];
-#pragma unroll
-  for (int r = 0; r < kSpreadPre; ++r) {
-    const int e = e0 + kSpreadChunk * r;
-    if (e < n) {
-      const int g = slist[ls + e];
-      pr[r] = xt[g];
-      mr[r] = mut[g];
-      ar[r] = anchor[g];
-    }
-  }
-  for (int i = tid; i < TT * ST; i += 256) acc[0][i] = acc[1][i] = A(0);
+  const int nbk = (TT + kSpreadBlock - 1) / kSpreadBlock;
+  for (int i = tid; i < NACC * TT * ST; i += 256) spread_lds[i] = 0ull;
+  if (tid < nbk * nbk) s_blk[tid] = 0u;
+  if (tid == 0) s_max = s_bad = 0u;
   if (tid < P) ck[tid] = gauss_step<T>(ag, h, tid);
-  constexpr bool kFixed = std::is_same<A, unsigned long long>::value;
-  T S = T(1);       // fixed-point scale (kFixed)
-  bool finite = true;  // a non-finite density makes the tile's grid NaN (as floating-point sums would)
-  if constexpr (kFixed) {
-    __shared__ T red[4];
-    // max |mu| over the list; any NaN or infinity (which fmax would skip) is flagged
-    T m = T(0);
-    int bad = 0;
-    auto take = [&](V2 mu) {
+  __syncthreads();
+  // bound of the partial sums: max |mu| of the tile, then per block the sum of
+  // the quantised max(|mu_x|, |mu_y|) (rounded up) of the entries meeting it
+  auto origin = [&](int a, int g0) {
+    const int o = stencil_origin(a, half, g0, M);
+    return o < TT ? o : o - M;
+  };
+  {
+    float mloc = 0.f;
+    bool bad = false;
+    for (int e = tid; e < n; e += 256) {
+      const V2 mu = mut[slist[ls + e]];
       const T a = fmax(fabs(mu.x), fabs(mu.y));
-      bad |= !(fabs(mu.x) <= T(3.0e38) && fabs(mu.y) <= T(3.0e38));
-      m = fmax(m, a);
-    };
+      bad |= !isfinite(mu.x) || !isfinite(mu.y);
+      mloc = fmaxf(mloc, (float)a);
+    }
 #pragma unroll
-    for (int r = 0; r < kSpreadPre; ++r)
-      if (e0 + kSpreadChunk * r < n) take(mr[r]);
-    for (int e = kSpreadChunk * kSpreadPre + tid; e < n; e += 256) take(mut[slist[ls + e]]);  // rare: crowded tiles
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-    if ((tid & 63) == 0) red[tid >> 6] = m;
-    finite = __syncthreads_or(bad) == 0;  // also the barrier for red
-    m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    const double B = 2.0 * (double)n * (double)cg * (double)m;  // no overflow for finite FP32 inputs
-    if (finite && B > 0.0) {
-      int k;
-      frexp(B, &k);  // B < 2^k
-      constexpr int kMaxE = sizeof(T) == 4 ? 126 : 1000;
-      S = ldexp(T(1), max(min(62 - k, kMaxE), -kMaxE));
+    for (int o = 32; o > 0; o >>= 1) mloc = fmaxf(mloc, __shfl_xor(mloc, o));
+    const unsigned long long anybad = __ballot(bad);
+    if (lane == 0) {
+      atomicMax(&s_max, __float_as_uint(isfinite(mloc) ? mloc : 0.f));
+      if (anybad) atomicOr(&s_bad, 1u);
     }
   }
-  __syncthreads();  // ck (and the zeroed accumulator) before any use
-
-  // per entry: the stencil's first row / column relative to the tile (negative when
-  // it starts in the neighbouring tile across a periodic edge), the columns
-  // [pc0, pc1) that fall in the tile, and the P weights per direction
-  auto weights = [&](V2 p, V2 mu, int2 an) {
-    if (!ycomp) {
-      const int ox = stencil_origin(an.x, half, gx0, M);
-      const int xs = ox < TT ? ox : ox - M;
-      nbx[e0] = xs;
-      ncol[e0] = max(0, -xs) | (min(P, TT - xs) << 8);
-      nmx[e0] = mu.x;
-      nmy[e0] = mu.y;
-      gauss_row<T>(p.x, T(1), ag, h, half, P, ck, wgx + e0 * P);
-    } else {
-      const int oy = stencil_origin(an.y, half, gy0, M);
-      nby[e0] = oy < TT ? oy : oy - M;
-      gauss_row<T>(p.y, cg, ag, h, half, P, ck, wgy + e0 * P);
+  __syncthreads();
+  const float mmax = __uint_as_float(s_max);
+  const bool finite = s_bad == 0u;
+  int E = 0;  // quantisation exponent of the block sums: n (mmax 2^E + 1) < 2^32
+  if (mmax > 0.f) {
+    int k;
+    frexpf(mmax * (float)max(n, 1) * 1.0001f, &k);  // n mmax < 2^k
+    E = 31 - k;
+  }
+  for (int e = tid; e < n; e += 256) {
+    const int g = slist[ls + e];
+    const V2 mu = mut[g];
+    const int2 an = anchor[g];
+    const int ox = origin(an.x, gx0), oy = origin(an.y, gy0);
+    const int bx0 = max(ox, 0) / kSpreadBlock, bx1 = min(ox + P - 1, TT - 1) / kSpreadBlock;
+    const int by0 = max(oy, 0) / kSpreadBlock, by1 = min(oy + P - 1, TT - 1) / kSpreadBlock;
+    const float m = finite ? (float)fmax(fabs(mu.x), fabs(mu.y)) : 0.f;
+    const unsigned qv = (unsigned)ceilf(ldexpf(m, E));
+    for (int by = by0; by <= by1; ++by)
+      for (int bx = bx0; bx <= bx1; ++bx) atomicAdd(&s_blk[by * nbk + bx], qv);
+  }
+  __syncthreads();
+  T S = T(1);
+  if (finite && mmax > 0.f) {
+    unsigned bq = 0u;
+    for (int b = 0; b < nbk * nbk; ++b) bq = max(bq, s_blk[b]);
+    const double B = (double)cg * ldexp((double)bq, -E) * (1.0 + 0x1p-20);
+    int k;
+    frexp(B, &k);  // B < 2^k
+    constexpr int kTop = F32 ? 30 : 62, kMaxE = F32 ? 126 : 1000;
+    S = ldexp(T(1), max(min(kTop - k, kMaxE), -kMaxE));
+  }
+  for (int c = 0; c < n; c += CH) {
+    const int cnt = min(CH, n - c);
+    if (tid < cnt) {
+      const int g = slist[ls + c + tid];
+      const V2 p = xt[g], mu = mut[g];
+      const int2 an = anchor[g];
+      nbx[tid] = origin(an.x, gx0) + PADC;
+      nby[tid] = origin(an.y, gy0);
+      nmx[tid] = mu.x * S;  // exact: S is a power of two
+      nmy[tid] = mu.y * S;
+      T wr[kPmax];
+      gauss_row<T>(p.x, T(1), ag, h, half, P, ck, wr);
+#pragma unroll
+      for (int k = 0; k < PP; ++k) wgx[tid * PP + k] = k < P ? wr[k] : T(0);
+      gauss_row<T>(p.y, cg, ag, h, half, P, ck, wr);
+#pragma unroll
+      for (int k = 0; k < PP; ++k) wgy[tid * PP + k] = k < P ? wr[k] : T(0);
     }
-  };
-  const float invP = 1.0f / (float)P;
-  auto items = [&](int cnt) {
+    __syncthreads();
+    const float invP = 1.0f / (float)P;
     for (int it = tid; it < cnt * P; it += 256) {
       const int j = (int)(((float)it + 0.5f) * invP), q = it - j * P;  // it / P, exact for it < 2^20
       const int ry = nby[j] + q;
-      if (ry < 0 || ry >= TT) continue;
-      const T wy = wgy[j * P + q];
-      const T ux = wy * nmx[j], uy = wy * nmy[j];
-      const int cr = ncol[j], xs = nbx[j];
-      A *a0 = &acc[0][ry * ST + xs], *a1 = &acc[1][ry * ST + xs];
-      if constexpr (kFixed) {
-        const T sx = ux * S, sy = uy * S;  // exact: S is a power of two
-        for (int pc = cr & 255; pc < (cr >> 8); ++pc) {
-          const T wx = wgx[j * P + pc];
-          atomicAdd(a0 + pc, to_fixed(sx * wx));
-          atomicAdd(a1 + pc, to_fixed(sy * wx));
-        }
-      } else {
-        for (int pc = cr & 255; pc < (cr >> 8); ++pc) {
-          const T wx = wgx[j * P + pc];
-          atomicAdd(a0 + pc, (A)(ux * wx));
-          atomicAdd(a1 + pc, (A)(uy * wx));
+      if ((unsigned)ry >= (unsigned)TT) continue;
+      T w[PP];
+#pragma unroll
+      for (int k = 0; k < PP; ++k) w[k] = wgx[j * PP + k];
+      const T wy = wgy[j * PP + q];
+      const T sx = wy * nmx[j], sy = wy * nmy[j];
+      const int base = ry * ST + nbx[j];
+#pragma unroll
+      for (int k = 0; k < PP; ++k) {
+        if constexpr (F32) {
+          atomicAdd(acc0 + base + k, pack32(sx * w[k], sy * w[k]));
+        } else {
+          atomicAdd(acc0 + base + k, fix64(sx * w[k]));
+          atomicAdd(acc1 + base + k, fix64(sy * w[k]));
         }
       }
     }
-  };
-#pragma unroll
-  for (int r = 0; r < kSpreadPre; ++r) {
-    const int c = kSpreadChunk * r;
-    if (c >= n) break;  // n is uniform over the work group
-    const int cnt = min(kSpreadChunk, n - c);
-    if (e0 < cnt) weights(pr[r], mr[r], ar[r]);
-    __syncthreads();
-    items(cnt);
     __syncthreads();
   }
-  for (int c = kSpreadChunk * kSpreadPre; c < n; c += kSpreadChunk) {  // rare: crowded tiles
-    const int cnt = min(kSpreadChunk, n - c);
-    if (e0 < cnt) {
-      const int g = slist[ls + c + e0];
-      weights(xt[g], mut[g], anchor[g]);
-    }
-    __syncthreads();
-    items(cnt);
-    __syncthreads();
-  }
+  const T inv = finite ? T(1) / S : T(NAN);  // exact power of two
   for (int i = tid; i < TT * TT; i += 256) {
     const int ry = i / TT, rx = i - ry * TT;
     const size_t gidx = (size_t)(gy0 + ry) * M + gx0 + rx;
-    if constexpr (kFixed) {
-      const T inv = finite ? T(1) / S : T(NAN);  // exact power of two
-      grid[gidx] = (T)(long long)acc[0][ry * ST + rx] * inv;
-      grid[(size_t)M * M + gidx] = (T)(long long)acc[1][ry * ST + rx] * inv;
+    const int a = ry * ST + rx + PADC;
+    if constexpr (F32) {
+      const unsigned long long v = acc0[a];
+      const int lo = (int)(unsigned)v;
+      const int hi = (int)((v - (unsigned long long)(long long)lo) >> 32);
+      grid[gidx] = (T)lo * inv;
+      grid[(size_t)M * M + gidx] = (T)hi * inv;
     } else {
-      grid[gidx] = (T)acc[0][ry * ST + rx];
-      grid[(size_t)M * M + gidx] = (T)acc[1][ry * ST + rx];
+      grid[gidx] = (T)(long long)acc0[a] * inv;
+      grid[(size_t)M * M + gidx] = (T)(long long)acc1[a] * inv;
     }
   }
 }
@@ -369,15 +398,15 @@ __device__ __forceinline__ void multiplier_body(int M, T twopi_L, T inv4xi2, T o
   Fy.y = sc * (pxy * fx.y + pyy * fy.y);
 }
 
-template <typename T, typename A>
+template <typename T, int PP>
 __global__ __launch_bounds__(256) void k_spread(int M, int TT, int P, int nts, T h, T ag, T cg,
                                                 const int *__restrict__ slist_start, const int *__restrict__ slist,
                                                 const typename Vec2<T>::type *__restrict__ xt,
                                                 const int2 *__restrict__ anchor,
                                                 const typename Vec2<T>::type *__restrict__ mut,
                                                 T *__restrict__ grid) {
-  spread_body<T, A>(M, TT, P, nts, h, ag, cg, slist_start, slist, xt, anchor, mut, grid,
-                    xcd_remap(blockIdx.x, gridDim.x));
+  spread_body<T, PP>(M, TT, P, nts, h, ag, cg, slist_start, slist, xt, anchor, mut, grid,
+                     xcd_remap(blockIdx.x, gridDim.x));
 }
 
 template <typename T>
@@ -399,15 +428,15 @@ __global__ void k_multiplier(int M, T twopi_L, T inv4xi2, T one_m_eta, T scale, 
 
 // batched forms: the XCD-aware order is taken over the whole grid, then the
 // block's system and its tile within that system are found
-template <typename T, typename A>
+template <typename T, int PP>
 __global__ __launch_bounds__(256) void k_spread_batch(const SpreadJob *__restrict__ jobs, BatchGrid bg) {
   using V2 = typename Vec2<T>::type;
   const int gb = xcd_remap(blockIdx.x, gridDim.x);
   const int s = batch_system(bg.begin, bg.S, gb);
   const SpreadJob &j = jobs[s];
-  spread_body<T, A>(j.w.M, j.w.T, j.w.P, j.w.nts, (T)j.w.h, (T)j.w.ag, (T)j.w.cg, j.w.slist_start, j.w.slist,
-                    reinterpret_cast<const V2 *>(j.xt), reinterpret_cast<const int2 *>(j.w.anchor),
-                    reinterpret_cast<const V2 *>(j.mut), reinterpret_cast<T *>(j.grid), gb - bg.begin[s]);
+  spread_body<T, PP>(j.w.M, j.w.T, j.w.P, j.w.nts, (T)j.w.h, (T)j.w.ag, (T)j.w.cg, j.w.slist_start, j.w.slist,
+                     reinterpret_cast<const V2 *>(j.xt), reinterpret_cast<const int2 *>(j.w.anchor),
+                     reinterpret_cast<const V2 *>(j.mut), reinterpret_cast<T *>(j.grid), gb - bg.begin[s]);
 }
 
 template <typename T>
@@ -432,16 +461,35 @@ __global__ __launch_bounds__(256) void k_multiplier_batch(const MultJob *__restr
 
 }  // namespace
 
+// the stencil bound PP (odd, >= P) of a launch selects the kernel instance
+template <typename T, typename F>
+static hipError_t spread_dispatch(int pp, F &&launch) {
+  switch (pp) {
+    case 1: case 3: return launch(std::integral_constant<int, 3>{});
+    case 5: return launch(std::integral_constant<int, 5>{});
+    case 7: return launch(std::integral_constant<int, 7>{});
+    case 9: return launch(std::integral_constant<int, 9>{});
+    case 11: return launch(std::integral_constant<int, 11>{});
+    case 13: return launch(std::integral_constant<int, 13>{});
+    case 15: return launch(std::integral_constant<int, 15>{});
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t spread_batch_t(const SpreadJob *jobs, BatchGrid bg, int pmax, hipStream_t s) {
+  return spread_dispatch<T>(pmax, [&](auto pp) {
+    constexpr int PP = decltype(pp)::value;
+    const size_t lds = spread_lds_bytes<T, PP>();
+    hipLaunchKernelGGL((k_spread_batch<T, PP>), dim3(bg.nblocks), dim3(256), lds, s, jobs, bg);
+    return hipGetLastError();
+  });
+}
+
 hipError_t launch_spread_batch(const SpreadJob *jobs, BatchGrid bg, int f32, int pmax, hipStream_t s) {
   if (bg.nblocks == 0) return hipSuccess;
   if (pmax < 1 || pmax > kPmax) return hipErrorInvalidValue;
-  if (f32)
-    hipLaunchKernelGGL((k_spread_batch<float, unsigned long long>), dim3(bg.nblocks), dim3(256), spread_lds_bytes(pmax, 4), s,
-                       jobs, bg);
-  else
-    hipLaunchKernelGGL((k_spread_batch<double, unsigned long long>), dim3(bg.nblocks), dim3(256), spread_lds_bytes(pmax, 8), s,
-                       jobs, bg);
-  return hipGetLastError();
+  return f32 ? spread_batch_t<float>(jobs, bg, pmax, s) : spread_batch_t<double>(jobs, bg, pmax, s);
 }
 
 hipError_t launch_interp_batch(const InterpJob *jobs, BatchGrid bg, int f32, hipStream_t s) {
@@ -470,19 +518,27 @@ hipError_t launch_spread_lists(const WaveArgs &w, int *count, const int *start, 
   return hipGetLastError();
 }
 
-hipError_t launch_spread_f64(const WaveArgs &w, const double *xt, const double *mut, double *grid, hipStream_t s) {
+template <typename T>
+static hipError_t spread_one(const WaveArgs &w, const T *xt, const T *mut, T *grid, hipStream_t s) {
+  using V2 = typename Vec2<T>::type;
   const int nt = w.nts * w.nts;
-  hipLaunchKernelGGL((k_spread<double, unsigned long long>), dim3(nt), dim3(256), spread_lds_bytes(w.P, 8), s, w.M, w.T, w.P, w.nts, w.h, w.ag, w.cg,
-                     w.slist_start, w.slist, (const double2 *)xt, (const int2 *)w.anchor, (const double2 *)mut, grid);
-  return hipGetLastError();
+  if (w.P < 1 || w.P > kPmax || w.T > kTmax) return hipErrorInvalidValue;
+  return spread_dispatch<T>(w.P, [&](auto pp) {
+    constexpr int PP = decltype(pp)::value;
+    const size_t lds = spread_lds_bytes<T, PP>();
+    hipLaunchKernelGGL((k_spread<T, PP>), dim3(nt), dim3(256), lds, s, w.M, w.T, w.P, w.nts,
+                       (T)w.h, (T)w.ag, (T)w.cg, w.slist_start, w.slist, (const V2 *)xt, (const int2 *)w.anchor,
+                       (const V2 *)mut, grid);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_spread_f64(const WaveArgs &w, const double *xt, const double *mut, double *grid, hipStream_t s) {
+  return spread_one<double>(w, xt, mut, grid, s);
 }
 
 hipError_t launch_spread_f32(const WaveArgs &w, const float *xt, const float *mut, float *grid, hipStream_t s) {
-  const int nt = w.nts * w.nts;
-  hipLaunchKernelGGL((k_spread<float, unsigned long long>), dim3(nt), dim3(256), spread_lds_bytes(w.P, 4), s, w.M, w.T, w.P, w.nts, (float)w.h, (float)w.ag,
-                     (float)w.cg, w.slist_start, w.slist, (const float2 *)xt, (const int2 *)w.anchor, (const float2 *)mut,
-                     grid);
-  return hipGetLastError();
+  return spread_one<float>(w, xt, mut, grid, s);
 }
 
 hipError_t launch_interp_f64(const WaveArgs &w, const double *xt, const int *tperm, const double *grid,
