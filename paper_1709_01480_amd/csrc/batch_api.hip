@@ -37,6 +37,7 @@ struct Tables {
   PrecondJob *pre;
   BatchGrid bg_nodes{}, bg_pair{}, bg_tiles{}, bg_spec{}, bg_bodies4{}, bg_prec{};
   size_t prec_lds = 0;
+  int prec_mfma = 0;  // row blocks per wave when every system takes the matrix-core form, else 0
   int spread_pmax = 1;  // largest stencil width P of the list
   Segs seg{};
   // per-system vectors (pointer tables) and leading dimension of the basis
@@ -389,6 +390,14 @@ fbim_status build_tables(BatchEngine *E, const std::vector<int> &list, Tables &T
   T.bg_bodies4.nblocks = b_bod.back();
   T.bg_prec.nblocks = b_prec.back();
   T.prec_lds = lds;
+  // the largest row-block count of the list, 0 if a system lacks the matrix-core form
+  T.prec_mfma = 0;
+  bool all_mfma = true;
+  for (int i : list) {
+    all_mfma = all_mfma && E->sys[i]->bt.mfma > 0;
+    T.prec_mfma = std::max(T.prec_mfma, E->sys[i]->bt.mfma);
+  }
+  if (!all_mfma) T.prec_mfma = 0;
   T.spread_pmax = 1;
   for (int i : list) T.spread_pmax = std::max(T.spread_pmax, E->sys[i]->d.P);
   T.seg.nchunk = (int)chunks.size();
@@ -464,7 +473,7 @@ Tables &tables_for(BatchEngine *E, const std::vector<int> &list, fbim_status &st
 // y = P^-1 bx for every system of T (into t1)
 fbim_status run_precond(BatchEngine *E, Tables &T) {
   Timer t(E->sys[0], "precond");
-  EHIP(E, launch_precond_batch(T.pre, T.bg_prec, T.prec_lds, E->stream));
+  EHIP(E, launch_precond_batch(T.pre, T.bg_prec, T.prec_lds, T.prec_mfma, E->stream));
   return FBIM_OK;
 }
 
@@ -556,6 +565,7 @@ std::vector<uint64_t> launch_signature(const BatchEngine *E, const Tables &T) {
     v.push_back(((uint64_t)(uint32_t)g->S << 32) | (uint32_t)g->nblocks);
   }
   v.push_back(T.prec_lds);
+  v.push_back((uint64_t)T.prec_mfma);
   v.push_back((uint64_t)T.spread_pmax);
   P(E->sys[0]->d_e1tab);
   P(E->sys[0]->d_e1tab32);
@@ -1102,7 +1112,6 @@ fbim_status em_rfd_batch(BatchEngine *E, const std::vector<fbim_ctx *> &mem, dou
                          const double *const *W_tilde, double *const *dQ, int32_t apply, fbim_info *info) {
   const int S = (int)mem.size();
   std::vector<fbim_info> inf(S);
-  std::vector<std::vector<double>> q0(S), th0(S), wt(S);
   fbim_status worst = FBIM_OK;
   for (int i = 0; i < S; ++i) {
     fbim_ctx *c = mem[i];
@@ -1111,29 +1120,21 @@ fbim_status em_rfd_batch(BatchEngine *E, const std::vector<fbim_ctx *> &mem, dou
     fbim_status st = brownian_slip(c, dt, W_r[i], W_grid[i], c->d_w, &inf[i]);
     if (st != FBIM_OK && st != FBIM_ENOCONV) return efail(E, st, c->err);
     if (st != FBIM_OK) worst = st;
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 2; ++k) {
       if (!c->rfd[k]) {
         EST(clone_ctx(c, &c->rfd[k]));
         c->rfd[k]->mlp_on = false;
       }
-    const int n = c->n;
-    wt[i].resize(3 * (size_t)n);
-    EHIP(E, hipMemcpyAsync(wt[i].data(), W_tilde[i], wt[i].size() * sizeof(double), hipMemcpyDeviceToHost,
-                           c->stream));
-    EHIP(E, hipStreamSynchronize(c->stream));
-    q0[i] = c->h_q;
-    th0[i] = c->h_theta;
-    std::vector<double> qs(2 * (size_t)n), ths(n);
-    for (int k = 0; k < 2; ++k) {
-      const double sg = k == 0 ? 0.5 * delta : -0.5 * delta;
-      for (int b = 0; b < n; ++b) {
-        qs[2 * b] = q0[i][2 * b] + sg * wt[i][3 * b];
-        qs[2 * b + 1] = q0[i][2 * b + 1] + sg * wt[i][3 * b + 1];
-        ths[b] = th0[i][b] + sg * wt[i][3 * b + 2];
-      }
       fbim_ctx *r = c->rfd[k];
       r->stream = c->stream;
-      st = fbim_set_bodies(r, n, c->h_shape.data(), qs.data(), ths.data());
+      if (!r->have_bodies || r->n != c->n || r->h_shape != c->h_shape) {
+        // first use (or new bodies): the copy takes the member's bodies at the
+        // configuration its caller last gave, then moves on the device
+        st = fbim_set_bodies(r, c->n, c->h_shape.data(), c->h_q.data(), c->h_theta.data());
+        if (st != FBIM_OK) return efail(E, st, fbim_last_error(r));
+      }
+      // Q +- delta/2 Wt, computed on the device from the member's configuration
+      st = move_bodies(r, c->d_q, c->d_theta, W_tilde[i], k == 0 ? 0.5 * delta : -0.5 * delta);
       if (st != FBIM_OK) return efail(E, st, fbim_last_error(r));
     }
   }
@@ -1184,25 +1185,17 @@ fbim_status em_rfd_batch(BatchEngine *E, const std::vector<fbim_ctx *> &mem, dou
     inf[i].status = sts[i];
   }
   if (apply) {
-    // move every member to Q + dQ; if one move is rejected (its context stays at
-    // Q), the members moved before it go back to Q as well
+    // move every member to Q + dQ on the device; if one move is rejected (its
+    // context stays at Q), the members moved before it go back to Q as well
     for (int i = 0; i < S; ++i) {
       fbim_ctx *c = mem[i];
-      const size_t n3 = 3 * (size_t)c->n;
-      std::vector<double> dq(n3);
-      EHIP(E, hipMemcpyAsync(dq.data(), dQ[i], n3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-      EHIP(E, hipStreamSynchronize(c->stream));
-      std::vector<double> qs(2 * (size_t)c->n), ths(c->n);
-      for (int b = 0; b < c->n; ++b) {
-        qs[2 * b] = q0[i][2 * b] + dq[3 * b];
-        qs[2 * b + 1] = q0[i][2 * b + 1] + dq[3 * b + 1];
-        ths[b] = th0[i][b] + dq[3 * b + 2];
-      }
-      const fbim_status st = fbim_set_bodies(c, c->n, c->h_shape.data(), qs.data(), ths.data());
+      const size_t n = c->n;
+      EHIP(E, hipMemcpyAsync(c->d_qstep, c->d_q, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      EHIP(E, hipMemcpyAsync(c->d_thstep, c->d_theta, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      const fbim_status st = move_bodies(c, c->d_qstep, c->d_thstep, dQ[i], 1.0);
       if (st != FBIM_OK) {
         const std::string msg = c->err;
-        for (int k = 0; k < i; ++k)
-          fbim_set_bodies(mem[k], mem[k]->n, mem[k]->h_shape.data(), q0[k].data(), th0[k].data());
+        for (int k = 0; k < i; ++k) move_bodies(mem[k], mem[k]->d_qstep, mem[k]->d_thstep, nullptr, 0.0);
         return efail(E, st, msg);
       }
     }

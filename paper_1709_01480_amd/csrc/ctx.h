@@ -97,6 +97,13 @@ struct fbim_ctx {
       *d_bc_start = nullptr;
   size_t bc_cap_n = 0, bc_cap_c = 0;
   double *d_q = nullptr, *d_theta = nullptr, *d_x = nullptr;
+  // device snapshots of (q, theta): the configuration before a move (restored when
+  // the move is rejected) and the configuration at the start of a step.  d_q and
+  // d_theta hold the current configuration; h_q / h_theta the one last given by
+  // the caller (steps move the bodies on the device).
+  double *d_qprev = nullptr, *d_thprev = nullptr, *d_qstep = nullptr, *d_thstep = nullptr;
+  double *h_qpin = nullptr;  // pinned staging of caller configurations (3 capn doubles)
+  int *h_pin = nullptr;      // pinned host words for small device -> host reads
   bool have_bodies = false;
 
   // cell list
@@ -300,6 +307,11 @@ fbim_status norm2(fbim_ctx *c, const double *x, size_t n, double &out);
 fbim_status brownian_slip(fbim_ctx *c, double dt, const double *W_r, const double *W_grid, double *slip_out,
                           fbim_info *info);
 fbim_status setup_fft(fbim_ctx *c);
+// move the bodies to (q_src, th_src) + a dQ (device arrays; dQ null: exactly
+// there) and rebuild the geometry; a rejected move restores the previous
+// configuration (device snapshot) and returns the error
+fbim_status move_bodies(fbim_ctx *c, const double *q_src, const double *th_src, const double *dQ, double a);
+
 // fills the noise arrays a call did not receive (NULL pointers; W_tilde may be
 // null when the call takes none) from the context's generator at one draw
 // counter, which is then advanced; the pointers are redirected to the draws

@@ -155,24 +155,31 @@ fbim_status ensure_krylov(fbim_ctx *c) {
   return FBIM_OK;
 }
 
-// tiles of up to body_tile_cap(2 n_p) same-shape bodies
+// tiles of same-shape bodies: kBodyMfmaCols per tile when every shape takes the
+// matrix-core form, else up to body_tile_cap(2 n_p)
 fbim_status build_body_tiles(fbim_ctx *c) {
   std::vector<int> list;
   std::vector<int4> tiles;
   size_t lds = 0;
+  bool mfma = true;
+  int n2max = 0;
+  for (auto &sh : c->shapes) {
+    mfma = mfma && body_mfma_ok(2 * sh.h.n_p);
+    n2max = std::max(n2max, 2 * sh.h.n_p);
+  }
   for (int sh = 0; sh < (int)c->shapes.size(); ++sh) {
     const int n2 = 2 * c->shapes[sh].h.n_p;
-    const int per = body_tile_cap(n2);
+    const int per = mfma ? kBodyMfmaCols : body_tile_cap(n2);
     const int first = (int)list.size();
     for (int b = 0; b < c->n; ++b)
       if (c->h_shape[b] == sh) list.push_back(b);
     const int cnt = (int)list.size() - first;
     for (int t = 0; t < cnt; t += per) tiles.push_back(make_int4(sh, first + t, std::min(per, cnt - t), 0));
-    if (cnt > 0) lds = std::max(lds, body_tile_lds(n2));
+    if (cnt > 0) lds = std::max(lds, mfma ? body_mfma_lds(n2) : body_tile_lds(n2));
   }
   STCHK(upload(c, c->d_blist, list));
   STCHK(upload(c, c->d_btile, tiles));
-  c->bt = BodyTiles{c->d_btile, c->d_blist, (int)tiles.size(), lds};
+  c->bt = BodyTiles{c->d_btile, c->d_blist, (int)tiles.size(), lds, mfma ? body_mfma_rb(n2max) : 0};
   return FBIM_OK;
 }
 
@@ -344,11 +351,10 @@ fbim_status mlp_refresh(fbim_ctx *c) {
 }
 
 // ------------------------------------------------------------------ geometry
-fbim_status build_geometry(fbim_ctx *c) {
-  const int N = c->N, n = c->n;
+// geometry of the configuration in d_q, d_theta
+fbim_status build_geometry_dev(fbim_ctx *c) {
+  const int N = c->N;
   hipStream_t s = c->stream;
-  HIPCHK(c, hipMemcpyAsync(c->d_q, c->h_q.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_theta, c->h_theta.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
   HIPCHK(c, launch_nodes(c->geom(), c->d.L, c->d_x, s));
   // cell list
   HIPCHK(c, hipMemsetAsync(c->d_ccount, 0, c->ncell * sizeof(int), s));
@@ -384,7 +390,7 @@ fbim_status build_geometry(fbim_ctx *c) {
   if (!fused)
     HIPCHK(c, launch_overlap(N, c->d_cstart, c->d_cperm, c->d_x, c->d_body, c->d.n_box, c->d.L, thresh,
                              c->d_scal_int + 1, s));
-  int hv[3];
+  int *hv = c->h_pin;  // pinned: no staging copy
   HIPCHK(c, hipMemcpyAsync(hv, c->d_scal_int, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   c->max_cell = hv[0];
@@ -400,12 +406,13 @@ fbim_status build_geometry(fbim_ctx *c) {
   HIPCHK(c, launch_scan(c->ngroups, c->d_gsize, c->d_goff, c->d_scal_int + 3, s));
   HIPCHK(c, launch_spread_lists(c->wave(), c->d_scount, nullptr, nullptr, 0, s));
   HIPCHK(c, launch_scan(c->ntile, c->d_scount, c->d_sstart, c->d_scal_int + 4, s));
-  int total[2] = {0, 0}, olap = 0, maxslots = 0;
-  HIPCHK(c, hipMemcpyAsync(&total[0], c->d_goff + c->ngroups, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipMemcpyAsync(&maxslots, c->d_scal_int + 3, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipMemcpyAsync(&total[1], c->d_sstart + c->ntile, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipMemcpyAsync(&olap, c->d_scal_int + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  int *pin = c->h_pin + 4;  // pinned: [0] pair slots, [1] spreading entries, [2] overlap flag, [3] longest group
+  HIPCHK(c, hipMemcpyAsync(pin + 0, c->d_goff + c->ngroups, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(pin + 3, c->d_scal_int + 3, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(pin + 1, c->d_sstart + c->ntile, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(pin + 2, c->d_scal_int + 1, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
+  const int total[2] = {pin[0], pin[1]}, olap = pin[2], maxslots = pin[3];
   if (olap) return fail(c, FBIM_EOVERLAP, overlap_msg);
   if ((size_t)total[0] > c->ell_cap) {
     const size_t cap = (size_t)total[0] + total[0] / 4 + 64;
@@ -424,6 +431,37 @@ fbim_status build_geometry(fbim_ctx *c) {
   HIPCHK(c, launch_spread_lists(c->wave(), nullptr, c->d_sstart, c->d_slist, 1, s));
   if (c->mlp_on) STCHK(mlp_refresh(c));
   return FBIM_OK;
+}
+
+// geometry of the caller's configuration h_q, h_theta (uploaded through pinned staging)
+fbim_status build_geometry(fbim_ctx *c) {
+  const size_t n = c->n;
+  hipStream_t s = c->stream;
+  HIPCHK(c, hipStreamSynchronize(s));  // the staging buffer may still feed an earlier upload
+  std::memcpy(c->h_qpin, c->h_q.data(), 2 * n * sizeof(double));
+  std::memcpy(c->h_qpin + 2 * n, c->h_theta.data(), n * sizeof(double));
+  HIPCHK(c, hipMemcpyAsync(c->d_q, c->h_qpin, 2 * n * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_theta, c->h_qpin + 2 * n, n * sizeof(double), hipMemcpyHostToDevice, s));
+  return build_geometry_dev(c);
+}
+
+fbim_status move_bodies(fbim_ctx *c, const double *q_src, const double *th_src, const double *dQ, double a) {
+  const size_t n = c->n;
+  hipStream_t s = c->stream;
+  HIPCHK(c, hipMemcpyAsync(c->d_qprev, c->d_q, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_thprev, c->d_theta, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, launch_move_bodies((int)n, q_src, th_src, dQ, a, c->d_q, c->d_theta, s));
+  const fbim_status st = build_geometry_dev(c);
+  if (st != FBIM_OK) {
+    const std::string msg = c->err;
+    fbim_status st2 = FBIM_OK;
+    if (hipMemcpyAsync(c->d_q, c->d_qprev, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(c->d_theta, c->d_thprev, n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+      st2 = FBIM_EDEVICE;
+    if (st2 != FBIM_OK || build_geometry_dev(c) != FBIM_OK) c->have_bodies = false;
+    c->err = msg;
+  }
+  return st;
 }
 
 // ------------------------------------------------------------------ matvec
@@ -731,9 +769,12 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
 }
 
 // Solve the saddle system to tol.  FP64 contexts: GMRES directly.  Mixed
-// contexts: iterative refinement -- the residual b - A x is formed with the
-// FP64 matvec, and each correction solves A d = r with GMRES on the FP32
-// matvec to a relative tolerance of 1e-3.
+// contexts, by default: relaxed-matvec GMRES (FP64 operator until the residual
+// estimate falls below kRelax ||b||, then the FP32 operator; every restart and
+// the stopping test use the FP64 residual).  With FBIM_FLAG_REFINEMENT: iterative
+// refinement -- the residual b - A x is formed with the FP64 matvec, and each
+// correction solves A d = r with GMRES on the FP32 matvec to a relative
+// tolerance of 1e-3.
 fbim_status solve_saddle(fbim_ctx *c, const double *b, double *x, double tol, int &iters, double &relres,
                          bool warm = false) {
   if (!c->mixed) return gmres(c, b, x, tol, iters, relres, c->gmres_max, warm);
@@ -1005,7 +1046,8 @@ fbim_status fbim_create(const fbim_params *params, fbim_ctx **out) {
   *out = nullptr;
   auto *c = new fbim_ctx();
   c->p = *params;
-  if (hipGetDevice(&c->device) != hipSuccess || resolve_noalloc_scratch(c) != FBIM_OK) {
+  if (hipGetDevice(&c->device) != hipSuccess || resolve_noalloc_scratch(c) != FBIM_OK ||
+      hipHostMalloc((void **)&c->h_pin, 16 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
     fbim_destroy(c);
     return FBIM_EDEVICE;
   }
@@ -1090,8 +1132,10 @@ void fbim_destroy(fbim_ctx *c) {
                   c->d_mut, c->d_src32, c->d_xt32, c->d_mut32, c->d_grid, c->d_spec, c->d_grid32,
                   c->d_spec32, c->d_e1tab, c->d_e1tab32, c->d_V, c->d_w, c->d_t1, c->d_t2, c->d_b, c->d_x2,
                   c->d_r, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
-                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU, c->d_bx, c->d_by, c->d_tw, c->d_tw32, c->d_ey, c->d_ey32, c->d_scount, c->d_sstart, c->d_slist, c->d_nz_r, c->d_nz_g, c->d_nz_t, c->d_bc_key, c->d_bc_perm, c->d_bc_count, c->d_bc_cursor, c->d_bc_start};
+                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU, c->d_bx, c->d_by, c->d_tw, c->d_tw32, c->d_ey, c->d_ey32, c->d_scount, c->d_sstart, c->d_slist, c->d_nz_r, c->d_nz_g, c->d_nz_t, c->d_bc_key, c->d_bc_perm, c->d_bc_count, c->d_bc_cursor, c->d_bc_start, c->d_qprev, c->d_thprev, c->d_qstep, c->d_thstep};
   pub_free(c->pub);
+  if (c->h_pin) hipHostFree(c->h_pin);
+  if (c->h_qpin) hipHostFree(c->h_qpin);
   engine_delete(c->rfd_engine);
   for (fbim_ctx *r : c->rfd)
     if (r) fbim_destroy(r);
@@ -1154,6 +1198,9 @@ fbim_status fbim_set_bodies(fbim_ctx *c, int32_t n, const int32_t *shape_id, con
     // same bodies moved: only positions and angles change.  A rejected move
     // (overlap, device error) rebuilds the previous configuration, so the
     // context stays where it was.
+    hipStream_t s = c->stream;
+    HIPCHK(c, hipMemcpyAsync(c->d_qprev, c->d_q, 2 * (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d_thprev, c->d_theta, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
     std::vector<double> q_old = c->h_q, th_old = c->h_theta;
     c->h_q.assign(q, q + 2 * n);
     c->h_theta.assign(theta, theta + n);
@@ -1162,7 +1209,12 @@ fbim_status fbim_set_bodies(fbim_ctx *c, int32_t n, const int32_t *shape_id, con
       const std::string msg = c->err;
       c->h_q.swap(q_old);
       c->h_theta.swap(th_old);
-      if (build_geometry(c) != FBIM_OK) c->have_bodies = false;
+      if (hipMemcpyAsync(c->d_q, c->d_qprev, 2 * (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+              hipSuccess ||
+          hipMemcpyAsync(c->d_theta, c->d_thprev, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+              hipSuccess ||
+          build_geometry_dev(c) != FBIM_OK)
+        c->have_bodies = false;
       c->err = msg;
     }
     return st;
@@ -1179,6 +1231,16 @@ fbim_status fbim_set_bodies(fbim_ctx *c, int32_t n, const int32_t *shape_id, con
     HIPCHK(c, dalloc(c->d_off, n + 1));
     HIPCHK(c, dalloc(c->d_q, 2 * n));
     HIPCHK(c, dalloc(c->d_theta, n));
+    HIPCHK(c, dalloc(c->d_qprev, 2 * n));
+    HIPCHK(c, dalloc(c->d_thprev, n));
+    HIPCHK(c, dalloc(c->d_qstep, 2 * n));
+    HIPCHK(c, dalloc(c->d_thstep, n));
+    if (c->h_qpin) {
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      hipHostFree(c->h_qpin);
+      c->h_qpin = nullptr;
+    }
+    HIPCHK(c, hipHostMalloc((void **)&c->h_qpin, 3 * (size_t)n * sizeof(double), hipHostMallocDefault));
     c->capn = n;
   }
   if (realloc_N) {
@@ -1336,36 +1398,28 @@ fbim_status fbim_step_em_rfd(fbim_ctx *c, double dt, double delta, const double 
   hipStream_t s = c->stream;
   const int n = c->n;
   const size_t n3 = 3 * (size_t)n;
-  std::vector<double> wt(n3), q0 = c->h_q, th0 = c->h_theta, qs(2 * n), ths(n);
-  std::vector<int> sid = c->h_shape;
+  // Q^n on the device; every configuration of the step is moved from it there
+  HIPCHK(c, hipMemcpyAsync(c->d_qstep, c->d_q, 2 * (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_thstep, c->d_theta, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
   // any error after the configuration has left Q puts the bodies back at Q
   struct BackToQ {
     fbim_ctx *c;
-    const std::vector<int> &sid;
-    const std::vector<double> &q, &th;
-    bool armed = true;
+    bool moved = false, armed = true;
     ~BackToQ() {
-      if (!armed) return;
+      if (!armed || !moved || !c->have_bodies) return;
       const std::string msg = c->err;
-      if (c->have_bodies && (c->h_q != q || c->h_theta != th))
-        fbim_set_bodies(c, (int)th.size(), sid.data(), q.data(), th.data());
+      move_bodies(c, c->d_qstep, c->d_thstep, nullptr, 0.0);
       c->err = msg;
     }
-  } guard{c, sid, q0, th0};
+  } guard{c};
   // U0 = N F + sqrt(2kT/dt) N^(1/2) W at Q
   fbim_status st = brownian(c, dt, F, W_r, W_grid, c->d_U3, info);
   if (st != FBIM_OK && st != FBIM_ENOCONV) return st;
   fbim_status worst = st;
-  HIPCHK(c, hipMemcpyAsync(wt.data(), W_tilde, n3 * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipStreamSynchronize(s));
   // RFD solves N(Q +- delta/2 Wt) Wt
   for (int sgn = 1; sgn >= -1; sgn -= 2) {
-    for (int b = 0; b < n; ++b) {
-      qs[2 * b] = q0[2 * b] + sgn * 0.5 * delta * wt[3 * b];
-      qs[2 * b + 1] = q0[2 * b + 1] + sgn * 0.5 * delta * wt[3 * b + 1];
-      ths[b] = th0[b] + sgn * 0.5 * delta * wt[3 * b + 2];
-    }
-    STCHK(fbim_set_bodies(c, n, sid.data(), qs.data(), ths.data()));
+    guard.moved = true;
+    STCHK(move_bodies(c, c->d_qstep, c->d_thstep, W_tilde, sgn * 0.5 * delta));
     int it = 0;
     double res = 0;
     // the second configuration starts from the first one's solution (same right-hand
@@ -1383,19 +1437,8 @@ fbim_status fbim_step_em_rfd(fbim_ctx *c, double dt, double delta, const double 
   HIPCHK(c, launch_axpby(n3, dt, c->d_U3, 0.0, dQ, s));
   HIPCHK(c, launch_axpby(n3, dt * c->p.kT / delta, c->d_U4, 1.0, dQ, s));
   HIPCHK(c, launch_axpby(n3, -dt * c->p.kT / delta, c->d_U5, 1.0, dQ, s));
-  if (apply) {
-    std::vector<double> dq(n3);
-    HIPCHK(c, hipMemcpyAsync(dq.data(), dQ, n3 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    for (int b = 0; b < n; ++b) {
-      qs[2 * b] = q0[2 * b] + dq[3 * b];
-      qs[2 * b + 1] = q0[2 * b + 1] + dq[3 * b + 1];
-      ths[b] = th0[b] + dq[3 * b + 2];
-    }
-    STCHK(fbim_set_bodies(c, n, sid.data(), qs.data(), ths.data()));
-  } else {
-    STCHK(fbim_set_bodies(c, n, sid.data(), q0.data(), th0.data()));
-  }
+  // Q^{n+1} = Q^n + dQ (apply), else back to Q^n
+  STCHK(move_bodies(c, c->d_qstep, c->d_thstep, apply ? dQ : nullptr, 1.0));
   guard.armed = false;
   HIPCHK(c, hipStreamSynchronize(s));
   if (info) {

@@ -20,6 +20,9 @@ struct GeomDev {
 
 // nodes (wrapped into [0, L)) -> x[2N]
 hipError_t launch_nodes(const GeomDev &g, double L, double *x, hipStream_t s);
+// bodies moved on the device: q = q_src + a dQ_xy, theta = th_src + a dQ_theta (dQ [3n] or null)
+hipError_t launch_move_bodies(int n, const double *q_src, const double *th_src, const double *dQ, double a,
+                              double *q, double *theta, hipStream_t s);
 
 // binning: key per node, counts (atomic), exclusive scan, scatter, in-bin sort
 hipError_t launch_cell_keys(int N, const double *x, double L, int nb, int *key, int *count, hipStream_t s);
@@ -188,7 +191,16 @@ struct BodyTiles {
   const int *list;
   int ntile;
   size_t lds_bytes;
+  int mfma = 0;  // matrix-core form: row blocks per wave (body_mfma_rb), 0: the other form
 };
+// The FP64 matrix-core form of the per-body operators: tiles of 16 bodies, the
+// shared matrix times the tile's body-frame vectors as 16 x 16 x 4 FP64 MFMA
+// blocks.  It serves shapes with 16 | 2 n_p and 2 n_p <= 256.
+constexpr int kBodyMfmaCols = 16;
+__host__ __device__ inline bool body_mfma_ok(int n2) { return n2 % 16 == 0 && n2 >= 32 && n2 <= 256; }
+__host__ __device__ inline size_t body_mfma_lds(int n2) { return (size_t)n2 * kBodyMfmaCols * sizeof(double); }
+// 16-row blocks of the product per wave (four waves) for the largest 2 n_p of the tiles
+__host__ __device__ inline int body_mfma_rb(int n2max) { return n2max <= 64 ? 1 : (n2max <= 128 ? 2 : 4); }
 // block-diagonal saddle preconditioner: z = [a (2N) | b (3n)] -> y = [mu | U];
 // dN (optional, [n][6] = xx, yy, tt, xy, xt, yt) corrects N_ref per body in the body frame
 hipError_t launch_precond(const GeomDev &g, const BodyMats &m, const BodyTiles &bt, const double *dN,
@@ -387,7 +399,10 @@ hipError_t launch_multiplier_batch(const MultJob *jobs, BatchGrid bg, int f32, i
 hipError_t launch_rigid_batch(const RigidJob *jobs, BatchGrid bg_nodes, BatchGrid bg_bodies, hipStream_t s);
                                                                         // ceil(N/256); bodies: ceil(n/4) (64 per body)
 // bt.ntile blocks per system; lds_bytes = the largest bt.lds_bytes of the systems
-hipError_t launch_precond_batch(const PrecondJob *jobs, BatchGrid bg, size_t lds_bytes, hipStream_t s);
+// all_mfma: row blocks per wave when every system's tiles take the matrix-core form (a kernel
+// without the other form), else 0
+hipError_t launch_precond_batch(const PrecondJob *jobs, BatchGrid bg, size_t lds_bytes, int all_mfma,
+                                hipStream_t s);
 
 // learned preconditioner correction (MLP 32 -> 128 -> 128 -> 6, tanh)
 constexpr int kMlpNeighbours = 6, kMlpIn = 32, kMlpHid = 128, kMlpOut = 6;

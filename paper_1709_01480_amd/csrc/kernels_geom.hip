@@ -26,6 +26,30 @@ __global__ void k_nodes(int N, const int *__restrict__ body, const int *__restri
   x[2 * i + 1] = py;
 }
 
+// q[b] = q_src[b] + a dQ[3b, 3b+1], theta[b] = theta_src[b] + a dQ[3b+2] (dQ null: a copy);
+// in place when q_src == q
+__global__ void k_move_bodies(int n, const double *q_src, const double *th_src, const double *__restrict__ dQ,
+                              double a, double *q, double *theta) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  double qx = q_src[2 * b], qy = q_src[2 * b + 1], th = th_src[b];
+  if (dQ) {
+    qx += a * dQ[3 * b];
+    qy += a * dQ[3 * b + 1];
+    th += a * dQ[3 * b + 2];
+  }
+  q[2 * b] = qx;
+  q[2 * b + 1] = qy;
+  theta[b] = th;
+}
+
+hipError_t launch_move_bodies(int n, const double *q_src, const double *th_src, const double *dQ, double a,
+                              double *q, double *theta, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_move_bodies, dim3((n + 255) / 256), dim3(256), 0, s, n, q_src, th_src, dQ, a, q, theta);
+  return hipGetLastError();
+}
+
 hipError_t launch_nodes(const GeomDev &g, double L, double *x, hipStream_t s) {
   if (g.N == 0) return hipSuccess;
   hipLaunchKernelGGL(k_nodes, dim3((g.N + 255) / 256), dim3(256), 0, s, g.N, g.body, g.off, g.shape, g.q,

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -383,6 +384,205 @@ __device__ __forceinline__ void body_tile(const BodyTiles &bt, int tile, const i
   }
 }
 
+// The same operators on the FP64 matrix cores, 16 bodies per 256-thread work
+// group (columns of one 16 x 16 x 4 MFMA block).  MODE 1 forms the rigid-body
+// part before the product: with M_ref^+ symmetric, f = K_ref^T M_ref^+ a~ =
+// P_ref^T a~ (P_ref = M_ref^+ K_ref), so U_ref = -N_ref (R'^T b + P_ref^T a~) is
+// known first and mu_ref = M_ref^+ (a~ + K_ref U_ref) is a single product.
+// v_mfma_f64_16x16x4f64 operands (checked on the device): lane l holds A(l % 16,
+// l / 16) and B(l / 16, l % 16) and item r of its accumulator is D(4 r + l / 16,
+// l % 16).  Wave w computes the 16-row blocks w, w + 4, ... of the n2 x 16 product;
+// the shared matrix comes from global memory (L2-resident, 128-byte rows per
+// step), the tile's vectors from LDS.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <int MODE, int RB>
+__device__ __forceinline__ void body_mfma(const BodyTiles &bt, int tile, const int *__restrict__ off,
+                                          const double *__restrict__ theta, const double *const *ref,
+                                          const int *__restrict__ np, const double *const *X,
+                                          const double *const *Pref, const double *const *Nt,
+                                          const double *__restrict__ dN, int N, const double *__restrict__ z,
+                                          double *__restrict__ y) {
+  constexpr int NB = kBodyMfmaCols;
+  constexpr int kLd = NB * 256 / 2 / 256;  // node pairs per thread at 2 n_p = 256 (loads in flight)
+  extern __shared__ double sm[];           // T[k][NB]: body-frame inputs, then the product
+  __shared__ double cs_[NB], sn_[NB], Ur[NB][3], fpart[4][NB][3];
+  __shared__ double Ps[MODE == 1 ? 3 * 256 : 1], rfs[MODE == 1 ? 256 : 1];  // P_ref, reference nodes
+  __shared__ int base_[NB];
+  const int4 tl = bt.tile[tile];
+  const int sh = tl.x, nb = tl.z;
+  const int npt = np[sh], n2 = 2 * npt;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (MODE == 1) {  // P_ref and the reference nodes into LDS
+    const double *Pm = Pref[sh], *rf = ref[sh];
+    for (int i = tid; i < 3 * n2; i += 256) Ps[i] = Pm[i];
+    for (int i = tid; i < n2; i += 256) rfs[i] = rf[i];
+  }
+  // MODE 1: each body's rigid-body inputs, requested now (used after the first products)
+  double bq[3] = {0.0, 0.0, 0.0}, dq[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, nm[9];
+  if (tid < NB) {
+    double sn = 0.0, cs = 0.0;
+    int bs = 0;
+    if (tid < nb) {
+      const int b = bt.list[tl.y + tid];
+      if (MODE == 1) {
+        const double *bb = z + 2 * (size_t)N + 3 * (size_t)b;
+        bq[0] = bb[0];
+        bq[1] = bb[1];
+        bq[2] = bb[2];
+        if (dN)
+#pragma unroll
+          for (int q = 0; q < 6; ++q) dq[q] = dN[6 * (size_t)b + q];
+        const double *Nm = Nt[sh];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) nm[q] = Nm[q];
+      }
+      sincos(theta[b], &sn, &cs);
+      bs = off[b];
+    }
+    cs_[tid] = cs;
+    sn_[tid] = sn;
+    base_[tid] = bs;
+  }
+  __syncthreads();
+  // body-frame inputs: T[2t + c][j] = (R_j^T a_j)_{t, c}; columns of absent bodies are zero.
+  // Every load of a thread is issued before the first is used.
+  {
+    double2 av[kLd];
+#pragma unroll
+    for (int u = 0; u < kLd; ++u) {
+      const int idx = tid + 256 * u, j = idx / npt, t = idx - j * npt;
+      av[u] = make_double2(0.0, 0.0);
+      if (idx < NB * npt && j < nb) av[u] = reinterpret_cast<const double2 *>(z)[base_[j] + t];
+    }
+#pragma unroll
+    for (int u = 0; u < kLd; ++u) {
+      const int idx = tid + 256 * u, j = idx / npt, t = idx - j * npt;
+      if (idx < NB * npt) {
+        sm[(2 * t) * NB + j] = cs_[j] * av[u].x + sn_[j] * av[u].y;
+        sm[(2 * t + 1) * NB + j] = -sn_[j] * av[u].x + cs_[j] * av[u].y;
+      }
+    }
+  }
+  __syncthreads();
+  if constexpr (MODE == 1) {
+    // f_j = P_ref^T a~_j: thread (j = tid % 16, part p = tid / 16) sums rows p, p + 16, ...
+    const int j = tid % NB, p = tid / NB;
+    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+    for (int k = p; k < n2; k += 256 / NB) {
+      const double a = sm[k * NB + j];
+      f0 = fma(Ps[k], a, f0);
+      f1 = fma(Ps[n2 + k], a, f1);
+      f2 = fma(Ps[2 * n2 + k], a, f2);
+    }
+    // the four parts of a wave that share j (lanes j, j + 16, j + 32, j + 48)
+    f0 += __shfl_xor(f0, 16);
+    f1 += __shfl_xor(f1, 16);
+    f2 += __shfl_xor(f2, 16);
+    f0 += __shfl_xor(f0, 32);
+    f1 += __shfl_xor(f1, 32);
+    f2 += __shfl_xor(f2, 32);
+    if (lane < NB) {
+      fpart[wv][lane][0] = f0;
+      fpart[wv][lane][1] = f1;
+      fpart[wv][lane][2] = f2;
+    }
+    __syncthreads();
+    if (tid < nb) {
+      const int jj = tid, b = bt.list[tl.y + jj];
+      const double cs = cs_[jj], sn = sn_[jj];
+      const double *d = dq;
+      const double bx = bq[0], by = bq[1], b2 = bq[2];
+      const double b0 = cs * bx + sn * by, b1 = -sn * bx + cs * by;
+      double g[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) g[q] = ((fpart[0][jj][q] + fpart[1][jj][q]) + (fpart[2][jj][q] + fpart[3][jj][q]));
+      g[0] += b0;
+      g[1] += b1;
+      g[2] += b2;
+      const double u0 = -(nm[0] * g[0] + nm[1] * g[1] + nm[2] * g[2]);
+      const double u1 = -(nm[3] * g[0] + nm[4] * g[1] + nm[5] * g[2]);
+      const double u2 = -(nm[6] * g[0] + nm[7] * g[1] + nm[8] * g[2]);
+      Ur[jj][0] = u0;
+      Ur[jj][1] = u1;
+      Ur[jj][2] = u2;
+      // learned correction C = dN_b (xx, yy, tt, xy, xt, yt): mu unchanged, U gains -C R'^T b
+      const double v0 = u0 - (d[0] * b0 + d[3] * b1 + d[4] * b2);
+      const double v1 = u1 - (d[3] * b0 + d[1] * b1 + d[5] * b2);
+      const double v2 = u2 - (d[4] * b0 + d[5] * b1 + d[2] * b2);
+      double *yU = y + 2 * (size_t)N + 3 * (size_t)b;
+      yU[0] = cs * v0 - sn * v1;
+      yU[1] = sn * v0 + cs * v1;
+      yU[2] = v2;
+    } else if (tid < NB) {
+      Ur[tid][0] = Ur[tid][1] = Ur[tid][2] = 0.0;
+    }
+    __syncthreads();
+    // a~ + K_ref U_ref: (u_x - omega r_y, u_y + omega r_x) at each reference node
+    for (int idx = tid; idx < NB * npt; idx += 256) {
+      const int j = idx % NB, t = idx / NB;
+      sm[(2 * t) * NB + j] += Ur[j][0] - Ur[j][2] * rfs[2 * t + 1];
+      sm[(2 * t + 1) * NB + j] += Ur[j][1] + Ur[j][2] * rfs[2 * t];
+    }
+    __syncthreads();
+  }
+  // product X T on the matrix cores (X[k n2 + r] multiplies input k of output r), the
+  // operands of kStep k-steps loaded before their products
+  constexpr int kStep = 16;
+  const double *__restrict__ Xm = X[sh];
+  const int nrb = n2 / 16, nk = n2 / 4, li = lane & 15, lk = lane >> 4;
+  constexpr int kMaxRb = RB;          // row blocks per wave at the largest n2 of the launch
+  const int nq = (nrb - wv + 3) / 4;  // this wave's row blocks wv, wv + 4, ...
+  f64x4 acc[kMaxRb];
+#pragma unroll
+  for (int q = 0; q < kMaxRb; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const double *xa = Xm + (size_t)lk * n2 + 16 * wv + li;
+  const double *tb = sm + lk * NB + li;
+  for (int s0 = 0; s0 < nk; s0 += kStep) {
+    // one batch: the X operands of every row block of the wave, then the products
+    double xv[kMaxRb][kStep], tv[kStep];
+#pragma unroll
+    for (int u = 0; u < kStep; ++u) {
+      const bool ok = s0 + u < nk;
+      tv[u] = ok ? tb[4 * (s0 + u) * NB] : 0.0;
+#pragma unroll
+      for (int q = 0; q < kMaxRb; ++q)
+        xv[q][u] = (ok && q < nq) ? xa[(size_t)(4 * (s0 + u)) * n2 + 64 * q] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxRb; ++q)
+      if (q < nq)
+#pragma unroll
+        for (int u = 0; u < kStep; ++u)
+          if (s0 + u < nk) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[q][u], tv[u], acc[q], 0, 0, 0);
+  }
+  __syncthreads();  // every wave is done reading T
+#pragma unroll
+  for (int q = 0; q < kMaxRb; ++q) {
+    const int rb = wv + 4 * q;
+    if (rb < nrb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sm[(16 * rb + 4 * r + lk) * NB + li] = acc[q][r];
+  }
+  __syncthreads();
+  // back to the lab frame, each body's nodes written contiguously
+  for (int idx = tid; idx < nb * npt; idx += 256) {
+    const int j = idx / npt, t = idx - j * npt;
+    const double mx = sm[(2 * t) * NB + j], my = sm[(2 * t + 1) * NB + j];
+    reinterpret_cast<double2 *>(y)[base_[j] + t] = make_double2(cs_[j] * mx - sn_[j] * my, sn_[j] * mx + cs_[j] * my);
+  }
+}
+
+template <int MODE, int RB>
+__global__ __launch_bounds__(256) void k_body_mfma(BodyTiles bt, const int *__restrict__ off,
+                                                   const double *__restrict__ theta, const double *const *ref,
+                                                   const int *__restrict__ np, const double *const *X,
+                                                   const double *const *Pref, const double *const *Nt,
+                                                   const double *__restrict__ dN, int N,
+                                                   const double *__restrict__ z, double *__restrict__ y) {
+  body_mfma<MODE, RB>(bt, blockIdx.x, off, theta, ref, np, X, Pref, Nt, dN, N, z, y);
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_body_tile(BodyTiles bt, const int *__restrict__ off,
                                                    const double *__restrict__ theta, const double *const *ref,
@@ -396,12 +596,42 @@ __global__ __launch_bounds__(256) void k_body_tile(BodyTiles bt, const int *__re
 __global__ __launch_bounds__(256) void k_precond_batch(const PrecondJob *__restrict__ jobs, BatchGrid bg) {
   const int s = batch_system(bg.begin, bg.S, blockIdx.x);
   const PrecondJob &j = jobs[s];
-  body_tile<1>(j.bt, blockIdx.x - bg.begin[s], j.g.off, j.g.theta, j.g.ref, j.g.np, j.m.Mp, j.m.Pref, j.m.Nt, j.dN,
+  if (j.bt.mfma)  // a list mixing both forms: the instance for every n2
+    body_mfma<1, 4>(j.bt, blockIdx.x - bg.begin[s], j.g.off, j.g.theta, j.g.ref, j.g.np, j.m.Mp, j.m.Pref, j.m.Nt, j.dN,
+                 j.g.N, j.z, j.y);
+  else
+    body_tile<1>(j.bt, blockIdx.x - bg.begin[s], j.g.off, j.g.theta, j.g.ref, j.g.np, j.m.Mp, j.m.Pref, j.m.Nt, j.dN,
+                 j.g.N, j.z, j.y);
+}
+
+template <int RB>
+__global__ __launch_bounds__(256) void k_precond_mfma_batch(const PrecondJob *__restrict__ jobs, BatchGrid bg) {
+  const int s = batch_system(bg.begin, bg.S, blockIdx.x);
+  const PrecondJob &j = jobs[s];
+  body_mfma<1, RB>(j.bt, blockIdx.x - bg.begin[s], j.g.off, j.g.theta, j.g.ref, j.g.np, j.m.Mp, j.m.Pref, j.m.Nt, j.dN,
                j.g.N, j.z, j.y);
 }
 
-hipError_t launch_precond_batch(const PrecondJob *jobs, BatchGrid bg, size_t lds_bytes, hipStream_t s) {
+// the matrix-core instance for `rb` row blocks per wave
+template <typename F>
+static hipError_t body_mfma_dispatch(int rb, F &&launch) {
+  switch (rb) {
+    case 1: return launch(std::integral_constant<int, 1>{});
+    case 2: return launch(std::integral_constant<int, 2>{});
+    case 4: return launch(std::integral_constant<int, 4>{});
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_precond_batch(const PrecondJob *jobs, BatchGrid bg, size_t lds_bytes, int all_mfma,
+                                hipStream_t s) {
   if (bg.nblocks == 0) return hipSuccess;
+  if (all_mfma)
+    return body_mfma_dispatch(all_mfma, [&](auto rb) {
+      hipLaunchKernelGGL((k_precond_mfma_batch<decltype(rb)::value>), dim3(bg.nblocks), dim3(256), lds_bytes, s,
+                         jobs, bg);
+      return hipGetLastError();
+    });
   hipLaunchKernelGGL(k_precond_batch, dim3(bg.nblocks), dim3(256), lds_bytes, s, jobs, bg);
   return hipGetLastError();
 }
@@ -409,16 +639,28 @@ hipError_t launch_precond_batch(const PrecondJob *jobs, BatchGrid bg, size_t lds
 hipError_t launch_precond(const GeomDev &g, const BodyMats &m, const BodyTiles &bt, const double *dN,
                           const double *z, double *y, hipStream_t s) {
   if (g.n == 0) return hipSuccess;
+  if (bt.mfma)
+    return body_mfma_dispatch(bt.mfma, [&](auto rb) {
+      hipLaunchKernelGGL((k_body_mfma<1, decltype(rb)::value>), dim3(bt.ntile), dim3(256), bt.lds_bytes, s, bt, g.off,
+                         g.theta, g.ref, g.np, m.Mp, m.Pref, m.Nt, dN, g.N, z, y);
+      return hipGetLastError();
+    });
   hipLaunchKernelGGL(k_body_tile<1>, dim3(bt.ntile), dim3(256), bt.lds_bytes, s, bt, g.off, g.theta, g.ref, g.np,
-                     m.Mp, m.Pref, m.Nt, dN, g.N, z, y);
+                       m.Mp, m.Pref, m.Nt, dN, g.N, z, y);
   return hipGetLastError();
 }
 
 hipError_t launch_body_apply(const GeomDev &g, const BodyMats &m, const BodyTiles &bt, int which, const double *x,
                              double *y, hipStream_t s) {
   if (g.n == 0) return hipSuccess;
+  if (bt.mfma)
+    return body_mfma_dispatch(bt.mfma, [&](auto rb) {
+      hipLaunchKernelGGL((k_body_mfma<0, decltype(rb)::value>), dim3(bt.ntile), dim3(256), bt.lds_bytes, s, bt, g.off,
+                         g.theta, g.ref, g.np, which ? m.Gp : m.G, m.Pref, m.Nt, (const double *)nullptr, g.N, x, y);
+      return hipGetLastError();
+    });
   hipLaunchKernelGGL(k_body_tile<0>, dim3(bt.ntile), dim3(256), bt.lds_bytes, s, bt, g.off, g.theta, g.ref, g.np,
-                     which ? m.Gp : m.G, m.Pref, m.Nt, (const double *)nullptr, g.N, x, y);
+                       which ? m.Gp : m.G, m.Pref, m.Nt, (const double *)nullptr, g.N, x, y);
   return hipGetLastError();
 }
 
