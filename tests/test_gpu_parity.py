@@ -11,9 +11,13 @@ reached only through other GPU results:
   - a batch of two suspensions of different sizes through the batched step,
     each member against the oracle step;
   - the mixed-precision matvec on power-of-two grids, where the fused FP32
-    transform kernels run, against the oracle's parts.
+    transform kernels run, against the oracle's parts;
+  - the whole EM-RFD step of the 100-starfish suspension (12,800 nodes, grid
+    256^2), FP64 and the flagship flag set, against the matrix-free oracle's
+    displacement stored under tests/golden/.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -169,3 +173,38 @@ def test_mixed_matvec_on_power_of_two_grid(name):
         alp[sl] = blk @ mu[sl]
     ctx.apply_M(dev(mu), out, fb.PART_ALL)
     assert relerr(host(out), real + alp + wave) < 2e-6
+
+
+def _golden_starfish100():
+    path = os.path.join(os.path.dirname(__file__), "golden", "starfish100_em_rfd.txt")
+    with open(path) as f:
+        lines = f.read().splitlines()
+    rows = np.array([[float(v) for v in ln.split()] for ln in lines if not ln.startswith("#")])
+    delta = float([ln for ln in lines if ln.startswith("# kT")][0].split()[6])
+    return rows[:, 1:4].ravel(), rows[:, 4:7].ravel(), delta
+
+
+@pytest.mark.parametrize("form", ["fp64", "flagship"])
+def test_starfish100_step_matches_matrix_free_oracle(form):
+    # 100 bodies x 128 nodes, grid 256^2: the full EM-RFD step (eq. 4.3) against the
+    # matrix-free oracle's displacement stored by tests/golden/make_starfish100_step.py
+    import paper_1709_01480_amd as fb
+    wl = workload("starfish100")
+    log("starfish100 step %s" % form)
+    ref, _, delta = _golden_starfish100()
+    if form == "fp64":
+        ctx = make_ctx(wl, tol_gmres=1e-10, tol_lanczos=1e-10)
+        bar = 1e-6
+    else:
+        flags = fb.FLAG_BATCH_RFD | fb.FLAG_GRAPH | fb.FLAG_BASIS32
+        ctx = make_ctx(wl, precision=fb.PREC_MIXED, flags=flags, tol_gmres=1e-8, tol_lanczos=1e-8)
+        ctx.mlp_init(seed=3, sym_order=wl.n_arm)
+        ctx.mlp_use(True)
+        bar = 1e-4
+    M = ctx.get_derived()["grid_M"]
+    Wr, Wg, Wt = W.noise(wl, M)
+    dQ = zeros(3 * wl.n_bodies)
+    info = ctx.step_em_rfd(wl.dt, delta, dev(wl.F), dev(Wr), dev(Wg), dev(Wt), dQ)
+    err = relerr(host(dQ), ref)
+    log("starfish100 %s: rel err %.3e, %s" % (form, err, info))
+    assert err < bar
