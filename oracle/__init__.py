@@ -16,7 +16,14 @@ Modules
   fbim     geometry, Ewald-split Stokeslet kernels, dense single-layer
            matrix, saddle-point mobility, Brownian velocity, EM-RFD step
   direct   O(N^2) real-space and direct k-space sums in plain C (OpenMP)
-           for sizes where dense numpy assembly is too large
+           for sizes where dense numpy assembly is too large; the cell-list
+           real-space sum and the Gaussian gridding of the fast path
+  matfree  the Brownian step without assembling M (GMRES, Lanczos)
+  fastpath the FP64 CPU fast path of the matvec (cell list, shared Alpert
+           block, spectral Ewald) that the GPU is timed beside
+  precond  the block-diagonal preconditioner and a plain GMRES
+  philox   Philox4x32-10 and Box-Muller, the library's noise generator
+  mlp      the learned correction's network, forward and backward
 
 Functions whose result is pinned only by consistency (no closed form or
 printed value) say "parity unpinned" in their docstring.
