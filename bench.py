@@ -253,48 +253,59 @@ def roofline(kt, xh, wl, d):
 
 
 def run_batch(args, fb, W, np, torch):
-    """The uneven-suspension batch (64 suspensions, bodies log-uniform in [16, 512],
-    64 / 128 / 256 nodes per body): one batched mobility solve of all of them
-    (graphs on) against the same member contexts solving one after another.
-    One JSON line per precision on stdout."""
+    """The uneven-suspension batch: 64 independent suspensions, bodies per
+    suspension log-uniform in [16, 512], 64 / 128 / 256 nodes per body, mixed
+    precision with the FP32 Krylov basis.  One batched EM-RFD step of all of them
+    (three mobility solves per suspension in lockstep launch sets, preconditioner
+    and saddle operator replayed from graphs, noise drawn by each member, bodies
+    moved) against the same member contexts stepping one after another.  One
+    JSON line on stdout."""
     wls = W.uneven_suspensions(64)
+    prms = []
+    for k, wl in enumerate(wls):
+        p = wl.params()
+        p.update(precision=fb.PREC_MIXED, flags=fb.FLAG_BASIS32, seed=W.noise_key(wl, 100 + k))
+        prms.append(p)
+    b = fb.Batch(prms, graph=True)
+    for m, wl in zip(b.members, wls):
+        sid = m.add_shape(fb.starfish(wl.r_s, wl.b, wl.n_arm, wl.n_p))
+        m.set_bodies(np.full(wl.n_bodies, sid), wl.q, wl.theta)
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
-    for prec, flags, label in ((fb.PREC_FP64, 0, "fp64"), (fb.PREC_MIXED, fb.FLAG_BASIS32, "mixed+basis32")):
-        prms = []
-        for wl in wls:
-            p = wl.params()
-            p.update(precision=prec, flags=flags)
-            prms.append(p)
-        b = fb.Batch(prms, graph=True)
-        for m, wl in zip(b.members, wls):
-            sid = m.add_shape(fb.starfish(wl.r_s, wl.b, wl.n_arm, wl.n_p))
-            m.set_bodies(np.full(wl.n_bodies, sid), wl.q, wl.theta)
-        Fs = [dev(wl.F) for wl in wls]
-        Us = [torch.zeros(3 * wl.n_bodies, dtype=torch.float64, device="cuda") for wl in wls]
-        for _ in range(max(1, args.warmup)):
-            b.mobility(Fs, Us)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            infos = b.mobility(Fs, Us)
-        torch.cuda.synchronize()
-        t_b = (time.perf_counter() - t0) / args.steps
-        for m, F, U in zip(b.members, Fs, Us):  # warm the single-system paths
-            m.mobility(F, U)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        its = 0
-        for m, F, U in zip(b.members, Fs, Us):
-            its += m.mobility(F, U)["gmres_iters"]
-        torch.cuda.synchronize()
-        t_s = time.perf_counter() - t0
-        print(json.dumps({"mode": "batch", "precision": label, "suspensions": len(wls),
-                          "nodes": sum(w.n_nodes for w in wls), "ms_batched": 1e3 * t_b,
-                          "ms_one_after_another": 1e3 * t_s, "speedup": t_s / t_b,
-                          "gmres_iters_batched": sum(i["gmres_iters"] for i in infos),
-                          "gmres_iters_one_after_another": its,
-                          "max_residual": max(i["gmres_residual"] for i in infos)}))
-        b.close()
+    Fs = [dev(wl.F) for wl in wls]
+    dQs = [torch.zeros(3 * wl.n_bodies, dtype=torch.float64, device="cuda") for wl in wls]
+    delta = min(wl.a for wl in wls) * 1e-2
+    dt = 1e-7  # RMS move ~2% of the smallest bodies' radius per step
+    nw = [None] * len(wls)
+    for _ in range(max(1, args.warmup)):
+        b.step_em_rfd(dt, delta, Fs, nw, nw, nw, dQs, apply=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    binfo = []
+    for _ in range(args.steps):
+        binfo.append(b.step_em_rfd(dt, delta, Fs, nw, nw, nw, dQs, apply=True))
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / args.steps
+    # the members one after another (same contexts, sequential EM-RFD step each)
+    for m, F, dQ in zip(b.members, Fs, dQs):
+        m.step_em_rfd(dt, delta, F, None, None, None, dQ, apply=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = 0
+    for _ in range(args.steps):
+        for m, F, dQ in zip(b.members, Fs, dQs):
+            its += m.step_em_rfd(dt, delta, F, None, None, None, dQ, apply=True)["gmres_iters"]
+    torch.cuda.synchronize()
+    t_s = (time.perf_counter() - t0) / args.steps
+    print(json.dumps({"mode": "batch", "workload": "64 uneven suspensions, bodies log-uniform in [16, 512], "
+                      "64/128/256 nodes per body, area fraction 0.2, tol 1e-6; EM-RFD step, 3 RHS each",
+                      "precision": "mixed+basis32", "suspensions": len(wls), "bodies": sum(w.n_bodies for w in wls),
+                      "nodes": sum(w.n_nodes for w in wls), "steps": args.steps,
+                      "ms_per_step_batched": 1e3 * t_b, "ms_per_step_one_after_another": 1e3 * t_s,
+                      "speedup": t_s / t_b,
+                      "gmres_iters_batched": sum(i["gmres_iters"] for st in binfo for i in st) / args.steps,
+                      "gmres_iters_one_after_another": its / args.steps,
+                      "max_residual": max(i["gmres_residual"] for st in binfo for i in st)}), flush=True)
+    b.close()
 
 
 def main():
@@ -310,7 +321,7 @@ def main():
     ap.add_argument("--mode", default="step", choices=["step", "matvec", "copy", "batch"],
                     help="step: the EM-RFD benchmark; matvec: only single-layer matvecs of the first form "
                          "(short runs for counter collection); copy: a plain 1 GiB device copy "
-                         "used to calibrate the HBM byte counters; batch: mobility solves of the "
+                         "used to calibrate the HBM byte counters; batch: EM-RFD steps of the "
                          "64-suspension uneven batch, batched against one after another")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -227,3 +227,39 @@ def test_mixed_batched_rfd_step_matches_sequential(basis32):
         assert i1["status"] == 0 and i1["gmres_solves"] == 3
         assert i1["gmres_residual"] <= 1e-9
         assert relerr(host(d1), host(d0)) < 1e-6
+
+
+def test_uneven_batch_em_rfd_step_against_oracle():
+    """The uneven-suspension workload as a batched EM-RFD step: 64 suspensions,
+    mixed precision with the FP32 Krylov basis, graphs on, three right-hand sides
+    per suspension (U0 at Q, U+- at Q +- delta/2 Wt) in lockstep launch sets.
+    Every member meets the GMRES tolerance on its FP64 true residual; the two
+    smallest suspensions' displacements match the matrix-free FP64 oracle's step
+    (eq. 4.3) at the mixed-precision bar 1e-4."""
+    import paper_1709_01480_amd as fb
+    from gpu_util import oracle_params
+    from oracle import fbim as OF
+    from oracle import matfree as MF
+    wls = W.uneven_suspensions(64)
+    log("uneven batch EM-RFD: %d suspensions, %d nodes" % (len(wls), sum(w.n_nodes for w in wls)))
+    b = _batch(wls, graph=True, precision=fb.PREC_MIXED, flags=fb.FLAG_BASIS32, tol_gmres=1e-8, tol_lanczos=1e-8)
+    noise = [W.noise(wl, m.get_derived()["grid_M"]) for wl, m in zip(wls, b.members)]
+    delta = min(wl.a for wl in wls) * 1e-2
+    dt = 1e-3
+    dQs = [zeros(3 * wl.n_bodies) for wl in wls]
+    infos = b.step_em_rfd(dt, delta, [dev(wl.F) for wl in wls], [dev(n[0]) for n in noise],
+                          [dev(n[1]) for n in noise], [dev(n[2]) for n in noise], dQs)
+    log("iterations min %d max %d" % (min(i["gmres_iters"] for i in infos), max(i["gmres_iters"] for i in infos)))
+    for info in infos:
+        assert info["status"] == 0 and info["gmres_solves"] == 3 and info["gmres_residual"] <= 1e-8
+    sizes = [wl.n_nodes for wl in wls]
+    for k in np.argsort(sizes)[:2]:
+        wl, m = wls[k], b.members[k]
+        prm = oracle_params(wl)
+        d = m.get_derived()
+        assert prm["grid_M"] == d["grid_M"] and prm["P"] == d["P"] and abs(prm["xi"] / d["xi"] - 1) < 1e-12
+        ref, _, _, _, _ = MF.em_rfd_step(OF.geometry_from_workload(wl), prm, wl.F, *noise[k], wl.kT, dt, delta,
+                                         order=wl.alpert_order, tau=wl.tau_spurious, tol=1e-10)
+        err = relerr(host(dQs[k]), ref)
+        log("member %d (%d x %d): rel err %.3e" % (k, wl.n_bodies, wl.n_p, err))
+        assert err < 1e-4
