@@ -26,6 +26,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# autotuner cache (JSON lines); the first run on a device times the candidates
+TUNE_CACHE = os.environ.get("FBIM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "fbim",
+                                                            "tune_cache.jsonl"))
 METRIC = "Stokeslet matvec Mnodes/s + Brownian steps/s @640k nodes; mixed+learned vs FP64"
 PEAK = {"hbm": 8000.0, "fp64_vec": 78.6, "fp32_vec": 157.3}  # GB/s, TFLOP/s
 FLOP_PER_PAIR = 60.0       # kernel evaluation per in-range pair (E1, exp, 2x2 apply)
@@ -104,9 +107,19 @@ def run_form(name, form, wl, args, fb, W, np, torch):
     prec = fb.PREC_FP64 if form["precision"] == "fp64" else fb.PREC_MIXED
     flags = ((fb.FLAG_BATCH_RFD if form["batch_rfd"] else 0) | (fb.FLAG_GRAPH if form.get("graph") else 0)
              | (fb.FLAG_BASIS32 if form.get("basis32") else 0))
-    ctx = fb.Context(**wl.params(), precision=prec, flags=flags, seed=W.noise_key(wl))
+    prm = dict(wl.params(), precision=prec, flags=flags, seed=W.noise_key(wl))
+    ctx = fb.Context(**prm)
     sid = ctx.add_shape(fb.starfish(wl.r_s, wl.b, wl.n_arm, wl.n_p))
     ctx.set_bodies(np.full(wl.n_bodies, sid), wl.q, wl.theta)
+    # untimed: the spreading tile from the autotuner (the grid is part of the workload)
+    tuned, tune_rep = ctx.autotune(fb.TUNE_TILE, TUNE_CACHE)
+    if tuned["tile"] != ctx.get_derived()["tile"]:
+        ctx.close()
+        prm["tile"] = tuned["tile"]
+        ctx = fb.Context(**prm)
+        sid = ctx.add_shape(fb.starfish(wl.r_s, wl.b, wl.n_arm, wl.n_p))
+        ctx.set_bodies(np.full(wl.n_bodies, sid), wl.q, wl.theta)
+    log("%s: spreading tile %d (%s)" % (name, ctx.get_derived()["tile"], tune_rep))
     d = ctx.get_derived()
     M, N = d["grid_M"], d["n_nodes"]
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
@@ -172,6 +185,7 @@ def run_form(name, form, wl, args, fb, W, np, torch):
     ctx.get_nodes(x)
     res = {
         "steps_per_s": 1.0 / t_step, "ms_per_step": 1e3 * t_step,
+        "tuning": dict(tune_rep, tile=d["tile"]),
         "matvec": {"value": N / t_mv / 1e6, "unit": "Mnodes/s", "ms": 1e3 * t_mv},
         "solver": {"gmres_iters_per_solve": sum(i["gmres_iters"] for i in infos)
                    / max(1, sum(i["gmres_solves"] for i in infos)),
@@ -336,6 +350,7 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    os.makedirs(os.path.dirname(TUNE_CACHE), exist_ok=True)
     if args.mode == "copy":
         n = (1 << 30) // 8
         a = torch.ones(n, dtype=torch.float64, device="cuda")

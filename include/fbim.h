@@ -401,6 +401,52 @@ fbim_status fbim_mlp_use(fbim_ctx *ctx, int32_t on);
 fbim_status fbim_set_timing(fbim_ctx *ctx, int32_t enable);
 fbim_status fbim_kernel_time(fbim_ctx *ctx, const char *name, double *ms, int64_t *count);
 
+/* ---- Autotuner ----------------------------------------------------------------
+ * Not a step of the paper's method: a throughput choice among parameters that
+ * the method leaves free.  Times the single-layer matvec (fbim_apply_M, all
+ * parts, in the context's own precision; median of 5 after 2 untimed) of the
+ * context's current configuration for each candidate, on the context's stream,
+ * and returns the context's parameters with the fastest admissible candidate
+ * filled in (explicit n_box, grid_M, tile); the caller creates a context with
+ * them.  Candidates:
+ *   FBIM_TUNE_TILE   every spreading tile edge T <= 32 with T | M, M / T >= 3 and
+ *                    T >= (P - 1)/2 (results agree to round-off: the spread sums
+ *                    are fixed point per tile);
+ *   FBIM_TUNE_SPLIT  the Ewald split of Section 3.2: n_box (r_c = L / n_box) at
+ *                    0.6 ... 1.3 times the given one, each with the grid of the
+ *                    parameter rule for tol_ewald and with the next power of two;
+ *                    a candidate whose shapes break r_Alpert <= 0.6 r_c is not
+ *                    admissible.  Results change within the Ewald tolerance.
+ *                    Needs params.n_box given and grid_M = xi = 0.
+ * cache_path (may be NULL): a JSON-lines file, one object per line
+ *   {"key": "<key>", "n_box": ., "grid_M": ., "tile": ., "ms": .}; a line whose key
+ *   matches (device architecture and compute-unit count, precision, node count,
+ *   nodes per body and body count per shape, L, tolerance, Alpert order, the
+ *   given grid_M / n_box / xi / P, the tuning set) is used without timing (the
+ *   last such line wins; malformed lines are skipped); otherwise the choice is
+ *   appended.  Host file I/O is serialised within the process.
+ * The call allocates two node vectors and each candidate's context; it
+ * synchronises the context's stream.  FBIM_EINVAL: no bodies set, invalid set,
+ * SPLIT without a free split, or no admissible candidate. */
+#define FBIM_TUNE_TILE 1u
+#define FBIM_TUNE_SPLIT 2u
+typedef struct {
+  int32_t candidates;  /* candidates timed (0 when taken from the cache) */
+  int32_t from_cache;  /* 1 when the cache answered */
+  int32_t cache_error; /* 1 when the choice could not be appended to the cache */
+  int32_t reserved;
+  double ms_best;      /* median matvec time of the choice (cached value if from_cache) */
+  double ms_default;   /* median matvec time of the context's own parameters (-1 if from_cache) */
+} fbim_tune_report;
+fbim_status fbim_autotune(fbim_ctx *ctx, uint32_t what, const char *cache_path, fbim_params *out,
+                          fbim_tune_report *report);
+/* The cache key fbim_autotune uses for ctx and `what` (NUL-terminated into
+ * buf[len]; FBIM_EINVAL if it does not fit). */
+fbim_status fbim_autotune_key(const fbim_ctx *ctx, uint32_t what, char *buf, int32_t len);
+/* Host only: 1 and the cached choice when cache_path holds `key`, else 0. */
+int32_t fbim_autotune_lookup(const char *cache_path, const char *key, int32_t *n_box, int32_t *grid_M,
+                             int32_t *tile);
+
 #ifdef __cplusplus
 }
 #endif

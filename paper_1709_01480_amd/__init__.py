@@ -12,7 +12,7 @@ import os
 
 __all__ = ["Params", "Derived", "Info", "Context", "lib", "derive_params", "alpert_rule", "starfish",
            "PART_REAL", "PART_ALPERT", "PART_WAVE", "PART_ALL", "PREC_FP64", "PREC_MIXED", "FbimError",
-           "LIB_PATH", "MLP_IN", "MLP_OUT", "MLP_NPARAM"]
+           "LIB_PATH", "MLP_IN", "MLP_OUT", "MLP_NPARAM", "TuneReport", "TUNE_TILE", "TUNE_SPLIT", "autotune_lookup"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfbim.so")
 
@@ -24,6 +24,8 @@ NOISE_W_R, NOISE_W_GRID, NOISE_W_TILDE = 0, 1, 2
 MLP_IN, MLP_HID, MLP_OUT = 32, 128, 6
 MLP_NPARAM = 32 * 128 + 128 + 128 * 128 + 128 + 128 * 6 + 6
 NOALLOC_MAX_BODIES = 8192
+TUNE_TILE = 1
+TUNE_SPLIT = 2
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EOVERLAP", 4: "ENOCONV", 5: "EDEVICE", 6: "ENOTSUP",
           7: "WACCURACY"}
 
@@ -53,6 +55,14 @@ class Derived(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("cache_error", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("ms_best", ctypes.c_double), ("ms_default", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class Info(ctypes.Structure):
@@ -131,6 +141,9 @@ def _load():
         "fbim_noise_words": (i32, [p, u32, ctypes.c_uint64, ctypes.c_size_t, p]),
         "fbim_noise_counter": (i32, [p, P(ctypes.c_uint64)]),
         "fbim_set_noise_counter": (i32, [p, ctypes.c_uint64]),
+        "fbim_autotune": (i32, [p, u32, ctypes.c_char_p, P(Params), P(TuneReport)]),
+        "fbim_autotune_key": (i32, [p, u32, ctypes.c_char_p, i32]),
+        "fbim_autotune_lookup": (i32, [ctypes.c_char_p, ctypes.c_char_p, P(i32), P(i32), P(i32)]),
         "fbim_set_timing": (i32, [p, i32]),
         "fbim_kernel_time": (i32, [p, ctypes.c_char_p, P(d), P(ctypes.c_int64)]),
     }
@@ -142,6 +155,15 @@ def _load():
 
 
 lib = _load()
+
+
+def autotune_lookup(cache_path, key):
+    """fbim_autotune_lookup (host only): (n_box, grid_M, tile) or None."""
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    if lib.fbim_autotune_lookup(os.fsencode(cache_path), key.encode(), ctypes.byref(a), ctypes.byref(b),
+                                ctypes.byref(c)):
+        return a.value, b.value, c.value
+    return None
 
 
 def make_params(**kw) -> Params:
@@ -261,6 +283,19 @@ class Context:
                                         q.ctypes.data_as(ctypes.c_void_p), th.ctypes.data_as(ctypes.c_void_p)))
         d = self.get_derived()
         self.n, self.N = d["n_bodies"], d["n_nodes"]
+
+    def autotune(self, what, cache_path=None):
+        """fbim_autotune: (parameters dict for Context(**...), report dict)."""
+        out = Params()
+        rep = TuneReport()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        self._check(lib.fbim_autotune(self._ctx, what, path, ctypes.byref(out), ctypes.byref(rep)))
+        return {k: getattr(out, k) for k, _ in Params._fields_}, rep.as_dict()
+
+    def autotune_key(self, what) -> str:
+        buf = ctypes.create_string_buffer(1024)
+        self._check(lib.fbim_autotune_key(self._ctx, what, buf, len(buf)))
+        return buf.value.decode()
 
     def get_derived(self) -> dict:
         out = Derived()

@@ -106,7 +106,7 @@ def test_params_struct_layout_matches_header(tmp_path):
     fields = [f for f, _ in fb.Params._fields_]
     body = "\n".join('  printf("%%zu ", offsetof(fbim_params, %s));' % f for f in fields)
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "fbim.h"\nint main(void) {\n%s\n'
-                   '  printf("%%zu %%zu %%zu\\n", sizeof(fbim_params), sizeof(fbim_info), sizeof(fbim_derived));\n'
+                   '  printf("%%zu %%zu %%zu %%zu\\n", sizeof(fbim_params), sizeof(fbim_info), sizeof(fbim_derived), sizeof(fbim_tune_report));\n'
                    '  return 0;\n}\n' % body)
     exe = tmp_path / "layout"
     import subprocess
@@ -114,4 +114,23 @@ def test_params_struct_layout_matches_header(tmp_path):
     vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     offs = [getattr(fb.Params, f).offset for f in fields]
     assert vals[:len(fields)] == offs
-    assert vals[len(fields):] == [ctypes.sizeof(fb.Params), ctypes.sizeof(fb.Info), ctypes.sizeof(fb.Derived)]
+    assert vals[len(fields):] == [ctypes.sizeof(fb.Params), ctypes.sizeof(fb.Info), ctypes.sizeof(fb.Derived),
+                                  ctypes.sizeof(fb.TuneReport)]
+
+
+def test_autotune_cache_lookup(tmp_path):
+    # the JSON-lines cache the autotuner reads and appends to: exact key match, the
+    # last matching line wins, malformed lines and other keys are skipped
+    path = tmp_path / "tune.jsonl"
+    key = "arch=gfx950:cu=256|prec=1|N=640000|bodies=64x10000|what=1"
+    path.write_text(
+        '{"key": "%s", "n_box": 201, "grid_M": 2048, "tile": 16, "ms": 0.31}\n' % key
+        + '{"key": "%s|extra", "n_box": 5, "grid_M": 64, "tile": 8, "ms": 0.1}\n' % key
+        + '{"key": "%s", "n_box": "oops", "grid_M": 2048}\n' % key
+        + 'not json at all\n'
+        + '{"key": "%s", "n_box": 201, "grid_M": 2048, "tile": 32, "ms": 0.29}\n' % key
+        + '{"key": "arch=gfx950:cu=256", "n_box": 7, "grid_M": 128, "tile": 32, "ms": 1}\n')
+    assert fb.autotune_lookup(str(path), key) == (201, 2048, 32)
+    assert fb.autotune_lookup(str(path), key + "|extra") == (5, 64, 8)
+    assert fb.autotune_lookup(str(path), key[:-1]) is None
+    assert fb.autotune_lookup(str(tmp_path / "missing.jsonl"), key) is None
