@@ -111,6 +111,9 @@ typedef struct {
   int32_t tile;          /* spreading tile edge in grid points (0: choose) */
   uint32_t flags;        /* FBIM_FLAG_* bits */
   uint64_t seed;         /* key of the context's noise generator (fbim_noise_normals) */
+  double tol_rfd;        /* GMRES tolerance of the two random-finite-difference solves of
+                            a time step (0: tol_gmres); the paper runs them at 1e-3 with
+                            1e-6 for the other solves (Section 4.4, spring-pair runs) */
 } fbim_params;
 
 /* Derived quantities reported back by fbim_get_derived. */
@@ -226,10 +229,28 @@ fbim_status fbim_brownian_velocity(fbim_ctx *ctx, double dt, const double *F, co
  * side, configurations delta apart); every solve stops on its own true residual.  DEVICE F[3n], W_r[2N],
  * W_grid[2MM], W_tilde[3n]; DEVICE dQ[3n] = (dq_x, dq_y, dtheta) per body.
  * If apply != 0 the bodies are moved by dQ afterwards; otherwise the
- * configuration is restored to Q. */
+ * configuration is restored to Q.  The two RFD solves stop at
+ * fbim_params.tol_rfd when it is set.  delta = 0 drops the RFD term (dQ = dt U0:
+ * the scheme without the stochastic drift of Section 4.4.1, whose equilibrium
+ * is biased by 1 / N_theta,theta; W_tilde is then neither read nor drawn). */
 fbim_status fbim_step_em_rfd(fbim_ctx *ctx, double dt, double delta, const double *F,
                              const double *W_r, const double *W_grid, const double *W_tilde,
                              double *dQ, int32_t apply, fbim_info *info);
+
+/* One step of the Adams-Bashforth scheme with the random finite difference
+ * (Section 4.4, the AB2-RFD equation):
+ *   dQ = dt (3/2 N^n F^n - 1/2 N^(n-1) F^(n-1)) + sqrt(2 kT dt) (N^n)^(1/2) W
+ *        + dt kT/delta [N(Q + delta/2 Wt) Wt - N(Q - delta/2 Wt) Wt],
+ * computed as the EM-RFD displacement of fbim_step_em_rfd plus
+ * dt/2 (N^n F^n - N^(n-1) F^(n-1)), where N^n F^n is a fourth mobility solve
+ * (F alone, zero slip) at Q.  DEVICE NF_hist[3n]: on entry N^(n-1) F^(n-1) when
+ * have_hist != 0 (else the step is the EM step: the usual start of the scheme);
+ * on return N^n F^n for the next step.  Other arguments, noise draws, delta = 0
+ * and apply as fbim_step_em_rfd. */
+fbim_status fbim_step_ab2_rfd(fbim_ctx *ctx, double dt, double delta, const double *F,
+                              const double *W_r, const double *W_grid, const double *W_tilde,
+                              double *NF_hist, int32_t have_hist, double *dQ, int32_t apply,
+                              fbim_info *info);
 
 /* ---- Noise ----------------------------------------------------------------
  * The method consumes independent standard normals (W^(r), W^(w): Sections
@@ -308,6 +329,15 @@ fbim_status fbim_batch_step_em_rfd(fbim_batch *batch, double dt, double delta, c
                                    const double *const *W_r, const double *const *W_grid,
                                    const double *const *W_tilde, double *const *dQ, int32_t apply,
                                    fbim_info *info);
+
+/* One AB2-RFD step (fbim_step_ab2_rfd) of every member: the EM-RFD solves as in
+ * fbim_batch_step_em_rfd, then the members' N^n F^n solves in one more batched
+ * GMRES.  HOST arrays of S DEVICE pointers; NF_hist[s] as NF_hist of
+ * fbim_step_ab2_rfd (have_hist applies to every member). */
+fbim_status fbim_batch_step_ab2_rfd(fbim_batch *batch, double dt, double delta, const double *const *F,
+                                    const double *const *W_r, const double *const *W_grid,
+                                    const double *const *W_tilde, double *const *NF_hist, int32_t have_hist,
+                                    double *const *dQ, int32_t apply, fbim_info *info);
 
 /* ---- Learned correction of the block-diagonal preconditioner ----------------
  * A per-body MLP 32 -> 128 -> 128 -> 6 with tanh hidden layers maps features

@@ -530,9 +530,36 @@ def em_rfd_step(geo: Geometry, prm, F, W_r, W_grid, W_tilde, kT, dt, delta, orde
     """Displacement of one Euler-Maruyama step with the centred random finite
     difference drift (eq. 4.3):
       dQ = dt U0 + dt kT/delta [N(Q + delta/2 Wt) Wt - N(Q - delta/2 Wt) Wt]
-    with U0 = N F + sqrt(2 kT/dt) N^(1/2) W from the saddle solve with slip."""
+    with U0 = N F + sqrt(2 kT/dt) N^(1/2) W from the saddle solve with slip.
+    delta = 0: the scheme without the drift term, dQ = dt U0 (Section 4.4.1)."""
     U0 = DenseFBIM(geo, prm, order, eta, tau).brownian_velocity(F, W_r, W_grid, kT, dt)
+    if delta == 0:
+        return dt * U0, U0, None, None
     h = 0.5 * delta * W_tilde
     Up, _ = DenseFBIM(moved(geo, h), prm, order, eta, tau).mobility(W_tilde)
     Um, _ = DenseFBIM(moved(geo, -h), prm, order, eta, tau).mobility(W_tilde)
     return dt * U0 + dt * kT / delta * (Up - Um), U0, Up, Um
+
+
+def ab2_rfd_step(geo: Geometry, prm, F, W_r, W_grid, W_tilde, kT, dt, delta, NF_prev=None, order=4,
+                 eta=1.0, tau=1e-8):
+    """Displacement of one step of the stochastic Adams-Bashforth scheme with the
+    random finite difference (Section 4.4, the AB2-RFD equation):
+      dQ = dt (3/2 N^n F^n - 1/2 N^(n-1) F^(n-1)) + sqrt(2 kT dt) (N^n)^(1/2) W
+           + dt kT/delta [N(Q + delta/2 Wt) Wt - N(Q - delta/2 Wt) Wt],
+    where sqrt(2 kT dt) N^(1/2) W = dt times the response to the slip alone
+    (eq. 3.27) and the deterministic and stochastic velocities are separate solves.
+    NF_prev = None: the first step, where N^(n-1) F^(n-1) is taken as N^n F^n.
+    delta = 0 drops the drift term.  Returns (dQ, N^n F^n)."""
+    D = DenseFBIM(geo, prm, order, eta, tau)
+    NF, _ = D.mobility(F)
+    slip, _, _ = D.slip(W_r, W_grid, kT, dt)
+    Us, _ = D.mobility(np.zeros_like(F), slip)
+    prev = NF if NF_prev is None else NF_prev
+    dQ = dt * (1.5 * NF - 0.5 * prev) + dt * Us
+    if delta != 0:
+        h = 0.5 * delta * W_tilde
+        Up, _ = DenseFBIM(moved(geo, h), prm, order, eta, tau).mobility(W_tilde)
+        Um, _ = DenseFBIM(moved(geo, -h), prm, order, eta, tau).mobility(W_tilde)
+        dQ = dQ + dt * kT / delta * (Up - Um)
+    return dQ, NF

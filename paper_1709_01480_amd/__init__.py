@@ -43,7 +43,7 @@ class Params(ctypes.Structure):
                 ("alpert_order", ctypes.c_int32), ("n_box", ctypes.c_int32), ("grid_M", ctypes.c_int32),
                 ("P", ctypes.c_int32), ("precision", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
                 ("gmres_maxiter", ctypes.c_int32), ("lanczos_maxiter", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+                ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("tol_rfd", ctypes.c_double)]
 
 
 class Derived(ctypes.Structure):
@@ -116,6 +116,7 @@ def _load():
         "fbim_apply_precond": (i32, [p, p, p]),
         "fbim_brownian_velocity": (i32, [p, d, p, p, p, p, P(Info)]),
         "fbim_step_em_rfd": (i32, [p, d, d, p, p, p, p, p, i32, P(Info)]),
+        "fbim_step_ab2_rfd": (i32, [p, d, d, p, p, p, p, p, i32, p, i32, P(Info)]),
         "fbim_derive_params": (i32, [P(Params), P(Derived)]),
         "fbim_alpert_rule": (i32, [i32, P(i32), P(i32), p, p]),
         "fbim_mlp_init": (i32, [p, ctypes.c_uint64, i32]),
@@ -137,6 +138,7 @@ def _load():
         "fbim_batch_apply_M": (i32, [p, p, p]),
         "fbim_batch_mobility": (i32, [p, p, p, p, P(Info)]),
         "fbim_batch_step_em_rfd": (i32, [p, d, d, p, p, p, p, p, i32, P(Info)]),
+        "fbim_batch_step_ab2_rfd": (i32, [p, d, d, p, p, p, p, p, i32, p, i32, P(Info)]),
         "fbim_noise_normals": (i32, [p, u32, ctypes.c_uint64, ctypes.c_size_t, p]),
         "fbim_noise_words": (i32, [p, u32, ctypes.c_uint64, ctypes.c_size_t, p]),
         "fbim_noise_counter": (i32, [p, P(ctypes.c_uint64)]),
@@ -349,6 +351,16 @@ class Context:
                                          _dptr(dQ, 3 * self.n), 1 if apply else 0, ctypes.byref(info)))
         return info.as_dict()
 
+    def step_ab2_rfd(self, dt, delta, F, W_r, W_grid, W_tilde, NF_hist, have_hist, dQ, apply=False):
+        """AB2-RFD step; NF_hist (3n, GPU) carries N F from one step to the next."""
+        M = self.get_derived()["grid_M"]
+        info = Info()
+        self._check(lib.fbim_step_ab2_rfd(self._ctx, dt, delta, _dptr(F, 3 * self.n), _optr(W_r, 2 * self.N),
+                                          _optr(W_grid, 2 * M * M), _optr(W_tilde, 3 * self.n),
+                                          _dptr(NF_hist, 3 * self.n), 1 if have_hist else 0,
+                                          _dptr(dQ, 3 * self.n), 1 if apply else 0, ctypes.byref(info)))
+        return info.as_dict()
+
     # -- noise
     def noise_normals(self, stream, counter, out):
         self._check(lib.fbim_noise_normals(self._ctx, stream, counter, out.numel(), _dptr(out)))
@@ -498,4 +510,20 @@ class Batch:
             self._b, dt, delta, arr(Fs, [3 * c.n for c in m]), arr(W_rs, [2 * c.N for c in m]),
             arr(W_grids, [2 * M * M for M in Ms]), arr(W_tildes, [3 * c.n for c in m]),
             arr(dQs, [3 * c.n for c in m]), 1 if apply else 0, info), allow=(4,))
+        return [i.as_dict() for i in info]
+
+    def step_ab2_rfd(self, dt, delta, Fs, W_rs, W_grids, W_tildes, hists, have_hist, dQs, apply=False):
+        m = self.members
+        info = (Info * len(m))()
+        Ms = [c.get_derived()["grid_M"] for c in m]
+
+        def arr(xs, sizes):
+            if xs is None:
+                return None
+            return _ptr_array([None if x is None else _dptr(x, k).value for x, k in zip(xs, sizes)], lambda v: v)
+        n3 = [3 * c.n for c in m]
+        self._check(lib.fbim_batch_step_ab2_rfd(
+            self._b, dt, delta, arr(Fs, n3), arr(W_rs, [2 * c.N for c in m]),
+            arr(W_grids, [2 * M * M for M in Ms]), arr(W_tildes, n3), arr(hists, n3), 1 if have_hist else 0,
+            arr(dQs, n3), 1 if apply else 0, info), allow=(4,))
         return [i.as_dict() for i in info]

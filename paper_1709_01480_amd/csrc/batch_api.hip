@@ -1102,6 +1102,24 @@ void engine_set_stream(BatchEngine *E, hipStream_t s) {
   if (E->einfo) rocfft_execution_info_set_stream(E->einfo, s);
 }
 
+// Move every member to Q + dQ on the device; if one move is rejected (its
+// context stays at Q), the members moved before it go back to Q as well.
+fbim_status apply_moves(BatchEngine *E, const std::vector<fbim_ctx *> &mem, double *const *dQ) {
+  for (size_t i = 0; i < mem.size(); ++i) {
+    fbim_ctx *c = mem[i];
+    const size_t n = c->n;
+    EHIP(E, hipMemcpyAsync(c->d_qstep, c->d_q, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    EHIP(E, hipMemcpyAsync(c->d_thstep, c->d_theta, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    const fbim_status st = move_bodies(c, c->d_qstep, c->d_thstep, dQ[i], 1.0);
+    if (st != FBIM_OK) {
+      const std::string msg = c->err;
+      for (size_t k = 0; k < i; ++k) move_bodies(mem[k], mem[k]->d_qstep, mem[k]->d_thstep, nullptr, 0.0);
+      return efail(E, st, msg);
+    }
+  }
+  return FBIM_OK;
+}
+
 // Batched EM-RFD solves of a list of systems: for member i, its RFD copies are
 // rfd[0] (at Q + delta/2 Wt) and rfd[1] (at Q - delta/2 Wt).  U0 = N(Q) F +
 // slip response and U+ = N(Q + delta/2 Wt) Wt of every member in one lockstep
@@ -1111,6 +1129,7 @@ fbim_status em_rfd_batch(BatchEngine *E, const std::vector<fbim_ctx *> &mem, dou
                          const double *const *F, const double *const *W_r, const double *const *W_grid,
                          const double *const *W_tilde, double *const *dQ, int32_t apply, fbim_info *info) {
   const int S = (int)mem.size();
+  const bool rfd = delta > 0;  // delta = 0: no RFD term, U0 alone
   std::vector<fbim_info> inf(S);
   fbim_status worst = FBIM_OK;
   for (int i = 0; i < S; ++i) {
@@ -1120,13 +1139,14 @@ fbim_status em_rfd_batch(BatchEngine *E, const std::vector<fbim_ctx *> &mem, dou
     fbim_status st = brownian_slip(c, dt, W_r[i], W_grid[i], c->d_w, &inf[i]);
     if (st != FBIM_OK && st != FBIM_ENOCONV) return efail(E, st, c->err);
     if (st != FBIM_OK) worst = st;
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; rfd && k < 2; ++k) {
       if (!c->rfd[k]) {
         EST(clone_ctx(c, &c->rfd[k]));
         c->rfd[k]->mlp_on = false;
       }
       fbim_ctx *r = c->rfd[k];
       r->stream = c->stream;
+      r->p.tol_gmres = c->p.tol_rfd;  // the RFD solves stop at their own tolerance
       if (!r->have_bodies || r->n != c->n || r->h_shape != c->h_shape) {
         // first use (or new bodies): the copy takes the member's bodies at the
         // configuration its caller last gave, then moves on the device
@@ -1141,41 +1161,47 @@ fbim_status em_rfd_batch(BatchEngine *E, const std::vector<fbim_ctx *> &mem, dou
   // one engine over members and their RFD copies
   E->sys.clear();
   for (auto *c : mem) E->sys.push_back(c);
-  for (auto *c : mem) E->sys.push_back(c->rfd[0]);
-  for (auto *c : mem) E->sys.push_back(c->rfd[1]);
+  if (rfd) {
+    for (auto *c : mem) E->sys.push_back(c->rfd[0]);
+    for (auto *c : mem) E->sys.push_back(c->rfd[1]);
+  }
   EST(engine_prepare(E));
   for (int i = 0; i < S; ++i) {
     fbim_ctx *c = mem[i];
     if (rhs_one(c, F[i], c->d_w) != FBIM_OK) return efail(E, FBIM_EDEVICE, c->err);
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; rfd && k < 2; ++k)
       if (rhs_one(c->rfd[k], W_tilde[i], nullptr) != FBIM_OK) return efail(E, FBIM_EDEVICE, c->rfd[k]->err);
   }
   // U0 and U+ in one lockstep solve; then U- from U+ (same right-hand side,
   // configurations delta apart: the initial residual is O(delta))
-  std::vector<int> first(2 * S), second(S);
-  for (int i = 0; i < 2 * S; ++i) first[i] = i;
+  std::vector<int> first(rfd ? 2 * S : S), second(S);
+  for (int i = 0; i < (int)first.size(); ++i) first[i] = i;
   for (int i = 0; i < S; ++i) second[i] = 2 * S + i;
   std::vector<int> its, sts, its2, sts2;
   std::vector<double> res, res2;
   EST(solve_b(E, first, its, res, sts));
-  for (int i = 0; i < S; ++i) {
-    const fbim_ctx *p = mem[i]->rfd[0], *m = mem[i]->rfd[1];
-    EHIP(E, hipMemcpyAsync(m->d_x2, p->d_x2, (2 * (size_t)p->N + 3 * (size_t)p->n) * sizeof(double),
-                           hipMemcpyDeviceToDevice, E->stream));
+  if (rfd) {
+    for (int i = 0; i < S; ++i) {
+      const fbim_ctx *p = mem[i]->rfd[0], *m = mem[i]->rfd[1];
+      EHIP(E, hipMemcpyAsync(m->d_x2, p->d_x2, (2 * (size_t)p->N + 3 * (size_t)p->n) * sizeof(double),
+                             hipMemcpyDeviceToDevice, E->stream));
+    }
+    EST(solve_b(E, second, its2, res2, sts2, true));
+    its.insert(its.end(), its2.begin(), its2.end());
+    res.insert(res.end(), res2.begin(), res2.end());
+    sts.insert(sts.end(), sts2.begin(), sts2.end());
   }
-  EST(solve_b(E, second, its2, res2, sts2, true));
-  its.insert(its.end(), its2.begin(), its2.end());
-  res.insert(res.end(), res2.begin(), res2.end());
-  sts.insert(sts.end(), sts2.begin(), sts2.end());
   for (int i = 0; i < S; ++i) {
     fbim_ctx *c = mem[i];
     const size_t n3 = 3 * (size_t)c->n, twoN = 2 * (size_t)c->N;
     hipStream_t s = c->stream;
-    const double *U0 = c->d_x2 + twoN, *Up = c->rfd[0]->d_x2 + twoN, *Um = c->rfd[1]->d_x2 + twoN;
-    EHIP(E, launch_axpby(n3, dt, U0, 0.0, dQ[i], s));
-    EHIP(E, launch_axpby(n3, dt * c->p.kT / delta, Up, 1.0, dQ[i], s));
-    EHIP(E, launch_axpby(n3, -dt * c->p.kT / delta, Um, 1.0, dQ[i], s));
-    for (int k = 0; k < 3; ++k) {
+    EHIP(E, launch_axpby(n3, dt, c->d_x2 + twoN, 0.0, dQ[i], s));
+    if (rfd) {
+      const double *Up = c->rfd[0]->d_x2 + twoN, *Um = c->rfd[1]->d_x2 + twoN;
+      EHIP(E, launch_axpby(n3, dt * c->p.kT / delta, Up, 1.0, dQ[i], s));
+      EHIP(E, launch_axpby(n3, -dt * c->p.kT / delta, Um, 1.0, dQ[i], s));
+    }
+    for (int k = 0; k < (rfd ? 3 : 1); ++k) {
       const int j = i + k * S;
       inf[i].gmres_iters += its[j];
       inf[i].gmres_solves += 1;
@@ -1184,22 +1210,50 @@ fbim_status em_rfd_batch(BatchEngine *E, const std::vector<fbim_ctx *> &mem, dou
     }
     inf[i].status = sts[i];
   }
-  if (apply) {
-    // move every member to Q + dQ on the device; if one move is rejected (its
-    // context stays at Q), the members moved before it go back to Q as well
-    for (int i = 0; i < S; ++i) {
-      fbim_ctx *c = mem[i];
-      const size_t n = c->n;
-      EHIP(E, hipMemcpyAsync(c->d_qstep, c->d_q, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-      EHIP(E, hipMemcpyAsync(c->d_thstep, c->d_theta, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-      const fbim_status st = move_bodies(c, c->d_qstep, c->d_thstep, dQ[i], 1.0);
-      if (st != FBIM_OK) {
-        const std::string msg = c->err;
-        for (int k = 0; k < i; ++k) move_bodies(mem[k], mem[k]->d_qstep, mem[k]->d_thstep, nullptr, 0.0);
-        return efail(E, st, msg);
-      }
+  if (apply) EST(apply_moves(E, mem, dQ));
+  EHIP(E, hipStreamSynchronize(E->stream));
+  if (info)
+    for (int i = 0; i < S; ++i) info[i] = inf[i];
+  return worst;
+}
+
+// One AB2-RFD step of every member: the EM-RFD displacement (engine E, members
+// left at Q), then N^n F^n of every member in one lockstep solve on engine Em
+// (members only), dQ += dt/2 (N^n F^n - hist) and hist = N^n F^n.
+fbim_status ab2_rfd_batch(BatchEngine *E, BatchEngine *Em, const std::vector<fbim_ctx *> &mem, double dt,
+                          double delta, const double *const *F, const double *const *W_r,
+                          const double *const *W_grid, const double *const *W_tilde, double *const *hist,
+                          bool have_hist, double *const *dQ, int32_t apply, fbim_info *info) {
+  const int S = (int)mem.size();
+  std::vector<fbim_info> inf(S);
+  fbim_status worst = em_rfd_batch(E, mem, dt, delta, F, W_r, W_grid, W_tilde, dQ, 0, inf.data());
+  if (worst != FBIM_OK && worst != FBIM_ENOCONV) return worst;
+  Em->sys = mem;
+  fbim_status st = engine_prepare(Em);
+  if (st != FBIM_OK) return efail(E, st, Em->err);
+  for (int i = 0; i < S; ++i)
+    if (rhs_one(mem[i], F[i], nullptr) != FBIM_OK) return efail(E, FBIM_EDEVICE, mem[i]->err);
+  std::vector<int> all(S), its, sts;
+  std::vector<double> res;
+  for (int i = 0; i < S; ++i) all[i] = i;
+  st = solve_b(Em, all, its, res, sts);
+  if (st != FBIM_OK) return efail(E, st, Em->err);
+  for (int i = 0; i < S; ++i) {
+    fbim_ctx *c = mem[i];
+    const size_t n3 = 3 * (size_t)c->n;
+    hipStream_t s = c->stream;
+    const double *NF = c->d_x2 + 2 * (size_t)c->N;
+    if (have_hist) {
+      EHIP(E, launch_axpby(n3, 0.5 * dt, NF, 1.0, dQ[i], s));
+      EHIP(E, launch_axpby(n3, -0.5 * dt, hist[i], 1.0, dQ[i], s));
     }
+    EHIP(E, hipMemcpyAsync(hist[i], NF, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    inf[i].gmres_iters += its[i];
+    inf[i].gmres_solves += 1;
+    inf[i].gmres_residual = std::max(inf[i].gmres_residual, res[i]);
+    if (sts[i] != FBIM_OK) worst = (fbim_status)sts[i];
   }
+  if (apply) EST(apply_moves(E, mem, dQ));
   EHIP(E, hipStreamSynchronize(E->stream));
   if (info)
     for (int i = 0; i < S; ++i) info[i] = inf[i];
@@ -1221,6 +1275,25 @@ fbim_status bfail(fbim_batch *b, fbim_status s, const std::string &m) {
   if (b) b->err = m;
   return s;
 }
+// each member's noise: the caller's, or drawn by the member's generator (no W_tilde
+// without the RFD term)
+fbim_status batch_noise(fbim_batch *b, double delta, const double *const *W_r, const double *const *W_grid,
+                        const double *const *W_tilde, std::vector<const double *> &wr,
+                        std::vector<const double *> &wg, std::vector<const double *> &wt) {
+  const size_t S = b->mem.size();
+  wr.assign(S, nullptr);
+  wg.assign(S, nullptr);
+  wt.assign(S, nullptr);
+  for (size_t i = 0; i < S; ++i) {
+    wr[i] = W_r ? W_r[i] : nullptr;
+    wg[i] = W_grid ? W_grid[i] : nullptr;
+    wt[i] = W_tilde ? W_tilde[i] : nullptr;
+    const fbim_status sn = fbim::fill_noise(b->mem[i], wr[i], wg[i], delta > 0 ? &wt[i] : nullptr);
+    if (sn != FBIM_OK) return bfail(b, sn, b->mem[i]->err);
+  }
+  return FBIM_OK;
+}
+
 fbim_status from_engine(fbim_batch *b, fbim::BatchEngine *E, fbim_status s) {
   if (s != FBIM_OK) b->err = E->err;
   return s;
@@ -1348,19 +1421,32 @@ fbim_status fbim_batch_step_em_rfd(fbim_batch *b, double dt, double delta, const
                                    const double *const *W_r, const double *const *W_grid,
                                    const double *const *W_tilde, double *const *dQ, int32_t apply,
                                    fbim_info *info) {
-  if (!b || !F || !dQ || !(dt > 0) || !(delta > 0)) return bfail(b, FBIM_EINVAL, "invalid arguments");
+  if (!b || !F || !dQ || !(dt > 0) || !(delta >= 0)) return bfail(b, FBIM_EINVAL, "invalid arguments");
   const double t0 = fbim::now_ms();
-  const size_t S = b->mem.size();
-  std::vector<const double *> wr(S), wg(S), wt(S);
-  for (size_t i = 0; i < S; ++i) {
-    wr[i] = W_r ? W_r[i] : nullptr;
-    wg[i] = W_grid ? W_grid[i] : nullptr;
-    wt[i] = W_tilde ? W_tilde[i] : nullptr;
-    const fbim_status sn = fbim::fill_noise(b->mem[i], wr[i], wg[i], &wt[i]);
-    if (sn != FBIM_OK) return bfail(b, sn, b->mem[i]->err);
-  }
+  std::vector<const double *> wr, wg, wt;
+  const fbim_status sn = batch_noise(b, delta, W_r, W_grid, W_tilde, wr, wg, wt);
+  if (sn != FBIM_OK) return sn;
   const fbim_status st =
       fbim::em_rfd_batch(b->rfd, b->mem, dt, delta, F, wr.data(), wg.data(), wt.data(), dQ, apply, info);
+  if (info)
+    for (size_t i = 0; i < b->mem.size(); ++i) info[i].ms_total = fbim::now_ms() - t0;
+  if (st != FBIM_OK) b->err = b->rfd->err;
+  return st;
+}
+
+fbim_status fbim_batch_step_ab2_rfd(fbim_batch *b, double dt, double delta, const double *const *F,
+                                    const double *const *W_r, const double *const *W_grid,
+                                    const double *const *W_tilde, double *const *NF_hist, int32_t have_hist,
+                                    double *const *dQ, int32_t apply, fbim_info *info) {
+  if (!b || !F || !dQ || !NF_hist || !(dt > 0) || !(delta >= 0)) return bfail(b, FBIM_EINVAL, "invalid arguments");
+  for (size_t i = 0; i < b->mem.size(); ++i)
+    if (!NF_hist[i] || !F[i] || !dQ[i]) return bfail(b, FBIM_EINVAL, "null member pointer");
+  const double t0 = fbim::now_ms();
+  std::vector<const double *> wr, wg, wt;
+  const fbim_status sn = batch_noise(b, delta, W_r, W_grid, W_tilde, wr, wg, wt);
+  if (sn != FBIM_OK) return sn;
+  const fbim_status st = fbim::ab2_rfd_batch(b->rfd, b->eng, b->mem, dt, delta, F, wr.data(), wg.data(), wt.data(),
+                                             NF_hist, have_hist != 0, dQ, apply, info);
   if (info)
     for (size_t i = 0; i < b->mem.size(); ++i) info[i].ms_total = fbim::now_ms() - t0;
   if (st != FBIM_OK) b->err = b->rfd->err;

@@ -158,7 +158,8 @@ struct fbim_ctx {
   size_t cap_bxy = 0;
   fbim_ctx *rfd[2] = {nullptr, nullptr};     // copies at Q +- delta/2 Wt for batched EM-RFD solves
   fbim::BatchEngine *rfd_engine = nullptr;   // launch set of the batched EM-RFD solves
-  double *d_vec_a = nullptr, *d_vec_b = nullptr, *d_U3 = nullptr, *d_U4 = nullptr, *d_U5 = nullptr;
+  double *d_vec_a = nullptr, *d_vec_b = nullptr, *d_U3 = nullptr, *d_U4 = nullptr, *d_U5 = nullptr,
+         *d_U6 = nullptr;
 
   // noise drawn by the context (NULL noise arguments): draw counter and buffers
   uint64_t noise_next = 0;

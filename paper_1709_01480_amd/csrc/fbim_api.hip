@@ -152,6 +152,7 @@ fbim_status ensure_krylov(fbim_ctx *c) {
   HIPCHK(c, dalloc(c->d_U3, 3 * (size_t)c->n));
   HIPCHK(c, dalloc(c->d_U4, 3 * (size_t)c->n));
   HIPCHK(c, dalloc(c->d_U5, 3 * (size_t)c->n));
+  HIPCHK(c, dalloc(c->d_U6, 3 * (size_t)c->n));
   return FBIM_OK;
 }
 
@@ -931,7 +932,7 @@ fbim_status fill_noise(fbim_ctx *c, const double *&W_r, const double *&W_grid, c
 
 // warm: start GMRES from the solution of the previous solve of this context
 fbim_status mobility(fbim_ctx *c, const double *F, const double *slip, double *U, double *mu_out, int &its,
-                     double &res, bool warm = false) {
+                     double &res, bool warm = false, double tol = 0.0) {
   const size_t twoN = 2 * (size_t)c->N, nt = c->ntot;
   hipStream_t s = c->stream;
   // b = -[slip; F]
@@ -940,7 +941,7 @@ fbim_status mobility(fbim_ctx *c, const double *F, const double *slip, double *U
   else
     HIPCHK(c, launch_fill(twoN, 0.0, c->d_b, s));
   HIPCHK(c, launch_axpby(3 * (size_t)c->n, -1.0, F, 0.0, c->d_b + twoN, s));
-  fbim_status st = solve_saddle(c, c->d_b, c->d_x2, c->p.tol_gmres, its, res, warm);
+  fbim_status st = solve_saddle(c, c->d_b, c->d_x2, tol > 0 ? tol : c->p.tol_gmres, its, res, warm);
   if (st != FBIM_OK && st != FBIM_ENOCONV) return st;
   HIPCHK(c, hipMemcpyAsync(U, c->d_x2 + twoN, 3 * (size_t)c->n * sizeof(double), hipMemcpyDeviceToDevice, s));
   if (mu_out) HIPCHK(c, hipMemcpyAsync(mu_out, c->d_x2, twoN * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1055,6 +1056,11 @@ fbim_status fbim_create(const fbim_params *params, fbim_ctx **out) {
   if (c->p.tau_spurious <= 0) c->p.tau_spurious = 1e-8;
   if (c->p.tol_gmres <= 0) c->p.tol_gmres = 1e-6;
   if (c->p.tol_lanczos <= 0) c->p.tol_lanczos = 1e-6;
+  if (!(c->p.tol_rfd >= 0 && c->p.tol_rfd < 1)) {  // NaN included
+    fbim_destroy(c);
+    return FBIM_EINVAL;
+  }
+  if (c->p.tol_rfd == 0) c->p.tol_rfd = c->p.tol_gmres;
   if (c->p.alpert_order == 0) c->p.alpert_order = 4;
   c->restart = c->p.gmres_restart > 0 ? c->p.gmres_restart : 100;
   c->gmres_max = c->p.gmres_maxiter > 0 ? c->p.gmres_maxiter : 1000;
@@ -1132,7 +1138,7 @@ void fbim_destroy(fbim_ctx *c) {
                   c->d_mut, c->d_src32, c->d_xt32, c->d_mut32, c->d_grid, c->d_spec, c->d_grid32,
                   c->d_spec32, c->d_e1tab, c->d_e1tab32, c->d_V, c->d_w, c->d_t1, c->d_t2, c->d_b, c->d_x2,
                   c->d_r, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
-                  c->d_U4, c->d_U5, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU, c->d_bx, c->d_by, c->d_tw, c->d_tw32, c->d_ey, c->d_ey32, c->d_scount, c->d_sstart, c->d_slist, c->d_nz_r, c->d_nz_g, c->d_nz_t, c->d_bc_key, c->d_bc_perm, c->d_bc_count, c->d_bc_cursor, c->d_bc_start, c->d_qprev, c->d_thprev, c->d_qstep, c->d_thstep};
+                  c->d_U4, c->d_U5, c->d_U6, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU, c->d_bx, c->d_by, c->d_tw, c->d_tw32, c->d_ey, c->d_ey32, c->d_scount, c->d_sstart, c->d_slist, c->d_nz_r, c->d_nz_g, c->d_nz_t, c->d_bc_key, c->d_bc_perm, c->d_bc_count, c->d_bc_cursor, c->d_bc_start, c->d_qprev, c->d_thprev, c->d_qstep, c->d_thstep};
   pub_free(c->pub);
   if (c->h_pin) hipHostFree(c->h_pin);
   if (c->h_qpin) hipHostFree(c->h_qpin);
@@ -1380,11 +1386,11 @@ fbim_status fbim_brownian_velocity(fbim_ctx *c, double dt, const double *F, cons
 fbim_status fbim_step_em_rfd(fbim_ctx *c, double dt, double delta, const double *F, const double *W_r,
                              const double *W_grid, const double *W_tilde, double *dQ, int32_t apply,
                              fbim_info *info) {
-  if (!c || !F || !dQ || !(dt > 0) || !(delta > 0) || !c->have_bodies)
+  if (!c || !F || !dQ || !(dt > 0) || !(delta >= 0) || !c->have_bodies)
     return fail(c, FBIM_EINVAL, "invalid arguments");
   info_reset(info);
   const double t0 = now_ms();
-  STCHK(fill_noise(c, W_r, W_grid, &W_tilde));
+  STCHK(fill_noise(c, W_r, W_grid, delta > 0 ? &W_tilde : nullptr));
   if (c->p.flags & FBIM_FLAG_BATCH_RFD) {
     // the three solves in one lockstep batch with two copies of the context
     if (!c->rfd_engine) c->rfd_engine = engine_new();
@@ -1416,15 +1422,16 @@ fbim_status fbim_step_em_rfd(fbim_ctx *c, double dt, double delta, const double 
   fbim_status st = brownian(c, dt, F, W_r, W_grid, c->d_U3, info);
   if (st != FBIM_OK && st != FBIM_ENOCONV) return st;
   fbim_status worst = st;
-  // RFD solves N(Q +- delta/2 Wt) Wt
-  for (int sgn = 1; sgn >= -1; sgn -= 2) {
+  // RFD solves N(Q +- delta/2 Wt) Wt (none without the RFD term)
+  for (int sgn = 1; delta > 0 && sgn >= -1; sgn -= 2) {
     guard.moved = true;
     STCHK(move_bodies(c, c->d_qstep, c->d_thstep, W_tilde, sgn * 0.5 * delta));
     int it = 0;
     double res = 0;
     // the second configuration starts from the first one's solution (same right-hand
     // side, configurations delta apart): the initial residual is O(delta)
-    fbim_status s2 = mobility(c, W_tilde, nullptr, sgn > 0 ? c->d_U4 : c->d_U5, nullptr, it, res, sgn < 0);
+    fbim_status s2 =
+        mobility(c, W_tilde, nullptr, sgn > 0 ? c->d_U4 : c->d_U5, nullptr, it, res, sgn < 0, c->p.tol_rfd);
     if (s2 != FBIM_OK && s2 != FBIM_ENOCONV) return s2;
     if (s2 != FBIM_OK) worst = s2;
     if (info) {
@@ -1435,11 +1442,55 @@ fbim_status fbim_step_em_rfd(fbim_ctx *c, double dt, double delta, const double 
   }
   // dQ = dt U0 + dt kT/delta (U+ - U-)
   HIPCHK(c, launch_axpby(n3, dt, c->d_U3, 0.0, dQ, s));
-  HIPCHK(c, launch_axpby(n3, dt * c->p.kT / delta, c->d_U4, 1.0, dQ, s));
-  HIPCHK(c, launch_axpby(n3, -dt * c->p.kT / delta, c->d_U5, 1.0, dQ, s));
+  if (delta > 0) {
+    HIPCHK(c, launch_axpby(n3, dt * c->p.kT / delta, c->d_U4, 1.0, dQ, s));
+    HIPCHK(c, launch_axpby(n3, -dt * c->p.kT / delta, c->d_U5, 1.0, dQ, s));
+  }
   // Q^{n+1} = Q^n + dQ (apply), else back to Q^n
   STCHK(move_bodies(c, c->d_qstep, c->d_thstep, apply ? dQ : nullptr, 1.0));
   guard.armed = false;
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (info) {
+    info->status = worst;
+    info->ms_total = now_ms() - t0;
+  }
+  return worst;
+}
+
+fbim_status fbim_step_ab2_rfd(fbim_ctx *c, double dt, double delta, const double *F, const double *W_r,
+                              const double *W_grid, const double *W_tilde, double *NF_hist, int32_t have_hist,
+                              double *dQ, int32_t apply, fbim_info *info) {
+  if (!c || !F || !dQ || !NF_hist || !(dt > 0) || !(delta >= 0) || !c->have_bodies)
+    return fail(c, FBIM_EINVAL, "invalid arguments");
+  const double t0 = now_ms();
+  // the EM-RFD displacement at Q (configuration left at Q)
+  fbim_status st = fbim_step_em_rfd(c, dt, delta, F, W_r, W_grid, W_tilde, dQ, 0, info);
+  if (st != FBIM_OK && st != FBIM_ENOCONV) return st;
+  fbim_status worst = st;
+  // N^n F^n: F alone, zero slip
+  int it = 0;
+  double res = 0;
+  fbim_status s2 = mobility(c, F, nullptr, c->d_U6, nullptr, it, res);
+  if (s2 != FBIM_OK && s2 != FBIM_ENOCONV) return s2;
+  if (s2 != FBIM_OK) worst = s2;
+  if (info) {
+    info->gmres_iters += it;
+    info->gmres_solves += 1;
+    info->gmres_residual = std::max(info->gmres_residual, res);
+  }
+  hipStream_t s = c->stream;
+  const size_t n3 = 3 * (size_t)c->n;
+  // dQ += dt/2 (N^n F^n - N^(n-1) F^(n-1)); the history becomes N^n F^n
+  if (have_hist) {
+    HIPCHK(c, launch_axpby(n3, 0.5 * dt, c->d_U6, 1.0, dQ, s));
+    HIPCHK(c, launch_axpby(n3, -0.5 * dt, NF_hist, 1.0, dQ, s));
+  }
+  HIPCHK(c, hipMemcpyAsync(NF_hist, c->d_U6, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (apply) {
+    HIPCHK(c, hipMemcpyAsync(c->d_qstep, c->d_q, 2 * (size_t)c->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d_thstep, c->d_theta, (size_t)c->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    STCHK(move_bodies(c, c->d_qstep, c->d_thstep, dQ, 1.0));
+  }
   HIPCHK(c, hipStreamSynchronize(s));
   if (info) {
     info->status = worst;

@@ -194,3 +194,32 @@ def test_planted_rfd_displacement_mistakes_fail(starfish_one, mobility_derivativ
     real = F.moved
     monkeypatch.setattr(F, "moved", lambda geo, dQ: real(geo, factor * np.asarray(dQ)))
     assert rfd_rotation_error(starfish_one, mobility_derivative) > 0.5
+
+
+def test_ab2_step_reduces_to_em_and_carries_the_force_history(tiny):
+    # AB2-RFD (Section 4.4): with N^(n-1) F^(n-1) = N^n F^n it is the EM-RFD step;
+    # otherwise it differs from it by exactly dt/2 (N^n F^n - N^(n-1) F^(n-1)), and
+    # the deterministic and stochastic parts, solved separately, add up to U0
+    wl, geo, prm, _ = tiny
+    Wr, Wg, Wt = W.noise(wl, prm["grid_M"])
+    delta = 1e-2 * wl.a
+    em, U0, _, _ = F.em_rfd_step(geo, prm, wl.F, Wr, Wg, Wt, wl.kT, wl.dt, delta, order=wl.alpert_order)
+    ab, NF = F.ab2_rfd_step(geo, prm, wl.F, Wr, Wg, Wt, wl.kT, wl.dt, delta, order=wl.alpert_order)
+    assert np.linalg.norm(ab - em) <= 1e-12 * np.linalg.norm(em)
+    NF_prev = np.random.default_rng(3).standard_normal(NF.size)
+    ab2, NF2 = F.ab2_rfd_step(geo, prm, wl.F, Wr, Wg, Wt, wl.kT, wl.dt, delta, NF_prev=NF_prev,
+                               order=wl.alpert_order)
+    assert np.allclose(NF2, NF, rtol=0, atol=1e-14 * np.abs(NF).max())
+    assert np.allclose(ab2 - em, 0.5 * wl.dt * (NF - NF_prev), rtol=1e-10, atol=1e-14 * np.abs(em).max())
+    # planted mistake: weights (1, 0) instead of (3/2, -1/2) fails
+    wrong = em + 0.0 * (NF - NF_prev)
+    assert np.linalg.norm(wrong - ab2) > 1e-3 * np.linalg.norm(ab2)
+
+
+def test_em_step_without_the_drift_term(tiny):
+    # delta = 0: the biased scheme dQ = dt U0 of Section 4.4.1
+    wl, geo, prm, _ = tiny
+    Wr, Wg, Wt = W.noise(wl, prm["grid_M"])
+    dQ, U0, Up, Um = F.em_rfd_step(geo, prm, wl.F, Wr, Wg, Wt, wl.kT, wl.dt, 0.0, order=wl.alpert_order)
+    U = F.DenseFBIM(geo, prm, wl.alpert_order).brownian_velocity(wl.F, Wr, Wg, wl.kT, wl.dt)
+    assert Up is None and Um is None and np.allclose(dQ, wl.dt * U, rtol=1e-13, atol=0)
