@@ -322,6 +322,173 @@ def run_batch(args, fb, W, np, torch):
     b.close()
 
 
+def _batch_of(fb, wl, count, seed0, **over):
+    """`count` independent copies of workload wl as members of one batch (graphs
+    on), member k with noise seed seed0 + k."""
+    import numpy as np
+    prms = []
+    for k in range(count):
+        p = wl.params()
+        p.update(over)
+        p["seed"] = seed0 + k
+        prms.append(p)
+    b = fb.Batch(prms, graph=True)
+    for m in b.members:
+        sid = m.add_shape(fb.starfish(wl.r_s, wl.b, wl.n_arm, wl.n_p))
+        m.set_bodies(np.full(wl.n_bodies, sid), wl.q, wl.theta)
+    return b
+
+
+def single_starfish_mobility(fb, W, np, thetas):
+    """N_xx and N_theta,theta of the single four-arm starfish at each angle
+    (FP64 solves to 1e-10 with forces e_x and e_theta)."""
+    import torch
+    wl = W.single_starfish()
+    ctx = fb.Context(**dict(wl.params(), tol_gmres=1e-10))
+    sid = ctx.add_shape(fb.starfish(wl.r_s, wl.b, wl.n_arm, wl.n_p))
+    out = []
+    U = torch.zeros(3, dtype=torch.float64, device="cuda")
+    for th in thetas:
+        ctx.set_bodies(np.full(1, sid), wl.q, np.array([th]))
+        row = []
+        for e in (0, 2):
+            F = torch.zeros(3, dtype=torch.float64, device="cuda")
+            F[e] = 1.0
+            ctx.mobility(F, U)
+            row.append(float(U[e]))
+        out.append(row)
+    ctx.close()
+    return np.array(out)
+
+
+def run_bd_starfish(fb, W, np, torch, n_traj=64, steps=1500, burn=250, dt=0.02, lags=(0.2, 1.0, 2.0),
+                    progress=log):
+    """Free diffusion of one four-arm starfish (b = 0.3, a = 0.45, 64 nodes,
+    tolerance 1e-7) in the unit periodic box, Section 4.4.1: n_traj independent
+    trajectories (one batch), EM with the RFD term and EM without it (delta = 0),
+    angles uniform at the start.  After `burn` steps: the histogram of theta mod
+    pi/2 and <cos 4 theta> against the Gibbs-Boltzmann distribution (uniform) and
+    the biased one (proportional to 1 / N_theta,theta), and the translational MSD
+    against 4 kT <N_xx> t under each.  Standard errors from the spread over
+    trajectories."""
+    wl = W.single_starfish()
+    delta = wl.a * wl.tol_ewald ** (1.0 / 3.0)
+    fine = (np.arange(256) + 0.5) * (0.5 * math.pi / 256)  # midpoints over one period
+    Nf = single_starfish_mobility(fb, W, np, fine)
+    w_b = 1.0 / Nf[:, 1]
+    w_b /= w_b.sum()
+    nb = 8
+    edges = np.linspace(0, 0.5 * math.pi, nb + 1)
+    binof = np.minimum((fine / (0.5 * math.pi) * nb).astype(int), nb - 1)
+    theory = {"rfd": {"hist": [1.0 / nb] * nb, "cos4": float(np.mean(np.cos(4 * fine))),
+                      "Nxx": float(np.mean(Nf[:, 0]))},
+              "no_rfd": {"hist": [float(w_b[binof == k].sum()) for k in range(nb)],
+                         "cos4": float(np.sum(w_b * np.cos(4 * fine))), "Nxx": float(np.sum(w_b * Nf[:, 0]))}}
+    rng = np.random.default_rng(0x5F5)
+    th0 = rng.uniform(0, 2 * math.pi, n_traj)
+    out = {"workload": "single four-arm starfish, b 0.3, a 0.45, 64 nodes, unit box, tol 1e-7, kT 1",
+           "dt": dt, "delta": delta, "trajectories": n_traj, "steps": steps, "burn_in": burn, "theory": theory}
+    for label, dl in (("rfd", delta), ("no_rfd", 0.0)):
+        b = _batch_of(fb, wl, n_traj, 1000 if dl else 2000)
+        for k, m in enumerate(b.members):
+            m.set_bodies(np.zeros(1, dtype=np.int64), wl.q, th0[k:k + 1])
+        Q = np.zeros((steps + 1, n_traj, 3))
+        Q[0, :, :2] = wl.q[0]
+        Q[0, :, 2] = th0
+        Fs = [torch.zeros(3, dtype=torch.float64, device="cuda") for _ in range(n_traj)]
+        dQs = [torch.zeros(3, dtype=torch.float64, device="cuda") for _ in range(n_traj)]
+        nw = [None] * n_traj
+        t0 = time.perf_counter()
+        for t in range(steps):
+            b.step_em_rfd(dt, dl, Fs, nw, nw, nw, dQs, apply=True)
+            Q[t + 1] = Q[t] + torch.stack(dQs).cpu().numpy()
+            if progress and (t + 1) % 250 == 0:
+                progress("bd-starfish %s: step %d / %d (%.1f s)" % (label, t + 1, steps, time.perf_counter() - t0))
+        b.close()
+        th = np.mod(Q[burn + 1:, :, 2], 0.5 * math.pi)  # [time, traj]
+        h = np.stack([np.histogram(th[:, k], bins=edges)[0] / th.shape[0] for k in range(n_traj)])
+        c4 = np.cos(4 * th).mean(axis=0)
+        msd = {}
+        for lag in lags:
+            L = int(round(lag / dt))
+            if L >= steps - burn:
+                continue
+            d = Q[burn + 1 + L:, :, :2] - Q[burn + 1:-L, :, :2]
+            per = (d ** 2).sum(axis=2).mean(axis=0)  # per trajectory
+            msd["%g" % lag] = {"msd": float(per.mean()), "se": float(per.std(ddof=1) / math.sqrt(n_traj)),
+                               "einstein": 4 * wl.kT * theory[label]["Nxx"] * lag}
+        out[label] = {"hist": h.mean(axis=0).tolist(), "hist_se": (h.std(axis=0, ddof=1) / math.sqrt(n_traj)).tolist(),
+                      "cos4": float(c4.mean()), "cos4_se": float(c4.std(ddof=1) / math.sqrt(n_traj)), "msd": msd,
+                      "s_per_step": (time.perf_counter() - t0) / steps}
+    return out
+
+
+def run_bd_pair(fb, W, np, torch, scheme="ab2", n_traj=16, T=14.86, dt=0.0149, tol_rfd=1e-3, progress=log):
+    """A pair of four-arm starfish (a = l/12, 48 nodes, box l = 2) joined by a
+    Hookean spring between the tracking points (rest length 5a, k_s = 81) with
+    each angle held by a harmonic potential (k_theta = 2.446, preferred angles
+    pi/4 and pi/2), Section 4.4.2: n_traj independent trajectories (one batch),
+    EM-RFD or AB2-RFD, deterministic solves at 1e-6 and RFD solves at tol_rfd.
+    Mean and covariance of theta_1, theta_2 and d = |q_1 - q_2| against the
+    Gibbs-Boltzmann distribution, d with density proportional to
+    d exp(-k_s (d - l_s)^2 / 2 kT) in the plane."""
+    wl = W.starfish_pair()
+    a, L = wl.a, wl.L
+    ls, ks, kth = 5 * a, 81.0, 2.446
+    pref = np.array([0.25 * math.pi, 0.5 * math.pi])
+    delta = a * 1e-6 ** (1.0 / 3.0)
+    steps = int(round(T / dt))
+    b = _batch_of(fb, wl, n_traj, 3000 if scheme == "ab2" else 4000, tol_gmres=1e-6, tol_rfd=tol_rfd)
+    Q = np.tile(np.concatenate([wl.q, wl.theta[:, None]], axis=1).ravel(), (n_traj, 1))  # [traj, 6]
+    dQs = [torch.zeros(6, dtype=torch.float64, device="cuda") for _ in range(n_traj)]
+    hists = [torch.zeros(6, dtype=torch.float64, device="cuda") for _ in range(n_traj)]
+    nw = [None] * n_traj
+
+    def forces(Q):
+        F = np.zeros_like(Q)
+        r = Q[:, 0:2] - Q[:, 3:5]
+        r -= L * np.round(r / L)
+        d = np.linalg.norm(r, axis=1)
+        f = -ks * (d - ls)[:, None] * r / d[:, None]
+        F[:, 0:2], F[:, 3:5] = f, -f
+        F[:, 2] = -kth * (Q[:, 2] - pref[0])
+        F[:, 5] = -kth * (Q[:, 5] - pref[1])
+        return F, d
+    rec = []
+    t0 = time.perf_counter()
+    for t in range(steps):
+        F, d = forces(Q)
+        rec.append(np.stack([Q[:, 2], Q[:, 5], d], axis=1))
+        Fs = [torch.as_tensor(F[k]).cuda() for k in range(n_traj)]
+        if scheme == "ab2":
+            b.step_ab2_rfd(dt, delta, Fs, nw, nw, nw, hists, t > 0, dQs, apply=True)
+        else:
+            b.step_em_rfd(dt, delta, Fs, nw, nw, nw, dQs, apply=True)
+        Q = Q + torch.stack(dQs).cpu().numpy()
+        if progress and (t + 1) % 200 == 0:
+            progress("bd-pair %s: step %d / %d (%.1f s)" % (scheme, t + 1, steps, time.perf_counter() - t0))
+    b.close()
+    R = np.array(rec)  # [time, traj, 3]: theta1, theta2, d
+    burn = int(round(1.0 / dt))  # ~8 relaxation times
+    R = R[burn:]
+    # Gibbs-Boltzmann: theta_i ~ N(pref_i, kT/k_theta), d from its planar density
+    dd = np.linspace(max(ls - 8 / math.sqrt(ks), 1e-6), ls + 8 / math.sqrt(ks), 20001)
+    pd = dd * np.exp(-ks * (dd - ls) ** 2 / 2)
+    pd /= np.trapezoid(pd, dd)
+    md = float(np.trapezoid(dd * pd, dd))
+    vd = float(np.trapezoid((dd - md) ** 2 * pd, dd))
+    theory = {"mean": [float(pref[0]), float(pref[1]), md], "var": [1 / kth, 1 / kth, vd]}
+    per_mean = R.mean(axis=0)  # [traj, 3]
+    per_cov = np.stack([np.cov(R[:, k, :].T) for k in range(n_traj)])  # [traj, 3, 3]
+    se = lambda x: (x.std(axis=0, ddof=1) / math.sqrt(n_traj)).tolist()  # noqa: E731
+    return {"workload": "starfish pair, a = l/12, 48 nodes, l = 2, k_s 81, l_s 5a, k_theta 2.446",
+            "scheme": scheme, "dt": dt, "T": T, "steps": steps, "trajectories": n_traj, "tol_rfd": tol_rfd,
+            "delta": delta, "theory": theory,
+            "mean": per_mean.mean(axis=0).tolist(), "mean_se": se(per_mean),
+            "cov": per_cov.mean(axis=0).tolist(), "cov_se": se(per_cov),
+            "s_per_step": (time.perf_counter() - t0) / steps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,11 +499,13 @@ def main():
     ap.add_argument("--matvecs", type=int, default=20)
     ap.add_argument("--train-configs", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="step", choices=["step", "matvec", "copy", "batch"],
+    ap.add_argument("--mode", default="step", choices=["step", "matvec", "copy", "batch", "bd-starfish", "bd-pair"],
                     help="step: the EM-RFD benchmark; matvec: only single-layer matvecs of the first form "
                          "(short runs for counter collection); copy: a plain 1 GiB device copy "
                          "used to calibrate the HBM byte counters; batch: EM-RFD steps of the "
-                         "64-suspension uneven batch, batched against one after another")
+                         "64-suspension uneven batch, batched against one after another; bd-starfish / bd-pair: "
+                         "the Brownian-dynamics validation runs (single starfish with and without the "
+                         "RFD term; spring-coupled pair with EM-RFD and AB2-RFD)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -362,6 +531,13 @@ def main():
         return
     if args.mode == "batch":
         run_batch(args, fb, W, np, torch)
+        return
+    if args.mode == "bd-starfish":
+        print(json.dumps(dict(mode="bd-starfish", **run_bd_starfish(fb, W, np, torch))), flush=True)
+        return
+    if args.mode == "bd-pair":
+        for scheme in ("em", "ab2"):
+            print(json.dumps(dict(mode="bd-pair", **run_bd_pair(fb, W, np, torch, scheme=scheme))), flush=True)
         return
     wl = W.make(args.config)
     names = [f for f in args.forms.split(",") if f]
