@@ -118,3 +118,62 @@ def reference_preconditioner(geo, prm, order=4, C=None, tau=1e-8, eta=1.0):
         return np.concatenate([mu, U])
 
     return apply, [bl[3] for bl in blocks]
+
+
+def surface_gaps(geo):
+    """Smallest node-to-node distance (minimum image) between every two bodies."""
+    X, body = F.nodes(geo)
+    n, L = geo.n, geo.L
+    G = np.full((n, n), np.inf)
+    for b in range(n):
+        for c in range(b + 1, n):
+            d = X[body == b][:, None, :] - X[body == c][None, :, :]
+            d -= L * np.round(d / L)
+            G[b, c] = G[c, b] = np.sqrt((d ** 2).sum(-1)).min()
+    return G
+
+
+def close_clusters(G, threshold, cap):
+    """Groups of bodies joined while their gap is below `threshold`, closest pairs
+    first, no group larger than `cap` (cap = 2: a matching of the closest pairs)."""
+    n = len(G)
+    parent = list(range(n))
+    size = [1] * n
+
+    def root(x):
+        while parent[x] != x:
+            parent[x] = parent[parent[x]]
+            x = parent[x]
+        return x
+    for g, b, c in sorted((G[b, c], b, c) for b in range(n) for c in range(b + 1, n) if G[b, c] < threshold):
+        rb, rc = root(b), root(c)
+        if rb != rc and size[rb] + size[rc] <= cap:
+            parent[rb] = rc
+            size[rc] += size[rb]
+    groups = {}
+    for b in range(n):
+        groups.setdefault(root(b), []).append(b)
+    return list(groups.values())
+
+
+def cluster_preconditioner(M, K, offsets, groups):
+    """z -> P^-1 z with P the saddle operator restricted to each group of bodies
+    (the exact inverse of the group's block [M_gg -K_g; -K_g^T 0]); groups of one
+    body give the block-diagonal preconditioner with each body's own block."""
+    N2 = 2 * offsets[-1]
+    blocks = []
+    for g in groups:
+        idx = np.concatenate([np.arange(2 * offsets[b], 2 * offsets[b + 1]) for b in g])
+        cidx = np.concatenate([np.arange(3 * b, 3 * b + 3) for b in g])
+        Kg = K[np.ix_(idx, cidx)]
+        Ag = np.block([[M[np.ix_(idx, idx)], -Kg], [-Kg.T, np.zeros((len(cidx), len(cidx)))]])
+        blocks.append((idx, cidx, np.linalg.pinv(Ag, rcond=1e-12)))
+
+    def apply(z):
+        out = np.zeros_like(z)
+        for idx, cidx, Ai in blocks:
+            y = Ai @ np.concatenate([z[idx], z[N2 + cidx]])
+            out[idx] = y[:len(idx)]
+            out[N2 + cidx] = y[len(idx):]
+        return out
+    return apply

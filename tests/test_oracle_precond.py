@@ -112,3 +112,31 @@ def test_reference_preconditioner_rotates_with_the_body():
     # same K (the body's own nodes), wrongly rotated reference block
     y_bad = P_bad(z)
     assert np.max(np.abs(y_bad[:N2] - yb[:N2])) > 1e-1 * np.max(np.abs(yb[:N2]))
+
+
+def test_cluster_blocks_of_close_bodies_bound_what_a_local_correction_can_gain():
+    # the iteration ceiling of any correction local to close bodies: the exact
+    # inverse of the saddle block of each cluster of nearly touching bodies (up to
+    # four, gaps below four node spacings) in place of the single-body blocks
+    wl, geo, M, K, A, N2 = _system(16, 32, 0.4, 5)
+    off = geo.offsets()
+    n = wl.n_bodies
+    h = 2 * math.pi * wl.r_s * (1 + wl.b) / wl.n_p  # largest node spacing
+    G = OP.surface_gaps(geo)
+    rhs = -np.concatenate([np.zeros(N2), np.random.default_rng(2).standard_normal(3 * n)])
+    singles = [[b] for b in range(n)]
+    P1 = OP.cluster_preconditioner(M, K, off, singles)
+    P0, _ = OP.block_preconditioner(M, K, off)
+    z = np.random.default_rng(4).standard_normal(A.shape[0])
+    # one-body groups are the block-diagonal preconditioner
+    assert np.linalg.norm(P1(z) - P0(z)) < 1e-8 * np.linalg.norm(P0(z))
+    _, i0 = OP.gmres(A, rhs, P0, tol=1e-8)
+    pairs = OP.close_clusters(G, 4 * h, 2)
+    clusters = OP.close_clusters(G, 4 * h, 4)
+    assert any(len(g) == 2 for g in pairs) and any(len(g) > 2 for g in clusters)
+    _, ip = OP.gmres(A, rhs, OP.cluster_preconditioner(M, K, off, pairs), tol=1e-8)
+    _, ic = OP.gmres(A, rhs, OP.cluster_preconditioner(M, K, off, clusters), tol=1e-8)
+    # measured 38 -> 34 (pairs) -> 33 (clusters): the near-contact blocks are worth
+    # about a tenth of the iterations; the rest is the suspension's long-range coupling
+    assert ic <= ip <= i0
+    assert ic >= 0.75 * i0
