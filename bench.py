@@ -430,8 +430,8 @@ def run_bd_pair(fb, W, np, torch, scheme="ab2", n_traj=16, T=14.86, dt=0.0149, t
     pi/4 and pi/2), Section 4.4.2: n_traj independent trajectories (one batch),
     EM-RFD or AB2-RFD, deterministic solves at 1e-6 and RFD solves at tol_rfd.
     Mean and covariance of theta_1, theta_2 and d = |q_1 - q_2| against the
-    Gibbs-Boltzmann distribution, d with density proportional to
-    d exp(-k_s (d - l_s)^2 / 2 kT) in the plane."""
+    Gibbs-Boltzmann distribution, the separation with density proportional to
+    exp(-k_s (d - l_s)^2 / 2 kT) on the periodic cell (d its minimum-image length)."""
     wl = W.starfish_pair()
     a, L = wl.a, wl.L
     ls, ks, kth = 5 * a, 81.0, 2.446
@@ -471,12 +471,15 @@ def run_bd_pair(fb, W, np, torch, scheme="ab2", n_traj=16, T=14.86, dt=0.0149, t
     R = np.array(rec)  # [time, traj, 3]: theta1, theta2, d
     burn = int(round(1.0 / dt))  # ~8 relaxation times
     R = R[burn:]
-    # Gibbs-Boltzmann: theta_i ~ N(pref_i, kT/k_theta), d from its planar density
-    dd = np.linspace(max(ls - 8 / math.sqrt(ks), 1e-6), ls + 8 / math.sqrt(ks), 20001)
-    pd = dd * np.exp(-ks * (dd - ls) ** 2 / 2)
-    pd /= np.trapezoid(pd, dd)
-    md = float(np.trapezoid(dd * pd, dd))
-    vd = float(np.trapezoid((dd - md) ** 2 * pd, dd))
+    # Gibbs-Boltzmann: theta_i ~ N(pref_i, kT/k_theta); the separation q_1 - q_2 lives
+    # on the periodic cell with density exp(-k_s (d - l_s)^2 / 2 kT), d its minimum-image
+    # length (the ring of radius l_s + 3 sd reaches past l/2, so the planar density
+    # d exp(...) would overstate <d> by 0.007): midpoint rule on the cell
+    g = (np.arange(4000) + 0.5) * (L / 4000) - 0.5 * L
+    dd = np.hypot(*np.meshgrid(g, g))
+    pw = np.exp(-ks * (dd - ls) ** 2 / 2)
+    md = float((dd * pw).sum() / pw.sum())
+    vd = float(((dd - md) ** 2 * pw).sum() / pw.sum())
     theory = {"mean": [float(pref[0]), float(pref[1]), md], "var": [1 / kth, 1 / kth, vd]}
     per_mean = R.mean(axis=0)  # [traj, 3]
     per_cov = np.stack([np.cov(R[:, k, :].T) for k in range(n_traj)])  # [traj, 3, 3]
@@ -489,6 +492,68 @@ def run_bd_pair(fb, W, np, torch, scheme="ab2", n_traj=16, T=14.86, dt=0.0149, t
             "s_per_step": (time.perf_counter() - t0) / steps}
 
 
+def run_learned(fb, W, np, torch, n_train=100, solves=100, epochs=4, n_test=6, progress=log):
+    """The learned-correction study on dense suspensions: 1000 five-arm starfish x
+    128 nodes, area fraction 0.35-0.45 (five values, one body shape each), jittered
+    lattice with bounding-circle gaps down to 0.05 r_s, grid 1024^2, mixed
+    precision.  Training: n_train configurations x `solves` random-force solves
+    (the method's own solves, GMRES at 1e-6), `epochs` Adam steps per
+    configuration.  Evaluation on n_test held-out configurations: GMRES iterations
+    and solve time of three random-force mobility solves, plain block-diagonal
+    preconditioner against the learned correction."""
+    phis = [0.35, 0.375, 0.4, 0.425, 0.45]
+    base = W.make("dense1000")
+    ctx = fb.Context(**dict(base.params(), precision=fb.PREC_MIXED))
+    sids = {}
+    for phi in phis:
+        r_s = W._rs_for_fraction(base.n_bodies, base.L, base.b, phi)
+        sids[phi] = (ctx.add_shape(fb.starfish(r_s, base.b, base.n_arm, base.n_p)), r_s)
+    ctx.mlp_init(seed=11, sym_order=base.n_arm)
+
+    def config(seed, phi):
+        w = W.make("dense1000", seed=seed, r_s=sids[phi][1])
+        ctx.set_bodies(np.full(w.n_bodies, sids[phi][0]), w.q, w.theta)
+        return w
+    t0 = time.perf_counter()
+    losses = []
+    for k in range(n_train):
+        phi = phis[k % len(phis)]
+        config(600 + k, phi)
+        info = ctx.mlp_train(n_solves=solves, epochs=epochs, lr=1e-3, seed=k)
+        losses.append((info["loss_first"], info["loss_last"]))
+        if progress and (k + 1) % 10 == 0:
+            progress("learned: trained on %d configurations, %d solves (%.0f s), loss %.4g -> %.4g"
+                     % (k + 1, (k + 1) * solves, time.perf_counter() - t0, info["loss_first"], info["loss_last"]))
+    t_train = time.perf_counter() - t0
+    rng = np.random.default_rng(77)
+    rows = []
+    for k in range(n_test):
+        phi = phis[k % len(phis)]
+        w = W.make("dense1000", seed=900 + k, r_s=sids[phi][1])
+        Fs = [torch.as_tensor(rng.standard_normal(3 * w.n_bodies)).cuda() for _ in range(3)]
+        U = torch.zeros(3 * w.n_bodies, dtype=torch.float64, device="cuda")
+        row = {"phi": phi, "seed": 900 + k}
+        for on in (False, True):
+            ctx.mlp_use(on)
+            ctx.set_bodies(np.full(w.n_bodies, sids[phi][0]), w.q, w.theta)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            its = [ctx.mobility(F, U)["gmres_iters"] for F in Fs]
+            torch.cuda.synchronize()
+            row["learned" if on else "plain"] = {"iters": its, "ms": 1e3 * (time.perf_counter() - t) / len(Fs)}
+        rows.append(row)
+        if progress:
+            progress("learned: held-out %d (phi %.3f): plain %s, learned %s"
+                     % (k, phi, row["plain"]["iters"], row["learned"]["iters"]))
+    ctx.close()
+    ip = sum(sum(r["plain"]["iters"]) for r in rows)
+    il = sum(sum(r["learned"]["iters"]) for r in rows)
+    return {"workload": "1000 five-arm starfish x 128 nodes, area fraction 0.35-0.45, grid 1024^2, mixed, tol 1e-6",
+            "train_configurations": n_train, "train_solves": n_train * solves, "train_s": t_train,
+            "loss_first_last": [losses[0], losses[-1]], "held_out": rows,
+            "iters_plain": ip, "iters_learned": il, "iteration_ratio": il / ip}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -499,13 +564,14 @@ def main():
     ap.add_argument("--matvecs", type=int, default=20)
     ap.add_argument("--train-configs", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="step", choices=["step", "matvec", "copy", "batch", "bd-starfish", "bd-pair"],
+    ap.add_argument("--mode", default="step", choices=["step", "matvec", "copy", "batch", "bd-starfish", "bd-pair", "learned"],
                     help="step: the EM-RFD benchmark; matvec: only single-layer matvecs of the first form "
                          "(short runs for counter collection); copy: a plain 1 GiB device copy "
                          "used to calibrate the HBM byte counters; batch: EM-RFD steps of the "
                          "64-suspension uneven batch, batched against one after another; bd-starfish / bd-pair: "
                          "the Brownian-dynamics validation runs (single starfish with and without the "
-                         "RFD term; spring-coupled pair with EM-RFD and AB2-RFD)")
+                         "RFD term; spring-coupled pair with EM-RFD and AB2-RFD at three time steps); learned: the "
+                         "learned-correction study on 1000-body dense suspensions")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -536,8 +602,13 @@ def main():
         print(json.dumps(dict(mode="bd-starfish", **run_bd_starfish(fb, W, np, torch))), flush=True)
         return
     if args.mode == "bd-pair":
-        for scheme in ("em", "ab2"):
-            print(json.dumps(dict(mode="bd-pair", **run_bd_pair(fb, W, np, torch, scheme=scheme))), flush=True)
+        for dt in (0.0297, 0.0149, 0.00743):  # tau_s / 4, / 8, / 16
+            for scheme in ("em", "ab2"):
+                print(json.dumps(dict(mode="bd-pair", **run_bd_pair(fb, W, np, torch, scheme=scheme, dt=dt))),
+                      flush=True)
+        return
+    if args.mode == "learned":
+        print(json.dumps(dict(mode="learned", **run_learned(fb, W, np, torch))), flush=True)
         return
     wl = W.make(args.config)
     names = [f for f in args.forms.split(",") if f]

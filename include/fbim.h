@@ -252,6 +252,38 @@ fbim_status fbim_step_ab2_rfd(fbim_ctx *ctx, double dt, double delta, const doub
                               double *NF_hist, int32_t have_hist, double *dQ, int32_t apply,
                               fbim_info *info);
 
+/* ---- Completed second-kind formulation (Appendix B) --------------------------
+ * The exterior flow as a double-layer potential of a density phi plus, per body,
+ * a Stokeslet with its force and a rotlet with its torque at its tracking point
+ * (the Power-Miranda completion).  On the boundary, with u and omega tied to phi,
+ *   u_b + omega_b (x - q_b)^perp = phi/2 + D phi + sum_c [G(x - q_c) f_c + R(x - q_c) tau_c] + slip,
+ *   u_b = (1/|Gamma_b|) int phi dS,  omega_b = (1/W_b) int phi . (x - q_b)^perp dS,
+ * W_b = int |x - q_b|^2 dS, trapezoid rule in the curve parameter (spectrally
+ * accurate in two dimensions: the stresslet is smooth on the curve).  The
+ * periodic stresslet, Stokeslet and rotlet sums are Ewald-split with the
+ * context's xi: real space over the neighbour lists / cutoff r_c, wave space by
+ * the spectral-Ewald steps (rocFFT), the stresslet's mean term and the
+ * trapezoid diagonal 2 kappa t t^T ds.  Curve normals, tangents and curvature
+ * come from trigonometric interpolation of each shape's reference nodes (either
+ * orientation).  Solved by the context's GMRES (tol_gmres, restart, iteration
+ * limit) without a preconditioner, FP64 in every context; ENOCONV still writes
+ * the outputs.  perp is counterclockwise, (-x_2, x_1), as in fbim_mobility.
+ * The first call in a configuration builds per-node curve data; the state lives
+ * with the context. */
+/* DEVICE F[3n] (forces, torques), slip[2N] or NULL, U[3n], phi_out[2N] or NULL. */
+fbim_status fbim_mobility_second_kind(fbim_ctx *ctx, const double *F, const double *slip, double *U,
+                                      double *phi_out, fbim_info *info);
+/* DEVICE out[2N] = D phi (the formulation's double layer, including the mean and
+ * diagonal terms), for checking the operator. */
+fbim_status fbim_apply_double_layer(fbim_ctx *ctx, const double *phi, double *out);
+/* The mixed first/second-kind Brownian velocity (the closing remark of Appendix
+ * B): the slip sqrt(2 kT/dt) (v^(r) + v^(w)) of the first-kind formulation (as in
+ * fbim_brownian_velocity: Lanczos on M^(r), random Fourier field; NULL noise drawn
+ * by the generator) with the second-kind solve.  Discrete fluctuation-dissipation
+ * balance holds only to the difference of the two discretisations. */
+fbim_status fbim_brownian_velocity_mixed(fbim_ctx *ctx, double dt, const double *F, const double *W_r,
+                                         const double *W_grid, double *U, fbim_info *info);
+
 /* ---- Noise ----------------------------------------------------------------
  * The method consumes independent standard normals (W^(r), W^(w): Sections
  * 3.1 and 3.3; W, W~: Section 4.4).  Each context carries a counter-based

@@ -239,13 +239,27 @@ class SecondKind:
         # unknowns [phi; U]: rows  K U - (1/2 + D) phi = C F  and  U - Z phi = 0
         self.A = np.block([[-(0.5 * np.eye(2 * N) + self.D), self.K], [-self.Z, np.eye(3 * nb)]])
 
-    def mobility(self, Fb):
-        """U = N F for body forces and torques F (3n); returns (U, phi)."""
+    def mobility(self, Fb, slip=None):
+        """U for body forces and torques F (3n) and an optional surface slip (2N)
+        added to the completion flow (u + omega r^perp = phi/2 + D phi + C F + slip);
+        returns (U, phi)."""
         N2 = 2 * len(self.X)
-        rhs = np.concatenate([self.C @ Fb, np.zeros(3 * self.geo.n)])
+        top = self.C @ Fb if slip is None else self.C @ Fb + slip
+        rhs = np.concatenate([top, np.zeros(3 * self.geo.n)])
         sol = np.linalg.solve(self.A, rhs)
         return sol[N2:], sol[:N2]
 
     def body_mobility(self):
         n3 = 3 * self.geo.n
         return np.stack([self.mobility(e)[0] for e in np.eye(n3)], axis=1)
+
+
+def brownian_velocity_mixed(geo, prm, F_b, W_r, W_grid, kT, dt, order=4, eta=1.0, tau=1e-8):
+    """The mixed first/second-kind Brownian velocity (closing remark of Appendix B):
+    the first-kind slip sqrt(2 kT/dt) (v^(r) + v^(w)) of eq. 3.27 (dense first-kind
+    oracle) with the second-kind solve at the first-kind parameters' xi.
+    Parity unpinned beyond its two parts: it is the composition of the pinned
+    first-kind slip and the pinned second-kind solve."""
+    slip, _, _ = F.DenseFBIM(geo, prm, order, eta, tau).slip(W_r, W_grid, kT, dt)
+    U, _ = SecondKind(geo, prm["xi"], eta).mobility(F_b, slip)
+    return U

@@ -143,6 +143,9 @@ def _load():
         "fbim_noise_words": (i32, [p, u32, ctypes.c_uint64, ctypes.c_size_t, p]),
         "fbim_noise_counter": (i32, [p, P(ctypes.c_uint64)]),
         "fbim_set_noise_counter": (i32, [p, ctypes.c_uint64]),
+        "fbim_mobility_second_kind": (i32, [p, p, p, p, p, P(Info)]),
+        "fbim_apply_double_layer": (i32, [p, p, p]),
+        "fbim_brownian_velocity_mixed": (i32, [p, d, p, p, p, p, P(Info)]),
         "fbim_autotune": (i32, [p, u32, ctypes.c_char_p, P(Params), P(TuneReport)]),
         "fbim_autotune_key": (i32, [p, u32, ctypes.c_char_p, i32]),
         "fbim_autotune_lookup": (i32, [ctypes.c_char_p, ctypes.c_char_p, P(i32), P(i32), P(i32)]),
@@ -285,6 +288,25 @@ class Context:
                                         q.ctypes.data_as(ctypes.c_void_p), th.ctypes.data_as(ctypes.c_void_p)))
         d = self.get_derived()
         self.n, self.N = d["n_bodies"], d["n_nodes"]
+
+    # -- completed second-kind formulation
+    def mobility_second_kind(self, F, U, slip=None, phi=None):
+        info = Info()
+        self._check(lib.fbim_mobility_second_kind(self._ctx, _dptr(F, 3 * self.n), _optr(slip, 2 * self.N),
+                                                  _dptr(U, 3 * self.n), _optr(phi, 2 * self.N),
+                                                  ctypes.byref(info)), allow=(4,))
+        return info.as_dict()
+
+    def apply_double_layer(self, phi, out):
+        self._check(lib.fbim_apply_double_layer(self._ctx, _dptr(phi, 2 * self.N), _dptr(out, 2 * self.N)))
+
+    def brownian_velocity_mixed(self, dt, F, W_r, W_grid, U):
+        M = self.get_derived()["grid_M"]
+        info = Info()
+        self._check(lib.fbim_brownian_velocity_mixed(self._ctx, dt, _dptr(F, 3 * self.n), _optr(W_r, 2 * self.N),
+                                                     _optr(W_grid, 2 * M * M), _dptr(U, 3 * self.n),
+                                                     ctypes.byref(info)), allow=(4,))
+        return info.as_dict()
 
     def autotune(self, what, cache_path=None):
         """fbim_autotune: (parameters dict for Context(**...), report dict)."""

@@ -13,7 +13,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfbim.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-SOURCES = ["kernels_geom.hip", "kernels_real.hip", "kernels_wave.hip", "kernels_la.hip", "kernels_mlp.hip", "kernels_fft.hip", "kernels_rng.hip", "fbim_api.hip", "batch_api.hip", "tune.hip",
+SOURCES = ["kernels_geom.hip", "kernels_real.hip", "kernels_wave.hip", "kernels_la.hip", "kernels_mlp.hip", "kernels_fft.hip", "kernels_rng.hip", "kernels_sk.hip", "fbim_api.hip", "batch_api.hip", "tune.hip", "second_kind.hip",
            "host_math.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result", "-Wno-unused-value",

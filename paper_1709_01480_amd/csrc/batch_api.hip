@@ -1142,11 +1142,20 @@ fbim_status em_rfd_batch(BatchEngine *E, const std::vector<fbim_ctx *> &mem, dou
     for (int k = 0; rfd && k < 2; ++k) {
       if (!c->rfd[k]) {
         EST(clone_ctx(c, &c->rfd[k]));
-        c->rfd[k]->mlp_on = false;
       }
       fbim_ctx *r = c->rfd[k];
       r->stream = c->stream;
       r->p.tol_gmres = c->p.tol_rfd;  // the RFD solves stop at their own tolerance
+      // the learned correction as the member uses it: its weights, refreshed at the
+      // copy's configuration when the copy moves below
+      r->mlp_on = false;
+      if (c->mlp_on && c->mlp_init) {
+        EST(ensure_mlp(r, c->n));
+        EHIP(E, hipMemcpyAsync(r->d_mw, c->d_mw, FBIM_MLP_NPARAM * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        r->mlp_sym = c->mlp_sym;
+        r->mlp_init = true;
+        r->mlp_on = true;
+      }
       if (!r->have_bodies || r->n != c->n || r->h_shape != c->h_shape) {
         // first use (or new bodies): the copy takes the member's bodies at the
         // configuration its caller last gave, then moves on the device

@@ -20,7 +20,8 @@
 
 namespace fbim {
 
-struct BatchEngine;  // launch set of a batch of systems (batch_api.hip)
+struct BatchEngine;      // launch set of a batch of systems (batch_api.hip)
+struct SecondKindState;  // second-kind solver state, allocated on first use (second_kind.hip)
 
 struct ShapeDev {
   ShapeHost h;
@@ -66,6 +67,9 @@ struct fbim_ctx {
   float *noalloc_scratch = nullptr;  // this device's copy of the no-allocation scratch array
   bool mixed = false;
   bool cur32 = true;  // in a mixed context: matvecs use the FP32 kernels
+  int op = 0;         // operator of apply_saddle / apply_precond: 0 first kind, 1 second kind
+  uint64_t geom_serial = 0;  // incremented by every geometry build
+  SecondKindState *sk = nullptr;
 
   std::vector<ShapeDev> shapes;
   double **d_ref_arr = nullptr, **d_band_arr = nullptr, **d_Mp_arr = nullptr, **d_Pref_arr = nullptr,
@@ -317,6 +321,12 @@ fbim_status move_bodies(fbim_ctx *c, const double *q_src, const double *th_src, 
 // null when the call takes none) from the context's generator at one draw
 // counter, which is then advanced; the pointers are redirected to the draws
 fbim_status fill_noise(fbim_ctx *c, const double *&W_r, const double *&W_grid, const double **W_tilde);
+// weights and activations of the learned correction for n bodies (fbim_api.hip)
+fbim_status ensure_mlp(fbim_ctx *c, int n);
+// the second-kind operator [phi; U] -> [-(1/2 + D) phi + K U; U - Z phi] and the
+// release of its state (second_kind.hip)
+fbim_status apply_second_kind(fbim_ctx *c, const double *x, double *y);
+void sk_destroy(fbim_ctx *c);
 
 // batches (batch_api.hip)
 BatchEngine *engine_new();

@@ -430,6 +430,7 @@ fbim_status build_geometry_dev(fbim_ctx *c) {
     c->slist_cap = cap;
   }
   HIPCHK(c, launch_spread_lists(c->wave(), nullptr, c->d_sstart, c->d_slist, 1, s));
+  ++c->geom_serial;
   if (c->mlp_on) STCHK(mlp_refresh(c));
   return FBIM_OK;
 }
@@ -582,6 +583,7 @@ fbim_status random_field(fbim_ctx *c, const double *W_grid, double *out) {
 
 // saddle operator of eq. 3.8: y = [M mu - K U; -K^T mu]
 fbim_status apply_saddle(fbim_ctx *c, const double *x, double *y) {
+  if (c->op == 1) return apply_second_kind(c, x, y);
   const size_t twoN = 2 * (size_t)c->N;
   STCHK(apply_M(c, x, y, FBIM_PART_ALL));
   HIPCHK(c, launch_sub_KU(c->geom(), x + twoN, y, c->stream));
@@ -590,6 +592,10 @@ fbim_status apply_saddle(fbim_ctx *c, const double *x, double *y) {
 }
 
 fbim_status apply_precond(fbim_ctx *c, const double *z, double *y) {
+  if (c->op == 1) {  // the second-kind system runs unpreconditioned
+    HIPCHK(c, hipMemcpyAsync(y, z, c->ntot * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return FBIM_OK;
+  }
   Timer t(c, "precond");
   HIPCHK(c, launch_precond(c->geom(), c->mats(), c->bt, c->mlp_on ? c->d_dN : nullptr, z, y, c->stream));
   return FBIM_OK;
@@ -1116,6 +1122,7 @@ void fbim_destroy(fbim_ctx *c) {
   if (!c) return;
   if (c->stream) hipStreamSynchronize(c->stream);
   resolve_timing(c);
+  sk_destroy(c);
   for (auto &s : c->shapes) {
     dfree(s.ref);
     dfree(s.band);

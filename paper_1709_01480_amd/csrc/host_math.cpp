@@ -743,4 +743,66 @@ std::string build_shape(int n_p, const double *ref_xy, const Derived &d, double 
   return "";
 }
 
+// ---------------------------------------------------------------- curve data (second kind)
+std::string curve_data(int n_p, const double *ref_xy, std::vector<double> &node6, double &length, double &W) {
+  if (n_p < 8 || n_p % 2) return "curve data needs an even n_p >= 8";
+  const int n = n_p;
+  // first and second derivatives in s of each coordinate: DFT, multiply by (i k),
+  // (i k)^2 with k in (-n/2, n/2) (the Nyquist mode dropped from the first
+  // derivative, kept in the second), inverse DFT; O(n^2), long double
+  std::vector<double> d1(2 * n), d2(2 * n);
+  const long double pi = 3.14159265358979323846264338327950288L;
+  for (int c = 0; c < 2; ++c) {
+    std::vector<long double> re(n), im(n);
+    for (int k = 0; k < n; ++k) {
+      long double a = 0, b = 0;
+      for (int j = 0; j < n; ++j) {
+        const long double ang = -2.0L * pi * (long double)((long long)j * k % n) / n;
+        a += ref_xy[2 * j + c] * cosl(ang);
+        b += ref_xy[2 * j + c] * sinl(ang);
+      }
+      re[k] = a;
+      im[k] = b;
+    }
+    for (int j = 0; j < n; ++j) {
+      long double s1 = 0, s2 = 0;
+      for (int k = 0; k < n; ++k) {
+        const int kk = k < n / 2 ? k : k - n;
+        const long double ang = 2.0L * pi * (long double)((long long)j * k % n) / n;
+        const long double cr = re[k] * cosl(ang) - im[k] * sinl(ang);  // Re(c_k e^{i ang})
+        const long double ci = re[k] * sinl(ang) + im[k] * cosl(ang);  // Im(c_k e^{i ang})
+        if (k != n / 2) s1 += -(long double)kk * ci;                   // Re(i kk c_k e^{i ang})
+        const long double kq = k == n / 2 ? (long double)(n / 2) : (long double)kk;
+        s2 += -kq * kq * cr;
+      }
+      d1[2 * j + c] = (double)(s1 / n);
+      d2[2 * j + c] = (double)(s2 / n);
+    }
+  }
+  // orientation from the signed area (1/2) int (x y' - y x') ds
+  double area = 0;
+  for (int j = 0; j < n; ++j) area += ref_xy[2 * j] * d1[2 * j + 1] - ref_xy[2 * j + 1] * d1[2 * j];
+  if (!(std::fabs(area) > 0)) return "degenerate curve";
+  const double sgn = area > 0 ? 1.0 : -1.0;
+  node6.assign(6 * (size_t)n, 0.0);
+  length = 0;
+  W = 0;
+  for (int j = 0; j < n; ++j) {
+    const double xp = d1[2 * j], yp = d1[2 * j + 1], xpp = d2[2 * j], ypp = d2[2 * j + 1];
+    const double sp = std::hypot(xp, yp);
+    if (!(sp > 0)) return "curve with a stationary point";
+    const double tx = xp / sp, ty = yp / sp;
+    double *o = &node6[6 * (size_t)j];
+    o[0] = sgn * ty;  // outward: the tangent turned clockwise for a counterclockwise curve
+    o[1] = -sgn * tx;
+    o[2] = tx;
+    o[3] = ty;
+    o[4] = sgn * (xp * ypp - yp * xpp) / (sp * sp * sp);
+    o[5] = sp * 2.0 * (double)pi / n;
+    length += o[5];
+    W += (ref_xy[2 * j] * ref_xy[2 * j] + ref_xy[2 * j + 1] * ref_xy[2 * j + 1]) * o[5];
+  }
+  return "";
+}
+
 }  // namespace fbim

@@ -61,6 +61,14 @@ struct ShapeHost {
   std::vector<double> Gref, Gpref; // (2n_p)^2 column-major (symmetric)
 };
 
+// Second-kind data of a closed curve sampled at n_p equispaced parameter values
+// s_j = 2 pi j / n_p (either orientation): derivatives by trigonometric
+// interpolation; per node [n_x, n_y, t_x, t_y, kappa, ds] with n the outward unit
+// normal, t the unit tangent, kappa the curvature (positive where the curve is
+// convex), ds = |gamma'(s_j)| 2 pi / n_p; length = sum ds, W = sum |x|^2 ds
+// (about the reference origin, the tracking point).  Returns "" on success.
+std::string curve_data(int n_p, const double *ref_xy, std::vector<double> &node6, double &length, double &W);
+
 // Build all per-shape reference data; returns "" on success.
 std::string build_shape(int n_p, const double *ref_xy, const Derived &d, double eta, int order,
                         double tau, ShapeHost &out);

@@ -154,6 +154,41 @@ hipError_t launch_wave_conv_f32(const WaveConvArgs &a, float *grid, float *spec,
 hipError_t launch_multiplier_f32(int M, double L, double xi, double eta_s, double scale, int mode, float *spec,
                                  hipStream_t s);
 
+// second-kind formulation (Appendix B; kernels_real.hip, kernels_sk.hip)
+// real-space periodic stresslet over the neighbour lists: out[node] = cG sum_s
+// T^(r)_jlm phi_l w_m with src the pair records (x, y, phi) and wc[k] = n ds of the
+// k-th cell-sorted node (outward normal)
+hipError_t launch_dl_real(const PairLists &pl, const PairArgs &a, const double *src, const double *wc, double *out,
+                          hipStream_t s);
+// real-space completion flow at every node from the bodies' (f_x, f_y, tau) F[3n]
+// at q[2n] (x: wrapped node positions), O(N n)
+hipError_t launch_sk_complete_real(int N, int n, const double *x, const double *q, const double *F, double L,
+                                   const PairArgs &a, double *out, hipStream_t s);
+// per node: w = n ds, diag = 2 kappa ds t t^T (xx, xy, yy), ds, r = x - q (rotated
+// reference data sk6[shape][n_p][nx, ny, tx, ty, kappa, ds]); wc = w in cell order
+hipError_t launch_sk_geom(const GeomDev &g, const double *const *sk6, const int *cperm, double *w, double *wc,
+                          double *diag, double *ds, double *r, hipStream_t s);
+// tile-ordered spreading inputs A = phi_x w, B = phi_y w
+hipError_t launch_sk_prep(int N, const int *tperm, const double *phi, const double *w, double *A, double *B,
+                          hipStream_t s);
+// the bodies' (f_x, f_y, tau) spread with the Gaussian of w into grid planes 0..2
+// (added; FP64 atomics, P <= 15)
+hipError_t launch_point_spread(int n, const double *q, const double *F, const WaveArgs &w, double *grid,
+                               hipStream_t s);
+// multiplier on [4][M][M/2+1] half spectra: mode 0 stresslet (S_xx, S_xy, S_yx, S_yy
+// -> U_x, U_y), mode 1 completion (f_x, f_y, tau -> U_x, U_y); sc = h^2 / (eta L^2)
+hipError_t launch_sk_mult(int M, double L, double xi, double eta_s, double sc, int mode, double *spec,
+                          hipStream_t s);
+// closure rows yU = U - Z phi per body and the stresslet mean term mean[2] =
+// cm sum_s (q + r)_s (phi . w)_s (lw: per shape length, W; part: n x 2 scratch)
+hipError_t launch_sk_body(const GeomDev &g, const double *lw, const double *phi, const double *w, const double *ds,
+                          const double *r, const double *U, double *yU, double *part, double cm, double *mean,
+                          hipStream_t s);
+// y_phi = -phi/2 + real + wave + mean + cG diag phi + U_b + omega_b r^perp
+hipError_t launch_sk_combine(const GeomDev &g, const double *phi, const double *real, const double *wave,
+                             const double *mean, const double *diag, double cG, const double *r, const double *U,
+                             double *y, hipStream_t s);
+
 // rigid-body maps (Section 3.1)
 // y_mu[i] = y_mu[i] - (K U)_i ; y_U[b] = sgn * (K^T mu)_b
 hipError_t launch_sub_KU(const GeomDev &g, const double *U, double *y, hipStream_t s);

@@ -420,4 +420,105 @@ hipError_t launch_pair_batch(const PairJob *jobs, BatchGrid bg, int f32, const d
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ second kind (Appendix B)
+namespace {
+
+// Real-space periodic stresslet over the neighbour lists: for each cell-sorted
+// target, sum over its in-range sources of T^(r)_jlm(d) phi_l w_m with
+// d = x_t - x_s, w = n ds (outward normal times arc weight):
+//   T^(r)_jlm phi_l w_m = e [-4 (1 + z) / r^4 (d.phi)(d.w) d_j + 2 xi^2 ((phi.w) d_j + (d.phi) w_j)],
+// z = xi^2 r^2, e = exp(-z).  One thread per target; output (times cG) in node order.
+__global__ __launch_bounds__(256) void k_dl_ell(PairJob j, const double2 *__restrict__ wc) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= j.N) return;
+  const int g = t >> 6, lane = t & 63;
+  const double4 me = Rec<double>::load(j.src, t);
+  const double cell = j.cell, xi2 = j.xi2;
+  const int base = j.goff[g], rows = j.gnn[g] + j.gnf[g];
+  double vx = 0, vy = 0;
+  for (int i = 0; i < rows; ++i) {
+    const int code = j.ell[base + (size_t)i * 64 + lane];
+    if (code < 0) continue;
+    const int sidx = code & kIndexMask;
+    const double4 r = Rec<double>::load(j.src, sidx);
+    const double2 w = wc[sidx];
+    const double ox = (double)((code >> kCodeShift) & 3) - 1.0, oy = (double)((code >> (kCodeShift + 2)) & 3) - 1.0;
+    const double dx = me.x - (r.x + ox * cell), dy = me.y - (r.y + oy * cell);
+    const double r2 = dx * dx + dy * dy;
+    const double z = xi2 * r2;
+    const double e = exp(-z);
+    const double dp = dx * r.z + dy * r.w, dw = dx * w.x + dy * w.y, pw = r.z * w.x + r.w * w.y;
+    const double a = -4.0 * (1.0 + z) / (r2 * r2) * dp * dw + 2.0 * xi2 * pw;
+    const double b = 2.0 * xi2 * dp;
+    vx += e * (a * dx + b * w.x);
+    vy += e * (a * dy + b * w.y);
+  }
+  const int node = j.perm[t];
+  j.out[2 * node] = j.cG * vx;
+  j.out[2 * node + 1] = j.cG * vy;
+}
+
+// Real-space part of the completion flow: at every node, the Hasimoto-split
+// Stokeslet G^(r) (eq. 3.15) and rotlet R^(r) = r^perp / r^2 (1 - z) e^-z of every
+// body's tracking point within r_c (minimum image), with force f_c and torque
+// tau_c (F = [f_x, f_y, tau] per body), times cG = 1 / (4 pi eta).  One thread per
+// node, a loop over the bodies: O(N n), evaluated once per solve.
+__global__ __launch_bounds__(256) void k_sk_complete_real(int N, int n, const double *__restrict__ x,
+                                                         const double *__restrict__ q, const double *__restrict__ F,
+                                                         double L, double rc2, double xi2, double cG,
+                                                         const double *__restrict__ tab, double *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double xx = x[2 * i], xy = x[2 * i + 1];
+  double vx = 0, vy = 0;
+  for (int c = 0; c < n; ++c) {
+    double dx = xx - q[2 * c], dy = xy - q[2 * c + 1];
+    dx -= L * rint(dx / L);
+    dy -= L * rint(dy / L);
+    const double r2 = dx * dx + dy * dy;
+    if (r2 > rc2 || r2 == 0.0) continue;
+    const double z = xi2 * r2;
+    const double ez = exp(-z);
+    const double e1 = z <= 2.0 ? poly<double, 16>(tab, z) - log(z) : ez * poly<double, 16>(tab + far_interval(z) * 19, z);
+    const double fx = F[3 * c], fy = F[3 * c + 1], tq = F[3 * c + 2];
+    const double a = 0.5 * e1 - ez;
+    const double sdot = ez * (dx * fx + dy * fy) / r2;
+    const double rot = (1.0 - z) * ez / r2 * tq;
+    vx += a * fx + sdot * dx - rot * dy;
+    vy += a * fy + sdot * dy + rot * dx;
+  }
+  out[2 * i] = cG * vx;
+  out[2 * i + 1] = cG * vy;
+}
+
+}  // namespace
+
+hipError_t launch_dl_real(const PairLists &pl, const PairArgs &a, const double *src, const double *wc, double *out,
+                          hipStream_t s) {
+  if (pl.N == 0) return hipSuccess;
+  PairJob j;
+  j.N = pl.N;
+  j.ngroups = pl.ngroups;
+  j.perm = a.perm;
+  j.goff = pl.goff;
+  j.gnn = pl.gnn;
+  j.gnf = pl.gnf;
+  j.ell = pl.ell;
+  j.cell = a.cell;
+  j.xi2 = a.xi2;
+  j.cG = a.cG;
+  j.src = src;
+  j.out = out;
+  hipLaunchKernelGGL(k_dl_ell, dim3((pl.N + 255) / 256), dim3(256), 0, s, j, (const double2 *)wc);
+  return hipGetLastError();
+}
+
+hipError_t launch_sk_complete_real(int N, int n, const double *x, const double *q, const double *F, double L,
+                                   const PairArgs &a, double *out, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sk_complete_real, dim3((N + 255) / 256), dim3(256), 0, s, N, n, x, q, F, L, a.rc2, a.xi2,
+                     a.cG, a.e1tab, out);
+  return hipGetLastError();
+}
+
 }  // namespace fbim
