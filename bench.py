@@ -554,6 +554,48 @@ def run_learned(fb, W, np, torch, n_train=100, solves=100, epochs=4, n_test=6, p
             "iters_plain": ip, "iters_learned": il, "iteration_ratio": il / ip}
 
 
+def run_second_kind(fb, W, np, torch, reps=5):
+    """The completed second-kind solver against the first-kind one on the
+    100-starfish suspension (12,800 nodes, grid 256^2, FP64, GMRES 1e-8): time per
+    operator application (HIP events around `reps` applications), iterations and
+    time per mobility solve, and the two mobilities' difference."""
+    wl = W.make("starfish100")
+    ctx = fb.Context(**dict(wl.params(), tol_gmres=1e-8))
+    sid = ctx.add_shape(fb.starfish(wl.r_s, wl.b, wl.n_arm, wl.n_p))
+    ctx.set_bodies(np.full(wl.n_bodies, sid), wl.q, wl.theta)
+    N = wl.n_nodes
+    phi = torch.as_tensor(np.random.default_rng(3).standard_normal(2 * N)).cuda()
+    out = torch.zeros(2 * N, dtype=torch.float64, device="cuda")
+    F = torch.as_tensor(wl.F).cuda()
+    U1 = torch.zeros(3 * wl.n_bodies, dtype=torch.float64, device="cuda")
+    U2 = torch.zeros_like(U1)
+    res = {"workload": "starfish100: 100 five-arm starfish x 128 nodes, grid 256^2, FP64, GMRES tol 1e-8"}
+    for name, fn in (("single_layer_matvec_ms", lambda: ctx.apply_M(phi, out, fb.PART_ALL)),
+                     ("double_layer_matvec_ms", lambda: ctx.apply_double_layer(phi, out))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / reps
+    for name, fn, U in (("first_kind", lambda: ctx.mobility(F, U1), U1),
+                        ("second_kind", lambda: ctx.mobility_second_kind(F, U2), U2)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = fn()
+        torch.cuda.synchronize()
+        res[name] = {"ms": 1e3 * (time.perf_counter() - t0), "gmres_iters": info["gmres_iters"],
+                     "residual": info["gmres_residual"]}
+    u1, u2 = U1.cpu().numpy(), U2.cpu().numpy()
+    res["mobility_difference"] = float(np.linalg.norm(u1 - u2) / np.linalg.norm(u2))
+    ctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -564,14 +606,16 @@ def main():
     ap.add_argument("--matvecs", type=int, default=20)
     ap.add_argument("--train-configs", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="step", choices=["step", "matvec", "copy", "batch", "bd-starfish", "bd-pair", "learned"],
+    ap.add_argument("--mode", default="step", choices=["step", "matvec", "copy", "batch", "bd-starfish", "bd-pair", "learned",
+                             "second-kind"],
                     help="step: the EM-RFD benchmark; matvec: only single-layer matvecs of the first form "
                          "(short runs for counter collection); copy: a plain 1 GiB device copy "
                          "used to calibrate the HBM byte counters; batch: EM-RFD steps of the "
                          "64-suspension uneven batch, batched against one after another; bd-starfish / bd-pair: "
                          "the Brownian-dynamics validation runs (single starfish with and without the "
                          "RFD term; spring-coupled pair with EM-RFD and AB2-RFD at three time steps); learned: the "
-                         "learned-correction study on 1000-body dense suspensions")
+                         "learned-correction study on 1000-body dense suspensions; second-kind: the completed "
+                         "second-kind solver against the first-kind one on 100 bodies")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -606,6 +650,9 @@ def main():
             for scheme in ("em", "ab2"):
                 print(json.dumps(dict(mode="bd-pair", **run_bd_pair(fb, W, np, torch, scheme=scheme, dt=dt))),
                       flush=True)
+        return
+    if args.mode == "second-kind":
+        print(json.dumps(dict(mode="second-kind", **run_second_kind(fb, W, np, torch))), flush=True)
         return
     if args.mode == "learned":
         print(json.dumps(dict(mode="learned", **run_learned(fb, W, np, torch))), flush=True)
