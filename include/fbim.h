@@ -101,7 +101,9 @@ typedef struct {
   double xi;             /* Ewald splitting parameter (0: derive) */
   double tau_spurious;   /* eigenvalues <= tau * lambda_max treated as spurious (default 1e-8) */
   int32_t alpert_order;  /* 4 or 8 */
-  int32_t n_box;         /* cells per side; r_c = L / n_box (0: derive); must be >= 3 */
+  int32_t n_box;         /* cells per side; r_c = L / n_box (0: derive); must be >= 3,
+                            and xi r_c <= 8 (the real-space series covers xi^2 r^2 <= 64,
+                            where the Stokeslet's real part is below 1e-28) */
   int32_t grid_M;        /* Fourier grid M (even; 0: derive) */
   int32_t P;             /* spreading support (odd; 0: derive) */
   int32_t precision;     /* FBIM_PREC_FP64 or FBIM_PREC_MIXED */
@@ -168,7 +170,10 @@ void fbim_starfish(double r_s, double b, int32_t n_arm, int32_t n_p, double *ref
 /* Set the bodies (HOST arrays): shape_id[n], q[2n] tracking points, theta[n].
  * Builds node positions, the cell list (cells of side L/n_box) and the
  * spreading tile lists on the device.  Returns FBIM_EOVERLAP if two nodes of
- * distinct bodies are closer than 0.05 of the smaller node spacing. */
+ * distinct bodies are closer than 0.05 of the smaller node spacing, and
+ * FBIM_EINVAL for more than 2^26 - 2 nodes or more than 4096 nodes in one
+ * cutoff cell (the neighbour lists address a source by its place in its cell;
+ * a larger n_box makes the cells smaller). */
 fbim_status fbim_set_bodies(fbim_ctx *ctx, int32_t n, const int32_t *shape_id, const double *q,
                             const double *theta);
 

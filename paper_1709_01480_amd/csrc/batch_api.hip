@@ -249,6 +249,9 @@ fbim_status build_tables(BatchEngine *E, const std::vector<int> &list, Tables &T
       j.gnn = c->d_gnn;
       j.gnf = c->d_gnf;
       j.ell = c->d_ell;
+      j.tcell = c->d_tcell;
+      j.cell_start = c->d_cstart;
+      j.nb = c->d.n_box;
       j.cell = c->d.L / c->d.n_box;
       j.xi2 = c->d.xi * c->d.xi;
       j.cG = 1.0 / (4.0 * kPi * c->p.eta);

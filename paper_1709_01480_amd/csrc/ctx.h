@@ -127,7 +127,8 @@ struct fbim_ctx {
   int *d_scount = nullptr, *d_sstart = nullptr, *d_slist = nullptr;
   size_t slist_cap = 0;
   int *d_cnt_near = nullptr, *d_cnt_far = nullptr, *d_gnn = nullptr, *d_gnf = nullptr, *d_goff = nullptr,
-      *d_gsize = nullptr, *d_ell = nullptr;
+      *d_gsize = nullptr, *d_tcell = nullptr;
+  uint16_t *d_ell = nullptr;
 
   // matvec scratch
   double *d_mut = nullptr;
@@ -196,6 +197,7 @@ struct fbim_ctx {
     a.cell_start = d_cstart;
     a.perm = d_cperm;
     a.ckey = d_ckey;
+    a.tcell = d_tcell;
     a.nb = d.n_box;
     a.cell = d.L / d.n_box;
     a.rc2 = d.r_c * d.r_c;

@@ -365,7 +365,7 @@ fbim_status build_geometry_dev(fbim_ctx *c) {
   HIPCHK(c, launch_scatter(N, c->d_ckey, c->d_cstart, c->d_ccursor, c->d_cperm, s));
   HIPCHK(c, launch_sort_bins(c->ncell, c->d_cstart, c->d_cperm, s));
   HIPCHK(c, launch_cell_local(N, c->d_cperm, c->d_ckey, c->d_x, c->d.n_box, c->d.L / c->d.n_box, c->d_xs,
-                              c->d_src64, c->mixed ? c->d_src32 : nullptr, s));
+                              c->d_src64, c->mixed ? c->d_src32 : nullptr, c->d_tcell, s));
   // tiles
   HIPCHK(c, hipMemsetAsync(c->d_tcount, 0, c->ntile * sizeof(int), s));
   HIPCHK(c, hipMemsetAsync(c->d_tcursor, 0, c->ntile * sizeof(int), s));
@@ -398,6 +398,8 @@ fbim_status build_geometry_dev(fbim_ctx *c) {
   c->max_tile = hv[2];
   const char *overlap_msg = "nodes of distinct bodies closer than 5% of the node spacing";
   if (hv[1]) return fail(c, FBIM_EOVERLAP, overlap_msg);
+  if (c->max_cell > kEllMaxCell)
+    return fail(c, FBIM_EINVAL, "more than 4096 nodes in one cutoff cell (raise n_box)");
   // neighbour lists of the real-space sum (count, group rows, offsets, fill) and
   // spreading lists of the tiles (count, offsets, fill); one read of both totals
   PairArgs pa = c->pair_args();
@@ -415,14 +417,17 @@ fbim_status build_geometry_dev(fbim_ctx *c) {
   HIPCHK(c, hipStreamSynchronize(s));
   const int total[2] = {pin[0], pin[1]}, olap = pin[2], maxslots = pin[3];
   if (olap) return fail(c, FBIM_EOVERLAP, overlap_msg);
-  if ((size_t)total[0] > c->ell_cap) {
-    const size_t cap = (size_t)total[0] + total[0] / 4 + 64;
+  if ((size_t)total[0] + kEllSlack > c->ell_cap) {
+    const size_t cap = (size_t)total[0] + total[0] / 4 + kEllSlack;
     HIPCHK(c, dalloc(c->d_ell, cap));
     c->ell_cap = cap;
     pl.ell = c->d_ell;
   }
   const int stage = pair_lists_stage_rows(maxslots / 64);
-  if (!stage) HIPCHK(c, launch_fill_int((size_t)total[0], -1, c->d_ell, s));
+  // empty slots (16-bit, two per fill word; total is a multiple of 64)
+  const int empty2 = (int)((unsigned)kEllEmpty | ((unsigned)kEllEmpty << 16));
+  HIPCHK(c, launch_fill_int((stage ? (size_t)kEllSlack : (size_t)total[0] + kEllSlack) / 2, empty2,
+                            reinterpret_cast<int *>(c->d_ell + (stage ? total[0] : 0)), s));
   HIPCHK(c, launch_pair_lists(pa, pl, c->d_xs, 1, s, nullptr, 0.0, nullptr, stage));
   if ((size_t)total[1] > c->slist_cap) {
     const size_t cap = (size_t)total[1] + total[1] / 4 + 64;
@@ -1145,7 +1150,7 @@ void fbim_destroy(fbim_ctx *c) {
                   c->d_mut, c->d_src32, c->d_xt32, c->d_mut32, c->d_grid, c->d_spec, c->d_grid32,
                   c->d_spec32, c->d_e1tab, c->d_e1tab32, c->d_V, c->d_w, c->d_t1, c->d_t2, c->d_b, c->d_x2,
                   c->d_r, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
-                  c->d_U4, c->d_U5, c->d_U6, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU, c->d_bx, c->d_by, c->d_tw, c->d_tw32, c->d_ey, c->d_ey32, c->d_scount, c->d_sstart, c->d_slist, c->d_nz_r, c->d_nz_g, c->d_nz_t, c->d_bc_key, c->d_bc_perm, c->d_bc_count, c->d_bc_cursor, c->d_bc_start, c->d_qprev, c->d_thprev, c->d_qstep, c->d_thstep};
+                  c->d_U4, c->d_U5, c->d_U6, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_tcell, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU, c->d_bx, c->d_by, c->d_tw, c->d_tw32, c->d_ey, c->d_ey32, c->d_scount, c->d_sstart, c->d_slist, c->d_nz_r, c->d_nz_g, c->d_nz_t, c->d_bc_key, c->d_bc_perm, c->d_bc_count, c->d_bc_cursor, c->d_bc_start, c->d_qprev, c->d_thprev, c->d_qstep, c->d_thstep};
   pub_free(c->pub);
   if (c->h_pin) hipHostFree(c->h_pin);
   if (c->h_qpin) hipHostFree(c->h_qpin);
@@ -1206,7 +1211,7 @@ fbim_status fbim_set_bodies(fbim_ctx *c, int32_t n, const int32_t *shape_id, con
     off[b + 1] = off[b] + c->shapes[shape_id[b]].h.n_p;
   }
   const int N = off[n];
-  if (N >= (1 << 30) / 4) return fail(c, FBIM_EINVAL, "too many nodes");
+  if (N > kMaxNodes) return fail(c, FBIM_EINVAL, "too many nodes (at most 2^26 - 2 per context)");
   if (c->have_bodies && n == c->n && std::equal(shape_id, shape_id + n, c->h_shape.begin())) {
     // same bodies moved: only positions and angles change.  A rejected move
     // (overlap, device error) rebuilds the previous configuration, so the
@@ -1266,17 +1271,18 @@ fbim_status fbim_set_bodies(fbim_ctx *c, int32_t n, const int32_t *shape_id, con
     HIPCHK(c, dalloc(c->d_tperm, N));
     HIPCHK(c, dalloc(c->d_xt, 2 * N));
     HIPCHK(c, dalloc(c->d_anchor, 2 * N));
-    HIPCHK(c, dalloc(c->d_src64, 4 * N));
+    HIPCHK(c, dalloc(c->d_src64, 4 * (N + 1)));  // + the zero record
     HIPCHK(c, dalloc(c->d_mut, 2 * N));
     c->ngroups = (N + 63) / 64;
     HIPCHK(c, dalloc(c->d_cnt_near, N));
     HIPCHK(c, dalloc(c->d_cnt_far, N));
+    HIPCHK(c, dalloc(c->d_tcell, N));
     HIPCHK(c, dalloc(c->d_gnn, c->ngroups));
     HIPCHK(c, dalloc(c->d_gnf, c->ngroups));
     HIPCHK(c, dalloc(c->d_gsize, c->ngroups));
     HIPCHK(c, dalloc(c->d_goff, c->ngroups + 1));
     if (c->mixed) {
-      HIPCHK(c, dalloc(c->d_src32, 4 * N));
+      HIPCHK(c, dalloc(c->d_src32, 4 * (N + 1)));
       HIPCHK(c, dalloc(c->d_xt32, 2 * N));
       HIPCHK(c, dalloc(c->d_mut32, 2 * N));
     }

@@ -55,6 +55,7 @@ std::string derive(const fbim_params &p, Derived &d) {
   d.xi = xi;
   d.n_box = n_box;
   d.r_c = L / n_box;
+  if (xi * d.r_c > 8.0) return "xi r_c must not exceed 8 (the real-space E1 series covers xi^2 r^2 <= 64)";
   d.M = M;
   d.P = P;
   d.h = h;
@@ -92,10 +93,21 @@ long double e1l(long double z) {
   return expl(-z) / f;
 }
 
+// interval ends of the far rows: every binade [2^e, 2^(e+1)] from 2 to 64 split at
+// 1.5 * 2^e, so that a far row is the float's exponent and leading mantissa bit
+static const double kFarEnds[kE1Intervals] = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+
 static void interval(int k, double &lo, double &hi) {
   if (k == 0) { lo = 0.0; hi = 2.0; return; }
-  lo = 2.0 * std::pow(1.5, k - 1);
-  hi = 2.0 * std::pow(1.5, k);
+  lo = kFarEnds[k - 1];
+  hi = kFarEnds[k];
+}
+
+int e1_row(double z) {
+  if (z <= 2.0) return 0;
+  int k = 1;
+  while (k < kE1Intervals - 1 && z >= kFarEnds[k]) ++k;
+  return k;
 }
 
 static long double e1_target(int k, long double z) {
@@ -142,8 +154,8 @@ std::vector<double> e1_table(int deg) {
       tc = tn;
     }
     double *row = &tab[k * stride];
-    row[0] = (double)c;
-    row[1] = (double)(1.0L / hw);
+    row[0] = (double)(1.0L / hw);  // x = z row[0] + row[1]
+    row[1] = (double)(-c / hw);
     for (int m = 0; m < n; ++m) row[2 + m] = (double)a[m];
   }
   return tab;
@@ -151,10 +163,9 @@ std::vector<double> e1_table(int deg) {
 
 double e1_table_eval(const std::vector<double> &tab, int deg, double z) {
   const int stride = deg + 3;
-  int k = 0;
-  if (z > 2.0) k = std::min(kE1Intervals - 1, 1 + (int)std::floor(std::log(z / 2.0) / std::log(1.5)));
+  const int k = e1_row(z);
   const double *row = &tab[k * stride];
-  const double x = (z - row[0]) * row[1];
+  const double x = std::fma(z, row[0], row[1]);
   double f = row[2 + deg];
   for (int m = deg - 1; m >= 0; --m) f = std::fma(f, x, row[2 + m]);
   return k == 0 ? f - std::log(z) : std::exp(-z) * f;

@@ -23,17 +23,20 @@ std::string derive(const fbim_params &p, Derived &d);
 // E1 in long double (series for z <= 2, continued fraction by modified Lentz beyond).
 long double e1l(long double z);
 
-// Piecewise polynomial tables for the device E1 evaluation: per interval the
-// centre c, 1 / half-width, then deg + 1 power-series coefficients in
-// x = (z - c) / half-width of the interval's Chebyshev interpolant.
-//   interval 0: [0, 2],              f = E1(z) + ln z
-//   interval k: [2*1.5^(k-1), 2*1.5^k], f = e^z E1(z)
-// Layout per interval: {centre, 1/half-width, a_0, a_1, ..., a_deg}, f = sum a_m x^m.
-constexpr int kE1Intervals = 9;
+// Piecewise polynomial tables for the device E1 evaluation: per interval with
+// centre c and half-width h, deg + 1 power-series coefficients in x = (z - c) / h
+// of the interval's Chebyshev interpolant.
+//   interval 0:  [0, 2],          f = E1(z) + ln z
+//   interval k:  [b_(k-1), b_k],  f = e^z E1(z), ends b = 2, 3, 4, 6, 8, ..., 48, 64
+//                (each binade split at 1.5 times its start)
+// Layout per interval: {1/h, -c/h, a_0, a_1, ..., a_deg}: x = z row[0] + row[1],
+// f = sum a_m x^m.
+constexpr int kE1Intervals = 11;
 constexpr int kE1Deg64 = 16;
 constexpr int kE1Deg32 = 9;
 std::vector<double> e1_table(int deg);
 double e1_table_eval(const std::vector<double> &tab, int deg, double z);  // host check
+int e1_row(double z);  // table row of argument z
 
 // Alpert log-singular end correction: j nodes chi, weights w, a dropped points.
 bool alpert_rule(int order, int &j, int &a, double *chi, double *w, std::string &err);

@@ -35,10 +35,11 @@ hipError_t launch_gather2f(int N, const int *perm, const double *src, float *dst
 // tile order: nearest grid indices a = floor(x / h + 1/2) and offsets x - a h (FP64, and FP32 if off32)
 hipError_t launch_anchors(int N, const int *tperm, const double *x, double h, int *anchor, double *off64,
                           float *off32, hipStream_t s);
-// cell order: coordinates relative to the node's cell corner (loc64 FP64 pairs; and the
-// (x, y) halves of the packed source records src64 and, if given, src32)
+// cell order: each node's cell (tcell) and coordinates relative to the cell's corner (loc64 FP64 pairs; and the
+// (x, y) halves of the packed source records src64 and, if given, src32, which hold
+// N + 1 records: the last is the zero record of empty neighbour-list slots)
 hipError_t launch_cell_local(int N, const int *cperm, const int *key, const double *x, int nb, double cell,
-                             double *loc64, double *src64, float *src32, hipStream_t s);
+                             double *loc64, double *src64, float *src32, int *tcell, hipStream_t s);
 // packed pair-kernel sources: (x, y) from launch_cell_local, densities here:
 // src[i].zw = mu[perm[i]] (src64: double4 records, src32: float4 records)
 hipError_t launch_gather_src(int N, const int *perm, const double *mu, double *src64, float *src32, hipStream_t s);
@@ -53,6 +54,7 @@ struct PairArgs {
   const int *cell_start;
   const int *perm;
   const int *ckey;      // cell of each original node
+  const int *tcell;     // cell of each cell-sorted node
   int nb;
   double cell, rc2, xi2, cG;  // cell side L / n_box
   const double *e1tab;  // FP64 table
@@ -63,13 +65,28 @@ struct PairLists {
   int N, ngroups;
   int *cnt_near, *cnt_far;  // [N]
   int *gnn, *gnf, *goff;    // [ngroups], goff [ngroups + 1]
-  int *ell;                 // [goff[ngroups]]
+  uint16_t *ell;            // [goff[ngroups] + kEllSlack]
 };
+// An ELL entry (16 bits) names a source by the neighbour cell of its target's cell
+// it lies in and its place there: bits 12-15 hold k = (dcx + 1) + 3 (dcy + 1)
+// (0..8), bits 0-11 the source's index within that cell (cells hold at most
+// kEllMaxCell nodes).  k = 9 (kEllEmpty) marks an empty slot, which the pair
+// kernel maps to the zero record after the N sources of the packed record arrays
+// (position (-1.5, -1.5) cells from its cell corner, density 0): it is evaluated
+// like any source and adds exactly 0.  kEllSlack slots after the last group, kept
+// empty: the pair kernel reads up to 12 rows past a group's end (list entries in
+// flight for rows it then skips).
+constexpr int kEllMaxCell = 4096;
+// nodes per context: the N + 1 packed records are indexed below 2^26
+constexpr int kMaxNodes = (1 << 26) - 2;
+constexpr uint16_t kEllEmpty = 9 << 12;
+constexpr int kEllSlack = 16 * 64;
 // mode 0: per-target near / far counts; mode 1: fill pl.ell.  With `flag`
 // (mode 0), *flag is set when nodes of distinct bodies (body[] per original node
 // index) are closer than sqrt(thresh2) (which must not exceed r_c).  Mode 1 with
 // maxrows (the longest group, from pair_lists_stage_rows) > 0 writes every slot
-// (empty ones -1) through LDS; with maxrows = 0 pl.ell must be pre-set to -1.
+// (empty ones kEllEmpty) through LDS; with maxrows = 0 pl.ell must be pre-set to
+// kEllEmpty.
 constexpr size_t kListStageBytes = 64 * 1024;
 int pair_lists_stage_rows(int maxrows);  // maxrows if its staging fits kListStageBytes, else 0
 hipError_t launch_pair_lists(const PairArgs &a, PairLists &pl, const double *xs, int mode, hipStream_t s,
@@ -377,7 +394,10 @@ struct GatherJob {  // dst[i] = src[perm[i]] for N (x, y) pairs; dst FP64 or FP3
 };
 struct PairJob {  // one system's real-space pair sum (launch_pair_f64 / _f32 arguments)
   int N, ngroups;
-  const int *perm, *goff, *gnn, *gnf, *ell;
+  const int *perm, *goff, *gnn, *gnf;
+  const uint16_t *ell;
+  const int *tcell, *cell_start;  // cell of each cell-sorted node; cell offsets
+  int nb;
   double cell, xi2, cG;
   const void *src;  // packed (x, y, mu_x, mu_y) records in cell order (double4 or float4)
   double *out;

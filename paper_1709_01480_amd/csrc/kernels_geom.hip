@@ -312,15 +312,24 @@ hipError_t launch_anchors(int N, const int *tperm, const double *x, double h, in
   return hipGetLastError();
 }
 
-// Cell-ordered coordinates relative to the lower-left corner of the node's cell.
+// Cell-ordered coordinates relative to the lower-left corner of the node's cell;
+// thread N writes the zero record after the sources of the packed record arrays
+// (the source of every empty neighbour-list slot): position (-1.5, -1.5) cells,
+// 1.5 to 2.5 cells from any target of the cell frame, density 0.
 __global__ void k_cell_local(int N, const int *__restrict__ cperm, const int *__restrict__ key,
                              const double *__restrict__ x, int nb, double cell, double2 *__restrict__ loc64,
-                             double2 *__restrict__ src64, float4 *__restrict__ src32) {
+                             double2 *__restrict__ src64, float4 *__restrict__ src32, int *__restrict__ tcell) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == N) {
+    src64[2 * N] = make_double2(-1.5 * cell, -1.5 * cell);
+    src64[2 * N + 1] = make_double2(0.0, 0.0);
+    if (src32) src32[N] = make_float4((float)(-1.5 * cell), (float)(-1.5 * cell), 0.0f, 0.0f);
+  }
   if (k >= N) return;
   const int i = cperm[k];
   const int c = key[i];
   const double lx = x[2 * i] - (c % nb) * cell, ly = x[2 * i + 1] - (c / nb) * cell;
+  tcell[k] = c;
   loc64[k] = make_double2(lx, ly);
   src64[2 * k] = make_double2(lx, ly);
   if (src32) {
@@ -332,10 +341,10 @@ __global__ void k_cell_local(int N, const int *__restrict__ cperm, const int *__
 }
 
 hipError_t launch_cell_local(int N, const int *cperm, const int *key, const double *x, int nb, double cell,
-                             double *loc64, double *src64, float *src32, hipStream_t s) {
+                             double *loc64, double *src64, float *src32, int *tcell, hipStream_t s) {
   if (N == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cell_local, dim3((N + 255) / 256), dim3(256), 0, s, N, cperm, key, x, nb, cell,
-                     (double2 *)loc64, (double2 *)src64, (float4 *)src32);
+  hipLaunchKernelGGL(k_cell_local, dim3((N + 256) / 256), dim3(256), 0, s, N, cperm, key, x, nb, cell,
+                     (double2 *)loc64, (double2 *)src64, (float4 *)src32, tcell);
   return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ template <typename T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
 
-constexpr int kE1Int = 9;         // intervals of the E1 table
+constexpr int kE1Int = 11;        // intervals of the E1 table
 
 // blockIdx -> work item such that consecutive items land on the same XCD
 // (work groups are dealt round-robin over the 8 XCDs)
@@ -29,12 +29,13 @@ __device__ inline double dev_log(double x) { return log(x); }
 __device__ inline float dev_log(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
 
 // E1(z) from the piecewise polynomial table: interval 0 holds E1 + ln z on [0, 2],
-// interval k >= 1 holds e^z E1(z) on [2*1.5^(k-1), 2*1.5^k]; a row is
-// {centre, 1 / half-width, a_0 .. a_DEG} of the power series in
+// interval k >= 1 holds e^z E1(z) on [b_(k-1), b_k] with ends b = 2, 3, 4, 6, 8,
+// 12, ..., 48, 64 (each binade of z split at 1.5 times its start); a row is
+// {1 / half-width, -centre / half-width, a_0 .. a_DEG} of the power series in
 // x = (z - centre) / half-width, evaluated by Horner's rule.
 template <typename T, int DEG>
 __device__ inline T poly(const T *row, T z) {
-  const T x = (z - row[0]) * row[1];
+  const T x = fma(z, row[0], row[1]);
   T f = row[2 + DEG];
 #pragma unroll
   for (int m = DEG - 1; m >= 0; --m) f = fma(f, x, row[2 + m]);
@@ -46,19 +47,18 @@ __device__ inline T poly(const T *row, T z) {
 // layout grouped by 64 consecutive cell-sorted targets (one wavefront): group g
 // owns slots [goff[g], goff[g] + 64 (nn_g + nf_g)); slot i of target lane l is
 // goff[g] + 64 i + l.  The first nn_g rows hold near pairs (xi^2 r^2 <= 2), the
-// next nf_g rows far pairs; empty slots are -1.  An entry packs the source's
-// sorted index (bits 0-26) and its neighbour-cell offset dcx+1 (bits 27-28) and
-// dcy+1 (bits 29-30), so a valid entry is non-negative.
-constexpr int kCodeShift = 27;
-constexpr int kIndexMask = (1 << kCodeShift) - 1;
+// next nf_g rows far pairs.  A 16-bit entry holds the source's neighbour cell k
+// (bits 12-15; k = 9 an empty slot) and its index within that cell (bits 0-11).
+constexpr int kEllK = 10;  // neighbour cells 0..8 and the empty slot
+constexpr int kOffMask = kEllMaxCell - 1;
 
 // One thread per cell-sorted target: it scans the nodes of the 3 x 3 neighbouring
 // cells (cell by cell, node order -- the order of its list rows), counts its near
 // and far pairs (mode 0) or writes them into its ELL slots (mode 1).  With `flag`
 // (mode 0) it also flags nodes of distinct bodies closer than sqrt(thresh2).
 // Mode 1 with maxrows > 0 stages each group's rows in LDS (a lane writes only its
-// own column, empty slots -1) and stores them as whole contiguous rows; with
-// maxrows = 0 it writes the slots directly (ell pre-set to -1).
+// own column, empty slots N) and stores them as whole contiguous rows; with
+// maxrows = 0 it writes the slots directly (ell pre-set to N).
 constexpr int kListBlock = 128;  // two groups of 64 targets
 
 __global__ __launch_bounds__(kListBlock) void k_pair_lists(int N, int ngroups, const int *__restrict__ cell_start,
@@ -67,10 +67,10 @@ __global__ __launch_bounds__(kListBlock) void k_pair_lists(int N, int ngroups, c
                                                            double rc2, double r2near, const double2 *__restrict__ xs,
                                                            int *__restrict__ cnt_near, int *__restrict__ cnt_far,
                                                            const int *__restrict__ goff, const int *__restrict__ gnn,
-                                                           const int *__restrict__ gnf, int *__restrict__ ell,
+                                                           const int *__restrict__ gnf, uint16_t *__restrict__ ell,
                                                            int mode, int maxrows, const int *__restrict__ body,
                                                            double thresh2, int *__restrict__ flag) {
-  extern __shared__ int stile[];  // mode 1 staged: [kListBlock / 64][maxrows][64]
+  extern __shared__ uint16_t stile[];  // mode 1 staged: [kListBlock / 64][maxrows][64]
   const int gt = xcd_remap(blockIdx.x, gridDim.x) * kListBlock + threadIdx.x;
   const int grp = gt >> 6, gl = gt & 63;
   const bool staged = mode && maxrows > 0;
@@ -79,9 +79,9 @@ __global__ __launch_bounds__(kListBlock) void k_pair_lists(int N, int ngroups, c
     nn = gnn[grp];
     rows = nn + gnf[grp];
   }
-  int *col = stile + (threadIdx.x >> 6) * maxrows * 64 + gl;
+  uint16_t *col = stile + (threadIdx.x >> 6) * maxrows * 64 + gl;
   if (staged)
-    for (int r = 0; r < rows; ++r) col[r * 64] = -1;
+    for (int r = 0; r < rows; ++r) col[r * 64] = kEllEmpty;
   if (gt < N) {
     const int c = ckey[perm[gt]];
     const int ccx = c % nb, ccy = c / nb;
@@ -92,10 +92,9 @@ __global__ __launch_bounds__(kListBlock) void k_pair_lists(int N, int ngroups, c
       const int dx = k % 3 - 1, dy = k / 3 - 1;
       const int cc = ((ccy + dy + nb) % nb) * nb + (ccx + dx + nb) % nb;
       const double ox = p.x - dx * cell, oy = p.y - dy * cell;  // target relative to cell cc's corner frame
-      const int code = ((k % 3) << kCodeShift) | ((k / 3) << (kCodeShift + 2));
-      const int g1 = cell_start[cc + 1];
+      const int g0 = cell_start[cc], g1 = cell_start[cc + 1];
 #pragma unroll 4
-      for (int g = cell_start[cc]; g < g1; ++g) {
+      for (int g = g0; g < g1; ++g) {
         const double2 q = xs[g];
         const double ex = ox - q.x, ey = oy - q.y;
         const double r2 = ex * ex + ey * ey;
@@ -103,10 +102,11 @@ __global__ __launch_bounds__(kListBlock) void k_pair_lists(int N, int ngroups, c
         if (flag && r2 < thresh2 && body[perm[gt]] != body[perm[g]]) atomicOr(flag, 1);
         const bool near = r2 <= r2near;
         const int row = near ? cn : nn + cf;
+        const uint16_t e = (uint16_t)((k << 12) | (g - g0));
         if (staged)
-          col[row * 64] = g | code;
+          col[row * 64] = e;
         else if (mode)
-          ell[base + (size_t)row * 64 + gl] = g | code;
+          ell[base + (size_t)row * 64 + gl] = e;
         cn += near;
         cf += !near;
       }
@@ -119,8 +119,8 @@ __global__ __launch_bounds__(kListBlock) void k_pair_lists(int N, int ngroups, c
   if (staged) {
     __syncthreads();
     if (grp < ngroups) {  // the group's rows, contiguous
-      const int *tile = stile + (threadIdx.x >> 6) * maxrows * 64;
-      int *dst = ell + goff[grp];
+      const uint16_t *tile = stile + (threadIdx.x >> 6) * maxrows * 64;
+      uint16_t *dst = ell + goff[grp];
       for (int i = gl; i < rows * 64; i += 64) dst[i] = tile[i];
     }
   }
@@ -151,12 +151,19 @@ __global__ void k_group_rows(int N, int ngroups, const int *__restrict__ cnt_nea
 // Packed source records: (x, y, mu_x, mu_y) in one 16-byte (FP32) or 32-byte
 // (FP64) record per cell-sorted node, so a pair gathers one record.
 template <typename T> struct Rec;
+// Record indices are below 2^26 (at most kMaxNodes + 1 records), so a record's
+// byte offset fits 32 bits: one unsigned (base + index) << shift, no 64-bit
+// address math.
 template <> struct Rec<float> {
-  __device__ static inline float4 load(const void *p, int i) { return reinterpret_cast<const float4 *>(p)[i]; }
+  __device__ static inline float4 load(const void *p, unsigned i) {
+    __builtin_assume(i < (1u << 26));
+    return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(p) + (i << 4));
+  }
 };
 template <> struct Rec<double> {
-  __device__ static inline double4 load(const void *p, int i) {
-    const double2 *q = reinterpret_cast<const double2 *>(p) + 2 * i;
+  __device__ static inline double4 load(const void *p, unsigned i) {
+    __builtin_assume(i < (1u << 26));
+    const double2 *q = reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(p) + (i << 5));
     const double2 a = q[0], b = q[1];
     return make_double4(a.x, a.y, b.x, b.y);
   }
@@ -170,14 +177,16 @@ __device__ inline double dev_rcp(double x) {
   return fma(fma(-x, y, 1.0), y, y);
 }
 
-// interval of a far argument z > 2 of the E1 table: k = 1 + floor(log_1.5(z / 2)),
-// clamped to [1, 8]; taken in FP32 for either precision (an argument within
-// rounding of an interval end may take the neighbouring interval, whose series
-// is accurate there too)
+// row of a far argument z > 2 of the E1 table, read off the FP32 bits of z: bits
+// 22-30 are twice the biased exponent plus the leading mantissa bit, 256 on
+// [2, 3), 257 on [3, 4), 258 on [4, 6), ...; less 255 and clamped to
+// [1, kE1Int - 1].  Taken in FP32 for either precision (an argument within
+// rounding of an interval end may take the neighbouring interval, whose series is
+// accurate there too).
 template <typename T>
 __device__ inline int far_interval(T z) {
-  const float l = __log2f((float)z * 0.5f) * 1.7095112913514547f;  // 1 / log2(1.5)
-  return min(8, max(1, 1 + (int)l));
+  const int key = ((int)__float_as_uint((float)z) - (255 << 22)) >> 22;
+  return min(max(key, 1), kE1Int - 1);
 }
 
 // One 256-thread work group per group of 64 targets: wave w takes rows w, w + 4,
@@ -186,18 +195,42 @@ __device__ inline int far_interval(T z) {
 // per group instead of one long one: at 640k nodes the 10^4 groups fill the
 // chip's wave slots about five times over instead of 1.2 times (a second round
 // of 0.2 of the machine).
-// FP32 sums are compensated (Kahan); FP64 sums of ~15 terms per wave need not be.
-// The loop keeps two loads in flight: the entry two rows ahead and the source
-// record one row ahead are requested before the current row is evaluated.
+// An entry is resolved through the group's neighbour-cell table in LDS: row k of
+// lane l holds the first source of target l's neighbour cell k and the cell's
+// offsets (row 9: the zero record, offsets 0).
+// Row indices are wave-uniform (scalar loop control and near / far branch).  The
+// FP32 loop takes two rows per trip (rows i and i + 4 of the wave) with the next
+// trip's list entries and the second row's source record in flight while the
+// first row is evaluated; a trip's two terms are added in FP32 and the ~8 trip
+// sums of a lane per wave in FP64, so the sum rounds about once per term (as a
+// compensated FP32 sum would) without the compensation's instructions.
 constexpr int kPairWaves = 4;
 
 template <typename T, int DEG>
 __device__ __forceinline__ void pair_ell_body(const PairJob &j, const T *__restrict__ tab, int g) {
-  constexpr bool kKahan = sizeof(T) == 4;
   __shared__ double part[kPairWaves - 1][64][2];
+  __shared__ int4 nbr[kEllK][64];  // (first source, dcx, dcy as float bits, 0)
   const T cell = (T)j.cell, xi2 = (T)j.xi2;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int t = g * 64 + lane;
+  {
+    const int tc = t < j.N ? j.tcell[t] : 0, nb = j.nb;
+    const int cx = tc % nb, cy = tc / nb;
+    for (int k = wv; k < kEllK; k += kPairWaves) {
+      int4 e = make_int4(j.N, 0, 0, 0);
+      if (k < 9) {
+        const int dx = k % 3 - 1, dy = k / 3 - 1;
+        int ux = cx + dx, uy = cy + dy;  // periodic wrap of a neighbour one cell away
+        ux += ux < 0 ? nb : (ux >= nb ? -nb : 0);
+        uy += uy < 0 ? nb : (uy >= nb ? -nb : 0);
+        e = make_int4(j.cell_start[uy * nb + ux], __float_as_int((float)dx), __float_as_int((float)dy), 0);
+      }
+      nbr[k][lane] = e;
+    }
+  }
+  // positions are relative to their cell's corner: a source in neighbour cell
+  // (dcx, dcy) sits at r + (dcx, dcy) cell, so d = (tx - r.x) - dcx cell (exact
+  // difference of nearby coordinates, then one rounding)
   T tx = 0, ty = 0;
   if (t < j.N) {
     const auto p = Rec<T>::load(j.src, t);
@@ -205,66 +238,99 @@ __device__ __forceinline__ void pair_ell_body(const PairJob &j, const T *__restr
     ty = p.y;
   }
   const int base = j.goff[g], nn = j.gnn[g], rows = nn + j.gnf[g];
-  const int *__restrict__ col = j.ell + base + lane;
-  T vx = 0, vy = 0, kx = 0, ky = 0;
-  auto add = [&](T a, T b) {
-    if (kKahan) {
-      T y = a - kx;
-      T s2 = vx + y;
-      kx = (s2 - vx) - y;
-      vx = s2;
-      y = b - ky;
-      s2 = vy + y;
-      ky = (s2 - vy) - y;
-      vy = s2;
-    } else {
-      vx += a;
-      vy += b;
-    }
+  const uint16_t *__restrict__ col = j.ell + base + lane;
+  double vx = 0, vy = 0;
+  __syncthreads();
+  // rows past the group's last are read without a test (the next group's entries,
+  // or the kEllSlack slots after the last group) and never resolved
+  auto entry = [&](int i) { return (unsigned)col[(size_t)i * 64]; };
+  // source record and cell offsets of entry e
+  auto resolve = [&](unsigned e, float &ox, float &oy) {
+    const int4 c = nbr[e >> 12][lane];
+    ox = __int_as_float(c.y);
+    oy = __int_as_float(c.z);
+    return Rec<T>::load(j.src, (unsigned)c.x + (e & kOffMask));
   };
-  // empty slots and slots past the last row read record 0 (always present) and add nothing
-  int c_cur = wv < rows ? col[(size_t)wv * 64] : -1;
-  int c_nxt = wv + kPairWaves < rows ? col[(size_t)(wv + kPairWaves) * 64] : -1;
-  auto rec_cur = Rec<T>::load(j.src, c_cur < 0 ? 0 : (c_cur & kIndexMask));
-  for (int i = wv; i < rows; i += kPairWaves) {
-    const int c_far = i + 2 * kPairWaves < rows ? col[(size_t)(i + 2 * kPairWaves) * 64] : -1;
-    const auto rec_nxt = Rec<T>::load(j.src, c_nxt < 0 ? 0 : (c_nxt & kIndexMask));
-    const int code = c_cur;
-    const auto r = rec_cur;
-    c_cur = c_nxt;
-    c_nxt = c_far;
-    rec_cur = rec_nxt;
-    if (code < 0) continue;
-    const T ox = (T)((code >> kCodeShift) & 3) - T(1), oy = (T)((code >> (kCodeShift + 2)) & 3) - T(1);
-    const T dx = tx - (r.x + ox * cell), dy = ty - (r.y + oy * cell);
-    const T r2 = dx * dx + dy * dy;
+  // one slot's term (cx, cy); an empty slot reads the zero record: a source at
+  // 1.5 to 2.5 cells (finite z, every series finite) with density 0, term 0
+  auto eval = [&](const auto &r, float ox, float oy, bool near, T &cx, T &cy) {
+    const T dx = fma(-(T)ox, cell, tx - r.x), dy = fma(-(T)oy, cell, ty - r.y);
+    const T r2 = fma(dx, dx, dy * dy);
     const T z = xi2 * r2;
     const T ez = dev_exp(-z);
-    // near rows: E1 + ln z on [0, 2]; far rows: e^z E1 on [2*1.5^(k-1), 2*1.5^k].
-    // FP64: one series evaluation on the selected row (fewer registers for the
-    // degree-16 coefficients); FP32: one per branch.
-    const bool near = i < nn;
-    T e1;
+    // near rows: E1 + ln z on [0, 2]; far rows: e^z E1 on the table interval of z
+    // (FP64: one series evaluation on the selected row, fewer registers for the
+    // degree-16 coefficients) or a rational form (FP32).
+    T e1, ir2;  // E1(z) and 1 / r^2
     if constexpr (sizeof(T) == 8) {
       const T p = poly<T, DEG>(tab + (near ? 0 : far_interval(z) * (DEG + 3)), z);
       e1 = near ? p - dev_log(z) : ez * p;
+      ir2 = dev_rcp(r2);
+    } else if (near) {
+      e1 = poly<T, DEG>(tab, z) - dev_log(z);
+      ir2 = dev_rcp(r2);
     } else {
-      if (near)
-        e1 = poly<T, DEG>(tab, z) - dev_log(z);
-      else
-        e1 = ez * poly<T, DEG>(tab + far_interval(z) * (DEG + 3), z);
+      // FP32 far rows: z e^z E1(z) = P(z) / Q(z) with the quartics of Abramowitz
+      // and Stegun 5.1.56 (absolute error below 2e-8 for z >= 1), no table reads;
+      // one reciprocal of r^2 z Q gives both 1 / (z Q) and 1 / r^2
+      const T P = fma(fma(fma(z + T(8.5733287401), z, T(18.0590169730)), z, T(8.6347608925)), z,
+                      T(0.2677737343));
+      const T Q = fma(fma(fma(z + T(9.5733223454), z, T(25.6329561486)), z, T(21.0996530827)), z,
+                      T(3.9584969228));
+      const T zq = z * Q;
+      const T inv = dev_rcp(r2 * zq);
+      ir2 = zq * inv;
+      e1 = ez * (P * (r2 * inv));
     }
-    const T a = T(0.5) * e1 - ez;
-    const T sdot = ez * (dx * r.z + dy * r.w) * dev_rcp(r2);
-    add(a * r.z + sdot * dx, a * r.w + sdot * dy);
+    const T a = fma(T(0.5), e1, -ez);
+    const T sdot = ez * fma(dx, r.z, dy * r.w) * ir2;
+    cx = fma(a, r.z, sdot * dx);
+    cy = fma(a, r.w, sdot * dy);
+  };
+  int i = wv;
+  unsigned eb = entry(wv + kPairWaves);
+  float oxa = 0, oya = 0;
+  decltype(Rec<T>::load(nullptr, 0)) ra{};
+  if (i < rows) ra = resolve(entry(wv), oxa, oya);
+  // FP32: two trips per loop turn, so that the loads in flight alternate between
+  // two register sets instead of being copied at the back edge (FP64 keeps one:
+  // its records are twice as wide)
+  constexpr int kTrips = sizeof(T) == 4 ? 2 : 1;
+#pragma unroll kTrips
+  for (; i + kPairWaves < rows; i += 2 * kPairWaves) {
+    float oxb, oyb;
+    const auto rb = resolve(eb, oxb, oyb);
+    const unsigned na = entry(i + 2 * kPairWaves);
+    eb = entry(i + 3 * kPairWaves);
+    T ax, ay, bx, by;
+    eval(ra, oxa, oya, i < nn, ax, ay);
+    if constexpr (sizeof(T) == 8) {
+      vx += ax;
+      vy += ay;
+    }
+    if (i + 2 * kPairWaves < rows) ra = resolve(na, oxa, oya);
+    eval(rb, oxb, oyb, i + kPairWaves < nn, bx, by);
+    if constexpr (sizeof(T) == 8) {
+      vx += bx;
+      vy += by;
+    } else {  // the trip's two terms meet in FP32 (one rounding), then the FP64 sums
+      vx += (double)(ax + bx);
+      vy += (double)(ay + by);
+    }
+  }
+  if (i < rows) {  // the wave's last row when its count is odd
+    T ax, ay;
+    eval(ra, oxa, oya, i < nn, ax, ay);
+    vx += (double)ax;
+    vy += (double)ay;
   }
   if (wv > 0) {
-    part[wv - 1][lane][0] = (double)vx;
-    part[wv - 1][lane][1] = (double)vy;
+    part[wv - 1][lane][0] = vx;
+    part[wv - 1][lane][1] = vy;
   }
   __syncthreads();
   if (wv == 0 && t < j.N) {
-    double sx = (double)vx, sy = (double)vy;
+    double sx = vx, sy = vy;
 #pragma unroll
     for (int w = 0; w < kPairWaves - 1; ++w) {
       sx += part[w][lane][0];
@@ -310,6 +376,9 @@ hipError_t pair_ell_launch(const PairLists &pl, const PairArgs &a, const T *src,
   j.gnn = pl.gnn;
   j.gnf = pl.gnf;
   j.ell = pl.ell;
+  j.tcell = a.tcell;
+  j.cell_start = a.cell_start;
+  j.nb = a.nb;
   j.cell = a.cell;
   j.xi2 = a.xi2;
   j.cG = a.cG;
@@ -322,13 +391,13 @@ hipError_t pair_ell_launch(const PairLists &pl, const PairArgs &a, const T *src,
 }  // namespace
 
 int pair_lists_stage_rows(int maxrows) {
-  return (size_t)(kListBlock / 64) * maxrows * 64 * sizeof(int) <= kListStageBytes ? maxrows : 0;
+  return (size_t)(kListBlock / 64) * maxrows * 64 * sizeof(uint16_t) <= kListStageBytes ? maxrows : 0;
 }
 
 hipError_t launch_pair_lists(const PairArgs &a, PairLists &pl, const double *xs, int mode, hipStream_t s,
                              const int *body, double thresh2, int *flag, int maxrows) {
   if (pl.N == 0) return hipSuccess;
-  const size_t lds = (mode && maxrows > 0) ? (size_t)(kListBlock / 64) * maxrows * 64 * sizeof(int) : 0;
+  const size_t lds = (mode && maxrows > 0) ? (size_t)(kListBlock / 64) * maxrows * 64 * sizeof(uint16_t) : 0;
   hipLaunchKernelGGL(k_pair_lists, dim3((pl.N + kListBlock - 1) / kListBlock), dim3(kListBlock), lds, s, pl.N,
                      pl.ngroups, a.cell_start, a.ckey, a.perm, a.nb, a.cell, a.rc2, 2.0 / a.xi2, (const double2 *)xs,
                      pl.cnt_near, pl.cnt_far, pl.goff, pl.gnn, pl.gnf, pl.ell, mode, mode ? maxrows : 0, body,
@@ -435,14 +504,18 @@ __global__ __launch_bounds__(256) void k_dl_ell(PairJob j, const double2 *__rest
   const double4 me = Rec<double>::load(j.src, t);
   const double cell = j.cell, xi2 = j.xi2;
   const int base = j.goff[g], rows = j.gnn[g] + j.gnf[g];
+  const int nb = j.nb, cx = j.tcell[t] % nb, cy = j.tcell[t] / nb;
   double vx = 0, vy = 0;
   for (int i = 0; i < rows; ++i) {
-    const int code = j.ell[base + (size_t)i * 64 + lane];
-    if (code < 0) continue;
-    const int sidx = code & kIndexMask;
+    const unsigned ent = j.ell[base + (size_t)i * 64 + lane];
+    const int k = (int)(ent >> 12);
+    if (k >= 9) continue;  // empty slot
+    const int dcx = k % 3 - 1, dcy = k / 3 - 1;
+    const int cc = ((cy + dcy + nb) % nb) * nb + (cx + dcx + nb) % nb;
+    const int sidx = j.cell_start[cc] + (int)(ent & kOffMask);
     const double4 r = Rec<double>::load(j.src, sidx);
     const double2 w = wc[sidx];
-    const double ox = (double)((code >> kCodeShift) & 3) - 1.0, oy = (double)((code >> (kCodeShift + 2)) & 3) - 1.0;
+    const double ox = (double)dcx, oy = (double)dcy;
     const double dx = me.x - (r.x + ox * cell), dy = me.y - (r.y + oy * cell);
     const double r2 = dx * dx + dy * dy;
     const double z = xi2 * r2;
@@ -504,6 +577,9 @@ hipError_t launch_dl_real(const PairLists &pl, const PairArgs &a, const double *
   j.gnn = pl.gnn;
   j.gnf = pl.gnf;
   j.ell = pl.ell;
+  j.tcell = a.tcell;
+  j.cell_start = a.cell_start;
+  j.nb = a.nb;
   j.cell = a.cell;
   j.xi2 = a.xi2;
   j.cG = a.cG;

@@ -73,6 +73,10 @@ def test_starfish_helper_matches_oracle_curve():
 def test_invalid_parameters_rejected():
     with pytest.raises(fb.FbimError):
         fb.derive_params(L=1.0, tol_ewald=1e-9, n_box=2)
+    # cutoff cell wider than the real-space E1 series covers (xi r_c = 10 > 8)
+    with pytest.raises(fb.FbimError):
+        fb.derive_params(L=1.0, tol_ewald=1e-9, n_box=3, xi=30.0, grid_M=64)
+    fb.derive_params(L=1.0, tol_ewald=1e-9, n_box=4, xi=30.0, grid_M=64)  # xi r_c = 7.5
     with pytest.raises(fb.FbimError):
         fb.derive_params(L=1.0, tol_ewald=1e-9, n_box=4, grid_M=63)
     with pytest.raises(fb.FbimError):

@@ -123,3 +123,24 @@ def test_non_finite_inputs():
     with pytest.raises(fb.FbimError):
         ctx.set_bodies(np.zeros(wl.n_bodies, dtype=np.int32), np.full((wl.n_bodies, 2), np.nan), wl.theta)
     ctx.mobility(dev(wl.F), U)  # the context is unchanged
+
+
+def test_crowded_cutoff_cell_rejected():
+    # the neighbour lists address a source by its place in its cutoff cell (at most
+    # 4096 nodes per cell): 72 bodies x 64 nodes inside one of 3 x 3 cells is refused,
+    # 60 (3840 nodes) are accepted
+    import paper_1709_01480_amd as fb
+    ctx = fb.Context(L=1.0, tol_ewald=1e-6, n_box=3)
+    sid = ctx.add_shape(fb.starfish(0.012, 0.3, 5, 64))
+    g = np.linspace(0.03, 0.30, 9)
+    q = np.array([(x, y) for y in g[:8] for x in g])
+    log("crowded cell: %d bodies" % len(q))
+    with pytest.raises(fb.FbimError) as e:
+        ctx.set_bodies(np.full(len(q), sid), q, np.zeros(len(q)))
+    assert e.value.status == 1
+    q = q[:60]
+    ctx.set_bodies(np.full(len(q), sid), q, np.zeros(len(q)))
+    out = zeros(2 * 64 * len(q))
+    ctx.apply_M(dev(np.ones(2 * 64 * len(q))), out, fb.PART_ALL)
+    assert np.all(np.isfinite(host(out)))
+    ctx.close()
