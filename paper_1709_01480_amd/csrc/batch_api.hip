@@ -532,7 +532,7 @@ fbim_status run_operator(BatchEngine *E, Tables &T, bool f32, bool saddle) {
   }
   {
     Timer t(tc, f32 ? "interp32" : "interp");
-    EHIP(E, launch_interp_batch(T.itp[p], T.bg_tiles, p, s));
+    EHIP(E, launch_interp_batch(T.itp[p], T.bg_tiles, p, T.spread_pmax, s));
   }
   if (saddle) EHIP(E, launch_rigid_batch(T.rig, T.bg_nodes, T.bg_bodies4, s));
   return FBIM_OK;

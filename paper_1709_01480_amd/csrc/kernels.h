@@ -448,7 +448,7 @@ hipError_t launch_pair_batch(const PairJob *jobs, BatchGrid bg, int f32, const d
 hipError_t launch_alpert_batch(const AlpertJob *jobs, BatchGrid bg, hipStream_t s);              // ceil(N/256)
 // pmax: the largest stencil width P of the batch (sizes the dynamic LDS)
 hipError_t launch_spread_batch(const SpreadJob *jobs, BatchGrid bg, int f32, int pmax, hipStream_t s);  // nts^2
-hipError_t launch_interp_batch(const InterpJob *jobs, BatchGrid bg, int f32, hipStream_t s);     // nts^2
+hipError_t launch_interp_batch(const InterpJob *jobs, BatchGrid bg, int f32, int pmax, hipStream_t s);  // nts^2
 hipError_t launch_multiplier_batch(const MultJob *jobs, BatchGrid bg, int f32, int mode,
                                    hipStream_t s);                                                // ceil(M(M/2+1)/256)
 hipError_t launch_rigid_batch(const RigidJob *jobs, BatchGrid bg_nodes, BatchGrid bg_bodies, hipStream_t s);

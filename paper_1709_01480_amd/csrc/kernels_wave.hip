@@ -105,6 +105,27 @@ template <typename T>
 __device__ inline T gauss_step(T ag, T h, int k) {
   return dev_exp(-ag * h * h * T(2 * k + 1));
 }
+// the same over a compile-time bound PP >= P (registers, unrolled; entries past P
+// are computed and must be discarded by the caller)
+template <typename T, int PP>
+__device__ __forceinline__ void gauss_row_pp(T x, T ag, T h, int half, const T *ck, T (&w)[PP]) {
+  if constexpr (sizeof(T) == 8) {
+    const T d0 = x + T(half) * h;
+    const T e1 = dev_exp(T(2) * ag * d0 * h);
+    T v = dev_exp(-ag * d0 * d0);
+#pragma unroll
+    for (int k = 0; k < PP; ++k) {
+      w[k] = v;
+      v = v * e1 * ck[k];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < PP; ++k) {
+      const T d = x + T(half - k) * h;
+      w[k] = dev_exp(-ag * d * d);
+    }
+  }
+}
 template <typename T>
 __device__ inline void gauss_row(T x, T scale, T ag, T h, int half, int P, const T *ck, T *w) {
   if constexpr (sizeof(T) == 8) {
@@ -324,51 +345,66 @@ __device__ __forceinline__ void spread_body(int M, int TT, int P, int nts, T h, 
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void interp_body(int M, int TT, int P, int nts, T h, T ag, T scale, const int *__restrict__ tile_start,
-                            const typename Vec2<T>::type *__restrict__ xt, const int2 *__restrict__ anchor,
-                            const int *__restrict__ tperm, const T *__restrict__ grid, double *__restrict__ out,
-                            int tile) {
-  constexpr int W = kTmax + kPmax - 1;
-  __shared__ T win[2][W * W];
-  __shared__ T ck[kPmax];
+// Interpolation: one work group per grid tile, the tile's window of grid points
+// (both components interleaved) in LDS, one thread per node of the tile.  The
+// stencil bound PP (odd, >= P) is a template parameter, so the P x P loop is
+// unrolled with one 64-bit (FP32) or 128-bit (FP64) LDS read per point; for P < PP
+// the extra weights are zero and the window's extra columns and rows hold zeros.
+template <typename T, int PP>
+__device__ __forceinline__ void interp_body(int M, int TT, int P, int nts, T h, T ag, T scale,
+                                            const int *__restrict__ tile_start,
+                                            const typename Vec2<T>::type *__restrict__ xt,
+                                            const int2 *__restrict__ anchor, const int *__restrict__ tperm,
+                                            const T *__restrict__ grid, double *__restrict__ out, int tile) {
+  using V2 = typename Vec2<T>::type;
+  constexpr int W = kTmax + PP - 1;
+  __shared__ V2 win[W * W];
+  __shared__ T ck[PP];
   const int tid = threadIdx.x;
   const int tyi = tile / nts, txi = tile % nts;
   const int gx0 = txi * TT, gy0 = tyi * TT;
   const int half = (P - 1) / 2;
-  const int w = TT + P - 1;
-  for (int i = tid; i < w * w; i += 256) {
-    const int ry = i / w, rx = i - ry * w;
-    const size_t gidx = (size_t)wrapi(gy0 - half + ry, M) * M + wrapi(gx0 - half + rx, M);
-    win[0][i] = grid[gidx];
-    win[1][i] = grid[(size_t)M * M + gidx];
+  const int w = TT + P - 1, wa = TT + PP - 1;  // window edge, and as allocated for PP
+  for (int i = tid; i < wa * wa; i += 256) {
+    const int ry = i / wa, rx = i - ry * wa;
+    V2 g;
+    g.x = g.y = T(0);
+    if (ry < w && rx < w) {
+      const size_t gidx = (size_t)wrapi(gy0 - half + ry, M) * M + wrapi(gx0 - half + rx, M);
+      g.x = grid[gidx];
+      g.y = grid[(size_t)M * M + gidx];
+    }
+    win[i] = g;
   }
-  if (tid < P) ck[tid] = gauss_step<T>(ag, h, tid);
+  if (tid < PP) ck[tid] = tid < P ? gauss_step<T>(ag, h, tid) : T(0);
   __syncthreads();
   const int a = tile_start[tile], b = tile_start[tile + 1];
   for (int k = a + tid; k < b; k += 256) {
     const auto p = xt[k];
     const int2 an = anchor[k];
-    const int ixn = an.x, iyn = an.y;
-    const int bx = wrapi(ixn - half - (gx0 - half), M);  // window column of the first stencil point
-    const int by = wrapi(iyn - half - (gy0 - half), M);
+    const int bx = wrapi(an.x - half - (gx0 - half), M);  // window column of the first stencil point
+    const int by = wrapi(an.y - half - (gy0 - half), M);
     // weights of the stencil's columns and rows (offsets p + (half - k) h from the
-    // nearest grid point) by the product recurrence
-    T wx[kPmax], wyr[kPmax];
-    gauss_row<T>(p.x, T(1), ag, h, half, P, ck, wx);
-    gauss_row<T>(p.y, T(1), ag, h, half, P, ck, wyr);
+    // nearest grid point) by the product recurrence; zero past P
+    T wx[PP], wyr[PP];
+    gauss_row_pp<T, PP>(p.x, ag, h, half, ck, wx);
+    gauss_row_pp<T, PP>(p.y, ag, h, half, ck, wyr);
+#pragma unroll
+    for (int q = 0; q < PP; ++q)
+      if (q >= P) wx[q] = wyr[q] = T(0);
     T sx = 0, sy = 0;
-    for (int qr = 0; qr < P; ++qr) {
-      const T wy = wyr[qr];
-      const T *r0 = &win[0][(by + qr) * w + bx];
-      const T *r1 = &win[1][(by + qr) * w + bx];
+    const V2 *r = win + by * wa + bx;
+#pragma unroll
+    for (int qr = 0; qr < PP; ++qr) {
       T rx0 = 0, rx1 = 0;
-      for (int pc = 0; pc < P; ++pc) {
-        rx0 += wx[pc] * r0[pc];
-        rx1 += wx[pc] * r1[pc];
+#pragma unroll
+      for (int pc = 0; pc < PP; ++pc) {
+        const V2 g = r[qr * wa + pc];
+        rx0 += wx[pc] * g.x;
+        rx1 += wx[pc] * g.y;
       }
-      sx += wy * rx0;
-      sy += wy * rx1;
+      sx += wyr[qr] * rx0;
+      sy += wyr[qr] * rx1;
     }
     const int node = tperm[k];
     out[2 * node] += (double)(scale * sx);
@@ -409,14 +445,14 @@ __global__ __launch_bounds__(256) void k_spread(int M, int TT, int P, int nts, T
                      xcd_remap(blockIdx.x, gridDim.x));
 }
 
-template <typename T>
+template <typename T, int PP>
 __global__ __launch_bounds__(256) void k_interp(int M, int TT, int P, int nts, T h, T ag, T scale,
                                                 const int *__restrict__ tile_start,
                                                 const typename Vec2<T>::type *__restrict__ xt,
                                                 const int2 *__restrict__ anchor,
                                                 const int *__restrict__ tperm, const T *__restrict__ grid,
                                                 double *__restrict__ out) {
-  interp_body<T>(M, TT, P, nts, h, ag, scale, tile_start, xt, anchor, tperm, grid, out,
+  interp_body<T, PP>(M, TT, P, nts, h, ag, scale, tile_start, xt, anchor, tperm, grid, out,
                  xcd_remap(blockIdx.x, gridDim.x));
 }
 
@@ -439,13 +475,13 @@ __global__ __launch_bounds__(256) void k_spread_batch(const SpreadJob *__restric
                      reinterpret_cast<const V2 *>(j.mut), reinterpret_cast<T *>(j.grid), gb - bg.begin[s]);
 }
 
-template <typename T>
+template <typename T, int PP>
 __global__ __launch_bounds__(256) void k_interp_batch(const InterpJob *__restrict__ jobs, BatchGrid bg) {
   using V2 = typename Vec2<T>::type;
   const int gb = xcd_remap(blockIdx.x, gridDim.x);
   const int s = batch_system(bg.begin, bg.S, gb);
   const InterpJob &j = jobs[s];
-  interp_body<T>(j.w.M, j.w.T, j.w.P, j.w.nts, (T)j.w.h, (T)j.w.ag, (T)(j.w.h * j.w.h * j.w.cg), j.w.tile_start,
+  interp_body<T, PP>(j.w.M, j.w.T, j.w.P, j.w.nts, (T)j.w.h, (T)j.w.ag, (T)(j.w.h * j.w.h * j.w.cg), j.w.tile_start,
                  reinterpret_cast<const V2 *>(j.xt), reinterpret_cast<const int2 *>(j.w.anchor), j.tperm,
                  reinterpret_cast<const T *>(j.grid), j.out, gb - bg.begin[s]);
 }
@@ -492,13 +528,17 @@ hipError_t launch_spread_batch(const SpreadJob *jobs, BatchGrid bg, int f32, int
   return f32 ? spread_batch_t<float>(jobs, bg, pmax, s) : spread_batch_t<double>(jobs, bg, pmax, s);
 }
 
-hipError_t launch_interp_batch(const InterpJob *jobs, BatchGrid bg, int f32, hipStream_t s) {
+hipError_t launch_interp_batch(const InterpJob *jobs, BatchGrid bg, int f32, int pmax, hipStream_t s) {
   if (bg.nblocks == 0) return hipSuccess;
-  if (f32)
-    hipLaunchKernelGGL((k_interp_batch<float>), dim3(bg.nblocks), dim3(256), 0, s, jobs, bg);
-  else
-    hipLaunchKernelGGL((k_interp_batch<double>), dim3(bg.nblocks), dim3(256), 0, s, jobs, bg);
-  return hipGetLastError();
+  if (pmax < 1 || pmax > kPmax) return hipErrorInvalidValue;
+  return spread_dispatch<float>(pmax, [&](auto pp) {
+    constexpr int PP = decltype(pp)::value;
+    if (f32)
+      hipLaunchKernelGGL((k_interp_batch<float, PP>), dim3(bg.nblocks), dim3(256), 0, s, jobs, bg);
+    else
+      hipLaunchKernelGGL((k_interp_batch<double, PP>), dim3(bg.nblocks), dim3(256), 0, s, jobs, bg);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_multiplier_batch(const MultJob *jobs, BatchGrid bg, int f32, int mode, hipStream_t s) {
@@ -544,18 +584,27 @@ hipError_t launch_spread_f32(const WaveArgs &w, const float *xt, const float *mu
 hipError_t launch_interp_f64(const WaveArgs &w, const double *xt, const int *tperm, const double *grid,
                              double *out, hipStream_t s) {
   const int nt = w.nts * w.nts;
-  hipLaunchKernelGGL(k_interp<double>, dim3(nt), dim3(256), 0, s, w.M, w.T, w.P, w.nts, w.h, w.ag,
-                     w.h * w.h * w.cg, w.tile_start, (const double2 *)xt, (const int2 *)w.anchor, tperm, grid, out);
-  return hipGetLastError();
+  if (w.P < 1 || w.P > kPmax || w.T > kTmax) return hipErrorInvalidValue;
+  return spread_dispatch<double>(w.P, [&](auto pp) {
+    constexpr int PP = decltype(pp)::value;
+    hipLaunchKernelGGL((k_interp<double, PP>), dim3(nt), dim3(256), 0, s, w.M, w.T, w.P, w.nts, w.h, w.ag,
+                       w.h * w.h * w.cg, w.tile_start, (const double2 *)xt, (const int2 *)w.anchor, tperm, grid,
+                       out);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_interp_f32(const WaveArgs &w, const float *xt, const int *tperm, const float *grid, double *out,
                              hipStream_t s) {
   const int nt = w.nts * w.nts;
-  hipLaunchKernelGGL(k_interp<float>, dim3(nt), dim3(256), 0, s, w.M, w.T, w.P, w.nts, (float)w.h, (float)w.ag,
-                     (float)(w.h * w.h * w.cg), w.tile_start, (const float2 *)xt, (const int2 *)w.anchor, tperm,
-                     grid, out);
-  return hipGetLastError();
+  if (w.P < 1 || w.P > kPmax || w.T > kTmax) return hipErrorInvalidValue;
+  return spread_dispatch<float>(w.P, [&](auto pp) {
+    constexpr int PP = decltype(pp)::value;
+    hipLaunchKernelGGL((k_interp<float, PP>), dim3(nt), dim3(256), 0, s, w.M, w.T, w.P, w.nts, (float)w.h,
+                       (float)w.ag, (float)(w.h * w.h * w.cg), w.tile_start, (const float2 *)xt,
+                       (const int2 *)w.anchor, tperm, grid, out);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_multiplier_f64(int M, double L, double xi, double eta_s, double scale, int mode, double *spec,
