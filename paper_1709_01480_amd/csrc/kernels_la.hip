@@ -746,8 +746,12 @@ __device__ inline void block_sum_store(const double (&acc)[NV], int nv, double *
 //   MODE 1: w -= V h; out[j] = V_j . w (j < K), out[K] = w . w
 //   MODE 2: w -= V h; out[0] = w . w
 // E elements per thread and iteration keep E (K + 1) loads in flight.
+// At most two waves per SIMD: the passes launch one work group per chunk (~2.5 per
+// CU at 640k nodes), so occupancy buys nothing, and the register room lets every
+// thread keep all of its column loads in flight (at the default target the dot
+// pass issued them one after another, waiting on each).
 template <int MODE, int K, typename VT>
-__global__ __launch_bounds__(256) void k_orth(OrthArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_orth(OrthArgs a) {
   constexpr int E = K <= 4 ? 4 : (K <= 12 ? 2 : 1);
   constexpr int NV = MODE == 2 ? 1 : K + 1;
   const int cidx = blockIdx.x;
@@ -806,7 +810,7 @@ __global__ __launch_bounds__(256) void k_orth(OrthArgs a) {
 // Runtime column count k (any k < kOrthMaxCols): MODE 0 in passes of 32 columns,
 // MODE 2 with a runtime loop.  Used beyond the unrolled range.
 template <int MODE, typename VT>
-__global__ __launch_bounds__(256) void k_orth_any(OrthArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_orth_any(OrthArgs a) {
   constexpr int KR = 32;
   const int cidx = blockIdx.x;
   const int sys = a.seg.chunk_sys[cidx];
