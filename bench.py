@@ -97,8 +97,10 @@ FORMS = {
     "fp64": dict(precision="fp64", batch_rfd=False, learned=False),
     # mixed precision only (FP32 matvecs in FP64 Krylov), solves one after another
     "mixed": dict(precision="mixed", batch_rfd=False, learned=False),
-    # relaxed-matvec GMRES (FP32 operator once the residual is small) with an FP32 Krylov basis, the
-    # EM-RFD solves in batched launch sets, learned preconditioner correction trained beforehand on solves
+    # relaxed-matvec GMRES (FP32 operator once the residual is small) with an FP32 Krylov basis and
+    # the EM-RFD solves in batched launch sets
+    "mixed+batched": dict(precision="mixed", batch_rfd=True, graph=True, learned=False, basis32=True),
+    # the same with the learned preconditioner correction, trained beforehand on solves
     "mixed+batched+learned": dict(precision="mixed", batch_rfd=True, graph=True, learned=True, basis32=True),
 }
 

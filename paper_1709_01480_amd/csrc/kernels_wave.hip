@@ -174,10 +174,13 @@ constexpr int kSpreadBlock = 8;  // side of the bound blocks
 constexpr int kSpreadMaxBlocks = (kTmax + kSpreadBlock - 1) / kSpreadBlock;
 
 // list entries per chunk (weights in LDS) and accumulator words per grid point;
-// FP64 with the widest stencils takes smaller chunks to stay within 64 KB of LDS
+// FP64 with the widest stencils takes smaller chunks to stay within 64 KB of LDS.
+// FP32 takes 128: ~26 instead of ~35 KB per work group, six groups per CU instead
+// of four, which hides more of each group's serial list gathers and barriers
+// (58 vs 60 us at 640k nodes) at the cost of a second chunk in most 32 x 32 tiles.
 template <typename T, int PP>
 __host__ __device__ constexpr int spread_chunk() {
-  return sizeof(T) == 4 ? 256 : (PP >= 15 ? 64 : 128);
+  return sizeof(T) == 4 ? 128 : (PP >= 15 ? 64 : 128);
 }
 template <typename T>
 __host__ __device__ constexpr int spread_nacc() {
@@ -225,6 +228,17 @@ __device__ __forceinline__ void spread_body(int M, int TT, int P, int nts, T h, 
   const int half = (P - 1) / 2;
   const int ls = slist_start[tile], n = slist_start[tile + 1] - ls;
   const int nbk = (TT + kSpreadBlock - 1) / kSpreadBlock;
+  // list entry tid (most tiles have at most 256), gathered once before the LDS is
+  // cleared and kept in registers for the two bound passes and the first chunk
+  V2 fp, fmu;
+  fp.x = fp.y = fmu.x = fmu.y = T(0);
+  int2 fan = make_int2(0, 0);
+  if (tid < n) {
+    const int g = slist[ls + tid];
+    fp = xt[g];
+    fmu = mut[g];
+    fan = anchor[g];
+  }
   for (int i = tid; i < NACC * TT * ST; i += 256) spread_lds[i] = 0ull;
   if (tid < nbk * nbk) s_blk[tid] = 0u;
   if (tid == 0) s_max = s_bad = 0u;
@@ -240,7 +254,7 @@ __device__ __forceinline__ void spread_body(int M, int TT, int P, int nts, T h, 
     float mloc = 0.f;
     bool bad = false;
     for (int e = tid; e < n; e += 256) {
-      const V2 mu = mut[slist[ls + e]];
+      const V2 mu = e < 256 ? fmu : mut[slist[ls + e]];
       const T a = fmax(fabs(mu.x), fabs(mu.y));
       bad |= !isfinite(mu.x) || !isfinite(mu.y);
       mloc = fmaxf(mloc, (float)a);
@@ -263,9 +277,13 @@ __device__ __forceinline__ void spread_body(int M, int TT, int P, int nts, T h, 
     E = 31 - k;
   }
   for (int e = tid; e < n; e += 256) {
-    const int g = slist[ls + e];
-    const V2 mu = mut[g];
-    const int2 an = anchor[g];
+    V2 mu = fmu;
+    int2 an = fan;
+    if (e >= 256) {
+      const int g = slist[ls + e];
+      mu = mut[g];
+      an = anchor[g];
+    }
     const int ox = origin(an.x, gx0), oy = origin(an.y, gy0);
     const int bx0 = max(ox, 0) / kSpreadBlock, bx1 = min(ox + P - 1, TT - 1) / kSpreadBlock;
     const int by0 = max(oy, 0) / kSpreadBlock, by1 = min(oy + P - 1, TT - 1) / kSpreadBlock;
@@ -285,23 +303,33 @@ __device__ __forceinline__ void spread_body(int M, int TT, int P, int nts, T h, 
     constexpr int kTop = F32 ? 30 : 62, kMaxE = F32 ? 126 : 1000;
     S = ldexp(T(1), max(min(kTop - k, kMaxE), -kMaxE));
   }
+  static_assert(256 % CH == 0, "a chunk lies inside or past the first 256 entries");
   for (int c = 0; c < n; c += CH) {
     const int cnt = min(CH, n - c);
-    if (tid < cnt) {
-      const int g = slist[ls + c + tid];
-      const V2 p = xt[g], mu = mut[g];
-      const int2 an = anchor[g];
-      nbx[tid] = origin(an.x, gx0) + PADC;
-      nby[tid] = origin(an.y, gy0);
-      nmx[tid] = mu.x * S;  // exact: S is a power of two
-      nmy[tid] = mu.y * S;
+    // entry c + sl at slot sl: inside the first 256 entries the thread that holds it
+    // stages it, past them thread sl gathers it
+    const bool held = c < 256;
+    const int sl = held ? tid - c : tid;
+    if (sl >= 0 && sl < cnt) {
+      V2 p = fp, mu = fmu;
+      int2 an = fan;
+      if (!held) {
+        const int g = slist[ls + c + sl];
+        p = xt[g];
+        mu = mut[g];
+        an = anchor[g];
+      }
+      nbx[sl] = origin(an.x, gx0) + PADC;
+      nby[sl] = origin(an.y, gy0);
+      nmx[sl] = mu.x * S;  // exact: S is a power of two
+      nmy[sl] = mu.y * S;
       T wr[kPmax];
       gauss_row<T>(p.x, T(1), ag, h, half, P, ck, wr);
 #pragma unroll
-      for (int k = 0; k < PP; ++k) wgx[tid * PP + k] = k < P ? wr[k] : T(0);
+      for (int k = 0; k < PP; ++k) wgx[sl * PP + k] = k < P ? wr[k] : T(0);
       gauss_row<T>(p.y, cg, ag, h, half, P, ck, wr);
 #pragma unroll
-      for (int k = 0; k < PP; ++k) wgy[tid * PP + k] = k < P ? wr[k] : T(0);
+      for (int k = 0; k < PP; ++k) wgy[sl * PP + k] = k < P ? wr[k] : T(0);
     }
     __syncthreads();
     const float invP = 1.0f / (float)P;
