@@ -92,6 +92,8 @@ def cpu_baseline(wl, prm, gmres_mv, lanczos_mv, reps=3):
     }
 
 
+# every form runs GMRES with the second Gram-Schmidt pass of each Arnoldi step delayed
+# into the next step's read of the basis (FBIM_FLAG_LAGGED_REORTH)
 FORMS = {
     # plain method: FP64 everywhere, block-diagonal preconditioner, solves one after another
     "fp64": dict(precision="fp64", batch_rfd=False, learned=False),
@@ -108,7 +110,7 @@ FORMS = {
 def run_form(name, form, wl, args, fb, W, np, torch):
     prec = fb.PREC_FP64 if form["precision"] == "fp64" else fb.PREC_MIXED
     flags = ((fb.FLAG_BATCH_RFD if form["batch_rfd"] else 0) | (fb.FLAG_GRAPH if form.get("graph") else 0)
-             | (fb.FLAG_BASIS32 if form.get("basis32") else 0))
+             | (fb.FLAG_BASIS32 if form.get("basis32") else 0) | fb.FLAG_LAGGED_REORTH)
     prm = dict(wl.params(), precision=prec, flags=flags, seed=W.noise_key(wl))
     ctx = fb.Context(**prm)
     sid = ctx.add_shape(fb.starfish(wl.r_s, wl.b, wl.n_arm, wl.n_p))

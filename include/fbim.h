@@ -78,7 +78,15 @@ enum {
      entries, residuals and solution updates stay FP64, and every restart residual is
      the FP64 one, so the stopping test is unchanged.  Ignored by FP64 contexts and
      by single-context solves.  Applies to a batch when all of its members set it. */
-  FBIM_FLAG_BASIS32 = 32u
+  FBIM_FLAG_BASIS32 = 32u,
+  /* GMRES (single contexts; batches when all members set it): delayed
+     reorthogonalisation, DCGS2 (Swirydowicz et al. 2020, Bielich et al. 2022).  The
+     second Gram-Schmidt pass of each new basis vector is applied one Arnoldi step
+     later, in the same read of the basis that projects the next vector, so a step
+     reads the basis twice instead of three times; the Hessenberg entries are
+     corrected on the host.  The Krylov dimension is then at most 32 before a restart.
+     Takes precedence over FBIM_FLAG_SELECTIVE_REORTH in GMRES; Lanczos unchanged. */
+  FBIM_FLAG_LAGGED_REORTH = 64u
 };
 
 /* bits of `parts` in fbim_apply_M */

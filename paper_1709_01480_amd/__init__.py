@@ -17,7 +17,8 @@ __all__ = ["Params", "Derived", "Info", "Context", "lib", "derive_params", "alpe
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfbim.so")
 
 PART_REAL, PART_ALPERT, PART_WAVE, PART_ALL = 1, 2, 4, 7
-FLAG_SELECTIVE_REORTH, FLAG_BATCH_RFD, FLAG_GRAPH, FLAG_REFINEMENT, FLAG_LIBRARY_FFT, FLAG_BASIS32 = 1, 2, 4, 8, 16, 32
+(FLAG_SELECTIVE_REORTH, FLAG_BATCH_RFD, FLAG_GRAPH, FLAG_REFINEMENT, FLAG_LIBRARY_FFT, FLAG_BASIS32,
+ FLAG_LAGGED_REORTH) = 1, 2, 4, 8, 16, 32, 64
 BATCH_GRAPH = 1
 PREC_FP64, PREC_MIXED = 0, 1
 NOISE_W_R, NOISE_W_GRID, NOISE_W_TILDE = 0, 1, 2

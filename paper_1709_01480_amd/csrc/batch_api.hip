@@ -71,6 +71,10 @@ struct BatchEngine {
   int hs = 0;
   double *d_partial = nullptr;
   size_t partial_cap = 0;
+  // lagged reorthogonalisation: the previous lagged-pass outputs of the systems of
+  // the next pass, uploaded in table order (pinned staging, kLagSlot per system)
+  double *d_lagin = nullptr, *h_lagin = nullptr;
+  size_t lag_cap = 0;
   HostPub pub;  // per-system orthogonalisation results and norms read by the host
   // graphs of the precond + operator launch set per table slot (full, then
   // sub[]) and precision, with the launch arguments they were captured with
@@ -449,7 +453,15 @@ fbim_status engine_prepare(BatchEngine *E) {
     EHIP(E, dalloc(E->d_sc, need));
     E->sc_cap = need;
   }
-  EHIP(E, pub_alloc(E->pub, E->sys.size() * ((size_t)E->hs + 1)));
+  EHIP(E, pub_alloc(E->pub, E->sys.size() * std::max((size_t)E->hs + 1, (size_t)2 * kLagSlot)));
+  if (E->sys.size() * (size_t)kLagSlot > E->lag_cap) {
+    if (E->h_lagin) hipHostFree(E->h_lagin);
+    E->h_lagin = nullptr;
+    E->lag_cap = 0;
+    EHIP(E, dalloc(E->d_lagin, E->sys.size() * (size_t)kLagSlot));
+    EHIP(E, hipHostMalloc((void **)&E->h_lagin, E->sys.size() * kLagSlot * sizeof(double), hipHostMallocDefault));
+    E->lag_cap = E->sys.size() * (size_t)kLagSlot;
+  }
   const size_t pneed = (size_t)std::max(E->full.seg.nchunk, 1) * (E->hs + 1);
   if (pneed > E->partial_cap) {
     EHIP(E, dalloc(E->d_partial, pneed));
@@ -796,6 +808,57 @@ fbim_status orthogonalise_b(BatchEngine *E, Tables &T, int k, std::vector<std::v
   return FBIM_OK;
 }
 
+// One lockstep Arnoldi step with delayed reorthogonalisation (FBIM_FLAG_LAGGED_REORTH)
+// for the systems of T: each system's previous lagged-pass output (lagprev, table
+// order; j + 1 values) is uploaded, the dot-product pass and the lagged pass run over
+// basis slots 0..j and w = by, and u_{j+1} = w' / ||w'|| is written to `next` and its
+// FP64 copy to bx.  dots[q] and outs[q] point to system q's published dot products
+// and lagged-pass output (j + 2 values each) until the next publication.
+fbim_status orthogonalise_lag_b(BatchEngine *E, Tables &T, int j, const std::vector<const double *> &lagprev,
+                                const VecRef &next, std::vector<const double *> &dots,
+                                std::vector<const double *> &outs) {
+  const int S = T.S, hs = E->hs;
+  Scal q = scalars(E, S);
+  if (j > 0) {
+    // the staging buffer's previous copy ran before the last publication the host waited for
+    for (int p = 0; p < S; ++p) std::memcpy(E->h_lagin + (size_t)p * kLagSlot, lagprev[p], (j + 1) * sizeof(double));
+    EHIP(E, hipMemcpyAsync(E->d_lagin, E->h_lagin, (size_t)S * kLagSlot * sizeof(double), hipMemcpyHostToDevice,
+                           E->stream));
+  }
+  EST(orth_pass_b(E, T, 0, j + 1, T.by, nullptr, nullptr, q.h, hs));
+  {
+    Timer t(E->sys[0], "blas");
+    OrthArgs a{};
+    a.seg = T.seg;
+    a.k = j;
+    a.Vs = T.V;
+    a.v32 = E->basis32 ? 1 : 0;
+    a.ws = const_cast<double *const *>(T.by);
+    a.lds = T.ld;
+    a.h = q.h;
+    a.hstride = hs;
+    a.cond = nullptr;
+    a.partial = E->d_partial;
+    a.out = q.h2;
+    a.ostride = hs;
+    a.lag = j > 0 ? E->d_lagin : nullptr;
+    a.lagstride = kLagSlot;
+    EHIP(E, launch_orth_lag(a, E->stream));
+    EHIP(E, launch_rsqrt_strided(S, q.h2 + j + 1, hs, q.a, E->stream));
+    EHIP(E, launch_seg_scale2(T.seg, vref(T.by), next, vref(T.bx), q.a, E->stream));
+  }
+  const unsigned long long tag = ++E->pub.seq;
+  EHIP(E, launch_publish2(S, j + 2, q.h, hs, j + 2, q.h2, hs, E->pub, tag, E->stream));
+  EHIP(E, pub_wait(E->pub, tag, E->stream));
+  dots.resize(S);
+  outs.resize(S);
+  for (int p = 0; p < S; ++p) {
+    dots[p] = E->pub.v + (size_t)p * 2 * (j + 2);
+    outs[p] = dots[p] + j + 2;
+  }
+  return FBIM_OK;
+}
+
 std::vector<int> pick(const std::vector<int> &v, const std::vector<int> &pos) {
   std::vector<int> out;
   for (int p : pos) out.push_back(v[p]);
@@ -819,7 +882,12 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
   relres.assign(S0, 0.0);
   status.assign(S0, FBIM_OK);
   int m = 1 << 30;
-  for (int i : sysl) m = std::min(m, E->sys[i]->restart);
+  bool lagged = true;  // delayed reorthogonalisation when every system asks for it
+  for (int i : sysl) {
+    m = std::min(m, E->sys[i]->restart);
+    lagged = lagged && (E->sys[i]->p.flags & FBIM_FLAG_LAGGED_REORTH);
+  }
+  if (lagged) m = std::min(m, kOrthFused);
   fbim_status st;
   auto rhs = [&](Tables &T) { return ir ? T.irr : T.b; };
   auto sol = [&](Tables &T) { return ir ? T.ird : T.x2; };
@@ -838,6 +906,8 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
     if (nb[i] > 0.0) running.push_back(i);
   // per-system Arnoldi state
   std::vector<std::vector<double>> H(S0), g(S0), cs(S0), sn(S0);
+  // lagged: unrotated columns, lag of the newest vector, last lagged-pass output
+  std::vector<std::vector<double>> Hu(S0), slag(S0), lagraw(S0);
   bool first = !warm;
   while (!running.empty()) {
     T = &tables_for(E, pick(sysl, running), st);
@@ -867,6 +937,11 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
       cyc.push_back(i);
       inv.push_back(1.0 / beta);
       H[i].assign((size_t)(m + 1) * m, 0.0);
+      if (lagged) {
+        Hu[i].assign((size_t)(m + 1) * m, 0.0);
+        slag[i].clear();
+        lagraw[i].clear();
+      }
       g[i].assign(m + 1, 0.0);
       cs[i].assign(m, 0.0);
       sn[i].assign(m, 0.0);
@@ -909,7 +984,25 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
       std::vector<std::vector<double>> hc;
       std::vector<double> hn;
       const VecRef vnext = vbasis(E, *T, j + 1);
-      EST(orthogonalise_b(E, *T, j + 1, hc, hn, &vnext));  // V_{j+1} = w / ||w||
+      if (lagged) {
+        std::vector<const double *> lp(act.size()), dts, outs;
+        for (size_t q = 0; q < act.size(); ++q) lp[q] = lagraw[act[q]].data();
+        EST(orthogonalise_lag_b(E, *T, j, lp, vnext, dts, outs));  // u_{j+1}, V_j final
+        hc.assign(act.size(), std::vector<double>());
+        hn.assign(act.size(), 0.0);
+        std::vector<double> col(j + 2);
+        for (size_t q = 0; q < act.size(); ++q) {
+          const int i = act[q];
+          if (!lagged_column(j, dts[q], outs[q], Hu[i], m, slag[i], col.data()))
+            return efail(E, FBIM_EDEVICE, "non-finite Krylov vector in a batch system");
+          for (int r = 0; r <= j + 1; ++r) Hu[i][(size_t)r * m + j] = col[r];
+          lagraw[i].assign(outs[q], outs[q] + j + 2);
+          hc[q].assign(col.begin(), col.begin() + j + 1);
+          hn[q] = col[j + 1];
+        }
+      } else {
+        EST(orthogonalise_b(E, *T, j + 1, hc, hn, &vnext));  // V_{j+1} = w / ||w||
+      }
       std::vector<int> next;
       for (size_t q = 0; q < act.size(); ++q) {
         const int i = act[q];
@@ -1069,6 +1162,8 @@ void engine_destroy(BatchEngine *E) {
     if (t.dev) hipFree(t.dev);
   dfree(E->d_sc);
   dfree(E->d_partial);
+  dfree(E->d_lagin);
+  if (E->h_lagin) hipHostFree(E->h_lagin);
   pub_free(E->pub);
   delete E;
 }

@@ -153,6 +153,7 @@ struct fbim_ctx {
   double *d_V = nullptr;      // (restart+1) * ntot  (also Lanczos basis)
   double *d_w = nullptr, *d_t1 = nullptr, *d_t2 = nullptr, *d_b = nullptr, *d_x2 = nullptr, *d_r = nullptr;
   double *d_partial = nullptr, *d_h = nullptr, *d_h2 = nullptr, *d_nrm = nullptr, *d_c = nullptr;
+  double *d_lag = nullptr;  // lagged reorthogonalisation: dot products, then two lagged-pass outputs
   HostPub pub;  // orthogonalisation coefficients and norms read by the host
   // chunk tables of the Krylov vectors: saddle vectors (2N + 3n) and node vectors (2N)
   Segs seg_sad{}, seg_nod{};
@@ -311,6 +312,9 @@ inline double now_ms() {
 fbim_status random_field(fbim_ctx *c, const double *W_grid, double *out);
 fbim_status lanczos_sqrt(fbim_ctx *c, const double *b, double *out, int &iters, double &change);
 fbim_status norm2(fbim_ctx *c, const double *x, size_t n, double &out);
+// host half of an Arnoldi step with delayed reorthogonalisation (fbim_api.hip)
+bool lagged_column(int j, const double *dots, const double *out, const std::vector<double> &Hu, int m,
+                   std::vector<double> &s, double *col);
 fbim_status brownian_slip(fbim_ctx *c, double dt, const double *W_r, const double *W_grid, double *slip_out,
                           fbim_info *info);
 fbim_status setup_fft(fbim_ctx *c);

@@ -145,7 +145,8 @@ fbim_status ensure_krylov(fbim_ctx *c) {
   HIPCHK(c, dalloc(c->d_h, cols));
   HIPCHK(c, dalloc(c->d_h2, cols));
   HIPCHK(c, dalloc(c->d_nrm, 4));
-  HIPCHK(c, pub_alloc(c->pub, cols + 1));
+  HIPCHK(c, dalloc(c->d_lag, 3 * (size_t)kLagSlot));
+  HIPCHK(c, pub_alloc(c->pub, std::max(cols + 1, (size_t)2 * kLagSlot)));
   HIPCHK(c, dalloc(c->d_c, cols));
   HIPCHK(c, dalloc(c->d_vec_a, 2 * (size_t)c->N));
   HIPCHK(c, dalloc(c->d_vec_b, 2 * (size_t)c->N));
@@ -676,6 +677,84 @@ fbim_status orthogonalise(fbim_ctx *c, const double *V, int k, double *w, size_t
   return FBIM_OK;
 }
 
+// Host half of a lagged Arnoldi step (the relations are given with arnoldi_lagged):
+// dots = (V_{<j}^T w, u_j . w, w . w) and out = (V_{<=j}^T w', w' . w') as published,
+// s the lag of u_j.  Writes the unrotated column j into col[0..j+1] and replaces s by
+// the lag of u_{j+1}; false if a value is not finite.  s, rho and e are computed as
+// the lagged pass computes them on the device.
+bool lagged_column(int j, const double *dots, const double *out, const std::vector<double> &Hu, int m,
+                   std::vector<double> &s, double *col) {
+  double ss = 0.0, stt = 0.0;
+  for (int i = 0; i < j; ++i) {
+    ss += s[i] * s[i];
+    stt += s[i] * dots[i];
+  }
+  const double rho = std::sqrt(std::max(1.0 - ss, 0.0)), irho = rho > 0.0 ? 1.0 / rho : 0.0;
+  const double e_j = (dots[j] - stt) * irho;
+  const double nw = std::sqrt(std::max(out[j + 1], 0.0)), inw = nw > 0.0 ? 1.0 / nw : 0.0;
+  std::vector<double> sn(j + 1);
+  double sn2 = 0.0;
+  for (int i = 0; i <= j; ++i) {
+    sn[i] = out[i] * inw;
+    sn2 += sn[i] * sn[i];
+  }
+  for (int i = 0; i <= j; ++i) {
+    double hs = 0.0;  // (H_{<j} s)_i
+    for (int l = 0; l < j; ++l) hs += Hu[(size_t)i * m + l] * s[l];
+    col[i] = ((i < j ? dots[i] : e_j) - hs) * irho + nw * sn[i];
+  }
+  col[j + 1] = nw * std::sqrt(std::max(1.0 - sn2, 0.0));
+  s = std::move(sn);
+  for (int i = 0; i <= j + 1; ++i)
+    if (!std::isfinite(col[i])) return false;
+  return std::isfinite(dots[j + 1]);
+}
+
+// One Arnoldi step with delayed reorthogonalisation (FBIM_FLAG_LAGGED_REORTH).
+// On entry slot j of V holds u_j: unit norm, orthogonal to V_0..V_{j-1} but for
+// s = V_{<j}^T u_j (host, from the previous step; empty for j = 0), and w = A u_j.
+// A dot-product pass gives t = V_{<j}^T w, u_j . w and ||w||^2; the lagged pass
+// turns u_j into the final V_j = (u_j - V_{<j} s) / rho (rho = sqrt(1 - s.s)),
+// projects w out of V_{<=j} and returns its dot products with V_{<=j}; w is then
+// normalised.  With e = (t, (u_j . w - s.t) / rho) = V_{<=j}^T w, the step's
+// Arnoldi column follows without touching the vectors again:
+//   A V_j = (w - A V_{<j} s) / rho,   A V_{<j} = V H_{<j}   (columns 0..j-1 final)
+//   h = (e - H s) / rho,  w' = (w - V_{<=j} e) / rho = |w'| u_{j+1}
+//   u_{j+1} = rho' V_{j+1} + V_{<=j} s'  =>  col[0..j] = h + |w'| s',  col[j+1] = |w'| rho'
+// Hu holds the unrotated Arnoldi columns (row i of column l at Hu[i * m + l]);
+// col[0..j+1] is column j on return and s is replaced by s'.
+fbim_status arnoldi_lagged(fbim_ctx *c, int j, double *w, size_t n, const std::vector<double> &Hu, int m,
+                           std::vector<double> &s, double *col) {
+  hipStream_t st = c->stream;
+  double *dots = c->d_lag, *cur = c->d_lag + kLagSlot * (1 + (j & 1)), *prev = c->d_lag + kLagSlot * (1 + (~j & 1));
+  STCHK(orth_pass(c, 0, n, c->d_V, j + 1, w, nullptr, nullptr, dots));  // t, u_j . w, ||w||^2
+  {
+    Timer t(c, "blas");
+    OrthArgs a{};
+    a.seg = segs_for(c, n);
+    a.cond = nullptr;
+    a.V = c->d_V;
+    a.ld = c->ntot;
+    a.k = j;
+    a.w = w;
+    a.h = dots;
+    a.hstride = 0;
+    a.partial = c->d_partial;
+    a.out = cur;
+    a.ostride = 0;
+    a.lag = j > 0 ? prev : nullptr;
+    a.lagstride = 0;
+    HIPCHK(c, launch_orth_lag(a, st));
+    HIPCHK(c, launch_scale_rsqrt_dev(n, cur + j + 1, w, st));
+  }
+  const unsigned long long tag = ++c->pub.seq;
+  HIPCHK(c, launch_publish2(1, j + 2, dots, 0, j + 2, cur, 0, c->pub, tag, st));
+  HIPCHK(c, pub_wait(c->pub, tag, st));
+  if (!lagged_column(j, c->pub.v, c->pub.v + j + 2, Hu, m, s, col))
+    return fail(c, FBIM_EDEVICE, "non-finite Krylov vector");
+  return FBIM_OK;
+}
+
 fbim_status norm2(fbim_ctx *c, const double *x, size_t n, double &out) {
   STCHK(orth_pass(c, 0, n, x, 0, const_cast<double *>(x), nullptr, nullptr, c->d_nrm));
   const unsigned long long tag = ++c->pub.seq;
@@ -698,7 +777,8 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
                   bool warm = false, double relax = 0.0) {
   const size_t nt = c->ntot;
   hipStream_t s = c->stream;
-  const int m = c->restart;
+  const bool lagged = (c->p.flags & FBIM_FLAG_LAGGED_REORTH) != 0;
+  const int m = lagged ? std::min(c->restart, kOrthFused) : c->restart;
   iters = 0;
   relres = 0;
   double nb;
@@ -707,6 +787,7 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
   if (!warm || nb == 0.0) HIPCHK(c, launch_fill(nt, 0.0, x, s));
   if (nb == 0.0) return FBIM_OK;
   std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), hcol(m + 3), y(m);
+  std::vector<double> Hu(lagged ? (size_t)(m + 1) * m : 0), slag;  // unrotated columns, lag of the newest vector
   bool first = !warm;
   const bool saved32 = c->cur32;
   struct Restore {
@@ -736,6 +817,7 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
     }
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
+    slag.clear();
     int jend = 0;
     for (int j = 0; j < m; ++j) {
       double *vj = c->d_V + (size_t)j * nt;
@@ -744,7 +826,13 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
       STCHK(apply_precond(c, vj, c->d_t1));
       STCHK(apply_saddle(c, c->d_t1, w));
       double hn = 0;
-      STCHK(orthogonalise(c, c->d_V, j + 1, w, nt, hcol.data(), hn, true));
+      if (lagged) {
+        STCHK(arnoldi_lagged(c, j, w, nt, Hu, m, slag, hcol.data()));
+        for (int i = 0; i <= j + 1; ++i) Hu[(size_t)i * m + j] = hcol[i];
+        hn = hcol[j + 1];
+      } else {
+        STCHK(orthogonalise(c, c->d_V, j + 1, w, nt, hcol.data(), hn, true));
+      }
       if (!std::isfinite(hn)) return fail(c, FBIM_EDEVICE, "non-finite Krylov vector");
       hcol[j + 1] = hn;
       for (int i = 0; i < j; ++i) {  // previous rotations
@@ -1149,7 +1237,7 @@ void fbim_destroy(fbim_ctx *c) {
                   c->d_tcount, c->d_tstart, c->d_tperm, c->d_tcursor, c->d_xt, c->d_anchor, c->d_scal_int, c->d_src64,
                   c->d_mut, c->d_src32, c->d_xt32, c->d_mut32, c->d_grid, c->d_spec, c->d_grid32,
                   c->d_spec32, c->d_e1tab, c->d_e1tab32, c->d_V, c->d_w, c->d_t1, c->d_t2, c->d_b, c->d_x2,
-                  c->d_r, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
+                  c->d_r, c->d_partial, c->d_h, c->d_h2, c->d_nrm, c->d_lag, c->d_c, c->d_vec_a, c->d_vec_b, c->d_U3,
                   c->d_U4, c->d_U5, c->d_U6, c->d_irx, c->d_irr, c->d_ird, c->d_cnt_near, c->d_cnt_far, c->d_tcell, c->d_gnn, c->d_gnf, c->d_goff, c->d_gsize, c->d_ell, c->d_chunks, c->d_chunk_sys, c->d_sys_chunk, c->d_btile, c->d_blist, c->d_dN, c->d_mw, c->d_am, c->d_av, c->d_g, c->d_X, c->d_H1, c->d_H2, c->d_Y, c->d_dY, c->d_Z2, c->d_Z1, c->d_ones, c->d_loss, c->d_trF, c->d_trU, c->d_bx, c->d_by, c->d_tw, c->d_tw32, c->d_ey, c->d_ey32, c->d_scount, c->d_sstart, c->d_slist, c->d_nz_r, c->d_nz_g, c->d_nz_t, c->d_bc_key, c->d_bc_perm, c->d_bc_count, c->d_bc_cursor, c->d_bc_start, c->d_qprev, c->d_thprev, c->d_qstep, c->d_thstep};
   pub_free(c->pub);
   if (c->h_pin) hipHostFree(c->h_pin);

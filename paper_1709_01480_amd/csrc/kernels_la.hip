@@ -916,6 +916,106 @@ hipError_t launch_orth(int mode, const OrthArgs &a, hipStream_t s) {
   return a.v32 ? launch_orth_t<float>(mode, a, s) : launch_orth_t<double>(mode, a, s);
 }
 
+// Lagged pass of delayed classical Gram-Schmidt with reorthogonalisation (DCGS2:
+// Swirydowicz, Langou, Ananthan, Yang and Thomas 2020; Bielich, Langou, Thomas et al.
+// 2022).  The reorthogonalisation of the newest basis vector u, due one Arnoldi step
+// earlier, is applied in the same read of the basis that projects w, so a step reads
+// the basis twice (this pass and the dot-product pass before it) instead of three
+// times.  The coefficients are computed from h and lag in every work group (K + 1
+// values).  E elements per thread as in k_orth.
+template <int K, typename VT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_orth_lag(OrthArgs a) {
+  constexpr int E = K <= 4 ? 4 : (K <= 12 ? 2 : 1);
+  constexpr int NV = K + 2;
+  const int cidx = blockIdx.x;
+  const int sys = a.seg.chunk_sys[cidx];
+  const int2 rg = a.seg.chunk[cidx];
+  const int tid = threadIdx.x;
+  const double *h = a.h + (size_t)sys * a.hstride;
+  double sc[K > 0 ? K : 1], tc[K > 0 ? K : 1];
+  double ss = 0.0, st = 0.0;
+  if constexpr (K > 0) {
+    const double *lag = a.lag + (size_t)sys * a.lagstride;
+    const double nu = sqrt(fmax(lag[K], 0.0));
+    const double inu = nu > 0.0 ? 1.0 / nu : 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      sc[j] = lag[j] * inu;
+      tc[j] = h[j];
+      ss += sc[j] * sc[j];
+      st += sc[j] * tc[j];
+    }
+  }
+  const double rho = sqrt(fmax(1.0 - ss, 0.0));
+  const double irho = rho > 0.0 ? 1.0 / rho : 0.0;
+  const double ecoef = (h[K] - st) * irho;
+  VT *__restrict__ V = reinterpret_cast<VT *>(const_cast<double *>(a.Vs ? a.Vs[sys] : a.V));
+  double *__restrict__ w = a.ws ? a.ws[sys] : a.w;
+  const size_t ld = a.lds ? a.lds[sys] : a.ld;
+  double acc[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) acc[c] = 0.0;
+  for (int i0 = rg.x + tid; i0 < rg.y; i0 += 256 * E) {
+    double vv[E][K > 0 ? K : 1], uv[E], wv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = min(i0 + 256 * e, rg.y - 1);  // clamped: out-of-chunk lanes reload a valid element
+      wv[e] = w[i];
+      uv[e] = (double)V[(size_t)K * ld + i];
+#pragma unroll
+      for (int j = 0; j < K; ++j) vv[e][j] = (double)V[(size_t)j * ld + i];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const bool ok = i0 + 256 * e < rg.y;
+      double v = uv[e];
+      double p0 = 0.0, p1 = 0.0;
+      if constexpr (K > 0) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          if (j & 1) {
+            s1 += vv[e][j] * sc[j];
+            p1 += vv[e][j] * tc[j];
+          } else {
+            s0 += vv[e][j] * sc[j];
+            p0 += vv[e][j] * tc[j];
+          }
+        }
+        v = (v - (s0 + s1)) * irho;
+        if (ok) V[(size_t)K * ld + i0 + 256 * e] = (VT)v;
+      }
+      double x = (wv[e] - (p0 + p1) - v * ecoef) * irho;
+      if (ok) w[i0 + 256 * e] = x;
+      if (!ok) x = 0.0;
+#pragma unroll
+      for (int j = 0; j < K; ++j) acc[j] += vv[e][j] * x;
+      acc[K] += v * x;
+      acc[K + 1] += x * x;
+    }
+  }
+  block_sum_store<NV>(acc, NV, a.partial + (size_t)cidx * NV);
+}
+
+template <int K, typename VT>
+hipError_t launch_orth_lag_k(const OrthArgs &a, hipStream_t s) {
+  if constexpr (K >= kOrthFused) {
+    return hipErrorInvalidValue;
+  } else {
+    if (a.k == K) {
+      hipLaunchKernelGGL((k_orth_lag<K, VT>), dim3(a.seg.nchunk), dim3(256), 0, s, a);
+      return finish(K + 2, a, s);
+    }
+    return launch_orth_lag_k<K + 1, VT>(a, s);
+  }
+}
+
+hipError_t launch_orth_lag(const OrthArgs &a, hipStream_t s) {
+  if (a.seg.nchunk == 0) return hipSuccess;
+  if (a.k < 0 || a.k >= kOrthFused || (a.k > 0 && !a.lag) || a.cond) return hipErrorInvalidValue;
+  return a.v32 ? launch_orth_lag_k<0, float>(a, s) : launch_orth_lag_k<0, double>(a, s);
+}
+
 // ------------------------------------------------------------------ segmented vector kernels (batches)
 template <typename T>
 __device__ inline T *vec_ptr(const VecRef &v, int s) {
@@ -1145,6 +1245,42 @@ __global__ __launch_bounds__(256) void k_publish(int n, const double *__restrict
   if (threadIdx.x == 0) *reinterpret_cast<volatile unsigned long long *>(tag_out) = tag;
 }
 
+__global__ __launch_bounds__(256) void k_publish2(int S, int n0, const double *__restrict__ src0, int stride0, int n1,
+                                                  const double *__restrict__ src1, int stride1,
+                                                  double *__restrict__ v, unsigned long long *tag_out,
+                                                  unsigned long long tag) {
+  const int n = n0 + n1;
+  for (int i = threadIdx.x; i < S * n; i += blockDim.x) {
+    const int sys = i / n, j = i - sys * n;
+    v[i] = j < n0 ? src0[(size_t)sys * stride0 + j] : src1[(size_t)sys * stride1 + j - n0];
+  }
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) *reinterpret_cast<volatile unsigned long long *>(tag_out) = tag;
+}
+
+hipError_t launch_publish2(int S, int n0, const double *src0, int stride0, int n1, const double *src1, int stride1,
+                           HostPub &p, unsigned long long tag, hipStream_t s) {
+  if (S < 0 || n0 < 0 || n1 < 0 || (size_t)S * (n0 + n1) > p.cap || !p.tag) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_publish2, dim3(1), dim3(256), 0, s, S, n0, src0, stride0, n1, src1, stride1, p.v_dev,
+                     p.tag_dev, tag);
+  return hipGetLastError();
+}
+
+__global__ void k_rsqrt_strided(int S, const double *__restrict__ src, int stride, double *__restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < S) {
+    const double v = src[(size_t)i * stride];
+    dst[i] = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
+  }
+}
+
+hipError_t launch_rsqrt_strided(int S, const double *src, int stride, double *dst, hipStream_t s) {
+  if (S <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rsqrt_strided, dim3((S + 255) / 256), dim3(256), 0, s, S, src, stride, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_publish(int n, const double *src, int stride, HostPub &p, unsigned long long tag, hipStream_t s) {
   if (n < 0 || (size_t)n > p.cap || !p.tag) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_publish, dim3(1), dim3(256), 0, s, n, src, stride, p.v_dev, p.tag_dev, tag);
@@ -1155,6 +1291,19 @@ __global__ void k_scale_dev(size_t n, const double *__restrict__ a, double *__re
   const double f = a[0];
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     y[i] *= f;
+}
+
+__global__ void k_scale_rsqrt_dev(size_t n, const double *__restrict__ a, double *__restrict__ y) {
+  const double f = a[0] > 0.0 ? 1.0 / sqrt(a[0]) : 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] *= f;
+}
+
+hipError_t launch_scale_rsqrt_dev(size_t n, const double *a, double *y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int nb = (int)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_scale_rsqrt_dev, dim3(nb), dim3(256), 0, s, n, a, y);
+  return hipGetLastError();
 }
 
 hipError_t launch_scale_dev(size_t n, const double *a, double *y, hipStream_t s) {

@@ -96,21 +96,25 @@ def test_uneven_suspensions_batched_mobility():
         assert relerr(host(U), host(ref)) < 1e-8
 
 
-@pytest.mark.parametrize("basis32,graph", [(False, False), (True, False), (True, True)])
-def test_batched_mixed_mobility_reaches_fp64_tolerance(basis32, graph):
-    """Relaxed-matvec GMRES, with the Krylov basis in FP64 or FP32: the FP64
-    restart residual meets the tolerance, and the solution matches the FP64
+@pytest.mark.parametrize("basis32,graph,lagged", [(False, False, False), (True, False, False), (True, True, False),
+                                                  (False, False, True), (True, True, True)])
+def test_batched_mixed_mobility_reaches_fp64_tolerance(basis32, graph, lagged):
+    """Relaxed-matvec GMRES, with the Krylov basis in FP64 or FP32, with two
+    Gram-Schmidt passes per step or the second one delayed (FBIM_FLAG_LAGGED_REORTH):
+    the FP64 restart residual meets the tolerance, and the solution matches the FP64
     context's to the accuracy that tolerance allows.  Each system switches to the
-    FP32 operator on its own; with graphs on (three systems) the launch sets of
-    mixed groupings run eagerly, the others from graphs."""
+    FP32 operator on its own and leaves the lockstep launches when it converges (the
+    delayed passes then take the remaining systems' lags in the new order); with
+    graphs on (three systems) the launch sets of mixed groupings run eagerly, the
+    others from graphs."""
     import paper_1709_01480_amd as fb
     wls = [W.make(n) for n in NAMES]
-    b = _batch(wls, graph=graph, precision=fb.PREC_MIXED, tol_gmres=1e-8,
-               flags=fb.FLAG_BASIS32 if basis32 else 0)
+    flags = (fb.FLAG_BASIS32 if basis32 else 0) | (fb.FLAG_LAGGED_REORTH if lagged else 0)
+    b = _batch(wls, graph=graph, precision=fb.PREC_MIXED, tol_gmres=1e-8, flags=flags)
     Fs = [dev(wl.F) for wl in wls]
     Us = [zeros(3 * wl.n_bodies) for wl in wls]
     infos = b.mobility(Fs, Us)
-    log("basis32 %s iterations %s" % (basis32, [i["gmres_iters"] for i in infos]))
+    log("basis32 %s lagged %s iterations %s" % (basis32, lagged, [i["gmres_iters"] for i in infos]))
     for wl, U, info in zip(wls, Us, infos):
         assert info["status"] == 0
         assert info["gmres_residual"] <= 1e-8

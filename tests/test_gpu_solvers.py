@@ -37,6 +37,57 @@ def test_mobility_matches_dense_solve(name):
     assert relerr(host(U), Uo) < 1e-6
 
 
+@pytest.mark.parametrize("name,prec", [("tiny2", "fp64"), ("starfish4", "fp64"), ("starfish4", "mixed")])
+def test_lagged_reorthogonalisation_matches_dense_solve(name, prec):
+    """FBIM_FLAG_LAGGED_REORTH (delayed second Gram-Schmidt pass): the mobility solve
+    against the dense oracle, and the iteration count against the two-pass default."""
+    import paper_1709_01480_amd as fb
+    wl = workload(name)
+    log("lagged reorth %s %s" % (name, prec))
+    over = dict(TIGHT) if prec == "fp64" else dict(tol_gmres=1e-8, tol_lanczos=1e-8, precision=fb.PREC_MIXED)
+    geo, prm, d = _dense(wl)
+    Uo, _ = d.mobility(wl.F)
+    its = {}
+    for flags in (0, fb.FLAG_LAGGED_REORTH):
+        ctx = make_ctx(wl, flags=flags, **over)
+        U = zeros(3 * wl.n_bodies)
+        info = ctx.mobility(dev(wl.F), U)
+        its[flags] = info["gmres_iters"]
+        assert info["gmres_residual"] <= over["tol_gmres"]
+        assert relerr(host(U), Uo) < (1e-6 if prec == "fp64" else 1e-5)
+        ctx.close()
+    log("iterations two-pass %d lagged %d" % (its[0], its[fb.FLAG_LAGGED_REORTH]))
+    assert abs(its[fb.FLAG_LAGGED_REORTH] - its[0]) <= 1
+
+
+@pytest.mark.parametrize("name", ["starfish4", "small12"])
+def test_lagged_reorthogonalisation_batched_step(name):
+    """The batched mixed EM-RFD step (lockstep solves, graphs, FP32 basis) with the
+    delayed second Gram-Schmidt pass: the displacement against the oracle's step, and
+    the iteration count against the same step with two passes per Arnoldi step."""
+    import paper_1709_01480_amd as fb
+    wl = workload(name)
+    log("lagged batched step %s" % name)
+    geo, prm, _ = _dense(wl)
+    Wr, Wg, Wt = W.noise(wl, prm["grid_M"])
+    delta = wl.a * 1e-2
+    ref, _, _, _ = OF.em_rfd_step(geo, prm, wl.F, Wr, Wg, Wt, wl.kT, wl.dt, delta, order=wl.alpert_order,
+                                  tau=wl.tau_spurious)
+    base = fb.FLAG_BATCH_RFD | fb.FLAG_GRAPH | fb.FLAG_BASIS32
+    its = {}
+    for flags in (base, base | fb.FLAG_LAGGED_REORTH):
+        ctx = make_ctx(wl, precision=fb.PREC_MIXED, flags=flags, tol_gmres=1e-8, tol_lanczos=1e-8)
+        for rep in range(2):  # the second step replays the captured graphs
+            dQ = zeros(3 * wl.n_bodies)
+            info = ctx.step_em_rfd(wl.dt, delta, dev(wl.F), dev(Wr), dev(Wg), dev(Wt), dQ)
+            assert info["gmres_solves"] == 3 and info["gmres_residual"] <= 1e-8
+            assert relerr(host(dQ), ref) < 1e-4
+        its[flags] = info["gmres_iters"]
+        ctx.close()
+    log("iterations two-pass %d lagged %d" % (its[base], its[base | fb.FLAG_LAGGED_REORTH]))
+    assert abs(its[base | fb.FLAG_LAGGED_REORTH] - its[base]) <= 2
+
+
 def test_mobility_with_slip_matches_dense_solve():
     wl = workload("tiny2")
     ctx = make_ctx(wl, **TIGHT)
