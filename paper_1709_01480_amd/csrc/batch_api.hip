@@ -809,17 +809,19 @@ fbim_status orthogonalise_b(BatchEngine *E, Tables &T, int k, std::vector<std::v
 }
 
 // One lockstep Arnoldi step with delayed reorthogonalisation (FBIM_FLAG_LAGGED_REORTH)
-// for the systems of T: each system's previous lagged-pass output (lagprev, table
-// order; j + 1 values) is uploaded, the dot-product pass and the lagged pass run over
-// basis slots 0..j and w = by, and u_{j+1} = w' / ||w'|| is written to `next` and its
-// FP64 copy to bx.  dots[q] and outs[q] point to system q's published dot products
-// and lagged-pass output (j + 2 values each) until the next publication.
-fbim_status orthogonalise_lag_b(BatchEngine *E, Tables &T, int j, const std::vector<const double *> &lagprev,
-                                const VecRef &next, std::vector<const double *> &dots,
-                                std::vector<const double *> &outs) {
+// for the systems of T: the dot-product pass and the lagged pass run over basis slots
+// 0..j and w = by, and u_{j+1} = w' / ||w'|| is written to `next` and its FP64 copy to
+// bx.  The lagged pass reads each system's previous lagged-pass output (j + 1 values)
+// where the previous step left it when it ran on the same systems in the same table
+// order (`same`), else from lagprev (host, table order) through a pinned upload.
+// dots[q] and outs[q] point to system q's published dot products and lagged-pass
+// output (j + 2 values each) until the next publication.
+fbim_status orthogonalise_lag_b(BatchEngine *E, Tables &T, int j, bool same,
+                                const std::vector<const double *> &lagprev, const VecRef &next,
+                                std::vector<const double *> &dots, std::vector<const double *> &outs) {
   const int S = T.S, hs = E->hs;
   Scal q = scalars(E, S);
-  if (j > 0) {
+  if (j > 0 && !same) {
     // the staging buffer's previous copy ran before the last publication the host waited for
     for (int p = 0; p < S; ++p) std::memcpy(E->h_lagin + (size_t)p * kLagSlot, lagprev[p], (j + 1) * sizeof(double));
     EHIP(E, hipMemcpyAsync(E->d_lagin, E->h_lagin, (size_t)S * kLagSlot * sizeof(double), hipMemcpyHostToDevice,
@@ -841,8 +843,10 @@ fbim_status orthogonalise_lag_b(BatchEngine *E, Tables &T, int j, const std::vec
     a.partial = E->d_partial;
     a.out = q.h2;
     a.ostride = hs;
-    a.lag = j > 0 ? E->d_lagin : nullptr;
-    a.lagstride = kLagSlot;
+    // in place: every work group reads its system's lag before the reduction launch
+    // that writes this pass's output over it
+    a.lag = j == 0 ? nullptr : (same ? q.h2 : E->d_lagin);
+    a.lagstride = same ? hs : kLagSlot;
     EHIP(E, launch_orth_lag(a, E->stream));
     EHIP(E, launch_rsqrt_strided(S, q.h2 + j + 1, hs, q.a, E->stream));
     EHIP(E, launch_seg_scale2(T.seg, vref(T.by), next, vref(T.bx), q.a, E->stream));
@@ -908,6 +912,7 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
   std::vector<std::vector<double>> H(S0), g(S0), cs(S0), sn(S0);
   // lagged: unrotated columns, lag of the newest vector, last lagged-pass output
   std::vector<std::vector<double>> Hu(S0), slag(S0), lagraw(S0);
+  std::vector<int> lag_act;  // the systems (positions in sysl) of the last lagged pass
   bool first = !warm;
   while (!running.empty()) {
     T = &tables_for(E, pick(sysl, running), st);
@@ -987,7 +992,9 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
       if (lagged) {
         std::vector<const double *> lp(act.size()), dts, outs;
         for (size_t q = 0; q < act.size(); ++q) lp[q] = lagraw[act[q]].data();
-        EST(orthogonalise_lag_b(E, *T, j, lp, vnext, dts, outs));  // u_{j+1}, V_j final
+        const bool same = j > 0 && act == lag_act;
+        EST(orthogonalise_lag_b(E, *T, j, same, lp, vnext, dts, outs));  // u_{j+1}, V_j final
+        lag_act = act;
         hc.assign(act.size(), std::vector<double>());
         hn.assign(act.size(), 0.0);
         std::vector<double> col(j + 2);
