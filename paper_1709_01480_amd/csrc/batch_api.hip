@@ -810,15 +810,16 @@ fbim_status orthogonalise_b(BatchEngine *E, Tables &T, int k, std::vector<std::v
 
 // One lockstep Arnoldi step with delayed reorthogonalisation (FBIM_FLAG_LAGGED_REORTH)
 // for the systems of T: the dot-product pass and the lagged pass run over basis slots
-// 0..j and w = by, and u_{j+1} = w' / ||w'|| is written to `next` and its FP64 copy to
-// bx.  The lagged pass reads each system's previous lagged-pass output (j + 1 values)
+// 0..j and w = by; the lagged pass finalises slot j and writes the new vector w',
+// unnormalised, to slot j + 1 and its FP64 copy to bx (the next operator input).  The
+// lagged pass reads each system's previous lagged-pass output (j + 1 values)
 // where the previous step left it when it ran on the same systems in the same table
 // order (`same`), else from lagprev (host, table order) through a pinned upload.
 // dots[q] and outs[q] point to system q's published dot products and lagged-pass
 // output (j + 2 values each) until the next publication.
 fbim_status orthogonalise_lag_b(BatchEngine *E, Tables &T, int j, bool same,
-                                const std::vector<const double *> &lagprev, const VecRef &next,
-                                std::vector<const double *> &dots, std::vector<const double *> &outs) {
+                                const std::vector<const double *> &lagprev, std::vector<const double *> &dots,
+                                std::vector<const double *> &outs) {
   const int S = T.S, hs = E->hs;
   Scal q = scalars(E, S);
   if (j > 0 && !same) {
@@ -847,9 +848,9 @@ fbim_status orthogonalise_lag_b(BatchEngine *E, Tables &T, int j, bool same,
     // that writes this pass's output over it
     a.lag = j == 0 ? nullptr : (same ? q.h2 : E->d_lagin);
     a.lagstride = same ? hs : kLagSlot;
+    a.next = 1;
+    a.xs = const_cast<double *const *>(T.bx);
     EHIP(E, launch_orth_lag(a, E->stream));
-    EHIP(E, launch_rsqrt_strided(S, q.h2 + j + 1, hs, q.a, E->stream));
-    EHIP(E, launch_seg_scale2(T.seg, vref(T.by), next, vref(T.bx), q.a, E->stream));
   }
   const unsigned long long tag = ++E->pub.seq;
   EHIP(E, launch_publish2(S, j + 2, q.h, hs, j + 2, q.h2, hs, E->pub, tag, E->stream));
@@ -912,6 +913,7 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
   std::vector<std::vector<double>> H(S0), g(S0), cs(S0), sn(S0);
   // lagged: unrotated columns, lag of the newest vector, last lagged-pass output
   std::vector<std::vector<double>> Hu(S0), slag(S0), lagraw(S0);
+  std::vector<double> nlag(S0, 1.0);  // norm of the newest vector as it stands in the basis
   std::vector<int> lag_act;  // the systems (positions in sysl) of the last lagged pass
   bool first = !warm;
   while (!running.empty()) {
@@ -946,6 +948,7 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
         Hu[i].assign((size_t)(m + 1) * m, 0.0);
         slag[i].clear();
         lagraw[i].clear();
+        nlag[i] = 1.0;
       }
       g[i].assign(m + 1, 0.0);
       cs[i].assign(m, 0.0);
@@ -993,14 +996,14 @@ fbim_status gmres_b(BatchEngine *E, const std::vector<int> &sysl, bool ir, bool 
         std::vector<const double *> lp(act.size()), dts, outs;
         for (size_t q = 0; q < act.size(); ++q) lp[q] = lagraw[act[q]].data();
         const bool same = j > 0 && act == lag_act;
-        EST(orthogonalise_lag_b(E, *T, j, same, lp, vnext, dts, outs));  // u_{j+1}, V_j final
+        EST(orthogonalise_lag_b(E, *T, j, same, lp, dts, outs));  // V_j final, w' into slot j + 1 and bx
         lag_act = act;
         hc.assign(act.size(), std::vector<double>());
         hn.assign(act.size(), 0.0);
         std::vector<double> col(j + 2);
         for (size_t q = 0; q < act.size(); ++q) {
           const int i = act[q];
-          if (!lagged_column(j, dts[q], outs[q], Hu[i], m, slag[i], col.data()))
+          if (!lagged_column(j, dts[q], outs[q], Hu[i], m, slag[i], nlag[i], col.data()))
             return efail(E, FBIM_EDEVICE, "non-finite Krylov vector in a batch system");
           for (int r = 0; r <= j + 1; ++r) Hu[i][(size_t)r * m + j] = col[r];
           lagraw[i].assign(outs[q], outs[q] + j + 2);

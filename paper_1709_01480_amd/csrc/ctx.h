@@ -314,7 +314,7 @@ fbim_status lanczos_sqrt(fbim_ctx *c, const double *b, double *out, int &iters, 
 fbim_status norm2(fbim_ctx *c, const double *x, size_t n, double &out);
 // host half of an Arnoldi step with delayed reorthogonalisation (fbim_api.hip)
 bool lagged_column(int j, const double *dots, const double *out, const std::vector<double> &Hu, int m,
-                   std::vector<double> &s, double *col);
+                   std::vector<double> &s, double &nu, double *col);
 fbim_status brownian_slip(fbim_ctx *c, double dt, const double *W_r, const double *W_grid, double *slip_out,
                           fbim_info *info);
 fbim_status setup_fft(fbim_ctx *c);

@@ -678,19 +678,23 @@ fbim_status orthogonalise(fbim_ctx *c, const double *V, int k, double *w, size_t
 }
 
 // Host half of a lagged Arnoldi step (the relations are given with arnoldi_lagged):
-// dots = (V_{<j}^T w, u_j . w, w . w) and out = (V_{<=j}^T w', w' . w') as published,
-// s the lag of u_j.  Writes the unrotated column j into col[0..j+1] and replaces s by
-// the lag of u_{j+1}; false if a value is not finite.  s, rho and e are computed as
-// the lagged pass computes them on the device.
+// dots = V_{<=j}^T w (and w . w) and out = (V_{<=j}^T w', w' . w') as published, where
+// slot j holds nu u_j and w = nu A u_j; s is the lag of u_j.  Writes the unrotated
+// column j into col[0..j+1] and replaces s and nu by the lag and norm of w' = |w'|
+// u_{j+1} (left unnormalised in slot j + 1); false if a value is not finite.  s, rho,
+// t and e are computed as the lagged pass computes them on the device.
 bool lagged_column(int j, const double *dots, const double *out, const std::vector<double> &Hu, int m,
-                   std::vector<double> &s, double *col) {
+                   std::vector<double> &s, double &nu, double *col) {
+  const double inu = nu > 0.0 ? 1.0 / nu : 0.0;
+  std::vector<double> t(j);
   double ss = 0.0, stt = 0.0;
   for (int i = 0; i < j; ++i) {
+    t[i] = dots[i] * inu;
     ss += s[i] * s[i];
-    stt += s[i] * dots[i];
+    stt += s[i] * t[i];
   }
   const double rho = std::sqrt(std::max(1.0 - ss, 0.0)), irho = rho > 0.0 ? 1.0 / rho : 0.0;
-  const double e_j = (dots[j] - stt) * irho;
+  const double e_j = (dots[j] * inu * inu - stt) * irho;
   const double nw = std::sqrt(std::max(out[j + 1], 0.0)), inw = nw > 0.0 ? 1.0 / nw : 0.0;
   std::vector<double> sn(j + 1);
   double sn2 = 0.0;
@@ -701,30 +705,33 @@ bool lagged_column(int j, const double *dots, const double *out, const std::vect
   for (int i = 0; i <= j; ++i) {
     double hs = 0.0;  // (H_{<j} s)_i
     for (int l = 0; l < j; ++l) hs += Hu[(size_t)i * m + l] * s[l];
-    col[i] = ((i < j ? dots[i] : e_j) - hs) * irho + nw * sn[i];
+    col[i] = ((i < j ? t[i] : e_j) - hs) * irho + nw * sn[i];
   }
   col[j + 1] = nw * std::sqrt(std::max(1.0 - sn2, 0.0));
   s = std::move(sn);
+  nu = nw;
   for (int i = 0; i <= j + 1; ++i)
     if (!std::isfinite(col[i])) return false;
   return std::isfinite(dots[j + 1]);
 }
 
 // One Arnoldi step with delayed reorthogonalisation (FBIM_FLAG_LAGGED_REORTH).
-// On entry slot j of V holds u_j: unit norm, orthogonal to V_0..V_{j-1} but for
-// s = V_{<j}^T u_j (host, from the previous step; empty for j = 0), and w = A u_j.
-// A dot-product pass gives t = V_{<j}^T w, u_j . w and ||w||^2; the lagged pass
-// turns u_j into the final V_j = (u_j - V_{<j} s) / rho (rho = sqrt(1 - s.s)),
-// projects w out of V_{<=j} and returns its dot products with V_{<=j}; w is then
-// normalised.  With e = (t, (u_j . w - s.t) / rho) = V_{<=j}^T w, the step's
-// Arnoldi column follows without touching the vectors again:
+// On entry slot j of V holds nu u_j, u_j of unit norm and orthogonal to V_0..V_{j-1}
+// but for s = V_{<j}^T u_j (host, from the previous step; empty, and nu = 1, for
+// j = 0), and w = nu A u_j (the operator was applied to the slot as it stands).  A
+// dot-product pass gives V_{<=j}^T w and ||w||^2; the lagged pass turns the slot into
+// the final V_j = (u_j - V_{<j} s) / rho (rho = sqrt(1 - s.s)), projects w out of
+// V_{<=j} and returns its dot products with V_{<=j} and its norm; w is left
+// unnormalised (its norm is the next step's nu).  With t = V_{<j}^T A u_j and
+// e = (t, (u_j . A u_j - s.t) / rho) = V_{<=j}^T A u_j, the step's Arnoldi column
+// follows without touching the vectors again (w below is A u_j):
 //   A V_j = (w - A V_{<j} s) / rho,   A V_{<j} = V H_{<j}   (columns 0..j-1 final)
 //   h = (e - H s) / rho,  w' = (w - V_{<=j} e) / rho = |w'| u_{j+1}
 //   u_{j+1} = rho' V_{j+1} + V_{<=j} s'  =>  col[0..j] = h + |w'| s',  col[j+1] = |w'| rho'
 // Hu holds the unrotated Arnoldi columns (row i of column l at Hu[i * m + l]);
-// col[0..j+1] is column j on return and s is replaced by s'.
+// col[0..j+1] is column j on return, s is replaced by s' and nu by |w'|.
 fbim_status arnoldi_lagged(fbim_ctx *c, int j, double *w, size_t n, const std::vector<double> &Hu, int m,
-                           std::vector<double> &s, double *col) {
+                           std::vector<double> &s, double &nu, double *col) {
   hipStream_t st = c->stream;
   double *dots = c->d_lag, *cur = c->d_lag + kLagSlot * (1 + (j & 1)), *prev = c->d_lag + kLagSlot * (1 + (~j & 1));
   STCHK(orth_pass(c, 0, n, c->d_V, j + 1, w, nullptr, nullptr, dots));  // t, u_j . w, ||w||^2
@@ -745,12 +752,11 @@ fbim_status arnoldi_lagged(fbim_ctx *c, int j, double *w, size_t n, const std::v
     a.lag = j > 0 ? prev : nullptr;
     a.lagstride = 0;
     HIPCHK(c, launch_orth_lag(a, st));
-    HIPCHK(c, launch_scale_rsqrt_dev(n, cur + j + 1, w, st));
   }
   const unsigned long long tag = ++c->pub.seq;
   HIPCHK(c, launch_publish2(1, j + 2, dots, 0, j + 2, cur, 0, c->pub, tag, st));
   HIPCHK(c, pub_wait(c->pub, tag, st));
-  if (!lagged_column(j, c->pub.v, c->pub.v + j + 2, Hu, m, s, col))
+  if (!lagged_column(j, c->pub.v, c->pub.v + j + 2, Hu, m, s, nu, col))
     return fail(c, FBIM_EDEVICE, "non-finite Krylov vector");
   return FBIM_OK;
 }
@@ -788,6 +794,7 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
   if (nb == 0.0) return FBIM_OK;
   std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), hcol(m + 3), y(m);
   std::vector<double> Hu(lagged ? (size_t)(m + 1) * m : 0), slag;  // unrotated columns, lag of the newest vector
+  double nlag = 1.0;                                                 // and its norm as it stands in V
   bool first = !warm;
   const bool saved32 = c->cur32;
   struct Restore {
@@ -818,6 +825,7 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     slag.clear();
+    nlag = 1.0;
     int jend = 0;
     for (int j = 0; j < m; ++j) {
       double *vj = c->d_V + (size_t)j * nt;
@@ -827,7 +835,7 @@ fbim_status gmres(fbim_ctx *c, const double *b, double *x, double tol, int &iter
       STCHK(apply_saddle(c, c->d_t1, w));
       double hn = 0;
       if (lagged) {
-        STCHK(arnoldi_lagged(c, j, w, nt, Hu, m, slag, hcol.data()));
+        STCHK(arnoldi_lagged(c, j, w, nt, Hu, m, slag, nlag, hcol.data()));
         for (int i = 0; i <= j + 1; ++i) Hu[(size_t)i * m + j] = hcol[i];
         hn = hcol[j + 1];
       } else {

@@ -298,21 +298,25 @@ struct OrthArgs {
   double *out;
   int ostride;
   int v32 = 0;  // V / Vs address FP32 columns (widened to FP64 for the arithmetic)
-  // lagged pass only: the previous lagged pass's output per system (lag[s * lagstride + j])
+  // lagged pass only: the previous lagged pass's output per system (lag[s * lagstride + j]);
+  // with next set, the new vector goes to basis slot K + 1 and to xs[s] (FP64) instead of w
   const double *lag = nullptr;
   int lagstride = 0;
+  int next = 0;
+  double *const *xs = nullptr;
 };
 hipError_t launch_orth(int mode, const OrthArgs &a, hipStream_t s);
 // Lagged pass of delayed reorthogonalisation (one Arnoldi step reads the basis
 // twice instead of three times) over the k = K final columns V_0..V_{K-1}, the
-// column u in slot K and w, K < kOrthFused.  Slot K holds u, of unit norm and
-// orthogonal to V_{<K} but for s = lag[0..K) / sqrt(lag[K]) (lag: the previous
-// lagged pass's output for u before its normalisation); h[0..K] = (V_{<K}^T w,
-// u . w) from a mode-0 pass over slots 0..K.  With rho = sqrt(1 - s . s) and
-// e = (h[K] - s . h[0..K)) / rho:
-//   V_K = (u - V_{<K} s) / rho            (over u; not written for K = 0)
-//   w  <- (w - V_{<K} h[0..K) - V_K e) / rho
-//   out[j] = V_j . w (j <= K), out[K + 1] = w . w
+// column in slot K and w, K < kOrthFused.  Slot K holds nu u, u of unit norm and
+// orthogonal to V_{<K} but for s = lag[0..K) / nu, where nu = sqrt(lag[K]) (lag: the
+// previous lagged pass's output; nu = 1 and no lag for K = 0), and w = nu A u.
+// h[0..K] = V_{<=K}^T w from a mode-0 pass over slots 0..K.  With rho = sqrt(1 - s.s),
+// t = h[0..K) / nu and e = (h[K] / nu^2 - s.t) / rho:
+//   V_K = (u - V_{<K} s) / rho             (over slot K; not written for K = 0)
+//   x   = (w / nu - V_{<K} t - V_K e) / rho  into w, or with `next` into slot K + 1
+//                                           and xs (FP64)
+//   out[j] = V_j . x (j <= K), out[K + 1] = x . x
 hipError_t launch_orth_lag(const OrthArgs &a, hipStream_t s);
 // vector of system s in a batch: base[s] + col * ld[s] (ld may be null: col ignored)
 struct VecRef {
@@ -367,10 +371,6 @@ hipError_t launch_publish(int n, const double *src, int stride, HostPub &p, unsi
 // src1[s stride1 + j - n0] (j < n0 + n1); then the tag
 hipError_t launch_publish2(int S, int n0, const double *src0, int stride0, int n1, const double *src1, int stride1,
                            HostPub &p, unsigned long long tag, hipStream_t s);
-// dst[s] = 1 / sqrt(src[s stride]) (0 when src <= 0), s < S
-hipError_t launch_rsqrt_strided(int S, const double *src, int stride, double *dst, hipStream_t s);
-// y *= 1 / sqrt(a[0]) (0 when a[0] <= 0) with a on the device
-hipError_t launch_scale_rsqrt_dev(size_t n, const double *a, double *y, hipStream_t s);
 // y *= a[0] with a on the device
 hipError_t launch_scale_dev(size_t n, const double *a, double *y, hipStream_t s);
 // y[i] = sum_j V[j*ld + i] * c[j]

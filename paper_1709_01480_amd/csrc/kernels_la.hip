@@ -933,22 +933,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   const int tid = threadIdx.x;
   const double *h = a.h + (size_t)sys * a.hstride;
   double sc[K > 0 ? K : 1], tc[K > 0 ? K : 1];
-  double ss = 0.0, st = 0.0;
+  double ss = 0.0, st = 0.0, inu = 1.0;
   if constexpr (K > 0) {
     const double *lag = a.lag + (size_t)sys * a.lagstride;
     const double nu = sqrt(fmax(lag[K], 0.0));
-    const double inu = nu > 0.0 ? 1.0 / nu : 0.0;
+    inu = nu > 0.0 ? 1.0 / nu : 0.0;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
       sc[j] = lag[j] * inu;
-      tc[j] = h[j];
+      tc[j] = h[j] * inu;
       ss += sc[j] * sc[j];
       st += sc[j] * tc[j];
     }
   }
   const double rho = sqrt(fmax(1.0 - ss, 0.0));
   const double irho = rho > 0.0 ? 1.0 / rho : 0.0;
-  const double ecoef = (h[K] - st) * irho;
+  const double ecoef = (h[K] * inu * inu - st) * irho;
+  double *__restrict__ xs = a.next ? a.xs[sys] : nullptr;
   VT *__restrict__ V = reinterpret_cast<VT *>(const_cast<double *>(a.Vs ? a.Vs[sys] : a.V));
   double *__restrict__ w = a.ws ? a.ws[sys] : a.w;
   const size_t ld = a.lds ? a.lds[sys] : a.ld;
@@ -968,7 +969,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const bool ok = i0 + 256 * e < rg.y;
-      double v = uv[e];
+      double v = uv[e] * inu;
       double p0 = 0.0, p1 = 0.0;
       if constexpr (K > 0) {
         double s0 = 0.0, s1 = 0.0;
@@ -985,8 +986,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
         v = (v - (s0 + s1)) * irho;
         if (ok) V[(size_t)K * ld + i0 + 256 * e] = (VT)v;
       }
-      double x = (wv[e] - (p0 + p1) - v * ecoef) * irho;
-      if (ok) w[i0 + 256 * e] = x;
+      double x = (wv[e] * inu - (p0 + p1) - v * ecoef) * irho;
+      if (ok) {
+        const int i = i0 + 256 * e;
+        if (xs) {
+          V[(size_t)(K + 1) * ld + i] = (VT)x;
+          xs[i] = x;
+        } else {
+          w[i] = x;
+        }
+      }
       if (!ok) x = 0.0;
 #pragma unroll
       for (int j = 0; j < K; ++j) acc[j] += vv[e][j] * x;
@@ -1012,7 +1021,7 @@ hipError_t launch_orth_lag_k(const OrthArgs &a, hipStream_t s) {
 
 hipError_t launch_orth_lag(const OrthArgs &a, hipStream_t s) {
   if (a.seg.nchunk == 0) return hipSuccess;
-  if (a.k < 0 || a.k >= kOrthFused || (a.k > 0 && !a.lag) || a.cond) return hipErrorInvalidValue;
+  if (a.k < 0 || a.k >= kOrthFused || (a.k > 0 && !a.lag) || a.cond || (a.next && !a.xs)) return hipErrorInvalidValue;
   return a.v32 ? launch_orth_lag_k<0, float>(a, s) : launch_orth_lag_k<0, double>(a, s);
 }
 
@@ -1267,20 +1276,6 @@ hipError_t launch_publish2(int S, int n0, const double *src0, int stride0, int n
   return hipGetLastError();
 }
 
-__global__ void k_rsqrt_strided(int S, const double *__restrict__ src, int stride, double *__restrict__ dst) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < S) {
-    const double v = src[(size_t)i * stride];
-    dst[i] = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
-  }
-}
-
-hipError_t launch_rsqrt_strided(int S, const double *src, int stride, double *dst, hipStream_t s) {
-  if (S <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rsqrt_strided, dim3((S + 255) / 256), dim3(256), 0, s, S, src, stride, dst);
-  return hipGetLastError();
-}
-
 hipError_t launch_publish(int n, const double *src, int stride, HostPub &p, unsigned long long tag, hipStream_t s) {
   if (n < 0 || (size_t)n > p.cap || !p.tag) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_publish, dim3(1), dim3(256), 0, s, n, src, stride, p.v_dev, p.tag_dev, tag);
@@ -1291,19 +1286,6 @@ __global__ void k_scale_dev(size_t n, const double *__restrict__ a, double *__re
   const double f = a[0];
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     y[i] *= f;
-}
-
-__global__ void k_scale_rsqrt_dev(size_t n, const double *__restrict__ a, double *__restrict__ y) {
-  const double f = a[0] > 0.0 ? 1.0 / sqrt(a[0]) : 0.0;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    y[i] *= f;
-}
-
-hipError_t launch_scale_rsqrt_dev(size_t n, const double *a, double *y, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  const int nb = (int)std::min<size_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_scale_rsqrt_dev, dim3(nb), dim3(256), 0, s, n, a, y);
-  return hipGetLastError();
 }
 
 hipError_t launch_scale_dev(size_t n, const double *a, double *y, hipStream_t s) {
