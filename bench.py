@@ -273,7 +273,8 @@ def roofline(kt, xh, wl, d):
 def run_batch(args, fb, W, np, torch):
     """The uneven-suspension batch: 64 independent suspensions, bodies per
     suspension log-uniform in [16, 512], 64 / 128 / 256 nodes per body, mixed
-    precision with the FP32 Krylov basis.  One batched EM-RFD step of all of them
+    precision with the FP32 Krylov basis and the delayed second Gram-Schmidt pass.
+    One batched EM-RFD step of all of them
     (three mobility solves per suspension in lockstep launch sets, preconditioner
     and saddle operator replayed from graphs, noise drawn by each member, bodies
     moved) against the same member contexts stepping one after another.  One
@@ -282,7 +283,7 @@ def run_batch(args, fb, W, np, torch):
     prms = []
     for k, wl in enumerate(wls):
         p = wl.params()
-        p.update(precision=fb.PREC_MIXED, flags=fb.FLAG_BASIS32, seed=W.noise_key(wl, 100 + k))
+        p.update(precision=fb.PREC_MIXED, flags=fb.FLAG_BASIS32 | fb.FLAG_LAGGED_REORTH, seed=W.noise_key(wl, 100 + k))
         prms.append(p)
     b = fb.Batch(prms, graph=True)
     for m, wl in zip(b.members, wls):
@@ -316,7 +317,7 @@ def run_batch(args, fb, W, np, torch):
     t_s = (time.perf_counter() - t0) / args.steps
     print(json.dumps({"mode": "batch", "workload": "64 uneven suspensions, bodies log-uniform in [16, 512], "
                       "64/128/256 nodes per body, area fraction 0.2, tol 1e-6; EM-RFD step, 3 RHS each",
-                      "precision": "mixed+basis32", "suspensions": len(wls), "bodies": sum(w.n_bodies for w in wls),
+                      "precision": "mixed+basis32+lagged", "suspensions": len(wls), "bodies": sum(w.n_bodies for w in wls),
                       "nodes": sum(w.n_nodes for w in wls), "steps": args.steps,
                       "ms_per_step_batched": 1e3 * t_b, "ms_per_step_one_after_another": 1e3 * t_s,
                       "speedup": t_s / t_b,
