@@ -122,41 +122,59 @@ hipError_t launch_tile_keys(int N, const double *x, double h, int M, int T, int 
   return hipGetLastError();
 }
 
-// single-workgroup exclusive scan (n up to a few 10^5), also the maximum count
+// single-workgroup exclusive scan (n up to a few 10^5), also the maximum count.
+// Tiles of 4096 counts: each thread sums four consecutive counts, the 64 lanes of a
+// wave scan their sums by shuffles, the 16 wave totals meet in LDS, and each thread
+// writes its four starts; two barriers per tile.
 __global__ __launch_bounds__(1024) void k_scan(int n, const int *__restrict__ count, int *__restrict__ start,
                                                int *__restrict__ maxcount) {
-  __shared__ int buf[1024];
-  __shared__ int carry;
-  __shared__ int mx[1024];
-  const int tid = threadIdx.x;
-  if (tid == 0) carry = 0;
-  int lmax = 0;
-  __syncthreads();
-  for (int base = 0; base < n; base += 1024) {
-    const int i = base + tid;
-    const int v = (i < n) ? count[i] : 0;
-    lmax = max(lmax, v);
-    buf[tid] = v;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {  // inclusive Hillis-Steele
-      int t = (tid >= o) ? buf[tid - o] : 0;
-      __syncthreads();
-      buf[tid] += t;
-      __syncthreads();
+  __shared__ int wsum[16], wmax[16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int carry = 0, lmax = 0;
+  for (int base = 0; base < n; base += 4096) {
+    int v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = base + 4 * tid + q;
+      v[q] = i < n ? count[i] : 0;
+      lmax = max(lmax, v[q]);
     }
-    if (i < n) start[i] = carry + buf[tid] - v;
+    const int tsum = (v[0] + v[1]) + (v[2] + v[3]);
+    int x = tsum;  // inclusive scan over the wave
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
     __syncthreads();
-    if (tid == 1023) carry += buf[1023];
-    __syncthreads();
+    int woff = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+      const int t = wsum[w];
+      woff += w < wv ? t : 0;
+      total += t;
+    }
+    int run = carry + woff + x - tsum;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = base + 4 * tid + q;
+      if (i < n) start[i] = run;
+      run += v[q];
+    }
+    carry += total;
+    __syncthreads();  // every thread has read wsum before the next tile writes it
   }
   if (tid == 0) start[n] = carry;
-  mx[tid] = lmax;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) lmax = max(lmax, __shfl_xor(lmax, o));
+  if (lane == 0) wmax[wv] = lmax;
   __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
-    if (tid < o) mx[tid] = max(mx[tid], mx[tid + o]);
-    __syncthreads();
+  if (tid == 0) {
+    int m = wmax[0];
+    for (int w = 1; w < 16; ++w) m = max(m, wmax[w]);
+    *maxcount = m;
   }
-  if (tid == 0) *maxcount = mx[0];
 }
 
 hipError_t launch_scan(int n, const int *count, int *start, int *maxcount, hipStream_t s) {
