@@ -124,6 +124,29 @@ def test_batched_mixed_mobility_reaches_fp64_tolerance(basis32, graph, lagged):
         assert relerr(host(U), host(ref)) < 1e-6
 
 
+@pytest.mark.parametrize("lagged", [False, True])
+def test_batched_mobility_with_short_restarts(lagged):
+    """Restart length 6, so every solve restarts several times (with the delayed
+    Gram-Schmidt pass each cycle starts its lags afresh): the FP64 restart residual
+    meets the tolerance and the solution matches each system solved alone with the
+    default restart length."""
+    import paper_1709_01480_amd as fb
+    wls = [W.make(n) for n in NAMES]
+    b = _batch(wls, tol_gmres=1e-10, gmres_restart=6, flags=fb.FLAG_LAGGED_REORTH if lagged else 0)
+    Fs = [dev(wl.F) for wl in wls]
+    Us = [zeros(3 * wl.n_bodies) for wl in wls]
+    infos = b.mobility(Fs, Us)
+    log("restart 6 lagged %s iterations %s" % (lagged, [i["gmres_iters"] for i in infos]))
+    for wl, U, info in zip(wls, Us, infos):
+        assert info["status"] == 0
+        assert info["gmres_residual"] <= 1e-10
+        ctx = make_ctx(wl, tol_gmres=1e-10, flags=fb.FLAG_LAGGED_REORTH if lagged else 0)
+        ref = zeros(3 * wl.n_bodies)
+        ctx.mobility(dev(wl.F), ref)
+        assert relerr(host(U), host(ref)) < 1e-8
+        ctx.close()
+
+
 def test_batched_em_rfd_matches_each_system():
     wls = [W.make(n) for n in NAMES[:2]]
     log("batch em-rfd")

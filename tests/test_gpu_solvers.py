@@ -60,6 +60,25 @@ def test_lagged_reorthogonalisation_matches_dense_solve(name, prec):
     assert abs(its[fb.FLAG_LAGGED_REORTH] - its[0]) <= 1
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_lagged_reorthogonalisation_with_short_restarts(prec):
+    """Restart length 6 with the delayed Gram-Schmidt pass (every solve restarts
+    several times and each cycle starts its lags afresh): the mobility solve against
+    the dense oracle."""
+    import paper_1709_01480_amd as fb
+    wl = workload("starfish4")
+    log("lagged reorth restart 6 %s" % prec)
+    over = dict(TIGHT) if prec == "fp64" else dict(tol_gmres=1e-8, tol_lanczos=1e-8, precision=fb.PREC_MIXED)
+    geo, prm, d = _dense(wl)
+    Uo, _ = d.mobility(wl.F)
+    ctx = make_ctx(wl, flags=fb.FLAG_LAGGED_REORTH, gmres_restart=6, **over)
+    U = zeros(3 * wl.n_bodies)
+    info = ctx.mobility(dev(wl.F), U)
+    log("iterations %d" % info["gmres_iters"])
+    assert info["gmres_residual"] <= over["tol_gmres"]
+    assert relerr(host(U), Uo) < (1e-6 if prec == "fp64" else 1e-5)
+
+
 @pytest.mark.parametrize("name", ["starfish4", "small12"])
 def test_lagged_reorthogonalisation_batched_step(name):
     """The batched mixed EM-RFD step (lockstep solves, graphs, FP32 basis) with the
